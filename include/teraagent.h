@@ -1,0 +1,251 @@
+/*
+ * teraagent.h -- C ABI of the MI355X aura-exchange library (libteraagent.so).
+ *
+ * One GPU holds one rank's share of space (one or many partition boxes).  Each
+ * iteration the library
+ *   1. selects the aura agents of every partition for each neighbour
+ *      direction                                   (ta_select_aura),
+ *   2. serializes them into flat, in-place usable TAM1 messages
+ *                                                  (ta_serialize, ta_view),
+ *   3. delta-encodes every message against the previous iteration's message
+ *      of the same neighbour pair                  (ta_delta_encode),
+ *   4. decodes and applies the encoding on the receive side
+ *                                                  (ta_delta_decode).
+ * Paper: Sec. 2.1 (aura update), Sec. 2.2 / 2.2.1 (TA IO serialization and
+ * single-pass deserialization), Sec. 2.3 (delta encoding against a reference
+ * shared by sender and receiver).
+ *
+ * Conventions for every call:
+ *  - Pointers marked "device" are HIP device pointers (e.g. a torch CUDA
+ *    tensor's data_ptr()); "host" pointers are ordinary memory.  The caller
+ *    owns every buffer it passes.  Device buffers must be 8-byte aligned.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work and return without synchronising; results are valid once the
+ *    stream has reached them.
+ *  - Counts produced on the device stay on the device; nothing in the
+ *    exchange calls syncs the host, so an iteration can be captured in a
+ *    HIP graph once the context has been sized with ta_reserve.
+ *  - Errors found on the host (bad arguments) are returned at once.  Errors
+ *    that depend on data (corrupt encodings, wrong reference, duplicate or
+ *    zero uid, output larger than its capacity) are recorded in the
+ *    context's device status word and read by ta_status_poll.  After such
+ *    an error the outputs of that call are unspecified, but nothing is ever
+ *    written outside the buffers and capacities passed in.
+ *  - Several errors in one call are reported with the precedence
+ *    TA_ERR_INVALID, TA_ERR_REF_MISMATCH, TA_ERR_CORRUPT, TA_ERR_CAPACITY.
+ *  - A context is used by one host thread and one stream at a time.
+ *
+ * Wire formats (little-endian, every record and section 8-byte aligned,
+ * every pad byte zero):
+ *
+ *  TAM1 message (Sec. 2.2.1; offsets stand in for the paper's pointer
+ *  markers so a GPU can address record i directly):
+ *    u32 magic "TAM1" | u16 version 1 | u16 flags 0 | u32 n | u32 0 |
+ *    u64 rec_words | u64 0 | u32 off[n] (record i starts at word off[i] of
+ *    the record area; off[0]=0, off[i+1]=off[i]+words_i), padded to 8 |
+ *    record area (rec_words words).
+ *  Record: u64 uid (non-zero) | u16 class, u16 behaviour count, u32 record
+ *    words | the class's fp64 fields (0..2 position, 3 diameter) | its int32
+ *    attributes, padded to 8 | behaviour blocks verbatim (u32 class,
+ *    u32 payload bytes (multiple of 8), payload).  The class id stands in
+ *    for the vtable pointer.
+ *
+ *  TAD1 encoding of a current message C against a reference R (Sec. 2.3):
+ *    64-byte header: u32 magic "TAD1" | u16 version 1 | u8 mode (0 plain,
+ *    1 learned) | u8 packer (1) | u32 n_ref | u32 n_match | u32 n_new |
+ *    u32 0 | u64 ref_words | u64 XOR of all reference uids | u64 W |
+ *    u64 new_words | u64 var_bytes;
+ *    presence bitmap (ceil(n_ref/64) u64; bit j: reference slot j matched);
+ *    word bitmap (ceil(W/64) u64; bit q: residual word q non-zero);
+ *    group block sizes (ceil(W/64) u8, bytes/8), padded to 8;
+ *    new record sizes (n_new u32 words), padded to 8;
+ *    new records verbatim (new_words words);
+ *    group blocks (var_bytes): for each group of 64 residual words, one
+ *    4-bit length per non-zero word (bytes up to its highest non-zero byte;
+ *    two per byte, low nibble first), then those low-order bytes of each
+ *    non-zero word, padded to a multiple of 8 bytes.
+ *  A reference slot is matched when C holds a record with the same uid and
+ *  the same header word.  The residual is the XOR of the matched current
+ *  records, taken in reference order, with X: the reference record (plain)
+ *  or the reference record with words 2..5 replaced by the predictor's
+ *  estimate (learned).  C' = matched records in reference order followed by
+ *  the new records in C order; it is returned to the sender and rebuilt by
+ *  the receiver, and it is the next reference of both.
+ */
+#ifndef TERAAGENT_H
+#define TERAAGENT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TA_OK = 0,
+  TA_ERR_INVALID = 1,      /* bad argument, bad message, zero or duplicate uid */
+  TA_ERR_CAPACITY = 2,     /* an output buffer is too small */
+  TA_ERR_CORRUPT = 3,      /* a TAD1 encoding is damaged */
+  TA_ERR_REF_MISMATCH = 4, /* a TAD1 encoding was made against another reference */
+  TA_ERR_HIP = 5           /* a HIP runtime call failed */
+} ta_status;
+
+typedef struct ta_ctx ta_ctx;
+
+/* Agent store: struct of arrays, all partitions concatenated, all device. */
+typedef struct {
+  int64_t n;               /* number of agents */
+  const uint64_t *uid;     /* [n] */
+  const uint16_t *cls;     /* [n] class id, < n_classes */
+  const uint16_t *nb;      /* [n] behaviour block count */
+  const double *f64;       /* field k of agent i at f64[k * f64_stride + i] */
+  int64_t f64_stride;      /* >= n */
+  const int32_t *i32;      /* attribute k of agent i at i32[k * i32_stride + i] */
+  int64_t i32_stride;      /* >= n */
+  const int64_t *beh_off;  /* [n+1] byte offsets into beh, multiples of 8 */
+  const uint8_t *beh;      /* behaviour blocks of agent i: beh[beh_off[i] .. beh_off[i+1]) */
+} ta_agents;
+
+/* Read-only description of one TAM1 message (see ta_view). */
+typedef struct {
+  int64_t n;               /* records */
+  int64_t rec_words;       /* 8-byte words in the record area */
+  const uint32_t *off;     /* n word offsets (same memory space as the message) */
+  uint8_t *records;        /* record area; record i at records + 8 * off[i] */
+} ta_view_t;
+
+/* Create a context for a class schema: class c has n_f64[c] fp64 fields and
+ * n_i32[c] int32 attributes (host arrays of n_classes entries, n_classes <=
+ * 256, n_f64[c] <= 64, n_i32[c] <= 64).  Uses the current HIP device. */
+ta_status ta_create(ta_ctx **out, uint32_t n_classes, const uint16_t *n_f64, const uint16_t *n_i32);
+
+/* Release the context and its device scratch memory.  Null is accepted. */
+void ta_destroy(ta_ctx *ctx);
+
+/* Pre-size the device scratch memory for calls with at most max_agents
+ * agents in the store, max_segments segments, idx_cap <= max_records and
+ * message buffers (cur_len, ref_len, enc_len, out_cap, ...) of at most
+ * max_msg_bytes bytes.  Calls that need more grow the scratch memory
+ * themselves (which allocates and synchronises); calls within the reserved
+ * sizes allocate nothing and may be captured in a HIP graph. */
+ta_status ta_reserve(ta_ctx *ctx, int64_t max_agents, int64_t max_segments, int64_t max_records,
+                     int64_t max_msg_bytes);
+
+/* Wait for `stream`, read and clear the device status word: TA_OK or the
+ * highest-precedence data-dependent error of the calls since the last poll. */
+ta_status ta_status_poll(ta_ctx *ctx, void *stream);
+
+/* Aura selection (Sec. 2.1, "Aura Update").
+ * P partitions; partition p holds agents [part_off[p], part_off[p+1]) of the
+ * store (part_off: device int64[P+1]) and owns the half-open box boxes[6p ..
+ * 6p+5] = lo0 lo1 lo2 hi0 hi1 hi2 (device double[6P]).  ndirs is 6 (face
+ * neighbours) or 26 (faces, edges, corners).  With thresholds lo+w and hi-w
+ * (each one fp64 operation), an agent belongs to direction (dx,dy,dz) when on
+ * every axis with d=-1 its coordinate is < lo+w and on every axis with d=+1
+ * it is >= hi-w.  Segment s = p*ndirs + k, k-th direction in ascending order
+ * of (dx+1) + 3(dy+1) + 9(dz+1).
+ * Output: idx_out (device int32[idx_cap]) store indices, segment by segment,
+ * ascending within a segment; seg_off_out (device int64[P*ndirs+1]) segment
+ * starts.  More than idx_cap selections -> TA_ERR_CAPACITY (seg_off_out still
+ * holds the needed sizes).  Agents beyond 2^31-1 are not supported. */
+ta_status ta_select_aura(ta_ctx *ctx, const ta_agents *agents, int32_t P, const int64_t *part_off,
+                         const double *boxes, double w, int32_t ndirs, int32_t *idx_out, int64_t idx_cap,
+                         int64_t *seg_off_out, void *stream);
+
+/* TA IO serialization (Sec. 2.2.1, "Serialization"): one TAM1 message per
+ * segment.  idx / seg_off (device) as produced by ta_select_aura, nseg
+ * segments, at most idx_cap records in total.  Messages are packed densely
+ * into out (device, out_cap bytes); msg_off_out (device int64[nseg+1])
+ * receives their byte offsets.  A class id >= n_classes or a behaviour range
+ * that is not a multiple of 8 bytes -> TA_ERR_INVALID; messages larger than
+ * out_cap -> TA_ERR_CAPACITY (msg_off_out still holds the needed sizes). */
+ta_status ta_serialize(ta_ctx *ctx, const ta_agents *agents, const int32_t *idx, const int64_t *seg_off,
+                       int64_t nseg, int64_t idx_cap, uint8_t *out, int64_t out_cap, int64_t *msg_off_out,
+                       void *stream);
+
+/* Upper bound of the serialized size of nrec records of at most max_words
+ * words each, in nseg messages. */
+int64_t ta_serialize_bound(int64_t nseg, int64_t nrec, int64_t max_words);
+
+/* View of one TAM1 message (Sec. 2.2.1, "Deserialization"/"Mutability"):
+ * O(1).  The message may be in host or device memory; for device memory the
+ * 32-byte header is copied to the host (a synchronous copy).  Checks the
+ * header and the size identity len == 32 + 8*ceil(n/2) + 8*rec_words and
+ * fills *out with pointers into the message itself, so records are read and
+ * updated in place.  Bad header or size -> TA_ERR_INVALID. */
+ta_status ta_view(uint8_t *msg, int64_t len, ta_view_t *out);
+
+/* Full O(n) check of the offsets and record headers of nseg device messages
+ * (msgs at msg_off[s] .. msg_off[s+1]); problems -> TA_ERR_INVALID in the
+ * status word. */
+ta_status ta_view_validate(ta_ctx *ctx, const uint8_t *msgs, const int64_t *msg_off, int64_t nseg,
+                           int64_t msgs_len, void *stream);
+
+/* Predictor for learned delta encoding: an integer MLP 12 -> 64 -> 64 -> 4
+ * (int8 weights, int32 accumulation) estimating the next position and
+ * diameter of an agent from its last moves.  Blob (host, 5672 bytes): u32
+ * magic "TAP1", u32 version 1, int8 W1[64][12], int8 W2[64][64], int8
+ * W3[4][64], int32 b1[64], int32 b2[64], int32 b3[4], u8 r1, r2, r3, 5 zero
+ * bytes, f64 cell; |b| <= 2^24, r <= 24, cell > 0.  Copied to the device. */
+typedef struct ta_predictor ta_predictor;
+ta_status ta_predictor_load(ta_ctx *ctx, const void *blob, size_t len, ta_predictor **out);
+void ta_predictor_free(ta_predictor *p);
+
+/* Per reference slot history of the predicted words (device):
+ * h1[4j..4j+3] words 2..5 of slot j's record one exchange before the
+ * reference, h2 two exchanges before (raw fp64 bits), hlen[j] in {0,1,2}. */
+typedef struct {
+  uint64_t *h1;
+  uint64_t *h2;
+  uint8_t *hlen;
+  int64_t cap;             /* slots the arrays hold */
+} ta_history;
+
+/* Delta encoding (Sec. 2.3) of nseg current messages against nseg
+ * reference messages (same segment order).  cur/ref: device buffers of
+ * cur_len/ref_len bytes holding the messages at cur_off/ref_off (device
+ * int64[nseg+1]).  pred == NULL: plain mode.  Otherwise learned mode: each
+ * segment is encoded both ways and the smaller encoding is kept (plain on
+ * ties); hist_in (slots flattened in segment order, device) must then be
+ * given.  hist_out (nullable) receives the history of C'.
+ * Outputs: enc (device, enc_cap bytes) with the TAD1 encodings packed densely
+ * at enc_off (device int64[nseg+1]); newref (device, newref_cap bytes) with
+ * the C' messages at newref_off (device int64[nseg+1]); modes (nullable,
+ * device uint8[nseg]) the mode chosen per segment.  Invalid or duplicate
+ * input -> TA_ERR_INVALID; too small outputs -> TA_ERR_CAPACITY. */
+ta_status ta_delta_encode(ta_ctx *ctx, int64_t nseg, const uint8_t *cur, int64_t cur_len, const int64_t *cur_off,
+                          const uint8_t *ref, int64_t ref_len, const int64_t *ref_off, const ta_predictor *pred,
+                          const ta_history *hist_in, ta_history *hist_out, uint8_t *enc, int64_t enc_cap,
+                          int64_t *enc_off, uint8_t *newref, int64_t newref_cap, int64_t *newref_off,
+                          uint8_t *modes, void *stream);
+
+/* Upper bound of the encoding size for current messages of cur_len bytes
+ * and a reference of ref_len bytes, nseg segments. */
+int64_t ta_delta_bound(int64_t nseg, int64_t cur_len, int64_t ref_len);
+
+/* Delta decoding (Sec. 2.3): rebuild C' of every segment from its TAD1
+ * encoding (enc at enc_off, device) and the stored reference (ref at
+ * ref_off, device).  Learned encodings need pred and hist_in.  Output: C'
+ * messages packed densely in out (device, out_cap bytes) at out_off (device
+ * int64[nseg+1]); hist_out (nullable) as for encoding.  Damaged encodings ->
+ * TA_ERR_CORRUPT; encodings made against another reference ->
+ * TA_ERR_REF_MISMATCH; too small output -> TA_ERR_CAPACITY. */
+ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t enc_len, const int64_t *enc_off,
+                          const uint8_t *ref, int64_t ref_len, const int64_t *ref_off, const ta_predictor *pred,
+                          const ta_history *hist_in, ta_history *hist_out, uint8_t *out, int64_t out_cap,
+                          int64_t *out_off, void *stream);
+
+/* Timing of one kernel family for measurement: when enabled, every launch
+ * of the named kernel is bracketed by HIP events on its stream, and
+ * ta_kernel_time returns (after syncing) the number of launches and their
+ * summed duration in milliseconds since the last call.  name = NULL
+ * disables.  Names: "select_count", "select_scatter", "serialize_pack",
+ * "encode_xor", "decode_unpack". */
+ta_status ta_time_kernel(ta_ctx *ctx, const char *name);
+ta_status ta_kernel_time(ta_ctx *ctx, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

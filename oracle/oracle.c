@@ -114,10 +114,11 @@ int orc_select_aura(int64_t P, const int64_t *part_off, const double *f64, int64
  */
 static int64_t record_words(const orc_agents *a, int n_classes, const uint16_t *n_f64,
                             const uint16_t *n_i32, int64_t i, int *err) {
+  if (i < 0 || i >= a->n) { *err = 1; return 0; }
   uint16_t c = a->cls[i];
   if (c >= n_classes) { *err = 1; return 0; }
   int64_t beh_bytes = a->beh_off[i + 1] - a->beh_off[i];
-  if (beh_bytes < 0 || beh_bytes % 8 != 0) { *err = 1; return 0; }
+  if (beh_bytes < 0 || beh_bytes % 8 != 0 || a->beh_off[i] % 8 != 0) { *err = 1; return 0; }
   return 2 + n_f64[c] + (n_i32[c] + 1) / 2 + beh_bytes / 8;
 }
 
@@ -186,6 +187,7 @@ int orc_view(const uint8_t *msg, int64_t len, int64_t *n_out, int64_t *rw_out) {
   int64_t n = get32(msg + 8);
   uint64_t rw = get64(msg + 16);
   if (n > len / 4 || rw > (uint64_t)len / 8) return ORC_INVALID;
+  if (rw < 2 * (uint64_t)n) return ORC_INVALID; /* records have at least 2 words */
   int64_t table = 8 * ((n + 1) / 2);
   if (32 + table + 8 * (int64_t)rw != len) return ORC_INVALID;
   if (n % 2 && get32(msg + 32 + 4 * n) != 0) return ORC_INVALID;

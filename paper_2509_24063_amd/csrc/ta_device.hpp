@@ -1,0 +1,215 @@
+// ta_device.hpp -- device-side building blocks shared by the exchange kernels:
+// wave64 collectives, a 256-thread block scan, the single-pass decoupled
+// look-back prefix used by every device-wide scan, and small search helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ta {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int WAVES = BLOCK / WAVE;
+
+constexpr uint32_t TAM1_MAGIC = 0x314D4154u;  // "TAM1"
+constexpr uint32_t TAD1_MAGIC = 0x31444154u;  // "TAD1"
+
+// bits of the device status word
+enum : uint32_t { ERR_INVALID = 1, ERR_CAPACITY = 2, ERR_CORRUPT = 3, ERR_REF = 4, ERR_INTERNAL = 5 };
+
+__device__ inline void fail(uint32_t* status, uint32_t code) { atomicOr(status, 1u << code); }
+__device__ inline uint32_t status_of(const uint32_t* status) {
+  return __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int lane_id() { return (int)__lane_id(); }
+__device__ inline int wave_id() { return (int)(threadIdx.x / WAVE); }
+
+__device__ inline uint64_t lanemask_le(int l) { return l >= 63 ? ~0ull : ((2ull << l) - 1); }
+__device__ inline uint64_t lanemask_lt(int l) { return l == 0 ? 0ull : (l >= 64 ? ~0ull : ((1ull << l) - 1)); }
+
+__device__ inline uint64_t wave_incl_scan(uint64_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint64_t t = __shfl_up(v, d, WAVE);
+    if (l >= d) v += t;
+  }
+  return v;
+}
+__device__ inline uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+  for (int d = WAVE / 2; d; d >>= 1) v += __shfl_xor(v, d, WAVE);
+  return v;
+}
+__device__ inline uint64_t wave_or(uint64_t v) {
+#pragma unroll
+  for (int d = WAVE / 2; d; d >>= 1) v |= __shfl_xor(v, d, WAVE);
+  return v;
+}
+__device__ inline uint64_t wave_xor(uint64_t v) {
+#pragma unroll
+  for (int d = WAVE / 2; d; d >>= 1) v ^= __shfl_xor(v, d, WAVE);
+  return v;
+}
+__device__ inline uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Exclusive prefix of v over the 256 threads of the block; *total = block sum.
+// s_wave: __shared__ uint64_t[WAVES].  Contains two block barriers.
+__device__ inline uint64_t block_excl_scan(uint64_t v, uint64_t* s_wave, uint64_t* total) {
+  const uint64_t incl = wave_incl_scan(v);
+  if (lane_id() == WAVE - 1) s_wave[wave_id()] = incl;
+  __syncthreads();
+  uint64_t off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) {
+    const uint64_t x = s_wave[i];
+    off += (i < wave_id()) ? x : 0;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back (single-pass chained scan).  Tiles are handed out in
+// order through an atomic ticket, so a tile only ever waits for tiles that
+// were handed out earlier and are therefore already running; tile 0 never
+// waits.  Each tile publishes its aggregate, sums predecessors' values back to
+// the nearest inclusive prefix, and publishes its own inclusive prefix.  A
+// status word per tile packs a 2-bit flag and a 62-bit value so one 64-bit
+// atomic store publishes both.  The flag array and the ticket must be zero
+// before the kernel starts; every look-back kernel clears the array and
+// ticket that the next one will use (see LookBack::clear_*).
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INCL = 2ull << 62;
+constexpr uint64_t LB_VALUE = (1ull << 62) - 1;
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 20;
+
+struct LookBack {
+  uint64_t* flags;        // per tile status words (zero on entry)
+  uint32_t* ticket;       // tile ticket (zero on entry)
+  uint64_t* clear_flags;  // array the next look-back kernel uses: zeroed here
+  uint32_t* clear_ticket;
+  int64_t clear_n;
+  uint32_t* status;
+};
+
+__device__ inline void lb_clear_next(const LookBack& lb) {
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < lb.clear_n; i += stride) lb.clear_flags[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && lb.clear_ticket) *lb.clear_ticket = 0;
+}
+
+__device__ inline uint32_t lb_take_ticket(const LookBack& lb, uint32_t* s_ticket) {
+  if (threadIdx.x == 0) *s_ticket = atomicAdd(lb.ticket, 1u);
+  __syncthreads();
+  const uint32_t t = *s_ticket;
+  __syncthreads();
+  return t;
+}
+
+// Called by all 64 lanes of one wave; returns the exclusive prefix of tile t.
+__device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t agg) {
+  const int l = lane_id();
+  if (t == 0) {
+    if (l == 0) __hip_atomic_store(lb.flags, LB_INCL | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  if (l == 0) __hip_atomic_store(lb.flags + t, LB_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t excl = 0;
+  int64_t hi = (int64_t)t - 1;
+  uint32_t spins = 0;
+  for (;;) {
+    const int64_t k = hi - l;
+    const uint64_t f =
+        k >= 0 ? __hip_atomic_load(lb.flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : LB_INCL;
+    const uint64_t incl = __ballot((f >> 62) == 2);
+    const uint64_t none = __ballot((f >> 62) == 0);
+    const int first = incl ? (__ffsll((unsigned long long)incl) - 1) : WAVE;
+    const uint64_t need = first >= WAVE - 1 ? ~0ull : ((2ull << first) - 1);
+    if (none & need) {
+      if (++spins > LB_SPIN_LIMIT) {  // never reached when every tile publishes; keeps the wave finite
+        if (l == 0) fail(lb.status, ERR_INTERNAL);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += wave_sum(l <= first ? (f & LB_VALUE) : 0);
+    if (first < WAVE) break;
+    hi -= WAVE;
+  }
+  if (l == 0) __hip_atomic_store(lb.flags + t, LB_INCL | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of n values given by a functor (value(i) for
+// i < n, uint64_t).  out[i] = sum of values before i, out[n] = total.  n is
+// read from device memory so the launch needs only a host bound.
+constexpr int SCAN_IPT = 8;
+constexpr int SCAN_TILE = BLOCK * SCAN_IPT;
+
+template <class In>
+__global__ __launch_bounds__(BLOCK) void k_scan(In in, const int64_t* n_dev, uint64_t* out, LookBack lb) {
+  __shared__ uint64_t s_wave[WAVES];
+  __shared__ uint32_t s_ticket;
+  __shared__ uint64_t s_prefix;
+  lb_clear_next(lb);
+  const int64_t n = *n_dev;
+  if (n <= 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+    return;
+  }
+  const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  for (;;) {
+    const uint32_t t = lb_take_ticket(lb, &s_ticket);
+    if ((int64_t)t >= ntiles) break;
+    const int64_t base = (int64_t)t * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    uint64_t v[SCAN_IPT];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; ++k) {
+      v[k] = (base + k < n) ? in(base + k) : 0;
+      sum += v[k];
+    }
+    uint64_t tot;
+    const uint64_t pre = block_excl_scan(sum, s_wave, &tot);
+    if (threadIdx.x < WAVE) {
+      const uint64_t e = lb_exclusive(lb, t, tot);
+      if (threadIdx.x == 0) s_prefix = e;
+    }
+    __syncthreads();
+    uint64_t run = s_prefix + pre;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
+    if ((int64_t)t == ntiles - 1 && threadIdx.x == BLOCK - 1) out[n] = run;
+    __syncthreads();
+  }
+}
+
+// Largest i in [lo, hi) with a[i] <= x (a non-decreasing); lo if none.
+template <class T>
+__device__ inline int64_t last_le(const T* a, int64_t lo, int64_t hi, T x) {
+  int64_t l = lo, h = hi;  // invariant: answer in [l, h)
+  while (h - l > 1) {
+    const int64_t m = l + (h - l) / 2;
+    if (a[m] <= x) l = m;
+    else h = m;
+  }
+  return l;
+}
+
+__device__ inline uint64_t ld64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
+__device__ inline uint32_t ld32(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
+
+}  // namespace ta

@@ -1,0 +1,315 @@
+// ta_select.hip -- aura selection (Sec. 2.1, "Aura Update").
+//
+// An agent is copied to the neighbour in direction d when its interaction
+// region reaches into that neighbour's box: on every axis where d points down
+// its coordinate is below lo+w, on every axis where d points up it is at or
+// above hi-w.  Per agent this is a 6-bit code (below lo+w / at or above hi-w
+// per axis); direction d needs the bits of its nonzero components.
+//
+// Kernels (all partitions in one launch each):
+//   k_sel_prep    one block: tiles per partition and their prefix
+//   k_sel_count   per 2048-agent tile: the 6-bit codes (1 byte/agent) and the
+//                 number of members per direction
+//   k_scan        look-back exclusive scan of the counts, laid out
+//                 [partition][direction][tile], which yields every tile's
+//                 output position in segment order
+//   k_sel_scatter per tile: stable compaction of store indices into the
+//                 segments, and the segment offsets
+#include "ta_internal.hpp"
+#include "ta_scratch.hpp"
+
+using namespace ta;
+
+namespace {
+
+constexpr int SEL_IPT = 8;
+constexpr int SEL_TILE = BLOCK * SEL_IPT;
+
+struct DirTable {
+  uint8_t req[26];  // code bits direction k requires
+};
+
+struct SelScratch {
+  uint8_t* code;       // [n_agents]
+  int64_t* tile_off;   // [P+1]
+  uint32_t* cnt;       // [cnt_cap]
+  uint64_t* cnt_pre;   // [cnt_cap+1]
+  int64_t* meta;       // [0] tiles, [1] count entries
+};
+
+__global__ __launch_bounds__(1024) void k_sel_prep(const int64_t* part_off, int32_t P, int32_t ndirs, int64_t n_agents,
+                                                   SelScratch sc, ClearFirst cf, uint32_t* status) {
+  __shared__ uint64_t s_w[16];
+  __shared__ int64_t s_carry;
+  __shared__ int s_bad;
+  do_clear_first(cf);
+  if (threadIdx.x == 0) {
+    s_carry = 0;
+    s_bad = part_off[0] != 0 || part_off[P] > n_agents;
+  }
+  __syncthreads();
+  for (int64_t p0 = 0; p0 < P; p0 += 1024) {
+    const int64_t p = p0 + threadIdx.x;
+    uint64_t nt = 0;
+    if (p < P) {
+      const int64_t len = part_off[p + 1] - part_off[p];
+      if (len < 0) s_bad = 1;
+      else nt = (uint64_t)((len + SEL_TILE - 1) / SEL_TILE);
+    }
+    const uint64_t incl = wave_incl_scan(nt);
+    if (lane_id() == 63) s_w[threadIdx.x / 64] = incl;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+    for (int i = 0; i < 16; ++i) {
+      pre += (i < (int)(threadIdx.x / 64)) ? s_w[i] : 0;
+      tot += s_w[i];
+    }
+    if (p < P) sc.tile_off[p] = s_carry + (int64_t)(pre + incl - nt);
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += (int64_t)tot;
+    __syncthreads();
+  }
+  __syncthreads();
+  if (s_bad) {
+    // invalid partition table: no tiles, every segment empty
+    for (int64_t p = threadIdx.x; p <= P; p += 1024) sc.tile_off[p] = 0;
+    if (threadIdx.x == 0) {
+      fail(status, ERR_INVALID);
+      sc.meta[0] = 0;
+      sc.meta[1] = 0;
+    }
+    return;
+  }
+  if (threadIdx.x == 0) {
+    sc.tile_off[P] = s_carry;
+    sc.meta[0] = s_carry;
+    sc.meta[1] = s_carry * ndirs;
+  }
+}
+
+struct TileInfo {
+  int64_t p, lt, nt, a0, a1;
+};
+
+__device__ inline TileInfo tile_info(const SelScratch& sc, const int64_t* part_off, int32_t P, int64_t t) {
+  TileInfo ti;
+  ti.p = last_le<int64_t>(sc.tile_off, 0, P, t);
+  ti.lt = t - sc.tile_off[ti.p];
+  ti.nt = sc.tile_off[ti.p + 1] - sc.tile_off[ti.p];
+  ti.a0 = part_off[ti.p] + ti.lt * SEL_TILE;
+  const int64_t e = part_off[ti.p + 1];
+  ti.a1 = ti.a0 + SEL_TILE < e ? ti.a0 + SEL_TILE : e;
+  return ti;
+}
+
+template <int NDIRS>
+__global__ __launch_bounds__(BLOCK) void k_sel_count(const double* f64, int64_t stride, const int64_t* part_off,
+                                                     const double* boxes, double w, int32_t P, DirTable dt,
+                                                     SelScratch sc) {
+  __shared__ uint32_t s_cnt[WAVES][NDIRS];
+  const int64_t ntiles = sc.meta[0];
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const TileInfo ti = tile_info(sc, part_off, P, t);
+    const double* box = boxes + 6 * ti.p;
+    const double tlo0 = box[0] + w, tlo1 = box[1] + w, tlo2 = box[2] + w;
+    const double thi0 = box[3] - w, thi1 = box[4] - w, thi2 = box[5] - w;
+    uint32_t cnt[NDIRS];
+#pragma unroll
+    for (int d = 0; d < NDIRS; ++d) cnt[d] = 0;
+#pragma unroll 2
+    for (int k = 0; k < SEL_IPT; ++k) {
+      const int64_t i = ti.a0 + (int64_t)k * BLOCK + threadIdx.x;
+      uint32_t code = 0;
+      if (i < ti.a1) {
+        const double x = f64[i], y = f64[stride + i], z = f64[2 * stride + i];
+        code = (uint32_t)(x < tlo0) | ((uint32_t)(x >= thi0) << 1) | ((uint32_t)(y < tlo1) << 2) |
+               ((uint32_t)(y >= thi1) << 3) | ((uint32_t)(z < tlo2) << 4) | ((uint32_t)(z >= thi2) << 5);
+        sc.code[i] = (uint8_t)code;
+      }
+      if (__ballot(code != 0) == 0) continue;
+#pragma unroll
+      for (int d = 0; d < NDIRS; ++d) cnt[d] += (uint32_t)__popcll(__ballot((code & dt.req[d]) == dt.req[d]));
+    }
+    if (lane_id() == 0) {
+#pragma unroll
+      for (int d = 0; d < NDIRS; ++d) s_cnt[wave_id()][d] = cnt[d];
+    }
+    __syncthreads();
+    if (threadIdx.x < NDIRS) {
+      const int d = threadIdx.x;
+      uint32_t sum = 0;
+#pragma unroll
+      for (int wv = 0; wv < WAVES; ++wv) sum += s_cnt[wv][d];
+      sc.cnt[sc.tile_off[ti.p] * NDIRS + d * ti.nt + ti.lt] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+struct CntIn {
+  const uint32_t* a;
+  __device__ uint64_t operator()(int64_t i) const { return a[i]; }
+};
+
+// Per-direction thread counts (<= 8) packed 5 to a word in 12-bit fields, so a
+// block-wide exclusive scan of NW words gives all directions at once (block
+// totals <= 2048 < 4096: no field overflows into the next).
+template <int NDIRS>
+__global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, int32_t P, DirTable dt, SelScratch sc,
+                                                       int32_t* idx_out, int64_t idx_cap, int64_t* seg_off,
+                                                       uint32_t* status) {
+  constexpr int NW = (NDIRS + 4) / 5;
+  __shared__ uint64_t s_w[WAVES][NW];
+  const int64_t nseg = (int64_t)P * NDIRS;
+  const int64_t gstride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s <= nseg; s += gstride) {
+    int64_t pos;
+    if (s == nseg) {
+      pos = (int64_t)sc.cnt_pre[sc.meta[1]];
+      if (pos > idx_cap) fail(status, ERR_CAPACITY);
+    } else {
+      const int64_t p = s / NDIRS, d = s % NDIRS;
+      const int64_t nt = sc.tile_off[p + 1] - sc.tile_off[p];
+      pos = (int64_t)sc.cnt_pre[sc.tile_off[p] * NDIRS + d * nt];
+    }
+    seg_off[s] = pos;
+  }
+  const int64_t ntiles = sc.meta[0];
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const TileInfo ti = tile_info(sc, part_off, P, t);
+    const int64_t i0 = ti.a0 + (int64_t)threadIdx.x * SEL_IPT;
+    uint32_t code[SEL_IPT];
+    uint64_t packed[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) packed[j] = 0;
+#pragma unroll
+    for (int k = 0; k < SEL_IPT; ++k) code[k] = (i0 + k < ti.a1) ? sc.code[i0 + k] : 0u;
+#pragma unroll
+    for (int d = 0; d < NDIRS; ++d) {
+      uint64_t c = 0;
+#pragma unroll
+      for (int k = 0; k < SEL_IPT; ++k) c += (code[k] & dt.req[d]) == dt.req[d] && code[k];
+      packed[d / 5] += c << (12 * (d % 5));
+    }
+    // block exclusive scan of the packed words
+    uint64_t incl[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) incl[j] = wave_incl_scan(packed[j]);
+    if (lane_id() == WAVE - 1) {
+#pragma unroll
+      for (int j = 0; j < NW; ++j) s_w[wave_id()][j] = incl[j];
+    }
+    __syncthreads();
+    uint64_t pre[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      uint64_t off = 0;
+#pragma unroll
+      for (int wv = 0; wv < WAVES; ++wv) off += (wv < wave_id()) ? s_w[wv][j] : 0;
+      pre[j] = off + incl[j] - packed[j];
+    }
+    __syncthreads();
+    const int64_t cbase = sc.tile_off[ti.p] * NDIRS + ti.lt;
+#pragma unroll
+    for (int d = 0; d < NDIRS; ++d) {
+      const uint64_t mine = (packed[d / 5] >> (12 * (d % 5))) & 0xFFF;
+      if (!mine) continue;
+      int64_t pos = (int64_t)sc.cnt_pre[cbase + d * ti.nt] + (int64_t)((pre[d / 5] >> (12 * (d % 5))) & 0xFFF);
+#pragma unroll
+      for (int k = 0; k < SEL_IPT; ++k) {
+        if (code[k] && (code[k] & dt.req[d]) == dt.req[d]) {
+          if (pos < idx_cap) idx_out[pos] = (int32_t)(i0 + k);
+          ++pos;
+        }
+      }
+    }
+  }
+}
+
+DirTable make_dirs(int ndirs) {
+  DirTable dt{};
+  int n = 0;
+  for (int c = 0; c < 27; ++c) {
+    if (c == 13) continue;
+    const int d[3] = {c % 3 - 1, (c / 3) % 3 - 1, c / 9 - 1};
+    const int nz = (d[0] != 0) + (d[1] != 0) + (d[2] != 0);
+    if (ndirs == 6 && nz != 1) continue;
+    uint8_t req = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (d[a] == -1) req |= (uint8_t)(1u << (2 * a));
+      if (d[a] == +1) req |= (uint8_t)(1u << (2 * a + 1));
+    }
+    dt.req[n++] = req;
+  }
+  return dt;
+}
+
+struct Sizes {
+  int64_t ntiles, cnt_cap;
+};
+Sizes sel_sizes(int64_t n, int64_t P, int ndirs) {
+  Sizes z;
+  z.ntiles = ceil_div(n, SEL_TILE) + P;
+  z.cnt_cap = z.ntiles * ndirs;
+  return z;
+}
+
+SelScratch carve(Arena& ar, int64_t n, int64_t P, int ndirs) {
+  const Sizes z = sel_sizes(n, P, ndirs);
+  SelScratch sc;
+  sc.code = ar.take<uint8_t>(n + 8);
+  sc.tile_off = ar.take<int64_t>(P + 1);
+  sc.cnt = ar.take<uint32_t>(z.cnt_cap);
+  sc.cnt_pre = ar.take<uint64_t>(z.cnt_cap + 1);
+  sc.meta = ar.take<int64_t>(4);
+  return sc;
+}
+
+}  // namespace
+
+namespace ta {
+size_t select_scratch(int64_t n, int64_t P, int ndirs, int64_t* tiles) {
+  Arena ar{nullptr, 0, 0};
+  carve(ar, n, P, ndirs);
+  *tiles = ceil_div(sel_sizes(n, P, ndirs).cnt_cap + 1, SCAN_TILE) + 1;
+  return ar.used + 256;
+}
+}  // namespace ta
+
+extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off,
+                                    const double* boxes, double w, int32_t ndirs, int32_t* idx_out, int64_t idx_cap,
+                                    int64_t* seg_off_out, void* stream) {
+  if (!c || !ag || P < 1 || (ndirs != 6 && ndirs != 26) || !part_off || !boxes || !seg_off_out || idx_cap < 0 ||
+      (idx_cap > 0 && !idx_out) || ag->n < 0 || ag->n > INT32_MAX || (ag->n > 0 && !ag->f64) ||
+      ag->f64_stride < ag->n || !(w == w))
+    return TA_ERR_INVALID;
+  int64_t tiles;
+  ta_status st = ensure_scratch(c, select_scratch(ag->n, P, ndirs, &tiles), tiles);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar{c->scratch, c->scratch_cap, 0};
+  SelScratch sc = carve(ar, ag->n, P, ndirs);
+  const DirTable dt = make_dirs(ndirs);
+  const int64_t cnt_cap = sel_sizes(ag->n, P, ndirs).cnt_cap;
+  const int g = grid_for(c, sel_sizes(ag->n, P, ndirs).ntiles, 1);
+  k_sel_prep<<<1, 1024, 0, s>>>(part_off, P, ndirs, ag->n, sc, clear_first(c), c->d_status);
+  {
+    Timed tm(c, "select_count", s);
+    if (ndirs == 26)
+      k_sel_count<26><<<g, BLOCK, 0, s>>>(ag->f64, ag->f64_stride, part_off, boxes, w, P, dt, sc);
+    else
+      k_sel_count<6><<<g, BLOCK, 0, s>>>(ag->f64, ag->f64_stride, part_off, boxes, w, P, dt, sc);
+  }
+  k_scan<CntIn><<<grid_for(c, cnt_cap + 1, SCAN_TILE), BLOCK, 0, s>>>(CntIn{sc.cnt}, sc.meta + 1, sc.cnt_pre,
+                                                                      lookback(c, 0));
+  {
+    Timed tm(c, "select_scatter", s);
+    const int gs = grid_for(c, std::max<int64_t>(sel_sizes(ag->n, P, ndirs).ntiles, ceil_div(P * ndirs + 1, BLOCK)), 1);
+    if (ndirs == 26)
+      k_sel_scatter<26><<<gs, BLOCK, 0, s>>>(part_off, P, dt, sc, idx_out, idx_cap, seg_off_out, c->d_status);
+    else
+      k_sel_scatter<6><<<gs, BLOCK, 0, s>>>(part_off, P, dt, sc, idx_out, idx_cap, seg_off_out, c->d_status);
+  }
+  TA_LAUNCH_CHECK();
+  return TA_OK;
+}

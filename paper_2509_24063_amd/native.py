@@ -1,0 +1,281 @@
+"""ctypes binding of libteraagent.so.
+
+Argument marshalling only: torch CUDA tensors provide device memory and the
+current stream; every step of the exchange runs in the library's HIP kernels.
+The library must be built (``__graft_entry__.build()``); nothing here falls
+back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "lib", "libteraagent.so")
+
+OK, INVALID, CAPACITY, CORRUPT, REF_MISMATCH, HIP = 0, 1, 2, 3, 4, 5
+NAMES = {0: "ok", 1: "invalid", 2: "capacity", 3: "corrupt", 4: "ref_mismatch", 5: "hip"}
+
+
+class TAError(RuntimeError):
+    def __init__(self, code, what=""):
+        super().__init__(f"{what}: {NAMES.get(code, code)}")
+        self.code = code
+
+
+class Agents(C.Structure):
+    _fields_ = [("n", C.c_int64), ("uid", C.c_void_p), ("cls", C.c_void_p), ("nb", C.c_void_p),
+                ("f64", C.c_void_p), ("f64_stride", C.c_int64), ("i32", C.c_void_p), ("i32_stride", C.c_int64),
+                ("beh_off", C.c_void_p), ("beh", C.c_void_p)]
+
+
+class ViewT(C.Structure):
+    _fields_ = [("n", C.c_int64), ("rec_words", C.c_int64), ("off", C.c_void_p), ("records", C.c_void_p)]
+
+
+class HistT(C.Structure):
+    _fields_ = [("h1", C.c_void_p), ("h2", C.c_void_p), ("hlen", C.c_void_p), ("cap", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"{LIB} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB)
+        vp, i64, i32, st = C.c_void_p, C.c_int64, C.c_int32, C.c_int
+        L.ta_create.argtypes = [C.POINTER(vp), C.c_uint32, vp, vp]
+        L.ta_destroy.argtypes = [vp]
+        L.ta_destroy.restype = None
+        L.ta_reserve.argtypes = [vp, i64, i64, i64, i64]
+        L.ta_status_poll.argtypes = [vp, vp]
+        L.ta_select_aura.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, C.c_double, i32, vp, i64, vp, vp]
+        L.ta_serialize.argtypes = [vp, C.POINTER(Agents), vp, vp, i64, i64, vp, i64, vp, vp]
+        L.ta_serialize_bound.argtypes = [i64, i64, i64]
+        L.ta_serialize_bound.restype = i64
+        L.ta_view.argtypes = [vp, i64, C.POINTER(ViewT)]
+        L.ta_view_validate.argtypes = [vp, vp, vp, i64, i64, vp]
+        L.ta_predictor_load.argtypes = [vp, vp, C.c_size_t, C.POINTER(vp)]
+        L.ta_predictor_free.argtypes = [vp]
+        L.ta_predictor_free.restype = None
+        L.ta_delta_encode.argtypes = [vp, i64, vp, i64, vp, vp, i64, vp, vp, C.POINTER(HistT), C.POINTER(HistT),
+                                      vp, i64, vp, vp, i64, vp, vp, vp]
+        L.ta_delta_bound.argtypes = [i64, i64, i64]
+        L.ta_delta_bound.restype = i64
+        L.ta_delta_decode.argtypes = [vp, i64, vp, i64, vp, vp, i64, vp, vp, C.POINTER(HistT), C.POINTER(HistT),
+                                      vp, i64, vp, vp]
+        L.ta_time_kernel.argtypes = [vp, C.c_char_p]
+        L.ta_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        for f in ("ta_create", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_serialize", "ta_view",
+                  "ta_view_validate", "ta_predictor_load", "ta_delta_encode", "ta_delta_decode", "ta_time_kernel",
+                  "ta_kernel_time"):
+            getattr(L, f).restype = st
+        _lib = L
+    return _lib
+
+
+def _p(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr()) if t.numel() else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(code, what):
+    if code:
+        raise TAError(code, what)
+
+
+class DeviceStore:
+    """An agent store (see synth.Store) copied to device tensors."""
+
+    def __init__(self, store, device="cuda"):
+        def up(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)
+        self.n = store.n
+        self.P = store.P
+        self.uid = up(store.uid, np.int64)
+        self.cls = up(store.cls, np.int16)
+        self.nb = up(store.nb, np.int16)
+        self.f64 = up(store.f64, np.float64)
+        self.i32 = up(store.i32, np.int32)
+        self.beh_off = up(store.beh_off, np.int64)
+        beh = store.beh if store.beh.size else np.zeros(8, np.uint8)
+        self.beh = up(beh, np.uint8)
+        self.part_off = up(store.part_off, np.int64)
+        self.boxes = up(np.ascontiguousarray(store.boxes, np.float64).reshape(-1), np.float64)
+        bw = np.diff(store.beh_off) // 8
+        self.max_beh_words = int(bw.max()) if bw.size else 0
+        self._s = Agents(self.n, _p(self.uid), _p(self.cls), _p(self.nb), _p(self.f64), self.f64.shape[1],
+                         _p(self.i32), self.i32.shape[1], _p(self.beh_off), _p(self.beh))
+
+    def agents(self):
+        return self._s
+
+
+class History:
+    """Predictor history on the device: h1, h2 int64[n,4] (fp64 bits), hlen uint8[n]."""
+
+    def __init__(self, n, device="cuda"):
+        self.h1 = torch.zeros((max(n, 1), 4), dtype=torch.int64, device=device)
+        self.h2 = torch.zeros((max(n, 1), 4), dtype=torch.int64, device=device)
+        self.hlen = torch.zeros(max(n, 1), dtype=torch.uint8, device=device)
+        self.n = n
+
+    def struct(self):
+        return HistT(_p(self.h1), _p(self.h2), _p(self.hlen), self.n)
+
+
+class Predictor:
+    def __init__(self, ctx, blob: bytes):
+        b = (C.c_uint8 * len(blob)).from_buffer_copy(blob)
+        h = C.c_void_p()
+        _check(lib().ta_predictor_load(ctx.h, b, len(blob), C.byref(h)), "ta_predictor_load")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ta_predictor_free(self.h)
+            self.h = None
+
+
+class Context:
+    def __init__(self, schema):
+        nf = (C.c_uint16 * len(schema.n_f64))(*schema.n_f64)
+        ni = (C.c_uint16 * len(schema.n_i32))(*schema.n_i32)
+        h = C.c_void_p()
+        _check(lib().ta_create(C.byref(h), len(schema.n_f64), nf, ni), "ta_create")
+        self.h = h
+        self.max_f = max(schema.n_f64)
+        self.max_i = max(schema.n_i32)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ta_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, max_agents, max_segments, max_records, max_msg_bytes):
+        _check(lib().ta_reserve(self.h, max_agents, max_segments, max_records, max_msg_bytes), "ta_reserve")
+
+    def poll(self) -> int:
+        return lib().ta_status_poll(self.h, _stream())
+
+    def check(self, what="exchange"):
+        _check(self.poll(), what)
+
+    # -- the exchange --------------------------------------------------------
+    def select_aura(self, ds: DeviceStore, w: float, ndirs: int, idx_cap: int | None = None, out=None):
+        if idx_cap is None:
+            idx_cap = max(64, 26 * ds.n)
+        idx = out[0] if out is not None else torch.empty(max(idx_cap, 1), dtype=torch.int32, device=ds.uid.device)
+        seg_off = out[1] if out is not None else torch.empty(ds.P * ndirs + 1, dtype=torch.int64,
+                                                             device=ds.uid.device)
+        _check(lib().ta_select_aura(self.h, C.byref(ds.agents()), ds.P, _p(ds.part_off), _p(ds.boxes), float(w),
+                                    ndirs, _p(idx), idx_cap, _p(seg_off), _stream()), "ta_select_aura")
+        return idx, seg_off
+
+    def serialize_bound(self, ds: DeviceStore, nseg: int, idx_cap: int) -> int:
+        words = 2 + self.max_f + (self.max_i + 1) // 2 + ds.max_beh_words
+        return int(lib().ta_serialize_bound(nseg, idx_cap, words))
+
+    def serialize(self, ds: DeviceStore, idx, seg_off, idx_cap: int | None = None, out_cap: int | None = None,
+                  out=None):
+        nseg = seg_off.numel() - 1
+        if idx_cap is None:
+            idx_cap = idx.numel()
+        if out is None:
+            if out_cap is None:
+                out_cap = self.serialize_bound(ds, nseg, idx_cap)
+            buf = torch.empty(max(out_cap, 8), dtype=torch.uint8, device=seg_off.device)
+            msg_off = torch.empty(nseg + 1, dtype=torch.int64, device=seg_off.device)
+        else:
+            buf, msg_off = out
+            out_cap = buf.numel()
+        _check(lib().ta_serialize(self.h, C.byref(ds.agents()), _p(idx), _p(seg_off), nseg, idx_cap, _p(buf),
+                                  out_cap, _p(msg_off), _stream()), "ta_serialize")
+        return buf, msg_off
+
+    def delta_encode(self, cur, cur_off, ref, ref_off, pred: Predictor | None = None, hist: History | None = None,
+                     hist_out: History | None = None, out=None, enc_cap=None):
+        nseg = cur_off.numel() - 1
+        dev = cur.device
+        if out is None:
+            if enc_cap is None:
+                enc_cap = int(lib().ta_delta_bound(nseg, cur.numel(), ref.numel()))
+            enc = torch.empty(max(enc_cap, 8), dtype=torch.uint8, device=dev)
+            enc_off = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
+            newref = torch.empty(max(cur.numel(), 8), dtype=torch.uint8, device=dev)
+            newref_off = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
+            modes = torch.empty(max(nseg, 1), dtype=torch.uint8, device=dev)
+        else:
+            enc, enc_off, newref, newref_off, modes = out
+        hs = hist.struct() if hist is not None else None
+        ho = hist_out.struct() if hist_out is not None else None
+        _check(lib().ta_delta_encode(self.h, nseg, _p(cur), cur.numel(), _p(cur_off), _p(ref), ref.numel(),
+                                     _p(ref_off), pred.h if pred is not None else None,
+                                     C.byref(hs) if hs is not None else None, C.byref(ho) if ho is not None else None,
+                                     _p(enc), enc.numel(), _p(enc_off), _p(newref), newref.numel(), _p(newref_off),
+                                     _p(modes), _stream()), "ta_delta_encode")
+        return enc, enc_off, newref, newref_off, modes
+
+    def delta_decode(self, enc, enc_off, ref, ref_off, pred: Predictor | None = None, hist: History | None = None,
+                     hist_out: History | None = None, out=None, out_cap=None):
+        nseg = enc_off.numel() - 1
+        dev = enc.device
+        if out is None:
+            if out_cap is None:
+                out_cap = ref.numel() + enc.numel() + 8 * nseg + 64
+            buf = torch.empty(max(out_cap, 8), dtype=torch.uint8, device=dev)
+            off = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
+        else:
+            buf, off = out
+        hs = hist.struct() if hist is not None else None
+        ho = hist_out.struct() if hist_out is not None else None
+        _check(lib().ta_delta_decode(self.h, nseg, _p(enc), enc.numel(), _p(enc_off), _p(ref), ref.numel(),
+                                     _p(ref_off), pred.h if pred is not None else None,
+                                     C.byref(hs) if hs is not None else None, C.byref(ho) if ho is not None else None,
+                                     _p(buf), buf.numel(), _p(off), _stream()), "ta_delta_decode")
+        return buf, off
+
+    def view(self, buf, start: int, length: int):
+        v = ViewT()
+        ptr = C.c_void_p(buf.data_ptr() + start)
+        _check(lib().ta_view(ptr, length, C.byref(v)), "ta_view")
+        return v
+
+    def validate(self, buf, off):
+        nseg = off.numel() - 1
+        _check(lib().ta_view_validate(self.h, _p(buf), _p(off), nseg, buf.numel(), _stream()), "ta_view_validate")
+
+    def time_kernel(self, name: str | None):
+        _check(lib().ta_time_kernel(self.h, name.encode() if name else None), "ta_time_kernel")
+
+    def kernel_time(self):
+        n, ms = C.c_int64(0), C.c_double(0)
+        _check(lib().ta_kernel_time(self.h, C.byref(n), C.byref(ms)), "ta_kernel_time")
+        return n.value, ms.value
+
+
+def empty_messages(nseg: int, device="cuda"):
+    """nseg empty TAM1 messages: the reference before the first exchange."""
+    one = np.zeros(32, np.uint8)
+    one[:4] = np.frombuffer(b"TAM1", np.uint8)
+    one[4] = 1
+    buf = torch.from_numpy(np.tile(one, max(nseg, 1))).to(device)
+    off = torch.arange(nseg + 1, dtype=torch.int64, device=device) * 32
+    return buf, off

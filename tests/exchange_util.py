@@ -1,0 +1,68 @@
+"""Helpers for the GPU parity tests: one exchange through the HIP library and
+the same exchange through the oracle, and byte comparisons of every buffer."""
+import numpy as np
+
+import oracle
+
+
+def host(t, off=None):
+    if off is None:
+        return t.cpu().numpy()
+    end = int(off[-1])
+    return t[:end].cpu().numpy()
+
+
+class GpuSide:
+    """Sender and receiver on the GPU: references kept on the device."""
+
+    def __init__(self, ctx, nseg, device="cuda"):
+        from paper_2509_24063_amd import native
+        self.ctx = ctx
+        self.ref, self.ref_off = native.empty_messages(nseg, device)
+        self.rx_ref, self.rx_ref_off = self.ref, self.ref_off
+
+    def step(self, ds, cfg, idx_cap=None):
+        ctx = self.ctx
+        idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=idx_cap)
+        buf, moff = ctx.serialize(ds, idx, seg)
+        enc, eoff, nref, noff, modes = ctx.delta_encode(buf, moff, self.ref, self.ref_off)
+        dec, doff = ctx.delta_decode(enc, eoff, self.rx_ref, self.rx_ref_off)
+        ctx.check("exchange")
+        out = dict(idx=idx, seg=seg, buf=buf, moff=moff, enc=enc, eoff=eoff, nref=nref, noff=noff, dec=dec,
+                   doff=doff)
+        self.ref, self.ref_off = nref, noff
+        self.rx_ref, self.rx_ref_off = dec, doff
+        return out
+
+
+class OracleSide:
+    def __init__(self, nseg):
+        self.ref, self.ref_off = oracle.empty_messages(nseg)
+
+    def step(self, store, cfg):
+        idx, seg = oracle.select_aura(store, cfg.w, cfg.ndirs)
+        buf, moff = oracle.serialize(store, cfg.schema, idx, seg)
+        enc, eoff, nref, noff, modes, _ = oracle.encode_all(buf, moff, self.ref, self.ref_off)
+        dec, doff, _ = oracle.decode_all(enc, eoff, self.ref, self.ref_off)
+        assert np.array_equal(dec, nref)
+        out = dict(idx=idx, seg=seg, buf=buf, moff=moff, enc=enc, eoff=eoff, nref=nref, noff=noff)
+        self.ref, self.ref_off = nref, noff
+        return out
+
+
+def assert_same(g, o, tag=""):
+    seg = host(g["seg"])
+    assert np.array_equal(seg, o["seg"]), f"{tag}: segment offsets"
+    assert np.array_equal(host(g["idx"])[: int(seg[-1])], o["idx"]), f"{tag}: selected indices"
+    moff = host(g["moff"])
+    assert np.array_equal(moff, o["moff"]), f"{tag}: message offsets"
+    assert np.array_equal(host(g["buf"], moff), o["buf"]), f"{tag}: TAM1 messages"
+    eoff = host(g["eoff"])
+    assert np.array_equal(eoff, o["eoff"]), f"{tag}: encoding offsets"
+    assert np.array_equal(host(g["enc"], eoff), o["enc"]), f"{tag}: TAD1 encodings"
+    noff = host(g["noff"])
+    assert np.array_equal(noff, o["noff"]), f"{tag}: C' offsets (sender)"
+    assert np.array_equal(host(g["nref"], noff), o["nref"]), f"{tag}: C' (sender)"
+    doff = host(g["doff"])
+    assert np.array_equal(doff, o["noff"]), f"{tag}: C' offsets (receiver)"
+    assert np.array_equal(host(g["dec"], doff), o["nref"]), f"{tag}: C' (receiver)"

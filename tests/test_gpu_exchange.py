@@ -1,0 +1,236 @@
+"""GPU parity: the HIP library against the oracle, byte for byte, through the
+C ABI.  Every buffer of every exchange is compared: selected indices and
+segment offsets, TAM1 messages, TAD1 encodings, the sender's C' and the C'
+the receiver rebuilds."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_24063_amd import synth
+from tests.exchange_util import GpuSide, OracleSide, assert_same, host
+from tests.test_oracle_delta import rec, tam1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def native():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_24063_amd import native as n
+    n.lib()
+    return n
+
+
+def _run(native, cfg, iterations, tag, idx_cap=None, max_agents=None):
+    world = synth.World(cfg, max_agents=max_agents)
+    ctx = native.Context(cfg.schema)
+    nseg = world.store.P * cfg.ndirs
+    gs, os_ = GpuSide(ctx, nseg), OracleSide(nseg)
+    for it in range(iterations):
+        print(f"[{tag}] iteration {it}: {world.store.n} agents, {nseg} segments", flush=True)
+        ds = native.DeviceStore(world.store)
+        g = gs.step(ds, cfg, idx_cap=idx_cap)
+        o = os_.step(world.store, cfg)
+        assert_same(g, o, f"{tag} it {it}")
+        world.step()
+    ctx.close()
+
+
+def test_config1_iterations(native):
+    _run(native, synth.config(1), 5, "cfg1")
+
+
+def test_batched_uneven_partitions(native):
+    # the 8x8x8 periodic layout with lognormal sizes, scaled down
+    _run(native, synth.config(3, median=300.0), 3, "cfg3-small")
+
+
+def test_heterogeneous_variable_records(native):
+    # spheres and cylinders, 14 fields each, 0..4 behaviours of 1..7 payload words
+    _run(native, synth.config(5, median=400.0, grid=(4, 4, 2)), 3, "cfg5-small")
+
+
+def test_face_and_corner_edge_cases(native):
+    # tiny partitions (several empty segments, boxes narrower than 2w)
+    cfg = synth.config(3, median=3.0, sigma=1.0, side=40.0)
+    _run(native, cfg, 3, "tiny")
+
+
+def test_full_size_config2(native):
+    """1e7 agents, 26 directions: the benchmark's launch configuration, full parity."""
+    cfg = synth.config(2)
+    _run(native, cfg, 2, "cfg2", idx_cap=int(0.3 * 1e7) + 4096)
+
+
+def _upload(native, msgs):
+    import torch
+    buf, off = oracle.join([np.asarray(m, np.uint8) for m in msgs])
+    return (torch.from_numpy(buf if buf.size else np.zeros(8, np.uint8)).cuda(),
+            torch.from_numpy(off).cuda())
+
+
+def test_handmade_messages(native):
+    a = [rec(u, x=float(u)) for u in range(1, 70)]
+    cases = [
+        ([], []), (a, []), ([], a), (a, a), ([rec(u + 1000) for u in range(1, 50)], a),
+        ([rec(1, x=2.0)], [rec(1)]), (a[::-1], a), ([rec(5, words=9)] + a[5:], a),
+    ]
+    for words in (2, 3, 5):
+        n = 64 * 3 // words + 1
+        r = [rec(u, words=words, fill=u) for u in range(1, n + 1)]
+        c = [list(x) for x in r]
+        for x in c:
+            x[-1] ^= 0xFF00FF
+        cases.append((c, r))
+    curs = [tam1(c) for c, _ in cases]
+    refs = [tam1(r) for _, r in cases]
+    ctx = native.Context(synth.Schema((4,), (1,)))
+    cur, coff = _upload(native, curs)
+    ref, roff = _upload(native, refs)
+    print("[handmade] encode/decode", len(cases), "segments", flush=True)
+    enc, eoff, nref, noff, _ = ctx.delta_encode(cur, coff, ref, roff)
+    dec, doff = ctx.delta_decode(enc, eoff, ref, roff)
+    ctx.check("handmade")
+    oenc, oeoff, onref, onoff, _, _ = oracle.encode_all(*oracle.join(curs), *oracle.join(refs))
+    assert np.array_equal(host(eoff), oeoff)
+    assert np.array_equal(host(enc, host(eoff)), oenc)
+    assert np.array_equal(host(nref, host(noff)), onref)
+    assert np.array_equal(host(dec, host(doff)), onref)
+    ctx.close()
+
+
+def test_error_statuses(native):
+    import torch
+    ctx = native.Context(synth.Schema((4,), (1,)))
+    r = [rec(u, x=float(u), words=8) for u in range(1, 300)]
+    c = [list(x) for x in r[20:]] + [rec(900 + u) for u in range(7)]
+    for x in c:
+        x[2] ^= 0x5A5A5A
+    ref, roff = _upload(native, [tam1(r)])
+    cur, coff = _upload(native, [tam1(c)])
+    print("[errors] duplicate uid", flush=True)
+    dup, doff_ = _upload(native, [tam1([rec(3), rec(3)])])
+    ctx.delta_encode(dup, doff_, ref, roff)
+    assert ctx.poll() == native.INVALID
+    zero, zoff = _upload(native, [tam1([rec(0)])])
+    ctx.delta_encode(zero, zoff, ref, roff)
+    assert ctx.poll() == native.INVALID
+    print("[errors] small capacity", flush=True)
+    ctx.delta_encode(cur, coff, ref, roff, enc_cap=200)
+    assert ctx.poll() == native.CAPACITY
+    enc, eoff, nref, noff, _ = ctx.delta_encode(cur, coff, ref, roff)
+    ctx.check("encode")
+    e = host(enc, host(eoff))
+    print("[errors] truncated / other reference", flush=True)
+    tr, troff = _upload(native, [e[:-8]])
+    ctx.delta_decode(tr, troff, ref, roff)
+    assert ctx.poll() == native.CORRUPT
+    other, ooff = _upload(native, [tam1(r[:-1] + [rec(5000, words=8)])])
+    ctx.delta_decode(enc, eoff, other, ooff)
+    assert ctx.poll() == native.REF_MISMATCH
+    ctx.delta_decode(enc, eoff, ref, roff, out_cap=64)
+    assert ctx.poll() == native.CAPACITY
+    ctx.close()
+
+
+def test_damaged_encodings_match_oracle_status(native):
+    """Random single-bit damage: the GPU reports the oracle's status, and
+    equal output whenever the damage still decodes."""
+    rng = np.random.default_rng(12)
+    r = [rec(u, x=float(rng.random()), words=int(rng.integers(6, 11))) for u in range(1, 400)]
+    c = [list(x) for x in r[10:]]
+    for x in c:
+        x[2] ^= int(rng.integers(1, 1 << 44))
+        x[3] ^= int(rng.integers(0, 1 << 20))
+    c += [rec(900 + u, words=int(rng.integers(2, 9))) for u in range(9)]
+    R, Cm = tam1(r), tam1(c)
+    st, e, _, _, _ = oracle.delta_encode(Cm, R)
+    assert st == 0
+    damaged, expect = [], []
+    for _ in range(200):
+        bad = e.copy()
+        bad[rng.integers(0, e.size)] ^= np.uint8(1 << rng.integers(0, 8))
+        damaged.append(bad)
+        expect.append(oracle.delta_decode(bad, R))
+    ctx = native.Context(synth.Schema((4,), (1,)))
+    ref, roff = _upload(native, [R])
+    print("[damage] 200 single-bit variants", flush=True)
+    for k, bad in enumerate(damaged):
+        enc, eoff = _upload(native, [bad])
+        dec, doff = ctx.delta_decode(enc, eoff, ref, roff)
+        st = ctx.poll()
+        assert st == expect[k][0], (k, st, expect[k][0])
+        if st == 0:
+            assert np.array_equal(host(dec, host(doff)), expect[k][1])
+    ctx.close()
+
+
+def test_selection_and_serialize_capacity(native):
+    cfg = synth.config(1, median=2000.0)
+    w = synth.World(cfg)
+    ds = native.DeviceStore(w.store)
+    ctx = native.Context(cfg.schema)
+    print("[capacity] select", flush=True)
+    idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=10)
+    assert ctx.poll() == native.CAPACITY
+    oidx, oseg = oracle.select_aura(w.store, cfg.w, cfg.ndirs)
+    assert np.array_equal(host(seg), oseg)        # sizes are still reported
+    idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs)
+    ctx.check("select")
+    buf, moff = ctx.serialize(ds, idx, seg, out_cap=1000)
+    assert ctx.poll() == native.CAPACITY
+    ctx.close()
+
+
+def test_runs_are_deterministic(native):
+    cfg = synth.config(5, median=300.0, grid=(2, 2, 2))
+    outs = []
+    for rep in range(2):
+        w = synth.World(cfg)
+        ctx = native.Context(cfg.schema)
+        gs = GpuSide(ctx, w.store.P * cfg.ndirs)
+        res = []
+        for it in range(2):
+            g = gs.step(native.DeviceStore(w.store), cfg)
+            res.append([host(g["buf"], host(g["moff"])), host(g["enc"], host(g["eoff"])),
+                        host(g["dec"], host(g["doff"]))])
+            w.step()
+        outs.append(res)
+        ctx.close()
+    for a, b in zip(*outs):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_view_reads_and_mutates_in_place(native):
+    import torch
+    cfg = synth.config(1, median=1000.0)
+    w = synth.World(cfg)
+    ds = native.DeviceStore(w.store)
+    ctx = native.Context(cfg.schema)
+    idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs)
+    buf, moff = ctx.serialize(ds, idx, seg)
+    ctx.validate(buf, moff)
+    ctx.check("validate")
+    mo = host(moff)
+    v = ctx.view(buf, int(mo[1]), int(mo[2] - mo[1]))
+    n = v.n
+    assert n == int(host(seg)[2] - host(seg)[1])
+    offs = torch.tensor(np.frombuffer(host(buf)[mo[1] + 32: mo[1] + 32 + 4 * n].tobytes(), np.uint32).astype(np.int64))
+    body = int(mo[1]) + 32 + 8 * ((n + 1) // 2)
+    assert v.records - buf.data_ptr() == body
+    # field 0 (x) of record 3, read and changed in place through the offsets
+    words = buf[body:body + 8 * v.rec_words].view(torch.float64)
+    k = int(offs[3]) + 2
+    a = int(host(idx)[int(host(seg)[1]) + 3])
+    assert float(words[k]) == float(w.store.f64[0, a])
+    words[k] = 123.5
+    assert float(buf[body + 8 * k: body + 8 * k + 8].view(torch.float64)[0]) == 123.5
+    # a broken offset is caught by the full validation
+    bad = buf.clone()
+    bad[int(mo[1]) + 36] += 1
+    ctx.validate(bad, moff)
+    assert ctx.poll() == native.INVALID
+    ctx.close()
