@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--agents", type=float, default=1e7)
-    ap.add_argument("--roofline-kernel", default="encode_xor")
+    ap.add_argument("--roofline-kernel", default="encode_resid")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     return ap.parse_args()
@@ -75,9 +75,7 @@ def main():
     u8 = dict(dtype=torch.uint8, device=dev)
     i64 = dict(dtype=torch.int64, device=dev)
     idx = torch.empty(idx_cap, dtype=torch.int32, device=dev)
-    seg = torch.empty(nseg + 1, **i64)
     buf = torch.empty(ser_cap, **u8)
-    moff = torch.empty(nseg + 1, **i64)
     # per step outputs kept for the byte accounting after the timed region
     encs = [torch.empty(enc_cap, **u8) for _ in range(nstates)]
     eoffs = [torch.empty(nseg + 1, **i64) for _ in range(nstates)]
@@ -98,15 +96,13 @@ def main():
     def step(k):
         ds = dev_states[k]
         cur_ref, nxt = (k + 1) % 2, k % 2
-        ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=idx_cap, out=(idx, seg))
+        ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=idx_cap, out=(idx, seg_hist[k]))
         ev[k][0].record()
-        ctx.serialize(ds, idx, seg, idx_cap=idx_cap, out=(buf, moff))
-        ctx.delta_encode(buf, moff, refs[cur_ref], roffs[cur_ref],
+        ctx.serialize(ds, idx, seg_hist[k], idx_cap=idx_cap, out=(buf, moff_hist[k]))
+        ctx.delta_encode(buf, moff_hist[k], refs[cur_ref], roffs[cur_ref],
                          out=(encs[k], eoffs[k], refs[nxt], roffs[nxt], modes))
         ev[k][1].record()
         ctx.delta_decode(encs[k], eoffs[k], rx[cur_ref], rxoffs[cur_ref], out=(rx[nxt], rxoffs[nxt]))
-        seg_hist[k].copy_(seg)
-        moff_hist[k].copy_(moff)
 
     for k in range(args.warmup):
         step(k)
@@ -129,10 +125,9 @@ def main():
     timed = range(args.warmup, nstates)
     records = 0
     ser_bytes = enc_bytes = dec_bytes = sel_bytes = 0
-    W_total = var_total = 0
+    W_total = var_total = match_total = groups_total = 0
     tad_total = msg_total = 0
     sd_ms = 0.0
-    prev_msg = None
     for k in timed:
         s_h = seg_hist[k].cpu().numpy()
         mo = moff_hist[k].cpu().numpy()
@@ -146,6 +141,8 @@ def main():
             h = np.frombuffer(hdrs[eo[sgi]:eo[sgi] + 64].tobytes(), np.uint64)
             W_total += int(h[5])
             var_total += int(h[7])
+            match_total += int(h[1]) >> 32
+            groups_total += (int(h[5]) + 63) // 64
         tad_total += T
         msg_total += M
         # the reference is the previous step's C', which has the size of that step's messages
@@ -165,11 +162,21 @@ def main():
     value = records / elapsed
     sd_gbps = (ser_bytes + enc_bytes) / (sd_ms / 1000.0) / 1e9
     kernel_avg_ms = kernel_ms / max(launches, 1)
-    if args.roofline_kernel == "encode_xor":
-        # reads C and R residual words, writes C' words and the group blocks
-        kb = (24 * W_total + var_total) / max(launches, 1)
-    else:
-        kb = float("nan")
+    # algorithmic bytes of one launch of each measured kernel
+    per_kernel = {
+        # read C and R words of matched records and their directory entries,
+        # write C' words and the residual
+        "encode_resid": 32 * W_total + 40 * match_total,
+        # read the residual, write the group blocks, bitmaps, sizes, offsets
+        "encode_pack": 8 * W_total + var_total + 17 * groups_total,
+        # read the residual, R words and directory entries, write C' words
+        "decode_apply": 32 * W_total + 40 * match_total,
+        # read the group blocks and their tables, write the residual
+        "decode_unpack": 8 * W_total + var_total + 17 * groups_total,
+        # gather the agents' fields (about the record bytes), indices, offsets; write records + offsets
+        "serialize_pack": 2 * msg_total + 32 * records,
+    }
+    kb = per_kernel.get(args.roofline_kernel, float("nan")) / max(launches, 1)
     achieved = kb / (kernel_avg_ms / 1000.0) / 1e9 if kernel_avg_ms > 0 else 0.0
     out = {
         "metric": METRIC,

@@ -56,7 +56,9 @@ LookBack lookback(ta_ctx* c, int k) {
   return lb;
 }
 
-ClearFirst clear_first(ta_ctx* c) { return ClearFirst{c->d_lb[0], c->d_tickets, c->lb_cap}; }
+ClearFirst clear_first(ta_ctx* c, int64_t tiles) {
+  return ClearFirst{c->d_lb[0], c->d_tickets, tiles + 1 < c->lb_cap ? tiles + 1 : c->lb_cap};
+}
 
 Timed::Timed(ta_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stream) {
   on = !c->timed.empty() && c->timed == name;

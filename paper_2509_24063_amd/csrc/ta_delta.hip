@@ -39,11 +39,11 @@ namespace {
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int PK = 34;  // packed scan value: count << 34 | words
 constexpr uint64_t WMASK = (1ull << PK) - 1;
-constexpr int XG = 4;                 // groups per wave in the xor/unpack kernels
-constexpr int TILE_G = WAVES * XG;    // groups per tile
 constexpr int BLK_MAX = 544;          // 32 nibble bytes + 512 significant bytes
 constexpr uint32_t ANY_ERR = (1u << ERR_INVALID) | (1u << ERR_CAPACITY) | (1u << ERR_CORRUPT) | (1u << ERR_REF) |
                              (1u << ERR_INTERNAL);
+
+constexpr int FOLD_SLOTS = 16;
 
 struct Entry {
   unsigned long long key;
@@ -66,14 +66,27 @@ struct Seg {
   uint64_t rfold;             // decoder: XOR of the reference uids it holds
   uint64_t var;               // decoder: group block bytes announced by the header
   uint64_t size_plain, size_learned;  // encoder, learned mode: block bytes both ways
+  uint64_t jB, jT, jTC, jTJ;  // join: buckets, count tiles (C tiles first), items per tile
+  uint64_t jebase;            // join: first count entry of the segment
+  uint64_t fold_part[FOLD_SLOTS];  // partial XORs of reference uids (spread to avoid atomic contention)
+  uint64_t cpw;               // word index of C' for residual position 0 (C' word of position d = cpw + d)
 };
 
 struct MDir {
   uint64_t cword;   // encoder: C record word index in cur; decoder: unused
   uint64_t rword;   // R record word index in ref
   uint64_t dstart;  // global residual word position of the record
-  uint64_t g;       // global reference slot
+  uint64_t gs;      // global reference slot | segment << 34
 };
+__device__ inline int64_t mdir_seg(const MDir& e) { return (int64_t)(e.gs >> 34); }
+[[maybe_unused]] __device__ inline uint64_t mdir_slot(const MDir& e) { return e.gs & ((1ull << 34) - 1); }
+
+// wave-local ordering of LDS accesses (all lanes of one wave)
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 __device__ inline uint64_t mix64(uint64_t x) {
   x ^= x >> 31;
@@ -92,16 +105,25 @@ __device__ inline int64_t seg_of(const uint64_t* pre, int64_t nseg, uint64_t g) 
 
 // XOR-reduce v over the lanes of this wave that belong to the same segment and
 // fold it into dst[segment] with one atomic per segment present in the wave.
+// fold_base points at slot 0 of segment 0; the wave adds into one of
+// FOLD_SLOTS slots chosen by its position so waves rarely share an address.
 __device__ inline void seg_xor(uint64_t* fold_base, size_t stride_words, int64_t s, bool active, uint64_t v) {
   uint64_t pending = __ballot(active);
+  const uint32_t slot = (blockIdx.x * WAVES + wave_id()) % FOLD_SLOTS;
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
     const int64_t s0 = __shfl(s, leader, WAVE);
     const bool mine = active && s == s0;
     const uint64_t part = wave_xor(mine ? v : 0);
-    if (lane_id() == leader) atomicXor((unsigned long long*)(fold_base + stride_words * s0), (unsigned long long)part);
+    if (lane_id() == leader && part)
+      atomicXor((unsigned long long*)(fold_base + stride_words * s0 + slot), (unsigned long long)part);
     pending &= ~__ballot(mine);
   }
+}
+__device__ inline uint64_t fold_of(const uint64_t* parts) {
+  uint64_t f = 0;
+  for (int i = 0; i < FOLD_SLOTS; ++i) f ^= parts[i];
+  return f;
 }
 
 struct Common {
@@ -112,10 +134,23 @@ struct Common {
   uint64_t* gpre;  // [nseg+1] residual group prefixes
   uint64_t* ppre;  // [nseg+1] presence word prefixes
   uint64_t* npre;  // [nseg+1] new record prefixes
+  uint64_t* tpre;  // [nseg+1] join count tiles
+  uint64_t* bpre;  // [nseg+1] join buckets
   int64_t* meta;   // [0] C records [1] R records [2] hash slots [3] groups [4] presence words [5] matched
-                   // [6] new records [7] new words [8] C+R records
+                   // [6] new records [7] new words [8] C+R records [9] fixed bytes [10] join tiles
+                   // [11] join count entries [12] join buckets [13] join bucket overflow
   uint32_t* status;
 };
+
+// Partitioned join: every segment's C and R uids are split into B hash
+// buckets (mean <= JB_TARGET items), and one block joins each bucket in LDS.
+constexpr int JT = 2048;          // minimum items per counting tile
+constexpr int JT_MAX_TILES = 64;  // counting tiles per segment side at most
+constexpr int JB_TARGET = 1024;
+constexpr int JB_MAX = 8192;      // buckets per segment (LDS histogram)
+constexpr int JCAP = 3072;        // items of one bucket held in LDS
+constexpr int JTAB = 4096;        // LDS hash slots
+__device__ inline uint32_t join_bucket(uint64_t uid, uint64_t B) { return (uint32_t)(mix64(uid) & (B - 1)); }
 
 // ---------------------------------------------------------------------------
 // one block of 1024 threads: per segment values and their prefixes
@@ -145,14 +180,14 @@ __global__ __launch_bounds__(1024) void k_enc_setup(Common cm, const uint8_t* cu
                                                     const int64_t* cur_off, const uint8_t* ref, int64_t ref_len,
                                                     const int64_t* ref_off, ClearFirst cf) {
   __shared__ uint64_t s_w[16];
-  __shared__ uint64_t s_carry[3];
+  __shared__ uint64_t s_carry[6];
   BlockScan1024 bs{s_w};
   do_clear_first(cf);
-  if (threadIdx.x < 3) s_carry[threadIdx.x] = 0;
+  if (threadIdx.x < 6) s_carry[threadIdx.x] = 0;
   __syncthreads();
   for (int64_t s0 = 0; s0 < cm.nseg; s0 += 1024) {
     const int64_t s = s0 + threadIdx.x;
-    uint64_t nc = 0, nr = 0, hs = 0;
+    uint64_t nc = 0, nr = 0, hs = 0, jt = 0, je = 0, jb = 0;
     if (s < cm.nseg) {
       Seg& g = cm.seg[s];
       const int64_t ca = cur_off[s], cb = cur_off[s + 1], ra = ref_off[s], rb = ref_off[s + 1];
@@ -185,35 +220,63 @@ __global__ __launch_bounds__(1024) void k_enc_setup(Common cm, const uint8_t* cu
       hs = pow2ceil(2 * (nc + nr));
       g.hsize = hs;
       g.fold = 0;
+      for (int k = 0; k < FOLD_SLOTS; ++k) g.fold_part[k] = 0;
       g.mode = 0;
+      // join layout: B buckets, counting tiles of TJ items (C tiles, then R tiles)
+      uint64_t B = pow2ceil((nc + nr + JB_TARGET - 1) / JB_TARGET);
+      if (B < 1) B = 1;
+      if (B > JB_MAX) B = JB_MAX;
+      uint64_t TJ = (nc > nr ? nc : nr) / JT_MAX_TILES + 1;
+      if (TJ < JT) TJ = JT;
+      g.jB = B;
+      g.jTJ = TJ;
+      g.jTC = (nc + TJ - 1) / TJ;
+      g.jT = g.jTC + (nr + TJ - 1) / TJ;
+      jt = g.jT;
+      je = g.jT * B;
+      jb = B;
     }
-    uint64_t t0, t1, t2;
+    uint64_t t0, t1, t2, t3, t4, t5;
     const uint64_t e0 = bs.excl(nc, &t0), e1 = bs.excl(nr, &t1), e2 = bs.excl(hs, &t2);
+    const uint64_t e3 = bs.excl(jt, &t3), e4 = bs.excl(je, &t4), e5 = bs.excl(jb, &t5);
     if (s < cm.nseg) {
       cm.cpre[s] = s_carry[0] + e0;
       cm.rpre[s] = s_carry[1] + e1;
       cm.seg[s].hbase = s_carry[2] + e2;
+      cm.tpre[s] = s_carry[3] + e3;
+      cm.seg[s].jebase = s_carry[4] + e4;
+      cm.bpre[s] = s_carry[5] + e5;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       s_carry[0] += t0;
       s_carry[1] += t1;
       s_carry[2] += t2;
+      s_carry[3] += t3;
+      s_carry[4] += t4;
+      s_carry[5] += t5;
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     cm.cpre[cm.nseg] = s_carry[0];
     cm.rpre[cm.nseg] = s_carry[1];
+    cm.tpre[cm.nseg] = s_carry[3];
+    cm.bpre[cm.nseg] = s_carry[5];
     cm.meta[0] = s_carry[0];
     cm.meta[1] = s_carry[1];
     cm.meta[2] = s_carry[2];
     cm.meta[8] = s_carry[0] + s_carry[1];
+    cm.meta[10] = s_carry[3];
+    cm.meta[11] = s_carry[4];
+    cm.meta[12] = s_carry[5];
+    cm.meta[13] = 0;
   }
 }
 
+// Global-table join: only used when a join bucket overflowed its LDS block.
 __global__ __launch_bounds__(BLOCK) void k_clear_tab(Common cm, Entry* tab, uint8_t* cflag) {
-  if (status_of(cm.status) & ANY_ERR) return;
+  if ((status_of(cm.status) & ANY_ERR) || !cm.meta[13]) return;
   const int64_t H = cm.meta[2], Ct = cm.meta[0];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < H; i += stride) {
@@ -226,7 +289,7 @@ __global__ __launch_bounds__(BLOCK) void k_clear_tab(Common cm, Entry* tab, uint
 
 __global__ __launch_bounds__(BLOCK) void k_enc_insert(Common cm, const uint8_t* cur, const uint8_t* ref, Entry* tab,
                                                       uint32_t* cwords, uint32_t* rwords, uint32_t* rslot) {
-  if (status_of(cm.status) & ANY_ERR) return;
+  if ((status_of(cm.status) & ANY_ERR) || !cm.meta[13]) return;
   const int64_t Ct = cm.meta[0], total = cm.meta[8];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   // whole waves iterate together so the per-segment XOR fold can use the wave
@@ -278,16 +341,13 @@ __global__ __launch_bounds__(BLOCK) void k_enc_insert(Common cm, const uint8_t* 
         }
       }
     }
-    // per segment XOR of the reference uids (identity of the reference)
-    const bool isR = active && !isC && okr;
-    seg_xor(&cm.seg[0].fold, sizeof(Seg) / 8, s, isR, uid);
   }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_enc_match(Common cm, const uint8_t* cur, const uint8_t* ref,
                                                      const Entry* tab, const uint32_t* rslot, int32_t* m,
                                                      uint8_t* cflag) {
-  if (status_of(cm.status) & ANY_ERR) return;
+  if ((status_of(cm.status) & ANY_ERR) || !cm.meta[13]) return;
   const int64_t Rt = cm.meta[1];
   for (int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x; g < Rt; g += (int64_t)gridDim.x * BLOCK) {
     const int64_t s = seg_of(cm.rpre, cm.nseg, (uint64_t)g);
@@ -309,6 +369,191 @@ __global__ __launch_bounds__(BLOCK) void k_enc_match(Common cm, const uint8_t* c
   }
 }
 
+
+struct JoinArgs {
+  Common cm;
+  const uint8_t* cur;
+  const uint8_t* ref;
+  uint64_t* juid;    // [C+R] uid of every item
+  uint64_t* jhdr;    // [C+R] header word of every item
+  uint32_t* cwords;
+  uint32_t* rwords;
+  uint32_t* cnt;     // [count entries] items per (segment, bucket, tile)
+  uint64_t* cnt_pre; // [count entries + 1]
+  uint64_t* part;    // [2 (C+R)] bucketed items: uid, item
+  int32_t* m;
+  uint8_t* cflag;
+};
+
+struct JTile {
+  int64_t s;
+  uint64_t lt, i0, i1;  // items [i0, i1) of one side of the segment
+  bool isC;
+};
+__device__ inline JTile join_tile(const Common& cm, int64_t t) {
+  JTile jt;
+  jt.s = last_le<uint64_t>(cm.tpre, 0, cm.nseg, (uint64_t)t);
+  const Seg& g = cm.seg[jt.s];
+  jt.lt = (uint64_t)t - cm.tpre[jt.s];
+  jt.isC = jt.lt < g.jTC;
+  const uint64_t k = jt.isC ? jt.lt : jt.lt - g.jTC;
+  const uint64_t n = jt.isC ? g.nc : g.nr;
+  jt.i0 = k * g.jTJ;
+  jt.i1 = jt.i0 + g.jTJ < n ? jt.i0 + g.jTJ : n;
+  return jt;
+}
+
+// J1: validate every record, gather uid and header, count items per bucket.
+__global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a) {
+  __shared__ uint32_t s_hist[JB_MAX];
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t Tt = cm.meta[10];
+  const uint64_t Ct = (uint64_t)cm.meta[0];
+  for (int64_t t = blockIdx.x; t < Tt; t += gridDim.x) {
+    const JTile jt = join_tile(cm, t);
+    Seg& g = cm.seg[jt.s];
+    const uint64_t B = g.jB;
+    for (uint64_t b = threadIdx.x; b < B; b += BLOCK) s_hist[b] = 0;
+    __syncthreads();
+    const uint8_t* msg = jt.isC ? a.cur + g.cmsg : a.ref + g.rmsg;
+    const uint32_t n = (uint32_t)(jt.isC ? g.nc : g.nr);
+    const uint64_t rw = jt.isC ? g.rwc : g.rwr;
+    const uint64_t gbase = jt.isC ? cm.cpre[jt.s] : Ct + cm.rpre[jt.s];
+    uint64_t fold = 0;
+    for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += BLOCK) {
+      const uint64_t i = i0 + threadIdx.x;
+      if (i < jt.i1) {
+        uint32_t o;
+        uint64_t hdr, uid = 0;
+        bool ok = tam1_record(msg, n, rw, (uint32_t)i, &o, &hdr);
+        if (ok) {
+          uid = ld64(tam1_records(msg, n) + 8 * (uint64_t)o);
+          ok = uid != 0;
+        }
+        if (!ok) {
+          fail(cm.status, ERR_INVALID);
+        } else {
+          const uint64_t item = gbase + (i - 0);
+          a.juid[item] = uid;
+          a.jhdr[item] = hdr;
+          if (jt.isC) a.cwords[cm.cpre[jt.s] + i] = (uint32_t)(hdr >> 32);
+          else a.rwords[cm.rpre[jt.s] + i] = (uint32_t)(hdr >> 32);
+          atomicAdd(&s_hist[join_bucket(uid, B)], 1u);
+          if (!jt.isC) fold ^= uid;
+        }
+      }
+    }
+    if (!jt.isC) {
+      fold = wave_xor(fold);
+      if (lane_id() == 0 && fold)
+        atomicXor((unsigned long long*)&g.fold_part[(t * WAVES + wave_id()) % FOLD_SLOTS], (unsigned long long)fold);
+    }
+    __syncthreads();
+    uint32_t* dst = a.cnt + g.jebase + jt.lt;
+    for (uint64_t b = threadIdx.x; b < B; b += BLOCK) dst[b * g.jT] = s_hist[b];
+    __syncthreads();
+  }
+}
+
+struct JCntIn {
+  const uint32_t* a;
+  __device__ uint64_t operator()(int64_t i) const { return a[i]; }
+};
+
+// J3: scatter (uid, item) pairs into their buckets.
+__global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a) {
+  __shared__ uint32_t s_off[JB_MAX];
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t Tt = cm.meta[10];
+  const uint64_t Ct = (uint64_t)cm.meta[0];
+  for (int64_t t = blockIdx.x; t < Tt; t += gridDim.x) {
+    const JTile jt = join_tile(cm, t);
+    const Seg& g = cm.seg[jt.s];
+    const uint64_t B = g.jB;
+    const uint64_t* src = a.cnt_pre + g.jebase + jt.lt;
+    // bucket starts relative to the segment's first entry (fits 32 bits:
+    // a segment holds < 2^28 + 2^28 items)
+    const uint64_t seg0 = a.cnt_pre[g.jebase];
+    for (uint64_t b = threadIdx.x; b < B; b += BLOCK) s_off[b] = (uint32_t)(src[b * g.jT] - seg0);
+    __syncthreads();
+    const uint64_t gbase = jt.isC ? cm.cpre[jt.s] : Ct + cm.rpre[jt.s];
+    for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += BLOCK) {
+      const uint64_t i = i0 + threadIdx.x;
+      if (i < jt.i1) {
+        const uint64_t item = gbase + i;
+        const uint64_t uid = a.juid[item];
+        const uint32_t pos = atomicAdd(&s_off[join_bucket(uid, B)], 1u);
+        a.part[2 * (seg0 + pos)] = uid;
+        a.part[2 * (seg0 + pos) + 1] = item;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// J4: one block per bucket: an LDS hash table pairs current and reference
+// items with equal uids; a second item of the same side, or a third item,
+// is a duplicate.
+__global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a) {
+  __shared__ uint64_t s_uid[JCAP];
+  __shared__ uint32_t s_id[JCAP];
+  __shared__ uint32_t s_partner[JCAP];
+  __shared__ uint32_t s_tab[JTAB];
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t Bt = cm.meta[12];
+  const uint64_t Ct = (uint64_t)cm.meta[0];
+  for (int64_t bk = blockIdx.x; bk < Bt; bk += gridDim.x) {
+    const int64_t s = last_le<uint64_t>(cm.bpre, 0, cm.nseg, (uint64_t)bk);
+    const Seg& g = cm.seg[s];
+    const uint64_t b = (uint64_t)bk - cm.bpre[s];
+    const uint64_t p0 = a.cnt_pre[g.jebase + b * g.jT], p1 = a.cnt_pre[g.jebase + (b + 1) * g.jT];
+    const uint32_t n = (uint32_t)(p1 - p0);
+    if (n > JCAP) {  // uniform: leave this bucket to the global-table join
+      if (threadIdx.x == 0) atomicOr((unsigned long long*)&cm.meta[13], 1ull);
+      continue;
+    }
+    for (uint32_t k = threadIdx.x; k < n; k += BLOCK) {
+      s_uid[k] = a.part[2 * (p0 + k)];
+      s_id[k] = (uint32_t)a.part[2 * (p0 + k) + 1];
+      s_partner[k] = NONE;
+    }
+    for (uint32_t k = threadIdx.x; k < JTAB; k += BLOCK) s_tab[k] = 0;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < n; k += BLOCK) {
+      const uint64_t uid = s_uid[k];
+      uint32_t h = (uint32_t)(mix64(uid) >> 40) & (JTAB - 1);
+      for (int probe = 0; probe < JTAB; ++probe) {
+        const uint32_t old = atomicCAS(&s_tab[h], 0u, k + 1);
+        if (old == 0) break;
+        const uint32_t o = old - 1;
+        if (s_uid[o] == uid) {
+          if ((s_id[k] >= Ct) == (s_id[o] >= Ct) || atomicCAS(&s_partner[o], NONE, k) != NONE) {
+            fail(cm.status, ERR_INVALID);  // duplicate uid
+          } else {
+            s_partner[k] = o;
+          }
+          break;
+        }
+        h = (h + 1) & (JTAB - 1);
+      }
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < n; k += BLOCK) {
+      const uint32_t id = s_id[k], p = s_partner[k];
+      const bool matched = p != NONE && a.jhdr[id] == a.jhdr[s_id[p]];
+      if (id >= Ct) {
+        a.m[id - Ct] = matched ? (int32_t)(s_id[p] - cm.cpre[s]) : -1;
+      } else {
+        a.cflag[id] = matched ? 1 : 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 struct RMatchIn {  // count << 34 | words of matched reference slots
   const int32_t* m;
   const uint32_t* rwords;
@@ -323,7 +568,7 @@ struct CNewIn {  // count << 34 | words of new current records
 // Per segment layout after matching; block-wide prefixes; C' headers.
 __global__ __launch_bounds__(1024) void k_enc_seg2(Common cm, const uint64_t* rscan, const uint64_t* cscan,
                                                    uint8_t* newref, int64_t newref_cap, int64_t* newref_off,
-                                                   uint64_t* gex) {
+                                                   uint64_t* gex, uint64_t* mstart) {
   __shared__ uint64_t s_w[16];
   __shared__ uint64_t s_carry[4];
   BlockScan1024 bs{s_w};
@@ -335,6 +580,7 @@ __global__ __launch_bounds__(1024) void k_enc_seg2(Common cm, const uint64_t* rs
     uint64_t G = 0, fixed = 0, osize = 0, PG = 0;
     if (s < cm.nseg && !bad) {
       Seg& g = cm.seg[s];
+      g.fold = fold_of(g.fold_part);
       const uint64_t rs = rscan[cm.rpre[s]], re = rscan[cm.rpre[s + 1]];
       const uint64_t cs = cscan[cm.cpre[s]], ce = cscan[cm.cpre[s + 1]];
       g.mbase = rs >> PK;
@@ -359,6 +605,10 @@ __global__ __launch_bounds__(1024) void k_enc_seg2(Common cm, const uint64_t* rs
       cm.gpre[s] = s_carry[0] + e0;
       cm.seg[s].fixed_excl = s_carry[1] + e1;
       cm.seg[s].oref = s_carry[2] + e2;
+      {
+        Seg& g = cm.seg[s];
+        g.cpw = (g.oref + 32 + 8 * ((g.n_match + g.n_new + 1) / 2)) / 8 - g.dbase;
+      }
       newref_off[s] = (int64_t)(s_carry[2] + e2);
       cm.ppre[s] = s_carry[3] + e3;
     }
@@ -384,6 +634,7 @@ __global__ __launch_bounds__(1024) void k_enc_seg2(Common cm, const uint64_t* rs
     cm.meta[7] = cscan[cm.meta[0]] & WMASK;
     cm.meta[9] = (int64_t)s_carry[1];  // fixed total
     gex[s_carry[0]] = 0;
+    mstart[cm.meta[5]] = rscan[cm.meta[1]] & WMASK;  // end of the last matched record
     if (!fits) fail(cm.status, ERR_CAPACITY);
   }
   if (!fits) return;
@@ -401,15 +652,26 @@ __global__ __launch_bounds__(1024) void k_enc_seg2(Common cm, const uint64_t* rs
 }
 
 // Directory of matched records; C' offsets of matched records.
+// Groups whose first residual word lies in a matched record (local words
+// [q0, q0+w)) of segment s: remember the segment, so a group's wave finds it
+// without searching.
+__device__ inline void map_groups(const Common& cm, int64_t s, uint64_t q0, uint64_t w, uint32_t* gseg) {
+  for (uint64_t lg = (q0 + 63) / 64; 64 * lg < q0 + w; ++lg) gseg[cm.gpre[s] + lg] = (uint32_t)s;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
-                                                    const int32_t* m, const uint64_t* rscan, MDir* mdir,
-                                                    uint8_t* newref) {
+                                                    const int32_t* m, const uint64_t* rscan, const uint32_t* rwords,
+                                                    MDir* mdir, uint64_t* mstart, uint8_t* newref, uint32_t* gseg) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
-  for (int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x; g < Rt; g += (int64_t)gridDim.x * BLOCK) {
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t base = (int64_t)blockIdx.x * BLOCK + wave_id() * WAVE; base < Rt; base += stride) {
+    const int64_t g = base + lane_id();
+    const uint64_t last = (uint64_t)(base + WAVE - 1 < Rt ? base + WAVE - 1 : Rt - 1);
+    const int64_t s = wave_seg(cm.rpre, cm.nseg, (uint64_t)(g < Rt ? g : Rt - 1), (uint64_t)base, last);
+    if (g >= Rt) continue;
     const int32_t i = m[g];
     if (i < 0) continue;
-    const int64_t s = seg_of(cm.rpre, cm.nseg, (uint64_t)g);
     const Seg& sg = cm.seg[s];
     const uint64_t j = g - cm.rpre[s];
     const uint64_t k = rscan[g] >> PK;
@@ -418,32 +680,12 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
     e.cword = sg.cbody / 8 + ld32(cur + sg.cmsg + 32 + 4 * (uint64_t)i);
     e.rword = sg.rbody / 8 + ld32(ref + sg.rmsg + 32 + 4 * j);
     e.dstart = d;
-    e.g = (uint64_t)g;
+    e.gs = (uint64_t)g | ((uint64_t)s << 34);
     mdir[k] = e;
+    mstart[k] = d;
     *reinterpret_cast<uint32_t*>(newref + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
+    map_groups(cm, s, d - sg.dbase, rwords[g], gseg);
   }
-}
-
-// Record of each lane of a 64-word residual window starting at global
-// residual position dq0 inside segment sg: index into mdir.
-__device__ inline uint64_t window_record(const MDir* mdir, uint64_t kbeg, uint64_t kend, uint64_t dq0) {
-  // k0: last matched record of the segment starting at or before dq0 (uniform)
-  uint64_t lo = kbeg, hi = kend;
-  while (hi - lo > 1) {
-    const uint64_t mid = lo + (hi - lo) / 2;
-    if (mdir[mid].dstart <= dq0) lo = mid;
-    else hi = mid;
-  }
-  const uint64_t k0 = lo;
-  const int l = lane_id();
-  const uint64_t kk = k0 + 1 + (uint64_t)l;
-  uint64_t bit = 0;
-  if (kk < kend) {
-    const uint64_t rel = mdir[kk].dstart - dq0;
-    if (rel < 64) bit = 1ull << rel;
-  }
-  const uint64_t starts = wave_or(bit);
-  return k0 + (uint64_t)__popcll(starts & lanemask_le(l));
 }
 
 // Assemble the block of one group in LDS.  Returns the block size in bytes.
@@ -476,104 +718,174 @@ __device__ inline uint32_t build_block(uint64_t D, uint8_t* blk, uint64_t* bitma
   return size;
 }
 
-struct XorArgs {
+constexpr int RES_CAP = 1024;  // residual words one wave stages in LDS
+
+struct ResidArgs {
   Common cm;
   const uint64_t* cur;
   const uint64_t* ref;
   const MDir* mdir;
-  uint8_t* enc;
-  int64_t enc_cap;
-  uint64_t* newref;
-  uint64_t* bm;     // [groups] word bitmaps
-  uint8_t* gsz;     // [groups] block sizes / 8
-  uint64_t* gex;    // [groups+1] exclusive prefix of block bytes
-  const PredW* pw;  // learned mode: predictor (nullptr: plain)
+  const uint64_t* mstart;  // [matched+1] residual start of every matched record
   const uint64_t* pred_x;  // learned: predicted words 2..5 per matched record [k][4]
   const uint8_t* pred_on;  // learned: record k predicted
-  LookBack lb;
+  uint64_t* newref;        // C' (words)
+  uint64_t* D;             // dense residual of all segments
 };
 
-__global__ __launch_bounds__(BLOCK) void k_enc_xor(XorArgs a) {
-  __shared__ uint64_t s_blk[TILE_G][BLK_MAX / 8];
-  __shared__ uint32_t s_size[TILE_G];
-  __shared__ uint64_t s_pre[TILE_G];
-  __shared__ uint32_t s_ticket;
-  __shared__ uint64_t s_excl, s_agg;
-  lb_clear_next(a.lb);
+// One lane per matched record (64 consecutive matched records per wave): the
+// record's C words go to C' and C xor X to the dense residual.  Both outputs of
+// the wave are contiguous, so they are staged in LDS and written with
+// coalesced stores.
+__global__ __launch_bounds__(BLOCK) void k_enc_resid(ResidArgs a) {
+  __shared__ uint64_t s_buf[WAVES][RES_CAP];
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t M = cm.meta[5];
+  const int l = lane_id(), wv = wave_id();
+  uint64_t* buf = s_buf[wv];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t kb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; kb < M; kb += stride) {
+    const int64_t k = kb + l;
+    const bool act = k < M;
+    const int64_t ke = kb + WAVE < M ? kb + WAVE : M;
+    const uint64_t d0 = a.mstart[kb], d1 = a.mstart[ke];
+    MDir e{};
+    uint64_t words = 0, cpw = 0;
+    int64_t sg = -1;
+    bool learned = false;
+    if (act) {
+      e = a.mdir[k];
+      words = a.mstart[k + 1] - e.dstart;
+      sg = mdir_seg(e);
+      const Seg& g = cm.seg[sg];
+      cpw = g.cpw;
+      learned = g.mode == 1 && a.pred_on[k];
+    }
+    const int64_t s_first = __shfl(sg, 0, WAVE), s_last = __shfl(sg, (int)(ke - kb - 1), WAVE);
+    const uint64_t cpw0 = __shfl(cpw, 0, WAVE);
+    const bool staged = d1 - d0 <= RES_CAP;
+    const bool one_seg = s_first == s_last;
+    for (uint64_t w = 0; w < words; ++w) {
+      const uint64_t c = a.cur[e.cword + w];
+      if (staged) buf[e.dstart - d0 + w] = c;
+      else a.newref[cpw + e.dstart + w] = c;
+    }
+    wave_sync();
+    if (staged) {
+      if (one_seg) {
+        for (uint64_t p = l; p < d1 - d0; p += WAVE) a.newref[cpw0 + d0 + p] = buf[p];
+      } else {
+        for (uint64_t w = 0; w < words; ++w) a.newref[cpw + e.dstart + w] = buf[e.dstart - d0 + w];
+      }
+    }
+    wave_sync();
+    for (uint64_t w = 0; w < words; ++w) {
+      const uint64_t c = staged ? buf[e.dstart - d0 + w] : a.cur[e.cword + w];
+      uint64_t x = a.ref[e.rword + w];
+      if (learned && w >= 2 && w < 6) x = a.pred_x[4 * k + (w - 2)];
+      if (staged) buf[e.dstart - d0 + w] = c ^ x;
+      else a.D[e.dstart + w] = c ^ x;
+    }
+    wave_sync();
+    if (staged)
+      for (uint64_t p = l; p < d1 - d0; p += WAVE) a.D[d0 + p] = buf[p];
+    wave_sync();
+  }
+}
+
+struct PackArgs {
+  Common cm;
+  const uint64_t* D;
+  uint8_t* enc;
+  int64_t enc_cap;
+  uint64_t* bm;          // [groups] word bitmaps
+  uint8_t* gsz;          // [groups] block sizes / 8
+  const uint64_t* gex;   // [groups+1] exclusive prefix of block bytes (pass 3)
+  const uint32_t* gseg;  // [groups] segment of the group
+};
+
+constexpr int PG_WAVE = 4;  // groups one wave handles at a time (loads issued together)
+
+// Pass 1 of the zero-block packer: per 64-word group, its bitmap word and
+// its block size (nibbles + significant bytes, rounded to 8).
+__global__ __launch_bounds__(BLOCK) void k_enc_gsize(PackArgs a) {
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Gt = cm.meta[3];
-  const int64_t ntiles = (Gt + TILE_G - 1) / TILE_G;
-  const int l = lane_id(), wv = wave_id();
-  for (;;) {
-    const uint32_t t = lb_take_ticket(a.lb, &s_ticket);
-    if ((int64_t)t >= ntiles) break;
-    for (int x = 0; x < XG; ++x) {
-      const int loc = wv * XG + x;
-      const int64_t gg = (int64_t)t * TILE_G + loc;
-      if (gg >= Gt) {
-        if (l == 0) s_size[loc] = 0;
-        continue;
+  const int l = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * WAVES;
+  for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wave_id()) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
+    uint64_t Dv[PG_WAVE];
+#pragma unroll
+    for (int x = 0; x < PG_WAVE; ++x) {
+      const int64_t gg = g0 + x;
+      Dv[x] = 0;
+      if (gg < Gt) {
+        const Seg& sg = cm.seg[a.gseg[gg]];
+        const uint64_t q = 64 * ((uint64_t)gg - cm.gpre[a.gseg[gg]]) + (uint64_t)l;
+        if (q < sg.W) Dv[x] = a.D[sg.dbase + q];
       }
-      const int64_t s = seg_of(cm.gpre, cm.nseg, (uint64_t)gg);
-      const Seg& sg = cm.seg[s];
-      const uint64_t lg = (uint64_t)gg - cm.gpre[s];
-      const uint64_t q = 64 * lg + (uint64_t)l;
-      const uint64_t dq0 = sg.dbase + 64 * lg;
-      const uint64_t k = window_record(a.mdir, sg.mbase, sg.mbase + sg.n_match, dq0);
-      uint64_t D = 0;
-      if (q < sg.W) {
-        const MDir e = a.mdir[k];
-        const uint64_t w = dq0 + (uint64_t)l - e.dstart;
-        const uint64_t c = a.cur[e.cword + w];
-        uint64_t x_ = a.ref[e.rword + w];
-        if (sg.mode == 1 && w >= 2 && w < 6 && a.pred_on[k]) x_ = a.pred_x[4 * k + (w - 2)];
-        D = c ^ x_;
-        a.newref[(sg.oref + 32 + 8 * ((sg.n_match + sg.n_new + 1) / 2)) / 8 + q] = c;
-      }
-      uint64_t bm;
-      const uint32_t size = build_block(D, reinterpret_cast<uint8_t*>(s_blk[loc]), &bm);
+    }
+#pragma unroll
+    for (int x = 0; x < PG_WAVE; ++x) {
+      const int64_t gg = g0 + x;
+      if (gg >= Gt) break;
+      const uint64_t D = Dv[x];
+      const uint64_t bm = __ballot(D != 0);
+      const uint64_t len = D ? (uint64_t)(8 - (__clzll((long long)D) >> 3)) : 0;
+      const uint64_t sig = wave_sum(len);
       if (l == 0) {
-        s_size[loc] = size;
         a.bm[gg] = bm;
-        a.gsz[gg] = (uint8_t)(size / 8);
+        a.gsz[gg] = (uint8_t)(round8(((uint64_t)__popcll(bm) + 1) / 2 + sig) / 8);
       }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t run = 0;
-      for (int i = 0; i < TILE_G; ++i) {
-        s_pre[i] = run;
-        run += s_size[i];
+  }
+}
+
+struct GszIn {
+  const uint8_t* gsz;
+  __device__ uint64_t operator()(int64_t g) const { return 8 * (uint64_t)gsz[g]; }
+};
+
+// Pass 3: every group rebuilds its block in LDS and writes it at its offset.
+__global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
+  __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8];
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t Gt = cm.meta[3];
+  const int l = lane_id(), wv = wave_id();
+  const int64_t nw = (int64_t)gridDim.x * WAVES;
+  for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
+    uint64_t Dv[PG_WAVE], at[PG_WAVE];
+#pragma unroll
+    for (int x = 0; x < PG_WAVE; ++x) {
+      const int64_t gg = g0 + x;
+      Dv[x] = 0;
+      at[x] = 0;
+      if (gg < Gt) {
+        const int64_t s = a.gseg[gg];
+        const Seg& sg = cm.seg[s];
+        const uint64_t q = 64 * ((uint64_t)gg - cm.gpre[s]) + (uint64_t)l;
+        if (q < sg.W) Dv[x] = a.D[sg.dbase + q];
+        at[x] = sg.fixed_excl + sg.fixed + a.gex[gg];
       }
-      s_agg = run;
     }
-    __syncthreads();
-    if (threadIdx.x < WAVE) {
-      const uint64_t e = lb_exclusive(a.lb, t, s_agg);
-      if (threadIdx.x == 0) s_excl = e;
-    }
-    __syncthreads();
-    for (int x = 0; x < XG; ++x) {
-      const int loc = wv * XG + x;
-      const int64_t gg = (int64_t)t * TILE_G + loc;
-      if (gg >= Gt) continue;
-      const uint64_t V = s_excl + s_pre[loc];
-      if (l == 0) a.gex[gg] = V;
-      const uint32_t size = s_size[loc];
-      if (!size) continue;
-      const int64_t s = seg_of(cm.gpre, cm.nseg, (uint64_t)gg);
-      const Seg& sg = cm.seg[s];
-      const uint64_t at = sg.fixed_excl + sg.fixed + V;
-      if (at + size > (uint64_t)a.enc_cap) {
-        if (l == 0) fail(cm.status, ERR_CAPACITY);
-        continue;
+#pragma unroll
+    for (int x = 0; x < PG_WAVE; ++x) {
+      const int64_t gg = g0 + x;
+      if (gg >= Gt) break;
+      uint64_t bm;
+      const uint32_t size = build_block(Dv[x], reinterpret_cast<uint8_t*>(s_blk[wv]), &bm);
+      if (size) {
+        if (at[x] + size > (uint64_t)a.enc_cap) {
+          if (l == 0) fail(cm.status, ERR_CAPACITY);
+        } else {
+          uint64_t* dst = reinterpret_cast<uint64_t*>(a.enc + at[x]);
+          for (uint32_t w = l; w < size / 8; w += WAVE) dst[w] = s_blk[wv][w];
+        }
       }
-      uint64_t* dst = reinterpret_cast<uint64_t*>(a.enc + at);
-      for (uint32_t w = l; w < size / 8; w += WAVE) dst[w] = s_blk[loc][w];
+      wave_sync();
     }
-    if ((int64_t)t == ntiles - 1 && threadIdx.x == 0) a.gex[Gt] = s_excl + s_agg;
-    __syncthreads();
   }
 }
 
@@ -664,22 +976,23 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
   }
 }
 
-// New records, word by word: from C into the encoding and C'.
+// New records, word by word: from C into the encoding and C'.  A wave finds
+// the range of records its 64 words touch with two wave searches.
 __global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t* cscan, const uint8_t* cflag,
                                                        const uint8_t* cur, uint8_t* enc, uint8_t* newref) {
   if (status_of(cm.status) & ANY_ERR) return;
   const uint64_t NW = (uint64_t)cm.meta[7];
   const int64_t Cn = cm.meta[0];
-  for (uint64_t q = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; q < NW; q += (uint64_t)gridDim.x * BLOCK) {
-    // last C record whose new-word prefix is <= q: a new record holding q
-    int64_t lo = 0, hi = Cn;
-    while (hi - lo > 1) {
-      const int64_t mid = lo + (hi - lo) / 2;
-      if ((cscan[mid] & WMASK) <= q) lo = mid;
-      else hi = mid;
-    }
-    const int64_t gc = lo;
-    const int64_t s = seg_of(cm.cpre, cm.nseg, (uint64_t)gc);
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  for (uint64_t qb = (uint64_t)blockIdx.x * BLOCK + wave_id() * WAVE; qb < NW; qb += stride) {
+    const uint64_t q = qb + lane_id();
+    const uint64_t qe = qb + WAVE - 1 < NW ? qb + WAVE - 1 : NW - 1;
+    const int64_t rlo = wave_last_le_masked(cscan, 0, Cn, qb, WMASK);
+    const int64_t rhi = wave_last_le_masked(cscan, rlo, Cn, qe, WMASK);
+    // last C record whose new-word prefix is <= q: the new record holding q
+    const int64_t gc = last_le_masked(cscan, rlo, rhi + 1, q < NW ? q : NW - 1, WMASK);
+    const int64_t s = wave_seg(cm.cpre, cm.nseg, (uint64_t)gc, (uint64_t)rlo, (uint64_t)rhi);
+    if (q >= NW) continue;
     const Seg& g = cm.seg[s];
     const uint64_t i = gc - cm.cpre[s];
     const uint64_t w = q - (cscan[gc] & WMASK);
@@ -740,6 +1053,7 @@ __global__ __launch_bounds__(1024) void k_dec_setup(Common cm, const uint8_t* en
         const uint64_t len = (uint64_t)(eb - ea);
         g.fold = h[4];
         g.rfold = 0;
+        for (int k = 0; k < FOLD_SLOTS; ++k) g.fold_part[k] = 0;
         g.var = var;
         if (n_ref != n || ref_words != rw) {
           code = ERR_REF;
@@ -828,11 +1142,15 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
   for (int64_t it = 0; it < rounds; ++it) {
     const int64_t g = start + it * stride;
     const bool active = g < Rt;
-    int64_t s = 0;
     uint64_t uid = 0;
     bool ok = false;
+    const int64_t wbase = g - lane_id();
+    int64_t s = 0;
+    if (wbase < Rt) {
+      const uint64_t last = (uint64_t)(wbase + WAVE - 1 < Rt ? wbase + WAVE - 1 : Rt - 1);
+      s = wave_seg(cm.rpre, cm.nseg, (uint64_t)(active ? g : Rt - 1), (uint64_t)wbase, last);
+    }
     if (active) {
-      s = seg_of(cm.rpre, cm.nseg, (uint64_t)g);
       const Seg& sg = cm.seg[s];
       const uint64_t j = g - cm.rpre[s];
       uint32_t o;
@@ -848,7 +1166,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
       rwords[g] = (uint32_t)(hdr >> 32);
     }
     // XOR of the reference uids, compared with the encoding's later
-    seg_xor(&cm.seg[0].rfold, sizeof(Seg) / 8, s, active && ok, uid);
+    seg_xor(&cm.seg[0].fold_part[0], sizeof(Seg) / 8, s, active && ok, uid);
   }
 }
 
@@ -884,17 +1202,23 @@ struct DGroupIn {  // group block bytes
 
 
 __global__ __launch_bounds__(1024) void k_dec_seg2(Common cm, const uint64_t* rscan, const uint64_t* nscan,
-                                                   const uint64_t* gex, uint8_t* out) {
+                                                   const uint64_t* gex, uint8_t* out, uint64_t* mstart) {
   if (status_of(cm.status) & ANY_ERR) return;
+  if (threadIdx.x == 0) {
+    cm.meta[5] = (int64_t)(rscan[cm.meta[1]] >> PK);
+    mstart[cm.meta[5]] = rscan[cm.meta[1]] & WMASK;  // end of the last matched record
+  }
   for (int64_t s = threadIdx.x; s < cm.nseg; s += 1024) {
     Seg& g = cm.seg[s];
     const uint64_t rs = rscan[cm.rpre[s]], re = rscan[cm.rpre[s + 1]];
     g.mbase = rs >> PK;
     g.dbase = rs & WMASK;
+    g.cpw = (g.oref + 32 + 8 * ((g.n_match + g.n_new + 1) / 2)) / 8 - g.dbase;
     const uint64_t nm = (re >> PK) - g.mbase, W = (re & WMASK) - g.dbase;
     g.npbase = nscan[cm.npre[s]];
     const uint64_t nw = nscan[cm.npre[s + 1]] - g.npbase;
     const uint64_t var = gex[cm.gpre[s + 1]] - gex[cm.gpre[s]];
+    g.rfold = fold_of(g.fold_part);
     if (g.rfold != g.fold) fail(cm.status, ERR_REF);
     if (nm != g.n_match || W != g.W || nw != g.new_words || var != g.var) fail(cm.status, ERR_CORRUPT);
   }
@@ -915,12 +1239,16 @@ __global__ __launch_bounds__(1024) void k_dec_seg2(Common cm, const uint64_t* rs
 }
 
 __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* ref, const uint8_t* rmatch,
-                                                    const uint64_t* rscan, MDir* mdir, uint8_t* out) {
+                                                    const uint64_t* rscan, const uint32_t* rwords, MDir* mdir,
+                                                    uint64_t* mstart, uint8_t* out, uint32_t* gseg) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
-  for (int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x; g < Rt; g += (int64_t)gridDim.x * BLOCK) {
-    if (!rmatch[g]) continue;
-    const int64_t s = seg_of(cm.rpre, cm.nseg, (uint64_t)g);
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t base = (int64_t)blockIdx.x * BLOCK + wave_id() * WAVE; base < Rt; base += stride) {
+    const int64_t g = base + lane_id();
+    const uint64_t last = (uint64_t)(base + WAVE - 1 < Rt ? base + WAVE - 1 : Rt - 1);
+    const int64_t s = wave_seg(cm.rpre, cm.nseg, (uint64_t)(g < Rt ? g : Rt - 1), (uint64_t)base, last);
+    if (g >= Rt || !rmatch[g]) continue;
     const Seg& sg = cm.seg[s];
     const uint64_t j = g - cm.rpre[s];
     const uint64_t k = rscan[g] >> PK;
@@ -929,21 +1257,20 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
     e.cword = 0;
     e.rword = sg.rbody / 8 + ld32(ref + sg.rmsg + 32 + 4 * j);
     e.dstart = d;
-    e.g = (uint64_t)g;
+    e.gs = (uint64_t)g | ((uint64_t)s << 34);
     mdir[k] = e;
+    mstart[k] = d;
     *reinterpret_cast<uint32_t*>(out + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
+    map_groups(cm, s, d - sg.dbase, rwords[g], gseg);
   }
 }
 
 struct UnpackArgs {
   Common cm;
   const uint8_t* enc;
-  const uint64_t* ref;
-  const MDir* mdir;
   const uint64_t* gex;
-  uint64_t* out;
-  const uint64_t* pred_x;
-  const uint8_t* pred_on;
+  const uint32_t* gseg;
+  uint64_t* D;
 };
 
 // One wave per 64-word group: read the block, rebuild the residual words, xor
@@ -955,57 +1282,138 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
   const int64_t Gt = cm.meta[3];
   const int l = lane_id(), wv = wave_id();
   uint8_t* blk = reinterpret_cast<uint8_t*>(s_blk[wv]);
-  const int64_t nwaves = (int64_t)gridDim.x * WAVES;
-  for (int64_t gg = (int64_t)blockIdx.x * WAVES + wv; gg < Gt; gg += nwaves) {
-    const int64_t s = seg_of(cm.gpre, cm.nseg, (uint64_t)gg);
-    const Seg& sg = cm.seg[s];
-    const uint64_t lg = (uint64_t)gg - cm.gpre[s];
-    const uint8_t* e = a.enc + sg.encm;
-    const uint64_t bitmap = ld64(e + 64 + 8 * sg.PG + 8 * lg);
-    const uint32_t size = 8u * e[64 + 8 * sg.PG + 8 * sg.G + lg];
-    bool bad = size > BLK_MAX;
-    if (!bad) {
-      const uint64_t boff = sg.fixed + (a.gex[gg] - a.gex[cm.gpre[s]]);
-      for (uint32_t w = l; w < size / 8; w += WAVE) s_blk[wv][w] = ld64(e + boff + 8 * w);
+  const int64_t nw = (int64_t)gridDim.x * WAVES;
+  for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
+    // descriptors of the wave's groups, loaded together
+    uint64_t bmv[PG_WAVE], boffv[PG_WAVE];
+    uint32_t sizev[PG_WAVE];
+    int64_t sv[PG_WAVE];
+#pragma unroll
+    for (int x = 0; x < PG_WAVE; ++x) {
+      const int64_t gg = g0 + x;
+      bmv[x] = 0;
+      boffv[x] = 0;
+      sizev[x] = 0;
+      sv[x] = 0;
+      if (gg < Gt) {
+        const int64_t s = a.gseg[gg];
+        const Seg& sg = cm.seg[s];
+        const uint64_t lg = (uint64_t)gg - cm.gpre[s];
+        const uint8_t* e = a.enc + sg.encm;
+        sv[x] = s;
+        bmv[x] = ld64(e + 64 + 8 * sg.PG + 8 * lg);
+        sizev[x] = 8u * e[64 + 8 * sg.PG + 8 * sg.G + lg];
+        boffv[x] = sg.encm + sg.fixed + (a.gex[gg] - a.gex[cm.gpre[s]]);
+      }
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const bool bit = (bitmap >> l) & 1;
-    const uint32_t popc = (uint32_t)__popcll(bitmap);
-    const uint32_t nib = (popc + 1) / 2;
-    const uint32_t t = (uint32_t)__popcll(bitmap & lanemask_lt(l));
-    uint32_t len = 0;
-    if (bit && !bad) len = (blk[t / 2] >> (4 * (t & 1))) & 15u;
-    bool lbad = bit && (len < 1 || len > 8);
-    const uint64_t sig_incl = wave_incl_scan(len);
-    const uint64_t end = nib + uniform64(__shfl(sig_incl, 63, WAVE));
-    if (end > size || round8(end) != size) bad = true;
-    uint64_t D = 0;
-    if (bit && !bad && !lbad) {
-      const uint32_t so = nib + (uint32_t)(sig_incl - len);
-      for (uint32_t b = 0; b < len; ++b) D |= (uint64_t)blk[so + b] << (8 * b);
-      if ((D >> (8 * (len - 1))) == 0) lbad = true;
+#pragma unroll
+    for (int x = 0; x < PG_WAVE; ++x) {
+      const int64_t gg = g0 + x;
+      if (gg >= Gt) break;
+      const Seg& sg = cm.seg[sv[x]];
+      const uint64_t lg = (uint64_t)gg - cm.gpre[sv[x]];
+      const uint64_t bitmap = bmv[x];
+      const uint32_t size = sizev[x];
+      bool bad = size > BLK_MAX;
+      if (!bad)
+        for (uint32_t w = l; w < size / 8; w += WAVE) s_blk[wv][w] = ld64(a.enc + boffv[x] + 8 * w);
+      wave_sync();
+      const bool bit = (bitmap >> l) & 1;
+      const uint32_t popc = (uint32_t)__popcll(bitmap);
+      const uint32_t nib = (popc + 1) / 2;
+      const uint32_t t = (uint32_t)__popcll(bitmap & lanemask_lt(l));
+      uint32_t len = 0;
+      if (bit && !bad) len = (blk[t / 2] >> (4 * (t & 1))) & 15u;
+      bool lbad = bit && (len < 1 || len > 8);
+      const uint64_t sig_incl = wave_incl_scan(len);
+      const uint64_t end = nib + uniform64(__shfl(sig_incl, 63, WAVE));
+      if (end > size || round8(end) != size) bad = true;
+      uint64_t D = 0;
+      if (bit && !bad && !lbad) {
+        const uint32_t so = nib + (uint32_t)(sig_incl - len);
+        for (uint32_t b = 0; b < len; ++b) D |= (uint64_t)blk[so + b] << (8 * b);
+        if ((D >> (8 * (len - 1))) == 0) lbad = true;
+      }
+      if (!bad) {
+        if (end + (uint64_t)l < size && blk[end + l] != 0) lbad = true;   // padding bytes
+        if (l == 0 && (popc & 1) && (blk[popc / 2] >> 4) != 0) lbad = true;  // unused high nibble
+      }
+      const uint64_t q = 64 * lg + (uint64_t)l;
+      if (q < sg.W && !bad) a.D[sg.dbase + q] = D;
+      if (__ballot(lbad) || bad) {
+        if (l == 0) fail(cm.status, ERR_CORRUPT);
+      }
+      wave_sync();
     }
-    if (!bad) {
-      if (end + (uint64_t)l < size && blk[end + l] != 0) lbad = true;   // padding bytes
-      if (l == 0 && (popc & 1) && (blk[popc / 2] >> 4) != 0) lbad = true;  // unused high nibble
+  }
+}
+
+struct ApplyArgs {
+  Common cm;
+  const uint64_t* ref;
+  const MDir* mdir;
+  const uint64_t* mstart;
+  const uint64_t* pred_x;
+  const uint8_t* pred_on;
+  const uint64_t* D;
+  uint64_t* out;
+};
+
+// One lane per matched record: C' = D xor X.  The wave's residual words are
+// contiguous, so they are loaded, combined and written through LDS with
+// coalesced accesses.  A matched record keeps its uid and header: their
+// residual words must be zero.
+__global__ __launch_bounds__(BLOCK) void k_dec_apply(ApplyArgs a) {
+  __shared__ uint64_t s_buf[WAVES][RES_CAP];
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t M = cm.meta[5];
+  const int l = lane_id(), wv = wave_id();
+  uint64_t* buf = s_buf[wv];
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t kb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; kb < M; kb += stride) {
+    const int64_t k = kb + l;
+    const bool act = k < M;
+    const int64_t ke = kb + WAVE < M ? kb + WAVE : M;
+    const uint64_t d0 = a.mstart[kb], d1 = a.mstart[ke];
+    MDir e{};
+    uint64_t words = 0, cpw = 0;
+    int64_t sg = -1;
+    bool learned = false;
+    if (act) {
+      e = a.mdir[k];
+      words = a.mstart[k + 1] - e.dstart;
+      sg = mdir_seg(e);
+      const Seg& g = cm.seg[sg];
+      cpw = g.cpw;
+      learned = g.mode == 1 && a.pred_on[k];
     }
-    const uint64_t q = 64 * lg + (uint64_t)l;
-    const uint64_t dq0 = sg.dbase + 64 * lg;
-    const uint64_t k = window_record(a.mdir, sg.mbase, sg.mbase + sg.n_match, dq0);
-    if (q < sg.W && !bad) {
-      const MDir r = a.mdir[k];
-      const uint64_t w = dq0 + (uint64_t)l - r.dstart;
-      uint64_t x = a.ref[r.rword + w];
-      if (sg.mode == 1 && w >= 2 && w < 6 && a.pred_on[k]) x = a.pred_x[4 * k + (w - 2)];
-      if (w < 2 && D != 0) lbad = true;  // a matched record keeps its uid and header
-      const uint64_t n = sg.n_match + sg.n_new;
-      a.out[(sg.oref + 32 + 8 * ((n + 1) / 2)) / 8 + q] = D ^ x;
+    const int64_t s_first = __shfl(sg, 0, WAVE), s_last = __shfl(sg, (int)(ke - kb - 1), WAVE);
+    const uint64_t cpw0 = __shfl(cpw, 0, WAVE);
+    const bool staged = d1 - d0 <= RES_CAP;
+    const bool one_seg = s_first == s_last;
+    if (staged)
+      for (uint64_t p = l; p < d1 - d0; p += WAVE) buf[p] = a.D[d0 + p];
+    wave_sync();
+    bool bad = false;
+    for (uint64_t w = 0; w < words; ++w) {
+      const uint64_t d = staged ? buf[e.dstart - d0 + w] : a.D[e.dstart + w];
+      if (w < 2 && d != 0) bad = true;
+      uint64_t x = a.ref[e.rword + w];
+      if (learned && w >= 2 && w < 6) x = a.pred_x[4 * k + (w - 2)];
+      if (staged) buf[e.dstart - d0 + w] = d ^ x;
+      else a.out[cpw + e.dstart + w] = d ^ x;
     }
-    if (__ballot(lbad) || bad) {
-      if (l == 0) fail(cm.status, ERR_CORRUPT);
+    if (__ballot(bad) && l == 0) fail(cm.status, ERR_CORRUPT);
+    wave_sync();
+    if (staged) {
+      if (one_seg) {
+        for (uint64_t p = l; p < d1 - d0; p += WAVE) a.out[cpw0 + d0 + p] = buf[p];
+      } else {
+        for (uint64_t w = 0; w < words; ++w) a.out[cpw + e.dstart + w] = buf[e.dstart - d0 + w];
+      }
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
   }
 }
 
@@ -1015,9 +1423,15 @@ __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t
   if (status_of(cm.status) & ANY_ERR) return;
   const uint64_t NW = (uint64_t)cm.meta[7];
   const int64_t Nn = cm.meta[6];
-  for (uint64_t q = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; q < NW; q += (uint64_t)gridDim.x * BLOCK) {
-    const int64_t r = last_le<uint64_t>(nscan, 0, Nn, q);
-    const int64_t s = seg_of(cm.npre, cm.nseg, (uint64_t)r);
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  for (uint64_t qb = (uint64_t)blockIdx.x * BLOCK + wave_id() * WAVE; qb < NW; qb += stride) {
+    const uint64_t q = qb + lane_id();
+    const uint64_t qe = qb + WAVE - 1 < NW ? qb + WAVE - 1 : NW - 1;
+    const int64_t rlo = wave_last_le<uint64_t>(nscan, 0, Nn, qb);
+    const int64_t rhi = wave_last_le<uint64_t>(nscan, rlo, Nn, qe);
+    const int64_t r = last_le<uint64_t>(nscan, rlo, rhi + 1, q < NW ? q : NW - 1);
+    const int64_t s = wave_seg(cm.npre, cm.nseg, (uint64_t)r, (uint64_t)rlo, (uint64_t)rhi);
+    if (q >= NW) continue;
     const Seg& g = cm.seg[s];
     const uint64_t k = r - cm.npre[s];
     const uint64_t w = q - nscan[r];
@@ -1049,10 +1463,18 @@ struct Mem {
   uint64_t* gex;
   uint64_t* pred_x;
   uint8_t* pred_on;
+  uint32_t* gseg;
+  uint64_t* mstart;
+  uint64_t* D;
+  uint64_t* juid;
+  uint64_t* jhdr;
+  uint32_t* jcnt;
+  uint64_t* jcnt_pre;
+  uint64_t* part;
 };
 
 struct Bounds {
-  int64_t C, R, H, G;
+  int64_t C, R, H, G, E, T, B, W;
 };
 
 Mem carve(Arena& ar, int64_t nseg, const Bounds& b) {
@@ -1064,6 +1486,8 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b) {
   m.cm.gpre = ar.take<uint64_t>(nseg + 1);
   m.cm.ppre = ar.take<uint64_t>(nseg + 1);
   m.cm.npre = ar.take<uint64_t>(nseg + 1);
+  m.cm.tpre = ar.take<uint64_t>(nseg + 1);
+  m.cm.bpre = ar.take<uint64_t>(nseg + 1);
   m.cm.meta = ar.take<int64_t>(16);
   m.cm.status = nullptr;
   m.tab = ar.take<Entry>(b.H);
@@ -1080,6 +1504,14 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b) {
   m.gex = ar.take<uint64_t>(b.G + 1);
   m.pred_x = ar.take<uint64_t>(4 * b.R);
   m.pred_on = ar.take<uint8_t>(b.R);
+  m.gseg = ar.take<uint32_t>(b.G);
+  m.mstart = ar.take<uint64_t>(b.R + 1);
+  m.D = ar.take<uint64_t>(b.W);
+  m.juid = ar.take<uint64_t>(b.C + b.R);
+  m.jhdr = ar.take<uint64_t>(b.C + b.R);
+  m.jcnt = ar.take<uint32_t>(b.E);
+  m.jcnt_pre = ar.take<uint64_t>(b.E + 1);
+  m.part = ar.take<uint64_t>(2 * (b.C + b.R));
   return m;
 }
 
@@ -1089,6 +1521,11 @@ Bounds enc_bounds(int64_t nseg, int64_t cur_len, int64_t ref_len) {
   b.R = ref_len / 20 + 1;
   b.H = 4 * (b.C + b.R) + 2 * nseg + 1;
   b.G = ref_len / 512 + nseg + 1;
+  // join: per segment at most 130 counting tiles and 2 n/1024 + 1 buckets
+  b.E = (b.C + b.R) / 4 + 130 * nseg + 1;
+  b.T = (b.C + b.R) / JT + 2 * nseg + 1;
+  b.B = 2 * (b.C + b.R) / JB_TARGET + nseg + 1;
+  b.W = ref_len / 8 + 1;
   return b;
 }
 Bounds dec_bounds(int64_t nseg, int64_t enc_len, int64_t ref_len) {
@@ -1097,6 +1534,10 @@ Bounds dec_bounds(int64_t nseg, int64_t enc_len, int64_t ref_len) {
   b.R = ref_len / 20 + 1;
   b.H = 1;
   b.G = ref_len / 512 + nseg + 1;
+  b.E = 1;
+  b.T = 1;
+  b.B = 1;
+  b.W = ref_len / 8 + 1;
   return b;
 }
 
@@ -1107,7 +1548,7 @@ size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t* t
   Arena ar{nullptr, 0, 0};
   const Bounds b = enc_bounds(nseg, cur_len, ref_len);
   carve(ar, nseg, b);
-  *tiles = ceil_div(std::max(b.C, b.R) + 1, SCAN_TILE) + ceil_div(b.G, TILE_G) + 2;
+  *tiles = ceil_div(std::max(std::max(std::max(b.C, b.R), b.E), b.G) + 1, SCAN_TILE) + 2;
   return ar.used + 256;
 }
 size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t out_cap, int64_t* tiles) {
@@ -1147,22 +1588,41 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   Mem m = carve(ar, nseg, b);
   m.cm.status = c->d_status;
   const int g = c->grid;
-  k_enc_setup<<<1, 1024, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off, clear_first(c));
-  k_clear_tab<<<g, BLOCK, 0, s>>>(m.cm, m.tab, m.cflag);
-  k_enc_insert<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.cwords, m.rwords, m.rslot);
-  k_enc_match<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.rslot, m.m, m.cflag);
-  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(RMatchIn{m.m, m.rwords}, m.cm.meta + 1, m.rscan,
-                                                                     lookback(c, 0));
-  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, m.cscan,
-                                                                   lookback(c, 1));
-  k_enc_seg2<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, newref, newref_cap, newref_off, m.gex);
-  k_enc_mdir<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.mdir, newref);
+  k_enc_setup<<<1, 1024, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off,
+                                 clear_first(c, ceil_div(b.E + 1, SCAN_TILE)));
   {
-    Timed tm(c, "encode_xor", s);
-    XorArgs xa{m.cm,  reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir, enc,
-               enc_cap, reinterpret_cast<uint64_t*>(newref), m.bm, m.gsz, m.gex, nullptr, m.pred_x, m.pred_on,
-               lookback(c, 2)};
-    k_enc_xor<<<grid_for(c, b.G, TILE_G), BLOCK, 0, s>>>(xa);
+    Timed tm(c, "encode_join", s);
+    JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag};
+    k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja);
+    k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, m.jcnt_pre,
+                                                                     lookback(c, 0));
+    k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja);
+    k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja);
+    // only when a bucket overflowed its block: the global-table join
+    k_clear_tab<<<g, BLOCK, 0, s>>>(m.cm, m.tab, m.cflag);
+    k_enc_insert<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.cwords, m.rwords, m.rslot);
+    k_enc_match<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.rslot, m.m, m.cflag);
+  }
+  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(RMatchIn{m.m, m.rwords}, m.cm.meta + 1, m.rscan,
+                                                                     lookback(c, 1));
+  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, m.cscan,
+                                                                   lookback(c, 2));
+  k_enc_seg2<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, newref, newref_cap, newref_off, m.gex, m.mstart);
+  k_enc_mdir<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg);
+  {
+    Timed tm(c, "encode_resid", s);
+    ResidArgs ra{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir,
+                 m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(newref), m.D};
+    k_enc_resid<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
+  }
+  {
+    Timed tm(c, "encode_pack", s);
+    PackArgs pa{m.cm, m.D, enc, enc_cap, m.bm, m.gsz, m.gex, m.gseg};
+    const int gp = grid_for(c, b.G, WAVES * PG_WAVE);
+    k_enc_gsize<<<gp, BLOCK, 0, s>>>(pa);
+    k_scan<GszIn><<<grid_for(c, b.G + 1, SCAN_TILE), BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, m.gex,
+                                                                    lookback(c, 3));
+    k_enc_place<<<gp, BLOCK, 0, s>>>(pa);
   }
   k_enc_fin<<<1, 1024, 0, s>>>(m.cm, m.gex, enc, enc_cap, enc_off, modes);
   k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.cflag, m.cwords, m.cscan, m.bm, m.gsz, enc, enc_cap, newref);
@@ -1196,7 +1656,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   m.cm.status = c->d_status;
   const int g = c->grid;
   k_dec_setup<<<1, 1024, 0, s>>>(m.cm, enc, enc_len, enc_off, ref, ref_len, ref_off, pred != nullptr, out_cap,
-                                 out_off, out, clear_first(c));
+                                 out_off, out, clear_first(c, ceil_div(b.R + 1, SCAN_TILE)));
   k_dec_rslots<<<g, BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag);
   k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1,
                                                                      m.rscan, lookback(c, 0));
@@ -1204,13 +1664,18 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                                                                    lookback(c, 1));
   k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, m.gex,
                                                                      lookback(c, 2));
-  k_dec_seg2<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out);
-  k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.mdir, out);
+  k_dec_seg2<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, m.mstart);
+  k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg);
   {
     Timed tm(c, "decode_unpack", s);
-    UnpackArgs ua{m.cm, enc, reinterpret_cast<const uint64_t*>(ref), m.mdir, m.gex, reinterpret_cast<uint64_t*>(out),
-                  m.pred_x, m.pred_on};
-    k_dec_unpack<<<grid_for(c, b.G, WAVES), BLOCK, 0, s>>>(ua);
+    UnpackArgs ua{m.cm, enc, m.gex, m.gseg, m.D};
+    k_dec_unpack<<<grid_for(c, b.G, WAVES * PG_WAVE), BLOCK, 0, s>>>(ua);
+  }
+  {
+    Timed tm(c, "decode_apply", s);
+    ApplyArgs aa{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, m.mstart, m.pred_x, m.pred_on, m.D,
+                 reinterpret_cast<uint64_t*>(out)};
+    k_dec_apply<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(aa);
   }
   k_dec_newcopy<<<g, BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
   (void)hist_out;

@@ -152,9 +152,12 @@ __device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan of n values given by a functor (value(i) for
 // i < n, uint64_t).  out[i] = sum of values before i, out[n] = total.  n is
-// read from device memory so the launch needs only a host bound.
-constexpr int SCAN_IPT = 8;
-constexpr int SCAN_TILE = BLOCK * SCAN_IPT;
+// read from device memory so the launch needs only a host bound.  A tile is
+// 4 waves x SCAN_ROUNDS rounds of 64 consecutive items: every load and store
+// instruction of a wave touches 64 consecutive items, each round is one wave
+// scan, and one look-back per tile joins the tiles.
+constexpr int SCAN_ROUNDS = 16;
+constexpr int SCAN_TILE = BLOCK * SCAN_ROUNDS;
 
 template <class In>
 __global__ __launch_bounds__(BLOCK) void k_scan(In in, const int64_t* n_dev, uint64_t* out, LookBack lb) {
@@ -168,31 +171,44 @@ __global__ __launch_bounds__(BLOCK) void k_scan(In in, const int64_t* n_dev, uin
     return;
   }
   const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  // blocks beyond the tile count leave before taking a ticket: each ticket is
+  // an atomic on one address, and they serialize
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const int l = lane_id(), wv = wave_id();
   for (;;) {
     const uint32_t t = lb_take_ticket(lb, &s_ticket);
     if ((int64_t)t >= ntiles) break;
-    const int64_t base = (int64_t)t * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
-    uint64_t v[SCAN_IPT];
-    uint64_t sum = 0;
+    const int64_t wbase = (int64_t)t * SCAN_TILE + (int64_t)wv * (WAVE * SCAN_ROUNDS);
+    uint64_t ex[SCAN_ROUNDS];
+    uint64_t carry = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_IPT; ++k) {
-      v[k] = (base + k < n) ? in(base + k) : 0;
-      sum += v[k];
+    for (int r = 0; r < SCAN_ROUNDS; ++r) {
+      const int64_t i = wbase + r * WAVE + l;
+      const uint64_t v = i < n ? in(i) : 0;
+      const uint64_t incl = wave_incl_scan(v);
+      ex[r] = carry + incl - v;
+      carry += __shfl(incl, WAVE - 1, WAVE);
     }
-    uint64_t tot;
-    const uint64_t pre = block_excl_scan(sum, s_wave, &tot);
+    if (l == 0) s_wave[wv] = carry;
+    __syncthreads();
+    uint64_t woff = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < WAVES; ++i) {
+      woff += (i < wv) ? s_wave[i] : 0;
+      tot += s_wave[i];
+    }
     if (threadIdx.x < WAVE) {
       const uint64_t e = lb_exclusive(lb, t, tot);
       if (threadIdx.x == 0) s_prefix = e;
     }
     __syncthreads();
-    uint64_t run = s_prefix + pre;
+    const uint64_t base = s_prefix + woff;
 #pragma unroll
-    for (int k = 0; k < SCAN_IPT; ++k) {
-      if (base + k < n) out[base + k] = run;
-      run += v[k];
+    for (int r = 0; r < SCAN_ROUNDS; ++r) {
+      const int64_t i = wbase + r * WAVE + l;
+      if (i < n) out[i] = base + ex[r];
     }
-    if ((int64_t)t == ntiles - 1 && threadIdx.x == BLOCK - 1) out[n] = run;
+    if ((int64_t)t == ntiles - 1 && threadIdx.x == 0) out[n] = s_prefix + tot;
     __syncthreads();
   }
 }
@@ -207,6 +223,58 @@ __device__ inline int64_t last_le(const T* a, int64_t lo, int64_t hi, T x) {
     else h = m;
   }
   return l;
+}
+
+// The same search done by a whole wave: 64 probes per round (each round
+// shrinks the range 64-fold), result uniform across the wave.  All 64 lanes
+// must call it.
+template <class T>
+__device__ inline int64_t wave_last_le(const T* a, int64_t lo, int64_t hi, T x) {
+  const int l = lane_id();
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + WAVE - 1) / WAVE;
+    const int64_t p = lo + (int64_t)l * step;
+    const bool ok = p < hi && a[p] <= x;
+    const uint64_t m = __ballot(ok);
+    const int last = m ? 63 - __clzll((long long)m) : 0;
+    lo = lo + (int64_t)last * step;
+    hi = (lo + step < hi) ? lo + step : hi;
+  }
+  return lo;
+}
+
+// Same, comparing only the bits of a[] selected by mask (a[] & mask must be
+// non-decreasing).
+__device__ inline int64_t wave_last_le_masked(const uint64_t* a, int64_t lo, int64_t hi, uint64_t x, uint64_t mask) {
+  const int l = lane_id();
+  while (hi - lo > 1) {
+    const int64_t step = (hi - lo + WAVE - 1) / WAVE;
+    const int64_t p = lo + (int64_t)l * step;
+    const bool ok = p < hi && (a[p] & mask) <= x;
+    const uint64_t m = __ballot(ok);
+    const int last = m ? 63 - __clzll((long long)m) : 0;
+    lo = lo + (int64_t)last * step;
+    hi = (lo + step < hi) ? lo + step : hi;
+  }
+  return lo;
+}
+__device__ inline int64_t last_le_masked(const uint64_t* a, int64_t lo, int64_t hi, uint64_t x, uint64_t mask) {
+  int64_t l = lo, h = hi;
+  while (h - l > 1) {
+    const int64_t m = l + (h - l) / 2;
+    if ((a[m] & mask) <= x) l = m;
+    else h = m;
+  }
+  return l;
+}
+
+// Segment of item g (pre: per-segment prefix, nseg+1 entries) when the wave
+// works on the consecutive items [first, last]: two wave searches bound the
+// segments of the wave, then each lane searches only that small range.
+__device__ inline int64_t wave_seg(const uint64_t* pre, int64_t nseg, uint64_t g, uint64_t first, uint64_t last) {
+  const int64_t lo = wave_last_le<uint64_t>(pre, 0, nseg, first);
+  const int64_t hi = wave_last_le<uint64_t>(pre, lo, nseg, last);
+  return last_le<uint64_t>(pre, lo, hi + 1, g);
 }
 
 __device__ inline uint64_t ld64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }

@@ -66,13 +66,15 @@ ta_status ensure_scratch(ta_ctx* c, size_t bytes, int64_t tiles);
 // kernel of a call that has look-back kernels must clear array 0 itself
 // (clear_first()).
 LookBack lookback(ta_ctx* c, int k);
-// What the first kernel of a call clears: array 0 and ticket 0.
+// What the first kernel of a call clears: ticket 0 and the first `tiles`
+// entries of array 0 (at least what the call's first look-back kernel uses;
+// every later look-back kernel clears the whole other array).
 struct ClearFirst {
   uint64_t* flags;
   uint32_t* ticket;
   int64_t n;
 };
-ClearFirst clear_first(ta_ctx* c);
+ClearFirst clear_first(ta_ctx* c, int64_t tiles);
 
 __device__ inline void do_clear_first(const ClearFirst& cf) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;

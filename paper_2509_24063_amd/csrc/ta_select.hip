@@ -292,7 +292,8 @@ extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, c
   const DirTable dt = make_dirs(ndirs);
   const int64_t cnt_cap = sel_sizes(ag->n, P, ndirs).cnt_cap;
   const int g = grid_for(c, sel_sizes(ag->n, P, ndirs).ntiles, 1);
-  k_sel_prep<<<1, 1024, 0, s>>>(part_off, P, ndirs, ag->n, sc, clear_first(c), c->d_status);
+  k_sel_prep<<<1, 1024, 0, s>>>(part_off, P, ndirs, ag->n, sc, clear_first(c, ceil_div(cnt_cap + 1, SCAN_TILE)),
+                                c->d_status);
   {
     Timed tm(c, "select_count", s);
     if (ndirs == 26)

@@ -11,10 +11,8 @@
 //   k_ser_begin  checks the segment table, clears the look-back array
 //   k_scan       exclusive scan of record sizes (words) over all records
 //   k_ser_msgoff one block: message sizes, their offsets, the headers
-//   k_ser_pack   one thread per output word: each block stages the metadata
-//                of the records its 1024 words touch in LDS and writes the
-//                words with coalesced 8-byte stores; it also writes the
-//                offset table entries of the records starting in its window
+//   k_ser_pack   one thread per record: fields gathered from the store,
+//                record and offset-table entry written
 #include "ta_internal.hpp"
 #include "ta_msg.hpp"
 #include "ta_scratch.hpp"
@@ -22,10 +20,6 @@
 using namespace ta;
 
 namespace {
-
-constexpr int PACK_WPT = 4;
-constexpr int PACK_BW = BLOCK * PACK_WPT;   // words per block window
-constexpr int PACK_MAXREC = PACK_BW / 2 + 2;  // records are >= 2 words
 
 struct SerScratch {
   uint64_t* wpre;  // [idx_cap+1] exclusive prefix of record words
@@ -143,77 +137,72 @@ struct PackArgs {
   uint8_t* out;
 };
 
+constexpr int PACK_CAP = 1024;  // record words one wave stages in LDS
+
+// One lane per record: it gathers the agent's fields and writes its offset
+// table entry.  When the wave's 64 records belong to one message and fit in
+// LDS, the records are assembled there and written with coalesced stores;
+// otherwise each lane writes its own record.
 __global__ __launch_bounds__(BLOCK) void k_ser_pack(PackArgs a, SerScratch sc) {
-  __shared__ uint64_t s_start[PACK_MAXREC + 1];  // record start words (global word space)
-  __shared__ int64_t s_obase[PACK_MAXREC];       // byte offset of record start in out
-  __shared__ int32_t s_agent[PACK_MAXREC];
-  __shared__ uint32_t s_meta[PACK_MAXREC];       // class | nf << 8 | ni << 16 (i32 words)
-  __shared__ int64_t s_r0;
-  __shared__ int32_t s_nrec;
+  __shared__ uint64_t s_buf[WAVES][PACK_CAP];
   const int64_t R = sc.meta[0];
-  const uint64_t Wt = (uint64_t)sc.meta[1];
-  for (uint64_t q0 = (uint64_t)blockIdx.x * PACK_BW; q0 < Wt; q0 += (uint64_t)gridDim.x * PACK_BW) {
-    const uint64_t qe = q0 + PACK_BW < Wt ? q0 + PACK_BW : Wt;
-    if (threadIdx.x == 0) {
-      const int64_t r0 = last_le<uint64_t>(sc.wpre, 0, R, q0);
-      const int64_t r1 = last_le<uint64_t>(sc.wpre, 0, R, qe - 1);
-      s_r0 = r0;
-      s_nrec = (int32_t)(r1 - r0 + 1);
-    }
-    __syncthreads();
-    const int64_t r0 = s_r0;
-    const int nrec = s_nrec;
-    for (int k = threadIdx.x; k < nrec; k += BLOCK) {
-      const int64_t r = r0 + k;
-      const int32_t ag = a.idx[r];
-      const uint32_t c = a.cls[ag];
-      const int64_t s = last_le<int64_t>(a.seg_off, 0, a.nseg, r);
+  if (sc.meta[1] == 0) return;  // nothing to write (error, capacity, or no words)
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  const uint64_t* seg_off = reinterpret_cast<const uint64_t*>(a.seg_off);
+  const int l = lane_id(), wv = wave_id();
+  uint64_t* buf = s_buf[wv];
+  for (int64_t base = (int64_t)blockIdx.x * BLOCK + wv * WAVE; base < R; base += stride) {
+    const int64_t r = base + l;
+    const int64_t re = base + WAVE < R ? base + WAVE : R;
+    const uint64_t last = (uint64_t)(re - 1);
+    const int64_t s = wave_seg(seg_off, a.nseg, (uint64_t)(r < R ? r : R - 1), (uint64_t)base, last);
+    const int64_t s_first = __shfl(s, 0, WAVE), s_last = __shfl(s, (int)(re - 1 - base), WAVE);
+    const uint64_t w0 = sc.wpre[base], w1 = sc.wpre[re];
+    const bool staged = s_first == s_last && w1 - w0 <= PACK_CAP;
+    uint64_t* dst = nullptr;
+    uint64_t rel = 0, words = 0;
+    int32_t ag = 0;
+    uint32_t c = 0, F = 0, I = 0, IW = 0;
+    if (r < R) {
+      ag = a.idx[r];
+      c = a.cls[ag];
+      F = a.nf[c];
+      I = a.ni[c];
+      IW = (I + 1) / 2;
       const int64_t first = a.seg_off[s];
       const uint64_t n = (uint64_t)(a.seg_off[s + 1] - first);
       const uint64_t wr = sc.wpre[r], ws = sc.wpre[first];
-      s_start[k] = wr;
-      s_agent[k] = ag;
-      s_meta[k] = c | ((uint32_t)a.nf[c] << 8) | ((uint32_t)a.ni[c] << 16);
-      const int64_t mbase = a.msg_off[s];
-      s_obase[k] = mbase + 32 + 8 * (int64_t)((n + 1) / 2) + 8 * (int64_t)(wr - ws);
-      if (wr >= q0) *reinterpret_cast<uint32_t*>(a.out + mbase + 32 + 4 * (r - first)) = (uint32_t)(wr - ws);
-    }
-    if (threadIdx.x == 0) s_start[nrec] = sc.wpre[r0 + nrec];
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < PACK_WPT; ++j) {
-      const uint64_t q = q0 + (uint64_t)j * BLOCK + threadIdx.x;
-      if (q >= qe) break;
-      // record of word q: last staged start <= q
-      int lo = 0, hi = nrec;
-      while (hi - lo > 1) {
-        const int m = (lo + hi) >> 1;
-        if (s_start[m] <= q) lo = m;
-        else hi = m;
+      words = sc.wpre[r + 1] - wr;
+      uint8_t* m = a.out + a.msg_off[s];
+      *reinterpret_cast<uint32_t*>(m + 32 + 4 * (r - first)) = (uint32_t)(wr - ws);
+      rel = wr - w0;
+      dst = staged ? buf + rel : reinterpret_cast<uint64_t*>(m + 32 + 8 * ((n + 1) / 2) + 8 * (wr - ws));
+      dst[0] = a.uid[ag];
+      dst[1] = (uint64_t)c | ((uint64_t)a.nb[ag] << 16) | (words << 32);
+      for (uint32_t k = 0; k < F; ++k) dst[2 + k] = __double_as_longlong(a.f64[(int64_t)k * a.fstride + ag]);
+      for (uint32_t j = 0; j < IW; ++j) {
+        const uint32_t lo32 = (uint32_t)a.i32[(int64_t)(2 * j) * a.istride + ag];
+        const uint32_t hi32 = (2 * j + 1 < I) ? (uint32_t)a.i32[(int64_t)(2 * j + 1) * a.istride + ag] : 0u;
+        dst[2 + F + j] = (uint64_t)lo32 | ((uint64_t)hi32 << 32);
       }
-      const uint64_t k = q - s_start[lo];
-      const int32_t ag = s_agent[lo];
-      const uint32_t meta = s_meta[lo];
-      const uint32_t F = (meta >> 8) & 0xFF, I = meta >> 16, IW = (I + 1) / 2;
-      uint64_t v;
-      if (k == 0) {
-        v = a.uid[ag];
-      } else if (k == 1) {
-        const uint64_t words = s_start[lo + 1] - s_start[lo];
-        v = (uint64_t)(meta & 0xFF) | ((uint64_t)a.nb[ag] << 16) | (words << 32);
-      } else if (k < 2 + F) {
-        v = __double_as_longlong(a.f64[(int64_t)(k - 2) * a.fstride + ag]);
-      } else if (k < 2 + F + IW) {
-        const int64_t j2 = 2 * (int64_t)(k - 2 - F);
-        const uint32_t lo32 = (uint32_t)a.i32[j2 * a.istride + ag];
-        const uint32_t hi32 = (j2 + 1 < (int64_t)I) ? (uint32_t)a.i32[(j2 + 1) * a.istride + ag] : 0u;
-        v = (uint64_t)lo32 | ((uint64_t)hi32 << 32);
-      } else {
-        v = *reinterpret_cast<const uint64_t*>(a.beh + a.beh_off[ag] + 8 * (int64_t)(k - 2 - F - IW));
-      }
-      *reinterpret_cast<uint64_t*>(a.out + s_obase[lo] + 8 * (int64_t)k) = v;
+      const uint64_t* bsrc = reinterpret_cast<const uint64_t*>(a.beh + a.beh_off[ag]);
+      const uint64_t nbw = words - 2 - F - IW;
+      for (uint64_t k = 0; k < nbw; ++k) dst[2 + F + IW + k] = bsrc[k];
     }
-    __syncthreads();
+    if (staged) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // the wave's records are one contiguous stretch of its message
+      const int64_t first = a.seg_off[s_first];
+      const uint64_t n = (uint64_t)(a.seg_off[s_first + 1] - first);
+      uint64_t* out = reinterpret_cast<uint64_t*>(a.out + a.msg_off[s_first] + 32 + 8 * ((n + 1) / 2)) +
+                      (w0 - sc.wpre[first]);
+      for (uint64_t p = l; p < w1 - w0; p += WAVE) out[p] = buf[p];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
   }
 }
 
@@ -249,7 +238,8 @@ extern "C" ta_status ta_serialize(ta_ctx* c, const ta_agents* ag, const int32_t*
   hipStream_t s = (hipStream_t)stream;
   Arena ar{c->scratch, c->scratch_cap, 0};
   SerScratch sc = carve(ar, idx_cap);
-  k_ser_begin<<<1, BLOCK, 0, s>>>(seg_off, nseg, idx_cap, sc, clear_first(c), c->d_status);
+  k_ser_begin<<<1, BLOCK, 0, s>>>(seg_off, nseg, idx_cap, sc, clear_first(c, ceil_div(idx_cap + 1, SCAN_TILE)),
+                                  c->d_status);
   WordsIn win{idx, ag->cls, ag->beh_off, c->d_nf, c->d_ni, c->n_classes, ag->n, c->d_status};
   k_scan<WordsIn><<<grid_for(c, idx_cap + 1, SCAN_TILE), BLOCK, 0, s>>>(win, sc.meta, sc.wpre, lookback(c, 0));
   k_ser_msgoff<<<1, 1024, 0, s>>>(seg_off, nseg, sc, out, out_cap, msg_off, c->d_status);

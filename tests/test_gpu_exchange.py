@@ -234,3 +234,38 @@ def test_view_reads_and_mutates_in_place(native):
     ctx.validate(bad, moff)
     assert ctx.poll() == native.INVALID
     ctx.close()
+
+
+def _mix64(x):
+    x = np.asarray(x, np.uint64)
+    with np.errstate(over="ignore"):
+        x = x ^ (x >> np.uint64(31))
+        x = x * np.uint64(0x7fb5d329728ea185)
+        x = x ^ (x >> np.uint64(27))
+        x = x * np.uint64(0x81dadef4bc2dd44d)
+        x = x ^ (x >> np.uint64(33))
+    return x
+
+
+def test_join_bucket_overflow_falls_back(native):
+    """Uids chosen so that every item of a 4000-item segment lands in one of
+    its 4 join buckets (more than one block holds in LDS): the encoder must
+    switch to its global-table join and still match the oracle."""
+    cand = np.arange(1, 200000, dtype=np.uint64)
+    same = cand[(_mix64(cand) & np.uint64(3)) == 0][:2000]
+    r = [rec(int(u), x=float(k), words=7) for k, u in enumerate(same)]
+    c = [list(x) for x in r[100:]]
+    for x in c:
+        x[2] ^= 0x1234
+    c += [rec(int(u), words=7) for u in cand[(_mix64(cand) & np.uint64(3)) == 0][2000:2100]]
+    ctx = native.Context(synth.Schema((4,), (1,)))
+    cur, coff = _upload(native, [tam1(c)])
+    ref, roff = _upload(native, [tam1(r)])
+    print("[overflow] 4000-item segment in one bucket", flush=True)
+    enc, eoff, nref, noff, _ = ctx.delta_encode(cur, coff, ref, roff)
+    ctx.check("overflow encode")
+    st, oenc, onref, _, _ = oracle.delta_encode(tam1(c), tam1(r))
+    assert st == 0
+    assert np.array_equal(host(enc, host(eoff)), oenc)
+    assert np.array_equal(host(nref, host(noff)), onref)
+    ctx.close()
