@@ -192,6 +192,15 @@ typedef struct ta_predictor ta_predictor;
 ta_status ta_predictor_load(ta_ctx *ctx, const void *blob, size_t len, ta_predictor **out);
 void ta_predictor_free(ta_predictor *p);
 
+/* Evaluate the predictor on n rows of 12 int32 inputs (device, row-major; the
+ * inputs the exchange forms are q(R-h1) x4, q(h1-h2) x4, neighbour count,
+ * behaviour count, class, history length) into n rows of 4 int32 outputs
+ * (device): integer layers with int32 accumulation, requantisation
+ * floor((a + 2^(r-1)) / 2^r), ReLU clamp to [0,127] after layers 1 and 2,
+ * outputs clamped to +-2^24. */
+ta_status ta_predictor_eval(ta_ctx *ctx, const ta_predictor *p, const int32_t *in, int32_t *q, int64_t n,
+                            void *stream);
+
 /* Per reference slot history of the predicted words (device):
  * h1[4j..4j+3] words 2..5 of slot j's record one exchange before the
  * reference, h2 two exchanges before (raw fp64 bits), hlen[j] in {0,1,2}. */

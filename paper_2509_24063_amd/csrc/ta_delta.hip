@@ -589,6 +589,7 @@ __global__ __launch_bounds__(1024) void k_enc_seg2(Common cm, const uint64_t* rs
       g.W = (re & WMASK) - g.dbase;
       g.nbase = cs >> PK;
       g.n_new = (ce >> PK) - g.nbase;
+      cm.npre[s] = g.nbase;
       g.npbase = cs & WMASK;
       g.new_words = (ce & WMASK) - g.npbase;
       G = (g.W + 63) / 64;
@@ -631,6 +632,7 @@ __global__ __launch_bounds__(1024) void k_enc_seg2(Common cm, const uint64_t* rs
     cm.meta[4] = s_carry[3];
     cm.meta[5] = rscan[cm.meta[1]] >> PK;
     cm.meta[6] = cscan[cm.meta[0]] >> PK;
+    cm.npre[cm.nseg] = (uint64_t)cm.meta[6];
     cm.meta[7] = cscan[cm.meta[0]] & WMASK;
     cm.meta[9] = (int64_t)s_carry[1];  // fixed total
     gex[s_carry[0]] = 0;
@@ -729,7 +731,8 @@ struct ResidArgs {
   const uint64_t* pred_x;  // learned: predicted words 2..5 per matched record [k][4]
   const uint8_t* pred_on;  // learned: record k predicted
   uint64_t* newref;        // C' (words)
-  uint64_t* D;             // dense residual of all segments
+  uint64_t* D;             // dense residual of all segments (against R)
+  uint64_t* D2;            // learned mode: residual against the predictions (nullptr: plain)
 };
 
 // One lane per matched record (64 consecutive matched records per wave): the
@@ -765,6 +768,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_resid(ResidArgs a) {
     const uint64_t cpw0 = __shfl(cpw, 0, WAVE);
     const bool staged = d1 - d0 <= RES_CAP;
     const bool one_seg = s_first == s_last;
+    if (act && a.D2) learned = a.pred_on[k];  // both variants are formed; the mode is chosen later
     for (uint64_t w = 0; w < words; ++w) {
       const uint64_t c = a.cur[e.cword + w];
       if (staged) buf[e.dstart - d0 + w] = c;
@@ -781,15 +785,28 @@ __global__ __launch_bounds__(BLOCK) void k_enc_resid(ResidArgs a) {
     wave_sync();
     for (uint64_t w = 0; w < words; ++w) {
       const uint64_t c = staged ? buf[e.dstart - d0 + w] : a.cur[e.cword + w];
-      uint64_t x = a.ref[e.rword + w];
-      if (learned && w >= 2 && w < 6) x = a.pred_x[4 * k + (w - 2)];
+      const uint64_t x = a.ref[e.rword + w];
       if (staged) buf[e.dstart - d0 + w] = c ^ x;
       else a.D[e.dstart + w] = c ^ x;
+      if (!staged && a.D2) {
+        const uint64_t xl = (learned && w >= 2 && w < 6) ? a.pred_x[4 * k + (w - 2)] : x;
+        a.D2[e.dstart + w] = c ^ xl;
+      }
     }
     wave_sync();
     if (staged)
       for (uint64_t p = l; p < d1 - d0; p += WAVE) a.D[d0 + p] = buf[p];
     wave_sync();
+    if (staged && a.D2) {
+      // learned variant: D2 = D xor R xor P on the predicted words
+      if (learned) {
+        for (uint64_t w = 2; w < 6 && w < words; ++w)
+          buf[e.dstart - d0 + w] ^= a.ref[e.rword + w] ^ a.pred_x[4 * k + (w - 2)];
+      }
+      wave_sync();
+      for (uint64_t p = l; p < d1 - d0; p += WAVE) a.D2[d0 + p] = buf[p];
+      wave_sync();
+    }
   }
 }
 
@@ -798,10 +815,12 @@ struct PackArgs {
   const uint64_t* D;
   uint8_t* enc;
   int64_t enc_cap;
-  uint64_t* bm;          // [groups] word bitmaps
-  uint8_t* gsz;          // [groups] block sizes / 8
+  uint64_t* bm;          // [groups] word bitmaps (of the chosen variant after pass 3)
+  uint8_t* gsz;          // [groups] block sizes / 8 (of the chosen variant after pass 3)
   const uint64_t* gex;   // [groups+1] exclusive prefix of block bytes (pass 3)
   const uint32_t* gseg;  // [groups] segment of the group
+  const uint64_t* D2;    // learned variant (nullptr: plain only)
+  uint8_t* gsz2;         // learned variant block sizes / 8
 };
 
 constexpr int PG_WAVE = 4;  // groups one wave handles at a time (loads issued together)
@@ -815,15 +834,19 @@ __global__ __launch_bounds__(BLOCK) void k_enc_gsize(PackArgs a) {
   const int l = lane_id();
   const int64_t nw = (int64_t)gridDim.x * WAVES;
   for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wave_id()) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
-    uint64_t Dv[PG_WAVE];
+    uint64_t Dv[PG_WAVE], D2v[PG_WAVE];
 #pragma unroll
     for (int x = 0; x < PG_WAVE; ++x) {
       const int64_t gg = g0 + x;
       Dv[x] = 0;
+      D2v[x] = 0;
       if (gg < Gt) {
         const Seg& sg = cm.seg[a.gseg[gg]];
         const uint64_t q = 64 * ((uint64_t)gg - cm.gpre[a.gseg[gg]]) + (uint64_t)l;
-        if (q < sg.W) Dv[x] = a.D[sg.dbase + q];
+        if (q < sg.W) {
+          Dv[x] = a.D[sg.dbase + q];
+          if (a.D2) D2v[x] = a.D2[sg.dbase + q];
+        }
       }
     }
 #pragma unroll
@@ -838,6 +861,13 @@ __global__ __launch_bounds__(BLOCK) void k_enc_gsize(PackArgs a) {
         a.bm[gg] = bm;
         a.gsz[gg] = (uint8_t)(round8(((uint64_t)__popcll(bm) + 1) / 2 + sig) / 8);
       }
+      if (a.D2) {
+        const uint64_t D2 = D2v[x];
+        const uint64_t bm2 = __ballot(D2 != 0);
+        const uint64_t len2 = D2 ? (uint64_t)(8 - (__clzll((long long)D2) >> 3)) : 0;
+        const uint64_t sig2 = wave_sum(len2);
+        if (l == 0) a.gsz2[gg] = (uint8_t)(round8(((uint64_t)__popcll(bm2) + 1) / 2 + sig2) / 8);
+      }
     }
   }
 }
@@ -846,6 +876,26 @@ struct GszIn {
   const uint8_t* gsz;
   __device__ uint64_t operator()(int64_t g) const { return 8 * (uint64_t)gsz[g]; }
 };
+struct GChosenIn {  // block bytes of the variant chosen for the group's segment
+  const uint8_t* gsz;
+  const uint8_t* gsz2;
+  const uint32_t* gseg;
+  const Seg* seg;
+  __device__ uint64_t operator()(int64_t g) const {
+    return 8 * (uint64_t)(seg[gseg[g]].mode == 1 ? gsz2[g] : gsz[g]);
+  }
+};
+
+// Learned mode: per segment, keep the predictor's encoding only when it is
+// strictly smaller (the fixed sections are the same for both).
+__global__ __launch_bounds__(1024) void k_choose_mode(Common cm, const uint64_t* gex, const uint64_t* gex2) {
+  if (status_of(cm.status) & ANY_ERR) return;
+  for (int64_t s = threadIdx.x; s < cm.nseg; s += 1024) {
+    const uint64_t plain = gex[cm.gpre[s + 1]] - gex[cm.gpre[s]];
+    const uint64_t learned = gex2[cm.gpre[s + 1]] - gex2[cm.gpre[s]];
+    cm.seg[s].mode = learned < plain ? 1 : 0;
+  }
+}
 
 // Pass 3: every group rebuilds its block in LDS and writes it at its offset.
 __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
@@ -866,7 +916,8 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
         const int64_t s = a.gseg[gg];
         const Seg& sg = cm.seg[s];
         const uint64_t q = 64 * ((uint64_t)gg - cm.gpre[s]) + (uint64_t)l;
-        if (q < sg.W) Dv[x] = a.D[sg.dbase + q];
+        const uint64_t* src = (a.D2 && sg.mode == 1) ? a.D2 : a.D;
+        if (q < sg.W) Dv[x] = src[sg.dbase + q];
         at[x] = sg.fixed_excl + sg.fixed + a.gex[gg];
       }
     }
@@ -876,6 +927,10 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
       if (gg >= Gt) break;
       uint64_t bm;
       const uint32_t size = build_block(Dv[x], reinterpret_cast<uint8_t*>(s_blk[wv]), &bm);
+      if (a.D2 && l == 0) {  // the tables of the chosen variant
+        a.bm[gg] = bm;
+        a.gsz[gg] = (uint8_t)(size / 8);
+      }
       if (size) {
         if (at[x] + size > (uint64_t)a.enc_cap) {
           if (l == 0) fail(cm.status, ERR_CAPACITY);
@@ -1014,14 +1069,14 @@ __global__ __launch_bounds__(1024) void k_dec_setup(Common cm, const uint8_t* en
                                                     const int64_t* ref_off, bool have_pred, int64_t out_cap,
                                                     int64_t* out_off, uint8_t* out, ClearFirst cf) {
   __shared__ uint64_t s_w[16];
-  __shared__ uint64_t s_carry[5];
+  __shared__ uint64_t s_carry[6];
   BlockScan1024 bs{s_w};
   do_clear_first(cf);
-  if (threadIdx.x < 5) s_carry[threadIdx.x] = 0;
+  if (threadIdx.x < 6) s_carry[threadIdx.x] = 0;
   __syncthreads();
   for (int64_t s0 = 0; s0 < cm.nseg; s0 += 1024) {
     const int64_t s = s0 + threadIdx.x;
-    uint64_t nr = 0, G = 0, nn = 0, osz = 0, PG = 0;
+    uint64_t nr = 0, G = 0, nn = 0, osz = 0, PG = 0, hs = 0;
     if (s < cm.nseg) {
       Seg& g = cm.seg[s];
       const int64_t ea = enc_off[s], eb = enc_off[s + 1], ra = ref_off[s], rb = ref_off[s + 1];
@@ -1089,17 +1144,20 @@ __global__ __launch_bounds__(1024) void k_dec_setup(Common cm, const uint8_t* en
             nn = n_new;
             PG = PGs;
             osz = tam1_size(n_match + n_new, W + new_words);
+            hs = pow2ceil(2 * nr);
+            g.hsize = hs;
           }
         }
       }
       if (code) {
         fail(cm.status, code);
-        nr = G = nn = osz = PG = 0;
+        nr = G = nn = osz = PG = hs = 0;
       }
     }
-    uint64_t t0, t1, t2, t3, t4;
+    uint64_t t0, t1, t2, t3, t4, t5;
     const uint64_t e0 = bs.excl(nr, &t0), e1 = bs.excl(G, &t1), e2 = bs.excl(nn, &t2), e3 = bs.excl(osz, &t3),
-                   e4 = bs.excl(PG, &t4);
+                   e4 = bs.excl(PG, &t4), e5 = bs.excl(hs, &t5);
+    if (s < cm.nseg) cm.seg[s].hbase = s_carry[5] + e5;
     if (s < cm.nseg) {
       cm.rpre[s] = s_carry[0] + e0;
       cm.gpre[s] = s_carry[1] + e1;
@@ -1115,10 +1173,12 @@ __global__ __launch_bounds__(1024) void k_dec_setup(Common cm, const uint8_t* en
       s_carry[2] += t2;
       s_carry[3] += t3;
       s_carry[4] += t4;
+      s_carry[5] += t5;
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    cm.meta[2] = s_carry[5];
     cm.rpre[cm.nseg] = s_carry[0];
     cm.gpre[cm.nseg] = s_carry[1];
     cm.npre[cm.nseg] = s_carry[2];
@@ -1446,6 +1506,208 @@ __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Learned predictor inside the exchange (both sides evaluate it identically
+// from the reference and the per-slot history).
+
+// Cell of a reference record from its words 2..4 (x, y, z): floor(v / cell)
+// per axis, packed in 21 bits each; false when not finite or out of range.
+__device__ inline bool cell_key(const uint64_t* rec, double cell, uint64_t* key) {
+  uint64_t k = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double f = floor(__longlong_as_double((long long)rec[2 + a]) / cell);
+    if (!(f > -1048576.0 && f < 1048576.0)) return false;
+    k = (k << 21) | (uint64_t)((int64_t)f + 1048576);
+  }
+  *key = k;
+  return true;
+}
+
+// Neighbour counts: per segment, an open-addressing table of the cells of
+// its reference records (key, count).
+__global__ __launch_bounds__(BLOCK) void k_nbr_clear(Common cm, Entry* tab, int64_t hist_cap) {
+  if (status_of(cm.status) & ANY_ERR) return;
+  if (hist_cap < cm.meta[1]) {  // the history must cover every reference slot
+    if (blockIdx.x == 0 && threadIdx.x == 0) fail(cm.status, ERR_INVALID);
+    return;
+  }
+  const int64_t H = cm.meta[2];
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < H; i += (int64_t)gridDim.x * BLOCK) {
+    tab[i].key = 0;
+    tab[i].ci = 0;
+  }
+}
+
+__device__ inline uint64_t ref_record_word(const Common& cm, const uint8_t* ref, int64_t s, uint64_t j) {
+  const Seg& g = cm.seg[s];
+  return g.rbody / 8 + ld32(ref + g.rmsg + 32 + 4 * j);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_nbr_build(Common cm, const uint8_t* ref, const PredW* pw, Entry* tab) {
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t Rt = cm.meta[1];
+  const double cell = pw->cell;
+  const uint64_t* ref64 = reinterpret_cast<const uint64_t*>(ref);
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t base = (int64_t)blockIdx.x * BLOCK + wave_id() * WAVE; base < Rt; base += stride) {
+    const int64_t g = base + lane_id();
+    const uint64_t last = (uint64_t)(base + WAVE - 1 < Rt ? base + WAVE - 1 : Rt - 1);
+    const int64_t s = wave_seg(cm.rpre, cm.nseg, (uint64_t)(g < Rt ? g : Rt - 1), (uint64_t)base, last);
+    if (g >= Rt) continue;
+    const uint64_t* rec = ref64 + ref_record_word(cm, ref, s, g - cm.rpre[s]);
+    uint64_t key;
+    if ((rec[1] >> 32) < 5 || !cell_key(rec, cell, &key)) continue;
+    const Seg& sg = cm.seg[s];
+    const uint64_t H = sg.hsize;
+    uint64_t h = mix64(key) & (H - 1);
+    for (uint64_t probe = 0; probe < H; ++probe) {
+      const unsigned long long prev = atomicCAS(&tab[sg.hbase + h].key, 0ull, (unsigned long long)key);
+      if (prev == 0ull || prev == (unsigned long long)key) {
+        atomicAdd(&tab[sg.hbase + h].ci, 1u);
+        break;
+      }
+      h = (h + 1) & (H - 1);
+    }
+  }
+}
+
+__device__ inline uint32_t nbr_count(const Common& cm, const Entry* tab, int64_t s, const uint64_t* rec, double cell) {
+  uint64_t key;
+  if ((rec[1] >> 32) < 5 || !cell_key(rec, cell, &key)) return 0;
+  const Seg& sg = cm.seg[s];
+  const uint64_t H = sg.hsize;
+  uint64_t h = mix64(key) & (H - 1);
+  for (uint64_t probe = 0; probe < H; ++probe) {
+    const Entry e = tab[sg.hbase + h];
+    if (e.key == key) return e.ci > 127 ? 127 : e.ci;
+    if (e.key == 0) return 0;
+    h = (h + 1) & (H - 1);
+  }
+  return 0;
+}
+
+struct PredictArgs {
+  Common cm;
+  const uint64_t* ref;
+  const MDir* mdir;
+  const PredW* pw;
+  const Entry* tab;
+  const uint64_t* h1;  // history of reference slots
+  const uint64_t* h2;
+  const uint8_t* hlen;
+  uint64_t* pred_x;    // [matched][4] predicted words 2..5
+  uint8_t* pred_on;    // [matched]
+};
+
+// One wave per 16 matched records: inputs, integer MLP, predicted words.
+__global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
+  __shared__ PredW s_w;
+  __shared__ int32_t s_in[WAVES][16][12];
+  __shared__ int32_t s_q[WAVES][16][4];
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  load_weights(&s_w, a.pw);
+  const int64_t M = cm.meta[5];
+  const int l = lane_id(), wv = wave_id();
+  const int64_t chunks = (M + 15) / 16;
+  for (int64_t ch = (int64_t)blockIdx.x * WAVES + wv; ch < chunks; ch += (int64_t)gridDim.x * WAVES) {
+    const int64_t k = ch * 16 + l;
+    bool on = false;
+    const uint64_t* rec = nullptr;
+    if (l < 16 && k < M) {
+      const MDir e = a.mdir[k];
+      const uint64_t g = mdir_slot(e);
+      rec = a.ref + e.rword;
+      const uint64_t hdr = rec[1];
+      const int hl = a.hlen[g];
+      on = hl >= 1 && (hdr >> 32) >= 6;
+      int32_t* in = s_in[wv][l];
+      for (int c = 0; c < 12; ++c) in[c] = 0;
+      if (on) {
+        for (int c = 0; c < 4; ++c) {
+          const double r = __longlong_as_double((long long)rec[2 + c]);
+          const double v1 = __longlong_as_double((long long)a.h1[4 * g + c]);
+          const double v2 = __longlong_as_double((long long)a.h2[4 * g + c]);
+          in[c] = quantise(r - v1);
+          in[4 + c] = hl >= 2 ? quantise(v1 - v2) : 0;
+        }
+        in[8] = (int32_t)nbr_count(cm, a.tab, mdir_seg(e), rec, s_w.cell);
+        in[9] = (int32_t)((hdr >> 16) & 0xFFFF);
+        in[10] = (int32_t)(hdr & 0xFFFF);
+        in[11] = hl;
+      }
+    }
+    wave_sync();
+    mlp16(s_w, s_in[wv], s_q[wv]);
+    wave_sync();
+    if (l < 16 && k < M) {
+      a.pred_on[k] = on ? 1 : 0;
+      if (on) {
+        for (int c = 0; c < 4; ++c) {
+          const uint64_t rb = rec[2 + c];
+          const double r = __longlong_as_double((long long)rb);
+          const int32_t q = s_q[wv][l][c];
+          a.pred_x[4 * k + c] =
+              (q != 0 && isfinite(r)) ? (uint64_t)__double_as_longlong(r + (double)q * 0x1p-12) : rb;
+        }
+      }
+    }
+    wave_sync();
+  }
+}
+
+// History of C' (both sides): a matched record's slot history shifts by one
+// exchange (h2 <- h1, h1 <- the reference's words 2..5); new records start
+// empty.  C' record index: matched k -> k + new prefix of its segment;
+// new r -> matched prefix + n_match of its segment + r.
+struct HistArgs {
+  Common cm;
+  const uint64_t* ref;
+  const MDir* mdir;
+  const uint64_t* h1;  // nullable: no history yet
+  const uint8_t* hlen;
+  uint64_t* o1;
+  uint64_t* o2;
+  uint8_t* olen;
+  int64_t ocap;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_hist_out(HistArgs a) {
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t M = cm.meta[5], Nn = cm.meta[6];
+  if (M + Nn > a.ocap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) fail(cm.status, ERR_CAPACITY);
+    return;
+  }
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t it = (int64_t)blockIdx.x * BLOCK + threadIdx.x; it < M + Nn; it += stride) {
+    if (it < M) {
+      const MDir e = a.mdir[it];
+      const int64_t s = mdir_seg(e);
+      const uint64_t g = mdir_slot(e);
+      const uint64_t* rec = a.ref + e.rword;
+      const bool has = (rec[1] >> 32) >= 6;
+      const int64_t o = it + (int64_t)cm.npre[s];
+      const int hl = a.hlen ? a.hlen[g] : 0;
+      for (int c = 0; c < 4; ++c) {
+        a.o2[4 * o + c] = a.h1 ? a.h1[4 * g + c] : 0;
+        a.o1[4 * o + c] = has ? rec[2 + c] : 0;
+      }
+      a.olen[o] = (uint8_t)(hl + 1 > 2 ? 2 : hl + 1);
+    } else {
+      const int64_t r = it - M;
+      const int64_t s = last_le<uint64_t>(cm.npre, 0, cm.nseg, (uint64_t)r);
+      const Seg& g = cm.seg[s];
+      const int64_t o = (int64_t)(g.mbase + g.n_match) + r;
+      for (int c = 0; c < 4; ++c) a.o1[4 * o + c] = a.o2[4 * o + c] = 0;
+      a.olen[o] = 0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 struct Mem {
   Common cm;
@@ -1466,6 +1728,9 @@ struct Mem {
   uint32_t* gseg;
   uint64_t* mstart;
   uint64_t* D;
+  uint64_t* D2;
+  uint8_t* gsz2;
+  uint64_t* gex2;
   uint64_t* juid;
   uint64_t* jhdr;
   uint32_t* jcnt;
@@ -1477,7 +1742,7 @@ struct Bounds {
   int64_t C, R, H, G, E, T, B, W;
 };
 
-Mem carve(Arena& ar, int64_t nseg, const Bounds& b) {
+Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   Mem m;
   m.cm.nseg = nseg;
   m.cm.seg = ar.take<Seg>(nseg + 1);
@@ -1507,6 +1772,9 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b) {
   m.gseg = ar.take<uint32_t>(b.G);
   m.mstart = ar.take<uint64_t>(b.R + 1);
   m.D = ar.take<uint64_t>(b.W);
+  m.D2 = learned ? ar.take<uint64_t>(b.W) : nullptr;
+  m.gsz2 = ar.take<uint8_t>(b.G);
+  m.gex2 = ar.take<uint64_t>(b.G + 1);
   m.juid = ar.take<uint64_t>(b.C + b.R);
   m.jhdr = ar.take<uint64_t>(b.C + b.R);
   m.jcnt = ar.take<uint32_t>(b.E);
@@ -1532,7 +1800,7 @@ Bounds dec_bounds(int64_t nseg, int64_t enc_len, int64_t ref_len) {
   Bounds b;
   b.C = enc_len / 20 + 1;  // new records
   b.R = ref_len / 20 + 1;
-  b.H = 1;
+  b.H = 4 * b.R + 2 * nseg + 1;  // neighbour-count tables (learned mode)
   b.G = ref_len / 512 + nseg + 1;
   b.E = 1;
   b.T = 1;
@@ -1547,7 +1815,7 @@ namespace ta {
 size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t* tiles) {
   Arena ar{nullptr, 0, 0};
   const Bounds b = enc_bounds(nseg, cur_len, ref_len);
-  carve(ar, nseg, b);
+  carve(ar, nseg, b, true);
   *tiles = ceil_div(std::max(std::max(std::max(b.C, b.R), b.E), b.G) + 1, SCAN_TILE) + 2;
   return ar.used + 256;
 }
@@ -1555,7 +1823,7 @@ size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t ou
   (void)out_cap;
   Arena ar{nullptr, 0, 0};
   const Bounds b = dec_bounds(nseg, enc_len, ref_len);
-  carve(ar, nseg, b);
+  carve(ar, nseg, b, true);
   *tiles = ceil_div(std::max(std::max(b.C, b.R), b.G) + 1, SCAN_TILE) + 2;
   return ar.used + 256;
 }
@@ -1585,7 +1853,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   if (st) return st;
   Arena ar{c->scratch, c->scratch_cap, 0};
   const Bounds b = enc_bounds(nseg, cur_len, ref_len);
-  Mem m = carve(ar, nseg, b);
+  Mem m = carve(ar, nseg, b, pred != nullptr);
   m.cm.status = c->d_status;
   const int g = c->grid;
   k_enc_setup<<<1, 1024, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off,
@@ -1609,25 +1877,44 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                                                                    lookback(c, 2));
   k_enc_seg2<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, newref, newref_cap, newref_off, m.gex, m.mstart);
   k_enc_mdir<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg);
+  const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
+  if (pw) {
+    Timed tm(c, "predict", s);
+    k_nbr_clear<<<g, BLOCK, 0, s>>>(m.cm, m.tab, hist_in->cap);
+    k_nbr_build<<<g, BLOCK, 0, s>>>(m.cm, ref, pw, m.tab);
+    PredictArgs pa{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, pw, m.tab, hist_in->h1, hist_in->h2,
+                   hist_in->hlen, m.pred_x, m.pred_on};
+    k_predict<<<grid_for(c, b.R, 16 * WAVES), BLOCK, 0, s>>>(pa);
+  }
   {
     Timed tm(c, "encode_resid", s);
     ResidArgs ra{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir,
-                 m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(newref), m.D};
+                 m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(newref), m.D, m.D2};
     k_enc_resid<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
   }
   {
     Timed tm(c, "encode_pack", s);
-    PackArgs pa{m.cm, m.D, enc, enc_cap, m.bm, m.gsz, m.gex, m.gseg};
+    PackArgs pa{m.cm, m.D, enc, enc_cap, m.bm, m.gsz, m.gex, m.gseg, m.D2, m.gsz2};
     const int gp = grid_for(c, b.G, WAVES * PG_WAVE);
+    const int gs = grid_for(c, b.G + 1, SCAN_TILE);
     k_enc_gsize<<<gp, BLOCK, 0, s>>>(pa);
-    k_scan<GszIn><<<grid_for(c, b.G + 1, SCAN_TILE), BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, m.gex,
-                                                                    lookback(c, 3));
+    k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, m.gex, lookback(c, 3));
+    if (pw) {
+      k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, m.gex2, lookback(c, 4));
+      k_choose_mode<<<1, 1024, 0, s>>>(m.cm, m.gex, m.gex2);
+      k_scan<GChosenIn><<<gs, BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, m.gex,
+                                             lookback(c, 5));
+    }
     k_enc_place<<<gp, BLOCK, 0, s>>>(pa);
   }
   k_enc_fin<<<1, 1024, 0, s>>>(m.cm, m.gex, enc, enc_cap, enc_off, modes);
   k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.cflag, m.cwords, m.cscan, m.bm, m.gsz, enc, enc_cap, newref);
   k_enc_newcopy<<<g, BLOCK, 0, s>>>(m.cm, m.cscan, m.cflag, cur, enc, newref);
-  (void)hist_out;
+  if (hist_out) {
+    HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
+                hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};
+    k_hist_out<<<g, BLOCK, 0, s>>>(ha);
+  }
   TA_LAUNCH_CHECK();
   return TA_OK;
 }
@@ -1652,7 +1939,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   if (st) return st;
   Arena ar{c->scratch, c->scratch_cap, 0};
   const Bounds b = dec_bounds(nseg, enc_len, ref_len);
-  Mem m = carve(ar, nseg, b);
+  Mem m = carve(ar, nseg, b, pred != nullptr);
   m.cm.status = c->d_status;
   const int g = c->grid;
   k_dec_setup<<<1, 1024, 0, s>>>(m.cm, enc, enc_len, enc_off, ref, ref_len, ref_off, pred != nullptr, out_cap,
@@ -1666,6 +1953,15 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                                                                      lookback(c, 2));
   k_dec_seg2<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, m.mstart);
   k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg);
+  const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
+  if (pw) {
+    Timed tm(c, "predict", s);
+    k_nbr_clear<<<g, BLOCK, 0, s>>>(m.cm, m.tab, hist_in->cap);
+    k_nbr_build<<<g, BLOCK, 0, s>>>(m.cm, ref, pw, m.tab);
+    PredictArgs pa{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, pw, m.tab, hist_in->h1, hist_in->h2,
+                   hist_in->hlen, m.pred_x, m.pred_on};
+    k_predict<<<grid_for(c, b.R, 16 * WAVES), BLOCK, 0, s>>>(pa);
+  }
   {
     Timed tm(c, "decode_unpack", s);
     UnpackArgs ua{m.cm, enc, m.gex, m.gseg, m.D};
@@ -1678,16 +1974,11 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
     k_dec_apply<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(aa);
   }
   k_dec_newcopy<<<g, BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
-  (void)hist_out;
+  if (hist_out) {
+    HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
+                hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};
+    k_hist_out<<<g, BLOCK, 0, s>>>(ha);
+  }
   TA_LAUNCH_CHECK();
   return TA_OK;
 }
-
-extern "C" ta_status ta_predictor_load(ta_ctx* c, const void* blob, size_t len, ta_predictor** out) {
-  (void)c;
-  (void)blob;
-  (void)len;
-  (void)out;
-  return TA_ERR_INVALID;
-}
-extern "C" void ta_predictor_free(ta_predictor* p) { (void)p; }

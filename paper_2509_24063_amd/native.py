@@ -70,11 +70,12 @@ def lib():
         L.ta_delta_bound.restype = i64
         L.ta_delta_decode.argtypes = [vp, i64, vp, i64, vp, vp, i64, vp, vp, C.POINTER(HistT), C.POINTER(HistT),
                                       vp, i64, vp, vp]
+        L.ta_predictor_eval.argtypes = [vp, vp, vp, vp, i64, vp]
         L.ta_time_kernel.argtypes = [vp, C.c_char_p]
         L.ta_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         for f in ("ta_create", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_serialize", "ta_view",
-                  "ta_view_validate", "ta_predictor_load", "ta_delta_encode", "ta_delta_decode", "ta_time_kernel",
-                  "ta_kernel_time"):
+                  "ta_view_validate", "ta_predictor_load", "ta_predictor_eval", "ta_delta_encode", "ta_delta_decode",
+                  "ta_time_kernel", "ta_kernel_time"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -133,6 +134,21 @@ class History:
 
     def struct(self):
         return HistT(_p(self.h1), _p(self.h2), _p(self.hlen), self.n)
+
+    @staticmethod
+    def from_numpy(h1, h2, hlen, device="cuda"):
+        n = int(hlen.shape[0])
+        h = History(n, device)
+        if n:
+            h.h1[:n] = torch.from_numpy(np.ascontiguousarray(h1).view(np.int64)).to(device)
+            h.h2[:n] = torch.from_numpy(np.ascontiguousarray(h2).view(np.int64)).to(device)
+            h.hlen[:n] = torch.from_numpy(np.ascontiguousarray(hlen)).to(device)
+        return h
+
+    def numpy(self, n=None):
+        n = self.n if n is None else n
+        return (self.h1[:n].cpu().numpy().view(np.uint64), self.h2[:n].cpu().numpy().view(np.uint64),
+                self.hlen[:n].cpu().numpy())
 
 
 class Predictor:
@@ -251,6 +267,14 @@ class Context:
                                      C.byref(hs) if hs is not None else None, C.byref(ho) if ho is not None else None,
                                      _p(buf), buf.numel(), _p(off), _stream()), "ta_delta_decode")
         return buf, off
+
+    def predictor_eval(self, pred: Predictor, inputs):
+        """q = predictor(inputs) for device int32 [n,12] inputs -> int32 [n,4]."""
+        inputs = inputs.contiguous()
+        n = inputs.shape[0]
+        q = torch.empty((max(n, 1), 4), dtype=torch.int32, device=inputs.device)
+        _check(lib().ta_predictor_eval(self.h, pred.h, _p(inputs), _p(q), n, _stream()), "ta_predictor_eval")
+        return q[:n]
 
     def view(self, buf, start: int, length: int):
         v = ViewT()
