@@ -250,9 +250,54 @@ ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t
  * ta_kernel_time returns (after syncing) the number of launches and their
  * summed duration in milliseconds since the last call.  name = NULL
  * disables.  Names: "select_count", "select_scatter", "serialize_pack",
- * "encode_xor", "decode_unpack". */
+ * "encode_join", "predict", "encode_resid", "encode_pack", "decode_unpack",
+ * "decode_apply". */
 ta_status ta_time_kernel(ta_ctx *ctx, const char *name);
 ta_status ta_kernel_time(ta_ctx *ctx, int64_t *launches, double *total_ms);
+
+/* ---- Training of the learned predictor (an addition to the paper's
+ * method, off the per-exchange path).  The network is the one
+ * ta_predictor_load describes; training keeps fp32 parameters
+ * theta[5252] = W1 (64x12 row-major), b1[64], W2 (64x64), b2[64], W3 (4x64),
+ * b3[4], and its forward pass runs the integer network on the rounded
+ * parameters (round half to even; weights clamped to [-128,127], biases to
+ * +-2^24).  Loss: mean over windows of sum_k |o_k / 2^r3 - t_k|, o the
+ * unrounded integer output, t the true move in quanta of 2^-12 um.
+ * Backward: straight-through over every rounding, zero gradient where a
+ * hidden pre-activation lies outside [0,127]. ---- */
+
+/* Window tap: while set, every ta_delta_encode with a predictor on this
+ * context also writes, for each slot it predicts (matched, >= 6 words,
+ * history >= 1), that slot's 12 inputs to in_out[12 i ..] (device int32) and
+ * the true move of words 2..5, (C - R) * 2^12 rounded to float32, to
+ * tgt_out[4 i ..] (device float32).  *count (device uint64, zeroed by the
+ * caller) advances by every window with finite targets; windows at i >= cap
+ * are dropped, so *count > cap reports the overflow.  Window order is
+ * unspecified.  in_out == NULL switches the tap off. */
+ta_status ta_set_window_tap(ta_ctx *ctx, int32_t *in_out, float *tgt_out, int64_t cap, uint64_t *count);
+
+typedef struct ta_trainer ta_trainer;
+/* init: host float[5252]; shifts r1..r3 <= 24 and cell > 0 are written into
+ * exported blobs.  Allocates the trainer's device state (parameters, Adam
+ * moments, per-block gradient partials) on the context's device. */
+ta_status ta_trainer_create(ta_ctx *ctx, const float *init, uint32_t r1, uint32_t r2, uint32_t r3, double cell,
+                            ta_trainer **out);
+void ta_trainer_free(ta_trainer *t);
+/* Gradient of the loss at the current parameters over n windows (in:
+ * device int32[n][12], tgt: device float32[n][4]).  grad_out (nullable,
+ * device float32[5253]) receives the gradient and, last, the loss.  The sum
+ * over windows runs in a fixed order: the result is deterministic. */
+ta_status ta_trainer_grad(ta_ctx *ctx, ta_trainer *t, const int32_t *in, const float *tgt, int64_t n,
+                          float *grad_out, void *stream);
+/* One Adam step (bias-corrected, parameters clamped to the representable
+ * ranges) on the gradient over n windows. */
+ta_status ta_trainer_step(ta_ctx *ctx, ta_trainer *t, const int32_t *in, const float *tgt, int64_t n, float lr,
+                          float beta1, float beta2, float eps, void *stream);
+/* Copy the fp32 parameters to host float[5252] (synchronises the device). */
+ta_status ta_trainer_params(ta_trainer *t, float *host_out);
+/* Write the rounded parameters as a predictor blob (host, len == 5672) that
+ * ta_predictor_load accepts (synchronises the device). */
+ta_status ta_trainer_export(ta_trainer *t, void *blob, size_t len);
 
 #ifdef __cplusplus
 }

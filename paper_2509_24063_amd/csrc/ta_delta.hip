@@ -1599,6 +1599,12 @@ struct PredictArgs {
   const uint8_t* hlen;
   uint64_t* pred_x;    // [matched][4] predicted words 2..5
   uint8_t* pred_on;    // [matched]
+  // training-window tap (encoder only; tcount null: off)
+  const uint64_t* cur;
+  int32_t* tin;        // [tcap][12]
+  float* ttgt;         // [tcap][4]
+  int64_t tcap;
+  unsigned long long* tcount;
 };
 
 // One wave per 16 matched records: inputs, integer MLP, predicted words.
@@ -1637,6 +1643,32 @@ __global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
         in[9] = (int32_t)((hdr >> 16) & 0xFFFF);
         in[10] = (int32_t)(hdr & 0xFFFF);
         in[11] = hl;
+      }
+    }
+    if (a.tcount) {
+      // a window: the inputs and the true move (C - R) in quanta of 2^-12
+      float tg[4] = {0.f, 0.f, 0.f, 0.f};
+      bool w = on;
+      if (w) {
+        const uint64_t* crec = a.cur + a.mdir[k].cword;
+        for (int c = 0; c < 4; ++c) {
+          const double d = (__longlong_as_double((long long)crec[2 + c]) -
+                            __longlong_as_double((long long)rec[2 + c])) * 4096.0;
+          tg[c] = (float)d;
+          w = w && isfinite(tg[c]);
+        }
+      }
+      const uint64_t mask = __ballot(w);
+      if (mask) {
+        const int lead = __ffsll((long long)mask) - 1;
+        unsigned long long base = 0;
+        if (l == lead) base = atomicAdd(a.tcount, (unsigned long long)__popcll(mask));
+        base = __shfl(base, lead, WAVE);
+        const int64_t at = (int64_t)base + __popcll(mask & lanemask_lt(l));
+        if (w && at < a.tcap) {
+          for (int c = 0; c < 12; ++c) a.tin[12 * at + c] = s_in[wv][l][c];
+          for (int c = 0; c < 4; ++c) a.ttgt[4 * at + c] = tg[c];
+        }
       }
     }
     wave_sync();
@@ -1883,7 +1915,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     k_nbr_clear<<<g, BLOCK, 0, s>>>(m.cm, m.tab, hist_in->cap);
     k_nbr_build<<<g, BLOCK, 0, s>>>(m.cm, ref, pw, m.tab);
     PredictArgs pa{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, pw, m.tab, hist_in->h1, hist_in->h2,
-                   hist_in->hlen, m.pred_x, m.pred_on};
+                   hist_in->hlen, m.pred_x, m.pred_on, reinterpret_cast<const uint64_t*>(cur), c->tap_in,
+                   c->tap_tgt, c->tap_cap, c->tap_count};
     k_predict<<<grid_for(c, b.R, 16 * WAVES), BLOCK, 0, s>>>(pa);
   }
   {
@@ -1958,8 +1991,14 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
     Timed tm(c, "predict", s);
     k_nbr_clear<<<g, BLOCK, 0, s>>>(m.cm, m.tab, hist_in->cap);
     k_nbr_build<<<g, BLOCK, 0, s>>>(m.cm, ref, pw, m.tab);
-    PredictArgs pa{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, pw, m.tab, hist_in->h1, hist_in->h2,
-                   hist_in->hlen, m.pred_x, m.pred_on};
+    PredictArgs pa{m.cm,       reinterpret_cast<const uint64_t*>(ref),
+                   m.mdir,     pw,
+                   m.tab,      hist_in->h1,
+                   hist_in->h2, hist_in->hlen,
+                   m.pred_x,   m.pred_on,
+                   nullptr,    nullptr,
+                   nullptr,    0,
+                   nullptr};
     k_predict<<<grid_for(c, b.R, 16 * WAVES), BLOCK, 0, s>>>(pa);
   }
   {

@@ -48,6 +48,11 @@ struct ta_ctx {
   int64_t lb_cap = 0;  // tiles per flag array
   uint8_t* scratch = nullptr;
   size_t scratch_cap = 0;
+  // training-window tap of the encoder (null: off)
+  int32_t* tap_in = nullptr;
+  float* tap_tgt = nullptr;
+  int64_t tap_cap = 0;
+  unsigned long long* tap_count = nullptr;
   // timing of one kernel family
   std::string timed;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;

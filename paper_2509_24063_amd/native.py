@@ -73,9 +73,18 @@ def lib():
         L.ta_predictor_eval.argtypes = [vp, vp, vp, vp, i64, vp]
         L.ta_time_kernel.argtypes = [vp, C.c_char_p]
         L.ta_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.ta_set_window_tap.argtypes = [vp, vp, vp, i64, vp]
+        L.ta_trainer_create.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, C.POINTER(vp)]
+        L.ta_trainer_free.argtypes = [vp]
+        L.ta_trainer_free.restype = None
+        L.ta_trainer_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        L.ta_trainer_step.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.ta_trainer_params.argtypes = [vp, vp]
+        L.ta_trainer_export.argtypes = [vp, vp, C.c_size_t]
         for f in ("ta_create", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_serialize", "ta_view",
                   "ta_view_validate", "ta_predictor_load", "ta_predictor_eval", "ta_delta_encode", "ta_delta_decode",
-                  "ta_time_kernel", "ta_kernel_time"):
+                  "ta_time_kernel", "ta_kernel_time", "ta_set_window_tap", "ta_trainer_create", "ta_trainer_grad",
+                  "ta_trainer_step", "ta_trainer_params", "ta_trainer_export"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -293,6 +302,67 @@ class Context:
         n, ms = C.c_int64(0), C.c_double(0)
         _check(lib().ta_kernel_time(self.h, C.byref(n), C.byref(ms)), "ta_kernel_time")
         return n.value, ms.value
+
+
+    # -- training of the predictor ---------------------------------------------
+    def set_window_tap(self, inputs=None, targets=None, count=None):
+        """Collect training windows from every learned encode: inputs int32
+        [cap,12], targets float32 [cap,4], count int64 [1] (zeroed by the
+        caller; reads as the number of windows offered).  No arguments: off."""
+        if inputs is None:
+            _check(lib().ta_set_window_tap(self.h, None, None, 0, None), "ta_set_window_tap")
+            self._tap = None
+            return
+        assert inputs.dtype == torch.int32 and targets.dtype == torch.float32 and count.dtype == torch.int64
+        assert inputs.is_contiguous() and targets.is_contiguous() and inputs.shape[0] == targets.shape[0]
+        self._tap = (inputs, targets, count)  # keep the buffers alive while the tap is set
+        _check(lib().ta_set_window_tap(self.h, _p(inputs), _p(targets), inputs.shape[0], _p(count)),
+               "ta_set_window_tap")
+
+
+class Trainer:
+    """Device trainer of the predictor's parameters (fp32, 5252 values)."""
+    N_PARAMS = 5252
+
+    def __init__(self, ctx: Context, init, shifts, cell: float):
+        init = np.ascontiguousarray(init, np.float32)
+        assert init.shape == (self.N_PARAMS,)
+        h = C.c_void_p()
+        r1, r2, r3 = shifts
+        _check(lib().ta_trainer_create(ctx.h, init.ctypes.data_as(C.c_void_p), r1, r2, r3, float(cell), C.byref(h)),
+               "ta_trainer_create")
+        self.h, self.ctx = h, ctx
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ta_trainer_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def grad(self, inputs, targets):
+        """(loss, gradient float32 [5252]) at the current parameters."""
+        n = inputs.shape[0]
+        out = torch.empty(self.N_PARAMS + 1, dtype=torch.float32, device=inputs.device)
+        _check(lib().ta_trainer_grad(self.ctx.h, self.h, _p(inputs.contiguous()), _p(targets.contiguous()), n,
+                                     _p(out), _stream()), "ta_trainer_grad")
+        g = out.cpu().numpy()
+        return float(g[-1]), g[:-1]
+
+    def step(self, inputs, targets, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().ta_trainer_step(self.ctx.h, self.h, _p(inputs), _p(targets), inputs.shape[0], lr, beta1, beta2,
+                                     eps, _stream()), "ta_trainer_step")
+
+    def params(self):
+        out = np.zeros(self.N_PARAMS, np.float32)
+        _check(lib().ta_trainer_params(self.h, out.ctypes.data_as(C.c_void_p)), "ta_trainer_params")
+        return out
+
+    def export(self) -> bytes:
+        b = (C.c_uint8 * 5672)()
+        _check(lib().ta_trainer_export(self.h, b, 5672), "ta_trainer_export")
+        return bytes(b)
 
 
 def empty_messages(nseg: int, device="cuda"):
