@@ -255,6 +255,86 @@ ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t
 ta_status ta_time_kernel(ta_ctx *ctx, const char *name);
 ta_status ta_kernel_time(ta_ctx *ctx, int64_t *launches, double *total_ms);
 
+/* ---- One exchange iteration as a unit: batched over every partition and
+ * segment, run eagerly, captured in a HIP graph, or tuned. ---- */
+
+/* Every argument of the four calls of one iteration: ta_select_aura over P
+ * partitions (segments nseg = P * ndirs), ta_serialize of the selection,
+ * ta_delta_encode against the sender's reference, and (rx_out non-NULL)
+ * ta_delta_decode of that encoding against the receiver's reference.  Each
+ * member has the meaning, memory space and ownership of the argument of the
+ * same name there (msgs/msgs_cap/msg_off are ta_serialize's out/out_cap/
+ * msg_off_out and ta_delta_encode's cur/cur_len/cur_off; rx_* are
+ * ta_delta_decode's ref/hist/out arguments).  The structs pointed to are
+ * read during the call only. */
+typedef struct {
+  const ta_agents *agents;
+  int32_t P;
+  int32_t ndirs;
+  const int64_t *part_off;
+  const double *boxes;
+  double w;
+  int32_t *idx;
+  int64_t idx_cap;
+  int64_t *seg_off;
+  uint8_t *msgs;
+  int64_t msgs_cap;
+  int64_t *msg_off;
+  const ta_predictor *pred;
+  const uint8_t *ref;
+  int64_t ref_len;
+  const int64_t *ref_off;
+  const ta_history *hist_in;
+  ta_history *hist_out;
+  uint8_t *enc;
+  int64_t enc_cap;
+  int64_t *enc_off;
+  uint8_t *newref;
+  int64_t newref_cap;
+  int64_t *newref_off;
+  uint8_t *modes;
+  const uint8_t *rx_ref;
+  int64_t rx_ref_len;
+  const int64_t *rx_ref_off;
+  const ta_history *rx_hist_in;
+  ta_history *rx_hist_out;
+  uint8_t *rx_out;
+  int64_t rx_out_cap;
+  int64_t *rx_out_off;
+} ta_iteration;
+
+/* Enqueue the iteration's calls in order; the first host-side error is
+ * returned (data errors go to the status word as for the single calls). */
+ta_status ta_iteration_run(ta_ctx *ctx, const ta_iteration *it, void *stream);
+
+/* Capture the iteration into a HIP graph on `stream` (not the NULL stream).
+ * The context's scratch memory is sized first, so the captured calls
+ * allocate nothing; every pointer, capacity and launch shape is fixed in the
+ * graph, while counts and sizes stay on the device, so the graph is valid
+ * for any data that fits the capacities (e.g. a store whose partitions grow
+ * and shrink within agents->n).  The graph uses the context's scratch
+ * memory: replays of graphs of one context must not overlap.  Kernel timing
+ * (ta_time_kernel) does not apply inside graphs. */
+typedef struct ta_graph ta_graph;
+ta_status ta_graph_capture(ta_ctx *ctx, const ta_iteration *it, void *stream, ta_graph **out);
+ta_status ta_graph_launch(ta_graph *g, void *stream);
+void ta_graph_free(ta_graph *g);
+
+/* Launch grids of the four kernel families (select, serialize, encode,
+ * decode), in blocks; ta_set_grids(ctx, NULL) restores the defaults. */
+ta_status ta_get_grids(ta_ctx *ctx, int32_t *grids);
+ta_status ta_set_grids(ta_ctx *ctx, const int32_t *grids);
+
+/* Choose the launch grid of each kernel family for this iteration's shape
+ * by timing it (median of `reps` runs per candidate, coordinate descent over
+ * 1..16 blocks per compute unit) and keep the fastest in the context.
+ * Runs the iteration repeatedly (its outputs are rewritten with the same
+ * values) and synchronises.  cache_path (nullable, host text file): a
+ * result for the same device and shape is read from it instead of timing,
+ * and a new result is appended; *from_cache (nullable) tells which. */
+ta_status ta_tune(ta_ctx *ctx, const ta_iteration *it, const char *cache_path, int32_t reps, void *stream,
+                  int32_t *from_cache);
+
 /* ---- Training of the learned predictor (an addition to the paper's
  * method, off the per-exchange path).  The network is the one
  * ta_predictor_load describes; training keeps fp32 parameters

@@ -20,6 +20,7 @@ int persistent_blocks(int device) {
 }
 
 ta_status ensure_scratch(ta_ctx* c, size_t bytes, int64_t tiles) {
+  if (c->capturing && (bytes > c->scratch_cap || tiles > c->lb_cap)) return TA_ERR_CAPACITY;
   if (bytes > c->scratch_cap) {
     TA_HIP(hipDeviceSynchronize());
     if (c->scratch) TA_HIP(hipFree(c->scratch));
@@ -60,6 +61,18 @@ ClearFirst clear_first(ta_ctx* c, int64_t tiles) {
   return ClearFirst{c->d_lb[0], c->d_tickets, tiles + 1 < c->lb_cap ? tiles + 1 : c->lb_cap};
 }
 
+__global__ void k_zero_i64(int64_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+ta_status zero_i64(int64_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return TA_OK;
+  k_zero_i64<<<(int)std::min<int64_t>(ceil_div(n, BLOCK), 1024), BLOCK, 0, s>>>(p, n);
+  TA_LAUNCH_CHECK();
+  return TA_OK;
+}
+
 Timed::Timed(ta_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stream) {
   on = !c->timed.empty() && c->timed == name;
   if (on) {
@@ -87,7 +100,12 @@ extern "C" ta_status ta_create(ta_ctx** out, uint32_t n_classes, const uint16_t*
     delete c;
     return TA_ERR_HIP;
   }
-  c->grid = persistent_blocks(c->device);
+  c->grid = c->grid_default = persistent_blocks(c->device);
+  for (int f = 0; f < N_FAMILIES; ++f) c->fam_grid[f] = c->grid_default;
+  {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, c->device) == hipSuccess) c->cus = p.multiProcessorCount;
+  }
   c->n_classes = n_classes;
   for (uint32_t k = 0; k < n_classes; ++k) {
     c->max_f = std::max(c->max_f, n_f64[k]);
@@ -277,6 +295,7 @@ extern "C" ta_status ta_view_validate(ta_ctx* c, const uint8_t* msgs, const int6
                                       int64_t msgs_len, void* stream) {
   if (!c || nseg < 0 || (nseg > 0 && (!msgs || !msg_off))) return TA_ERR_INVALID;
   if (nseg == 0) return TA_OK;
+  c->grid = c->grid_default;
   int64_t tiles;
   ta_status st = ensure_scratch(c, validate_scratch(nseg, msgs_len, &tiles), tiles);
   if (st) return st;

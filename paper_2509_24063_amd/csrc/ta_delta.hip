@@ -1873,10 +1873,10 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     return TA_ERR_INVALID;
   hipStream_t s = (hipStream_t)stream;
   if (nseg == 0) {
-    TA_HIP(hipMemsetAsync(enc_off, 0, 8, s));
-    TA_HIP(hipMemsetAsync(newref_off, 0, 8, s));
-    return TA_OK;
+    ta_status z = zero_i64(enc_off, 1, s);
+    return z ? z : zero_i64(newref_off, 1, s);
   }
+  use_family(c, FAM_ENCODE);
   if (cur_len / 20 + 1 >= (1ll << 28) || cur_len / 8 >= (1ll << 34) || ref_len / 20 + 1 >= (1ll << 28) ||
       ref_len / 8 >= (1ll << 34))
     return TA_ERR_INVALID;  // packed scan fields: < 2^28 records, < 2^34 words
@@ -1961,10 +1961,8 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
       (enc_len && !enc) || (ref_len && !ref) || (out_cap && !out) || (pred && !hist_in))
     return TA_ERR_INVALID;
   hipStream_t s = (hipStream_t)stream;
-  if (nseg == 0) {
-    TA_HIP(hipMemsetAsync(out_off, 0, 8, s));
-    return TA_OK;
-  }
+  if (nseg == 0) return zero_i64(out_off, 1, s);
+  use_family(c, FAM_DECODE);
   if (enc_len / 8 >= (1ll << 34) || ref_len / 20 + 1 >= (1ll << 28) || ref_len / 8 >= (1ll << 34))
     return TA_ERR_INVALID;
   int64_t tiles;

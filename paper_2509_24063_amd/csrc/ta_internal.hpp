@@ -34,10 +34,16 @@ struct Arena {
 
 }  // namespace ta
 
+// Kernel families with their own launch grid (tuned by ta_tune).
+enum { FAM_SELECT = 0, FAM_SERIALIZE = 1, FAM_ENCODE = 2, FAM_DECODE = 3, N_FAMILIES = 4 };
+
 struct ta_ctx {
   int device = 0;
   int cus = 256;
-  int grid = 2048;
+  int grid = 2048;                  // grid of the call in progress
+  int grid_default = 2048;          // persistent grid: the chip filled several times over
+  int fam_grid[N_FAMILIES] = {2048, 2048, 2048, 2048};
+  bool capturing = false;           // a graph capture is in progress: no allocation
   uint32_t n_classes = 0;
   uint16_t* d_nf = nullptr;  // device copies of the schema
   uint16_t* d_ni = nullptr;
@@ -98,6 +104,10 @@ struct Timed {
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline void use_family(ta_ctx* c, int f) { c->grid = c->fam_grid[f]; }
+
+// Zero n int64 values on the stream with a kernel (graph-capture safe).
+ta_status zero_i64(int64_t* p, int64_t n, hipStream_t s);
 inline int grid_for(ta_ctx* c, int64_t items, int per_block) {
   int64_t g = ceil_div(items > 0 ? items : 1, per_block);
   if (g > c->grid) g = c->grid;

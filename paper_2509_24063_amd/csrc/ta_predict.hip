@@ -100,6 +100,7 @@ extern "C" ta_status ta_predictor_eval(ta_ctx* c, const ta_predictor* p, const i
                                        void* stream) {
   if (!c || !p || n < 0 || (n > 0 && (!in || !q))) return TA_ERR_INVALID;
   if (n == 0) return TA_OK;
+  c->grid = c->grid_default;
   const int g = grid_for(c, ceil_div(n, 16), WAVES);
   k_pred_eval<<<g, BLOCK, 0, (hipStream_t)stream>>>(static_cast<const PredW*>(p->dev), in, q, n);
   TA_LAUNCH_CHECK();

@@ -283,6 +283,7 @@ extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, c
       (idx_cap > 0 && !idx_out) || ag->n < 0 || ag->n > INT32_MAX || (ag->n > 0 && !ag->f64) ||
       ag->f64_stride < ag->n || !(w == w))
     return TA_ERR_INVALID;
+  use_family(c, FAM_SELECT);
   int64_t tiles;
   ta_status st = ensure_scratch(c, select_scratch(ag->n, P, ndirs, &tiles), tiles);
   if (st) return st;

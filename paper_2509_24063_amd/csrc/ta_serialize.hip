@@ -231,7 +231,8 @@ extern "C" ta_status ta_serialize(ta_ctx* c, const ta_agents* ag, const int32_t*
   if (!c || !ag || nseg < 0 || !seg_off || !msg_off || idx_cap < 0 || (idx_cap > 0 && !idx) || out_cap < 0 ||
       (out_cap > 0 && !out) || ag->n < 0 || ag->f64_stride < ag->n || ag->i32_stride < ag->n)
     return TA_ERR_INVALID;
-  if (nseg == 0) return hipMemsetAsync(msg_off, 0, 8, (hipStream_t)stream) == hipSuccess ? TA_OK : TA_ERR_HIP;
+  if (nseg == 0) return zero_i64(msg_off, 1, (hipStream_t)stream);
+  use_family(c, FAM_SERIALIZE);
   int64_t tiles;
   ta_status st = ensure_scratch(c, serialize_scratch(nseg, idx_cap, &tiles), tiles);
   if (st) return st;

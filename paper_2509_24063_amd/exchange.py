@@ -1,0 +1,115 @@
+"""Exchange iterations of one GPU's partitions with fixed device buffers.
+
+A Pipeline owns everything an iteration writes -- selection, messages,
+encodings -- and two copies of each side's reference state (messages and
+predictor history), used alternately: iteration t reads copy t % 2 and
+writes copy (t + 1) % 2.  It runs each iteration eagerly
+(Context.run_iteration), or replays one of two captured HIP graphs (one per
+parity) when the agent store lives in fixed buffers (DeviceStore with cap).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import native
+
+
+class Pipeline:
+    def __init__(self, ctx: native.Context, ds: native.DeviceStore, w: float, ndirs: int, idx_cap: int,
+                 msgs_cap: int, pred: native.Predictor | None = None, decode: bool = True, device="cuda"):
+        self.ctx, self.ds, self.w, self.ndirs, self.pred = ctx, ds, w, ndirs, pred
+        self.nseg = nseg = ds.P * ndirs
+        self.idx_cap, self.msgs_cap = idx_cap, msgs_cap
+        self.enc_cap = int(native.lib().ta_delta_bound(nseg, msgs_cap, msgs_cap))
+        z8 = lambda n: torch.zeros(max(n, 8), dtype=torch.uint8, device=device)  # noqa: E731
+        zo = lambda: torch.zeros(nseg + 1, dtype=torch.int64, device=device)  # noqa: E731
+        self.idx = torch.zeros(max(idx_cap, 1), dtype=torch.int32, device=device)
+        self.seg_off = zo()
+        self.msgs, self.msg_off = z8(msgs_cap), zo()
+        self.enc, self.enc_off = z8(self.enc_cap), zo()
+        self.modes = torch.zeros(max(nseg, 1), dtype=torch.uint8, device=device)
+        self.ref = [z8(msgs_cap), z8(msgs_cap)]
+        self.ref_off = [zo(), zo()]
+        self.rx = [z8(msgs_cap), z8(msgs_cap)] if decode else None
+        self.rx_off = [zo(), zo()] if decode else None
+        self.hist = [native.History(idx_cap, device), native.History(idx_cap, device)]
+        self.rx_hist = [native.History(idx_cap, device), native.History(idx_cap, device)] if decode else None
+        self.decode = decode
+        self.reset()
+        self.graphs = [None, None]
+
+    def reset(self):
+        """Back to the first iteration: empty references, no history."""
+        empty, off = native.empty_messages(self.nseg, self.ref[0].device)
+        for bufs, offs in ((self.ref, self.ref_off), (self.rx, self.rx_off)):
+            if bufs is None:
+                continue
+            bufs[0][:empty.numel()].copy_(empty)
+            offs[0].copy_(off)
+        for hs in (self.hist, self.rx_hist):
+            if hs is not None:
+                for h in hs:
+                    h.hlen.zero_()
+        self.t = 0
+
+    def iteration(self, parity: int, ds: native.DeviceStore | None = None) -> native.Iteration:
+        p, q = parity, 1 - parity
+        ds = self.ds if ds is None else ds
+        rx = dict(rx_ref=self.rx[p], rx_ref_off=self.rx_off[p], rx_out=self.rx[q], rx_out_off=self.rx_off[q],
+                  rx_hist=self.rx_hist[p], rx_hist_out=self.rx_hist[q]) if self.decode else {}
+        pred = self.pred
+        return native.Iteration(ds, self.w, self.ndirs, self.idx, self.seg_off, self.msgs, self.msg_off,
+                                self.ref[p], self.ref_off[p], self.enc, self.enc_off, self.ref[q], self.ref_off[q],
+                                self.modes, pred=pred, hist=self.hist[p] if pred else None,
+                                hist_out=self.hist[q] if pred else None, **rx)
+
+    def capture(self, stream=None):
+        """Capture the two parities' iterations as graphs (store: self.ds)."""
+        for p in (0, 1):
+            if self.graphs[p] is None:
+                self.graphs[p] = native.Graph(self.ctx, self.iteration(p), stream)
+
+    def step(self, ds: native.DeviceStore | None = None, graph: bool = False):
+        """Run one iteration on `ds` (default: the pipeline's store)."""
+        p = self.t % 2
+        if graph:
+            if ds is not None and ds is not self.ds:
+                raise ValueError("graphs are bound to the pipeline's store")
+            self.capture()
+            self.graphs[p].launch()
+        else:
+            self.ctx.run_iteration(self.iteration(p, ds))
+        self.t += 1
+
+    # -- results of the last iteration -------------------------------------------
+    def outputs(self):
+        """(enc, enc_off, newref, newref_off, rx_out, rx_out_off) of the last iteration."""
+        q = self.t % 2
+        rx = (self.rx[q], self.rx_off[q]) if self.decode else (None, None)
+        return (self.enc, self.enc_off, self.ref[q], self.ref_off[q]) + rx
+
+    def close(self):
+        for g in self.graphs:
+            if g is not None:
+                g.close()
+        self.graphs = [None, None]
+
+
+def capacities(ctx: native.Context, store, ndirs: int, w: float, slack: float = 1.25):
+    """(idx_cap, msgs_cap) for a population like `store`, with slack for growth:
+    the selection counted once on the device, and the TAM1 bound for it."""
+    ds = native.DeviceStore(store)
+    idx, seg = ctx.select_aura(ds, w, ndirs)
+    ctx.check("capacity probe")
+    nrec = int(seg[-1].item())
+    idx_cap = int(nrec * slack) + 1024
+    msgs_cap = ctx.serialize_bound(ds, store.P * ndirs, idx_cap)
+    del ds, idx, seg
+    return idx_cap, int(msgs_cap)
+
+
+def split_host(t, off):
+    """Host bytes of dense messages/encodings: (buffer up to off[-1], offsets)."""
+    o = off.cpu().numpy()
+    return t[: int(o[-1])].cpu().numpy(), o

@@ -40,6 +40,19 @@ class HistT(C.Structure):
     _fields_ = [("h1", C.c_void_p), ("h2", C.c_void_p), ("hlen", C.c_void_p), ("cap", C.c_int64)]
 
 
+class IterationT(C.Structure):
+    _fields_ = [("agents", C.c_void_p), ("P", C.c_int32), ("ndirs", C.c_int32), ("part_off", C.c_void_p),
+                ("boxes", C.c_void_p), ("w", C.c_double), ("idx", C.c_void_p), ("idx_cap", C.c_int64),
+                ("seg_off", C.c_void_p), ("msgs", C.c_void_p), ("msgs_cap", C.c_int64), ("msg_off", C.c_void_p),
+                ("pred", C.c_void_p), ("ref", C.c_void_p), ("ref_len", C.c_int64), ("ref_off", C.c_void_p),
+                ("hist_in", C.c_void_p), ("hist_out", C.c_void_p), ("enc", C.c_void_p), ("enc_cap", C.c_int64),
+                ("enc_off", C.c_void_p), ("newref", C.c_void_p), ("newref_cap", C.c_int64),
+                ("newref_off", C.c_void_p), ("modes", C.c_void_p), ("rx_ref", C.c_void_p),
+                ("rx_ref_len", C.c_int64), ("rx_ref_off", C.c_void_p), ("rx_hist_in", C.c_void_p),
+                ("rx_hist_out", C.c_void_p), ("rx_out", C.c_void_p), ("rx_out_cap", C.c_int64),
+                ("rx_out_off", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -81,6 +94,17 @@ def lib():
         L.ta_trainer_step.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.ta_trainer_params.argtypes = [vp, vp]
         L.ta_trainer_export.argtypes = [vp, vp, C.c_size_t]
+        L.ta_iteration_run.argtypes = [vp, C.POINTER(IterationT), vp]
+        L.ta_graph_capture.argtypes = [vp, C.POINTER(IterationT), vp, C.POINTER(vp)]
+        L.ta_graph_launch.argtypes = [vp, vp]
+        L.ta_graph_free.argtypes = [vp]
+        L.ta_graph_free.restype = None
+        L.ta_get_grids.argtypes = [vp, vp]
+        L.ta_set_grids.argtypes = [vp, vp]
+        L.ta_tune.argtypes = [vp, C.POINTER(IterationT), C.c_char_p, i32, vp, C.POINTER(C.c_int32)]
+        for f in ("ta_iteration_run", "ta_graph_capture", "ta_graph_launch", "ta_get_grids", "ta_set_grids",
+                  "ta_tune"):
+            getattr(L, f).restype = st
         for f in ("ta_create", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_serialize", "ta_view",
                   "ta_view_validate", "ta_predictor_load", "ta_predictor_eval", "ta_delta_encode", "ta_delta_decode",
                   "ta_time_kernel", "ta_kernel_time", "ta_set_window_tap", "ta_trainer_create", "ta_trainer_grad",
@@ -106,27 +130,58 @@ def _check(code, what):
 
 
 class DeviceStore:
-    """An agent store (see synth.Store) copied to device tensors."""
+    """An agent store (see synth.Store) copied to device tensors.
 
-    def __init__(self, store, device="cuda"):
-        def up(a, dt):
-            return torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)
-        self.n = store.n
+    With `cap` (agents) and `beh_cap` (bytes) the buffers are allocated
+    larger than the store, and load() copies later states of a population
+    into the same memory: the library then sees n = cap agents, of which
+    the partition table's part_off[P] are live (graphs stay valid)."""
+
+    def __init__(self, store, device="cuda", cap: int | None = None, beh_cap: int | None = None):
+        self.fixed = cap is not None
+        cap = store.n if cap is None else cap
+        bytes_ = store.beh.size if beh_cap is None else beh_cap
+        if cap < store.n or bytes_ < store.beh.size:
+            raise ValueError("store larger than the buffers")
+        F, I = store.f64.shape[0], store.i32.shape[0]
+        self.n = cap
         self.P = store.P
-        self.uid = up(store.uid, np.int64)
-        self.cls = up(store.cls, np.int16)
-        self.nb = up(store.nb, np.int16)
-        self.f64 = up(store.f64, np.float64)
-        self.i32 = up(store.i32, np.int32)
-        self.beh_off = up(store.beh_off, np.int64)
-        beh = store.beh if store.beh.size else np.zeros(8, np.uint8)
-        self.beh = up(beh, np.uint8)
-        self.part_off = up(store.part_off, np.int64)
-        self.boxes = up(np.ascontiguousarray(store.boxes, np.float64).reshape(-1), np.float64)
-        bw = np.diff(store.beh_off) // 8
-        self.max_beh_words = int(bw.max()) if bw.size else 0
+        self.uid = torch.zeros(max(cap, 1), dtype=torch.int64, device=device)
+        self.cls = torch.zeros(max(cap, 1), dtype=torch.int16, device=device)
+        self.nb = torch.zeros(max(cap, 1), dtype=torch.int16, device=device)
+        self.f64 = torch.zeros((F, max(cap, 1)), dtype=torch.float64, device=device)
+        self.i32 = torch.zeros((I, max(cap, 1)), dtype=torch.int32, device=device)
+        self.beh_off = torch.zeros(cap + 1, dtype=torch.int64, device=device)
+        self.beh = torch.zeros(max(bytes_, 8), dtype=torch.uint8, device=device)
+        self.part_off = torch.zeros(store.P + 1, dtype=torch.int64, device=device)
+        self.boxes = torch.from_numpy(np.ascontiguousarray(store.boxes, np.float64).reshape(-1)).to(device)
+        self.max_beh_words = 0
+        self.load(store)
         self._s = Agents(self.n, _p(self.uid), _p(self.cls), _p(self.nb), _p(self.f64), self.f64.shape[1],
                          _p(self.i32), self.i32.shape[1], _p(self.beh_off), _p(self.beh))
+
+    def load(self, store):
+        """Copy a state of the population (same partitions, n <= cap) in."""
+        n = store.n
+        if n > self.n or store.beh.size > self.beh.numel() or store.P != self.P:
+            raise ValueError("state does not fit the buffers")
+
+        def up(dst, a, dt):
+            if a.size:
+                dst.copy_(torch.from_numpy(np.ascontiguousarray(a).view(dt)))
+        up(self.uid[:n], store.uid, np.int64)
+        up(self.cls[:n], store.cls, np.int16)
+        up(self.nb[:n], store.nb, np.int16)
+        up(self.f64[:, :n], store.f64, np.float64)
+        up(self.i32[:, :n], store.i32, np.int32)
+        up(self.beh_off[:n + 1], store.beh_off, np.int64)
+        if n < self.n:  # behaviour offsets of the dead tail: empty ranges
+            self.beh_off[n + 1:] = int(store.beh_off[-1])
+        up(self.beh[:store.beh.size], store.beh, np.uint8)
+        up(self.part_off, store.part_off, np.int64)
+        bw = np.diff(store.beh_off) // 8
+        self.max_beh_words = max(self.max_beh_words, int(bw.max()) if bw.size else 0)
+        self.live = n
 
     def agents(self):
         return self._s
@@ -304,6 +359,26 @@ class Context:
         return n.value, ms.value
 
 
+    # -- iterations, graphs, tuning ---------------------------------------------
+    def run_iteration(self, it: Iteration):
+        _check(lib().ta_iteration_run(self.h, C.byref(it.s), _stream()), "ta_iteration_run")
+
+    def grids(self):
+        g = (C.c_int32 * 4)()
+        _check(lib().ta_get_grids(self.h, g), "ta_get_grids")
+        return list(g)
+
+    def set_grids(self, grids=None):
+        g = (C.c_int32 * 4)(*grids) if grids is not None else None
+        _check(lib().ta_set_grids(self.h, g), "ta_set_grids")
+
+    def tune(self, it: Iteration, cache_path: str | None = None, reps: int = 3) -> bool:
+        """Tune the family grids on this iteration; True when taken from the cache."""
+        fc = C.c_int32(0)
+        _check(lib().ta_tune(self.h, C.byref(it.s), cache_path.encode() if cache_path else None, reps, _stream(),
+                             C.byref(fc)), "ta_tune")
+        return bool(fc.value)
+
     # -- training of the predictor ---------------------------------------------
     def set_window_tap(self, inputs=None, targets=None, count=None):
         """Collect training windows from every learned encode: inputs int32
@@ -363,6 +438,54 @@ class Trainer:
         b = (C.c_uint8 * 5672)()
         _check(lib().ta_trainer_export(self.h, b, 5672), "ta_trainer_export")
         return bytes(b)
+
+
+class Iteration:
+    """One exchange iteration's arguments (select, serialize, encode and,
+    with rx_out, decode), kept alive together with the tensors they point to."""
+
+    def __init__(self, ds: DeviceStore, w: float, ndirs: int, idx, seg_off, msgs, msg_off, ref, ref_off, enc,
+                 enc_off, newref, newref_off, modes, pred: Predictor | None = None, hist: History | None = None,
+                 hist_out: History | None = None, rx_ref=None, rx_ref_off=None, rx_hist: History | None = None,
+                 rx_hist_out: History | None = None, rx_out=None, rx_out_off=None):
+        self._keep = [ds, idx, seg_off, msgs, msg_off, ref, ref_off, enc, enc_off, newref, newref_off, modes, pred,
+                      hist, hist_out, rx_ref, rx_ref_off, rx_hist, rx_hist_out, rx_out, rx_out_off]
+        self._agents = ds.agents()
+        hs = [h.struct() if h is not None else None for h in (hist, hist_out, rx_hist, rx_hist_out)]
+        self._hs = hs
+        ptr = lambda x: C.cast(C.pointer(x), C.c_void_p) if x is not None else None  # noqa: E731
+        self.s = IterationT(
+            ptr(self._agents), ds.P, ndirs, _p(ds.part_off), _p(ds.boxes), float(w), _p(idx), idx.numel(),
+            _p(seg_off), _p(msgs), msgs.numel(), _p(msg_off), pred.h if pred is not None else None, _p(ref),
+            ref.numel(), _p(ref_off), ptr(hs[0]), ptr(hs[1]), _p(enc), enc.numel(), _p(enc_off), _p(newref),
+            newref.numel(), _p(newref_off), _p(modes), _p(rx_ref), rx_ref.numel() if rx_ref is not None else 0,
+            _p(rx_ref_off), ptr(hs[2]), ptr(hs[3]), _p(rx_out), rx_out.numel() if rx_out is not None else 0,
+            _p(rx_out_off))
+
+
+class Graph:
+    """An iteration captured as a HIP graph."""
+
+    def __init__(self, ctx: "Context", it: Iteration, stream=None):
+        self.ctx, self.it = ctx, it
+        h = C.c_void_p()
+        # capture needs a stream of its own (not the NULL stream); the graph
+        # may be launched on any stream
+        st = stream if stream is not None else torch.cuda.Stream()
+        _check(lib().ta_graph_capture(ctx.h, C.byref(it.s), C.c_void_p(st.cuda_stream), C.byref(h)),
+               "ta_graph_capture")
+        self.h = h
+
+    def launch(self):
+        _check(lib().ta_graph_launch(self.h, _stream()), "ta_graph_launch")
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ta_graph_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def empty_messages(nseg: int, device="cuda"):
