@@ -27,6 +27,8 @@
 //                 record sizes, C' offsets of new records
 //   k_newcopy     new records into the encoding and into C'
 // The decoder mirrors these steps.
+#include <initializer_list>
+
 #include "ta_internal.hpp"
 #include "ta_msg.hpp"
 #include "ta_predict.hpp"
@@ -136,8 +138,13 @@ struct Common {
   uint64_t* npre;  // [nseg+1] new record prefixes
   uint64_t* tpre;  // [nseg+1] join count tiles
   uint64_t* bpre;  // [nseg+1] join buckets
+  uint64_t* hpre;  // [nseg+1] hash slot prefixes
+  uint64_t* jepre; // [nseg+1] join count entry prefixes
+  uint64_t* fxpre; // [nseg+1] fixed encoding byte prefixes
+  uint64_t* opre;  // [nseg+1] C' message offsets
+  uint64_t* cols;  // [COL_MAX][nseg+1] per segment values to scan
   int64_t* meta;   // [0] C records [1] R records [2] hash slots [3] groups [4] presence words [5] matched
-                   // [6] new records [7] new words [8] C+R records [9] fixed bytes [10] join tiles
+                   // [6] new records [7] new words [8] unused [9] fixed bytes [10] join tiles
                    // [11] join count entries [12] join buckets [13] join bucket overflow
   uint32_t* status;
 };
@@ -176,101 +183,86 @@ __device__ inline uint64_t pow2ceil(uint64_t x) {
   return 1ull << (64 - __clzll((long long)(x - 1)));
 }
 
-__global__ __launch_bounds__(1024) void k_enc_setup(Common cm, const uint8_t* cur, int64_t cur_len,
-                                                    const int64_t* cur_off, const uint8_t* ref, int64_t ref_len,
-                                                    const int64_t* ref_off, ClearFirst cf) {
-  __shared__ uint64_t s_w[16];
-  __shared__ uint64_t s_carry[6];
-  BlockScan1024 bs{s_w};
-  do_clear_first(cf);
-  if (threadIdx.x < 6) s_carry[threadIdx.x] = 0;
-  __syncthreads();
-  for (int64_t s0 = 0; s0 < cm.nseg; s0 += 1024) {
-    const int64_t s = s0 + threadIdx.x;
-    uint64_t nc = 0, nr = 0, hs = 0, jt = 0, je = 0, jb = 0;
-    if (s < cm.nseg) {
-      Seg& g = cm.seg[s];
-      const int64_t ca = cur_off[s], cb = cur_off[s + 1], ra = ref_off[s], rb = ref_off[s + 1];
-      uint32_t n;
-      uint64_t rw;
-      bool ok = ca >= 0 && cb >= ca && cb <= cur_len && !(ca & 7) && ra >= 0 && rb >= ra && rb <= ref_len &&
-                !(ra & 7);
-      if (ok && tam1_header(cur + ca, cb - ca, &n, &rw)) {
-        nc = n;
-        g.rwc = rw;
-      } else {
-        ok = false;
-      }
-      if (ok && tam1_header(ref + ra, rb - ra, &n, &rw)) {
-        nr = n;
-        g.rwr = rw;
-      } else {
-        ok = false;
-      }
-      if (!ok) {
-        fail(cm.status, ERR_INVALID);
-        nc = nr = 0;
-      }
-      g.cmsg = ca;
-      g.rmsg = ra;
-      g.cbody = ca + 32 + 8 * ((nc + 1) / 2);
-      g.rbody = ra + 32 + 8 * ((nr + 1) / 2);
-      g.nc = nc;
-      g.nr = nr;
-      hs = pow2ceil(2 * (nc + nr));
-      g.hsize = hs;
-      g.fold = 0;
-      for (int k = 0; k < FOLD_SLOTS; ++k) g.fold_part[k] = 0;
-      g.mode = 0;
-      // join layout: B buckets, counting tiles of TJ items (C tiles, then R tiles)
-      uint64_t B = pow2ceil((nc + nr + JB_TARGET - 1) / JB_TARGET);
-      if (B < 1) B = 1;
-      if (B > JB_MAX) B = JB_MAX;
-      uint64_t TJ = (nc > nr ? nc : nr) / JT_MAX_TILES + 1;
-      if (TJ < JT) TJ = JT;
-      g.jB = B;
-      g.jTJ = TJ;
-      g.jTC = (nc + TJ - 1) / TJ;
-      g.jT = g.jTC + (nr + TJ - 1) / TJ;
-      jt = g.jT;
-      je = g.jT * B;
-      jb = B;
-    }
-    uint64_t t0, t1, t2, t3, t4, t5;
-    const uint64_t e0 = bs.excl(nc, &t0), e1 = bs.excl(nr, &t1), e2 = bs.excl(hs, &t2);
-    const uint64_t e3 = bs.excl(jt, &t3), e4 = bs.excl(je, &t4), e5 = bs.excl(jb, &t5);
-    if (s < cm.nseg) {
-      cm.cpre[s] = s_carry[0] + e0;
-      cm.rpre[s] = s_carry[1] + e1;
-      cm.seg[s].hbase = s_carry[2] + e2;
-      cm.tpre[s] = s_carry[3] + e3;
-      cm.seg[s].jebase = s_carry[4] + e4;
-      cm.bpre[s] = s_carry[5] + e5;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      s_carry[0] += t0;
-      s_carry[1] += t1;
-      s_carry[2] += t2;
-      s_carry[3] += t3;
-      s_carry[4] += t4;
-      s_carry[5] += t5;
-    }
-    __syncthreads();
+__device__ inline uint64_t* col(const Common& cm, int c) { return cm.cols + (size_t)c * (cm.nseg + 1); }
+
+// Column scan over per-segment values: column c of cm.cols into out[c].
+inline ColScan col_scan(const Common& cm, std::initializer_list<uint64_t*> outs,
+                        std::initializer_list<int> meta_idx) {
+  ColScan a{};
+  int c = 0;
+  for (uint64_t* o : outs) {
+    a.in[c] = cm.cols + (size_t)c * (cm.nseg + 1);
+    a.out[c] = o;
+    ++c;
   }
-  if (threadIdx.x == 0) {
-    cm.cpre[cm.nseg] = s_carry[0];
-    cm.rpre[cm.nseg] = s_carry[1];
-    cm.tpre[cm.nseg] = s_carry[3];
-    cm.bpre[cm.nseg] = s_carry[5];
-    cm.meta[0] = s_carry[0];
-    cm.meta[1] = s_carry[1];
-    cm.meta[2] = s_carry[2];
-    cm.meta[8] = s_carry[0] + s_carry[1];
-    cm.meta[10] = s_carry[3];
-    cm.meta[11] = s_carry[4];
-    cm.meta[12] = s_carry[5];
-    cm.meta[13] = 0;
+  c = 0;
+  for (int m : meta_idx) a.meta_idx[c++] = (int8_t)m;
+  a.meta = cm.meta;
+  a.n = cm.nseg;
+  return a;
+}
+
+// One thread per segment: message headers, record counts, hash and join
+// sizes (scanned afterwards by k_scan_cols).
+__global__ __launch_bounds__(BLOCK) void k_enc_setup(Common cm, const uint8_t* cur, int64_t cur_len,
+                                                     const int64_t* cur_off, const uint8_t* ref, int64_t ref_len,
+                                                     const int64_t* ref_off, ClearFirst cf) {
+  do_clear_first(cf);
+  if (blockIdx.x == 0 && threadIdx.x == 0) cm.meta[13] = 0;
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
+    uint64_t nc = 0, nr = 0, hs = 0, jt = 0, je = 0, jb = 0;
+    Seg& g = cm.seg[s];
+    const int64_t ca = cur_off[s], cb = cur_off[s + 1], ra = ref_off[s], rb = ref_off[s + 1];
+    uint32_t n;
+    uint64_t rw;
+    bool ok = ca >= 0 && cb >= ca && cb <= cur_len && !(ca & 7) && ra >= 0 && rb >= ra && rb <= ref_len &&
+              !(ra & 7);
+    if (ok && tam1_header(cur + ca, cb - ca, &n, &rw)) {
+      nc = n;
+      g.rwc = rw;
+    } else {
+      ok = false;
+    }
+    if (ok && tam1_header(ref + ra, rb - ra, &n, &rw)) {
+      nr = n;
+      g.rwr = rw;
+    } else {
+      ok = false;
+    }
+    if (!ok) {
+      fail(cm.status, ERR_INVALID);
+      nc = nr = 0;
+    }
+    g.cmsg = ca;
+    g.rmsg = ra;
+    g.cbody = ca + 32 + 8 * ((nc + 1) / 2);
+    g.rbody = ra + 32 + 8 * ((nr + 1) / 2);
+    g.nc = nc;
+    g.nr = nr;
+    hs = pow2ceil(2 * (nc + nr));
+    g.hsize = hs;
+    g.fold = 0;
+    for (int k = 0; k < FOLD_SLOTS; ++k) g.fold_part[k] = 0;
+    g.mode = 0;
+    // join layout: B buckets, counting tiles of TJ items (C tiles, then R tiles)
+    uint64_t B = pow2ceil((nc + nr + JB_TARGET - 1) / JB_TARGET);
+    if (B < 1) B = 1;
+    if (B > JB_MAX) B = JB_MAX;
+    uint64_t TJ = (nc > nr ? nc : nr) / JT_MAX_TILES + 1;
+    if (TJ < JT) TJ = JT;
+    g.jB = B;
+    g.jTJ = TJ;
+    g.jTC = (nc + TJ - 1) / TJ;
+    g.jT = g.jTC + (nr + TJ - 1) / TJ;
+    jt = g.jT;
+    je = g.jT * B;
+    jb = B;
+    col(cm, 0)[s] = nc;
+    col(cm, 1)[s] = nr;
+    col(cm, 2)[s] = hs;
+    col(cm, 3)[s] = jt;
+    col(cm, 4)[s] = je;
+    col(cm, 5)[s] = jb;
   }
 }
 
@@ -290,7 +282,7 @@ __global__ __launch_bounds__(BLOCK) void k_clear_tab(Common cm, Entry* tab, uint
 __global__ __launch_bounds__(BLOCK) void k_enc_insert(Common cm, const uint8_t* cur, const uint8_t* ref, Entry* tab,
                                                       uint32_t* cwords, uint32_t* rwords, uint32_t* rslot) {
   if ((status_of(cm.status) & ANY_ERR) || !cm.meta[13]) return;
-  const int64_t Ct = cm.meta[0], total = cm.meta[8];
+  const int64_t Ct = cm.meta[0], total = cm.meta[0] + cm.meta[1];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   // whole waves iterate together so the per-segment XOR fold can use the wave
   const int64_t start = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -319,7 +311,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_insert(Common cm, const uint8_t* 
       if (!okr) {
         fail(cm.status, ERR_INVALID);
       } else {
-        const uint64_t H = sg.hsize, hb = sg.hbase;
+        const uint64_t H = sg.hsize, hb = cm.hpre[s];
         uint64_t h = mix64(uid) & (H - 1);
         uint32_t slot = NONE;
         for (uint64_t probe = 0; probe < H; ++probe) {
@@ -353,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_match(Common cm, const uint8_t* c
     const int64_t s = seg_of(cm.rpre, cm.nseg, (uint64_t)g);
     const Seg& sg = cm.seg[s];
     const uint64_t j = g - cm.rpre[s];
-    const uint32_t i = tab[sg.hbase + rslot[g]].ci;
+    const uint32_t i = tab[cm.hpre[s] + rslot[g]].ci;
     int32_t res = -1;
     if (i != NONE) {
       const uint32_t oc = ld32(cur + sg.cmsg + 32 + 4 * (uint64_t)i);
@@ -450,7 +442,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a) {
         atomicXor((unsigned long long*)&g.fold_part[(t * WAVES + wave_id()) % FOLD_SLOTS], (unsigned long long)fold);
     }
     __syncthreads();
-    uint32_t* dst = a.cnt + g.jebase + jt.lt;
+    uint32_t* dst = a.cnt + cm.jepre[jt.s] + jt.lt;
     for (uint64_t b = threadIdx.x; b < B; b += BLOCK) dst[b * g.jT] = s_hist[b];
     __syncthreads();
   }
@@ -472,10 +464,10 @@ __global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a) {
     const JTile jt = join_tile(cm, t);
     const Seg& g = cm.seg[jt.s];
     const uint64_t B = g.jB;
-    const uint64_t* src = a.cnt_pre + g.jebase + jt.lt;
+    const uint64_t* src = a.cnt_pre + cm.jepre[jt.s] + jt.lt;
     // bucket starts relative to the segment's first entry (fits 32 bits:
     // a segment holds < 2^28 + 2^28 items)
-    const uint64_t seg0 = a.cnt_pre[g.jebase];
+    const uint64_t seg0 = a.cnt_pre[cm.jepre[jt.s]];
     for (uint64_t b = threadIdx.x; b < B; b += BLOCK) s_off[b] = (uint32_t)(src[b * g.jT] - seg0);
     __syncthreads();
     const uint64_t gbase = jt.isC ? cm.cpre[jt.s] : Ct + cm.rpre[jt.s];
@@ -509,7 +501,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a) {
     const int64_t s = last_le<uint64_t>(cm.bpre, 0, cm.nseg, (uint64_t)bk);
     const Seg& g = cm.seg[s];
     const uint64_t b = (uint64_t)bk - cm.bpre[s];
-    const uint64_t p0 = a.cnt_pre[g.jebase + b * g.jT], p1 = a.cnt_pre[g.jebase + (b + 1) * g.jT];
+    const uint64_t p0 = a.cnt_pre[cm.jepre[s] + b * g.jT], p1 = a.cnt_pre[cm.jepre[s] + (b + 1) * g.jT];
     const uint32_t n = (uint32_t)(p1 - p0);
     if (n > JCAP) {  // uniform: leave this bucket to the global-table join
       if (threadIdx.x == 0) atomicOr((unsigned long long*)&cm.meta[13], 1ull);
@@ -565,85 +557,69 @@ struct CNewIn {  // count << 34 | words of new current records
   __device__ uint64_t operator()(int64_t g) const { return cflag[g] ? 0 : ((1ull << PK) | cwords[g]); }
 };
 
-// Per segment layout after matching; block-wide prefixes; C' headers.
-__global__ __launch_bounds__(1024) void k_enc_seg2(Common cm, const uint64_t* rscan, const uint64_t* cscan,
-                                                   uint8_t* newref, int64_t newref_cap, int64_t* newref_off,
-                                                   uint64_t* gex, uint64_t* mstart) {
-  __shared__ uint64_t s_w[16];
-  __shared__ uint64_t s_carry[4];
-  BlockScan1024 bs{s_w};
-  const bool bad = (status_of(cm.status) & ANY_ERR) != 0;
-  if (threadIdx.x < 4) s_carry[threadIdx.x] = 0;
-  __syncthreads();
-  for (int64_t s0 = 0; s0 < cm.nseg; s0 += 1024) {
-    const int64_t s = s0 + threadIdx.x;
-    uint64_t G = 0, fixed = 0, osize = 0, PG = 0;
-    if (s < cm.nseg && !bad) {
-      Seg& g = cm.seg[s];
-      g.fold = fold_of(g.fold_part);
-      const uint64_t rs = rscan[cm.rpre[s]], re = rscan[cm.rpre[s + 1]];
-      const uint64_t cs = cscan[cm.cpre[s]], ce = cscan[cm.cpre[s + 1]];
-      g.mbase = rs >> PK;
-      g.n_match = (re >> PK) - g.mbase;
-      g.dbase = rs & WMASK;
-      g.W = (re & WMASK) - g.dbase;
-      g.nbase = cs >> PK;
-      g.n_new = (ce >> PK) - g.nbase;
-      cm.npre[s] = g.nbase;
-      g.npbase = cs & WMASK;
-      g.new_words = (ce & WMASK) - g.npbase;
-      G = (g.W + 63) / 64;
-      PG = (g.nr + 63) / 64;
-      g.G = G;
-      g.PG = PG;
-      fixed = 64 + 8 * PG + 8 * G + round8(G) + round8(4 * g.n_new) + 8 * g.new_words;
-      g.fixed = fixed;
-      osize = tam1_size(g.n_match + g.n_new, g.W + g.new_words);
-    }
-    uint64_t t0, t1, t2, t3;
-    const uint64_t e0 = bs.excl(G, &t0), e1 = bs.excl(fixed, &t1), e2 = bs.excl(osize, &t2), e3 = bs.excl(PG, &t3);
-    if (s < cm.nseg && !bad) {
-      cm.gpre[s] = s_carry[0] + e0;
-      cm.seg[s].fixed_excl = s_carry[1] + e1;
-      cm.seg[s].oref = s_carry[2] + e2;
-      {
-        Seg& g = cm.seg[s];
-        g.cpw = (g.oref + 32 + 8 * ((g.n_match + g.n_new + 1) / 2)) / 8 - g.dbase;
-      }
-      newref_off[s] = (int64_t)(s_carry[2] + e2);
-      cm.ppre[s] = s_carry[3] + e3;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      s_carry[0] += t0;
-      s_carry[1] += t1;
-      s_carry[2] += t2;
-      s_carry[3] += t3;
-    }
-    __syncthreads();
+// Per segment layout after matching (one thread per segment); the sizes
+// are scanned by k_scan_cols, then k_enc_seg3 places the C' messages.
+__global__ __launch_bounds__(BLOCK) void k_enc_seg2(Common cm, const uint64_t* rscan, const uint64_t* cscan,
+                                                    uint64_t* mstart) {
+  if (status_of(cm.status) & ANY_ERR) {
+    // sizes of zero: the scans that follow stay within their arrays
+    for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK)
+      for (int c = 0; c < 4; ++c) col(cm, c)[s] = 0;
+    return;
   }
-  if (bad) return;
-  const bool fits = s_carry[2] <= (uint64_t)newref_cap;
-  if (threadIdx.x == 0) {
-    cm.gpre[cm.nseg] = s_carry[0];
-    cm.ppre[cm.nseg] = s_carry[3];
-    newref_off[cm.nseg] = (int64_t)s_carry[2];
-    cm.meta[3] = s_carry[0];
-    cm.meta[4] = s_carry[3];
-    cm.meta[5] = rscan[cm.meta[1]] >> PK;
-    cm.meta[6] = cscan[cm.meta[0]] >> PK;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cm.meta[5] = (int64_t)(rscan[cm.meta[1]] >> PK);
+    cm.meta[6] = (int64_t)(cscan[cm.meta[0]] >> PK);
     cm.npre[cm.nseg] = (uint64_t)cm.meta[6];
-    cm.meta[7] = cscan[cm.meta[0]] & WMASK;
-    cm.meta[9] = (int64_t)s_carry[1];  // fixed total
-    gex[s_carry[0]] = 0;
+    cm.meta[7] = (int64_t)(cscan[cm.meta[0]] & WMASK);
     mstart[cm.meta[5]] = rscan[cm.meta[1]] & WMASK;  // end of the last matched record
+  }
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
+    Seg& g = cm.seg[s];
+    g.fold = fold_of(g.fold_part);
+    const uint64_t rs = rscan[cm.rpre[s]], re = rscan[cm.rpre[s + 1]];
+    const uint64_t cs = cscan[cm.cpre[s]], ce = cscan[cm.cpre[s + 1]];
+    g.mbase = rs >> PK;
+    g.n_match = (re >> PK) - g.mbase;
+    g.dbase = rs & WMASK;
+    g.W = (re & WMASK) - g.dbase;
+    g.nbase = cs >> PK;
+    g.n_new = (ce >> PK) - g.nbase;
+    cm.npre[s] = g.nbase;
+    g.npbase = cs & WMASK;
+    g.new_words = (ce & WMASK) - g.npbase;
+    const uint64_t G = (g.W + 63) / 64, PG = (g.nr + 63) / 64;
+    g.G = G;
+    g.PG = PG;
+    const uint64_t fixed = 64 + 8 * PG + 8 * G + round8(G) + round8(4 * g.n_new) + 8 * g.new_words;
+    g.fixed = fixed;
+    col(cm, 0)[s] = G;
+    col(cm, 1)[s] = fixed;
+    col(cm, 2)[s] = tam1_size(g.n_match + g.n_new, g.W + g.new_words);
+    col(cm, 3)[s] = PG;
+  }
+}
+
+// C' offsets and headers (the prefixes of k_enc_seg2's sizes are in).
+__global__ __launch_bounds__(BLOCK) void k_enc_seg3(Common cm, uint8_t* newref, int64_t newref_cap,
+                                                    int64_t* newref_off, uint64_t* gex) {
+  if (status_of(cm.status) & ANY_ERR) return;
+  const bool fits = cm.opre[cm.nseg] <= (uint64_t)newref_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    newref_off[cm.nseg] = (int64_t)cm.opre[cm.nseg];
+    gex[cm.meta[3]] = 0;
     if (!fits) fail(cm.status, ERR_CAPACITY);
   }
-  if (!fits) return;
-  for (int64_t s = threadIdx.x; s < cm.nseg; s += 1024) {
-    const Seg& g = cm.seg[s];
-    uint8_t* o = newref + g.oref;
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
+    Seg& g = cm.seg[s];
+    const uint64_t oref = cm.opre[s];
+    g.fixed_excl = cm.fxpre[s];
+    g.oref = oref;
     const uint64_t n = g.n_match + g.n_new;
+    g.cpw = (oref + 32 + 8 * ((n + 1) / 2)) / 8 - g.dbase;
+    newref_off[s] = (int64_t)oref;
+    if (!fits) continue;
+    uint8_t* o = newref + oref;
     uint64_t* h = reinterpret_cast<uint64_t*>(o);
     h[0] = (uint64_t)TAM1_MAGIC | (1ull << 32);
     h[1] = n;
@@ -888,9 +864,9 @@ struct GChosenIn {  // block bytes of the variant chosen for the group's segment
 
 // Learned mode: per segment, keep the predictor's encoding only when it is
 // strictly smaller (the fixed sections are the same for both).
-__global__ __launch_bounds__(1024) void k_choose_mode(Common cm, const uint64_t* gex, const uint64_t* gex2) {
+__global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm, const uint64_t* gex, const uint64_t* gex2) {
   if (status_of(cm.status) & ANY_ERR) return;
-  for (int64_t s = threadIdx.x; s < cm.nseg; s += 1024) {
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
     const uint64_t plain = gex[cm.gpre[s + 1]] - gex[cm.gpre[s]];
     const uint64_t learned = gex2[cm.gpre[s + 1]] - gex2[cm.gpre[s]];
     cm.seg[s].mode = learned < plain ? 1 : 0;
@@ -945,16 +921,16 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
 }
 
 // Encoding offsets and headers.
-__global__ __launch_bounds__(1024) void k_enc_fin(Common cm, const uint64_t* gex, uint8_t* enc, int64_t enc_cap,
-                                                  int64_t* enc_off, uint8_t* modes) {
+__global__ __launch_bounds__(BLOCK) void k_enc_fin(Common cm, const uint64_t* gex, uint8_t* enc, int64_t enc_cap,
+                                                   int64_t* enc_off, uint8_t* modes) {
   if (status_of(cm.status) & ANY_ERR) return;
   const uint64_t total = (uint64_t)cm.meta[9] + gex[cm.meta[3]];
   const bool fits = total <= (uint64_t)enc_cap;
-  if (threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     enc_off[cm.nseg] = (int64_t)total;
     if (!fits) fail(cm.status, ERR_CAPACITY);
   }
-  for (int64_t s = threadIdx.x; s < cm.nseg; s += 1024) {
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
     Seg& g = cm.seg[s];
     const uint64_t off = g.fixed_excl + gex[cm.gpre[s]];
     g.encm = off;
@@ -1064,20 +1040,15 @@ __global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t
 // =============================================================================
 // Decoder
 // =============================================================================
-__global__ __launch_bounds__(1024) void k_dec_setup(Common cm, const uint8_t* enc, int64_t enc_len,
-                                                    const int64_t* enc_off, const uint8_t* ref, int64_t ref_len,
-                                                    const int64_t* ref_off, bool have_pred, int64_t out_cap,
-                                                    int64_t* out_off, uint8_t* out, ClearFirst cf) {
-  __shared__ uint64_t s_w[16];
-  __shared__ uint64_t s_carry[6];
-  BlockScan1024 bs{s_w};
+// One thread per segment: header checks and section sizes (scanned
+// afterwards by k_scan_cols).
+__global__ __launch_bounds__(BLOCK) void k_dec_setup(Common cm, const uint8_t* enc, int64_t enc_len,
+                                                     const int64_t* enc_off, const uint8_t* ref, int64_t ref_len,
+                                                     const int64_t* ref_off, bool have_pred, ClearFirst cf) {
   do_clear_first(cf);
-  if (threadIdx.x < 6) s_carry[threadIdx.x] = 0;
-  __syncthreads();
-  for (int64_t s0 = 0; s0 < cm.nseg; s0 += 1024) {
-    const int64_t s = s0 + threadIdx.x;
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
     uint64_t nr = 0, G = 0, nn = 0, osz = 0, PG = 0, hs = 0;
-    if (s < cm.nseg) {
+    {
       Seg& g = cm.seg[s];
       const int64_t ea = enc_off[s], eb = enc_off[s + 1], ra = ref_off[s], rb = ref_off[s + 1];
       uint32_t code = 0;
@@ -1154,41 +1125,12 @@ __global__ __launch_bounds__(1024) void k_dec_setup(Common cm, const uint8_t* en
         nr = G = nn = osz = PG = hs = 0;
       }
     }
-    uint64_t t0, t1, t2, t3, t4, t5;
-    const uint64_t e0 = bs.excl(nr, &t0), e1 = bs.excl(G, &t1), e2 = bs.excl(nn, &t2), e3 = bs.excl(osz, &t3),
-                   e4 = bs.excl(PG, &t4), e5 = bs.excl(hs, &t5);
-    if (s < cm.nseg) cm.seg[s].hbase = s_carry[5] + e5;
-    if (s < cm.nseg) {
-      cm.rpre[s] = s_carry[0] + e0;
-      cm.gpre[s] = s_carry[1] + e1;
-      cm.npre[s] = s_carry[2] + e2;
-      cm.seg[s].oref = s_carry[3] + e3;
-      out_off[s] = (int64_t)(s_carry[3] + e3);
-      cm.ppre[s] = s_carry[4] + e4;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      s_carry[0] += t0;
-      s_carry[1] += t1;
-      s_carry[2] += t2;
-      s_carry[3] += t3;
-      s_carry[4] += t4;
-      s_carry[5] += t5;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    cm.meta[2] = s_carry[5];
-    cm.rpre[cm.nseg] = s_carry[0];
-    cm.gpre[cm.nseg] = s_carry[1];
-    cm.npre[cm.nseg] = s_carry[2];
-    cm.ppre[cm.nseg] = s_carry[4];
-    out_off[cm.nseg] = (int64_t)s_carry[3];
-    cm.meta[1] = s_carry[0];
-    cm.meta[3] = s_carry[1];
-    cm.meta[6] = s_carry[2];
-    cm.meta[4] = s_carry[4];
-    if (s_carry[3] > (uint64_t)out_cap) fail(cm.status, ERR_CAPACITY);
+    col(cm, 0)[s] = nr;
+    col(cm, 1)[s] = G;
+    col(cm, 2)[s] = nn;
+    col(cm, 3)[s] = osz;
+    col(cm, 4)[s] = PG;
+    col(cm, 5)[s] = hs;
   }
 }
 
@@ -1261,19 +1203,29 @@ struct DGroupIn {  // group block bytes
 };
 
 
-__global__ __launch_bounds__(1024) void k_dec_seg2(Common cm, const uint64_t* rscan, const uint64_t* nscan,
-                                                   const uint64_t* gex, uint8_t* out, uint64_t* mstart) {
+// Per segment: matched and new record bases, checks against the header,
+// C' offsets and headers (one thread per segment).
+__global__ __launch_bounds__(BLOCK) void k_dec_seg2(Common cm, const uint64_t* rscan, const uint64_t* nscan,
+                                                    const uint64_t* gex, uint8_t* out, int64_t out_cap,
+                                                    int64_t* out_off, uint64_t* mstart) {
   if (status_of(cm.status) & ANY_ERR) return;
-  if (threadIdx.x == 0) {
+  const bool fits = cm.opre[cm.nseg] <= (uint64_t)out_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     cm.meta[5] = (int64_t)(rscan[cm.meta[1]] >> PK);
     mstart[cm.meta[5]] = rscan[cm.meta[1]] & WMASK;  // end of the last matched record
+    cm.meta[7] = (int64_t)nscan[cm.meta[6]];
+    out_off[cm.nseg] = (int64_t)cm.opre[cm.nseg];
+    if (!fits) fail(cm.status, ERR_CAPACITY);
   }
-  for (int64_t s = threadIdx.x; s < cm.nseg; s += 1024) {
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
     Seg& g = cm.seg[s];
     const uint64_t rs = rscan[cm.rpre[s]], re = rscan[cm.rpre[s + 1]];
+    const uint64_t oref = cm.opre[s];
+    g.oref = oref;
+    out_off[s] = (int64_t)oref;
     g.mbase = rs >> PK;
     g.dbase = rs & WMASK;
-    g.cpw = (g.oref + 32 + 8 * ((g.n_match + g.n_new + 1) / 2)) / 8 - g.dbase;
+    g.cpw = (oref + 32 + 8 * ((g.n_match + g.n_new + 1) / 2)) / 8 - g.dbase;
     const uint64_t nm = (re >> PK) - g.mbase, W = (re & WMASK) - g.dbase;
     g.npbase = nscan[cm.npre[s]];
     const uint64_t nw = nscan[cm.npre[s + 1]] - g.npbase;
@@ -1281,13 +1233,9 @@ __global__ __launch_bounds__(1024) void k_dec_seg2(Common cm, const uint64_t* rs
     g.rfold = fold_of(g.fold_part);
     if (g.rfold != g.fold) fail(cm.status, ERR_REF);
     if (nm != g.n_match || W != g.W || nw != g.new_words || var != g.var) fail(cm.status, ERR_CORRUPT);
-  }
-  if (threadIdx.x == 0) cm.meta[7] = (int64_t)nscan[cm.meta[6]];
-  __syncthreads();
-  if (status_of(cm.status) & ANY_ERR) return;
-  for (int64_t s = threadIdx.x; s < cm.nseg; s += 1024) {
-    const Seg& g = cm.seg[s];
-    uint8_t* o = out + g.oref;
+    // the header of this segment's C' (inside the output: oref + its size <= total <= out_cap)
+    if (!fits) continue;
+    uint8_t* o = out + oref;
     const uint64_t n = g.n_match + g.n_new;
     uint64_t* h = reinterpret_cast<uint64_t*>(o);
     h[0] = (uint64_t)TAM1_MAGIC | (1ull << 32);
@@ -1563,9 +1511,9 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_build(Common cm, const uint8_t* r
     const uint64_t H = sg.hsize;
     uint64_t h = mix64(key) & (H - 1);
     for (uint64_t probe = 0; probe < H; ++probe) {
-      const unsigned long long prev = atomicCAS(&tab[sg.hbase + h].key, 0ull, (unsigned long long)key);
+      const unsigned long long prev = atomicCAS(&tab[cm.hpre[s] + h].key, 0ull, (unsigned long long)key);
       if (prev == 0ull || prev == (unsigned long long)key) {
-        atomicAdd(&tab[sg.hbase + h].ci, 1u);
+        atomicAdd(&tab[cm.hpre[s] + h].ci, 1u);
         break;
       }
       h = (h + 1) & (H - 1);
@@ -1580,7 +1528,7 @@ __device__ inline uint32_t nbr_count(const Common& cm, const Entry* tab, int64_t
   const uint64_t H = sg.hsize;
   uint64_t h = mix64(key) & (H - 1);
   for (uint64_t probe = 0; probe < H; ++probe) {
-    const Entry e = tab[sg.hbase + h];
+    const Entry e = tab[cm.hpre[s] + h];
     if (e.key == key) return e.ci > 127 ? 127 : e.ci;
     if (e.key == 0) return 0;
     h = (h + 1) & (H - 1);
@@ -1785,6 +1733,11 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.cm.npre = ar.take<uint64_t>(nseg + 1);
   m.cm.tpre = ar.take<uint64_t>(nseg + 1);
   m.cm.bpre = ar.take<uint64_t>(nseg + 1);
+  m.cm.hpre = ar.take<uint64_t>(nseg + 1);
+  m.cm.jepre = ar.take<uint64_t>(nseg + 1);
+  m.cm.fxpre = ar.take<uint64_t>(nseg + 1);
+  m.cm.opre = ar.take<uint64_t>(nseg + 1);
+  m.cm.cols = ar.take<uint64_t>(COL_MAX * (nseg + 1));
   m.cm.meta = ar.take<int64_t>(16);
   m.cm.status = nullptr;
   m.tab = ar.take<Entry>(b.H);
@@ -1888,8 +1841,11 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   Mem m = carve(ar, nseg, b, pred != nullptr);
   m.cm.status = c->d_status;
   const int g = c->grid;
-  k_enc_setup<<<1, 1024, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off,
-                                 clear_first(c, ceil_div(b.E + 1, SCAN_TILE)));
+  const int gseg = grid_for(c, nseg, BLOCK);
+  k_enc_setup<<<gseg, BLOCK, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off,
+                                     clear_first(c, ceil_div(b.E + 1, SCAN_TILE)));
+  k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.cpre, m.cm.rpre, m.cm.hpre, m.cm.tpre, m.cm.jepre, m.cm.bpre},
+                                          {0, 1, 2, 10, 11, 12}));
   {
     Timed tm(c, "encode_join", s);
     JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag};
@@ -1907,7 +1863,9 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                                                                      lookback(c, 1));
   k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, m.cscan,
                                                                    lookback(c, 2));
-  k_enc_seg2<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, newref, newref_cap, newref_off, m.gex, m.mstart);
+  k_enc_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart);
+  k_scan_cols<<<4, 1024, 0, s>>>(col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4}));
+  k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
   k_enc_mdir<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
@@ -1934,13 +1892,13 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, m.gex, lookback(c, 3));
     if (pw) {
       k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, m.gex2, lookback(c, 4));
-      k_choose_mode<<<1, 1024, 0, s>>>(m.cm, m.gex, m.gex2);
+      k_choose_mode<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, m.gex2);
       k_scan<GChosenIn><<<gs, BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, m.gex,
                                              lookback(c, 5));
     }
     k_enc_place<<<gp, BLOCK, 0, s>>>(pa);
   }
-  k_enc_fin<<<1, 1024, 0, s>>>(m.cm, m.gex, enc, enc_cap, enc_off, modes);
+  k_enc_fin<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, enc, enc_cap, enc_off, modes);
   k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.cflag, m.cwords, m.cscan, m.bm, m.gsz, enc, enc_cap, newref);
   k_enc_newcopy<<<g, BLOCK, 0, s>>>(m.cm, m.cscan, m.cflag, cur, enc, newref);
   if (hist_out) {
@@ -1973,8 +1931,11 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   Mem m = carve(ar, nseg, b, pred != nullptr);
   m.cm.status = c->d_status;
   const int g = c->grid;
-  k_dec_setup<<<1, 1024, 0, s>>>(m.cm, enc, enc_len, enc_off, ref, ref_len, ref_off, pred != nullptr, out_cap,
-                                 out_off, out, clear_first(c, ceil_div(b.R + 1, SCAN_TILE)));
+  const int gseg = grid_for(c, nseg, BLOCK);
+  k_dec_setup<<<gseg, BLOCK, 0, s>>>(m.cm, enc, enc_len, enc_off, ref, ref_len, ref_off, pred != nullptr,
+                                     clear_first(c, ceil_div(b.R + 1, SCAN_TILE)));
+  k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.rpre, m.cm.gpre, m.cm.npre, m.cm.opre, m.cm.ppre, m.cm.hpre},
+                                          {1, 3, 6, -1, 4, 2}));
   k_dec_rslots<<<g, BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag);
   k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1,
                                                                      m.rscan, lookback(c, 0));
@@ -1982,7 +1943,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                                                                    lookback(c, 1));
   k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, m.gex,
                                                                      lookback(c, 2));
-  k_dec_seg2<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, m.mstart);
+  k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
   k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {

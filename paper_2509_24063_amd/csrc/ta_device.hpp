@@ -277,6 +277,61 @@ __device__ inline int64_t wave_seg(const uint64_t* pre, int64_t nseg, uint64_t g
   return last_le<uint64_t>(pre, lo, hi + 1, g);
 }
 
+// Exclusive scans of up to 8 columns of n per-segment values, one block of
+// 1024 threads per column: out[c][i] = sum of in[c][0..i), out[c][n] = the
+// column total (also stored to meta[meta_idx[c]] when meta_idx[c] >= 0).
+// Chunks of COL_CHUNK values are staged in LDS with coalesced loads and
+// stores; each thread scans 8 consecutive values, one block scan joins them.
+constexpr int COL_CHUNK = 8192;
+constexpr int COL_MAX = 8;
+struct ColScan {
+  const uint64_t* in[COL_MAX];
+  uint64_t* out[COL_MAX];
+  int8_t meta_idx[COL_MAX];
+  int64_t* meta;
+  int64_t n;
+};
+
+[[maybe_unused]] static __global__ __launch_bounds__(1024) void k_scan_cols(ColScan a) {
+  __shared__ uint64_t s_v[COL_CHUNK];
+  __shared__ uint64_t s_w[16];
+  const int c = blockIdx.x;
+  const uint64_t* in = a.in[c];
+  uint64_t* out = a.out[c];
+  const int t = threadIdx.x;
+  uint64_t carry = 0;
+  for (int64_t base = 0; base < a.n; base += COL_CHUNK) {
+    const int64_t m = a.n - base < COL_CHUNK ? a.n - base : COL_CHUNK;
+    for (int i = t; i < COL_CHUNK; i += 1024) s_v[i] = i < m ? in[base + i] : 0;
+    __syncthreads();
+    uint64_t v[8], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      v[k] = sum;
+      sum += s_v[8 * t + k];
+    }
+    const uint64_t incl = wave_incl_scan(sum);
+    if (lane_id() == 63) s_w[t / 64] = incl;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+    for (int i = 0; i < 16; ++i) {
+      pre += (i < t / 64) ? s_w[i] : 0;
+      tot += s_w[i];
+    }
+    const uint64_t e = carry + pre + incl - sum;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s_v[8 * t + k] = e + v[k];
+    __syncthreads();
+    for (int i = t; i < m; i += 1024) out[base + i] = s_v[i];
+    carry += tot;
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[a.n] = carry;
+    if (a.meta && a.meta_idx[c] >= 0) a.meta[a.meta_idx[c]] = (int64_t)carry;
+  }
+}
+
 __device__ inline uint64_t ld64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
 __device__ inline uint32_t ld32(const uint8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
 

@@ -10,7 +10,8 @@
 // Kernels (all segments in one launch each):
 //   k_ser_begin  checks the segment table, clears the look-back array
 //   k_scan       exclusive scan of record sizes (words) over all records
-//   k_ser_msgoff one block: message sizes, their offsets, the headers
+//   k_ser_sizes  message sizes; k_scan_cols turns them into offsets
+//   k_ser_heads  message headers
 //   k_ser_pack   one thread per record: fields gathered from the store,
 //                record and offset-table entry written
 #include "ta_internal.hpp"
@@ -23,23 +24,21 @@ namespace {
 
 struct SerScratch {
   uint64_t* wpre;  // [idx_cap+1] exclusive prefix of record words
+  uint64_t* size;  // [nseg] message sizes
   int64_t* meta;   // [0] records, [1] total words to pack (0 on error)
 };
 
 __global__ __launch_bounds__(BLOCK) void k_ser_begin(const int64_t* seg_off, int64_t nseg, int64_t idx_cap,
                                                      SerScratch sc, ClearFirst cf, uint32_t* status) {
   do_clear_first(cf);
-  __shared__ int s_bad;
-  if (threadIdx.x == 0) s_bad = seg_off[0] != 0 || seg_off[nseg] > idx_cap;
-  __syncthreads();
-  for (int64_t s = threadIdx.x; s < nseg; s += BLOCK)
-    if (seg_off[s + 1] < seg_off[s]) s_bad = 1;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (s_bad) fail(status, ERR_INVALID);
-    sc.meta[0] = s_bad ? 0 : seg_off[nseg];
+  const bool bad_ends = seg_off[0] != 0 || seg_off[nseg] > idx_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bad_ends) fail(status, ERR_INVALID);
+    sc.meta[0] = bad_ends ? 0 : seg_off[nseg];
     sc.meta[1] = 0;
   }
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * BLOCK)
+    if (seg_off[s + 1] < seg_off[s]) fail(status, ERR_INVALID);
 }
 
 struct WordsIn {
@@ -67,45 +66,30 @@ struct WordsIn {
   }
 };
 
-__global__ __launch_bounds__(1024) void k_ser_msgoff(const int64_t* seg_off, int64_t nseg, SerScratch sc,
-                                                     uint8_t* out, int64_t out_cap, int64_t* msg_off,
+// Message sizes (one thread per segment), scanned by k_scan_cols into the
+// message offsets; then k_ser_heads writes the headers.
+__global__ __launch_bounds__(BLOCK) void k_ser_sizes(const int64_t* seg_off, int64_t nseg, SerScratch sc,
                                                      uint32_t* status) {
-  __shared__ uint64_t s_w[16];
-  __shared__ uint64_t s_carry;
   const bool bad = (status_of(status) & (1u << ERR_INVALID)) != 0;
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  for (int64_t s0 = 0; s0 < nseg; s0 += 1024) {
-    const int64_t s = s0 + threadIdx.x;
-    uint64_t size = 0;
-    if (s < nseg) {
-      const uint64_t n = bad ? 0 : (uint64_t)(seg_off[s + 1] - seg_off[s]);
-      const uint64_t rw = bad ? 0 : sc.wpre[seg_off[s + 1]] - sc.wpre[seg_off[s]];
-      size = tam1_size(n, rw);
-    }
-    const uint64_t incl = wave_incl_scan(size);
-    if (lane_id() == 63) s_w[threadIdx.x / 64] = incl;
-    __syncthreads();
-    uint64_t pre = 0, tot = 0;
-    for (int i = 0; i < 16; ++i) {
-      pre += (i < (int)(threadIdx.x / 64)) ? s_w[i] : 0;
-      tot += s_w[i];
-    }
-    if (s < nseg) msg_off[s] = (int64_t)(s_carry + pre + incl - size);
-    __syncthreads();
-    if (threadIdx.x == 0) s_carry += tot;
-    __syncthreads();
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * BLOCK) {
+    const uint64_t n = bad ? 0 : (uint64_t)(seg_off[s + 1] - seg_off[s]);
+    const uint64_t rw = bad ? 0 : sc.wpre[seg_off[s + 1]] - sc.wpre[seg_off[s]];
+    sc.size[s] = tam1_size(n, rw);
   }
-  const uint64_t total = s_carry;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_ser_heads(const int64_t* seg_off, int64_t nseg, SerScratch sc,
+                                                     uint8_t* out, int64_t out_cap, const int64_t* msg_off,
+                                                     uint32_t* status) {
+  const bool bad = (status_of(status) & (1u << ERR_INVALID)) != 0;
+  const uint64_t total = (uint64_t)msg_off[nseg];
   const bool fits = total <= (uint64_t)out_cap && !bad;
-  if (threadIdx.x == 0) {
-    msg_off[nseg] = (int64_t)total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (!bad && !fits) fail(status, ERR_CAPACITY);
     sc.meta[1] = fits ? (int64_t)sc.wpre[sc.meta[0]] : 0;
   }
   if (!fits) return;
-  __syncthreads();
-  for (int64_t s = threadIdx.x; s < nseg; s += 1024) {
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * BLOCK) {
     uint8_t* m = out + msg_off[s];
     const uint64_t n = (uint64_t)(seg_off[s + 1] - seg_off[s]);
     const uint64_t rw = sc.wpre[seg_off[s + 1]] - sc.wpre[seg_off[s]];
@@ -206,9 +190,10 @@ __global__ __launch_bounds__(BLOCK) void k_ser_pack(PackArgs a, SerScratch sc) {
   }
 }
 
-SerScratch carve(Arena& ar, int64_t idx_cap) {
+SerScratch carve(Arena& ar, int64_t nseg, int64_t idx_cap) {
   SerScratch sc;
   sc.wpre = ar.take<uint64_t>(idx_cap + 1);
+  sc.size = ar.take<uint64_t>(nseg + 1);
   sc.meta = ar.take<int64_t>(4);
   return sc;
 }
@@ -217,9 +202,8 @@ SerScratch carve(Arena& ar, int64_t idx_cap) {
 
 namespace ta {
 size_t serialize_scratch(int64_t nseg, int64_t idx_cap, int64_t* tiles) {
-  (void)nseg;
   Arena ar{nullptr, 0, 0};
-  carve(ar, idx_cap);
+  carve(ar, nseg, idx_cap);
   *tiles = ceil_div(idx_cap + 1, SCAN_TILE) + 1;
   return ar.used + 256;
 }
@@ -238,12 +222,22 @@ extern "C" ta_status ta_serialize(ta_ctx* c, const ta_agents* ag, const int32_t*
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   Arena ar{c->scratch, c->scratch_cap, 0};
-  SerScratch sc = carve(ar, idx_cap);
-  k_ser_begin<<<1, BLOCK, 0, s>>>(seg_off, nseg, idx_cap, sc, clear_first(c, ceil_div(idx_cap + 1, SCAN_TILE)),
+  SerScratch sc = carve(ar, nseg, idx_cap);
+  const int gseg = grid_for(c, nseg, BLOCK);
+  k_ser_begin<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, idx_cap, sc, clear_first(c, ceil_div(idx_cap + 1, SCAN_TILE)),
                                   c->d_status);
   WordsIn win{idx, ag->cls, ag->beh_off, c->d_nf, c->d_ni, c->n_classes, ag->n, c->d_status};
   k_scan<WordsIn><<<grid_for(c, idx_cap + 1, SCAN_TILE), BLOCK, 0, s>>>(win, sc.meta, sc.wpre, lookback(c, 0));
-  k_ser_msgoff<<<1, 1024, 0, s>>>(seg_off, nseg, sc, out, out_cap, msg_off, c->d_status);
+  k_ser_sizes<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, sc, c->d_status);
+  {
+    ColScan cs{};
+    cs.in[0] = sc.size;
+    cs.out[0] = reinterpret_cast<uint64_t*>(msg_off);
+    cs.meta_idx[0] = -1;
+    cs.n = nseg;
+    k_scan_cols<<<1, 1024, 0, s>>>(cs);
+  }
+  k_ser_heads<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, sc, out, out_cap, msg_off, c->d_status);
   {
     Timed tm(c, "serialize_pack", s);
     PackArgs pa{ag->uid, ag->cls, ag->nb, ag->f64, ag->f64_stride, ag->i32, ag->i32_stride, ag->beh_off,
