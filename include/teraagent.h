@@ -128,7 +128,11 @@ void ta_destroy(ta_ctx *ctx);
  * message buffers (cur_len, ref_len, enc_len, out_cap, ...) of at most
  * max_msg_bytes bytes.  Calls that need more grow the scratch memory
  * themselves (which allocates and synchronises); calls within the reserved
- * sizes allocate nothing and may be captured in a HIP graph. */
+ * sizes allocate nothing and may be captured in a HIP graph.
+ * max_records > 0 also caps the records per side (current, reference, new)
+ * that ta_delta_encode / ta_delta_decode size their scratch for, instead of
+ * the bound the byte sizes give (20 bytes per record); a call with more
+ * records then fails with TA_ERR_CAPACITY.  max_records = 0 removes the cap. */
 ta_status ta_reserve(ta_ctx *ctx, int64_t max_agents, int64_t max_segments, int64_t max_records,
                      int64_t max_msg_bytes);
 

@@ -186,18 +186,22 @@ __device__ inline uint64_t pow2ceil(uint64_t x) {
 __device__ inline uint64_t* col(const Common& cm, int c) { return cm.cols + (size_t)c * (cm.nseg + 1); }
 
 // Column scan over per-segment values: column c of cm.cols into out[c].
-inline ColScan col_scan(const Common& cm, std::initializer_list<uint64_t*> outs,
-                        std::initializer_list<int> meta_idx) {
+inline ColScan col_scan(const Common& cm, std::initializer_list<uint64_t*> outs, std::initializer_list<int> meta_idx,
+                        std::initializer_list<int64_t> caps) {
   ColScan a{};
   int c = 0;
   for (uint64_t* o : outs) {
     a.in[c] = cm.cols + (size_t)c * (cm.nseg + 1);
     a.out[c] = o;
+    a.cap[c] = ~0ull;
     ++c;
   }
   c = 0;
   for (int m : meta_idx) a.meta_idx[c++] = (int8_t)m;
+  c = 0;
+  for (int64_t v : caps) a.cap[c++] = v < 0 ? ~0ull : (uint64_t)v;
   a.meta = cm.meta;
+  a.status = cm.status;
   a.n = cm.nseg;
   return a;
 }
@@ -1180,8 +1184,13 @@ struct DMatchIn {
 struct DNewIn {  // words of new records, from the encodings' size tables
   Common cm;
   const uint8_t* enc;
+  int64_t lo = 0, hi = 0;  // segments of the wave's items
+  __device__ void wave_begin(int64_t first, int64_t last) {
+    lo = wave_last_le<uint64_t>(cm.npre, 0, cm.nseg, (uint64_t)first);
+    hi = wave_last_le<uint64_t>(cm.npre, lo, cm.nseg, (uint64_t)last);
+  }
   __device__ uint64_t operator()(int64_t r) const {
-    const int64_t s = seg_of(cm.npre, cm.nseg, (uint64_t)r);
+    const int64_t s = last_le<uint64_t>(cm.npre, lo, hi + 1, (uint64_t)r);
     const Seg& g = cm.seg[s];
     const uint64_t k = r - cm.npre[s];
     const uint32_t sz = ld32(enc + g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + 4 * k);
@@ -1195,8 +1204,13 @@ struct DNewIn {  // words of new records, from the encodings' size tables
 struct DGroupIn {  // group block bytes
   Common cm;
   const uint8_t* enc;
+  int64_t lo = 0, hi = 0;  // segments of the wave's items
+  __device__ void wave_begin(int64_t first, int64_t last) {
+    lo = wave_last_le<uint64_t>(cm.gpre, 0, cm.nseg, (uint64_t)first);
+    hi = wave_last_le<uint64_t>(cm.gpre, lo, cm.nseg, (uint64_t)last);
+  }
   __device__ uint64_t operator()(int64_t gg) const {
-    const int64_t s = seg_of(cm.gpre, cm.nseg, (uint64_t)gg);
+    const int64_t s = last_le<uint64_t>(cm.gpre, lo, hi + 1, (uint64_t)gg);
     const Seg& g = cm.seg[s];
     return 8 * (uint64_t)enc[g.encm + 64 + 8 * g.PG + 8 * g.G + (gg - cm.gpre[s])];
   }
@@ -1768,10 +1782,17 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   return m;
 }
 
-Bounds enc_bounds(int64_t nseg, int64_t cur_len, int64_t ref_len) {
+// Records are >= 20 bytes (two words and an offset), so the byte sizes
+// bound the record counts; a record capacity (rec_cap > 0) tightens them and
+// the column scans flag larger inputs as capacity errors.
+inline int64_t rec_bound(int64_t len, int64_t rec_cap) {
+  const int64_t b = len / 20 + 1;
+  return rec_cap > 0 && rec_cap + 1 < b ? rec_cap + 1 : b;
+}
+Bounds enc_bounds(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t rec_cap) {
   Bounds b;
-  b.C = cur_len / 20 + 1;
-  b.R = ref_len / 20 + 1;
+  b.C = rec_bound(cur_len, rec_cap);
+  b.R = rec_bound(ref_len, rec_cap);
   b.H = 4 * (b.C + b.R) + 2 * nseg + 1;
   b.G = ref_len / 512 + nseg + 1;
   // join: per segment at most 130 counting tiles and 2 n/1024 + 1 buckets
@@ -1781,10 +1802,10 @@ Bounds enc_bounds(int64_t nseg, int64_t cur_len, int64_t ref_len) {
   b.W = ref_len / 8 + 1;
   return b;
 }
-Bounds dec_bounds(int64_t nseg, int64_t enc_len, int64_t ref_len) {
+Bounds dec_bounds(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t rec_cap) {
   Bounds b;
-  b.C = enc_len / 20 + 1;  // new records
-  b.R = ref_len / 20 + 1;
+  b.C = rec_bound(enc_len, rec_cap);  // new records
+  b.R = rec_bound(ref_len, rec_cap);
   b.H = 4 * b.R + 2 * nseg + 1;  // neighbour-count tables (learned mode)
   b.G = ref_len / 512 + nseg + 1;
   b.E = 1;
@@ -1797,17 +1818,18 @@ Bounds dec_bounds(int64_t nseg, int64_t enc_len, int64_t ref_len) {
 }  // namespace
 
 namespace ta {
-size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t* tiles) {
+size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t rec_cap, int64_t* tiles) {
   Arena ar{nullptr, 0, 0};
-  const Bounds b = enc_bounds(nseg, cur_len, ref_len);
+  const Bounds b = enc_bounds(nseg, cur_len, ref_len, rec_cap);
   carve(ar, nseg, b, true);
   *tiles = ceil_div(std::max(std::max(std::max(b.C, b.R), b.E), b.G) + 1, SCAN_TILE) + 2;
   return ar.used + 256;
 }
-size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t out_cap, int64_t* tiles) {
+size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t out_cap, int64_t rec_cap,
+                      int64_t* tiles) {
   (void)out_cap;
   Arena ar{nullptr, 0, 0};
-  const Bounds b = dec_bounds(nseg, enc_len, ref_len);
+  const Bounds b = dec_bounds(nseg, enc_len, ref_len, rec_cap);
   carve(ar, nseg, b, true);
   *tiles = ceil_div(std::max(std::max(b.C, b.R), b.G) + 1, SCAN_TILE) + 2;
   return ar.used + 256;
@@ -1834,10 +1856,10 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
       ref_len / 8 >= (1ll << 34))
     return TA_ERR_INVALID;  // packed scan fields: < 2^28 records, < 2^34 words
   int64_t tiles;
-  ta_status st = ensure_scratch(c, encode_scratch(nseg, cur_len, ref_len, &tiles), tiles);
+  ta_status st = ensure_scratch(c, encode_scratch(nseg, cur_len, ref_len, c->rec_cap, &tiles), tiles);
   if (st) return st;
   Arena ar{c->scratch, c->scratch_cap, 0};
-  const Bounds b = enc_bounds(nseg, cur_len, ref_len);
+  const Bounds b = enc_bounds(nseg, cur_len, ref_len, c->rec_cap);
   Mem m = carve(ar, nseg, b, pred != nullptr);
   m.cm.status = c->d_status;
   const int g = c->grid;
@@ -1845,12 +1867,12 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   k_enc_setup<<<gseg, BLOCK, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off,
                                      clear_first(c, ceil_div(b.E + 1, SCAN_TILE)));
   k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.cpre, m.cm.rpre, m.cm.hpre, m.cm.tpre, m.cm.jepre, m.cm.bpre},
-                                          {0, 1, 2, 10, 11, 12}));
+                                          {0, 1, 2, 10, 11, 12}, {b.C, b.R, b.H, b.T, b.E, b.B}));
   {
     Timed tm(c, "encode_join", s);
     JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag};
     k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja);
-    k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, m.jcnt_pre,
+    k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
                                                                      lookback(c, 0));
     k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja);
     k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja);
@@ -1859,12 +1881,13 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     k_enc_insert<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.cwords, m.rwords, m.rslot);
     k_enc_match<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.rslot, m.m, m.cflag);
   }
-  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(RMatchIn{m.m, m.rwords}, m.cm.meta + 1, m.rscan,
+  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(RMatchIn{m.m, m.rwords}, m.cm.meta + 1, b.R, m.rscan,
                                                                      lookback(c, 1));
-  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, m.cscan,
+  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, b.C, m.cscan,
                                                                    lookback(c, 2));
   k_enc_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart);
-  k_scan_cols<<<4, 1024, 0, s>>>(col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4}));
+  k_scan_cols<<<4, 1024, 0, s>>>(col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4},
+                                          {b.G, -1, -1, -1}));
   k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
   k_enc_mdir<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
@@ -1889,11 +1912,11 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     const int gp = grid_for(c, b.G, WAVES * PG_WAVE);
     const int gs = grid_for(c, b.G + 1, SCAN_TILE);
     k_enc_gsize<<<gp, BLOCK, 0, s>>>(pa);
-    k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, m.gex, lookback(c, 3));
+    k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, b.G, m.gex, lookback(c, 3));
     if (pw) {
-      k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, m.gex2, lookback(c, 4));
+      k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, b.G, m.gex2, lookback(c, 4));
       k_choose_mode<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, m.gex2);
-      k_scan<GChosenIn><<<gs, BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, m.gex,
+      k_scan<GChosenIn><<<gs, BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, b.G, m.gex,
                                              lookback(c, 5));
     }
     k_enc_place<<<gp, BLOCK, 0, s>>>(pa);
@@ -1924,10 +1947,10 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   if (enc_len / 8 >= (1ll << 34) || ref_len / 20 + 1 >= (1ll << 28) || ref_len / 8 >= (1ll << 34))
     return TA_ERR_INVALID;
   int64_t tiles;
-  ta_status st = ensure_scratch(c, decode_scratch(nseg, enc_len, ref_len, out_cap, &tiles), tiles);
+  ta_status st = ensure_scratch(c, decode_scratch(nseg, enc_len, ref_len, out_cap, c->rec_cap, &tiles), tiles);
   if (st) return st;
   Arena ar{c->scratch, c->scratch_cap, 0};
-  const Bounds b = dec_bounds(nseg, enc_len, ref_len);
+  const Bounds b = dec_bounds(nseg, enc_len, ref_len, c->rec_cap);
   Mem m = carve(ar, nseg, b, pred != nullptr);
   m.cm.status = c->d_status;
   const int g = c->grid;
@@ -1935,13 +1958,13 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_dec_setup<<<gseg, BLOCK, 0, s>>>(m.cm, enc, enc_len, enc_off, ref, ref_len, ref_off, pred != nullptr,
                                      clear_first(c, ceil_div(b.R + 1, SCAN_TILE)));
   k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.rpre, m.cm.gpre, m.cm.npre, m.cm.opre, m.cm.ppre, m.cm.hpre},
-                                          {1, 3, 6, -1, 4, 2}));
+                                          {1, 3, 6, -1, 4, 2}, {b.R, b.G, b.C, -1, -1, b.H}));
   k_dec_rslots<<<g, BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag);
-  k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1,
+  k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
                                                                      m.rscan, lookback(c, 0));
-  k_scan<DNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, m.cscan,
+  k_scan<DNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, b.C, m.cscan,
                                                                    lookback(c, 1));
-  k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, m.gex,
+  k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, b.G, m.gex,
                                                                      lookback(c, 2));
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
   k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ta {
 
 constexpr int WAVE = 64;
@@ -159,13 +161,26 @@ __device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t
 constexpr int SCAN_ROUNDS = 16;
 constexpr int SCAN_TILE = BLOCK * SCAN_ROUNDS;
 
+// A functor may define wave_begin(first, last): called by all 64 lanes of a
+// wave before it reads items first..last (consecutive), e.g. to bound a
+// segment search once per wave instead of once per item.
+template <class T, class = void>
+struct has_wave_begin : std::false_type {};
+template <class T>
+struct has_wave_begin<T, std::void_t<decltype(&T::wave_begin)>> : std::true_type {};
+
 template <class In>
-__global__ __launch_bounds__(BLOCK) void k_scan(In in, const int64_t* n_dev, uint64_t* out, LookBack lb) {
+__global__ __launch_bounds__(BLOCK) void k_scan(In in, const int64_t* n_dev, int64_t n_cap, uint64_t* out,
+                                                LookBack lb) {
   __shared__ uint64_t s_wave[WAVES];
   __shared__ uint32_t s_ticket;
   __shared__ uint64_t s_prefix;
   lb_clear_next(lb);
-  const int64_t n = *n_dev;
+  int64_t n = *n_dev;
+  if (n > n_cap) {  // more items than the arrays hold: nothing is scanned
+    if (blockIdx.x == 0 && threadIdx.x == 0) fail(lb.status, ERR_CAPACITY);
+    n = 0;
+  }
   if (n <= 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
     return;
@@ -179,12 +194,17 @@ __global__ __launch_bounds__(BLOCK) void k_scan(In in, const int64_t* n_dev, uin
     const uint32_t t = lb_take_ticket(lb, &s_ticket);
     if ((int64_t)t >= ntiles) break;
     const int64_t wbase = (int64_t)t * SCAN_TILE + (int64_t)wv * (WAVE * SCAN_ROUNDS);
+    In fn = in;
+    if constexpr (has_wave_begin<In>::value) {
+      const int64_t last = wbase + WAVE * SCAN_ROUNDS - 1 < n ? wbase + WAVE * SCAN_ROUNDS - 1 : n - 1;
+      fn.wave_begin(wbase < n ? wbase : n - 1, last);
+    }
     uint64_t ex[SCAN_ROUNDS];
     uint64_t carry = 0;
 #pragma unroll
     for (int r = 0; r < SCAN_ROUNDS; ++r) {
       const int64_t i = wbase + r * WAVE + l;
-      const uint64_t v = i < n ? in(i) : 0;
+      const uint64_t v = i < n ? fn(i) : 0;
       const uint64_t incl = wave_incl_scan(v);
       ex[r] = carry + incl - v;
       carry += __shfl(incl, WAVE - 1, WAVE);
@@ -287,8 +307,10 @@ constexpr int COL_MAX = 8;
 struct ColScan {
   const uint64_t* in[COL_MAX];
   uint64_t* out[COL_MAX];
+  uint64_t cap[COL_MAX];  // a total above cap[c] is a capacity error
   int8_t meta_idx[COL_MAX];
   int64_t* meta;
+  uint32_t* status;
   int64_t n;
 };
 
@@ -329,6 +351,7 @@ struct ColScan {
   if (t == 0) {
     out[a.n] = carry;
     if (a.meta && a.meta_idx[c] >= 0) a.meta[a.meta_idx[c]] = (int64_t)carry;
+    if (carry > a.cap[c] && a.status) fail(a.status, ERR_CAPACITY);
   }
 }
 

@@ -58,10 +58,10 @@ ta_status presize(ta_ctx* c, const ta_iteration* it) {
   tiles = std::max(tiles, t);
   need = std::max(need, serialize_scratch(nseg, it->idx_cap, &t));
   tiles = std::max(tiles, t);
-  need = std::max(need, encode_scratch(nseg, it->msgs_cap, it->ref_len, &t));
+  need = std::max(need, encode_scratch(nseg, it->msgs_cap, it->ref_len, c->rec_cap, &t));
   tiles = std::max(tiles, t);
   if (it->rx_out) {
-    need = std::max(need, decode_scratch(nseg, it->enc_cap, it->rx_ref_len, it->rx_out_cap, &t));
+    need = std::max(need, decode_scratch(nseg, it->enc_cap, it->rx_ref_len, it->rx_out_cap, c->rec_cap, &t));
     tiles = std::max(tiles, t);
   }
   return ensure_scratch(c, need, tiles);
@@ -173,6 +173,12 @@ extern "C" ta_status ta_graph_capture(ta_ctx* c, const ta_iteration* it, void* s
   }
   hipGraphExec_t x = nullptr;
   if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return TA_ERR_HIP;
+  }
+  // upload now, so that the first launch costs what every launch costs
+  if (hipGraphUpload(x, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGraphExecDestroy(x);
     (void)hipGraphDestroy(g);
     return TA_ERR_HIP;
   }

@@ -44,6 +44,7 @@ struct ta_ctx {
   int grid_default = 2048;          // persistent grid: the chip filled several times over
   int fam_grid[N_FAMILIES] = {2048, 2048, 2048, 2048};
   bool capturing = false;           // a graph capture is in progress: no allocation
+  int64_t rec_cap = 0;              // records per message side the delta scratch holds (0: from the sizes)
   uint32_t n_classes = 0;
   uint16_t* d_nf = nullptr;  // device copies of the schema
   uint16_t* d_ni = nullptr;

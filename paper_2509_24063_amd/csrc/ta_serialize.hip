@@ -227,13 +227,15 @@ extern "C" ta_status ta_serialize(ta_ctx* c, const ta_agents* ag, const int32_t*
   k_ser_begin<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, idx_cap, sc, clear_first(c, ceil_div(idx_cap + 1, SCAN_TILE)),
                                   c->d_status);
   WordsIn win{idx, ag->cls, ag->beh_off, c->d_nf, c->d_ni, c->n_classes, ag->n, c->d_status};
-  k_scan<WordsIn><<<grid_for(c, idx_cap + 1, SCAN_TILE), BLOCK, 0, s>>>(win, sc.meta, sc.wpre, lookback(c, 0));
+  k_scan<WordsIn><<<grid_for(c, idx_cap + 1, SCAN_TILE), BLOCK, 0, s>>>(win, sc.meta, idx_cap, sc.wpre, lookback(c, 0));
   k_ser_sizes<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, sc, c->d_status);
   {
     ColScan cs{};
     cs.in[0] = sc.size;
     cs.out[0] = reinterpret_cast<uint64_t*>(msg_off);
+    cs.cap[0] = ~0ull;  // the output capacity is checked by k_ser_heads
     cs.meta_idx[0] = -1;
+    cs.status = c->d_status;
     cs.n = nseg;
     k_scan_cols<<<1, 1024, 0, s>>>(cs);
   }

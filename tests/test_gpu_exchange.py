@@ -184,6 +184,43 @@ def test_selection_and_serialize_capacity(native):
     ctx.close()
 
 
+def test_record_capacity(native):
+    """A record capacity set by reserve bounds the delta scratch: inputs with
+    more records per side fail with a capacity error (and write nothing out of
+    bounds); within it, or with the cap removed, results match the oracle."""
+    cfg = synth.config(3, median=300.0, grid=(2, 2, 2))
+    w = synth.World(cfg)
+    ctx = native.Context(cfg.schema)
+    nseg = w.store.P * cfg.ndirs
+    ds = native.DeviceStore(w.store)
+    idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs)
+    buf, moff = ctx.serialize(ds, idx, seg)
+    ctx.check("serialize")
+    nrec = int(host(seg)[-1])
+    ref, roff = native.empty_messages(nseg)
+    obuf, omoff = oracle.serialize(w.store, cfg.schema, *oracle.select_aura(w.store, cfg.w, cfg.ndirs))
+    oenc, oeoff, onref, onoff, _, _ = oracle.encode_all(obuf, omoff, *oracle.empty_messages(nseg))
+    for cap, want in ((nrec // 2, native.CAPACITY), (nrec, native.OK), (0, native.OK)):
+        print(f"[record cap] {cap} for {nrec} records", flush=True)
+        ctx.reserve(ds.n, nseg, cap, buf.numel())
+        enc, eoff, nref, noff, _ = ctx.delta_encode(buf, moff, ref, roff)
+        assert ctx.poll() == want
+        if want == native.OK:
+            assert np.array_equal(host(enc, host(eoff)), oenc)
+            dec, doff = ctx.delta_decode(enc, eoff, ref, roff)
+            ctx.check("decode")
+            assert np.array_equal(host(dec, host(doff)), onref)
+        else:
+            # the decoder is bounded the same way
+            ctx.reserve(ds.n, nseg, 0, buf.numel())
+            enc, eoff, _, _, _ = ctx.delta_encode(buf, moff, ref, roff)
+            ctx.check("encode without a cap")
+            ctx.reserve(ds.n, nseg, nrec // 2, buf.numel())
+            ctx.delta_decode(enc, eoff, ref, roff)
+            assert ctx.poll() == native.CAPACITY
+    ctx.close()
+
+
 def test_runs_are_deterministic(native):
     cfg = synth.config(5, median=300.0, grid=(2, 2, 2))
     outs = []
