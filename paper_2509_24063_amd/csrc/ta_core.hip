@@ -157,9 +157,9 @@ extern "C" ta_status ta_reserve(ta_ctx* c, int64_t max_agents, int64_t max_segme
   need = std::max(need, serialize_scratch(max_segments, max_records, &t));
   tiles = std::max(tiles, t);
   c->rec_cap = max_records;
-  need = std::max(need, encode_scratch(max_segments, max_msg_bytes, max_msg_bytes, c->rec_cap, &t));
+  need = std::max(need, encode_scratch(max_segments, max_msg_bytes, max_msg_bytes, c->rec_cap, false, &t));
   tiles = std::max(tiles, t);
-  need = std::max(need, decode_scratch(max_segments, max_msg_bytes, max_msg_bytes, max_msg_bytes, c->rec_cap, &t));
+  need = std::max(need, decode_scratch(max_segments, max_msg_bytes, max_msg_bytes, max_msg_bytes, c->rec_cap, false, &t));
   tiles = std::max(tiles, t);
   need = std::max(need, validate_scratch(max_segments, max_msg_bytes, &t));
   tiles = std::max(tiles, t);

@@ -670,8 +670,11 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
   }
 }
 
-// Assemble the block of one group in LDS.  Returns the block size in bytes.
-__device__ inline uint32_t build_block(uint64_t D, uint8_t* blk, uint64_t* bitmap_out) {
+// Assemble the block of one group in LDS (b64: BLK_MAX/8 + 1 words).
+// Every lane ORs its nibble and its significant bytes into the 64-bit words
+// they fall in (one or two words: no byte stores).  Returns the block size in
+// bytes.
+__device__ inline uint32_t build_block(uint64_t D, uint64_t* b64, uint64_t* bitmap_out) {
   const int l = lane_id();
   const uint64_t bm = __ballot(D != 0);
   const uint32_t len = D ? (uint32_t)(8 - (__clzll((long long)D) >> 3)) : 0u;
@@ -680,27 +683,58 @@ __device__ inline uint32_t build_block(uint64_t D, uint8_t* blk, uint64_t* bitma
   const uint64_t sig_incl = wave_incl_scan(len);
   const uint64_t sig_tot = uniform64(__shfl(sig_incl, 63, WAVE));
   const uint32_t size = (uint32_t)round8(nib + sig_tot);
-  // zero the block
-  uint64_t* b64 = reinterpret_cast<uint64_t*>(blk);
   for (uint32_t k = l; k < size / 8; k += WAVE) b64[k] = 0;
-  __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  const uint32_t t = (uint32_t)__popcll(bm & lanemask_lt(l));
-  const uint64_t after = bm & ~lanemask_le(l);
-  const int nl = after ? (__ffsll((unsigned long long)after) - 1) : l;
-  const uint32_t len_next = (uint32_t)__shfl((int)len, nl, WAVE);
-  if (D && !(t & 1)) blk[t / 2] = (uint8_t)(len | ((after ? len_next : 0u) << 4));
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   if (D) {
+    // nibble t (t-th non-zero word): byte t/2, low nibble first = bits 4t of the block
+    const uint32_t t = (uint32_t)__popcll(bm & lanemask_lt(l));
+    atomicOr((unsigned long long*)&b64[t / 16], (unsigned long long)len << (4 * (t % 16)));
     const uint32_t so = nib + (uint32_t)(sig_incl - len);
-    for (uint32_t b = 0; b < len; ++b) blk[so + b] = (uint8_t)(D >> (8 * b));
+    const uint32_t sh = 8 * (so % 8);
+    atomicOr((unsigned long long*)&b64[so / 8], (unsigned long long)(D << sh));
+    if (sh && sh + 8 * len > 64) atomicOr((unsigned long long*)&b64[so / 8 + 1], (unsigned long long)(D >> (64 - sh)));
   }
-  __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   *bitmap_out = bm;
   return size;
 }
 
-constexpr int RES_CAP = 1024;  // residual words one wave stages in LDS
+// The 64 consecutive matched records a wave works on, as a table in LDS:
+// residual start (d[n] = end of the last record), source words in C and R,
+// and the record's first word in C'.  The wave then walks the residual
+// words lane-parallel: each lane finds its record with a binary search in
+// the table, and consecutive lanes read and write consecutive words.
+struct RecTab {
+  uint64_t d[WAVE + 1];
+  uint64_t c[WAVE];
+  uint64_t r[WAVE];
+  uint64_t o[WAVE];
+  uint8_t p[WAVE];  // learned: the record's words 2..5 are predicted
+};
+// Largest i < n with a[i] <= x (a non-decreasing, a[0] <= x): a search in LDS.
+__device__ inline int lds_last_le(const uint64_t* a, int n, uint64_t x) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int m = (lo + hi) >> 1;
+    if (a[m] <= x) lo = m;
+    else hi = m;
+  }
+  return lo;
+}
+__device__ inline int rec_of(const RecTab& t, int n, uint64_t d) { return lds_last_le(t.d, n, d); }
+
+// New records a wave copies (up to 64): word prefix within the wave (q[n]
+// = total), first source word, first destination words (uint64 indices).
+struct NewTab {
+  uint64_t q[WAVE + 1];
+  uint64_t src[WAVE];
+  uint64_t dst1[WAVE];
+  uint64_t dst2[WAVE];
+};
 
 struct ResidArgs {
   Common cm;
@@ -715,78 +749,44 @@ struct ResidArgs {
   uint64_t* D2;            // learned mode: residual against the predictions (nullptr: plain)
 };
 
-// One lane per matched record (64 consecutive matched records per wave): the
-// record's C words go to C' and C xor X to the dense residual.  Both outputs of
-// the wave are contiguous, so they are staged in LDS and written with
-// coalesced stores.
+// Matched records in C' order: their C words go to C' and C xor X to the
+// dense residual (D against R; D2 against the predictions in learned mode).
 __global__ __launch_bounds__(BLOCK) void k_enc_resid(ResidArgs a) {
-  __shared__ uint64_t s_buf[WAVES][RES_CAP];
+  __shared__ RecTab s_t[WAVES];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t M = cm.meta[5];
   const int l = lane_id(), wv = wave_id();
-  uint64_t* buf = s_buf[wv];
+  RecTab& t = s_t[wv];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   for (int64_t kb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; kb < M; kb += stride) {
     const int64_t k = kb + l;
-    const bool act = k < M;
     const int64_t ke = kb + WAVE < M ? kb + WAVE : M;
-    const uint64_t d0 = a.mstart[kb], d1 = a.mstart[ke];
-    MDir e{};
-    uint64_t words = 0, cpw = 0;
-    int64_t sg = -1;
-    bool learned = false;
-    if (act) {
-      e = a.mdir[k];
-      words = a.mstart[k + 1] - e.dstart;
-      sg = mdir_seg(e);
-      const Seg& g = cm.seg[sg];
-      cpw = g.cpw;
-      learned = g.mode == 1 && a.pred_on[k];
+    const int n = (int)(ke - kb);
+    if (k < M) {
+      const MDir e = a.mdir[k];
+      t.d[l] = e.dstart;
+      t.c[l] = e.cword;
+      t.r[l] = e.rword;
+      t.o[l] = cm.seg[mdir_seg(e)].cpw + e.dstart;
+      t.p[l] = a.D2 ? a.pred_on[k] : 0;
     }
-    const int64_t s_first = __shfl(sg, 0, WAVE), s_last = __shfl(sg, (int)(ke - kb - 1), WAVE);
-    const uint64_t cpw0 = __shfl(cpw, 0, WAVE);
-    const bool staged = d1 - d0 <= RES_CAP;
-    const bool one_seg = s_first == s_last;
-    if (act && a.D2) learned = a.pred_on[k];  // both variants are formed; the mode is chosen later
-    for (uint64_t w = 0; w < words; ++w) {
-      const uint64_t c = a.cur[e.cword + w];
-      if (staged) buf[e.dstart - d0 + w] = c;
-      else a.newref[cpw + e.dstart + w] = c;
-    }
+    if (l == 0) t.d[n] = a.mstart[ke];
     wave_sync();
-    if (staged) {
-      if (one_seg) {
-        for (uint64_t p = l; p < d1 - d0; p += WAVE) a.newref[cpw0 + d0 + p] = buf[p];
-      } else {
-        for (uint64_t w = 0; w < words; ++w) a.newref[cpw + e.dstart + w] = buf[e.dstart - d0 + w];
+    const uint64_t d1 = t.d[n];
+    for (uint64_t d = t.d[0] + l; d < d1; d += WAVE) {
+      const int i = rec_of(t, n, d);
+      const uint64_t off = d - t.d[i];
+      const uint64_t c = a.cur[t.c[i] + off];
+      const uint64_t x = a.ref[t.r[i] + off];
+      a.newref[t.o[i] + off] = c;
+      a.D[d] = c ^ x;
+      if (a.D2) {
+        const uint64_t xl = (t.p[i] && off >= 2 && off < 6) ? a.pred_x[4 * (kb + i) + (off - 2)] : x;
+        a.D2[d] = c ^ xl;
       }
     }
     wave_sync();
-    for (uint64_t w = 0; w < words; ++w) {
-      const uint64_t c = staged ? buf[e.dstart - d0 + w] : a.cur[e.cword + w];
-      const uint64_t x = a.ref[e.rword + w];
-      if (staged) buf[e.dstart - d0 + w] = c ^ x;
-      else a.D[e.dstart + w] = c ^ x;
-      if (!staged && a.D2) {
-        const uint64_t xl = (learned && w >= 2 && w < 6) ? a.pred_x[4 * k + (w - 2)] : x;
-        a.D2[e.dstart + w] = c ^ xl;
-      }
-    }
-    wave_sync();
-    if (staged)
-      for (uint64_t p = l; p < d1 - d0; p += WAVE) a.D[d0 + p] = buf[p];
-    wave_sync();
-    if (staged && a.D2) {
-      // learned variant: D2 = D xor R xor P on the predicted words
-      if (learned) {
-        for (uint64_t w = 2; w < 6 && w < words; ++w)
-          buf[e.dstart - d0 + w] ^= a.ref[e.rword + w] ^ a.pred_x[4 * k + (w - 2)];
-      }
-      wave_sync();
-      for (uint64_t p = l; p < d1 - d0; p += WAVE) a.D2[d0 + p] = buf[p];
-      wave_sync();
-    }
   }
 }
 
@@ -803,7 +803,10 @@ struct PackArgs {
   uint8_t* gsz2;         // learned variant block sizes / 8
 };
 
-constexpr int PG_WAVE = 4;  // groups one wave handles at a time (loads issued together)
+#ifndef TA_PG_WAVE
+#define TA_PG_WAVE 4
+#endif
+constexpr int PG_WAVE = TA_PG_WAVE;  // groups one wave handles at a time (loads issued together)
 
 // Pass 1 of the zero-block packer: per 64-word group, its bitmap word and
 // its block size (nibbles + significant bytes, rounded to 8).
@@ -879,7 +882,7 @@ __global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm, const uint64_t
 
 // Pass 3: every group rebuilds its block in LDS and writes it at its offset.
 __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
-  __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8];
+  __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8 + 1];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Gt = cm.meta[3];
@@ -906,7 +909,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
       const int64_t gg = g0 + x;
       if (gg >= Gt) break;
       uint64_t bm;
-      const uint32_t size = build_block(Dv[x], reinterpret_cast<uint8_t*>(s_blk[wv]), &bm);
+      const uint32_t size = build_block(Dv[x], s_blk[wv], &bm);
       if (a.D2 && l == 0) {  // the tables of the chosen variant
         a.bm[gg] = bm;
         a.gsz[gg] = (uint8_t)(size / 8);
@@ -1011,33 +1014,53 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
   }
 }
 
-// New records, word by word: from C into the encoding and C'.  A wave finds
-// the range of records its 64 words touch with two wave searches.
+// New records into the encoding and into C': a wave takes 64 consecutive C
+// records, tabulates the new ones in LDS and copies their words
+// lane-parallel (consecutive lanes, consecutive words).
 __global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t* cscan, const uint8_t* cflag,
-                                                       const uint8_t* cur, uint8_t* enc, uint8_t* newref) {
+                                                       const uint32_t* cwords, const uint8_t* cur, uint8_t* enc,
+                                                       uint8_t* newref) {
+  __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
-  const uint64_t NW = (uint64_t)cm.meta[7];
   const int64_t Cn = cm.meta[0];
-  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
-  for (uint64_t qb = (uint64_t)blockIdx.x * BLOCK + wave_id() * WAVE; qb < NW; qb += stride) {
-    const uint64_t q = qb + lane_id();
-    const uint64_t qe = qb + WAVE - 1 < NW ? qb + WAVE - 1 : NW - 1;
-    const int64_t rlo = wave_last_le_masked(cscan, 0, Cn, qb, WMASK);
-    const int64_t rhi = wave_last_le_masked(cscan, rlo, Cn, qe, WMASK);
-    // last C record whose new-word prefix is <= q: the new record holding q
-    const int64_t gc = last_le_masked(cscan, rlo, rhi + 1, q < NW ? q : NW - 1, WMASK);
-    const int64_t s = wave_seg(cm.cpre, cm.nseg, (uint64_t)gc, (uint64_t)rlo, (uint64_t)rhi);
-    if (q >= NW) continue;
-    const Seg& g = cm.seg[s];
-    const uint64_t i = gc - cm.cpre[s];
-    const uint64_t w = q - (cscan[gc] & WMASK);
-    const uint64_t qs = q - g.npbase;  // word within the segment's new records
-    const uint32_t o = ld32(cur + g.cmsg + 32 + 4 * i);
-    const uint64_t v = ld64(cur + g.cbody + 8 * ((uint64_t)o + w));
-    const uint64_t nsz = round8(4 * g.n_new);
-    *reinterpret_cast<uint64_t*>(enc + g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + nsz + 8 * qs) = v;
-    const uint64_t n = g.n_match + g.n_new;
-    *reinterpret_cast<uint64_t*>(newref + g.oref + 32 + 8 * ((n + 1) / 2) + 8 * (g.W + qs)) = v;
+  const int l = lane_id(), wv = wave_id();
+  NewTab& t = s_t[wv];
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(cur);
+  uint64_t* e64 = reinterpret_cast<uint64_t*>(enc);
+  uint64_t* o64 = reinterpret_cast<uint64_t*>(newref);
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t gb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; gb < Cn; gb += stride) {
+    const int64_t gc = gb + l;
+    const bool isnew = gc < Cn && !cflag[gc];
+    const uint64_t mask = __ballot(isnew);
+    if (!mask) continue;
+    const int64_t ge = gb + WAVE - 1 < Cn ? gb + WAVE - 1 : Cn - 1;
+    const int64_t s = wave_seg(cm.cpre, cm.nseg, (uint64_t)(gc < Cn ? gc : Cn - 1), (uint64_t)gb, (uint64_t)ge);
+    const int slot = __popcll(mask & lanemask_lt(l)), n = __popcll(mask);
+    uint64_t words = 0;
+    if (isnew) {
+      const Seg& g = cm.seg[s];
+      const uint32_t o = ld32(cur + g.cmsg + 32 + 4 * (uint64_t)(gc - (int64_t)cm.cpre[s]));
+      words = cwords[gc];
+      const uint64_t qs = (cscan[gc] & WMASK) - g.npbase;  // word within the segment's new records
+      const uint64_t nn = g.n_match + g.n_new;
+      t.src[slot] = (g.cbody + 8 * (uint64_t)o) / 8;
+      t.dst1[slot] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
+      t.dst2[slot] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
+    }
+    const uint64_t incl = wave_incl_scan(words);
+    if (isnew) t.q[slot] = incl - words;
+    if (l == WAVE - 1) t.q[n] = incl;
+    wave_sync();
+    const uint64_t tot = t.q[n];
+    for (uint64_t q = l; q < tot; q += WAVE) {
+      const int i = lds_last_le(t.q, n, q);
+      const uint64_t w = q - t.q[i];
+      const uint64_t v = src[t.src[i] + w];
+      e64[t.dst1[i] + w] = v;
+      o64[t.dst2[i] + w] = v;
+    }
+    wave_sync();
   }
 }
 
@@ -1298,7 +1321,7 @@ struct UnpackArgs {
 // One wave per 64-word group: read the block, rebuild the residual words, xor
 // with X and write C'.  Every length, size and padding byte is checked.
 __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
-  __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8];
+  __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8 + 1];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Gt = cm.meta[3];
@@ -1345,15 +1368,19 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
       const uint32_t nib = (popc + 1) / 2;
       const uint32_t t = (uint32_t)__popcll(bitmap & lanemask_lt(l));
       uint32_t len = 0;
-      if (bit && !bad) len = (blk[t / 2] >> (4 * (t & 1))) & 15u;
+      if (bit && !bad) len = (uint32_t)(s_blk[wv][t / 16] >> (4 * (t % 16))) & 15u;
       bool lbad = bit && (len < 1 || len > 8);
       const uint64_t sig_incl = wave_incl_scan(len);
       const uint64_t end = nib + uniform64(__shfl(sig_incl, 63, WAVE));
       if (end > size || round8(end) != size) bad = true;
       uint64_t D = 0;
       if (bit && !bad && !lbad) {
+        // the len bytes at so: two aligned words, shifted together
         const uint32_t so = nib + (uint32_t)(sig_incl - len);
-        for (uint32_t b = 0; b < len; ++b) D |= (uint64_t)blk[so + b] << (8 * b);
+        const uint32_t sh = 8 * (so % 8);
+        uint64_t v = s_blk[wv][so / 8] >> sh;
+        if (sh) v |= s_blk[wv][so / 8 + 1] << (64 - sh);
+        D = len == 8 ? v : (v & ((1ull << (8 * len)) - 1));
         if ((D >> (8 * (len - 1))) == 0) lbad = true;
       }
       if (!bad) {
@@ -1381,90 +1408,90 @@ struct ApplyArgs {
   uint64_t* out;
 };
 
-// One lane per matched record: C' = D xor X.  The wave's residual words are
-// contiguous, so they are loaded, combined and written through LDS with
-// coalesced accesses.  A matched record keeps its uid and header: their
+// Matched records in C' order: C' = D xor X, X the reference record (or its
+// prediction on words 2..5).  A matched record keeps its uid and header: their
 // residual words must be zero.
 __global__ __launch_bounds__(BLOCK) void k_dec_apply(ApplyArgs a) {
-  __shared__ uint64_t s_buf[WAVES][RES_CAP];
+  __shared__ RecTab s_t[WAVES];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t M = cm.meta[5];
   const int l = lane_id(), wv = wave_id();
-  uint64_t* buf = s_buf[wv];
+  RecTab& t = s_t[wv];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   for (int64_t kb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; kb < M; kb += stride) {
     const int64_t k = kb + l;
-    const bool act = k < M;
     const int64_t ke = kb + WAVE < M ? kb + WAVE : M;
-    const uint64_t d0 = a.mstart[kb], d1 = a.mstart[ke];
-    MDir e{};
-    uint64_t words = 0, cpw = 0;
-    int64_t sg = -1;
-    bool learned = false;
-    if (act) {
-      e = a.mdir[k];
-      words = a.mstart[k + 1] - e.dstart;
-      sg = mdir_seg(e);
-      const Seg& g = cm.seg[sg];
-      cpw = g.cpw;
-      learned = g.mode == 1 && a.pred_on[k];
+    const int n = (int)(ke - kb);
+    if (k < M) {
+      const MDir e = a.mdir[k];
+      const Seg& g = cm.seg[mdir_seg(e)];
+      t.d[l] = e.dstart;
+      t.r[l] = e.rword;
+      t.o[l] = g.cpw + e.dstart;
+      t.p[l] = (g.mode == 1 && a.pred_on[k]) ? 1 : 0;
     }
-    const int64_t s_first = __shfl(sg, 0, WAVE), s_last = __shfl(sg, (int)(ke - kb - 1), WAVE);
-    const uint64_t cpw0 = __shfl(cpw, 0, WAVE);
-    const bool staged = d1 - d0 <= RES_CAP;
-    const bool one_seg = s_first == s_last;
-    if (staged)
-      for (uint64_t p = l; p < d1 - d0; p += WAVE) buf[p] = a.D[d0 + p];
+    if (l == 0) t.d[n] = a.mstart[ke];
     wave_sync();
+    const uint64_t d1 = t.d[n];
     bool bad = false;
-    for (uint64_t w = 0; w < words; ++w) {
-      const uint64_t d = staged ? buf[e.dstart - d0 + w] : a.D[e.dstart + w];
-      if (w < 2 && d != 0) bad = true;
-      uint64_t x = a.ref[e.rword + w];
-      if (learned && w >= 2 && w < 6) x = a.pred_x[4 * k + (w - 2)];
-      if (staged) buf[e.dstart - d0 + w] = d ^ x;
-      else a.out[cpw + e.dstart + w] = d ^ x;
+    for (uint64_t d = t.d[0] + l; d < d1; d += WAVE) {
+      const int i = rec_of(t, n, d);
+      const uint64_t off = d - t.d[i];
+      const uint64_t dv = a.D[d];
+      if (off < 2 && dv != 0) bad = true;
+      const uint64_t x =
+          (t.p[i] && off >= 2 && off < 6) ? a.pred_x[4 * (kb + i) + (off - 2)] : a.ref[t.r[i] + off];
+      a.out[t.o[i] + off] = dv ^ x;
     }
     if (__ballot(bad) && l == 0) fail(cm.status, ERR_CORRUPT);
-    wave_sync();
-    if (staged) {
-      if (one_seg) {
-        for (uint64_t p = l; p < d1 - d0; p += WAVE) a.out[cpw0 + d0 + p] = buf[p];
-      } else {
-        for (uint64_t w = 0; w < words; ++w) a.out[cpw + e.dstart + w] = buf[e.dstart - d0 + w];
-      }
-    }
     wave_sync();
   }
 }
 
-// New records, word by word, from the encoding into C'; their offsets.
+// New records from the encoding into C', and their offsets: a wave takes
+// 64 new records, tabulates them in LDS and copies their words
+// lane-parallel.  A new record's uid must be non-zero and its header must
+// give the size the table announced.
 __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t* nscan, const uint8_t* enc,
                                                        uint8_t* out) {
+  __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
-  const uint64_t NW = (uint64_t)cm.meta[7];
   const int64_t Nn = cm.meta[6];
-  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
-  for (uint64_t qb = (uint64_t)blockIdx.x * BLOCK + wave_id() * WAVE; qb < NW; qb += stride) {
-    const uint64_t q = qb + lane_id();
-    const uint64_t qe = qb + WAVE - 1 < NW ? qb + WAVE - 1 : NW - 1;
-    const int64_t rlo = wave_last_le<uint64_t>(nscan, 0, Nn, qb);
-    const int64_t rhi = wave_last_le<uint64_t>(nscan, rlo, Nn, qe);
-    const int64_t r = last_le<uint64_t>(nscan, rlo, rhi + 1, q < NW ? q : NW - 1);
-    const int64_t s = wave_seg(cm.npre, cm.nseg, (uint64_t)r, (uint64_t)rlo, (uint64_t)rhi);
-    if (q >= NW) continue;
-    const Seg& g = cm.seg[s];
-    const uint64_t k = r - cm.npre[s];
-    const uint64_t w = q - nscan[r];
-    const uint64_t qs = q - g.npbase;
-    const uint64_t size = nscan[r + 1] - nscan[r];
-    const uint8_t* src = enc + g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new);
-    const uint64_t v = ld64(src + 8 * qs);
-    if ((w == 0 && v == 0) || (w == 1 && (v >> 32) != size)) fail(cm.status, ERR_CORRUPT);
-    const uint64_t n = g.n_match + g.n_new;
-    *reinterpret_cast<uint64_t*>(out + g.oref + 32 + 8 * ((n + 1) / 2) + 8 * (g.W + qs)) = v;
-    if (w == 0) *reinterpret_cast<uint32_t*>(out + g.oref + 32 + 4 * (g.n_match + k)) = (uint32_t)(g.W + nscan[r] - g.npbase);
+  const int l = lane_id(), wv = wave_id();
+  NewTab& t = s_t[wv];
+  const uint64_t* e64 = reinterpret_cast<const uint64_t*>(enc);
+  uint64_t* o64 = reinterpret_cast<uint64_t*>(out);
+  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  for (int64_t rb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; rb < Nn; rb += stride) {
+    const int64_t r = rb + l;
+    const int64_t re = rb + WAVE - 1 < Nn ? rb + WAVE - 1 : Nn - 1;
+    const int n = (int)(re - rb + 1);
+    const int64_t s = wave_seg(cm.npre, cm.nseg, (uint64_t)(r < Nn ? r : Nn - 1), (uint64_t)rb, (uint64_t)re);
+    if (r < Nn) {
+      const Seg& g = cm.seg[s];
+      const uint64_t qs = nscan[r] - g.npbase;
+      const uint64_t nn = g.n_match + g.n_new;
+      t.q[l] = nscan[r] - nscan[rb];
+      t.src[l] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
+      t.dst1[l] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
+      t.dst2[l] = nscan[r + 1] - nscan[r];  // size
+      *reinterpret_cast<uint32_t*>(out + g.oref + 32 + 4 * (g.n_match + (uint64_t)r - cm.npre[s])) =
+          (uint32_t)(g.W + qs);
+    }
+    if (l == 0) t.q[n] = nscan[rb + n] - nscan[rb];
+    wave_sync();
+    const uint64_t tot = t.q[n];
+    bool bad = false;
+    for (uint64_t q = l; q < tot; q += WAVE) {
+      const int i = lds_last_le(t.q, n, q);
+      const uint64_t w = q - t.q[i];
+      const uint64_t v = e64[t.src[i] + w];
+      if ((w == 0 && v == 0) || (w == 1 && (v >> 32) != t.dst2[i])) bad = true;
+      o64[t.dst1[i] + w] = v;
+    }
+    if (__ballot(bad) && l == 0) fail(cm.status, ERR_CORRUPT);
+    wave_sync();
   }
 }
 
@@ -1766,14 +1793,14 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.bm = ar.take<uint64_t>(b.G);
   m.gsz = ar.take<uint8_t>(b.G);
   m.gex = ar.take<uint64_t>(b.G + 1);
-  m.pred_x = ar.take<uint64_t>(4 * b.R);
-  m.pred_on = ar.take<uint8_t>(b.R);
+  m.pred_x = learned ? ar.take<uint64_t>(4 * b.R) : nullptr;
+  m.pred_on = learned ? ar.take<uint8_t>(b.R) : nullptr;
   m.gseg = ar.take<uint32_t>(b.G);
   m.mstart = ar.take<uint64_t>(b.R + 1);
   m.D = ar.take<uint64_t>(b.W);
   m.D2 = learned ? ar.take<uint64_t>(b.W) : nullptr;
-  m.gsz2 = ar.take<uint8_t>(b.G);
-  m.gex2 = ar.take<uint64_t>(b.G + 1);
+  m.gsz2 = learned ? ar.take<uint8_t>(b.G) : nullptr;
+  m.gex2 = learned ? ar.take<uint64_t>(b.G + 1) : nullptr;
   m.juid = ar.take<uint64_t>(b.C + b.R);
   m.jhdr = ar.take<uint64_t>(b.C + b.R);
   m.jcnt = ar.take<uint32_t>(b.E);
@@ -1818,19 +1845,20 @@ Bounds dec_bounds(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t rec_ca
 }  // namespace
 
 namespace ta {
-size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t rec_cap, int64_t* tiles) {
+size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t rec_cap, bool learned,
+                      int64_t* tiles) {
   Arena ar{nullptr, 0, 0};
   const Bounds b = enc_bounds(nseg, cur_len, ref_len, rec_cap);
-  carve(ar, nseg, b, true);
+  carve(ar, nseg, b, learned);
   *tiles = ceil_div(std::max(std::max(std::max(b.C, b.R), b.E), b.G) + 1, SCAN_TILE) + 2;
   return ar.used + 256;
 }
 size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t out_cap, int64_t rec_cap,
-                      int64_t* tiles) {
+                      bool learned, int64_t* tiles) {
   (void)out_cap;
   Arena ar{nullptr, 0, 0};
   const Bounds b = dec_bounds(nseg, enc_len, ref_len, rec_cap);
-  carve(ar, nseg, b, true);
+  carve(ar, nseg, b, learned);
   *tiles = ceil_div(std::max(std::max(b.C, b.R), b.G) + 1, SCAN_TILE) + 2;
   return ar.used + 256;
 }
@@ -1852,11 +1880,13 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     return z ? z : zero_i64(newref_off, 1, s);
   }
   use_family(c, FAM_ENCODE);
-  if (cur_len / 20 + 1 >= (1ll << 28) || cur_len / 8 >= (1ll << 34) || ref_len / 20 + 1 >= (1ll << 28) ||
-      ref_len / 8 >= (1ll << 34))
-    return TA_ERR_INVALID;  // packed scan fields: < 2^28 records, < 2^34 words
+  // packed scan fields: < 2^28 records (the record bound the scratch is
+  // sized for, checked on the device), < 2^34 words
+  if (rec_bound(cur_len, c->rec_cap) >= (1ll << 28) || cur_len / 8 >= (1ll << 34) ||
+      rec_bound(ref_len, c->rec_cap) >= (1ll << 28) || ref_len / 8 >= (1ll << 34))
+    return TA_ERR_INVALID;
   int64_t tiles;
-  ta_status st = ensure_scratch(c, encode_scratch(nseg, cur_len, ref_len, c->rec_cap, &tiles), tiles);
+  ta_status st = ensure_scratch(c, encode_scratch(nseg, cur_len, ref_len, c->rec_cap, pred != nullptr, &tiles), tiles);
   if (st) return st;
   Arena ar{c->scratch, c->scratch_cap, 0};
   const Bounds b = enc_bounds(nseg, cur_len, ref_len, c->rec_cap);
@@ -1923,7 +1953,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   }
   k_enc_fin<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, enc, enc_cap, enc_off, modes);
   k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.cflag, m.cwords, m.cscan, m.bm, m.gsz, enc, enc_cap, newref);
-  k_enc_newcopy<<<g, BLOCK, 0, s>>>(m.cm, m.cscan, m.cflag, cur, enc, newref);
+  k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.cflag, m.cwords, cur, enc, newref);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
                 hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};
@@ -1944,10 +1974,10 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   hipStream_t s = (hipStream_t)stream;
   if (nseg == 0) return zero_i64(out_off, 1, s);
   use_family(c, FAM_DECODE);
-  if (enc_len / 8 >= (1ll << 34) || ref_len / 20 + 1 >= (1ll << 28) || ref_len / 8 >= (1ll << 34))
+  if (enc_len / 8 >= (1ll << 34) || rec_bound(ref_len, c->rec_cap) >= (1ll << 28) || ref_len / 8 >= (1ll << 34))
     return TA_ERR_INVALID;
   int64_t tiles;
-  ta_status st = ensure_scratch(c, decode_scratch(nseg, enc_len, ref_len, out_cap, c->rec_cap, &tiles), tiles);
+  ta_status st = ensure_scratch(c, decode_scratch(nseg, enc_len, ref_len, out_cap, c->rec_cap, pred != nullptr, &tiles), tiles);
   if (st) return st;
   Arena ar{c->scratch, c->scratch_cap, 0};
   const Bounds b = dec_bounds(nseg, enc_len, ref_len, c->rec_cap);
@@ -1994,7 +2024,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                  reinterpret_cast<uint64_t*>(out)};
     k_dec_apply<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(aa);
   }
-  k_dec_newcopy<<<g, BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
+  k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
                 hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};

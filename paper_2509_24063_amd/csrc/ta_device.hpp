@@ -158,7 +158,10 @@ __device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t
 // 4 waves x SCAN_ROUNDS rounds of 64 consecutive items: every load and store
 // instruction of a wave touches 64 consecutive items, each round is one wave
 // scan, and one look-back per tile joins the tiles.
-constexpr int SCAN_ROUNDS = 16;
+#ifndef TA_SCAN_ROUNDS
+#define TA_SCAN_ROUNDS 8
+#endif
+constexpr int SCAN_ROUNDS = TA_SCAN_ROUNDS;
 constexpr int SCAN_TILE = BLOCK * SCAN_ROUNDS;
 
 // A functor may define wave_begin(first, last): called by all 64 lanes of a

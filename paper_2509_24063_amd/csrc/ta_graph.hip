@@ -58,10 +58,11 @@ ta_status presize(ta_ctx* c, const ta_iteration* it) {
   tiles = std::max(tiles, t);
   need = std::max(need, serialize_scratch(nseg, it->idx_cap, &t));
   tiles = std::max(tiles, t);
-  need = std::max(need, encode_scratch(nseg, it->msgs_cap, it->ref_len, c->rec_cap, &t));
+  need = std::max(need, encode_scratch(nseg, it->msgs_cap, it->ref_len, c->rec_cap, it->pred != nullptr, &t));
   tiles = std::max(tiles, t);
   if (it->rx_out) {
-    need = std::max(need, decode_scratch(nseg, it->enc_cap, it->rx_ref_len, it->rx_out_cap, c->rec_cap, &t));
+    need = std::max(need, decode_scratch(nseg, it->enc_cap, it->rx_ref_len, it->rx_out_cap, c->rec_cap, it->pred != nullptr,
+                                          &t));
     tiles = std::max(tiles, t);
   }
   return ensure_scratch(c, need, tiles);

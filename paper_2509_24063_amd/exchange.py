@@ -33,8 +33,10 @@ class Pipeline:
         self.ref_off = [zo(), zo()]
         self.rx = [z8(msgs_cap), z8(msgs_cap)] if decode else None
         self.rx_off = [zo(), zo()] if decode else None
-        self.hist = [native.History(idx_cap, device), native.History(idx_cap, device)]
-        self.rx_hist = [native.History(idx_cap, device), native.History(idx_cap, device)] if decode else None
+        # predictor history (learned mode only), per reference slot of each side
+        hc = idx_cap if pred is not None else 0
+        self.hist = [native.History(hc, device), native.History(hc, device)]
+        self.rx_hist = [native.History(hc, device), native.History(hc, device)] if decode else None
         self.decode = decode
         self.reset()
         self.graphs = [None, None]
@@ -56,9 +58,10 @@ class Pipeline:
     def iteration(self, parity: int, ds: native.DeviceStore | None = None) -> native.Iteration:
         p, q = parity, 1 - parity
         ds = self.ds if ds is None else ds
-        rx = dict(rx_ref=self.rx[p], rx_ref_off=self.rx_off[p], rx_out=self.rx[q], rx_out_off=self.rx_off[q],
-                  rx_hist=self.rx_hist[p], rx_hist_out=self.rx_hist[q]) if self.decode else {}
         pred = self.pred
+        rx = dict(rx_ref=self.rx[p], rx_ref_off=self.rx_off[p], rx_out=self.rx[q], rx_out_off=self.rx_off[q],
+                  rx_hist=self.rx_hist[p] if pred else None,
+                  rx_hist_out=self.rx_hist[q] if pred else None) if self.decode else {}
         return native.Iteration(ds, self.w, self.ndirs, self.idx, self.seg_off, self.msgs, self.msg_off,
                                 self.ref[p], self.ref_off[p], self.enc, self.enc_off, self.ref[q], self.ref_off[q],
                                 self.modes, pred=pred, hist=self.hist[p] if pred else None,

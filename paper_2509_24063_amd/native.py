@@ -14,7 +14,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(HERE, "lib", "libteraagent.so")
+# TERAAGENT_LIB: load another build of the library (e.g. one with other
+# compile-time launch shapes)
+LIB = os.environ.get("TERAAGENT_LIB") or os.path.join(HERE, "lib", "libteraagent.so")
 
 OK, INVALID, CAPACITY, CORRUPT, REF_MISMATCH, HIP = 0, 1, 2, 3, 4, 5
 NAMES = {0: "ok", 1: "invalid", 2: "capacity", 3: "corrupt", 4: "ref_mismatch", 5: "hip"}
