@@ -8,25 +8,34 @@
 // from R and drops the placeholders; the original order is not restored.
 //
 // Encoder kernels (all segments per launch):
-//   k_enc_setup   one block: message headers, record counts, hash sizes and
-//                 their prefixes
-//   k_clear_tab   empty hash table, flags
-//   k_enc_insert  every C and R record: validate, insert its uid into the
-//                 segment's open-addressing table (duplicates detected on both
-//                 sides); XOR of reference uids per segment
-//   k_enc_match   every R slot: matched C record (same uid and header word)
-//   k_scan x2     packed (count << 34 | words) prefixes over R slots (matched)
-//                 and C records (new)
-//   k_enc_seg2    one block: per segment sizes, section layout, C' headers
-//   k_enc_mdir    matched-record directory (C word, R word, residual start)
-//   k_enc_xor     one wave per 64-word residual group: C xor X, C' words,
-//                 bitmap, length nibbles and significant bytes assembled in
-//                 LDS; a look-back over group block sizes places the blocks
-//   k_enc_fin     one block: encoding offsets and headers
-//   k_enc_fixed   presence bitmaps, word bitmaps, block size tables, new
-//                 record sizes, C' offsets of new records
-//   k_newcopy     new records into the encoding and into C'
-// The decoder mirrors these steps.
+//   k_enc_setup    one thread per segment: message headers, record counts,
+//                  hash and join sizes; k_scan_cols turns them into prefixes
+//   k_join_count   per tile of records: validate, gather uid and header,
+//                  count items per hash bucket of the segment
+//   k_scan         bucket counts -> bucket starts
+//   k_join_scatter (uid, item) pairs into their buckets
+//   k_join_bucket  one block per bucket: LDS hash table pairs current and
+//                  reference items with equal uids (duplicates rejected);
+//                  k_clear_tab / k_enc_insert / k_enc_match: a global-table
+//                  join for buckets that overflow their block (rare)
+//   k_scan x2      packed (count << 34 | words) prefixes over R slots
+//                  (matched) and C records (new)
+//   k_enc_seg2/3   per segment layout, C' offsets and headers
+//   k_enc_mdir     matched-record directory (C word, R word, residual start)
+//                  and the segment of every residual group
+//   k_enc_resid    C' words and the dense residual C xor X
+//   k_enc_gsize    per 64-word group: bitmap and block size; k_scan places
+//                  the blocks; k_enc_place assembles each block in LDS and
+//                  writes it
+//   k_enc_fin      encoding offsets and headers
+//   k_enc_fixed    presence bitmaps, word bitmaps, block size tables, new
+//                  record sizes, C' offsets of new records
+//   k_enc_newcopy  new records into the encoding and into C'
+// Decoder: k_dec_setup (header checks), k_dec_rslots (reference slots,
+// presence bits), scans of matched slots, new records and group blocks,
+// k_dec_seg2 (checks against the header, C' headers), k_dec_mdir, then
+// k_dec_unpack (group blocks -> residual -> C' = D xor X in one pass) and
+// k_dec_newcopy.
 #include <initializer_list>
 
 #include "ta_internal.hpp"
@@ -83,12 +92,6 @@ struct MDir {
 __device__ inline int64_t mdir_seg(const MDir& e) { return (int64_t)(e.gs >> 34); }
 [[maybe_unused]] __device__ inline uint64_t mdir_slot(const MDir& e) { return e.gs & ((1ull << 34) - 1); }
 
-// wave-local ordering of LDS accesses (all lanes of one wave)
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 __device__ inline uint64_t mix64(uint64_t x) {
   x ^= x >> 31;
@@ -637,8 +640,12 @@ __global__ __launch_bounds__(BLOCK) void k_enc_seg3(Common cm, uint8_t* newref, 
 // Groups whose first residual word lies in a matched record (local words
 // [q0, q0+w)) of segment s: remember the segment, so a group's wave finds it
 // without searching.
-__device__ inline void map_groups(const Common& cm, int64_t s, uint64_t q0, uint64_t w, uint32_t* gseg) {
-  for (uint64_t lg = (q0 + 63) / 64; 64 * lg < q0 + w; ++lg) gseg[cm.gpre[s] + lg] = (uint32_t)s;
+__device__ inline void map_groups(const Common& cm, int64_t s, uint64_t q0, uint64_t w, uint32_t* gseg,
+                                  uint32_t* gfirst = nullptr, uint64_t k = 0) {
+  for (uint64_t lg = (q0 + 63) / 64; 64 * lg < q0 + w; ++lg) {
+    gseg[cm.gpre[s] + lg] = (uint32_t)s;
+    if (gfirst) gfirst[cm.gpre[s] + lg] = (uint32_t)k;  // the matched record holding the group's first word
+  }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
@@ -680,25 +687,21 @@ __device__ inline uint32_t build_block(uint64_t D, uint64_t* b64, uint64_t* bitm
   const uint32_t len = D ? (uint32_t)(8 - (__clzll((long long)D) >> 3)) : 0u;
   const uint32_t popc = (uint32_t)__popcll(bm);
   const uint32_t nib = (popc + 1) / 2;
-  const uint64_t sig_incl = wave_incl_scan(len);
-  const uint64_t sig_tot = uniform64(__shfl(sig_incl, 63, WAVE));
-  const uint32_t size = (uint32_t)round8(nib + sig_tot);
+  const uint32_t sig_incl = wave_incl_scan32(len);
+  const uint32_t sig_tot = (uint32_t)__builtin_amdgcn_readlane((int)sig_incl, 63);
+  const uint32_t size = (nib + sig_tot + 7) & ~7u;
   for (uint32_t k = l; k < size / 8; k += WAVE) b64[k] = 0;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  wave_sync();
   if (D) {
     // nibble t (t-th non-zero word): byte t/2, low nibble first = bits 4t of the block
     const uint32_t t = (uint32_t)__popcll(bm & lanemask_lt(l));
     atomicOr((unsigned long long*)&b64[t / 16], (unsigned long long)len << (4 * (t % 16)));
-    const uint32_t so = nib + (uint32_t)(sig_incl - len);
+    const uint32_t so = nib + sig_incl - len;
     const uint32_t sh = 8 * (so % 8);
     atomicOr((unsigned long long*)&b64[so / 8], (unsigned long long)(D << sh));
     if (sh && sh + 8 * len > 64) atomicOr((unsigned long long*)&b64[so / 8 + 1], (unsigned long long)(D >> (64 - sh)));
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  wave_sync();
   *bitmap_out = bm;
   return size;
 }
@@ -838,18 +841,18 @@ __global__ __launch_bounds__(BLOCK) void k_enc_gsize(PackArgs a) {
       if (gg >= Gt) break;
       const uint64_t D = Dv[x];
       const uint64_t bm = __ballot(D != 0);
-      const uint64_t len = D ? (uint64_t)(8 - (__clzll((long long)D) >> 3)) : 0;
-      const uint64_t sig = wave_sum(len);
+      const uint32_t len = D ? (uint32_t)(8 - (__clzll((long long)D) >> 3)) : 0u;
+      const uint32_t sig = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan32(len), 63);
       if (l == 0) {
         a.bm[gg] = bm;
-        a.gsz[gg] = (uint8_t)(round8(((uint64_t)__popcll(bm) + 1) / 2 + sig) / 8);
+        a.gsz[gg] = (uint8_t)((((uint32_t)__popcll(bm) + 1) / 2 + sig + 7) / 8);
       }
       if (a.D2) {
         const uint64_t D2 = D2v[x];
         const uint64_t bm2 = __ballot(D2 != 0);
-        const uint64_t len2 = D2 ? (uint64_t)(8 - (__clzll((long long)D2) >> 3)) : 0;
-        const uint64_t sig2 = wave_sum(len2);
-        if (l == 0) a.gsz2[gg] = (uint8_t)(round8(((uint64_t)__popcll(bm2) + 1) / 2 + sig2) / 8);
+        const uint32_t len2 = D2 ? (uint32_t)(8 - (__clzll((long long)D2) >> 3)) : 0u;
+        const uint32_t sig2 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan32(len2), 63);
+        if (l == 0) a.gsz2[gg] = (uint8_t)((((uint32_t)__popcll(bm2) + 1) / 2 + sig2 + 7) / 8);
       }
     }
   }
@@ -1285,7 +1288,8 @@ __global__ __launch_bounds__(BLOCK) void k_dec_seg2(Common cm, const uint64_t* r
 
 __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* ref, const uint8_t* rmatch,
                                                     const uint64_t* rscan, const uint32_t* rwords, MDir* mdir,
-                                                    uint64_t* mstart, uint8_t* out, uint32_t* gseg) {
+                                                    uint64_t* mstart, uint8_t* out, uint32_t* gseg,
+                                                    uint32_t* gfirst, uint64_t* mrw) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
@@ -1305,8 +1309,9 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
     e.gs = (uint64_t)g | ((uint64_t)s << 34);
     mdir[k] = e;
     mstart[k] = d;
+    mrw[k] = e.rword;
     *reinterpret_cast<uint32_t*>(out + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
-    map_groups(cm, s, d - sg.dbase, rwords[g], gseg);
+    map_groups(cm, s, d - sg.dbase, rwords[g], gseg, gfirst, k);
   }
 }
 
@@ -1315,23 +1320,33 @@ struct UnpackArgs {
   const uint8_t* enc;
   const uint64_t* gex;
   const uint32_t* gseg;
-  uint64_t* D;
+  const uint32_t* gfirst;  // matched record holding each group's first word
+  const uint64_t* ref;     // (words)
+  const uint64_t* mrw;     // [matched] R word of every matched record
+  const uint64_t* mstart;  // [matched+1]
+  const uint64_t* pred_x;
+  const uint8_t* pred_on;
+  uint64_t* out;           // C' (words)
 };
 
-// One wave per 64-word group: read the block, rebuild the residual words, xor
-// with X and write C'.  Every length, size and padding byte is checked.
+// One wave per 64-word group: read the block, rebuild the residual words D
+// and write C' = D xor X, X the reference record (or its prediction on words
+// 2..5).  The records overlapping the group (at most 33: records have at
+// least two words) are held one per lane; each word finds its record with a
+// search over the lanes.  Every length, size and padding byte is checked, and
+// the uid and header words of a matched record must have a zero residual.
 __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
   __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8 + 1];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
-  const int64_t Gt = cm.meta[3];
+  const int64_t Gt = cm.meta[3], M = cm.meta[5];
   const int l = lane_id(), wv = wave_id();
   uint8_t* blk = reinterpret_cast<uint8_t*>(s_blk[wv]);
   const int64_t nw = (int64_t)gridDim.x * WAVES;
   for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
     // descriptors of the wave's groups, loaded together
-    uint64_t bmv[PG_WAVE], boffv[PG_WAVE];
-    uint32_t sizev[PG_WAVE];
+    uint64_t bmv[PG_WAVE], boffv[PG_WAVE], msv[PG_WAVE], rwv[PG_WAVE];
+    uint32_t sizev[PG_WAVE], kfv[PG_WAVE];
     int64_t sv[PG_WAVE];
 #pragma unroll
     for (int x = 0; x < PG_WAVE; ++x) {
@@ -1340,7 +1355,16 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
       boffv[x] = 0;
       sizev[x] = 0;
       sv[x] = 0;
+      kfv[x] = 0;
+      msv[x] = ~0ull;
+      rwv[x] = 0;
       if (gg < Gt) {
+        // lane i <= 32: start and R word of the i-th record from the one
+        // holding the group's first word
+        const uint64_t k0 = a.gfirst[gg];
+        kfv[x] = (uint32_t)k0;
+        if (l <= 32 && k0 + l <= (uint64_t)M) msv[x] = a.mstart[k0 + l];
+        if (l <= 32 && k0 + l < (uint64_t)M) rwv[x] = a.mrw[k0 + l];
         const int64_t s = a.gseg[gg];
         const Seg& sg = cm.seg[s];
         const uint64_t lg = (uint64_t)gg - cm.gpre[s];
@@ -1362,6 +1386,35 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
       bool bad = size > BLK_MAX;
       if (!bad)
         for (uint32_t w = l; w < size / 8; w += WAVE) s_blk[wv][w] = ld64(a.enc + boffv[x] + 8 * w);
+      // this lane's word: its record (a search over the lanes' record starts)
+      // and the reference word X, loaded while the block is decoded
+      const uint64_t q = 64 * lg + (uint64_t)l;
+      const uint64_t d = sg.dbase + q;  // global residual position
+      const uint64_t k0 = kfv[x];
+      // record starts relative to the group's first word, clamped to [-2^30, 64]
+      const uint64_t g0w = sg.dbase + 64 * lg;
+      const int64_t rel64 = (int64_t)(msv[x] == ~0ull ? g0w + 64 : msv[x]) - (int64_t)g0w;
+      const int rel = rel64 > 64 ? 64 : (rel64 < -(1 << 30) ? -(1 << 30) : (int)rel64);
+      const int lastw = (int)((64 * lg + 63 < sg.W ? 64 * lg + 63 : sg.W - 1) - 64 * lg);
+      const int nrec = __popcll(__ballot(l <= 32 && rel <= lastw));
+      int lo = 0, hi = nrec;  // the last lane with start <= this lane's word
+#pragma unroll
+      for (int step = 0; step < 6; ++step) {
+        const int m = (lo + hi) >> 1;
+        const bool le = __shfl(rel, m, WAVE) <= l;
+        if (hi - lo > 1) {
+          if (le) lo = m;
+          else hi = m;
+        }
+      }
+      const uint64_t off = (uint64_t)(l - __shfl(rel, lo, WAVE));
+      const uint64_t rw_i = (uint64_t)__shfl((long long)rwv[x], lo, WAVE);
+      const bool live = q < sg.W && !bad;
+      uint64_t xw = 0;
+      if (live) {
+        const bool pred = sg.mode == 1 && off >= 2 && off < 6 && a.pred_on[k0 + lo];
+        xw = pred ? a.pred_x[4 * (k0 + lo) + (off - 2)] : a.ref[rw_i + off];
+      }
       wave_sync();
       const bool bit = (bitmap >> l) & 1;
       const uint32_t popc = (uint32_t)__popcll(bitmap);
@@ -1370,13 +1423,13 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
       uint32_t len = 0;
       if (bit && !bad) len = (uint32_t)(s_blk[wv][t / 16] >> (4 * (t % 16))) & 15u;
       bool lbad = bit && (len < 1 || len > 8);
-      const uint64_t sig_incl = wave_incl_scan(len);
-      const uint64_t end = nib + uniform64(__shfl(sig_incl, 63, WAVE));
-      if (end > size || round8(end) != size) bad = true;
+      const uint32_t sig_incl = wave_incl_scan32(len);
+      const uint32_t end = nib + (uint32_t)__builtin_amdgcn_readlane((int)sig_incl, 63);
+      if (end > size || ((end + 7) & ~7u) != size) bad = true;
       uint64_t D = 0;
       if (bit && !bad && !lbad) {
         // the len bytes at so: two aligned words, shifted together
-        const uint32_t so = nib + (uint32_t)(sig_incl - len);
+        const uint32_t so = nib + sig_incl - len;
         const uint32_t sh = 8 * (so % 8);
         uint64_t v = s_blk[wv][so / 8] >> sh;
         if (sh) v |= s_blk[wv][so / 8 + 1] << (64 - sh);
@@ -1384,68 +1437,18 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
         if ((D >> (8 * (len - 1))) == 0) lbad = true;
       }
       if (!bad) {
-        if (end + (uint64_t)l < size && blk[end + l] != 0) lbad = true;   // padding bytes
+        if (end + (uint32_t)l < size && blk[end + l] != 0) lbad = true;   // padding bytes
         if (l == 0 && (popc & 1) && (blk[popc / 2] >> 4) != 0) lbad = true;  // unused high nibble
       }
-      const uint64_t q = 64 * lg + (uint64_t)l;
-      if (q < sg.W && !bad) a.D[sg.dbase + q] = D;
+      if (live) {
+        if (off < 2 && D != 0) lbad = true;
+        a.out[sg.cpw + d] = D ^ xw;
+      }
       if (__ballot(lbad) || bad) {
         if (l == 0) fail(cm.status, ERR_CORRUPT);
       }
       wave_sync();
     }
-  }
-}
-
-struct ApplyArgs {
-  Common cm;
-  const uint64_t* ref;
-  const MDir* mdir;
-  const uint64_t* mstart;
-  const uint64_t* pred_x;
-  const uint8_t* pred_on;
-  const uint64_t* D;
-  uint64_t* out;
-};
-
-// Matched records in C' order: C' = D xor X, X the reference record (or its
-// prediction on words 2..5).  A matched record keeps its uid and header: their
-// residual words must be zero.
-__global__ __launch_bounds__(BLOCK) void k_dec_apply(ApplyArgs a) {
-  __shared__ RecTab s_t[WAVES];
-  const Common& cm = a.cm;
-  if (status_of(cm.status) & ANY_ERR) return;
-  const int64_t M = cm.meta[5];
-  const int l = lane_id(), wv = wave_id();
-  RecTab& t = s_t[wv];
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t kb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; kb < M; kb += stride) {
-    const int64_t k = kb + l;
-    const int64_t ke = kb + WAVE < M ? kb + WAVE : M;
-    const int n = (int)(ke - kb);
-    if (k < M) {
-      const MDir e = a.mdir[k];
-      const Seg& g = cm.seg[mdir_seg(e)];
-      t.d[l] = e.dstart;
-      t.r[l] = e.rword;
-      t.o[l] = g.cpw + e.dstart;
-      t.p[l] = (g.mode == 1 && a.pred_on[k]) ? 1 : 0;
-    }
-    if (l == 0) t.d[n] = a.mstart[ke];
-    wave_sync();
-    const uint64_t d1 = t.d[n];
-    bool bad = false;
-    for (uint64_t d = t.d[0] + l; d < d1; d += WAVE) {
-      const int i = rec_of(t, n, d);
-      const uint64_t off = d - t.d[i];
-      const uint64_t dv = a.D[d];
-      if (off < 2 && dv != 0) bad = true;
-      const uint64_t x =
-          (t.p[i] && off >= 2 && off < 6) ? a.pred_x[4 * (kb + i) + (off - 2)] : a.ref[t.r[i] + off];
-      a.out[t.o[i] + off] = dv ^ x;
-    }
-    if (__ballot(bad) && l == 0) fail(cm.status, ERR_CORRUPT);
-    wave_sync();
   }
 }
 
@@ -1747,6 +1750,8 @@ struct Mem {
   uint64_t* pred_x;
   uint8_t* pred_on;
   uint32_t* gseg;
+  uint32_t* gfirst;
+  uint64_t* mrw;
   uint64_t* mstart;
   uint64_t* D;
   uint64_t* D2;
@@ -1796,6 +1801,8 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.pred_x = learned ? ar.take<uint64_t>(4 * b.R) : nullptr;
   m.pred_on = learned ? ar.take<uint8_t>(b.R) : nullptr;
   m.gseg = ar.take<uint32_t>(b.G);
+  m.gfirst = ar.take<uint32_t>(b.G);
+  m.mrw = ar.take<uint64_t>(b.R);
   m.mstart = ar.take<uint64_t>(b.R + 1);
   m.D = ar.take<uint64_t>(b.W);
   m.D2 = learned ? ar.take<uint64_t>(b.W) : nullptr;
@@ -1997,7 +2004,8 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, b.G, m.gex,
                                                                      lookback(c, 2));
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
-  k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg);
+  k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg, m.gfirst,
+                                 m.mrw);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
     Timed tm(c, "predict", s);
@@ -2015,14 +2023,9 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   }
   {
     Timed tm(c, "decode_unpack", s);
-    UnpackArgs ua{m.cm, enc, m.gex, m.gseg, m.D};
+    UnpackArgs ua{m.cm,  enc,      m.gex,    m.gseg,    m.gfirst, reinterpret_cast<const uint64_t*>(ref),
+                  m.mrw, m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(out)};
     k_dec_unpack<<<grid_for(c, b.G, WAVES * PG_WAVE), BLOCK, 0, s>>>(ua);
-  }
-  {
-    Timed tm(c, "decode_apply", s);
-    ApplyArgs aa{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, m.mstart, m.pred_x, m.pred_on, m.D,
-                 reinterpret_cast<uint64_t*>(out)};
-    k_dec_apply<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(aa);
   }
   k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
   if (hist_out) {

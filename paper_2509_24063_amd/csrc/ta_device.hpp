@@ -25,6 +25,16 @@ __device__ inline uint32_t status_of(const uint32_t* status) {
 }
 
 __device__ inline int lane_id() { return (int)__lane_id(); }
+
+// Orders the LDS accesses of the lanes of one wave (LDS written by some lanes
+// and then read by others).  Wavefront scope: it keeps the compiler from
+// moving LDS accesses across it and waits for this wave's LDS operations, but
+// not for its global loads and stores, which stay in flight.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __device__ inline int wave_id() { return (int)(threadIdx.x / WAVE); }
 
 __device__ inline uint64_t lanemask_le(int l) { return l >= 63 ? ~0ull : ((2ull << l) - 1); }
@@ -39,6 +49,20 @@ __device__ inline uint64_t wave_incl_scan(uint64_t v) {
   }
   return v;
 }
+// Inclusive scan of a 32-bit value over the 64 lanes with DPP row shifts
+// (within rows of 16 lanes) and row broadcasts (15 -> rows 1 and 3, then
+// 31 -> rows 2 and 3): six adds, no LDS traffic.  All lanes must call it.
+__device__ inline uint32_t wave_incl_scan32(uint32_t v) {
+  int x = (int)v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return (uint32_t)x;
+}
+
 __device__ inline uint64_t wave_sum(uint64_t v) {
 #pragma unroll
   for (int d = WAVE / 2; d; d >>= 1) v += __shfl_xor(v, d, WAVE);

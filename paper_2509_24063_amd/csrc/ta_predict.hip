@@ -27,18 +27,12 @@ __global__ __launch_bounds__(BLOCK) void k_pred_eval(const PredW* w, const int32
       const int64_t row = r0 + e / 12;
       s_in[wv][e / 12][e % 12] = row < n ? in[row * 12 + e % 12] : 0;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    wave_sync();
     mlp16(s_w, s_in[wv], s_q[wv]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    wave_sync();
     const int64_t row = r0 + l / 4;
     if (l < 64 && row < n) q[row * 4 + (l & 3)] = s_q[wv][l / 4][l & 3];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    wave_sync();
   }
 }
 

@@ -174,18 +174,14 @@ __global__ __launch_bounds__(BLOCK) void k_ser_pack(PackArgs a, SerScratch sc) {
       for (uint64_t k = 0; k < nbw; ++k) dst[2 + F + IW + k] = bsrc[k];
     }
     if (staged) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      wave_sync();
       // the wave's records are one contiguous stretch of its message
       const int64_t first = a.seg_off[s_first];
       const uint64_t n = (uint64_t)(a.seg_off[s_first + 1] - first);
       uint64_t* out = reinterpret_cast<uint64_t*>(a.out + a.msg_off[s_first] + 32 + 8 * ((n + 1) / 2)) +
                       (w0 - sc.wpre[first]);
       for (uint64_t p = l; p < w1 - w0; p += WAVE) out[p] = buf[p];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      wave_sync();
     }
   }
 }
