@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--per-partition", action="store_true", help="batched: also time per-partition calls")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="MiB copied once by a plain device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -308,6 +310,14 @@ def main():
     nseg = P * cfg.ndirs
     n_agents = host_states[0].n
 
+    if args.copy_probe > 0:
+        nb = int(args.copy_probe * (1 << 20))
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nb} bytes")
+        del src, dst
     ctx = native.Context(cfg.schema)
     from paper_2509_24063_amd.exchange import capacities
     idx_cap, ser_cap = capacities(ctx, host_states[0], cfg.ndirs, cfg.w, slack=1.3)
@@ -354,10 +364,8 @@ def main():
         "encode_resid": 32 * acc["W"] + 40 * acc["match"],
         # read the residual, write the group blocks, bitmaps, sizes, offsets
         "encode_pack": 8 * acc["W"] + acc["var"] + 17 * acc["groups"],
-        # read the residual, R words and directory entries, write C' words
-        "decode_apply": 32 * acc["W"] + 40 * acc["match"],
-        # read the group blocks and their tables, write the residual
-        "decode_unpack": 8 * acc["W"] + acc["var"] + 17 * acc["groups"],
+        # read the group blocks and their tables, R words and directory entries, write C' words
+        "decode_unpack": 16 * acc["W"] + acc["var"] + 17 * acc["groups"] + 40 * acc["match"],
         # gather the agents' fields (about the record bytes), indices, offsets; write records + offsets
         "serialize_pack": 2 * acc["msg"] + 32 * records,
     }
@@ -413,7 +421,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.roofline_kernel, f"{args.workload}:{n_agents}"),
             "launches": launches,
             "avg_ms": kernel_avg_ms,
             "algorithmic_bytes_per_launch": kb,
@@ -436,6 +444,26 @@ def main():
     if not args.no_cpu and not batched:
         out["cpu_baseline"] = cpu_baseline(host_states, cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter measurement
+    (profiles/traffic.json), or None when there is none for this kernel and
+    workload or the kernel's source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))[kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2509_24063_amd", "csrc", rec["source"])
+    try:
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if digest != rec["sha256"] or rec["workload"] != workload:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(states, cfg, budget_s):

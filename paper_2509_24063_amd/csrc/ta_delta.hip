@@ -542,7 +542,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a) {
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < n; k += BLOCK) {
       const uint32_t id = s_id[k], p = s_partner[k];
-      const bool matched = p != NONE && a.jhdr[id] == a.jhdr[s_id[p]];
+      const bool matched = p != NONE;  // same uid; the headers are compared by RMatchIn
       if (id >= Ct) {
         a.m[id - Ct] = matched ? (int32_t)(s_id[p] - cm.cpre[s]) : -1;
       } else {
@@ -553,10 +553,36 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a) {
   }
 }
 
-struct RMatchIn {  // count << 34 | words of matched reference slots
-  const int32_t* m;
+// count << 34 | words of matched reference slots.  A slot is matched when
+// its uid was found in the current message and the two header words are
+// equal; a uid match with another header is undone here (the slot becomes
+// unmatched, the current record new).  Reference slots and their partners
+// run in the same order, so both header reads are close to sequential.
+struct RMatchIn {
+  Common cm;
+  int32_t* m;
   const uint32_t* rwords;
-  __device__ uint64_t operator()(int64_t g) const { return m[g] >= 0 ? ((1ull << PK) | rwords[g]) : 0; }
+  const uint64_t* jhdr;  // [C+R] header words: current records, then reference slots
+  uint8_t* cflag;
+  int64_t lo = 0, hi = 0;  // segments of the wave's slots
+  __device__ void wave_begin(int64_t first, int64_t last) {
+    lo = wave_last_le<uint64_t>(cm.rpre, 0, cm.nseg, (uint64_t)first);
+    hi = wave_last_le<uint64_t>(cm.rpre, lo, cm.nseg, (uint64_t)last);
+  }
+  __device__ uint64_t operator()(int64_t g) const {
+    const int32_t i = m[g];
+    if (i < 0) return 0;
+    const int64_t s = last_le<uint64_t>(cm.rpre, lo, hi + 1, (uint64_t)g);
+    // (after an earlier error the join may not have run: stay inside the segment)
+    if ((uint64_t)i >= cm.seg[s].nc) return 0;
+    const uint64_t ci = cm.cpre[s] + (uint64_t)i;
+    if (jhdr[(uint64_t)cm.meta[0] + (uint64_t)g] != jhdr[ci]) {
+      m[g] = -1;
+      cflag[ci] = 0;
+      return 0;
+    }
+    return (1ull << PK) | rwords[g];
+  }
 };
 struct CNewIn {  // count << 34 | words of new current records
   const uint8_t* cflag;
@@ -1289,7 +1315,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_seg2(Common cm, const uint64_t* r
 __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* ref, const uint8_t* rmatch,
                                                     const uint64_t* rscan, const uint32_t* rwords, MDir* mdir,
                                                     uint64_t* mstart, uint8_t* out, uint32_t* gseg,
-                                                    uint32_t* gfirst, uint64_t* mrw) {
+                                                    uint32_t* gfirst, uint32_t* mrw) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
@@ -1309,7 +1335,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
     e.gs = (uint64_t)g | ((uint64_t)s << 34);
     mdir[k] = e;
     mstart[k] = d;
-    mrw[k] = e.rword;
+    mrw[k] = (uint32_t)(e.rword - sg.rbody / 8);  // word offset in the reference's record area
     *reinterpret_cast<uint32_t*>(out + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
     map_groups(cm, s, d - sg.dbase, rwords[g], gseg, gfirst, k);
   }
@@ -1322,7 +1348,7 @@ struct UnpackArgs {
   const uint32_t* gseg;
   const uint32_t* gfirst;  // matched record holding each group's first word
   const uint64_t* ref;     // (words)
-  const uint64_t* mrw;     // [matched] R word of every matched record
+  const uint32_t* mrw;     // [matched] word offset of every matched record in its reference's record area
   const uint64_t* mstart;  // [matched+1]
   const uint64_t* pred_x;
   const uint8_t* pred_on;
@@ -1345,7 +1371,8 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
   const int64_t nw = (int64_t)gridDim.x * WAVES;
   for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
     // descriptors of the wave's groups, loaded together
-    uint64_t bmv[PG_WAVE], boffv[PG_WAVE], msv[PG_WAVE], rwv[PG_WAVE];
+    uint64_t bmv[PG_WAVE], boffv[PG_WAVE], msv[PG_WAVE];
+    uint32_t rwv[PG_WAVE];
     uint32_t sizev[PG_WAVE], kfv[PG_WAVE];
     int64_t sv[PG_WAVE];
 #pragma unroll
@@ -1408,12 +1435,13 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
         }
       }
       const uint64_t off = (uint64_t)(l - __shfl(rel, lo, WAVE));
-      const uint64_t rw_i = (uint64_t)__shfl((long long)rwv[x], lo, WAVE);
+      const uint32_t rw_i = (uint32_t)__shfl((int)rwv[x], lo, WAVE);
       const bool live = q < sg.W && !bad;
       uint64_t xw = 0;
       if (live) {
         const bool pred = sg.mode == 1 && off >= 2 && off < 6 && a.pred_on[k0 + lo];
-        xw = pred ? a.pred_x[4 * (k0 + lo) + (off - 2)] : a.ref[rw_i + off];
+        const uint64_t* rbody = a.ref + sg.rbody / 8;  // the segment's reference records
+        xw = pred ? a.pred_x[4 * (k0 + lo) + (off - 2)] : rbody[rw_i + (uint32_t)off];
       }
       wave_sync();
       const bool bit = (bitmap >> l) & 1;
@@ -1751,7 +1779,7 @@ struct Mem {
   uint8_t* pred_on;
   uint32_t* gseg;
   uint32_t* gfirst;
-  uint64_t* mrw;
+  uint32_t* mrw;
   uint64_t* mstart;
   uint64_t* D;
   uint64_t* D2;
@@ -1802,7 +1830,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.pred_on = learned ? ar.take<uint8_t>(b.R) : nullptr;
   m.gseg = ar.take<uint32_t>(b.G);
   m.gfirst = ar.take<uint32_t>(b.G);
-  m.mrw = ar.take<uint64_t>(b.R);
+  m.mrw = ar.take<uint32_t>(b.R);
   m.mstart = ar.take<uint64_t>(b.R + 1);
   m.D = ar.take<uint64_t>(b.W);
   m.D2 = learned ? ar.take<uint64_t>(b.W) : nullptr;
@@ -1918,7 +1946,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     k_enc_insert<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.cwords, m.rwords, m.rslot);
     k_enc_match<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.rslot, m.m, m.cflag);
   }
-  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(RMatchIn{m.m, m.rwords}, m.cm.meta + 1, b.R, m.rscan,
+  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
                                                                      lookback(c, 1));
   k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, b.C, m.cscan,
                                                                    lookback(c, 2));

@@ -182,14 +182,23 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
     uint64_t packed[NW];
 #pragma unroll
     for (int j = 0; j < NW; ++j) packed[j] = 0;
+    uint32_t any = 0;
 #pragma unroll
-    for (int k = 0; k < SEL_IPT; ++k) code[k] = (i0 + k < ti.a1) ? sc.code[i0 + k] : 0u;
+    for (int k = 0; k < SEL_IPT; ++k) {
+      code[k] = (i0 + k < ti.a1) ? sc.code[i0 + k] : 0u;
+      any |= code[k];
+    }
+    // most waves (agents away from the box faces) select nothing: they skip
+    // the per-direction counts and only join the block scan with zeros
+    const bool wave_any = __ballot(any != 0) != 0;
+    if (wave_any) {
 #pragma unroll
-    for (int d = 0; d < NDIRS; ++d) {
-      uint64_t c = 0;
+      for (int d = 0; d < NDIRS; ++d) {
+        uint64_t c = 0;
 #pragma unroll
-      for (int k = 0; k < SEL_IPT; ++k) c += (code[k] & dt.req[d]) == dt.req[d] && code[k];
-      packed[d / 5] += c << (12 * (d % 5));
+        for (int k = 0; k < SEL_IPT; ++k) c += (code[k] & dt.req[d]) == dt.req[d] && code[k];
+        packed[d / 5] += c << (12 * (d % 5));
+      }
     }
     // block exclusive scan of the packed words
     uint64_t incl[NW];
@@ -210,6 +219,7 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
     }
     __syncthreads();
     const int64_t cbase = sc.tile_off[ti.p] * NDIRS + ti.lt;
+    if (!wave_any) continue;
 #pragma unroll
     for (int d = 0; d < NDIRS; ++d) {
       const uint64_t mine = (packed[d / 5] >> (12 * (d % 5))) & 0xFFF;

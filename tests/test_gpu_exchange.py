@@ -42,6 +42,36 @@ def test_config1_iterations(native):
     _run(native, synth.config(1), 5, "cfg1")
 
 
+def _shuffled(store, rng):
+    """The same population with its agents in random order inside each
+    partition (uids no longer ascending in store order)."""
+    order = np.concatenate([int(a) + rng.permutation(int(b) - int(a))
+                            for a, b in zip(store.part_off[:-1], store.part_off[1:])]).astype(np.int64)
+    beh_off, beh = synth._gather_beh(store.beh_off, store.beh, order)
+    return synth.Store(uid=store.uid[order], cls=store.cls[order], nb=store.nb[order],
+                       f64=np.ascontiguousarray(store.f64[:, order]), i32=np.ascontiguousarray(store.i32[:, order]),
+                       beh_off=beh_off, beh=beh, part_off=store.part_off.copy(), boxes=store.boxes)
+
+
+def test_unsorted_uids(native):
+    """Stores reshuffled every iteration: messages list uids in no particular
+    order; results match the oracle."""
+    cfg = synth.config(3, median=300.0, grid=(2, 2, 2))
+    world = synth.World(cfg)
+    rng = np.random.default_rng(17)
+    ctx = native.Context(cfg.schema)
+    nseg = world.store.P * cfg.ndirs
+    gs, os_ = GpuSide(ctx, nseg), OracleSide(nseg)
+    for it in range(4):
+        store = _shuffled(world.store, rng)
+        print(f"[unsorted] iteration {it}: {store.n} agents", flush=True)
+        g = gs.step(native.DeviceStore(store), cfg)
+        o = os_.step(store, cfg)
+        assert_same(g, o, f"unsorted it {it}")
+        world.step()
+    ctx.close()
+
+
 def test_batched_uneven_partitions(native):
     # the 8x8x8 periodic layout with lognormal sizes, scaled down
     _run(native, synth.config(3, median=300.0), 3, "cfg3-small")
@@ -284,10 +314,12 @@ def _mix64(x):
     return x
 
 
-def test_join_bucket_overflow_falls_back(native):
+@pytest.mark.parametrize("shuffled", [True, False])
+def test_join_bucket_overflow_falls_back(native, shuffled):
     """Uids chosen so that every item of a 4000-item segment lands in one of
     its 4 join buckets (more than one block holds in LDS): the encoder must
-    switch to its global-table join and still match the oracle."""
+    switch to its global-table join and still match the oracle, with the
+    records in ascending or in shuffled uid order."""
     cand = np.arange(1, 200000, dtype=np.uint64)
     same = cand[(_mix64(cand) & np.uint64(3)) == 0][:2000]
     r = [rec(int(u), x=float(k), words=7) for k, u in enumerate(same)]
@@ -295,6 +327,10 @@ def test_join_bucket_overflow_falls_back(native):
     for x in c:
         x[2] ^= 0x1234
     c += [rec(int(u), words=7) for u in cand[(_mix64(cand) & np.uint64(3)) == 0][2000:2100]]
+    if shuffled:
+        rng = np.random.default_rng(3)
+        r = [r[i] for i in rng.permutation(len(r))]
+        c = [c[i] for i in rng.permutation(len(c))]
     ctx = native.Context(synth.Schema((4,), (1,)))
     cur, coff = _upload(native, [tam1(c)])
     ref, roff = _upload(native, [tam1(r)])
