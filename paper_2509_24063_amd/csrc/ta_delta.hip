@@ -839,7 +839,11 @@ constexpr int PG_WAVE = TA_PG_WAVE;  // groups one wave handles at a time (loads
 
 // Pass 1 of the zero-block packer: per 64-word group, its bitmap word and
 // its block size (nibbles + significant bytes, rounded to 8).
-__global__ __launch_bounds__(BLOCK) void k_enc_gsize(PackArgs a) {
+// (segs, gpre, gseg: read-only here; as restrict parameters their uniform
+// reads become scalar loads)
+__global__ __launch_bounds__(BLOCK) void k_enc_gsize(PackArgs a, const Seg* __restrict__ segs,
+                                                     const uint64_t* __restrict__ gpre,
+                                                     const uint32_t* __restrict__ gseg) {
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Gt = cm.meta[3];
@@ -853,8 +857,9 @@ __global__ __launch_bounds__(BLOCK) void k_enc_gsize(PackArgs a) {
       Dv[x] = 0;
       D2v[x] = 0;
       if (gg < Gt) {
-        const Seg& sg = cm.seg[a.gseg[gg]];
-        const uint64_t q = 64 * ((uint64_t)gg - cm.gpre[a.gseg[gg]]) + (uint64_t)l;
+        const int64_t s = (int64_t)uniform32(gseg[gg]);
+        const Seg& sg = segs[s];
+        const uint64_t q = 64 * ((uint64_t)gg - gpre[s]) + (uint64_t)l;
         if (q < sg.W) {
           Dv[x] = a.D[sg.dbase + q];
           if (a.D2) D2v[x] = a.D2[sg.dbase + q];
@@ -910,7 +915,10 @@ __global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm, const uint64_t
 }
 
 // Pass 3: every group rebuilds its block in LDS and writes it at its offset.
-__global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a, const Seg* __restrict__ segs,
+                                                     const uint64_t* __restrict__ gpre,
+                                                     const uint32_t* __restrict__ gseg,
+                                                     const uint64_t* __restrict__ gex) {
   __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8 + 1];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
@@ -925,12 +933,12 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a) {
       Dv[x] = 0;
       at[x] = 0;
       if (gg < Gt) {
-        const int64_t s = a.gseg[gg];
-        const Seg& sg = cm.seg[s];
-        const uint64_t q = 64 * ((uint64_t)gg - cm.gpre[s]) + (uint64_t)l;
+        const int64_t s = (int64_t)uniform32(gseg[gg]);
+        const Seg& sg = segs[s];
+        const uint64_t q = 64 * ((uint64_t)gg - gpre[s]) + (uint64_t)l;
         const uint64_t* src = (a.D2 && sg.mode == 1) ? a.D2 : a.D;
         if (q < sg.W) Dv[x] = src[sg.dbase + q];
-        at[x] = sg.fixed_excl + sg.fixed + a.gex[gg];
+        at[x] = uniform64(sg.fixed_excl + sg.fixed + gex[gg]);
       }
     }
 #pragma unroll
@@ -1361,7 +1369,13 @@ struct UnpackArgs {
 // least two words) are held one per lane; each word finds its record with a
 // search over the lanes.  Every length, size and padding byte is checked, and
 // the uid and header words of a matched record must have a zero residual.
-__global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
+// (segs, gpre, gex, gseg, gfirst: read-only here; as restrict parameters
+// their uniform reads become scalar loads)
+__global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* __restrict__ segs,
+                                                      const uint64_t* __restrict__ gpre,
+                                                      const uint64_t* __restrict__ gex,
+                                                      const uint32_t* __restrict__ gseg,
+                                                      const uint32_t* __restrict__ gfirst) {
   __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8 + 1];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
@@ -1388,28 +1402,30 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
       if (gg < Gt) {
         // lane i <= 32: start and R word of the i-th record from the one
         // holding the group's first word
-        const uint64_t k0 = a.gfirst[gg];
+        // (per-group values are the same in every lane: kept in scalar registers)
+        const uint64_t k0 = uniform32(gfirst[gg]);
         kfv[x] = (uint32_t)k0;
         if (l <= 32 && k0 + l <= (uint64_t)M) msv[x] = a.mstart[k0 + l];
         if (l <= 32 && k0 + l < (uint64_t)M) rwv[x] = a.mrw[k0 + l];
-        const int64_t s = a.gseg[gg];
-        const Seg& sg = cm.seg[s];
-        const uint64_t lg = (uint64_t)gg - cm.gpre[s];
+        const int64_t s = (int64_t)uniform32(gseg[gg]);
+        const Seg& sg = segs[s];
+        const uint64_t lg = (uint64_t)gg - gpre[s];
         const uint8_t* e = a.enc + sg.encm;
         sv[x] = s;
-        bmv[x] = ld64(e + 64 + 8 * sg.PG + 8 * lg);
-        sizev[x] = 8u * e[64 + 8 * sg.PG + 8 * sg.G + lg];
-        boffv[x] = sg.encm + sg.fixed + (a.gex[gg] - a.gex[cm.gpre[s]]);
+        bmv[x] = uniform64(ld64(e + 64 + 8 * sg.PG + 8 * lg));
+        sizev[x] = uniform32(8u * e[64 + 8 * sg.PG + 8 * sg.G + lg]);
+        boffv[x] = uniform64(sg.encm + sg.fixed + (gex[gg] - gex[gpre[s]]));
       }
     }
 #pragma unroll
     for (int x = 0; x < PG_WAVE; ++x) {
       const int64_t gg = g0 + x;
       if (gg >= Gt) break;
-      const Seg& sg = cm.seg[sv[x]];
-      const uint64_t lg = (uint64_t)gg - cm.gpre[sv[x]];
-      const uint64_t bitmap = bmv[x];
-      const uint32_t size = sizev[x];
+      const int64_t sx = (int64_t)uniform32((uint32_t)sv[x]);
+      const Seg& sg = segs[sx];
+      const uint64_t lg = uniform64((uint64_t)gg - gpre[sx]);
+      const uint64_t bitmap = uniform64(bmv[x]);
+      const uint32_t size = uniform32(sizev[x]);
       bool bad = size > BLK_MAX;
       if (!bad)
         for (uint32_t w = l; w < size / 8; w += WAVE) s_blk[wv][w] = ld64(a.enc + boffv[x] + 8 * w);
@@ -1417,7 +1433,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
       // and the reference word X, loaded while the block is decoded
       const uint64_t q = 64 * lg + (uint64_t)l;
       const uint64_t d = sg.dbase + q;  // global residual position
-      const uint64_t k0 = kfv[x];
+      const uint64_t k0 = uniform32(kfv[x]);
       // record starts relative to the group's first word, clamped to [-2^30, 64]
       const uint64_t g0w = sg.dbase + 64 * lg;
       const int64_t rel64 = (int64_t)(msv[x] == ~0ull ? g0w + 64 : msv[x]) - (int64_t)g0w;
@@ -1438,10 +1454,14 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a) {
       const uint32_t rw_i = (uint32_t)__shfl((int)rwv[x], lo, WAVE);
       const bool live = q < sg.W && !bad;
       uint64_t xw = 0;
-      if (live) {
-        const bool pred = sg.mode == 1 && off >= 2 && off < 6 && a.pred_on[k0 + lo];
-        const uint64_t* rbody = a.ref + sg.rbody / 8;  // the segment's reference records
-        xw = pred ? a.pred_x[4 * (k0 + lo) + (off - 2)] : rbody[rw_i + (uint32_t)off];
+      const uint64_t* rbody = a.ref + uniform64(sg.rbody / 8);  // the segment's reference records
+      if (uniform32((uint32_t)sg.mode) == 1) {
+        if (live) {
+          const bool pred = off >= 2 && off < 6 && a.pred_on[k0 + lo];
+          xw = pred ? a.pred_x[4 * (k0 + lo) + (off - 2)] : rbody[rw_i + (uint32_t)off];
+        }
+      } else if (live) {
+        xw = rbody[rw_i + (uint32_t)off];
       }
       wave_sync();
       const bool bit = (bitmap >> l) & 1;
@@ -1976,7 +1996,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     PackArgs pa{m.cm, m.D, enc, enc_cap, m.bm, m.gsz, m.gex, m.gseg, m.D2, m.gsz2};
     const int gp = grid_for(c, b.G, WAVES * PG_WAVE);
     const int gs = grid_for(c, b.G + 1, SCAN_TILE);
-    k_enc_gsize<<<gp, BLOCK, 0, s>>>(pa);
+    k_enc_gsize<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg);
     k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, b.G, m.gex, lookback(c, 3));
     if (pw) {
       k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, b.G, m.gex2, lookback(c, 4));
@@ -1984,7 +2004,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
       k_scan<GChosenIn><<<gs, BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, b.G, m.gex,
                                              lookback(c, 5));
     }
-    k_enc_place<<<gp, BLOCK, 0, s>>>(pa);
+    k_enc_place<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg, m.gex);
   }
   k_enc_fin<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, enc, enc_cap, enc_off, modes);
   k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.cflag, m.cwords, m.cscan, m.bm, m.gsz, enc, enc_cap, newref);
@@ -2053,7 +2073,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
     Timed tm(c, "decode_unpack", s);
     UnpackArgs ua{m.cm,  enc,      m.gex,    m.gseg,    m.gfirst, reinterpret_cast<const uint64_t*>(ref),
                   m.mrw, m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(out)};
-    k_dec_unpack<<<grid_for(c, b.G, WAVES * PG_WAVE), BLOCK, 0, s>>>(ua);
+    k_dec_unpack<<<grid_for(c, b.G, WAVES * PG_WAVE), BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst);
   }
   k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
   if (hist_out) {

@@ -78,6 +78,7 @@ __device__ inline uint64_t wave_xor(uint64_t v) {
   for (int d = WAVE / 2; d; d >>= 1) v ^= __shfl_xor(v, d, WAVE);
   return v;
 }
+__device__ inline uint32_t uniform32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 __device__ inline uint64_t uniform64(uint64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
