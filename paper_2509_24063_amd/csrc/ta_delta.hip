@@ -79,7 +79,6 @@ struct Seg {
   uint64_t size_plain, size_learned;  // encoder, learned mode: block bytes both ways
   uint64_t jB, jT, jTC, jTJ;  // join: buckets, count tiles (C tiles first), items per tile
   uint64_t jebase;            // join: first count entry of the segment
-  uint64_t fold_part[FOLD_SLOTS];  // partial XORs of reference uids (spread to avoid atomic contention)
   uint64_t cpw;               // word index of C' for residual position 0 (C' word of position d = cpw + d)
 };
 
@@ -146,6 +145,7 @@ struct Common {
   uint64_t* fxpre; // [nseg+1] fixed encoding byte prefixes
   uint64_t* opre;  // [nseg+1] C' message offsets
   uint64_t* cols;  // [COL_MAX][nseg+1] per segment values to scan
+  uint64_t* fold;  // [nseg][FOLD_SLOTS] partial XORs of reference uids (spread to avoid atomic contention)
   int64_t* meta;   // [0] C records [1] R records [2] hash slots [3] groups [4] presence words [5] matched
                    // [6] new records [7] new words [8] unused [9] fixed bytes [10] join tiles
                    // [11] join count entries [12] join buckets [13] join bucket overflow
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_setup(Common cm, const uint8_t* c
     hs = pow2ceil(2 * (nc + nr));
     g.hsize = hs;
     g.fold = 0;
-    for (int k = 0; k < FOLD_SLOTS; ++k) g.fold_part[k] = 0;
+    for (int k = 0; k < FOLD_SLOTS; ++k) cm.fold[s * FOLD_SLOTS + k] = 0;
     g.mode = 0;
     // join layout: B buckets, counting tiles of TJ items (C tiles, then R tiles)
     uint64_t B = pow2ceil((nc + nr + JB_TARGET - 1) / JB_TARGET);
@@ -389,11 +389,12 @@ struct JTile {
   uint64_t lt, i0, i1;  // items [i0, i1) of one side of the segment
   bool isC;
 };
-__device__ inline JTile join_tile(const Common& cm, int64_t t) {
+// (t is the same in every lane: the tile's segment is kept in a scalar register)
+__device__ inline JTile join_tile(const Seg* segs, const uint64_t* tpre, int64_t nseg, int64_t t) {
   JTile jt;
-  jt.s = last_le<uint64_t>(cm.tpre, 0, cm.nseg, (uint64_t)t);
-  const Seg& g = cm.seg[jt.s];
-  jt.lt = (uint64_t)t - cm.tpre[jt.s];
+  jt.s = (int64_t)uniform32((uint32_t)last_le<uint64_t>(tpre, 0, nseg, (uint64_t)t));
+  const Seg& g = segs[jt.s];
+  jt.lt = (uint64_t)t - tpre[jt.s];
   jt.isC = jt.lt < g.jTC;
   const uint64_t k = jt.isC ? jt.lt : jt.lt - g.jTC;
   const uint64_t n = jt.isC ? g.nc : g.nr;
@@ -403,22 +404,28 @@ __device__ inline JTile join_tile(const Common& cm, int64_t t) {
 }
 
 // J1: validate every record, gather uid and header, count items per bucket.
-__global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a) {
+// (segs, tpre, cpre, rpre, jepre: read-only in the join kernels; as restrict
+// parameters their uniform reads become scalar loads)
+__global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a, const Seg* __restrict__ segs,
+                                                      const uint64_t* __restrict__ tpre,
+                                                      const uint64_t* __restrict__ cpre,
+                                                      const uint64_t* __restrict__ rpre,
+                                                      const uint64_t* __restrict__ jepre) {
   __shared__ uint32_t s_hist[JB_MAX];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Tt = cm.meta[10];
   const uint64_t Ct = (uint64_t)cm.meta[0];
   for (int64_t t = blockIdx.x; t < Tt; t += gridDim.x) {
-    const JTile jt = join_tile(cm, t);
-    Seg& g = cm.seg[jt.s];
+    const JTile jt = join_tile(segs, tpre, cm.nseg, t);
+    const Seg& g = segs[jt.s];
     const uint64_t B = g.jB;
     for (uint64_t b = threadIdx.x; b < B; b += BLOCK) s_hist[b] = 0;
     __syncthreads();
     const uint8_t* msg = jt.isC ? a.cur + g.cmsg : a.ref + g.rmsg;
     const uint32_t n = (uint32_t)(jt.isC ? g.nc : g.nr);
     const uint64_t rw = jt.isC ? g.rwc : g.rwr;
-    const uint64_t gbase = jt.isC ? cm.cpre[jt.s] : Ct + cm.rpre[jt.s];
+    const uint64_t gbase = jt.isC ? cpre[jt.s] : Ct + rpre[jt.s];
     uint64_t fold = 0;
     for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += BLOCK) {
       const uint64_t i = i0 + threadIdx.x;
@@ -436,8 +443,8 @@ __global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a) {
           const uint64_t item = gbase + (i - 0);
           a.juid[item] = uid;
           a.jhdr[item] = hdr;
-          if (jt.isC) a.cwords[cm.cpre[jt.s] + i] = (uint32_t)(hdr >> 32);
-          else a.rwords[cm.rpre[jt.s] + i] = (uint32_t)(hdr >> 32);
+          if (jt.isC) a.cwords[cpre[jt.s] + i] = (uint32_t)(hdr >> 32);
+          else a.rwords[rpre[jt.s] + i] = (uint32_t)(hdr >> 32);
           atomicAdd(&s_hist[join_bucket(uid, B)], 1u);
           if (!jt.isC) fold ^= uid;
         }
@@ -446,10 +453,11 @@ __global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a) {
     if (!jt.isC) {
       fold = wave_xor(fold);
       if (lane_id() == 0 && fold)
-        atomicXor((unsigned long long*)&g.fold_part[(t * WAVES + wave_id()) % FOLD_SLOTS], (unsigned long long)fold);
+        atomicXor((unsigned long long*)&cm.fold[jt.s * FOLD_SLOTS + (t * WAVES + wave_id()) % FOLD_SLOTS],
+                  (unsigned long long)fold);
     }
     __syncthreads();
-    uint32_t* dst = a.cnt + cm.jepre[jt.s] + jt.lt;
+    uint32_t* dst = a.cnt + jepre[jt.s] + jt.lt;
     for (uint64_t b = threadIdx.x; b < B; b += BLOCK) dst[b * g.jT] = s_hist[b];
     __syncthreads();
   }
@@ -461,23 +469,28 @@ struct JCntIn {
 };
 
 // J3: scatter (uid, item) pairs into their buckets.
-__global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a, const Seg* __restrict__ segs,
+                                                        const uint64_t* __restrict__ tpre,
+                                                        const uint64_t* __restrict__ cpre,
+                                                        const uint64_t* __restrict__ rpre,
+                                                        const uint64_t* __restrict__ jepre,
+                                                        const uint64_t* __restrict__ cnt_pre) {
   __shared__ uint32_t s_off[JB_MAX];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Tt = cm.meta[10];
   const uint64_t Ct = (uint64_t)cm.meta[0];
   for (int64_t t = blockIdx.x; t < Tt; t += gridDim.x) {
-    const JTile jt = join_tile(cm, t);
-    const Seg& g = cm.seg[jt.s];
+    const JTile jt = join_tile(segs, tpre, cm.nseg, t);
+    const Seg& g = segs[jt.s];
     const uint64_t B = g.jB;
-    const uint64_t* src = a.cnt_pre + cm.jepre[jt.s] + jt.lt;
+    const uint64_t* src = cnt_pre + jepre[jt.s] + jt.lt;
     // bucket starts relative to the segment's first entry (fits 32 bits:
     // a segment holds < 2^28 + 2^28 items)
-    const uint64_t seg0 = a.cnt_pre[cm.jepre[jt.s]];
+    const uint64_t seg0 = uniform64(cnt_pre[jepre[jt.s]]);
     for (uint64_t b = threadIdx.x; b < B; b += BLOCK) s_off[b] = (uint32_t)(src[b * g.jT] - seg0);
     __syncthreads();
-    const uint64_t gbase = jt.isC ? cm.cpre[jt.s] : Ct + cm.rpre[jt.s];
+    const uint64_t gbase = jt.isC ? cpre[jt.s] : Ct + rpre[jt.s];
     for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += BLOCK) {
       const uint64_t i = i0 + threadIdx.x;
       if (i < jt.i1) {
@@ -495,7 +508,11 @@ __global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a) {
 // J4: one block per bucket: an LDS hash table pairs current and reference
 // items with equal uids; a second item of the same side, or a third item,
 // is a duplicate.
-__global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a, const Seg* __restrict__ segs,
+                                                       const uint64_t* __restrict__ bpre,
+                                                       const uint64_t* __restrict__ cpre,
+                                                       const uint64_t* __restrict__ jepre,
+                                                       const uint64_t* __restrict__ cnt_pre) {
   __shared__ uint64_t s_uid[JCAP];
   __shared__ uint32_t s_id[JCAP];
   __shared__ uint32_t s_partner[JCAP];
@@ -505,10 +522,10 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a) {
   const int64_t Bt = cm.meta[12];
   const uint64_t Ct = (uint64_t)cm.meta[0];
   for (int64_t bk = blockIdx.x; bk < Bt; bk += gridDim.x) {
-    const int64_t s = last_le<uint64_t>(cm.bpre, 0, cm.nseg, (uint64_t)bk);
-    const Seg& g = cm.seg[s];
-    const uint64_t b = (uint64_t)bk - cm.bpre[s];
-    const uint64_t p0 = a.cnt_pre[cm.jepre[s] + b * g.jT], p1 = a.cnt_pre[cm.jepre[s] + (b + 1) * g.jT];
+    const int64_t s = (int64_t)uniform32((uint32_t)last_le<uint64_t>(bpre, 0, cm.nseg, (uint64_t)bk));
+    const Seg& g = segs[s];
+    const uint64_t b = (uint64_t)bk - bpre[s];
+    const uint64_t p0 = uniform64(cnt_pre[jepre[s] + b * g.jT]), p1 = uniform64(cnt_pre[jepre[s] + (b + 1) * g.jT]);
     const uint32_t n = (uint32_t)(p1 - p0);
     if (n > JCAP) {  // uniform: leave this bucket to the global-table join
       if (threadIdx.x == 0) atomicOr((unsigned long long*)&cm.meta[13], 1ull);
@@ -544,7 +561,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a) {
       const uint32_t id = s_id[k], p = s_partner[k];
       const bool matched = p != NONE;  // same uid; the headers are compared by RMatchIn
       if (id >= Ct) {
-        a.m[id - Ct] = matched ? (int32_t)(s_id[p] - cm.cpre[s]) : -1;
+        a.m[id - Ct] = matched ? (int32_t)(s_id[p] - cpre[s]) : -1;
       } else {
         a.cflag[id] = matched ? 1 : 0;
       }
@@ -609,7 +626,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_seg2(Common cm, const uint64_t* r
   }
   for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
     Seg& g = cm.seg[s];
-    g.fold = fold_of(g.fold_part);
+    g.fold = fold_of(cm.fold + s * FOLD_SLOTS);
     const uint64_t rs = rscan[cm.rpre[s]], re = rscan[cm.rpre[s + 1]];
     const uint64_t cs = cscan[cm.cpre[s]], ce = cscan[cm.cpre[s + 1]];
     g.mbase = rs >> PK;
@@ -1112,6 +1129,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_setup(Common cm, const uint8_t* e
   do_clear_first(cf);
   for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
     uint64_t nr = 0, G = 0, nn = 0, osz = 0, PG = 0, hs = 0;
+    for (int k = 0; k < FOLD_SLOTS; ++k) cm.fold[s * FOLD_SLOTS + k] = 0;
     {
       Seg& g = cm.seg[s];
       const int64_t ea = enc_off[s], eb = enc_off[s + 1], ra = ref_off[s], rb = ref_off[s + 1];
@@ -1143,7 +1161,6 @@ __global__ __launch_bounds__(BLOCK) void k_dec_setup(Common cm, const uint8_t* e
         const uint64_t len = (uint64_t)(eb - ea);
         g.fold = h[4];
         g.rfold = 0;
-        for (int k = 0; k < FOLD_SLOTS; ++k) g.fold_part[k] = 0;
         g.var = var;
         if (n_ref != n || ref_words != rw) {
           code = ERR_REF;
@@ -1198,8 +1215,12 @@ __global__ __launch_bounds__(BLOCK) void k_dec_setup(Common cm, const uint8_t* e
   }
 }
 
+// (segs, rpre: read-only here; as restrict parameters, reads with a
+// wave-uniform segment become scalar loads)
 __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* enc, const uint8_t* ref,
-                                                      uint32_t* rwords, uint8_t* rmatch) {
+                                                      uint32_t* rwords, uint8_t* rmatch,
+                                                      const Seg* __restrict__ segs,
+                                                      const uint64_t* __restrict__ rpre) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
@@ -1212,15 +1233,17 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
     bool ok = false;
     const int64_t wbase = g - lane_id();
     int64_t s = 0;
+    bool one = false;
     if (wbase < Rt) {
       const uint64_t last = (uint64_t)(wbase + WAVE - 1 < Rt ? wbase + WAVE - 1 : Rt - 1);
-      s = wave_seg(cm.rpre, cm.nseg, (uint64_t)(active ? g : Rt - 1), (uint64_t)wbase, last);
+      s = wave_seg(rpre, cm.nseg, (uint64_t)(active ? g : Rt - 1), (uint64_t)wbase, last);
+      one = __shfl(s, 0, WAVE) == __shfl(s, (int)(last - (uint64_t)wbase), WAVE);
     }
-    if (active) {
-      const Seg& sg = cm.seg[s];
-      const uint64_t j = g - cm.rpre[s];
+    auto slot = [&](int64_t sg_i) {
+      const Seg& sg = segs[sg_i];
+      const uint64_t j = g - rpre[sg_i];
       uint32_t o;
-      uint64_t hdr;
+      uint64_t hdr = 0;
       const uint8_t* m = ref + sg.rmsg;
       if (tam1_record(m, (uint32_t)sg.nr, sg.rwr, (uint32_t)j, &o, &hdr)) {
         uid = ld64(tam1_records(m, (uint32_t)sg.nr) + 8 * (uint64_t)o);
@@ -1230,9 +1253,15 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
       const uint64_t pw = ld64(enc + sg.encm + 64 + 8 * (j / 64));
       rmatch[g] = (uint8_t)((pw >> (j & 63)) & 1);
       rwords[g] = (uint32_t)(hdr >> 32);
+    };
+    if (one) {
+      const int64_t su = (int64_t)uniform32((uint32_t)s);  // the whole wave in one segment
+      if (active) slot(su);
+    } else if (active) {
+      slot(s);
     }
     // XOR of the reference uids, compared with the encoding's later
-    seg_xor(&cm.seg[0].fold_part[0], sizeof(Seg) / 8, s, active && ok, uid);
+    seg_xor(cm.fold, FOLD_SLOTS, s, active && ok, uid);
   }
 }
 
@@ -1304,7 +1333,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_seg2(Common cm, const uint64_t* r
     g.npbase = nscan[cm.npre[s]];
     const uint64_t nw = nscan[cm.npre[s + 1]] - g.npbase;
     const uint64_t var = gex[cm.gpre[s + 1]] - gex[cm.gpre[s]];
-    g.rfold = fold_of(g.fold_part);
+    g.rfold = fold_of(cm.fold + s * FOLD_SLOTS);
     if (g.rfold != g.fold) fail(cm.status, ERR_REF);
     if (nm != g.n_match || W != g.W || nw != g.new_words || var != g.var) fail(cm.status, ERR_CORRUPT);
     // the header of this segment's C' (inside the output: oref + its size <= total <= out_cap)
@@ -1832,6 +1861,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.cm.fxpre = ar.take<uint64_t>(nseg + 1);
   m.cm.opre = ar.take<uint64_t>(nseg + 1);
   m.cm.cols = ar.take<uint64_t>(COL_MAX * (nseg + 1));
+  m.cm.fold = ar.take<uint64_t>(FOLD_SLOTS * (nseg + 1));
   m.cm.meta = ar.take<int64_t>(16);
   m.cm.status = nullptr;
   m.tab = ar.take<Entry>(b.H);
@@ -1956,11 +1986,12 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   {
     Timed tm(c, "encode_join", s);
     JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag};
-    k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja);
+    k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre);
     k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
                                                                      lookback(c, 0));
-    k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja);
-    k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja);
+    k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre,
+                                                         m.jcnt_pre);
+    k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.bpre, m.cm.cpre, m.cm.jepre, m.jcnt_pre);
     // only when a bucket overflowed its block: the global-table join
     k_clear_tab<<<g, BLOCK, 0, s>>>(m.cm, m.tab, m.cflag);
     k_enc_insert<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.cwords, m.rwords, m.rslot);
@@ -2044,7 +2075,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                                      clear_first(c, ceil_div(b.R + 1, SCAN_TILE)));
   k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.rpre, m.cm.gpre, m.cm.npre, m.cm.opre, m.cm.ppre, m.cm.hpre},
                                           {1, 3, 6, -1, 4, 2}, {b.R, b.G, b.C, -1, -1, b.H}));
-  k_dec_rslots<<<g, BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag);
+  k_dec_rslots<<<g, BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre);
   k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
                                                                      m.rscan, lookback(c, 0));
   k_scan<DNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, b.C, m.cscan,
