@@ -853,6 +853,10 @@ struct PackArgs {
 #define TA_PG_WAVE 4
 #endif
 constexpr int PG_WAVE = TA_PG_WAVE;  // groups one wave handles at a time (loads issued together)
+#ifndef TA_UNPACK_PG
+#define TA_UNPACK_PG 1
+#endif
+constexpr int UNPACK_PG = TA_UNPACK_PG;  // the decoder's groups per wave at a time
 
 // Pass 1 of the zero-block packer: per 64-word group, its bitmap word and
 // its block size (nibbles + significant bytes, rounded to 8).
@@ -1392,141 +1396,182 @@ struct UnpackArgs {
   uint64_t* out;           // C' (words)
 };
 
+// Byte-granular funnel: the 32 bits of hi:lo starting at bit s (s < 32).
+__device__ inline uint32_t funnel32(uint32_t hi, uint32_t lo, uint32_t s) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> s);
+}
+
 // One wave per 64-word group: read the block, rebuild the residual words D
 // and write C' = D xor X, X the reference record (or its prediction on words
-// 2..5).  The records overlapping the group (at most 33: records have at
-// least two words) are held one per lane; each word finds its record with a
-// search over the lanes.  Every length, size and padding byte is checked, and
-// the uid and header words of a matched record must have a zero residual.
+// 2..5).  A wave takes UNPACK_PG consecutive groups at a time and issues all
+// their loads (descriptors, record tables, block words, reference words)
+// before it consumes any.
+//
+// Each word's record: the records overlapping a group (at most 33, since
+// records have at least two words) are held one per lane, lane 0 holding
+// the one with the group's first word.  Lanes 1..32 mark their record's
+// start word in LDS with a tag unique to the group, one ballot turns the
+// marks into a start mask, and a word's record index is the number of
+// starts at or below it.
+//
+// Every length, size, padding byte and unused nibble is checked, and the
+// uid and header words of a matched record must have a zero residual.
 // (segs, gpre, gex, gseg, gfirst: read-only here; as restrict parameters
 // their uniform reads become scalar loads)
 __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* __restrict__ segs,
                                                       const uint64_t* __restrict__ gpre,
                                                       const uint64_t* __restrict__ gex,
                                                       const uint32_t* __restrict__ gseg,
-                                                      const uint32_t* __restrict__ gfirst) {
-  __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8 + 1];
+                                                      const uint32_t* __restrict__ gfirst,
+                                                      const uint8_t* __restrict__ enc) {
+  constexpr int BW = BLK_MAX / 8 + 1;  // block words, one spare for the two-word read
+  __shared__ uint64_t s_blk[WAVES][UNPACK_PG][BW];
+  __shared__ uint32_t s_mark[WAVES][UNPACK_PG][WAVE];  // record-start marks: group index + 1
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Gt = cm.meta[3], M = cm.meta[5];
   const int l = lane_id(), wv = wave_id();
-  uint8_t* blk = reinterpret_cast<uint8_t*>(s_blk[wv]);
-  const int64_t nw = (int64_t)gridDim.x * WAVES;
-  for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
-    // descriptors of the wave's groups, loaded together
-    uint64_t bmv[PG_WAVE], boffv[PG_WAVE], msv[PG_WAVE];
-    uint32_t rwv[PG_WAVE];
-    uint32_t sizev[PG_WAVE], kfv[PG_WAVE];
-    int64_t sv[PG_WAVE];
 #pragma unroll
-    for (int x = 0; x < PG_WAVE; ++x) {
+  for (int x = 0; x < UNPACK_PG; ++x) s_mark[wv][x][l] = 0;  // no group's tag
+  wave_sync();
+  const uint64_t le_mask = lanemask_le(l);
+  bool anybad = false;
+  const int64_t nw = (int64_t)gridDim.x * WAVES;
+  for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * UNPACK_PG; g0 < Gt; g0 += nw * UNPACK_PG) {
+    // wave-uniform per group (scalar registers) ...
+    uint64_t bmv[UNPACK_PG];
+    uint32_t sizev[UNPACK_PG];
+    // ... and per lane: record start (relative to the group's first word)
+    // and reference word offset of record k0 + lane, block words lane and 64 + lane
+    int relv[UNPACK_PG];
+    uint32_t rwv[UNPACK_PG];
+    uint64_t b0v[UNPACK_PG], b1v[UNPACK_PG];
+#pragma unroll
+    for (int x = 0; x < UNPACK_PG; ++x) {
       const int64_t gg = g0 + x;
       bmv[x] = 0;
-      boffv[x] = 0;
       sizev[x] = 0;
-      sv[x] = 0;
-      kfv[x] = 0;
-      msv[x] = ~0ull;
+      relv[x] = 64;
       rwv[x] = 0;
+      b0v[x] = b1v[x] = 0;
       if (gg < Gt) {
-        // lane i <= 32: start and R word of the i-th record from the one
-        // holding the group's first word
-        // (per-group values are the same in every lane: kept in scalar registers)
         const uint64_t k0 = uniform32(gfirst[gg]);
-        kfv[x] = (uint32_t)k0;
-        if (l <= 32 && k0 + l <= (uint64_t)M) msv[x] = a.mstart[k0 + l];
-        if (l <= 32 && k0 + l < (uint64_t)M) rwv[x] = a.mrw[k0 + l];
-        const int64_t s = (int64_t)uniform32(gseg[gg]);
-        const Seg& sg = segs[s];
-        const uint64_t lg = (uint64_t)gg - gpre[s];
-        const uint8_t* e = a.enc + sg.encm;
-        sv[x] = s;
+        const int64_t sx = (int64_t)uniform32(gseg[gg]);
+        const Seg& sg = segs[sx];
+        const uint64_t lg = (uint64_t)gg - gpre[sx];
+        const uint8_t* e = enc + sg.encm;
         bmv[x] = uniform64(ld64(e + 64 + 8 * sg.PG + 8 * lg));
-        sizev[x] = uniform32(8u * e[64 + 8 * sg.PG + 8 * sg.G + lg]);
-        boffv[x] = uniform64(sg.encm + sg.fixed + (gex[gg] - gex[gpre[s]]));
-      }
-    }
-#pragma unroll
-    for (int x = 0; x < PG_WAVE; ++x) {
-      const int64_t gg = g0 + x;
-      if (gg >= Gt) break;
-      const int64_t sx = (int64_t)uniform32((uint32_t)sv[x]);
-      const Seg& sg = segs[sx];
-      const uint64_t lg = uniform64((uint64_t)gg - gpre[sx]);
-      const uint64_t bitmap = uniform64(bmv[x]);
-      const uint32_t size = uniform32(sizev[x]);
-      bool bad = size > BLK_MAX;
-      if (!bad)
-        for (uint32_t w = l; w < size / 8; w += WAVE) s_blk[wv][w] = ld64(a.enc + boffv[x] + 8 * w);
-      // this lane's word: its record (a search over the lanes' record starts)
-      // and the reference word X, loaded while the block is decoded
-      const uint64_t q = 64 * lg + (uint64_t)l;
-      const uint64_t d = sg.dbase + q;  // global residual position
-      const uint64_t k0 = uniform32(kfv[x]);
-      // record starts relative to the group's first word, clamped to [-2^30, 64]
-      const uint64_t g0w = sg.dbase + 64 * lg;
-      const int64_t rel64 = (int64_t)(msv[x] == ~0ull ? g0w + 64 : msv[x]) - (int64_t)g0w;
-      const int rel = rel64 > 64 ? 64 : (rel64 < -(1 << 30) ? -(1 << 30) : (int)rel64);
-      const int lastw = (int)((64 * lg + 63 < sg.W ? 64 * lg + 63 : sg.W - 1) - 64 * lg);
-      const int nrec = __popcll(__ballot(l <= 32 && rel <= lastw));
-      int lo = 0, hi = nrec;  // the last lane with start <= this lane's word
-#pragma unroll
-      for (int step = 0; step < 6; ++step) {
-        const int m = (lo + hi) >> 1;
-        const bool le = __shfl(rel, m, WAVE) <= l;
-        if (hi - lo > 1) {
-          if (le) lo = m;
-          else hi = m;
+        // the size byte, from its aligned dword (the size table is 8-byte aligned)
+        const uint32_t sw = *reinterpret_cast<const uint32_t*>(e + 64 + 8 * sg.PG + 8 * sg.G + (lg & ~3ull));
+        const uint32_t size = uniform32(8u * ((sw >> (8 * (lg & 3))) & 0xFFu));
+        sizev[x] = size;
+        if (l <= 32 && k0 + l < (uint64_t)M) {
+          // clamped to [-2^30, 64]: lane 0's record may start long before the group
+          const int64_t r = (int64_t)a.mstart[k0 + l] - (int64_t)(sg.dbase + 64 * lg);
+          relv[x] = r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r);
+          rwv[x] = a.mrw[k0 + l];
+        }
+        if (size <= BLK_MAX) {
+          const uint64_t* src =
+              reinterpret_cast<const uint64_t*>(enc + uniform64(sg.encm + sg.fixed + (gex[gg] - gex[gpre[sx]])));
+          if ((uint32_t)l < size / 8) b0v[x] = src[l];
+          if (size > 8 * WAVE && (uint32_t)(WAVE + l) < size / 8) b1v[x] = src[WAVE + l];
         }
       }
-      const uint64_t off = (uint64_t)(l - __shfl(rel, lo, WAVE));
-      const uint32_t rw_i = (uint32_t)__shfl((int)rwv[x], lo, WAVE);
-      const bool live = q < sg.W && !bad;
-      uint64_t xw = 0;
+    }
+    // record starts inside each group
+#pragma unroll
+    for (int x = 0; x < UNPACK_PG; ++x)
+      if (g0 + x < Gt && l >= 1 && l <= 32 && relv[x] >= 1 && relv[x] < WAVE)
+        s_mark[wv][x][relv[x]] = (uint32_t)(g0 + x) + 1;
+    wave_sync();
+    // each word's record, and its reference word (loads issued for all groups)
+    uint64_t xwv[UNPACK_PG];
+    uint32_t offv[UNPACK_PG];
+#pragma unroll
+    for (int x = 0; x < UNPACK_PG; ++x) {
+      const int64_t gg = g0 + x;
+      xwv[x] = 0;
+      offv[x] = 0;
+      if (gg >= Gt) break;
+      const uint64_t starts = __ballot(s_mark[wv][x][l] == (uint32_t)gg + 1);
+      const int idx = __popcll(starts & le_mask);  // <= 32
+      const uint32_t off = (uint32_t)(l - __shfl(relv[x], idx, WAVE));
+      const uint32_t rw = (uint32_t)__shfl((int)rwv[x], idx, WAVE);
+      offv[x] = off;
+      const int64_t sx = (int64_t)uniform32(gseg[gg]);
+      const Seg& sg = segs[sx];
+      const uint64_t lg = uniform64((uint64_t)gg - gpre[sx]);
+      const bool live = 64 * lg + (uint64_t)l < sg.W;
       const uint64_t* rbody = a.ref + uniform64(sg.rbody / 8);  // the segment's reference records
       if (uniform32((uint32_t)sg.mode) == 1) {
         if (live) {
-          const bool pred = off >= 2 && off < 6 && a.pred_on[k0 + lo];
-          xw = pred ? a.pred_x[4 * (k0 + lo) + (off - 2)] : rbody[rw_i + (uint32_t)off];
+          const uint64_t k = uniform32(gfirst[gg]) + (uint64_t)idx;
+          const bool pred = off >= 2 && off < 6 && a.pred_on[k];
+          xwv[x] = pred ? a.pred_x[4 * k + (off - 2)] : rbody[rw + off];
         }
       } else if (live) {
-        xw = rbody[rw_i + (uint32_t)off];
+        xwv[x] = rbody[rw + off];
       }
+    }
+    // blocks into LDS, residual words, output
+#pragma unroll
+    for (int x = 0; x < UNPACK_PG; ++x) {
+      const int64_t gg = g0 + x;
+      if (gg >= Gt) break;
+      uint64_t* blk = s_blk[wv][x];
+      blk[l] = b0v[x];
+      if (l < BW - WAVE) blk[WAVE + l] = b1v[x];
       wave_sync();
-      const bool bit = (bitmap >> l) & 1;
+      const uint64_t bitmap = uniform64(bmv[x]);
+      const uint32_t size = uniform32(sizev[x]);
       const uint32_t popc = (uint32_t)__popcll(bitmap);
       const uint32_t nib = (popc + 1) / 2;
-      const uint32_t t = (uint32_t)__popcll(bitmap & lanemask_lt(l));
-      uint32_t len = 0;
-      if (bit && !bad) len = (uint32_t)(s_blk[wv][t / 16] >> (4 * (t % 16))) & 15u;
-      bool lbad = bit && (len < 1 || len > 8);
-      const uint32_t sig_incl = wave_incl_scan32(len);
-      const uint32_t end = nib + (uint32_t)__builtin_amdgcn_readlane((int)sig_incl, 63);
-      if (end > size || ((end + 7) & ~7u) != size) bad = true;
-      uint64_t D = 0;
-      if (bit && !bad && !lbad) {
-        // the len bytes at so: two aligned words, shifted together
-        const uint32_t so = nib + sig_incl - len;
-        const uint32_t sh = 8 * (so % 8);
-        uint64_t v = s_blk[wv][so / 8] >> sh;
-        if (sh) v |= s_blk[wv][so / 8 + 1] << (64 - sh);
-        D = len == 8 ? v : (v & ((1ull << (8 * len)) - 1));
-        if ((D >> (8 * (len - 1))) == 0) lbad = true;
+      const bool bit = (bitmap >> l) & 1;
+      const uint32_t t = __builtin_amdgcn_mbcnt_hi((uint32_t)(bitmap >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bitmap, 0u));
+      const uint8_t* b8 = reinterpret_cast<const uint8_t*>(blk);
+      const uint32_t len = bit ? (uint32_t)(b8[t >> 1] >> (4 * (t & 1))) & 15u : 0u;
+      bool bad = bit && (len - 1u > 7u);  // a length outside 1..8
+      const uint32_t incl = wave_incl_scan32(len);
+      const uint32_t end = nib + (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+      const bool gbad = size > BLK_MAX || end > size || ((end + 7) & ~7u) != size;
+      // the len bytes at so: two aligned words, funnel-shifted by bytes.  In
+      // a good group every set word has so + len <= end <= size <= BLK_MAX;
+      // anything else (a bad group, a zero length) reads word 0 instead and
+      // is reported, so both reads stay inside the buffer.
+      const uint32_t so0 = nib + incl - len;
+      const uint32_t so = (gbad || so0 >= (uint32_t)BLK_MAX) ? 0u : so0;
+      const uint32_t wi = so >> 3, sh = 8 * (so & 3);
+      const uint64_t w0 = blk[wi], w1 = blk[wi + 1];
+      const bool hi4 = (so & 4) != 0;
+      const uint32_t c0 = hi4 ? (uint32_t)(w0 >> 32) : (uint32_t)w0;
+      const uint32_t c1 = hi4 ? (uint32_t)w1 : (uint32_t)(w0 >> 32);
+      const uint32_t c2 = hi4 ? (uint32_t)(w1 >> 32) : (uint32_t)w1;
+      uint32_t dlo = funnel32(c1, c0, sh), dhi = funnel32(c2, c1, sh);
+      if (len < 4) dlo &= (1u << (8 * len)) - 1u;
+      dhi = len <= 4 ? 0u : (len < 8 ? dhi & ((1u << (8 * (len - 4))) - 1u) : dhi);
+      const uint64_t D = bit ? ((uint64_t)dhi << 32) | dlo : 0;
+      if (bit && !bad && (D >> (8 * (len - 1))) == 0) bad = true;  // a leading zero byte
+      bool gchk = gbad;
+      if (!gbad) {
+        // padding after `end` (inside the last block word) and an unused high nibble
+        if ((end & 7) && (blk[size / 8 - 1] >> (8 * (end & 7))) != 0) gchk = true;
+        if ((popc & 1) && (b8[popc >> 1] >> 4) != 0) gchk = true;
       }
-      if (!bad) {
-        if (end + (uint32_t)l < size && blk[end + l] != 0) lbad = true;   // padding bytes
-        if (l == 0 && (popc & 1) && (blk[popc / 2] >> 4) != 0) lbad = true;  // unused high nibble
+      const int64_t sx = (int64_t)uniform32(gseg[gg]);
+      const Seg& sg = segs[sx];
+      const uint64_t lg = uniform64((uint64_t)gg - gpre[sx]);
+      if (64 * lg + (uint64_t)l < sg.W) {
+        if (offv[x] < 2 && D != 0) bad = true;
+        uint64_t* ob = a.out + uniform64(sg.cpw + sg.dbase + 64 * lg);
+        ob[l] = D ^ xwv[x];
       }
-      if (live) {
-        if (off < 2 && D != 0) lbad = true;
-        a.out[sg.cpw + d] = D ^ xw;
-      }
-      if (__ballot(lbad) || bad) {
-        if (l == 0) fail(cm.status, ERR_CORRUPT);
-      }
-      wave_sync();
+      anybad = anybad || bad || gchk;
     }
+    wave_sync();
   }
+  if (__ballot(anybad) && l == 0) fail(cm.status, ERR_CORRUPT);
 }
 
 // New records from the encoding into C', and their offsets: a wave takes
@@ -2104,7 +2149,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
     Timed tm(c, "decode_unpack", s);
     UnpackArgs ua{m.cm,  enc,      m.gex,    m.gseg,    m.gfirst, reinterpret_cast<const uint64_t*>(ref),
                   m.mrw, m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(out)};
-    k_dec_unpack<<<grid_for(c, b.G, WAVES * PG_WAVE), BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst);
+    k_dec_unpack<<<grid_for(c, b.G, WAVES * UNPACK_PG), BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst, ua.enc);
   }
   k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
   if (hist_out) {

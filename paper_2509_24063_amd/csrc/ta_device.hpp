@@ -35,7 +35,10 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-__device__ inline int wave_id() { return (int)(threadIdx.x / WAVE); }
+// The wave's index in its block, as a wave-uniform (scalar) value, so that
+// indices derived from it stay in scalar registers and their loads can be
+// scalar loads.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)); }
 
 __device__ inline uint64_t lanemask_le(int l) { return l >= 63 ? ~0ull : ((2ull << l) - 1); }
 __device__ inline uint64_t lanemask_lt(int l) { return l == 0 ? 0ull : (l >= 64 ? ~0ull : ((1ull << l) - 1)); }

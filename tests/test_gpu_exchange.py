@@ -197,6 +197,44 @@ def test_damaged_encodings_match_oracle_status(native):
     ctx.close()
 
 
+def test_damaged_group_blocks_match_oracle_status(native):
+    """Damage confined to the group blocks (lengths, significant bytes,
+    padding, unused nibbles), in records of every residual length: the GPU
+    reports the oracle's status and, when the damage still decodes, its
+    output."""
+    rng = np.random.default_rng(31)
+    r = [rec(u, x=float(rng.random()), words=int(rng.integers(2, 13))) for u in range(1, 500)]
+    c = [list(x) for x in r[7:]]
+    for x in c:
+        for w in range(2, len(x)):
+            if rng.random() < 0.6:
+                x[w] ^= int(rng.integers(1, 1 << int(rng.integers(1, 64))))
+    c += [rec(2000 + u, words=int(rng.integers(2, 9))) for u in range(5)]
+    R, Cm = tam1(r), tam1(c)
+    st, e, _, _, _ = oracle.delta_encode(Cm, R)
+    assert st == 0
+    var = int(np.frombuffer(e[:64].tobytes(), np.uint64)[7])
+    assert var > 512
+    damaged, expect = [], []
+    for _ in range(600):
+        bad = e.copy()
+        bad[e.size - var + int(rng.integers(0, var))] ^= np.uint8(1 << rng.integers(0, 8))
+        damaged.append(bad)
+        expect.append(oracle.delta_decode(bad, R))
+    assert sum(x[0] == oracle.CORRUPT for x in expect) >= 50
+    ctx = native.Context(synth.Schema((4,), (1,)))
+    ref, roff = _upload(native, [R])
+    print("[damage] 600 group-block variants", flush=True)
+    for k, bad in enumerate(damaged):
+        enc, eoff = _upload(native, [bad])
+        dec, doff = ctx.delta_decode(enc, eoff, ref, roff)
+        st = ctx.poll()
+        assert st == expect[k][0], (k, st, expect[k][0])
+        if st == 0:
+            assert np.array_equal(host(dec, host(doff)), expect[k][1])
+    ctx.close()
+
+
 def test_selection_and_serialize_capacity(native):
     cfg = synth.config(1, median=2000.0)
     w = synth.World(cfg)
