@@ -276,9 +276,8 @@ __global__ __launch_bounds__(BLOCK) void k_vv_records(const uint8_t* msgs, const
     const uint32_t n = ld32(m + 8);
     const uint64_t rw = ld64(m + 16);
     uint32_t o;
-    uint64_t hdr;
-    if (!tam1_record(m, n, rw, (uint32_t)(g - (int64_t)rbase[s]), &o, &hdr) || ld64(tam1_records(m, n) + 8 * (uint64_t)o) == 0)
-      fail(status, ERR_INVALID);
+    uint64_t uid, hdr;
+    if (!tam1_record(m, n, rw, (uint32_t)(g - (int64_t)rbase[s]), &o, &uid, &hdr) || uid == 0) fail(status, ERR_INVALID);
   }
 }
 

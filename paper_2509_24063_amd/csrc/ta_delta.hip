@@ -157,6 +157,8 @@ struct Common {
 constexpr int JT = 2048;          // minimum items per counting tile
 constexpr int JT_MAX_TILES = 64;  // counting tiles per segment side at most
 constexpr int JB_TARGET = 1024;
+constexpr int JC_U = 4;           // join count: items per thread and pass
+constexpr int RS_U = 4;           // decoder reference slots: slots per lane and pass
 constexpr int JB_MAX = 8192;      // buckets per segment (LDS histogram)
 constexpr int JCAP = 3072;        // items of one bucket held in LDS
 constexpr int JTAB = 4096;        // LDS hash slots
@@ -311,10 +313,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_insert(Common cm, const uint8_t* 
       const uint64_t rw = isC ? sg.rwc : sg.rwr;
       uint32_t o;
       uint64_t hdr;
-      if (tam1_record(m, n, rw, (uint32_t)i, &o, &hdr)) {
-        uid = ld64(tam1_records(m, n) + 8 * (uint64_t)o);
-        okr = uid != 0;
-      }
+      okr = tam1_record(m, n, rw, (uint32_t)i, &o, &uid, &hdr) && uid != 0;
       if (!okr) {
         fail(cm.status, ERR_INVALID);
       } else {
@@ -427,29 +426,41 @@ __global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a, const Seg* __r
     const uint64_t rw = jt.isC ? g.rwc : g.rwr;
     const uint64_t gbase = jt.isC ? cpre[jt.s] : Ct + rpre[jt.s];
     uint64_t fold = 0;
-    for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += BLOCK) {
-      const uint64_t i = i0 + threadIdx.x;
-      if (i < jt.i1) {
-        uint32_t o;
-        uint64_t hdr, uid = 0;
-        bool ok = tam1_record(msg, n, rw, (uint32_t)i, &o, &hdr);
-        if (ok) {
-          uid = ld64(tam1_records(msg, n) + 8 * (uint64_t)o);
-          ok = uid != 0;
+    bool bad = false;
+    // JC_U items per thread and pass: their records' loads are issued
+    // together (indices past the tile read its first item, unused)
+    for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += (uint64_t)BLOCK * JC_U) {
+      Tam1Loc loc[JC_U];
+      uint64_t uid[JC_U], hdr[JC_U];
+      bool ok[JC_U];
+#pragma unroll
+      for (int u = 0; u < JC_U; ++u) {
+        const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
+        loc[u] = tam1_locate(msg, n, rw, (uint32_t)(i < jt.i1 ? i : jt.i0));
+      }
+#pragma unroll
+      for (int u = 0; u < JC_U; ++u) tam1_words(msg, n, loc[u], &uid[u], &hdr[u]);
+      __builtin_amdgcn_sched_barrier(0);  // keep the checks below every record load
+#pragma unroll
+      for (int u = 0; u < JC_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
+#pragma unroll
+      for (int u = 0; u < JC_U; ++u) {
+        const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
+        if (i >= jt.i1) continue;
+        if (!ok[u]) {
+          bad = true;
+          continue;
         }
-        if (!ok) {
-          fail(cm.status, ERR_INVALID);
-        } else {
-          const uint64_t item = gbase + (i - 0);
-          a.juid[item] = uid;
-          a.jhdr[item] = hdr;
-          if (jt.isC) a.cwords[cpre[jt.s] + i] = (uint32_t)(hdr >> 32);
-          else a.rwords[rpre[jt.s] + i] = (uint32_t)(hdr >> 32);
-          atomicAdd(&s_hist[join_bucket(uid, B)], 1u);
-          if (!jt.isC) fold ^= uid;
-        }
+        const uint64_t item = gbase + i;
+        a.juid[item] = uid[u];
+        a.jhdr[item] = hdr[u];
+        if (jt.isC) a.cwords[cpre[jt.s] + i] = (uint32_t)(hdr[u] >> 32);
+        else a.rwords[rpre[jt.s] + i] = (uint32_t)(hdr[u] >> 32);
+        atomicAdd(&s_hist[join_bucket(uid[u], B)], 1u);
+        if (!jt.isC) fold ^= uid[u];
       }
     }
+    if (bad) fail(cm.status, ERR_INVALID);
     if (!jt.isC) {
       fold = wave_xor(fold);
       if (lane_id() == 0 && fold)
@@ -1219,6 +1230,10 @@ __global__ __launch_bounds__(BLOCK) void k_dec_setup(Common cm, const uint8_t* e
   }
 }
 
+// Every reference slot: its size in words, whether the encoding keeps it
+// (presence bit), and the XOR of the reference uids (compared with the
+// encoding's later).  A wave takes RS_U * 64 consecutive slots per pass, RS_U
+// per lane, and issues all their loads before it stores anything.
 // (segs, rpre: read-only here; as restrict parameters, reads with a
 // wave-uniform segment become scalar loads)
 __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* enc, const uint8_t* ref,
@@ -1227,46 +1242,79 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
                                                       const uint64_t* __restrict__ rpre) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  const int64_t start = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const int64_t rounds = (Rt + stride - 1) / stride;
-  for (int64_t it = 0; it < rounds; ++it) {
-    const int64_t g = start + it * stride;
-    const bool active = g < Rt;
-    uint64_t uid = 0;
-    bool ok = false;
-    const int64_t wbase = g - lane_id();
-    int64_t s = 0;
-    bool one = false;
-    if (wbase < Rt) {
-      const uint64_t last = (uint64_t)(wbase + WAVE - 1 < Rt ? wbase + WAVE - 1 : Rt - 1);
-      s = wave_seg(rpre, cm.nseg, (uint64_t)(active ? g : Rt - 1), (uint64_t)wbase, last);
-      one = __shfl(s, 0, WAVE) == __shfl(s, (int)(last - (uint64_t)wbase), WAVE);
-    }
-    auto slot = [&](int64_t sg_i) {
-      const Seg& sg = segs[sg_i];
-      const uint64_t j = g - rpre[sg_i];
-      uint32_t o;
-      uint64_t hdr = 0;
-      const uint8_t* m = ref + sg.rmsg;
-      if (tam1_record(m, (uint32_t)sg.nr, sg.rwr, (uint32_t)j, &o, &hdr)) {
-        uid = ld64(tam1_records(m, (uint32_t)sg.nr) + 8 * (uint64_t)o);
-        ok = uid != 0;
-      }
-      if (!ok) fail(cm.status, ERR_INVALID);
-      const uint64_t pw = ld64(enc + sg.encm + 64 + 8 * (j / 64));
-      rmatch[g] = (uint8_t)((pw >> (j & 63)) & 1);
-      rwords[g] = (uint32_t)(hdr >> 32);
-    };
+  const int l = lane_id();
+  constexpr int64_t SPAN = (int64_t)WAVE * RS_U;
+  const int64_t nwv = (int64_t)gridDim.x * WAVES;
+  bool bad = false;
+  for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave_id()) * SPAN; base < Rt; base += nwv * SPAN) {
+    const int64_t last = base + SPAN - 1 < Rt ? base + SPAN - 1 : Rt - 1;
+    const int64_t lo = wave_last_le<uint64_t>(rpre, 0, cm.nseg, (uint64_t)base);
+    const int64_t hi = wave_last_le<uint64_t>(rpre, lo, cm.nseg, (uint64_t)last);
+    uint64_t uid[RS_U], hdr[RS_U], pw[RS_U], jv[RS_U];
+    int64_t sv[RS_U];
+    bool ok[RS_U];
+    Tam1Loc loc[RS_U];
+    // slots past the end read the last one (unused); all offsets and
+    // presence words are loaded before any record word
+    const bool one = lo == hi;  // uniform: the whole pass in one segment
     if (one) {
-      const int64_t su = (int64_t)uniform32((uint32_t)s);  // the whole wave in one segment
-      if (active) slot(su);
-    } else if (active) {
-      slot(s);
+      const int64_t su = (int64_t)uniform32((uint32_t)lo);
+      const Seg& sg = segs[su];
+      const uint64_t r0 = rpre[su];
+      const uint8_t* m = ref + sg.rmsg;
+#pragma unroll
+      for (int u = 0; u < RS_U; ++u) {
+        const int64_t g = base + (int64_t)u * WAVE + l;
+        const uint64_t j = (uint64_t)(g <= last ? g : last) - r0;
+        loc[u] = tam1_locate(m, (uint32_t)sg.nr, sg.rwr, (uint32_t)j);
+        pw[u] = ld64(enc + sg.encm + 64 + 8 * (j / 64));
+        jv[u] = j;
+        sv[u] = su;
+      }
+#pragma unroll
+      for (int u = 0; u < RS_U; ++u) tam1_words(m, (uint32_t)sg.nr, loc[u], &uid[u], &hdr[u]);
+      __builtin_amdgcn_sched_barrier(0);  // keep the checks below every record load
+#pragma unroll
+      for (int u = 0; u < RS_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
+    } else {
+#pragma unroll
+      for (int u = 0; u < RS_U; ++u) {
+        const int64_t g = base + (int64_t)u * WAVE + l;
+        const int64_t s = last_le<uint64_t>(rpre, lo, hi + 1, (uint64_t)(g <= last ? g : last));
+        const Seg& sg = segs[s];
+        const uint64_t j = (uint64_t)(g <= last ? g : last) - rpre[s];
+        loc[u] = tam1_locate(ref + sg.rmsg, (uint32_t)sg.nr, sg.rwr, (uint32_t)j);
+        pw[u] = ld64(enc + sg.encm + 64 + 8 * (j / 64));
+        jv[u] = j;
+        sv[u] = s;
+      }
+#pragma unroll
+      for (int u = 0; u < RS_U; ++u) {
+        const Seg& sg = segs[sv[u]];
+        tam1_words(ref + sg.rmsg, (uint32_t)sg.nr, loc[u], &uid[u], &hdr[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < RS_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
     }
-    // XOR of the reference uids, compared with the encoding's later
-    seg_xor(cm.fold, FOLD_SLOTS, s, active && ok, uid);
+    uint64_t f = 0;
+#pragma unroll
+    for (int u = 0; u < RS_U; ++u) {
+      const int64_t g = base + (int64_t)u * WAVE + l;
+      const bool active = g <= last;
+      if (active) {
+        if (!ok[u]) bad = true;
+        rmatch[g] = (uint8_t)((pw[u] >> (jv[u] & 63)) & 1);
+        rwords[g] = (uint32_t)(hdr[u] >> 32);
+      }
+      if (one) {
+        if (active && ok[u]) f ^= uid[u];
+      } else {
+        seg_xor(cm.fold, FOLD_SLOTS, sv[u], active && ok[u], uid[u]);
+      }
+    }
+    if (one) seg_xor(cm.fold, FOLD_SLOTS, lo, true, f);
   }
+  if (bad) fail(cm.status, ERR_INVALID);
 }
 
 struct DMatchIn {
@@ -2120,7 +2168,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                                      clear_first(c, ceil_div(b.R + 1, SCAN_TILE)));
   k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.rpre, m.cm.gpre, m.cm.npre, m.cm.opre, m.cm.ppre, m.cm.hpre},
                                           {1, 3, 6, -1, 4, 2}, {b.R, b.G, b.C, -1, -1, b.H}));
-  k_dec_rslots<<<g, BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre);
+  k_dec_rslots<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre);
   k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
                                                                      m.rscan, lookback(c, 0));
   k_scan<DNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, b.C, m.cscan,
