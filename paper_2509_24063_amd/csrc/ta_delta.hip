@@ -586,6 +586,8 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a, const Seg* __
 // equal; a uid match with another header is undone here (the slot becomes
 // unmatched, the current record new).  Reference slots and their partners
 // run in the same order, so both header reads are close to sequential.
+// Loaded in stages for the scan's rounds together: partners and segments,
+// then segment bounds, sizes and reference headers, then partner headers.
 struct RMatchIn {
   Common cm;
   int32_t* m;
@@ -597,25 +599,57 @@ struct RMatchIn {
     lo = wave_last_le<uint64_t>(cm.rpre, 0, cm.nseg, (uint64_t)first);
     hi = wave_last_le<uint64_t>(cm.rpre, lo, cm.nseg, (uint64_t)last);
   }
-  __device__ uint64_t operator()(int64_t g) const {
-    const int32_t i = m[g];
-    if (i < 0) return 0;
-    const int64_t s = last_le<uint64_t>(cm.rpre, lo, hi + 1, (uint64_t)g);
-    // (after an earlier error the join may not have run: stay inside the segment)
-    if ((uint64_t)i >= cm.seg[s].nc) return 0;
-    const uint64_t ci = cm.cpre[s] + (uint64_t)i;
-    if (jhdr[(uint64_t)cm.meta[0] + (uint64_t)g] != jhdr[ci]) {
-      m[g] = -1;
-      cflag[ci] = 0;
-      return 0;
+  template <int R>
+  __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
+    const int l = lane_id();
+    const uint64_t Ct = (uint64_t)cm.meta[0];
+    int64_t g[R], s[R];
+    int32_t mi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = wbase + r * WAVE + l;
+      g[r] = i < n ? i : n - 1;
+      mi[r] = m[g[r]];
+      s[r] = lo == hi ? lo : last_le<uint64_t>(cm.rpre, lo, hi + 1, (uint64_t)g[r]);
     }
-    return (1ull << PK) | rwords[g];
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t nc[R], cp[R], hr[R];
+    uint32_t rw[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      nc[r] = cm.seg[s[r]].nc;
+      cp[r] = cm.cpre[s[r]];
+      rw[r] = rwords[g[r]];
+      hr[r] = jhdr[Ct + (uint64_t)g[r]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // (after an earlier error the join may not have run: stay inside the segment)
+    bool ok[R];
+    uint64_t hc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ok[r] = mi[r] >= 0 && (uint64_t)mi[r] < nc[r];
+      hc[r] = ok[r] ? jhdr[cp[r] + (uint64_t)mi[r]] : 0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (ok[r] && hc[r] != hr[r]) {
+        m[g[r]] = -1;
+        cflag[cp[r] + (uint64_t)mi[r]] = 0;
+        ok[r] = false;
+      }
+      v[r] = ok[r] && wbase + r * WAVE + l < n ? (1ull << PK) | rw[r] : 0;
+    }
   }
 };
 struct CNewIn {  // count << 34 | words of new current records
   const uint8_t* cflag;
   const uint32_t* cwords;
-  __device__ uint64_t operator()(int64_t g) const { return cflag[g] ? 0 : ((1ull << PK) | cwords[g]); }
+  __device__ uint64_t operator()(int64_t g) const {
+    const uint64_t w = cwords[g];
+    return cflag[g] ? 0 : ((1ull << PK) | w);
+  }
 };
 
 // Per segment layout after matching (one thread per segment); the sizes
@@ -1320,9 +1354,15 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
 struct DMatchIn {
   const uint8_t* rmatch;
   const uint32_t* rwords;
-  __device__ uint64_t operator()(int64_t g) const { return rmatch[g] ? ((1ull << PK) | rwords[g]) : 0; }
+  __device__ uint64_t operator()(int64_t g) const {
+    const uint64_t w = rwords[g];
+    return rmatch[g] ? ((1ull << PK) | w) : 0;
+  }
 };
-struct DNewIn {  // words of new records, from the encodings' size tables
+// Words of new records, from the encodings' size tables, and group block
+// bytes, from their group size tables: segment and its table's offset for
+// the scan's rounds, then the table entries.
+struct DNewIn {
   Common cm;
   const uint8_t* enc;
   int64_t lo = 0, hi = 0;  // segments of the wave's items
@@ -1330,19 +1370,33 @@ struct DNewIn {  // words of new records, from the encodings' size tables
     lo = wave_last_le<uint64_t>(cm.npre, 0, cm.nseg, (uint64_t)first);
     hi = wave_last_le<uint64_t>(cm.npre, lo, cm.nseg, (uint64_t)last);
   }
-  __device__ uint64_t operator()(int64_t r) const {
-    const int64_t s = last_le<uint64_t>(cm.npre, lo, hi + 1, (uint64_t)r);
-    const Seg& g = cm.seg[s];
-    const uint64_t k = r - cm.npre[s];
-    const uint32_t sz = ld32(enc + g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + 4 * k);
-    if (sz < 2) {
-      fail(cm.status, ERR_CORRUPT);
-      return 2;
+  template <int R>
+  __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
+    const int l = lane_id();
+    uint64_t at[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = wbase + r * WAVE + l;
+      const uint64_t x = (uint64_t)(i < n ? i : n - 1);
+      const int64_t s = lo == hi ? lo : last_le<uint64_t>(cm.npre, lo, hi + 1, x);
+      const Seg& g = cm.seg[s];
+      at[r] = g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + 4 * (x - cm.npre[s]);
     }
-    return sz;
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t sz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sz[r] = ld32(enc + at[r]);
+    __builtin_amdgcn_sched_barrier(0);
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      bad = bad || sz[r] < 2;
+      v[r] = wbase + r * WAVE + l >= n ? 0 : (sz[r] < 2 ? 2 : sz[r]);
+    }
+    if (bad) fail(cm.status, ERR_CORRUPT);
   }
 };
-struct DGroupIn {  // group block bytes
+struct DGroupIn {
   Common cm;
   const uint8_t* enc;
   int64_t lo = 0, hi = 0;  // segments of the wave's items
@@ -1350,13 +1404,27 @@ struct DGroupIn {  // group block bytes
     lo = wave_last_le<uint64_t>(cm.gpre, 0, cm.nseg, (uint64_t)first);
     hi = wave_last_le<uint64_t>(cm.gpre, lo, cm.nseg, (uint64_t)last);
   }
-  __device__ uint64_t operator()(int64_t gg) const {
-    const int64_t s = last_le<uint64_t>(cm.gpre, lo, hi + 1, (uint64_t)gg);
-    const Seg& g = cm.seg[s];
-    return 8 * (uint64_t)enc[g.encm + 64 + 8 * g.PG + 8 * g.G + (gg - cm.gpre[s])];
+  template <int R>
+  __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
+    const int l = lane_id();
+    uint64_t at[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = wbase + r * WAVE + l;
+      const uint64_t x = (uint64_t)(i < n ? i : n - 1);
+      const int64_t s = lo == hi ? lo : last_le<uint64_t>(cm.gpre, lo, hi + 1, x);
+      const Seg& g = cm.seg[s];
+      at[r] = g.encm + 64 + 8 * g.PG + 8 * g.G + (x - cm.gpre[s]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint8_t b[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[r] = enc[at[r]];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = wbase + r * WAVE + l >= n ? 0 : 8 * (uint64_t)b[r];
   }
 };
-
 
 // Per segment: matched and new record bases, checks against the header,
 // C' offsets and headers (one thread per segment).
@@ -2080,7 +2148,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     Timed tm(c, "encode_join", s);
     JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag};
     k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre);
-    k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
+    k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
                                                                      lookback(c, 0));
     k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre,
                                                          m.jcnt_pre);
@@ -2090,9 +2158,9 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     k_enc_insert<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.cwords, m.rwords, m.rslot);
     k_enc_match<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.rslot, m.m, m.cflag);
   }
-  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
+  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
                                                                      lookback(c, 1));
-  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, b.C, m.cscan,
+  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, b.C, m.cscan,
                                                                    lookback(c, 2));
   k_enc_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart);
   k_scan_cols<<<4, 1024, 0, s>>>(col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4},
@@ -2121,11 +2189,11 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     const int gp = grid_for(c, b.G, WAVES * PG_WAVE);
     const int gs = grid_for(c, b.G + 1, SCAN_TILE);
     k_enc_gsize<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg);
-    k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, b.G, m.gex, lookback(c, 3));
+    k_scan<GszIn><<<gs, SCAN_BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, b.G, m.gex, lookback(c, 3));
     if (pw) {
-      k_scan<GszIn><<<gs, BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, b.G, m.gex2, lookback(c, 4));
+      k_scan<GszIn><<<gs, SCAN_BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, b.G, m.gex2, lookback(c, 4));
       k_choose_mode<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, m.gex2);
-      k_scan<GChosenIn><<<gs, BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, b.G, m.gex,
+      k_scan<GChosenIn><<<gs, SCAN_BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, b.G, m.gex,
                                              lookback(c, 5));
     }
     k_enc_place<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg, m.gex);
@@ -2169,11 +2237,11 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.rpre, m.cm.gpre, m.cm.npre, m.cm.opre, m.cm.ppre, m.cm.hpre},
                                           {1, 3, 6, -1, 4, 2}, {b.R, b.G, b.C, -1, -1, b.H}));
   k_dec_rslots<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre);
-  k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
+  k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
                                                                      m.rscan, lookback(c, 0));
-  k_scan<DNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, b.C, m.cscan,
+  k_scan<DNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, b.C, m.cscan,
                                                                    lookback(c, 1));
-  k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, b.G, m.gex,
+  k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, b.G, m.gex,
                                                                      lookback(c, 2));
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
   k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg, m.gfirst,

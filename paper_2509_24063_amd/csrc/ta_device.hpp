@@ -66,6 +66,27 @@ __device__ inline uint32_t wave_incl_scan32(uint32_t v) {
   return (uint32_t)x;
 }
 
+// The same scan on 64-bit values: each DPP move carries both halves from the
+// same source lane, then one 64-bit add.  All lanes must call it.
+__device__ inline uint64_t wave_incl_scan64(uint64_t v) {
+  auto step = [&](auto dpp) {
+    const uint32_t lo = dpp((uint32_t)v), hi = dpp((uint32_t)(v >> 32));
+    v += ((uint64_t)hi << 32) | lo;
+  };
+  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true); });
+  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true); });
+  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true); });
+  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true); });
+  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); });
+  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); });
+  return v;
+}
+__device__ inline uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ inline uint64_t wave_sum(uint64_t v) {
 #pragma unroll
   for (int d = WAVE / 2; d; d >>= 1) v += __shfl_xor(v, d, WAVE);
@@ -131,15 +152,15 @@ struct LookBack {
 };
 
 __device__ inline void lb_clear_next(const LookBack& lb) {
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < lb.clear_n; i += stride) lb.clear_flags[i] = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < lb.clear_n; i += stride) lb.clear_flags[i] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0 && lb.clear_ticket) *lb.clear_ticket = 0;
 }
 
 __device__ inline uint32_t lb_take_ticket(const LookBack& lb, uint32_t* s_ticket) {
   if (threadIdx.x == 0) *s_ticket = atomicAdd(lb.ticket, 1u);
   __syncthreads();
-  const uint32_t t = *s_ticket;
+  const uint32_t t = uniform32(*s_ticket);  // the same in every lane: a scalar value
   __syncthreads();
   return t;
 }
@@ -183,27 +204,43 @@ __device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t
 // Device-wide exclusive scan of n values given by a functor (value(i) for
 // i < n, uint64_t).  out[i] = sum of values before i, out[n] = total.  n is
 // read from device memory so the launch needs only a host bound.  A tile is
-// 4 waves x SCAN_ROUNDS rounds of 64 consecutive items: every load and store
+// SCAN_WAVES waves x SCAN_ROUNDS rounds of 64 consecutive items: every load and store
 // instruction of a wave touches 64 consecutive items, each round is one wave
 // scan, and one look-back per tile joins the tiles.
 #ifndef TA_SCAN_ROUNDS
 #define TA_SCAN_ROUNDS 8
 #endif
+#ifndef TA_SCAN_BLOCK
+#define TA_SCAN_BLOCK 512
+#endif
 constexpr int SCAN_ROUNDS = TA_SCAN_ROUNDS;
-constexpr int SCAN_TILE = BLOCK * SCAN_ROUNDS;
+constexpr int SCAN_BLOCK = TA_SCAN_BLOCK;  // threads of a scan block (a tile is SCAN_BLOCK x SCAN_ROUNDS items)
+constexpr int SCAN_WAVES = SCAN_BLOCK / WAVE;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ROUNDS;
 
-// A functor may define wave_begin(first, last): called by all 64 lanes of a
-// wave before it reads items first..last (consecutive), e.g. to bound a
-// segment search once per wave instead of once per item.
+// A functor gives the value of item i with operator()(i).  It may define
+// wave_begin(first, last), called by all 64 lanes of a wave before it reads
+// items first..last (consecutive), e.g. to bound a segment search once per
+// wave instead of once per item.  A functor whose value takes dependent
+// loads may instead define values(wbase, n, v): the values of the wave's
+// SCAN_ROUNDS items wbase + 64 r + lane (0 for items >= n), loaded in stages
+// (every item's first loads, then every item's second loads, ...), so that
+// a wave waits once per stage rather than once per stage and item.  Lanes
+// past n may call operator() with index n - 1 (side effects of a functor
+// must be idempotent), so that no load sits behind a branch.
 template <class T, class = void>
 struct has_wave_begin : std::false_type {};
 template <class T>
 struct has_wave_begin<T, std::void_t<decltype(&T::wave_begin)>> : std::true_type {};
+template <class T, class = void>
+struct has_values : std::false_type {};
+template <class T>
+struct has_values<T, std::void_t<decltype(&T::template values<SCAN_ROUNDS>)>> : std::true_type {};
 
 template <class In>
-__global__ __launch_bounds__(BLOCK) void k_scan(In in, const int64_t* n_dev, int64_t n_cap, uint64_t* out,
-                                                LookBack lb) {
-  __shared__ uint64_t s_wave[WAVES];
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan(In in, const int64_t* n_dev, int64_t n_cap, uint64_t* out,
+                                                     LookBack lb) {
+  __shared__ uint64_t s_wave[SCAN_WAVES];
   __shared__ uint32_t s_ticket;
   __shared__ uint64_t s_prefix;
   lb_clear_next(lb);
@@ -230,21 +267,34 @@ __global__ __launch_bounds__(BLOCK) void k_scan(In in, const int64_t* n_dev, int
       const int64_t last = wbase + WAVE * SCAN_ROUNDS - 1 < n ? wbase + WAVE * SCAN_ROUNDS - 1 : n - 1;
       fn.wave_begin(wbase < n ? wbase : n - 1, last);
     }
+    uint64_t v[SCAN_ROUNDS];
+    if constexpr (has_values<In>::value) {
+      fn.template values<SCAN_ROUNDS>(wbase, n, v);
+    } else if (wbase + WAVE * SCAN_ROUNDS <= n) {  // uniform: every item of the wave exists
+#pragma unroll
+      for (int r = 0; r < SCAN_ROUNDS; ++r) v[r] = fn(wbase + r * WAVE + l);
+    } else {
+#pragma unroll
+      for (int r = 0; r < SCAN_ROUNDS; ++r) {
+        const int64_t i = wbase + r * WAVE + l;
+        const uint64_t x = fn(i < n ? i : n - 1);
+        v[r] = i < n ? x : 0;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // every item's loads before the first scan
     uint64_t ex[SCAN_ROUNDS];
     uint64_t carry = 0;
 #pragma unroll
     for (int r = 0; r < SCAN_ROUNDS; ++r) {
-      const int64_t i = wbase + r * WAVE + l;
-      const uint64_t v = i < n ? fn(i) : 0;
-      const uint64_t incl = wave_incl_scan(v);
-      ex[r] = carry + incl - v;
-      carry += __shfl(incl, WAVE - 1, WAVE);
+      const uint64_t incl = wave_incl_scan64(v[r]);
+      ex[r] = carry + incl - v[r];
+      carry += readlane64(incl, WAVE - 1);
     }
     if (l == 0) s_wave[wv] = carry;
     __syncthreads();
     uint64_t woff = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < WAVES; ++i) {
+    for (int i = 0; i < SCAN_WAVES; ++i) {
       woff += (i < wv) ? s_wave[i] : 0;
       tot += s_wave[i];
     }

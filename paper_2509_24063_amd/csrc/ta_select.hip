@@ -312,7 +312,7 @@ extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, c
     else
       k_sel_count<6><<<g, BLOCK, 0, s>>>(ag->f64, ag->f64_stride, part_off, boxes, w, P, dt, sc);
   }
-  k_scan<CntIn><<<grid_for(c, cnt_cap + 1, SCAN_TILE), BLOCK, 0, s>>>(CntIn{sc.cnt}, sc.meta + 1, cnt_cap, sc.cnt_pre,
+  k_scan<CntIn><<<grid_for(c, cnt_cap + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CntIn{sc.cnt}, sc.meta + 1, cnt_cap, sc.cnt_pre,
                                                                       lookback(c, 0));
   {
     Timed tm(c, "select_scatter", s);

@@ -41,6 +41,10 @@ __global__ __launch_bounds__(BLOCK) void k_ser_begin(const int64_t* seg_off, int
     if (seg_off[s + 1] < seg_off[s]) fail(status, ERR_INVALID);
 }
 
+// Words of each selected record: 2 + fields + attribute pairs + behaviour
+// words, from the agent's class and behaviour range.  Loaded in stages (all
+// indices, then all agents' class and behaviour offsets, then the class
+// tables) for the scan's rounds together.
 struct WordsIn {
   const int32_t* idx;
   const uint16_t* cls;
@@ -50,19 +54,40 @@ struct WordsIn {
   uint32_t ncls;
   int64_t n_agents;
   uint32_t* status;
-  __device__ uint64_t operator()(int64_t r) const {
-    const int64_t a = idx[r];
-    if (a < 0 || a >= n_agents) {
-      fail(status, ERR_INVALID);
-      return 2;
+  template <int R>
+  __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
+    const int l = lane_id();
+    int64_t a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = wbase + r * WAVE + l;
+      a[r] = idx[i < n ? i : n - 1];
     }
-    const uint32_t c = cls[a];
-    const int64_t b0 = beh_off[a], b1 = beh_off[a + 1];
-    if (c >= ncls || b1 < b0 || ((b1 - b0) & 7) || (b0 & 7)) {
-      fail(status, ERR_INVALID);
-      return 2;
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t c[R];
+    int64_t b0[R], b1[R];
+    bool ok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ok[r] = a[r] >= 0 && a[r] < n_agents;
+      c[r] = 0;
+      b0[r] = b1[r] = 0;
+      if (ok[r]) {
+        c[r] = cls[a[r]];
+        b0[r] = beh_off[a[r]];
+        b1[r] = beh_off[a[r] + 1];
+      }
     }
-    return 2 + nf[c] + (ni[c] + 1) / 2 + (uint64_t)(b1 - b0) / 8;
+    __builtin_amdgcn_sched_barrier(0);
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ok[r] = ok[r] && c[r] < ncls && b1[r] >= b0[r] && !((b1[r] - b0[r]) & 7) && !(b0[r] & 7);
+      bad = bad || !ok[r];
+      v[r] = ok[r] ? 2 + nf[c[r]] + (ni[c[r]] + 1) / 2 + (uint64_t)(b1[r] - b0[r]) / 8 : 2;
+      if (wbase + r * WAVE + l >= n) v[r] = 0;
+    }
+    if (bad) fail(status, ERR_INVALID);
   }
 };
 
@@ -223,7 +248,7 @@ extern "C" ta_status ta_serialize(ta_ctx* c, const ta_agents* ag, const int32_t*
   k_ser_begin<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, idx_cap, sc, clear_first(c, ceil_div(idx_cap + 1, SCAN_TILE)),
                                   c->d_status);
   WordsIn win{idx, ag->cls, ag->beh_off, c->d_nf, c->d_ni, c->n_classes, ag->n, c->d_status};
-  k_scan<WordsIn><<<grid_for(c, idx_cap + 1, SCAN_TILE), BLOCK, 0, s>>>(win, sc.meta, idx_cap, sc.wpre, lookback(c, 0));
+  k_scan<WordsIn><<<grid_for(c, idx_cap + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(win, sc.meta, idx_cap, sc.wpre, lookback(c, 0));
   k_ser_sizes<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, sc, c->d_status);
   {
     ColScan cs{};
