@@ -22,7 +22,11 @@ using namespace ta;
 
 namespace {
 
-constexpr int SEL_IPT = 8;
+#ifndef TA_SEL_IPT
+#define TA_SEL_IPT 8
+#endif
+constexpr int SEL_IPT = TA_SEL_IPT;  // agents per thread and tile
+static_assert(BLOCK * SEL_IPT < 4096, "a tile's count per direction must fit a 12-bit field");
 constexpr int SEL_TILE = BLOCK * SEL_IPT;
 
 struct DirTable {
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
     // block exclusive scan of the packed words
     uint64_t incl[NW];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) incl[j] = wave_incl_scan(packed[j]);
+    for (int j = 0; j < NW; ++j) incl[j] = wave_incl_scan64(packed[j]);
     if (lane_id() == WAVE - 1) {
 #pragma unroll
       for (int j = 0; j < NW; ++j) s_w[wave_id()][j] = incl[j];

@@ -147,6 +147,7 @@ struct PackArgs {
 };
 
 constexpr int PACK_CAP = 1024;  // record words one wave stages in LDS
+constexpr int PACK_CHUNK = 8;   // payload words a lane gathers at a time
 
 // One lane per record: it gathers the agent's fields and writes its offset
 // table entry.  When the wave's 64 records belong to one message and fit in
@@ -173,30 +174,62 @@ __global__ __launch_bounds__(BLOCK) void k_ser_pack(PackArgs a, SerScratch sc) {
     int32_t ag = 0;
     uint32_t c = 0, F = 0, I = 0, IW = 0;
     if (r < R) {
+      // everything read per agent and per message, before the first store
       ag = a.idx[r];
       c = a.cls[ag];
-      F = a.nf[c];
-      I = a.ni[c];
-      IW = (I + 1) / 2;
+      const uint64_t uid = a.uid[ag], nb = a.nb[ag];
+      const int64_t boff = a.beh_off[ag];
       const int64_t first = a.seg_off[s];
       const uint64_t n = (uint64_t)(a.seg_off[s + 1] - first);
       const uint64_t wr = sc.wpre[r], ws = sc.wpre[first];
       words = sc.wpre[r + 1] - wr;
       uint8_t* m = a.out + a.msg_off[s];
+      F = a.nf[c];
+      I = a.ni[c];
+      IW = (I + 1) / 2;
       *reinterpret_cast<uint32_t*>(m + 32 + 4 * (r - first)) = (uint32_t)(wr - ws);
       rel = wr - w0;
       dst = staged ? buf + rel : reinterpret_cast<uint64_t*>(m + 32 + 8 * ((n + 1) / 2) + 8 * (wr - ws));
-      dst[0] = a.uid[ag];
-      dst[1] = (uint64_t)c | ((uint64_t)a.nb[ag] << 16) | (words << 32);
-      for (uint32_t k = 0; k < F; ++k) dst[2 + k] = __double_as_longlong(a.f64[(int64_t)k * a.fstride + ag]);
-      for (uint32_t j = 0; j < IW; ++j) {
-        const uint32_t lo32 = (uint32_t)a.i32[(int64_t)(2 * j) * a.istride + ag];
-        const uint32_t hi32 = (2 * j + 1 < I) ? (uint32_t)a.i32[(int64_t)(2 * j + 1) * a.istride + ag] : 0u;
-        dst[2 + F + j] = (uint64_t)lo32 | ((uint64_t)hi32 << 32);
+      dst[0] = uid;
+      dst[1] = (uint64_t)c | (nb << 16) | (words << 32);
+      // payload: F fields, IW attribute pairs, then behaviour words.  The
+      // 64-bit words (fields and behaviour words) are gathered PACK_CHUNK at a
+      // time, then the attribute pairs; every load of a chunk is issued
+      // before its stores and takes its address by selection, not behind a
+      // branch (an unused one reads the agent's uid instead).
+      const uint64_t* bsrc = reinterpret_cast<const uint64_t*>(a.beh + boff);
+      const uint64_t* dummy = a.uid + ag;
+      const uint32_t Q = (uint32_t)(words - 2 - IW);  // fields + behaviour words
+      for (uint32_t q0 = 0; q0 < Q; q0 += PACK_CHUNK) {
+        uint64_t t[PACK_CHUNK];
+#pragma unroll
+        for (int j = 0; j < PACK_CHUNK; ++j) {
+          const uint32_t q = q0 + j;
+          const uint64_t* src = q < F ? reinterpret_cast<const uint64_t*>(a.f64 + (int64_t)q * a.fstride + ag)
+                                      : (q < Q ? bsrc + (q - F) : dummy);
+          t[j] = *src;
+        }
+#pragma unroll
+        for (int j = 0; j < PACK_CHUNK; ++j) {
+          const uint32_t q = q0 + j;
+          if (q < Q) dst[q < F ? 2 + q : 2 + IW + q] = t[j];
+        }
       }
-      const uint64_t* bsrc = reinterpret_cast<const uint64_t*>(a.beh + a.beh_off[ag]);
-      const uint64_t nbw = words - 2 - F - IW;
-      for (uint64_t k = 0; k < nbw; ++k) dst[2 + F + IW + k] = bsrc[k];
+      for (uint32_t j0 = 0; j0 < IW; j0 += PACK_CHUNK / 2) {
+        uint32_t lo[PACK_CHUNK / 2], hi[PACK_CHUNK / 2];
+#pragma unroll
+        for (int j = 0; j < PACK_CHUNK / 2; ++j) {
+          const uint32_t q = 2 * (j0 + j);
+          const uint32_t* d32 = reinterpret_cast<const uint32_t*>(dummy);
+          lo[j] = *(q < I ? reinterpret_cast<const uint32_t*>(a.i32 + (int64_t)q * a.istride + ag) : d32);
+          hi[j] = *(q + 1 < I ? reinterpret_cast<const uint32_t*>(a.i32 + (int64_t)(q + 1) * a.istride + ag) : d32);
+        }
+#pragma unroll
+        for (int j = 0; j < PACK_CHUNK / 2; ++j) {
+          const uint32_t q = 2 * (j0 + j);
+          if (j0 + j < IW) dst[2 + F + j0 + j] = (uint64_t)lo[j] | ((uint64_t)(q + 1 < I ? hi[j] : 0u) << 32);
+        }
+      }
     }
     if (staged) {
       wave_sync();
