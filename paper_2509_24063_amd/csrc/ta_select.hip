@@ -120,14 +120,24 @@ __global__ __launch_bounds__(BLOCK) void k_sel_count(const double* f64, int64_t 
     uint32_t cnt[NDIRS];
 #pragma unroll
     for (int d = 0; d < NDIRS; ++d) cnt[d] = 0;
-#pragma unroll 2
+    // every coordinate of the tile loaded before the first code (agents past
+    // the tile read its last agent, unused)
+    double x[SEL_IPT], y[SEL_IPT], z[SEL_IPT];
+#pragma unroll
+    for (int k = 0; k < SEL_IPT; ++k) {
+      const int64_t i = ti.a0 + (int64_t)k * BLOCK + threadIdx.x;
+      const int64_t ic = i < ti.a1 ? i : ti.a1 - 1;
+      x[k] = f64[ic];
+      y[k] = f64[stride + ic];
+      z[k] = f64[2 * stride + ic];
+    }
+#pragma unroll
     for (int k = 0; k < SEL_IPT; ++k) {
       const int64_t i = ti.a0 + (int64_t)k * BLOCK + threadIdx.x;
       uint32_t code = 0;
       if (i < ti.a1) {
-        const double x = f64[i], y = f64[stride + i], z = f64[2 * stride + i];
-        code = (uint32_t)(x < tlo0) | ((uint32_t)(x >= thi0) << 1) | ((uint32_t)(y < tlo1) << 2) |
-               ((uint32_t)(y >= thi1) << 3) | ((uint32_t)(z < tlo2) << 4) | ((uint32_t)(z >= thi2) << 5);
+        code = (uint32_t)(x[k] < tlo0) | ((uint32_t)(x[k] >= thi0) << 1) | ((uint32_t)(y[k] < tlo1) << 2) |
+               ((uint32_t)(y[k] >= thi1) << 3) | ((uint32_t)(z[k] < tlo2) << 4) | ((uint32_t)(z[k] >= thi2) << 5);
         sc.code[i] = (uint8_t)code;
       }
       if (__ballot(code != 0) == 0) continue;
