@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["single", "batched"], default="single")
     ap.add_argument("--agents", type=float, default=None, help="agents (single) or median per partition (batched)")
-    ap.add_argument("--roofline-kernels", default="decode_unpack,encode_resid",
+    ap.add_argument("--roofline-kernels", default="decode_unpack,encode_groups",
                     help="kernel families timed with HIP events; the one with the largest time is `roofline`")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -365,7 +365,11 @@ def main():
     sd_gbps = (acc["ser"] + acc["enc"]) / (acc["sd_ms"] / 1000.0) / 1e9
     # algorithmic bytes of the measured kernels over the timed steps
     per_kernel = {
-        # read C and R words of matched records and their directory entries, write C' words and the residual
+        # plain mode: read C and R words of matched records and their starts and C/R words, write C' words,
+        # the group blocks, bitmaps, sizes and offsets; read the group-to-segment and first-record maps
+        "encode_groups": 24 * acc["W"] + 24 * acc["match"] + acc["var"] + 25 * acc["groups"],
+        # learned mode: read C and R words of matched records and their directory entries, write C' words and
+        # the residual
         "encode_resid": 32 * acc["W"] + 40 * acc["match"],
         # read the residual, write the group blocks, bitmaps, sizes, offsets
         "encode_pack": 8 * acc["W"] + acc["var"] + 17 * acc["groups"],

@@ -738,7 +738,8 @@ __device__ inline void map_groups(const Common& cm, int64_t s, uint64_t q0, uint
 
 __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
                                                     const int32_t* m, const uint64_t* rscan, const uint32_t* rwords,
-                                                    MDir* mdir, uint64_t* mstart, uint8_t* newref, uint32_t* gseg) {
+                                                    MDir* mdir, uint64_t* mstart, uint8_t* newref, uint32_t* gseg,
+                                                    uint32_t* gfirst) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
@@ -761,7 +762,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
     mdir[k] = e;
     mstart[k] = d;
     *reinterpret_cast<uint32_t*>(newref + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
-    map_groups(cm, s, d - sg.dbase, rwords[g], gseg);
+    map_groups(cm, s, d - sg.dbase, rwords[g], gseg, gfirst, k);
   }
 }
 
@@ -1027,6 +1028,177 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a, const Seg* __re
       }
       wave_sync();
     }
+  }
+}
+
+// Plain mode, residual and packing in one pass.  A wave takes EG_R
+// consecutive 64-word groups; for each, the matched records overlapping it
+// (at most 33, one per lane, lane 0 holding the one with the group's first
+// word) give every word's C and R words: C goes to C', D = C xor R stays in
+// registers with its block size.  Tiles of EG_TILE groups (one block) are
+// handed out in order and join a decoupled look-back over their block
+// bytes, which gives every group's block offset; then each group's block is
+// built in LDS and written in place.  The dense residual never goes to
+// memory.
+#ifndef TA_EG_R
+#define TA_EG_R 8
+#endif
+#ifndef TA_EG_BLOCK
+#define TA_EG_BLOCK 512
+#endif
+constexpr int EG_R = TA_EG_R;                 // groups per wave and tile
+constexpr int EG_BLOCK = TA_EG_BLOCK;         // threads per block
+constexpr int EG_WAVES = EG_BLOCK / WAVE;
+constexpr int EG_TILE = EG_WAVES * EG_R;      // groups per tile
+
+struct GroupArgs {
+  Common cm;
+  const uint64_t* cur;     // (words)
+  const uint64_t* ref;     // (words)
+  const MDir* mdir;        // [matched] C and R word of every matched record
+  const uint64_t* mstart;  // [matched+1] residual start of every matched record
+  uint64_t* newref;        // C' (words)
+  uint8_t* enc;
+  int64_t enc_cap;
+  uint64_t* bm;   // [groups] word bitmaps
+  uint8_t* gsz;   // [groups] block sizes / 8
+  uint64_t* gex;  // [groups+1] exclusive prefix of block bytes (gex[groups] = total)
+};
+
+// (segs, gpre, gseg, gfirst: read-only here; as restrict parameters their
+// uniform reads become scalar loads)
+__global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg* __restrict__ segs,
+                                                         const uint64_t* __restrict__ gpre,
+                                                         const uint32_t* __restrict__ gseg,
+                                                         const uint32_t* __restrict__ gfirst, LookBack lb) {
+  constexpr int BW = BLK_MAX / 8 + 1;
+  __shared__ uint64_t s_blk[EG_WAVES][BW];
+  __shared__ uint64_t s_wave[EG_WAVES];
+  __shared__ uint32_t s_ticket;
+  __shared__ uint64_t s_prefix;
+  lb_clear_next(lb);
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t Gt = cm.meta[3], M = cm.meta[5];
+  if (Gt <= 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.gex[0] = 0;
+    return;
+  }
+  const int64_t ntiles = (Gt + EG_TILE - 1) / EG_TILE;
+  // blocks beyond the tile count leave before taking a ticket
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const int l = lane_id(), wv = wave_id();
+  const uint64_t le_mask = lanemask_le(l);
+  for (;;) {
+    const uint32_t t = lb_take_ticket(lb, &s_ticket);
+    if ((int64_t)t >= ntiles) break;
+    const int64_t g0 = (int64_t)t * EG_TILE + (int64_t)wv * EG_R;
+    // The wave's groups in steps, each issuing its loads for every group
+    // before any is used: record tables, then C and R words.  Groups past the
+    // end work on the last group (clamped: no branch around loads) and store
+    // nothing.
+    int64_t gc[EG_R];
+    bool gv[EG_R], has[EG_R];
+    uint64_t mst[EG_R], cwd[EG_R], rwd[EG_R];
+#pragma unroll
+    for (int x = 0; x < EG_R; ++x) {
+      gv[x] = g0 + x < Gt;
+      gc[x] = gv[x] ? g0 + x : Gt - 1;
+      // lane i <= 32: start, C word and R word of record k0 + i (a group
+      // implies a matched record, so M >= 1 and the clamped index is valid)
+      const uint64_t k0 = uniform32(gfirst[gc[x]]);
+      has[x] = l <= 32 && k0 + l < (uint64_t)M;
+      const uint64_t kk = has[x] ? k0 + l : (uint64_t)M - 1;
+      mst[x] = a.mstart[kk];
+      cwd[x] = a.mdir[kk].cword;
+      rwd[x] = a.mdir[kk].rword;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t cv[EG_R], xv[EG_R];
+    bool live[EG_R];
+#pragma unroll
+    for (int x = 0; x < EG_R; ++x) {
+      const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
+      const Seg& sg = segs[sx];
+      const uint64_t lg = uniform64((uint64_t)gc[x] - gpre[sx]);
+      const uint64_t g0w = uniform64(sg.dbase + 64 * lg);  // the group's first residual position
+      // start relative to the group (clamped to [-2^30, 64]), words relative
+      // to the segment's record areas
+      const int64_t r = (int64_t)mst[x] - (int64_t)g0w;
+      const int rel = !has[x] ? 64 : (r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r));
+      const uint32_t cw = (uint32_t)(cwd[x] - sg.cbody / 8), rw = (uint32_t)(rwd[x] - sg.rbody / 8);
+      // records starting inside the group (lanes 1..32), one bit each
+      const uint64_t starts = wave_or_all64(l >= 1 && rel >= 1 && rel < WAVE ? 1ull << rel : 0ull);
+      const int idx = __popcll(starts & le_mask);  // <= 32
+      const uint32_t off = (uint32_t)(l - __shfl(rel, idx, WAVE));
+      const uint32_t cwi = (uint32_t)__shfl((int)cw, idx, WAVE), rwi = (uint32_t)__shfl((int)rw, idx, WAVE);
+      live[x] = gv[x] && 64 * lg + (uint64_t)l < sg.W;
+      // (a word that is not live reads word 0 of lane 0's record, the one
+      // holding the group's first word: in the segment, always valid)
+      const uint32_t cw0 = (uint32_t)__builtin_amdgcn_readlane((int)cw, 0);
+      const uint32_t rw0 = (uint32_t)__builtin_amdgcn_readlane((int)rw, 0);
+      cv[x] = a.cur[uniform64(sg.cbody / 8) + (live[x] ? cwi + off : cw0)];
+      xv[x] = a.ref[uniform64(sg.rbody / 8) + (live[x] ? rwi + off : rw0)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // C' words, residual words and block sizes
+    uint64_t D[EG_R];
+    uint32_t size[EG_R];
+    uint64_t wsum = 0;
+#pragma unroll
+    for (int x = 0; x < EG_R; ++x) {
+      D[x] = live[x] ? cv[x] ^ xv[x] : 0;
+      const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
+      const Seg& sg = segs[sx];
+      if (live[x]) a.newref[sg.cpw + sg.dbase + 64 * ((uint64_t)gc[x] - gpre[sx]) + (uint64_t)l] = cv[x];
+      const uint64_t bmw = __ballot(D[x] != 0);
+      const uint32_t len = D[x] ? (uint32_t)(8 - (__clzll((long long)D[x]) >> 3)) : 0u;
+      const uint32_t sig = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan32(len), 63);
+      size[x] = gv[x] ? ((((uint32_t)__popcll(bmw) + 1) / 2 + sig + 7) & ~7u) : 0u;
+      if (gv[x] && l == 0) {
+        a.bm[gc[x]] = bmw;
+        a.gsz[gc[x]] = (uint8_t)(size[x] / 8);
+      }
+      wsum += size[x];
+    }
+    // the tile's block bytes: waves, then the look-back over earlier tiles
+    if (l == 0) s_wave[wv] = wsum;
+    __syncthreads();
+    uint64_t woff = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < EG_WAVES; ++i) {
+      woff += (i < wv) ? s_wave[i] : 0;
+      tot += s_wave[i];
+    }
+    if (threadIdx.x < WAVE) {
+      const uint64_t e = lb_exclusive(lb, t, tot);
+      if (threadIdx.x == 0) s_prefix = e;
+    }
+    __syncthreads();
+    // blocks: built in the wave's LDS buffer one at a time, written in place
+    uint64_t pos = s_prefix + woff;  // block bytes before this wave's first group
+#pragma unroll
+    for (int x = 0; x < EG_R; ++x) {
+      if (!gv[x]) break;
+      const int64_t gg = gc[x];
+      if (l == 0) a.gex[gg] = pos;
+      if (size[x]) {
+        const Seg& sg = segs[(int64_t)uniform32(gseg[gg])];
+        const uint64_t at = uniform64(sg.fixed_excl + sg.fixed + pos);
+        uint64_t bmw;
+        build_block(D[x], s_blk[wv], &bmw);
+        if (at + size[x] > (uint64_t)a.enc_cap) {
+          if (l == 0) fail(cm.status, ERR_CAPACITY);
+        } else {
+          uint64_t* dst = reinterpret_cast<uint64_t*>(a.enc + at);
+          for (uint32_t w = l; w < size[x] / 8; w += WAVE) dst[w] = s_blk[wv][w];
+        }
+        wave_sync();  // the buffer is rebuilt for the next group
+      }
+      pos += size[x];
+    }
+    if ((int64_t)t == ntiles - 1 && threadIdx.x == 0) a.gex[Gt] = s_prefix + tot;
+    __syncthreads();
   }
 }
 
@@ -2043,7 +2215,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.gfirst = ar.take<uint32_t>(b.G);
   m.mrw = ar.take<uint32_t>(b.R);
   m.mstart = ar.take<uint64_t>(b.R + 1);
-  m.D = ar.take<uint64_t>(b.W);
+  m.D = learned ? ar.take<uint64_t>(b.W) : nullptr;
   m.D2 = learned ? ar.take<uint64_t>(b.W) : nullptr;
   m.gsz2 = learned ? ar.take<uint8_t>(b.G) : nullptr;
   m.gex2 = learned ? ar.take<uint64_t>(b.G + 1) : nullptr;
@@ -2096,7 +2268,8 @@ size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t re
   Arena ar{nullptr, 0, 0};
   const Bounds b = enc_bounds(nseg, cur_len, ref_len, rec_cap);
   carve(ar, nseg, b, learned);
-  *tiles = ceil_div(std::max(std::max(std::max(b.C, b.R), b.E), b.G) + 1, SCAN_TILE) + 2;
+  *tiles = std::max(ceil_div(std::max(std::max(std::max(b.C, b.R), b.E), b.G) + 1, SCAN_TILE),
+                    ceil_div(b.G, EG_TILE)) + 2;
   return ar.used + 256;
 }
 size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t out_cap, int64_t rec_cap,
@@ -2166,7 +2339,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   k_scan_cols<<<4, 1024, 0, s>>>(col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4},
                                           {b.G, -1, -1, -1}));
   k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
-  k_enc_mdir<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg);
+  k_enc_mdir<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg,
+                                 m.gfirst);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
     Timed tm(c, "predict", s);
@@ -2177,13 +2351,19 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                    c->tap_tgt, c->tap_cap, c->tap_count};
     k_predict<<<grid_for(c, b.R, 16 * WAVES), BLOCK, 0, s>>>(pa);
   }
-  {
-    Timed tm(c, "encode_resid", s);
-    ResidArgs ra{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir,
-                 m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(newref), m.D, m.D2};
-    k_enc_resid<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
-  }
-  {
+  if (!pw) {
+    Timed tm(c, "encode_groups", s);
+    GroupArgs ga{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir,
+                 m.mstart, reinterpret_cast<uint64_t*>(newref), enc, enc_cap, m.bm, m.gsz, m.gex};
+    k_enc_groups<<<grid_for(c, b.G, EG_TILE), EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst,
+                                                                 lookback(c, 3));
+  } else {
+    {
+      Timed tm(c, "encode_resid", s);
+      ResidArgs ra{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir,
+                   m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(newref), m.D, m.D2};
+      k_enc_resid<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
+    }
     Timed tm(c, "encode_pack", s);
     PackArgs pa{m.cm, m.D, enc, enc_cap, m.bm, m.gsz, m.gex, m.gseg, m.D2, m.gsz2};
     const int gp = grid_for(c, b.G, WAVES * PG_WAVE);
