@@ -770,6 +770,26 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
 // Every lane ORs its nibble and its significant bytes into the 64-bit words
 // they fall in (one or two words: no byte stores).  Returns the block size in
 // bytes.
+// The same block from values the caller already has: the word's length in
+// bytes, the inclusive scan of the lengths over the wave, the group's bitmap
+// and block size.
+__device__ inline void build_block_from(uint64_t D, uint32_t len, uint32_t sig_incl, uint64_t bm, uint32_t size,
+                                        uint64_t* b64) {
+  const int l = lane_id();
+  const uint32_t nib = ((uint32_t)__popcll(bm) + 1) / 2;
+  for (uint32_t k = l; k < size / 8; k += WAVE) b64[k] = 0;
+  wave_sync();
+  if (D) {
+    const uint32_t t = __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+    atomicOr((unsigned long long*)&b64[t / 16], (unsigned long long)len << (4 * (t % 16)));
+    const uint32_t so = nib + sig_incl - len;
+    const uint32_t sh = 8 * (so % 8);
+    atomicOr((unsigned long long*)&b64[so / 8], (unsigned long long)(D << sh));
+    if (sh && sh + 8 * len > 64) atomicOr((unsigned long long*)&b64[so / 8 + 1], (unsigned long long)(D >> (64 - sh)));
+  }
+  wave_sync();
+}
+
 __device__ inline uint32_t build_block(uint64_t D, uint64_t* b64, uint64_t* bitmap_out) {
   const int l = lane_id();
   const uint64_t bm = __ballot(D != 0);
@@ -1041,7 +1061,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a, const Seg* __re
 // built in LDS and written in place.  The dense residual never goes to
 // memory.
 #ifndef TA_EG_R
-#define TA_EG_R 8
+#define TA_EG_R 4
 #endif
 #ifndef TA_EG_BLOCK
 #define TA_EG_BLOCK 512
@@ -1073,6 +1093,7 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
                                                          const uint32_t* __restrict__ gfirst, LookBack lb) {
   constexpr int BW = BLK_MAX / 8 + 1;
   __shared__ uint64_t s_blk[EG_WAVES][BW];
+  __shared__ uint32_t s_mark[EG_WAVES][EG_R][WAVE];  // record-start marks: group index + 1
   __shared__ uint64_t s_wave[EG_WAVES];
   __shared__ uint32_t s_ticket;
   __shared__ uint64_t s_prefix;
@@ -1089,116 +1110,160 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
   if ((int64_t)blockIdx.x >= ntiles) return;
   const int l = lane_id(), wv = wave_id();
   const uint64_t le_mask = lanemask_le(l);
+#pragma unroll
+  for (int x = 0; x < EG_R; ++x) s_mark[wv][x][l] = 0;  // no group's tag
+  wave_sync();
+  // Tiles are pipelined: a block computes a new tile and publishes its
+  // aggregate before it finishes the previous one (look-back, then blocks),
+  // so the wait for predecessors overlaps the next tile's loads.
+  bool have = false;  // a computed tile waiting for its prefix
+  uint32_t tp = 0;
+  uint64_t Dp[EG_R], woffp = 0, totp = 0;
+  uint32_t szp[EG_R], incp[EG_R];
+#pragma unroll
+  for (int x = 0; x < EG_R; ++x) {
+    Dp[x] = 0;
+    szp[x] = incp[x] = 0;
+  }
   for (;;) {
     const uint32_t t = lb_take_ticket(lb, &s_ticket);
-    if ((int64_t)t >= ntiles) break;
-    const int64_t g0 = (int64_t)t * EG_TILE + (int64_t)wv * EG_R;
-    // The wave's groups in steps, each issuing its loads for every group
-    // before any is used: record tables, then C and R words.  Groups past the
-    // end work on the last group (clamped: no branch around loads) and store
-    // nothing.
-    int64_t gc[EG_R];
-    bool gv[EG_R], has[EG_R];
-    uint64_t mst[EG_R], cwd[EG_R], rwd[EG_R];
-#pragma unroll
-    for (int x = 0; x < EG_R; ++x) {
-      gv[x] = g0 + x < Gt;
-      gc[x] = gv[x] ? g0 + x : Gt - 1;
-      // lane i <= 32: start, C word and R word of record k0 + i (a group
-      // implies a matched record, so M >= 1 and the clamped index is valid)
-      const uint64_t k0 = uniform32(gfirst[gc[x]]);
-      has[x] = l <= 32 && k0 + l < (uint64_t)M;
-      const uint64_t kk = has[x] ? k0 + l : (uint64_t)M - 1;
-      mst[x] = a.mstart[kk];
-      cwd[x] = a.mdir[kk].cword;
-      rwd[x] = a.mdir[kk].rword;
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    uint64_t cv[EG_R], xv[EG_R];
-    bool live[EG_R];
-#pragma unroll
-    for (int x = 0; x < EG_R; ++x) {
-      const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
-      const Seg& sg = segs[sx];
-      const uint64_t lg = uniform64((uint64_t)gc[x] - gpre[sx]);
-      const uint64_t g0w = uniform64(sg.dbase + 64 * lg);  // the group's first residual position
-      // start relative to the group (clamped to [-2^30, 64]), words relative
-      // to the segment's record areas
-      const int64_t r = (int64_t)mst[x] - (int64_t)g0w;
-      const int rel = !has[x] ? 64 : (r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r));
-      const uint32_t cw = (uint32_t)(cwd[x] - sg.cbody / 8), rw = (uint32_t)(rwd[x] - sg.rbody / 8);
-      // records starting inside the group (lanes 1..32), one bit each
-      const uint64_t starts = wave_or_all64(l >= 1 && rel >= 1 && rel < WAVE ? 1ull << rel : 0ull);
-      const int idx = __popcll(starts & le_mask);  // <= 32
-      const uint32_t off = (uint32_t)(l - __shfl(rel, idx, WAVE));
-      const uint32_t cwi = (uint32_t)__shfl((int)cw, idx, WAVE), rwi = (uint32_t)__shfl((int)rw, idx, WAVE);
-      live[x] = gv[x] && 64 * lg + (uint64_t)l < sg.W;
-      // (a word that is not live reads word 0 of lane 0's record, the one
-      // holding the group's first word: in the segment, always valid)
-      const uint32_t cw0 = (uint32_t)__builtin_amdgcn_readlane((int)cw, 0);
-      const uint32_t rw0 = (uint32_t)__builtin_amdgcn_readlane((int)rw, 0);
-      cv[x] = a.cur[uniform64(sg.cbody / 8) + (live[x] ? cwi + off : cw0)];
-      xv[x] = a.ref[uniform64(sg.rbody / 8) + (live[x] ? rwi + off : rw0)];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    // C' words, residual words and block sizes
+    const bool got = (int64_t)t < ntiles;  // the same in the whole block
     uint64_t D[EG_R];
-    uint32_t size[EG_R];
-    uint64_t wsum = 0;
-#pragma unroll
-    for (int x = 0; x < EG_R; ++x) {
-      D[x] = live[x] ? cv[x] ^ xv[x] : 0;
-      const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
-      const Seg& sg = segs[sx];
-      if (live[x]) a.newref[sg.cpw + sg.dbase + 64 * ((uint64_t)gc[x] - gpre[sx]) + (uint64_t)l] = cv[x];
-      const uint64_t bmw = __ballot(D[x] != 0);
-      const uint32_t len = D[x] ? (uint32_t)(8 - (__clzll((long long)D[x]) >> 3)) : 0u;
-      const uint32_t sig = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan32(len), 63);
-      size[x] = gv[x] ? ((((uint32_t)__popcll(bmw) + 1) / 2 + sig + 7) & ~7u) : 0u;
-      if (gv[x] && l == 0) {
-        a.bm[gc[x]] = bmw;
-        a.gsz[gc[x]] = (uint8_t)(size[x] / 8);
-      }
-      wsum += size[x];
-    }
-    // the tile's block bytes: waves, then the look-back over earlier tiles
-    if (l == 0) s_wave[wv] = wsum;
-    __syncthreads();
+    uint32_t size[EG_R], inclv[EG_R];
     uint64_t woff = 0, tot = 0;
+    if (got) {
+      const int64_t g0 = (int64_t)t * EG_TILE + (int64_t)wv * EG_R;
+      // The wave's groups in steps, each issuing its loads for every group
+      // before any is used: record tables, then C and R words.  Groups past the
+      // end work on the last group (clamped: no branch around loads) and store
+      // nothing.
+      int64_t gc[EG_R];
+      bool gv[EG_R], has[EG_R];
+      uint64_t mst[EG_R], cwd[EG_R], rwd[EG_R];
 #pragma unroll
-    for (int i = 0; i < EG_WAVES; ++i) {
-      woff += (i < wv) ? s_wave[i] : 0;
-      tot += s_wave[i];
+      for (int x = 0; x < EG_R; ++x) {
+        gv[x] = g0 + x < Gt;
+        gc[x] = gv[x] ? g0 + x : Gt - 1;
+        // lane i <= 32: start, C word and R word of record k0 + i (a group
+        // implies a matched record, so M >= 1 and the clamped index is valid)
+        const uint64_t k0 = uniform32(gfirst[gc[x]]);
+        has[x] = l <= 32 && k0 + l < (uint64_t)M;
+        const uint64_t kk = has[x] ? k0 + l : (uint64_t)M - 1;
+        mst[x] = a.mstart[kk];
+        cwd[x] = a.mdir[kk].cword;
+        rwd[x] = a.mdir[kk].rword;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // start relative to the group (clamped to [-2^30, 64]), words relative to
+      // the segment's record areas; lanes 1..32 mark the starts inside the group
+      int relv[EG_R];
+      uint32_t cwv[EG_R], rwv[EG_R];
+#pragma unroll
+      for (int x = 0; x < EG_R; ++x) {
+        const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
+        const Seg& sg = segs[sx];
+        const uint64_t g0w = uniform64(sg.dbase + 64 * ((uint64_t)gc[x] - gpre[sx]));  // first residual position
+        const int64_t r = (int64_t)mst[x] - (int64_t)g0w;
+        relv[x] = !has[x] ? 64 : (r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r));
+        cwv[x] = (uint32_t)(cwd[x] - sg.cbody / 8);
+        rwv[x] = (uint32_t)(rwd[x] - sg.rbody / 8);
+        if (l >= 1 && relv[x] >= 1 && relv[x] < WAVE) s_mark[wv][x][relv[x]] = (uint32_t)gc[x] + 1;
+      }
+      wave_sync();
+      uint64_t cv[EG_R], xv[EG_R];
+      bool live[EG_R];
+#pragma unroll
+      for (int x = 0; x < EG_R; ++x) {
+        const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
+        const Seg& sg = segs[sx];
+        const uint64_t lg = uniform64((uint64_t)gc[x] - gpre[sx]);
+        const int rel = relv[x];
+        const uint32_t cw = cwv[x], rw = rwv[x];
+        const uint64_t starts = __ballot(s_mark[wv][x][l] == (uint32_t)gc[x] + 1);
+        const int idx = __popcll(starts & le_mask);  // <= 32
+        const uint32_t off = (uint32_t)(l - __shfl(rel, idx, WAVE));
+        const uint32_t cwi = (uint32_t)__shfl((int)cw, idx, WAVE), rwi = (uint32_t)__shfl((int)rw, idx, WAVE);
+        live[x] = gv[x] && 64 * lg + (uint64_t)l < sg.W;
+        // (a word that is not live reads word 0 of lane 0's record, the one
+        // holding the group's first word: in the segment, always valid)
+        const uint32_t cw0 = (uint32_t)__builtin_amdgcn_readlane((int)cw, 0);
+        const uint32_t rw0 = (uint32_t)__builtin_amdgcn_readlane((int)rw, 0);
+        cv[x] = a.cur[uniform64(sg.cbody / 8) + (live[x] ? cwi + off : cw0)];
+        xv[x] = a.ref[uniform64(sg.rbody / 8) + (live[x] ? rwi + off : rw0)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // C' words, residual words and block sizes
+      uint64_t wsum = 0;
+#pragma unroll
+      for (int x = 0; x < EG_R; ++x) {
+        D[x] = live[x] ? cv[x] ^ xv[x] : 0;
+        const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
+        const Seg& sg = segs[sx];
+        if (live[x]) a.newref[sg.cpw + sg.dbase + 64 * ((uint64_t)gc[x] - gpre[sx]) + (uint64_t)l] = cv[x];
+        const uint64_t bmw = __ballot(D[x] != 0);
+        const uint32_t len = D[x] ? (uint32_t)(8 - (__clzll((long long)D[x]) >> 3)) : 0u;
+        inclv[x] = wave_incl_scan32(len);
+        const uint32_t sig = (uint32_t)__builtin_amdgcn_readlane((int)inclv[x], 63);
+        size[x] = gv[x] ? ((((uint32_t)__popcll(bmw) + 1) / 2 + sig + 7) & ~7u) : 0u;
+        if (gv[x] && l == 0) {
+          a.bm[gc[x]] = bmw;
+          a.gsz[gc[x]] = (uint8_t)(size[x] / 8);
+        }
+        wsum += size[x];
+      }
+      // the tile's block bytes: waves, then its aggregate for the look-back
+      if (l == 0) s_wave[wv] = wsum;
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < EG_WAVES; ++i) {
+        woff += (i < wv) ? s_wave[i] : 0;
+        tot += s_wave[i];
+      }
+      if (threadIdx.x == 0) lb_publish(lb, t, tot);
     }
-    if (threadIdx.x < WAVE) {
-      const uint64_t e = lb_exclusive(lb, t, tot);
-      if (threadIdx.x == 0) s_prefix = e;
+    if (have) {  // the previous tile: its prefix, then its blocks
+      if (threadIdx.x < WAVE) {
+        const uint64_t e = lb_lookback(lb, tp, totp);
+        if (threadIdx.x == 0) s_prefix = e;
+      }
+      __syncthreads();
+      const int64_t g0p = (int64_t)tp * EG_TILE + (int64_t)wv * EG_R;
+      // blocks: built in the wave's LDS buffer one at a time, written in place
+      uint64_t pos = s_prefix + woffp;  // block bytes before this wave's first group
+#pragma unroll
+      for (int x = 0; x < EG_R; ++x) {
+        const int64_t gg = g0p + x;
+        if (gg >= Gt) break;
+        if (l == 0) a.gex[gg] = pos;
+        if (szp[x]) {
+          const Seg& sg = segs[(int64_t)uniform32(gseg[gg])];
+          const uint64_t at = uniform64(sg.fixed_excl + sg.fixed + pos);
+          const uint32_t len = Dp[x] ? (uint32_t)(8 - (__clzll((long long)Dp[x]) >> 3)) : 0u;
+          build_block_from(Dp[x], len, incp[x], __ballot(Dp[x] != 0), szp[x], s_blk[wv]);
+          if (at + szp[x] > (uint64_t)a.enc_cap) {
+            if (l == 0) fail(cm.status, ERR_CAPACITY);
+          } else {
+            uint64_t* dst = reinterpret_cast<uint64_t*>(a.enc + at);
+            for (uint32_t w = l; w < szp[x] / 8; w += WAVE) dst[w] = s_blk[wv][w];
+          }
+          wave_sync();  // the buffer is rebuilt for the next group
+        }
+        pos += szp[x];
+      }
+      if ((int64_t)tp == ntiles - 1 && threadIdx.x == 0) a.gex[Gt] = s_prefix + totp;
     }
-    __syncthreads();
-    // blocks: built in the wave's LDS buffer one at a time, written in place
-    uint64_t pos = s_prefix + woff;  // block bytes before this wave's first group
+    __syncthreads();  // s_wave, s_prefix and the LDS buffers are reused
+    if (!got) break;
+    have = true;
+    tp = t;
+    woffp = woff;
+    totp = tot;
 #pragma unroll
     for (int x = 0; x < EG_R; ++x) {
-      if (!gv[x]) break;
-      const int64_t gg = gc[x];
-      if (l == 0) a.gex[gg] = pos;
-      if (size[x]) {
-        const Seg& sg = segs[(int64_t)uniform32(gseg[gg])];
-        const uint64_t at = uniform64(sg.fixed_excl + sg.fixed + pos);
-        uint64_t bmw;
-        build_block(D[x], s_blk[wv], &bmw);
-        if (at + size[x] > (uint64_t)a.enc_cap) {
-          if (l == 0) fail(cm.status, ERR_CAPACITY);
-        } else {
-          uint64_t* dst = reinterpret_cast<uint64_t*>(a.enc + at);
-          for (uint32_t w = l; w < size[x] / 8; w += WAVE) dst[w] = s_blk[wv][w];
-        }
-        wave_sync();  // the buffer is rebuilt for the next group
-      }
-      pos += size[x];
+      Dp[x] = D[x];
+      szp[x] = size[x];
+      incp[x] = inclv[x];
     }
-    if ((int64_t)t == ntiles - 1 && threadIdx.x == 0) a.gex[Gt] = s_prefix + tot;
-    __syncthreads();
   }
 }
 

@@ -81,24 +81,6 @@ __device__ inline uint64_t wave_incl_scan64(uint64_t v) {
   step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); });
   return v;
 }
-// OR of a 64-bit value over the 64 lanes (the inclusive OR-scan of
-// wave_incl_scan64's structure, read from lane 63): uniform.  All lanes must
-// call it.
-__device__ inline uint64_t wave_or_all64(uint64_t v) {
-  auto step = [&](auto dpp) {
-    const uint32_t lo = dpp((uint32_t)v), hi = dpp((uint32_t)(v >> 32));
-    v |= ((uint64_t)hi << 32) | lo;
-  };
-  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true); });
-  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true); });
-  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true); });
-  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true); });
-  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); });
-  step([](uint32_t x) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); });
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
-  return ((uint64_t)hi << 32) | lo;
-}
 __device__ inline uint64_t readlane64(uint64_t v, int lane) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
@@ -183,14 +165,18 @@ __device__ inline uint32_t lb_take_ticket(const LookBack& lb, uint32_t* s_ticket
   return t;
 }
 
-// Called by all 64 lanes of one wave; returns the exclusive prefix of tile t.
-__device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t agg) {
+// The two halves of a tile's part in the look-back, for kernels that do
+// other work between them: lb_publish makes the tile's aggregate visible
+// (tile 0's is already its inclusive prefix); lb_lookback, called by all 64
+// lanes of one wave, sums predecessors back to the nearest inclusive prefix,
+// publishes the tile's own and returns its exclusive prefix.  Predecessors
+// only need to have published their aggregates.
+__device__ inline void lb_publish(const LookBack& lb, uint32_t t, uint64_t agg) {
+  __hip_atomic_store(lb.flags + t, (t == 0 ? LB_INCL : LB_AGG) | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t lb_lookback(const LookBack& lb, uint32_t t, uint64_t agg) {
   const int l = lane_id();
-  if (t == 0) {
-    if (l == 0) __hip_atomic_store(lb.flags, LB_INCL | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return 0;
-  }
-  if (l == 0) __hip_atomic_store(lb.flags + t, LB_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (t == 0) return 0;
   uint64_t excl = 0;
   int64_t hi = (int64_t)t - 1;
   uint32_t spins = 0;
@@ -216,6 +202,12 @@ __device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t
   }
   if (l == 0) __hip_atomic_store(lb.flags + t, LB_INCL | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return excl;
+}
+// Both halves at once; called by all 64 lanes of one wave, returns the
+// exclusive prefix of tile t.
+__device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t agg) {
+  if (lane_id() == 0) lb_publish(lb, t, agg);
+  return lb_lookback(lb, t, agg);
 }
 
 // ---------------------------------------------------------------------------
