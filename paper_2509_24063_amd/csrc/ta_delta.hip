@@ -383,6 +383,12 @@ struct JoinArgs {
   uint8_t* cflag;
 };
 
+// A bucketed join item: uid and item index, moved as one 16-byte access
+// (the pair array is 256-byte aligned).
+struct alignas(16) Pair {
+  uint64_t uid, item;
+};
+
 struct JTile {
   int64_t s;
   uint64_t lt, i0, i1;  // items [i0, i1) of one side of the segment
@@ -502,14 +508,22 @@ __global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a, const Seg* _
     for (uint64_t b = threadIdx.x; b < B; b += BLOCK) s_off[b] = (uint32_t)(src[b * g.jT] - seg0);
     __syncthreads();
     const uint64_t gbase = jt.isC ? cpre[jt.s] : Ct + rpre[jt.s];
-    for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += BLOCK) {
-      const uint64_t i = i0 + threadIdx.x;
-      if (i < jt.i1) {
-        const uint64_t item = gbase + i;
-        const uint64_t uid = a.juid[item];
-        const uint32_t pos = atomicAdd(&s_off[join_bucket(uid, B)], 1u);
-        a.part[2 * (seg0 + pos)] = uid;
-        a.part[2 * (seg0 + pos) + 1] = item;
+    // JC_U items per thread and pass, their uids loaded together; each pair
+    // goes out as one 16-byte store
+    for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += (uint64_t)BLOCK * JC_U) {
+      uint64_t uid[JC_U];
+#pragma unroll
+      for (int u = 0; u < JC_U; ++u) {
+        const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
+        uid[u] = a.juid[gbase + (i < jt.i1 ? i : jt.i1 - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < JC_U; ++u) {
+        const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
+        if (i < jt.i1) {
+          const uint32_t pos = atomicAdd(&s_off[join_bucket(uid[u], B)], 1u);
+          *reinterpret_cast<Pair*>(a.part + 2 * (seg0 + pos)) = Pair{uid[u], gbase + i};
+        }
       }
     }
     __syncthreads();
@@ -542,10 +556,23 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a, const Seg* __
       if (threadIdx.x == 0) atomicOr((unsigned long long*)&cm.meta[13], 1ull);
       continue;
     }
-    for (uint32_t k = threadIdx.x; k < n; k += BLOCK) {
-      s_uid[k] = a.part[2 * (p0 + k)];
-      s_id[k] = (uint32_t)a.part[2 * (p0 + k) + 1];
-      s_partner[k] = NONE;
+    // JC_U pairs per thread at a time, loaded before any is stored to LDS
+    for (uint32_t k0 = threadIdx.x; k0 < n; k0 += BLOCK * JC_U) {
+      Pair pr[JC_U];
+#pragma unroll
+      for (int u = 0; u < JC_U; ++u) {
+        const uint32_t k = k0 + u * BLOCK;
+        pr[u] = *reinterpret_cast<const Pair*>(a.part + 2 * (p0 + (k < n ? k : n - 1)));
+      }
+#pragma unroll
+      for (int u = 0; u < JC_U; ++u) {
+        const uint32_t k = k0 + u * BLOCK;
+        if (k < n) {
+          s_uid[k] = pr[u].uid;
+          s_id[k] = (uint32_t)pr[u].item;
+          s_partner[k] = NONE;
+        }
+      }
     }
     for (uint32_t k = threadIdx.x; k < JTAB; k += BLOCK) s_tab[k] = 0;
     __syncthreads();
