@@ -763,33 +763,65 @@ __device__ inline void map_groups(const Common& cm, int64_t s, uint64_t q0, uint
   }
 }
 
+// Directory of the matched records, in C' order: C and R word, residual
+// start, slot; C' offsets; groups' segment and first record.  A wave takes
+// RS_U * 64 consecutive reference slots per pass and issues their loads in
+// two stages before it stores anything.
 __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
                                                     const int32_t* m, const uint64_t* rscan, const uint32_t* rwords,
                                                     MDir* mdir, uint64_t* mstart, uint8_t* newref, uint32_t* gseg,
                                                     uint32_t* gfirst) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t base = (int64_t)blockIdx.x * BLOCK + wave_id() * WAVE; base < Rt; base += stride) {
-    const int64_t g = base + lane_id();
-    const uint64_t last = (uint64_t)(base + WAVE - 1 < Rt ? base + WAVE - 1 : Rt - 1);
-    const int64_t s = wave_seg(cm.rpre, cm.nseg, (uint64_t)(g < Rt ? g : Rt - 1), (uint64_t)base, last);
-    if (g >= Rt) continue;
-    const int32_t i = m[g];
-    if (i < 0) continue;
-    const Seg& sg = cm.seg[s];
-    const uint64_t j = g - cm.rpre[s];
-    const uint64_t k = rscan[g] >> PK;
-    const uint64_t d = rscan[g] & WMASK;
-    MDir e;
-    e.cword = sg.cbody / 8 + ld32(cur + sg.cmsg + 32 + 4 * (uint64_t)i);
-    e.rword = sg.rbody / 8 + ld32(ref + sg.rmsg + 32 + 4 * j);
-    e.dstart = d;
-    e.gs = (uint64_t)g | ((uint64_t)s << 34);
-    mdir[k] = e;
-    mstart[k] = d;
-    *reinterpret_cast<uint32_t*>(newref + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
-    map_groups(cm, s, d - sg.dbase, rwords[g], gseg, gfirst, k);
+  const int l = lane_id();
+  constexpr int64_t SPAN = (int64_t)WAVE * RS_U;
+  const int64_t nwv = (int64_t)gridDim.x * WAVES;
+  for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave_id()) * SPAN; base < Rt; base += nwv * SPAN) {
+    const int64_t last = base + SPAN - 1 < Rt ? base + SPAN - 1 : Rt - 1;
+    const int64_t lo = wave_last_le<uint64_t>(cm.rpre, 0, cm.nseg, (uint64_t)base);
+    const int64_t hi = wave_last_le<uint64_t>(cm.rpre, lo, cm.nseg, (uint64_t)last);
+    // slot values, the R offset and the C offset (of the message header for
+    // an unmatched slot: always there); slots past the end read the last one
+    int64_t sv[RS_U];
+    int32_t iv[RS_U];
+    uint64_t rsv[RS_U];
+    uint32_t rwv[RS_U], roff[RS_U], coff[RS_U];
+#pragma unroll
+    for (int u = 0; u < RS_U; ++u) {
+      const int64_t g = base + (int64_t)u * WAVE + l;
+      const int64_t gc = g <= last ? g : last;
+      const int64_t sx = lo == hi ? lo : last_le<uint64_t>(cm.rpre, lo, hi + 1, (uint64_t)gc);
+      sv[u] = sx;
+      iv[u] = m[gc];
+      rsv[u] = rscan[gc];
+      rwv[u] = rwords[gc];
+      roff[u] = ld32(ref + cm.seg[sx].rmsg + 32 + 4 * ((uint64_t)gc - cm.rpre[sx]));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < RS_U; ++u) {
+      const Seg& sg = cm.seg[sv[u]];
+      coff[u] = ld32(cur + sg.cmsg + (iv[u] >= 0 ? 32 + 4 * (uint64_t)iv[u] : 0));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < RS_U; ++u) {
+      const int64_t g = base + (int64_t)u * WAVE + l;
+      if (g > last || iv[u] < 0) continue;
+      const int64_t sx = sv[u];
+      const Seg& sg = cm.seg[sx];
+      const uint64_t k = rsv[u] >> PK;
+      const uint64_t d = rsv[u] & WMASK;
+      MDir e;
+      e.cword = sg.cbody / 8 + coff[u];
+      e.rword = sg.rbody / 8 + roff[u];
+      e.dstart = d;
+      e.gs = (uint64_t)g | ((uint64_t)sx << 34);
+      mdir[k] = e;
+      mstart[k] = d;
+      *reinterpret_cast<uint32_t*>(newref + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
+      map_groups(cm, sx, d - sg.dbase, rwv[u], gseg, gfirst, k);
+    }
   }
 }
 
@@ -1733,32 +1765,57 @@ __global__ __launch_bounds__(BLOCK) void k_dec_seg2(Common cm, const uint64_t* r
   }
 }
 
+// Directory of the matched records (decoder): R word, residual start,
+// slot; word offsets of the records in the reference's record area; C'
+// offsets; groups' segment and first record.  Staged like the encoder's.
 __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* ref, const uint8_t* rmatch,
                                                     const uint64_t* rscan, const uint32_t* rwords, MDir* mdir,
                                                     uint64_t* mstart, uint8_t* out, uint32_t* gseg,
                                                     uint32_t* gfirst, uint32_t* mrw) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t base = (int64_t)blockIdx.x * BLOCK + wave_id() * WAVE; base < Rt; base += stride) {
-    const int64_t g = base + lane_id();
-    const uint64_t last = (uint64_t)(base + WAVE - 1 < Rt ? base + WAVE - 1 : Rt - 1);
-    const int64_t s = wave_seg(cm.rpre, cm.nseg, (uint64_t)(g < Rt ? g : Rt - 1), (uint64_t)base, last);
-    if (g >= Rt || !rmatch[g]) continue;
-    const Seg& sg = cm.seg[s];
-    const uint64_t j = g - cm.rpre[s];
-    const uint64_t k = rscan[g] >> PK;
-    const uint64_t d = rscan[g] & WMASK;
-    MDir e;
-    e.cword = 0;
-    e.rword = sg.rbody / 8 + ld32(ref + sg.rmsg + 32 + 4 * j);
-    e.dstart = d;
-    e.gs = (uint64_t)g | ((uint64_t)s << 34);
-    mdir[k] = e;
-    mstart[k] = d;
-    mrw[k] = (uint32_t)(e.rword - sg.rbody / 8);  // word offset in the reference's record area
-    *reinterpret_cast<uint32_t*>(out + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
-    map_groups(cm, s, d - sg.dbase, rwords[g], gseg, gfirst, k);
+  const int l = lane_id();
+  constexpr int64_t SPAN = (int64_t)WAVE * RS_U;
+  const int64_t nwv = (int64_t)gridDim.x * WAVES;
+  for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave_id()) * SPAN; base < Rt; base += nwv * SPAN) {
+    const int64_t last = base + SPAN - 1 < Rt ? base + SPAN - 1 : Rt - 1;
+    const int64_t lo = wave_last_le<uint64_t>(cm.rpre, 0, cm.nseg, (uint64_t)base);
+    const int64_t hi = wave_last_le<uint64_t>(cm.rpre, lo, cm.nseg, (uint64_t)last);
+    int64_t sv[RS_U];
+    uint8_t mv[RS_U];
+    uint64_t rsv[RS_U];
+    uint32_t rwv[RS_U], roff[RS_U];
+#pragma unroll
+    for (int u = 0; u < RS_U; ++u) {
+      const int64_t g = base + (int64_t)u * WAVE + l;
+      const int64_t gc = g <= last ? g : last;
+      const int64_t sx = lo == hi ? lo : last_le<uint64_t>(cm.rpre, lo, hi + 1, (uint64_t)gc);
+      sv[u] = sx;
+      mv[u] = rmatch[gc];
+      rsv[u] = rscan[gc];
+      rwv[u] = rwords[gc];
+      roff[u] = ld32(ref + cm.seg[sx].rmsg + 32 + 4 * ((uint64_t)gc - cm.rpre[sx]));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < RS_U; ++u) {
+      const int64_t g = base + (int64_t)u * WAVE + l;
+      if (g > last || !mv[u]) continue;
+      const int64_t sx = sv[u];
+      const Seg& sg = cm.seg[sx];
+      const uint64_t k = rsv[u] >> PK;
+      const uint64_t d = rsv[u] & WMASK;
+      MDir e;
+      e.cword = 0;
+      e.rword = sg.rbody / 8 + roff[u];
+      e.dstart = d;
+      e.gs = (uint64_t)g | ((uint64_t)sx << 34);
+      mdir[k] = e;
+      mstart[k] = d;
+      mrw[k] = roff[u];  // word offset in the reference's record area
+      *reinterpret_cast<uint32_t*>(out + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
+      map_groups(cm, sx, d - sg.dbase, rwv[u], gseg, gfirst, k);
+    }
   }
 }
 
@@ -2431,7 +2488,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   k_scan_cols<<<4, 1024, 0, s>>>(col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4},
                                           {b.G, -1, -1, -1}));
   k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
-  k_enc_mdir<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg,
+  k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg,
                                  m.gfirst);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
@@ -2516,7 +2573,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, b.G, m.gex,
                                                                      lookback(c, 2));
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
-  k_dec_mdir<<<g, BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg, m.gfirst,
+  k_dec_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg, m.gfirst,
                                  m.mrw);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
