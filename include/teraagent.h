@@ -254,8 +254,10 @@ ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t
  * ta_kernel_time returns (after syncing) the number of launches and their
  * summed duration in milliseconds since the last call.  name = NULL
  * disables.  Names: "select_count", "select_scatter", "serialize_pack",
- * "encode_join", "predict", "encode_resid", "encode_pack", "decode_unpack"
- * (which also applies the residual to the reference). */
+ * "encode_join", "encode_groups" (plain encodings: residual, block sizes,
+ * offsets and blocks in one kernel), "predict", "encode_resid" and
+ * "encode_pack" (learned encodings), "decode_unpack" (which also applies the
+ * residual to the reference). */
 ta_status ta_time_kernel(ta_ctx *ctx, const char *name);
 ta_status ta_kernel_time(ta_ctx *ctx, int64_t *launches, double *total_ms);
 
