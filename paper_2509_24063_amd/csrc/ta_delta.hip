@@ -15,18 +15,19 @@
 //   k_scan         bucket counts -> bucket starts
 //   k_join_scatter (uid, item) pairs into their buckets
 //   k_join_bucket  one block per bucket: LDS hash table pairs current and
-//                  reference items with equal uids (duplicates rejected);
-//                  k_clear_tab / k_enc_insert / k_enc_match: a global-table
-//                  join for buckets that overflow their block (rare)
+//                  reference items with equal uids (duplicates rejected); a
+//                  bucket too large for LDS joins in a global table of its own
 //   k_scan x2      packed (count << 34 | words) prefixes over R slots
 //                  (matched) and C records (new)
 //   k_enc_seg2/3   per segment layout, C' offsets and headers
 //   k_enc_mdir     matched-record directory (C word, R word, residual start)
-//                  and the segment of every residual group
-//   k_enc_resid    C' words and the dense residual C xor X
-//   k_enc_gsize    per 64-word group: bitmap and block size; k_scan places
-//                  the blocks; k_enc_place assembles each block in LDS and
-//                  writes it
+//                  and the segment and first record of every residual group
+//   k_enc_groups   plain mode: per 64-word group, C' words, the residual
+//                  C xor R (in registers), its block; a look-back over tiles
+//                  of groups places the blocks
+//   learned mode instead: k_enc_resid (C' words and both dense residuals),
+//                  k_enc_gsize (bitmaps, block sizes), scans, k_choose_mode,
+//                  k_enc_place (blocks of the chosen variant)
 //   k_enc_fin      encoding offsets and headers
 //   k_enc_fixed    presence bitmaps, word bitmaps, block size tables, new
 //                  record sizes, C' offsets of new records
@@ -217,7 +218,6 @@ __global__ __launch_bounds__(BLOCK) void k_enc_setup(Common cm, const uint8_t* c
                                                      const int64_t* cur_off, const uint8_t* ref, int64_t ref_len,
                                                      const int64_t* ref_off, ClearFirst cf) {
   do_clear_first(cf);
-  if (blockIdx.x == 0 && threadIdx.x == 0) cm.meta[13] = 0;
   for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
     uint64_t nc = 0, nr = 0, hs = 0, jt = 0, je = 0, jb = 0;
     Seg& g = cm.seg[s];
@@ -276,98 +276,6 @@ __global__ __launch_bounds__(BLOCK) void k_enc_setup(Common cm, const uint8_t* c
 }
 
 // Global-table join: only used when a join bucket overflowed its LDS block.
-__global__ __launch_bounds__(BLOCK) void k_clear_tab(Common cm, Entry* tab, uint8_t* cflag) {
-  if ((status_of(cm.status) & ANY_ERR) || !cm.meta[13]) return;
-  const int64_t H = cm.meta[2], Ct = cm.meta[0];
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < H; i += stride) {
-    tab[i].key = 0;
-    tab[i].ci = NONE;
-    tab[i].ri = NONE;
-  }
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < Ct; i += stride) cflag[i] = 0;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_enc_insert(Common cm, const uint8_t* cur, const uint8_t* ref, Entry* tab,
-                                                      uint32_t* cwords, uint32_t* rwords, uint32_t* rslot) {
-  if ((status_of(cm.status) & ANY_ERR) || !cm.meta[13]) return;
-  const int64_t Ct = cm.meta[0], total = cm.meta[0] + cm.meta[1];
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  // whole waves iterate together so the per-segment XOR fold can use the wave
-  const int64_t start = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const int64_t rounds = (total + stride - 1) / stride;
-  for (int64_t it = 0; it < rounds; ++it) {
-    const int64_t g = start + it * stride;
-    const bool active = g < total;
-    const bool isC = g < Ct;
-    int64_t s = 0;
-    uint64_t uid = 0;
-    bool okr = false;
-    if (active) {
-      const uint64_t loc = isC ? (uint64_t)g : (uint64_t)(g - Ct);
-      s = seg_of(isC ? cm.cpre : cm.rpre, cm.nseg, loc);
-      const Seg& sg = cm.seg[s];
-      const uint64_t i = loc - (isC ? cm.cpre[s] : cm.rpre[s]);
-      const uint8_t* m = isC ? cur + sg.cmsg : ref + sg.rmsg;
-      const uint32_t n = (uint32_t)(isC ? sg.nc : sg.nr);
-      const uint64_t rw = isC ? sg.rwc : sg.rwr;
-      uint32_t o;
-      uint64_t hdr;
-      okr = tam1_record(m, n, rw, (uint32_t)i, &o, &uid, &hdr) && uid != 0;
-      if (!okr) {
-        fail(cm.status, ERR_INVALID);
-      } else {
-        const uint64_t H = sg.hsize, hb = cm.hpre[s];
-        uint64_t h = mix64(uid) & (H - 1);
-        uint32_t slot = NONE;
-        for (uint64_t probe = 0; probe < H; ++probe) {
-          const unsigned long long prev = atomicCAS(&tab[hb + h].key, 0ull, (unsigned long long)uid);
-          if (prev == 0ull || prev == (unsigned long long)uid) {
-            uint32_t* ip = isC ? &tab[hb + h].ci : &tab[hb + h].ri;
-            if (atomicCAS(ip, NONE, (uint32_t)i) != NONE) fail(cm.status, ERR_INVALID);  // duplicate uid
-            slot = (uint32_t)h;
-            break;
-          }
-          h = (h + 1) & (H - 1);
-        }
-        const uint32_t words = (uint32_t)(hdr >> 32);
-        if (isC) {
-          cwords[g] = words;
-        } else {
-          rwords[g - Ct] = words;
-          rslot[g - Ct] = slot;
-        }
-      }
-    }
-  }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_enc_match(Common cm, const uint8_t* cur, const uint8_t* ref,
-                                                     const Entry* tab, const uint32_t* rslot, int32_t* m,
-                                                     uint8_t* cflag) {
-  if ((status_of(cm.status) & ANY_ERR) || !cm.meta[13]) return;
-  const int64_t Rt = cm.meta[1];
-  for (int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x; g < Rt; g += (int64_t)gridDim.x * BLOCK) {
-    const int64_t s = seg_of(cm.rpre, cm.nseg, (uint64_t)g);
-    const Seg& sg = cm.seg[s];
-    const uint64_t j = g - cm.rpre[s];
-    const uint32_t i = tab[cm.hpre[s] + rslot[g]].ci;
-    int32_t res = -1;
-    if (i != NONE) {
-      const uint32_t oc = ld32(cur + sg.cmsg + 32 + 4 * (uint64_t)i);
-      const uint32_t orr = ld32(ref + sg.rmsg + 32 + 4 * j);
-      const uint64_t hc = ld64(cur + sg.cbody + 8 * (uint64_t)oc + 8);
-      const uint64_t hr = ld64(ref + sg.rbody + 8 * (uint64_t)orr + 8);
-      if (hc == hr) {
-        res = (int32_t)i;
-        cflag[cm.cpre[s] + i] = 1;
-      }
-    }
-    m[g] = res;
-  }
-}
-
-
 struct JoinArgs {
   Common cm;
   const uint8_t* cur;
@@ -381,6 +289,7 @@ struct JoinArgs {
   uint64_t* part;    // [2 (C+R)] bucketed items: uid, item
   int32_t* m;
   uint8_t* cflag;
+  Entry* tab;        // open-addressing tables of buckets too large for LDS
 };
 
 // A bucketed join item: uid and item index, moved as one 16-byte access
@@ -530,6 +439,48 @@ __global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a, const Seg* _
   }
 }
 
+// A bucket with more items than LDS holds, joined by its block alone in an
+// open-addressing table of its own in global memory: slots [4 p0, 4 p0 + H)
+// of the table array, H = pow2ceil(2 n) <= 4 n (so buckets never share
+// slots).  Same results as the LDS join: a current and a reference item with
+// equal uids are partners; a second item of one side is a duplicate.
+__device__ void join_bucket_global(const JoinArgs& a, uint64_t p0, uint32_t n, uint64_t Ct, uint64_t cbase) {
+  const Common& cm = a.cm;
+  Entry* tab = a.tab + 4 * p0;
+  uint32_t H = 1;
+  while (H < 2 * n) H <<= 1;
+  for (uint32_t h = threadIdx.x; h < H; h += BLOCK) {
+    tab[h].key = 0;
+    tab[h].ci = NONE;
+    tab[h].ri = NONE;
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < n; k += BLOCK) {
+    const Pair pr = *reinterpret_cast<const Pair*>(a.part + 2 * (p0 + k));
+    uint32_t h = (uint32_t)mix64(pr.uid) & (H - 1);
+    for (uint32_t probe = 0; probe < H; ++probe) {
+      const unsigned long long prev = atomicCAS(&tab[h].key, 0ull, (unsigned long long)pr.uid);
+      if (prev == 0ull || prev == (unsigned long long)pr.uid) {
+        uint32_t* ip = pr.item >= Ct ? &tab[h].ri : &tab[h].ci;
+        if (atomicCAS(ip, NONE, (uint32_t)pr.item) != NONE) fail(cm.status, ERR_INVALID);  // duplicate uid
+        break;
+      }
+      h = (h + 1) & (H - 1);
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < n; k += BLOCK) {
+    const Pair pr = *reinterpret_cast<const Pair*>(a.part + 2 * (p0 + k));
+    uint32_t h = (uint32_t)mix64(pr.uid) & (H - 1);
+    for (uint32_t probe = 0; probe < H && tab[h].key != pr.uid; ++probe) h = (h + 1) & (H - 1);
+    const bool isR = pr.item >= Ct;
+    const uint32_t partner = isR ? tab[h].ci : tab[h].ri;
+    if (isR) a.m[pr.item - Ct] = partner != NONE ? (int32_t)(partner - cbase) : -1;
+    else a.cflag[pr.item] = partner != NONE ? 1 : 0;
+  }
+  __syncthreads();
+}
+
 // J4: one block per bucket: an LDS hash table pairs current and reference
 // items with equal uids; a second item of the same side, or a third item,
 // is a duplicate.
@@ -552,8 +503,8 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a, const Seg* __
     const uint64_t b = (uint64_t)bk - bpre[s];
     const uint64_t p0 = uniform64(cnt_pre[jepre[s] + b * g.jT]), p1 = uniform64(cnt_pre[jepre[s] + (b + 1) * g.jT]);
     const uint32_t n = (uint32_t)(p1 - p0);
-    if (n > JCAP) {  // uniform: leave this bucket to the global-table join
-      if (threadIdx.x == 0) atomicOr((unsigned long long*)&cm.meta[13], 1ull);
+    if (n > JCAP) {  // uniform: a bucket too large for LDS joins in global memory
+      join_bucket_global(a, p0, n, Ct, cpre[s]);
       continue;
     }
     // JC_U pairs per thread at a time, loaded before any is stored to LDS
@@ -1317,7 +1268,6 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
     tp = t;
     woffp = woff;
     totp = tot;
-#pragma unroll
     for (int x = 0; x < EG_R; ++x) {
       Dp[x] = D[x];
       szp[x] = size[x];
@@ -2297,7 +2247,6 @@ struct Mem {
   Entry* tab;
   uint32_t* cwords;
   uint32_t* rwords;
-  uint32_t* rslot;
   int32_t* m;
   uint8_t* cflag;   // encoder: matched C records; decoder: matched R slots
   uint64_t* rscan;
@@ -2349,7 +2298,6 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.tab = ar.take<Entry>(b.H);
   m.cwords = ar.take<uint32_t>(b.C);
   m.rwords = ar.take<uint32_t>(b.R);
-  m.rslot = ar.take<uint32_t>(b.R);
   m.m = ar.take<int32_t>(b.R);
   m.cflag = ar.take<uint8_t>(std::max(b.C, b.R));
   m.rscan = ar.take<uint64_t>(b.R + 1);
@@ -2468,17 +2416,13 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                                           {0, 1, 2, 10, 11, 12}, {b.C, b.R, b.H, b.T, b.E, b.B}));
   {
     Timed tm(c, "encode_join", s);
-    JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag};
+    JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag, m.tab};
     k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre);
     k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
                                                                      lookback(c, 0));
     k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre,
                                                          m.jcnt_pre);
     k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.bpre, m.cm.cpre, m.cm.jepre, m.jcnt_pre);
-    // only when a bucket overflowed its block: the global-table join
-    k_clear_tab<<<g, BLOCK, 0, s>>>(m.cm, m.tab, m.cflag);
-    k_enc_insert<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.cwords, m.rwords, m.rslot);
-    k_enc_match<<<g, BLOCK, 0, s>>>(m.cm, cur, ref, m.tab, m.rslot, m.m, m.cflag);
   }
   k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
                                                                      lookback(c, 1));
