@@ -214,11 +214,11 @@ inline ColScan col_scan(const Common& cm, std::initializer_list<uint64_t*> outs,
 
 // One thread per segment: message headers, record counts, hash and join
 // sizes (scanned afterwards by k_scan_cols).
-__global__ __launch_bounds__(BLOCK) void k_enc_setup(Common cm, const uint8_t* cur, int64_t cur_len,
-                                                     const int64_t* cur_off, const uint8_t* ref, int64_t ref_len,
-                                                     const int64_t* ref_off, ClearFirst cf) {
+__device__ void enc_setup(Common cm, const uint8_t* cur, int64_t cur_len,
+                          const int64_t* cur_off, const uint8_t* ref, int64_t ref_len,
+                          const int64_t* ref_off, ClearFirst cf) {
   do_clear_first(cf);
-  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * blockDim.x) {
     uint64_t nc = 0, nr = 0, hs = 0, jt = 0, je = 0, jb = 0;
     Seg& g = cm.seg[s];
     const int64_t ca = cur_off[s], cb = cur_off[s + 1], ra = ref_off[s], rb = ref_off[s + 1];
@@ -273,6 +273,12 @@ __global__ __launch_bounds__(BLOCK) void k_enc_setup(Common cm, const uint8_t* c
     col(cm, 4)[s] = je;
     col(cm, 5)[s] = jb;
   }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_enc_setup(Common cm, const uint8_t* cur, int64_t cur_len,
+                                                     const int64_t* cur_off, const uint8_t* ref, int64_t ref_len,
+                                                     const int64_t* ref_off, ClearFirst cf) {
+  enc_setup(cm, cur, cur_len, cur_off, ref, ref_len, ref_off, cf);
 }
 
 // Global-table join: only used when a join bucket overflowed its LDS block.
@@ -632,11 +638,11 @@ struct CNewIn {  // count << 34 | words of new current records
 
 // Per segment layout after matching (one thread per segment); the sizes
 // are scanned by k_scan_cols, then k_enc_seg3 places the C' messages.
-__global__ __launch_bounds__(BLOCK) void k_enc_seg2(Common cm, const uint64_t* rscan, const uint64_t* cscan,
-                                                    uint64_t* mstart) {
+__device__ void enc_seg2(Common cm, const uint64_t* rscan, const uint64_t* cscan,
+                         uint64_t* mstart) {
   if (status_of(cm.status) & ANY_ERR) {
     // sizes of zero: the scans that follow stay within their arrays
-    for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK)
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * blockDim.x)
       for (int c = 0; c < 4; ++c) col(cm, c)[s] = 0;
     return;
   }
@@ -647,7 +653,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_seg2(Common cm, const uint64_t* r
     cm.meta[7] = (int64_t)(cscan[cm.meta[0]] & WMASK);
     mstart[cm.meta[5]] = rscan[cm.meta[1]] & WMASK;  // end of the last matched record
   }
-  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * blockDim.x) {
     Seg& g = cm.seg[s];
     g.fold = fold_of(cm.fold + s * FOLD_SLOTS);
     const uint64_t rs = rscan[cm.rpre[s]], re = rscan[cm.rpre[s + 1]];
@@ -673,9 +679,14 @@ __global__ __launch_bounds__(BLOCK) void k_enc_seg2(Common cm, const uint64_t* r
   }
 }
 
+__global__ __launch_bounds__(BLOCK) void k_enc_seg2(Common cm, const uint64_t* rscan, const uint64_t* cscan,
+                                                    uint64_t* mstart) {
+  enc_seg2(cm, rscan, cscan, mstart);
+}
+
 // C' offsets and headers (the prefixes of k_enc_seg2's sizes are in).
-__global__ __launch_bounds__(BLOCK) void k_enc_seg3(Common cm, uint8_t* newref, int64_t newref_cap,
-                                                    int64_t* newref_off, uint64_t* gex) {
+__device__ void enc_seg3(Common cm, uint8_t* newref, int64_t newref_cap,
+                         int64_t* newref_off, uint64_t* gex) {
   if (status_of(cm.status) & ANY_ERR) return;
   const bool fits = cm.opre[cm.nseg] <= (uint64_t)newref_cap;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -683,7 +694,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_seg3(Common cm, uint8_t* newref, 
     gex[cm.meta[3]] = 0;
     if (!fits) fail(cm.status, ERR_CAPACITY);
   }
-  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * blockDim.x) {
     Seg& g = cm.seg[s];
     const uint64_t oref = cm.opre[s];
     g.fixed_excl = cm.fxpre[s];
@@ -700,6 +711,11 @@ __global__ __launch_bounds__(BLOCK) void k_enc_seg3(Common cm, uint8_t* newref, 
     h[3] = 0;
     if (n & 1) *reinterpret_cast<uint32_t*>(o + 32 + 4 * n) = 0;
   }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_enc_seg3(Common cm, uint8_t* newref, int64_t newref_cap,
+                                                    int64_t* newref_off, uint64_t* gex) {
+  enc_seg3(cm, newref, newref_cap, newref_off, gex);
 }
 
 // Directory of matched records; C' offsets of matched records.
@@ -1418,11 +1434,11 @@ __global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t
 // =============================================================================
 // One thread per segment: header checks and section sizes (scanned
 // afterwards by k_scan_cols).
-__global__ __launch_bounds__(BLOCK) void k_dec_setup(Common cm, const uint8_t* enc, int64_t enc_len,
-                                                     const int64_t* enc_off, const uint8_t* ref, int64_t ref_len,
-                                                     const int64_t* ref_off, bool have_pred, ClearFirst cf) {
+__device__ void dec_setup(Common cm, const uint8_t* enc, int64_t enc_len,
+                          const int64_t* enc_off, const uint8_t* ref, int64_t ref_len,
+                          const int64_t* ref_off, bool have_pred, ClearFirst cf) {
   do_clear_first(cf);
-  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * blockDim.x) {
     uint64_t nr = 0, G = 0, nn = 0, osz = 0, PG = 0, hs = 0;
     for (int k = 0; k < FOLD_SLOTS; ++k) cm.fold[s * FOLD_SLOTS + k] = 0;
     {
@@ -1508,6 +1524,41 @@ __global__ __launch_bounds__(BLOCK) void k_dec_setup(Common cm, const uint8_t* e
     col(cm, 4)[s] = PG;
     col(cm, 5)[s] = hs;
   }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_dec_setup(Common cm, const uint8_t* enc, int64_t enc_len,
+                                                     const int64_t* enc_off, const uint8_t* ref, int64_t ref_len,
+                                                     const int64_t* ref_off, bool have_pred, ClearFirst cf) {
+  dec_setup(cm, enc, enc_len, enc_off, ref, ref_len, ref_off, have_pred, cf);
+}
+
+// Few segments: a call's per-segment passes and their column scans in one
+// block of 1024 threads (one launch instead of two or three).
+__global__ __launch_bounds__(1024) void k_enc_setup1(Common cm, const uint8_t* cur, int64_t cur_len,
+                                                     const int64_t* cur_off, const uint8_t* ref, int64_t ref_len,
+                                                     const int64_t* ref_off, ClearFirst cf, ColScan cs, int ncols) {
+  __shared__ uint64_t s_w[16];
+  enc_setup(cm, cur, cur_len, cur_off, ref, ref_len, ref_off, cf);
+  __syncthreads();
+  scan_columns_small(cs, ncols, s_w);
+}
+__global__ __launch_bounds__(1024) void k_enc_layout1(Common cm, const uint64_t* rscan, const uint64_t* cscan,
+                                                      uint64_t* mstart, ColScan cs, int ncols, uint8_t* newref,
+                                                      int64_t newref_cap, int64_t* newref_off, uint64_t* gex) {
+  __shared__ uint64_t s_w[16];
+  enc_seg2(cm, rscan, cscan, mstart);
+  __syncthreads();
+  scan_columns_small(cs, ncols, s_w);
+  enc_seg3(cm, newref, newref_cap, newref_off, gex);
+}
+__global__ __launch_bounds__(1024) void k_dec_setup1(Common cm, const uint8_t* enc, int64_t enc_len,
+                                                     const int64_t* enc_off, const uint8_t* ref, int64_t ref_len,
+                                                     const int64_t* ref_off, bool have_pred, ClearFirst cf,
+                                                     ColScan cs, int ncols) {
+  __shared__ uint64_t s_w[16];
+  dec_setup(cm, enc, enc_len, enc_off, ref, ref_len, ref_off, have_pred, cf);
+  __syncthreads();
+  scan_columns_small(cs, ncols, s_w);
 }
 
 // Every reference slot: its size in words, whether the encoding keeps it
@@ -2410,10 +2461,18 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   m.cm.status = c->d_status;
   const int g = c->grid;
   const int gseg = grid_for(c, nseg, BLOCK);
-  k_enc_setup<<<gseg, BLOCK, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off,
-                                     clear_first(c, ceil_div(b.E + 1, SCAN_TILE)));
-  k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.cpre, m.cm.rpre, m.cm.hpre, m.cm.tpre, m.cm.jepre, m.cm.bpre},
-                                          {0, 1, 2, 10, 11, 12}, {b.C, b.R, b.H, b.T, b.E, b.B}));
+  const bool few = nseg <= FUSE_NSEG;
+  {
+    const ClearFirst cf = clear_first(c, ceil_div(b.E + 1, SCAN_TILE));
+    const ColScan cs = col_scan(m.cm, {m.cm.cpre, m.cm.rpre, m.cm.hpre, m.cm.tpre, m.cm.jepre, m.cm.bpre},
+                                {0, 1, 2, 10, 11, 12}, {b.C, b.R, b.H, b.T, b.E, b.B});
+    if (few) {
+      k_enc_setup1<<<1, 1024, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off, cf, cs, 6);
+    } else {
+      k_enc_setup<<<gseg, BLOCK, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off, cf);
+      k_scan_cols<<<6, 1024, 0, s>>>(cs);
+    }
+  }
   {
     Timed tm(c, "encode_join", s);
     JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag, m.tab};
@@ -2428,10 +2487,16 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                                                                      lookback(c, 1));
   k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, b.C, m.cscan,
                                                                    lookback(c, 2));
-  k_enc_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart);
-  k_scan_cols<<<4, 1024, 0, s>>>(col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4},
-                                          {b.G, -1, -1, -1}));
-  k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
+  {
+    const ColScan cs = col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4}, {b.G, -1, -1, -1});
+    if (few) {
+      k_enc_layout1<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart, cs, 4, newref, newref_cap, newref_off, m.gex);
+    } else {
+      k_enc_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart);
+      k_scan_cols<<<4, 1024, 0, s>>>(cs);
+      k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
+    }
+  }
   k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg,
                                  m.gfirst);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
@@ -2505,10 +2570,17 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   m.cm.status = c->d_status;
   const int g = c->grid;
   const int gseg = grid_for(c, nseg, BLOCK);
-  k_dec_setup<<<gseg, BLOCK, 0, s>>>(m.cm, enc, enc_len, enc_off, ref, ref_len, ref_off, pred != nullptr,
-                                     clear_first(c, ceil_div(b.R + 1, SCAN_TILE)));
-  k_scan_cols<<<6, 1024, 0, s>>>(col_scan(m.cm, {m.cm.rpre, m.cm.gpre, m.cm.npre, m.cm.opre, m.cm.ppre, m.cm.hpre},
-                                          {1, 3, 6, -1, 4, 2}, {b.R, b.G, b.C, -1, -1, b.H}));
+  {
+    const ClearFirst cf = clear_first(c, ceil_div(b.R + 1, SCAN_TILE));
+    const ColScan cs = col_scan(m.cm, {m.cm.rpre, m.cm.gpre, m.cm.npre, m.cm.opre, m.cm.ppre, m.cm.hpre},
+                                {1, 3, 6, -1, 4, 2}, {b.R, b.G, b.C, -1, -1, b.H});
+    if (nseg <= FUSE_NSEG) {
+      k_dec_setup1<<<1, 1024, 0, s>>>(m.cm, enc, enc_len, enc_off, ref, ref_len, ref_off, pred != nullptr, cf, cs, 6);
+    } else {
+      k_dec_setup<<<gseg, BLOCK, 0, s>>>(m.cm, enc, enc_len, enc_off, ref, ref_len, ref_off, pred != nullptr, cf);
+      k_scan_cols<<<6, 1024, 0, s>>>(cs);
+    }
+  }
   k_dec_rslots<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre);
   k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
                                                                      m.rscan, lookback(c, 0));

@@ -405,10 +405,9 @@ struct ColScan {
   int64_t n;
 };
 
-[[maybe_unused]] static __global__ __launch_bounds__(1024) void k_scan_cols(ColScan a) {
-  __shared__ uint64_t s_v[COL_CHUNK];
-  __shared__ uint64_t s_w[16];
-  const int c = blockIdx.x;
+// Column c of a ColScan, by one block of 1024 threads (s_v: COL_CHUNK
+// values, s_w: 16 words of LDS).  Ends with a block barrier.
+__device__ inline void scan_column(const ColScan& a, int c, uint64_t* s_v, uint64_t* s_w) {
   const uint64_t* in = a.in[c];
   uint64_t* out = a.out[c];
   const int t = threadIdx.x;
@@ -444,6 +443,40 @@ struct ColScan {
     if (a.meta && a.meta_idx[c] >= 0) a.meta[a.meta_idx[c]] = (int64_t)carry;
     if (carry > a.cap[c] && a.status) fail(a.status, ERR_CAPACITY);
   }
+  __syncthreads();
+}
+
+// One block of 1024 threads per column.
+[[maybe_unused]] static __global__ __launch_bounds__(1024) void k_scan_cols(ColScan a) {
+  __shared__ uint64_t s_v[COL_CHUNK];
+  __shared__ uint64_t s_w[16];
+  scan_column(a, blockIdx.x, s_v, s_w);
+}
+
+// Segment counts up to which a call's per-segment passes and their column
+// scans run as one block of 1024 threads in one launch (fewer launches; above
+// it, one thread per segment over many blocks is faster).
+constexpr int64_t FUSE_NSEG = 127;
+
+// All columns of a ColScan with n <= FUSE_NSEG (so n + 1 values fit 128
+// threads) at once, column c by threads [128 c, 128 c + 128) of a block of
+// 1024: one load per value, a wave scan, the two waves of a column joined
+// through s_w (16 words of LDS).  Ends with a block barrier.
+__device__ inline void scan_columns_small(const ColScan& a, int ncols, uint64_t* s_w) {
+  const int t = threadIdx.x, c = t / 128, i = t % 128;
+  const bool on = c < ncols;
+  const uint64_t v = on && i < a.n ? a.in[c][i] : 0;
+  const uint64_t incl = wave_incl_scan64(v);
+  if (lane_id() == WAVE - 1) s_w[t / WAVE] = incl;
+  __syncthreads();
+  const uint64_t lo = (t / WAVE) & 1 ? s_w[t / WAVE - 1] : 0;  // the column's first wave
+  if (on && i <= a.n) a.out[c][i] = lo + incl - v;            // (i = n: the total)
+  if (on && i == 0) {
+    const uint64_t tot = s_w[2 * c] + s_w[2 * c + 1];
+    if (a.meta && a.meta_idx[c] >= 0) a.meta[a.meta_idx[c]] = (int64_t)tot;
+    if (tot > a.cap[c] && a.status) fail(a.status, ERR_CAPACITY);
+  }
+  __syncthreads();
 }
 
 __device__ inline uint64_t ld64(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }

@@ -93,19 +93,22 @@ struct WordsIn {
 
 // Message sizes (one thread per segment), scanned by k_scan_cols into the
 // message offsets; then k_ser_heads writes the headers.
-__global__ __launch_bounds__(BLOCK) void k_ser_sizes(const int64_t* seg_off, int64_t nseg, SerScratch sc,
-                                                     uint32_t* status) {
+__device__ void ser_sizes(const int64_t* seg_off, int64_t nseg, SerScratch sc, uint32_t* status) {
   const bool bad = (status_of(status) & (1u << ERR_INVALID)) != 0;
-  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t n = bad ? 0 : (uint64_t)(seg_off[s + 1] - seg_off[s]);
     const uint64_t rw = bad ? 0 : sc.wpre[seg_off[s + 1]] - sc.wpre[seg_off[s]];
     sc.size[s] = tam1_size(n, rw);
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_ser_heads(const int64_t* seg_off, int64_t nseg, SerScratch sc,
-                                                     uint8_t* out, int64_t out_cap, const int64_t* msg_off,
+__global__ __launch_bounds__(BLOCK) void k_ser_sizes(const int64_t* seg_off, int64_t nseg, SerScratch sc,
                                                      uint32_t* status) {
+  ser_sizes(seg_off, nseg, sc, status);
+}
+
+__device__ void ser_heads(const int64_t* seg_off, int64_t nseg, SerScratch sc, uint8_t* out, int64_t out_cap,
+                          const int64_t* msg_off, uint32_t* status) {
   const bool bad = (status_of(status) & (1u << ERR_INVALID)) != 0;
   const uint64_t total = (uint64_t)msg_off[nseg];
   const bool fits = total <= (uint64_t)out_cap && !bad;
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(BLOCK) void k_ser_heads(const int64_t* seg_off, int
     sc.meta[1] = fits ? (int64_t)sc.wpre[sc.meta[0]] : 0;
   }
   if (!fits) return;
-  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * BLOCK) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * blockDim.x) {
     uint8_t* m = out + msg_off[s];
     const uint64_t n = (uint64_t)(seg_off[s + 1] - seg_off[s]);
     const uint64_t rw = sc.wpre[seg_off[s + 1]] - sc.wpre[seg_off[s]];
@@ -125,6 +128,23 @@ __global__ __launch_bounds__(BLOCK) void k_ser_heads(const int64_t* seg_off, int
     h[3] = 0;
     if (n & 1) *reinterpret_cast<uint32_t*>(m + 32 + 4 * n) = 0;
   }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_ser_heads(const int64_t* seg_off, int64_t nseg, SerScratch sc,
+                                                     uint8_t* out, int64_t out_cap, const int64_t* msg_off,
+                                                     uint32_t* status) {
+  ser_heads(seg_off, nseg, sc, out, out_cap, msg_off, status);
+}
+
+// Few segments: message sizes, their offsets and the headers in one block.
+__global__ __launch_bounds__(1024) void k_ser_layout1(const int64_t* seg_off, int64_t nseg, SerScratch sc,
+                                                      uint8_t* out, int64_t out_cap, int64_t* msg_off, ColScan cs,
+                                                      uint32_t* status) {
+  __shared__ uint64_t s_w[16];
+  ser_sizes(seg_off, nseg, sc, status);
+  __syncthreads();
+  scan_columns_small(cs, 1, s_w);
+  ser_heads(seg_off, nseg, sc, out, out_cap, msg_off, status);
 }
 
 struct PackArgs {
@@ -282,18 +302,22 @@ extern "C" ta_status ta_serialize(ta_ctx* c, const ta_agents* ag, const int32_t*
                                   c->d_status);
   WordsIn win{idx, ag->cls, ag->beh_off, c->d_nf, c->d_ni, c->n_classes, ag->n, c->d_status};
   k_scan<WordsIn><<<grid_for(c, idx_cap + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(win, sc.meta, idx_cap, sc.wpre, lookback(c, 0));
-  k_ser_sizes<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, sc, c->d_status);
   {
     ColScan cs{};
     cs.in[0] = sc.size;
     cs.out[0] = reinterpret_cast<uint64_t*>(msg_off);
-    cs.cap[0] = ~0ull;  // the output capacity is checked by k_ser_heads
+    cs.cap[0] = ~0ull;  // the output capacity is checked with the headers
     cs.meta_idx[0] = -1;
     cs.status = c->d_status;
     cs.n = nseg;
-    k_scan_cols<<<1, 1024, 0, s>>>(cs);
+    if (nseg <= FUSE_NSEG) {
+      k_ser_layout1<<<1, 1024, 0, s>>>(seg_off, nseg, sc, out, out_cap, msg_off, cs, c->d_status);
+    } else {
+      k_ser_sizes<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, sc, c->d_status);
+      k_scan_cols<<<1, 1024, 0, s>>>(cs);
+      k_ser_heads<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, sc, out, out_cap, msg_off, c->d_status);
+    }
   }
-  k_ser_heads<<<gseg, BLOCK, 0, s>>>(seg_off, nseg, sc, out, out_cap, msg_off, c->d_status);
   {
     Timed tm(c, "serialize_pack", s);
     PackArgs pa{ag->uid, ag->cls, ag->nb, ag->f64, ag->f64_stride, ag->i32, ag->i32_stride, ag->beh_off,
