@@ -28,9 +28,9 @@
 //   learned mode instead: k_enc_resid (C' words and both dense residuals),
 //                  k_enc_gsize (bitmaps, block sizes), scans, k_choose_mode,
 //                  k_enc_place (blocks of the chosen variant)
-//   k_enc_fin      encoding offsets and headers
-//   k_enc_fixed    presence bitmaps, word bitmaps, block size tables, new
-//                  record sizes, C' offsets of new records
+//   k_enc_fixed    encoding offsets and headers; presence bitmaps, word
+//                  bitmaps, block size tables, new record sizes, C' offsets
+//                  of new records
 //   k_enc_newcopy  new records into the encoding and into C'
 // Decoder: k_dec_setup (header checks), k_dec_rslots (reference slots,
 // presence bits), scans of matched slots, new records and group blocks,
@@ -1292,14 +1292,23 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
   }
 }
 
-// Encoding offsets and headers.
-__global__ __launch_bounds__(BLOCK) void k_enc_fin(Common cm, const uint64_t* gex, uint8_t* enc, int64_t enc_cap,
-                                                   int64_t* enc_off, uint8_t* modes) {
+
+// The encodings' offsets and headers (per segment), then their fixed
+// sections: presence bitmaps (one wave per 64 reference slots), word bitmaps
+// and block size tables (per group), new record sizes and C' offsets (per C
+// record).  A segment's encoding starts at its fixed bytes' prefix plus the
+// block bytes before its first group.  The offsets are written even when the
+// encodings do not fit (they give the size needed).
+__global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m, const uint8_t* cflag,
+                                                     const uint32_t* cwords, const uint64_t* cscan,
+                                                     const uint64_t* bm, const uint8_t* gsz, const uint64_t* gex,
+                                                     uint8_t* enc, int64_t enc_cap, int64_t* enc_off, uint8_t* modes,
+                                                     uint8_t* newref) {
   if (status_of(cm.status) & ANY_ERR) return;
-  const uint64_t total = (uint64_t)cm.meta[9] + gex[cm.meta[3]];
-  const bool fits = total <= (uint64_t)enc_cap;
+  const uint64_t total_bytes = (uint64_t)cm.meta[9] + gex[cm.meta[3]];
+  const bool fits = total_bytes <= (uint64_t)enc_cap;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    enc_off[cm.nseg] = (int64_t)total;
+    enc_off[cm.nseg] = (int64_t)total_bytes;
     if (!fits) fail(cm.status, ERR_CAPACITY);
   }
   for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
@@ -1319,25 +1328,21 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fin(Common cm, const uint64_t* ge
     h[6] = g.new_words;
     h[7] = gex[cm.gpre[s + 1]] - gex[cm.gpre[s]];
   }
-}
-
-// Presence bitmaps (one wave per 64 reference slots), word bitmaps and block
-// size tables (per group), new record sizes and C' offsets (per C record).
-__global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m, const uint8_t* cflag,
-                                                     const uint32_t* cwords, const uint64_t* cscan,
-                                                     const uint64_t* bm, const uint8_t* gsz, uint8_t* enc,
-                                                     int64_t enc_cap, uint8_t* newref) {
-  if (status_of(cm.status) & ANY_ERR) return;
+  if (!fits) return;
+  auto encm = [&](int64_t s) { return cm.seg[s].fixed_excl + gex[cm.gpre[s]]; };
   // presence items first, padded to whole blocks so that every wave of the
-  // range works on one presence word; then groups, then C records
+  // range works on one presence word; then groups, padded to whole waves;
+  // then C records (every wave in one range: its segment found once)
   const int64_t A = (64 * cm.meta[4] + BLOCK - 1) / BLOCK * BLOCK, B = cm.meta[3], Cn = cm.meta[0];
-  const int64_t total = A + B + Cn;
+  const int64_t B64 = (B + 63) / 64 * 64;
+  const int64_t total = A + B64 + Cn;
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   const int l = lane_id();
   for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < total; base += stride) {
-    const int64_t it = base + threadIdx.x;
-    if (base < A) {  // whole waves: presence words (A is a multiple of 64, BLOCK too)
-      const int64_t pw = (base + 64 * wave_id()) / 64;
+    const int64_t wbase = base + 64 * wave_id();  // the wave's first item
+    const int64_t it = wbase + l;
+    if (wbase < A) {  // presence words (A is a multiple of 64, BLOCK too)
+      const int64_t pw = wbase / 64;
       bool bit = false;
       int64_t s = 0;
       if (pw < cm.meta[4]) {
@@ -1346,32 +1351,33 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
         bit = j < cm.seg[s].nr && m[cm.rpre[s] + j] >= 0;
       }
       const uint64_t word = __ballot(bit);
-      if (pw < cm.meta[4] && l == 0) {
-        const Seg& g = cm.seg[s];
-        *reinterpret_cast<uint64_t*>(enc + g.encm + 64 + 8 * (pw - cm.ppre[s])) = word;
-      }
-      continue;
-    }
-    if (it >= total) continue;
-    if (it < A + B) {
+      if (pw < cm.meta[4] && l == 0) *reinterpret_cast<uint64_t*>(enc + encm(s) + 64 + 8 * (pw - cm.ppre[s])) = word;
+    } else if (wbase < A + B64) {  // groups
+      const int64_t g0 = wbase - A;
+      if (g0 >= B) continue;
+      const int64_t gl = g0 + 63 < B ? g0 + 63 : B - 1;
       const int64_t gg = it - A;
-      const int64_t s = seg_of(cm.gpre, cm.nseg, (uint64_t)gg);
+      const int64_t s = wave_seg(cm.gpre, cm.nseg, (uint64_t)(gg < B ? gg : B - 1), (uint64_t)g0, (uint64_t)gl);
+      if (gg >= B) continue;
       const Seg& g = cm.seg[s];
       const uint64_t lg = gg - cm.gpre[s];
-      uint8_t* sec = enc + g.encm + 64 + 8 * g.PG;
+      uint8_t* sec = enc + encm(s) + 64 + 8 * g.PG;
       *reinterpret_cast<uint64_t*>(sec + 8 * lg) = bm[gg];
       sec += 8 * g.G;
       sec[lg] = gsz[gg];
       if (lg == g.G - 1)
         for (uint64_t b = g.G; b < round8(g.G); ++b) sec[b] = 0;
-    } else {
-      const int64_t gc = it - A - B;
-      if (cflag[gc]) continue;
-      const int64_t s = seg_of(cm.cpre, cm.nseg, (uint64_t)gc);
+    } else {  // C records
+      const int64_t c0 = wbase - A - B64;
+      if (c0 >= Cn) continue;
+      const int64_t cl = c0 + 63 < Cn ? c0 + 63 : Cn - 1;
+      const int64_t gc = it - A - B64;
+      const int64_t s = wave_seg(cm.cpre, cm.nseg, (uint64_t)(gc < Cn ? gc : Cn - 1), (uint64_t)c0, (uint64_t)cl);
+      if (gc >= Cn || cflag[gc]) continue;
       const Seg& g = cm.seg[s];
       const uint64_t r = (cscan[gc] >> PK) - g.nbase;
       const uint64_t np = (cscan[gc] & WMASK) - g.npbase;
-      uint8_t* ns = enc + g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G);
+      uint8_t* ns = enc + encm(s) + 64 + 8 * g.PG + 8 * g.G + round8(g.G);
       *reinterpret_cast<uint32_t*>(ns + 4 * r) = cwords[gc];
       if (r == g.n_new - 1 && (g.n_new & 1)) *reinterpret_cast<uint32_t*>(ns + 4 * (r + 1)) = 0;
       *reinterpret_cast<uint32_t*>(newref + g.oref + 32 + 4 * (g.n_match + r)) = (uint32_t)(g.W + np);
@@ -2536,8 +2542,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     }
     k_enc_place<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg, m.gex);
   }
-  k_enc_fin<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, enc, enc_cap, enc_off, modes);
-  k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.cflag, m.cwords, m.cscan, m.bm, m.gsz, enc, enc_cap, newref);
+  k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.cflag, m.cwords, m.cscan, m.bm, m.gsz, m.gex, enc, enc_cap, enc_off,
+                                  modes, newref);
   k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.cflag, m.cwords, cur, enc, newref);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
