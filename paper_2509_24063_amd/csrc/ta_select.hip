@@ -167,13 +167,21 @@ struct CntIn {
 
 // Per-direction thread counts (<= 8) packed 5 to a word in 12-bit fields, so a
 // block-wide exclusive scan of NW words gives all directions at once (block
-// totals <= 2048 < 4096: no field overflows into the next).
+// totals <= 2048 < 4096: no field overflows into the next).  Two tables per
+// block, indexed by an agent's 6-bit code, turn counting into lookups: the
+// packed increments of the directions the code belongs to, and those
+// directions as a bit mask; a wave then scatters only into the directions
+// some of its agents belong to.
 template <int NDIRS>
 __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, int32_t P, DirTable dt, SelScratch sc,
                                                        int32_t* idx_out, int64_t idx_cap, int64_t* seg_off,
                                                        uint32_t* status) {
   constexpr int NW = (NDIRS + 4) / 5;
   __shared__ uint64_t s_w[WAVES][NW];
+  __shared__ uint64_t s_inc[64][NW];  // per code: +1 in the field of every direction it belongs to
+  __shared__ uint32_t s_dm[64];       // per code: its directions, one bit each
+  __shared__ uint32_t s_wm[WAVES];    // per wave: directions some of its agents belong to
+  __shared__ uint32_t s_req[NDIRS];   // code bits each direction requires
   const int64_t nseg = (int64_t)P * NDIRS;
   const int64_t gstride = (int64_t)gridDim.x * BLOCK;
   for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s <= nseg; s += gstride) {
@@ -188,6 +196,25 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
     }
     seg_off[s] = pos;
   }
+  for (int c = threadIdx.x; c < 64; c += BLOCK) {
+    uint64_t inc[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) inc[j] = 0;
+    uint32_t dm = 0;
+#pragma unroll
+    for (int d = 0; d < NDIRS; ++d) {
+      if (c && (c & dt.req[d]) == dt.req[d]) {
+        inc[d / 5] += 1ull << (12 * (d % 5));
+        dm |= 1u << d;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NW; ++j) s_inc[c][j] = inc[j];
+    s_dm[c] = dm;
+  }
+  if (threadIdx.x < NDIRS) s_req[threadIdx.x] = dt.req[threadIdx.x];
+  __syncthreads();
+  const int l = lane_id(), wv = wave_id();
   const int64_t ntiles = sc.meta[0];
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const TileInfo ti = tile_info(sc, part_off, P, t);
@@ -205,48 +232,57 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
     // most waves (agents away from the box faces) select nothing: they skip
     // the per-direction counts and only join the block scan with zeros
     const bool wave_any = __ballot(any != 0) != 0;
+    uint32_t lmask = 0;
     if (wave_any) {
 #pragma unroll
-      for (int d = 0; d < NDIRS; ++d) {
-        uint64_t c = 0;
+      for (int k = 0; k < SEL_IPT; ++k) {
 #pragma unroll
-        for (int k = 0; k < SEL_IPT; ++k) c += (code[k] & dt.req[d]) == dt.req[d] && code[k];
-        packed[d / 5] += c << (12 * (d % 5));
+        for (int j = 0; j < NW; ++j) packed[j] += s_inc[code[k]][j];
+        lmask |= s_dm[code[k]];
       }
     }
     // block exclusive scan of the packed words
     uint64_t incl[NW];
 #pragma unroll
     for (int j = 0; j < NW; ++j) incl[j] = wave_incl_scan64(packed[j]);
-    if (lane_id() == WAVE - 1) {
+    if (l == WAVE - 1) {
 #pragma unroll
-      for (int j = 0; j < NW; ++j) s_w[wave_id()][j] = incl[j];
+      for (int j = 0; j < NW; ++j) s_w[wv][j] = incl[j];
     }
+    if (l == 0) s_wm[wv] = 0;
     __syncthreads();
     uint64_t pre[NW];
 #pragma unroll
     for (int j = 0; j < NW; ++j) {
       uint64_t off = 0;
 #pragma unroll
-      for (int wv = 0; wv < WAVES; ++wv) off += (wv < wave_id()) ? s_w[wv][j] : 0;
+      for (int w = 0; w < WAVES; ++w) off += (w < wv) ? s_w[w][j] : 0;
       pre[j] = off + incl[j] - packed[j];
     }
+    if (lmask) atomicOr(&s_wm[wv], lmask);
     __syncthreads();
+    const uint32_t wm = uniform32(s_wm[wv]);
     const int64_t cbase = sc.tile_off[ti.p] * NDIRS + ti.lt;
-    if (!wave_any) continue;
+    // the wave's directions, one at a time: the packed word of five
+    // directions by a static index, its directions present by a uniform loop
 #pragma unroll
-    for (int d = 0; d < NDIRS; ++d) {
-      const uint64_t mine = (packed[d / 5] >> (12 * (d % 5))) & 0xFFF;
-      if (!mine) continue;
-      int64_t pos = (int64_t)sc.cnt_pre[cbase + d * ti.nt] + (int64_t)((pre[d / 5] >> (12 * (d % 5))) & 0xFFF);
+    for (int j = 0; j < NW; ++j) {
+      for (uint32_t mm = (wm >> (5 * j)) & 31u; mm; mm &= mm - 1) {
+        const int b = __builtin_ctz(mm), d = 5 * j + b, sh = 12 * b;
+        const uint64_t mine = (packed[j] >> sh) & 0xFFF;
+        if (!mine) continue;
+        const uint32_t req = s_req[d];
+        int64_t pos = (int64_t)sc.cnt_pre[cbase + d * ti.nt] + (int64_t)((pre[j] >> sh) & 0xFFF);
 #pragma unroll
-      for (int k = 0; k < SEL_IPT; ++k) {
-        if (code[k] && (code[k] & dt.req[d]) == dt.req[d]) {
-          if (pos < idx_cap) idx_out[pos] = (int32_t)(i0 + k);
-          ++pos;
+        for (int k = 0; k < SEL_IPT; ++k) {
+          if (code[k] && (code[k] & req) == req) {
+            if (pos < idx_cap) idx_out[pos] = (int32_t)(i0 + k);
+            ++pos;
+          }
         }
       }
     }
+    __syncthreads();  // s_w and s_wm are reused by the next tile
   }
 }
 
