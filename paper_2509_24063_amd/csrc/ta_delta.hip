@@ -1909,17 +1909,21 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
         const uint32_t sw = *reinterpret_cast<const uint32_t*>(e + 64 + 8 * sg.PG + 8 * sg.G + (lg & ~3ull));
         const uint32_t size = uniform32(8u * ((sw >> (8 * (lg & 3))) & 0xFFu));
         sizev[x] = size;
-        if (l <= 32 && k0 + l < (uint64_t)M) {
-          // clamped to [-2^30, 64]: lane 0's record may start long before the group
-          const int64_t r = (int64_t)a.mstart[k0 + l] - (int64_t)(sg.dbase + 64 * lg);
-          relv[x] = r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r);
-          rwv[x] = a.mrw[k0 + l];
-        }
-        if (size <= BLK_MAX) {
+        // (loads from clamped indices, not behind divergent branches: a group
+        // implies a matched record, so M >= 1)
+        const bool has = l <= 32 && k0 + l < (uint64_t)M;
+        const uint64_t kk = has ? k0 + l : (uint64_t)M - 1;
+        const int64_t r = (int64_t)a.mstart[kk] - (int64_t)(sg.dbase + 64 * lg);
+        const uint32_t rwk = a.mrw[kk];
+        // clamped to [-2^30, 64]: lane 0's record may start long before the group
+        relv[x] = !has ? 64 : (r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r));
+        rwv[x] = has ? rwk : 0u;
+        if (size > 0 && size <= BLK_MAX) {  // uniform; lanes past the block read its last word
           const uint64_t* src =
               reinterpret_cast<const uint64_t*>(enc + uniform64(sg.encm + sg.fixed + (gex[gg] - gex[gpre[sx]])));
-          if ((uint32_t)l < size / 8) b0v[x] = src[l];
-          if (size > 8 * WAVE && (uint32_t)(WAVE + l) < size / 8) b1v[x] = src[WAVE + l];
+          const uint32_t nwd = size / 8;
+          b0v[x] = src[(uint32_t)l < nwd ? (uint32_t)l : nwd - 1];
+          if (size > 8 * WAVE) b1v[x] = src[(uint32_t)(WAVE + l) < nwd ? (uint32_t)(WAVE + l) : nwd - 1];
         }
       }
     }
@@ -1948,14 +1952,17 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
       const uint64_t lg = uniform64((uint64_t)gg - gpre[sx]);
       const bool live = 64 * lg + (uint64_t)l < sg.W;
       const uint64_t* rbody = a.ref + uniform64(sg.rbody / 8);  // the segment's reference records
+      // (a word that is not live reads word 0 of lane 0's record, the one
+      // holding the group's first word: in the segment, always valid)
+      const uint32_t ri = live ? rw + off : (uint32_t)__builtin_amdgcn_readlane((int)rwv[x], 0);
       if (uniform32((uint32_t)sg.mode) == 1) {
-        if (live) {
-          const uint64_t k = uniform32(gfirst[gg]) + (uint64_t)idx;
-          const bool pred = off >= 2 && off < 6 && a.pred_on[k];
-          xwv[x] = pred ? a.pred_x[4 * k + (off - 2)] : rbody[rw + off];
-        }
-      } else if (live) {
-        xwv[x] = rbody[rw + off];
+        const uint64_t k = uniform32(gfirst[gg]) + (live ? (uint64_t)idx : 0);
+        const bool pred = live && off >= 2 && off < 6 && a.pred_on[k];
+        const uint64_t px = a.pred_x[4 * k + (pred ? off - 2 : 0)];
+        const uint64_t rx = rbody[ri];
+        xwv[x] = pred ? px : rx;
+      } else {
+        xwv[x] = rbody[ri];
       }
     }
     // blocks into LDS, residual words, output
