@@ -731,13 +731,14 @@ __device__ inline void map_groups(const Common& cm, int64_t s, uint64_t q0, uint
 }
 
 // Directory of the matched records, in C' order: C and R word, residual
-// start, slot; C' offsets; groups' segment and first record.  A wave takes
+// start, slot (learned mode), or the C and R word offsets in the segment's
+// record areas (plain mode); C' offsets; groups' segment and first record.  A wave takes
 // RS_U * 64 consecutive reference slots per pass and issues their loads in
 // two stages before it stores anything.
 __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
                                                     const int32_t* m, const uint64_t* rscan, const uint32_t* rwords,
-                                                    MDir* mdir, uint64_t* mstart, uint8_t* newref, uint32_t* gseg,
-                                                    uint32_t* gfirst) {
+                                                    MDir* mdir, uint64_t* crw, uint64_t* mstart, uint8_t* newref,
+                                                    uint32_t* gseg, uint32_t* gfirst) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
@@ -779,12 +780,15 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
       const Seg& sg = cm.seg[sx];
       const uint64_t k = rsv[u] >> PK;
       const uint64_t d = rsv[u] & WMASK;
-      MDir e;
-      e.cword = sg.cbody / 8 + coff[u];
-      e.rword = sg.rbody / 8 + roff[u];
-      e.dstart = d;
-      e.gs = (uint64_t)g | ((uint64_t)sx << 34);
-      mdir[k] = e;
+      if (mdir) {  // learned mode or a history to write: the full entry
+        MDir e;
+        e.cword = sg.cbody / 8 + coff[u];
+        e.rword = sg.rbody / 8 + roff[u];
+        e.dstart = d;
+        e.gs = (uint64_t)g | ((uint64_t)sx << 34);
+        mdir[k] = e;
+      }
+      if (crw) crw[k] = (uint64_t)coff[u] | ((uint64_t)roff[u] << 32);  // plain mode
       mstart[k] = d;
       *reinterpret_cast<uint32_t*>(newref + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
       map_groups(cm, sx, d - sg.dbase, rwv[u], gseg, gfirst, k);
@@ -1101,7 +1105,7 @@ struct GroupArgs {
   Common cm;
   const uint64_t* cur;     // (words)
   const uint64_t* ref;     // (words)
-  const MDir* mdir;        // [matched] C and R word of every matched record
+  const uint64_t* crw;     // [matched] C and R word offsets of every matched record (in the record areas)
   const uint64_t* mstart;  // [matched+1] residual start of every matched record
   uint64_t* newref;        // C' (words)
   uint8_t* enc;
@@ -1176,8 +1180,9 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
         has[x] = l <= 32 && k0 + l < (uint64_t)M;
         const uint64_t kk = has[x] ? k0 + l : (uint64_t)M - 1;
         mst[x] = a.mstart[kk];
-        cwd[x] = a.mdir[kk].cword;
-        rwd[x] = a.mdir[kk].rword;
+        const uint64_t crw = a.crw[kk];
+        cwd[x] = (uint32_t)crw;
+        rwd[x] = crw >> 32;
       }
       __builtin_amdgcn_sched_barrier(0);
       // start relative to the group (clamped to [-2^30, 64]), words relative to
@@ -1191,8 +1196,8 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
         const uint64_t g0w = uniform64(sg.dbase + 64 * ((uint64_t)gc[x] - gpre[sx]));  // first residual position
         const int64_t r = (int64_t)mst[x] - (int64_t)g0w;
         relv[x] = !has[x] ? 64 : (r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r));
-        cwv[x] = (uint32_t)(cwd[x] - sg.cbody / 8);
-        rwv[x] = (uint32_t)(rwd[x] - sg.rbody / 8);
+        cwv[x] = (uint32_t)cwd[x];
+        rwv[x] = (uint32_t)rwd[x];
         if (l >= 1 && relv[x] >= 1 && relv[x] < WAVE) s_mark[wv][x][relv[x]] = (uint32_t)gc[x] + 1;
       }
       wave_sync();
@@ -1812,12 +1817,14 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
       const Seg& sg = cm.seg[sx];
       const uint64_t k = rsv[u] >> PK;
       const uint64_t d = rsv[u] & WMASK;
-      MDir e;
-      e.cword = 0;
-      e.rword = sg.rbody / 8 + roff[u];
-      e.dstart = d;
-      e.gs = (uint64_t)g | ((uint64_t)sx << 34);
-      mdir[k] = e;
+      if (mdir) {  // learned mode or a history to write: the full entry
+        MDir e;
+        e.cword = 0;
+        e.rword = sg.rbody / 8 + roff[u];
+        e.dstart = d;
+        e.gs = (uint64_t)g | ((uint64_t)sx << 34);
+        mdir[k] = e;
+      }
       mstart[k] = d;
       mrw[k] = roff[u];  // word offset in the reference's record area
       *reinterpret_cast<uint32_t*>(out + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
@@ -2316,6 +2323,7 @@ struct Mem {
   uint64_t* rscan;
   uint64_t* cscan;  // encoder: new C records; decoder: new record words
   MDir* mdir;
+  uint64_t* crw;
   uint64_t* bm;
   uint8_t* gsz;
   uint64_t* gex;
@@ -2367,6 +2375,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.rscan = ar.take<uint64_t>(b.R + 1);
   m.cscan = ar.take<uint64_t>(std::max(b.C, b.R) + 1);
   m.mdir = ar.take<MDir>(b.R);
+  m.crw = ar.take<uint64_t>(b.R);
   m.bm = ar.take<uint64_t>(b.G);
   m.gsz = ar.take<uint8_t>(b.G);
   m.gex = ar.take<uint64_t>(b.G + 1);
@@ -2510,7 +2519,9 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
       k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
     }
   }
-  k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords, m.mdir, m.mstart, newref, m.gseg,
+  k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords,
+                                                              pred || hist_out ? m.mdir : nullptr, pred ? nullptr : m.crw,
+                                                              m.mstart, newref, m.gseg,
                                  m.gfirst);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
@@ -2524,7 +2535,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   }
   if (!pw) {
     Timed tm(c, "encode_groups", s);
-    GroupArgs ga{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir,
+    GroupArgs ga{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.crw,
                  m.mstart, reinterpret_cast<uint64_t*>(newref), enc, enc_cap, m.bm, m.gsz, m.gex};
     k_enc_groups<<<grid_for(c, b.G, EG_TILE), EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst,
                                                                  lookback(c, 3));
@@ -2602,7 +2613,8 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, b.G, m.gex,
                                                                      lookback(c, 2));
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
-  k_dec_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords, m.mdir, m.mstart, out, m.gseg, m.gfirst,
+  k_dec_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords,
+                                                              pred || hist_out ? m.mdir : nullptr, m.mstart, out, m.gseg, m.gfirst,
                                  m.mrw);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {

@@ -138,3 +138,39 @@ def test_learned_iterations_match_oracle(native, persistent, which):
     if which == "zero":
         assert learned_segments == 0  # zero weights never beat plain (ties go to plain)
     ctx.close()
+
+
+def test_plain_exchange_with_history(native):
+    """Plain encodings (no predictor) that still write the history of C',
+    on both sides: encodings, C' and the histories equal the oracle's."""
+    cfg = synth.config(1, median=3000.0)
+    world = synth.World(cfg)
+    ctx = native.Context(cfg.schema)
+    nseg = cfg.ndirs
+    ref, roff = native.empty_messages(nseg)
+    rx, rxoff = ref, roff
+    oref, ooff = oracle.empty_messages(nseg)
+    for it in range(4):
+        s = world.store
+        print(f"[plain history] iteration {it}", flush=True)
+        ds = native.DeviceStore(s)
+        idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs)
+        buf, moff = ctx.serialize(ds, idx, seg)
+        nrec = int(host(seg)[-1])
+        hout, hrxo = native.History(nrec), native.History(nrec)
+        enc, eoff, nref, noff, _ = ctx.delta_encode(buf, moff, ref, roff, hist_out=hout)
+        dec, doff = ctx.delta_decode(enc, eoff, rx, rxoff, hist_out=hrxo)
+        ctx.check(f"iteration {it}")
+        obuf, omoff = oracle.serialize(s, cfg.schema, *oracle.select_aura(s, cfg.w, cfg.ndirs))
+        oenc, oeoff, onref, onoff, _, onh = oracle.encode_all(obuf, omoff, oref, ooff, want_hist=True)
+        assert np.array_equal(host(enc, host(eoff)), oenc)
+        assert np.array_equal(host(nref, host(noff)), onref)
+        assert np.array_equal(host(dec, host(doff)), onref)
+        for hh in (hout, hrxo):
+            a1, a2, al = hh.numpy()
+            assert np.array_equal(a1, onh.h1) and np.array_equal(a2, onh.h2) and np.array_equal(al, onh.hlen)
+        ref, roff = nref[: int(host(noff)[-1])].clone(), noff.clone()
+        rx, rxoff = dec[: int(host(doff)[-1])].clone(), doff.clone()
+        oref, ooff = onref, onoff
+        world.step()
+    ctx.close()
