@@ -29,9 +29,9 @@
 //                  k_enc_gsize (bitmaps, block sizes), scans, k_choose_mode,
 //                  k_enc_place (blocks of the chosen variant)
 //   k_enc_fixed    encoding offsets and headers; presence bitmaps, word
-//                  bitmaps, block size tables, new record sizes, C' offsets
-//                  of new records
-//   k_enc_newcopy  new records into the encoding and into C'
+//                  bitmaps, block size tables
+//   k_enc_newcopy  new record sizes, C' offsets of new records, new records
+//                  into the encoding and into C'
 // Decoder: k_dec_setup (header checks), k_dec_rslots (reference slots,
 // presence bits), scans of matched slots, new records and group blocks,
 // k_dec_seg2 (checks against the header, C' headers), k_dec_mdir, then
@@ -627,12 +627,16 @@ struct RMatchIn {
     }
   }
 };
-struct CNewIn {  // count << 34 | words of new current records
+struct CNewIn {  // count << 34 | words of new current records; nlist[rank] = index of each new record
   const uint8_t* cflag;
   const uint32_t* cwords;
+  uint32_t* nlist;
   __device__ uint64_t operator()(int64_t g) const {
     const uint64_t w = cwords[g];
     return cflag[g] ? 0 : ((1ull << PK) | w);
+  }
+  __device__ void emit(int64_t g, uint64_t excl, uint64_t v) const {
+    if (v) nlist[excl >> PK] = (uint32_t)g;
   }
 };
 
@@ -1300,15 +1304,13 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
 
 // The encodings' offsets and headers (per segment), then their fixed
 // sections: presence bitmaps (one wave per 64 reference slots), word bitmaps
-// and block size tables (per group), new record sizes and C' offsets (per C
-// record).  A segment's encoding starts at its fixed bytes' prefix plus the
+// and block size tables (per group).  The new record sizes and the C'
+// offsets of new records are written by k_enc_newcopy.  A segment's encoding starts at its fixed bytes' prefix plus the
 // block bytes before its first group.  The offsets are written even when the
 // encodings do not fit (they give the size needed).
-__global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m, const uint8_t* cflag,
-                                                     const uint32_t* cwords, const uint64_t* cscan,
-                                                     const uint64_t* bm, const uint8_t* gsz, const uint64_t* gex,
-                                                     uint8_t* enc, int64_t enc_cap, int64_t* enc_off, uint8_t* modes,
-                                                     uint8_t* newref) {
+__global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m, const uint64_t* bm,
+                                                     const uint8_t* gsz, const uint64_t* gex, uint8_t* enc,
+                                                     int64_t enc_cap, int64_t* enc_off, uint8_t* modes) {
   if (status_of(cm.status) & ANY_ERR) return;
   const uint64_t total_bytes = (uint64_t)cm.meta[9] + gex[cm.meta[3]];
   const bool fits = total_bytes <= (uint64_t)enc_cap;
@@ -1336,11 +1338,9 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
   if (!fits) return;
   auto encm = [&](int64_t s) { return cm.seg[s].fixed_excl + gex[cm.gpre[s]]; };
   // presence items first, padded to whole blocks so that every wave of the
-  // range works on one presence word; then groups, padded to whole waves;
-  // then C records (every wave in one range: its segment found once)
-  const int64_t A = (64 * cm.meta[4] + BLOCK - 1) / BLOCK * BLOCK, B = cm.meta[3], Cn = cm.meta[0];
-  const int64_t B64 = (B + 63) / 64 * 64;
-  const int64_t total = A + B64 + Cn;
+  // range works on one presence word; then groups
+  const int64_t A = (64 * cm.meta[4] + BLOCK - 1) / BLOCK * BLOCK, B = cm.meta[3];
+  const int64_t total = A + (B + 63) / 64 * 64;
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
   const int l = lane_id();
   for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < total; base += stride) {
@@ -1357,7 +1357,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
       }
       const uint64_t word = __ballot(bit);
       if (pw < cm.meta[4] && l == 0) *reinterpret_cast<uint64_t*>(enc + encm(s) + 64 + 8 * (pw - cm.ppre[s])) = word;
-    } else if (wbase < A + B64) {  // groups
+    } else {  // groups
       const int64_t g0 = wbase - A;
       if (g0 >= B) continue;
       const int64_t gl = g0 + 63 < B ? g0 + 63 : B - 1;
@@ -1372,70 +1372,80 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
       sec[lg] = gsz[gg];
       if (lg == g.G - 1)
         for (uint64_t b = g.G; b < round8(g.G); ++b) sec[b] = 0;
-    } else {  // C records
-      const int64_t c0 = wbase - A - B64;
-      if (c0 >= Cn) continue;
-      const int64_t cl = c0 + 63 < Cn ? c0 + 63 : Cn - 1;
-      const int64_t gc = it - A - B64;
-      const int64_t s = wave_seg(cm.cpre, cm.nseg, (uint64_t)(gc < Cn ? gc : Cn - 1), (uint64_t)c0, (uint64_t)cl);
-      if (gc >= Cn || cflag[gc]) continue;
-      const Seg& g = cm.seg[s];
-      const uint64_t r = (cscan[gc] >> PK) - g.nbase;
-      const uint64_t np = (cscan[gc] & WMASK) - g.npbase;
-      uint8_t* ns = enc + encm(s) + 64 + 8 * g.PG + 8 * g.G + round8(g.G);
-      *reinterpret_cast<uint32_t*>(ns + 4 * r) = cwords[gc];
-      if (r == g.n_new - 1 && (g.n_new & 1)) *reinterpret_cast<uint32_t*>(ns + 4 * (r + 1)) = 0;
-      *reinterpret_cast<uint32_t*>(newref + g.oref + 32 + 4 * (g.n_match + r)) = (uint32_t)(g.W + np);
     }
   }
 }
 
-// New records into the encoding and into C': a wave takes 64 consecutive C
-// records, tabulates the new ones in LDS and copies their words
-// lane-parallel (consecutive lanes, consecutive words).
-__global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t* cscan, const uint8_t* cflag,
+// Copies of the words a wave tabulated in t (t.q[n] words in all), NC_U per
+// lane in flight: all searches and loads first, then the stores.  dst2 may
+// be null.
+constexpr int NC_U = 4;
+__device__ inline void copy_tab(const NewTab& t, int n, const uint64_t* src, uint64_t* dst1, uint64_t* dst2) {
+  const uint64_t tot = t.q[n];
+  for (uint64_t q0 = lane_id(); q0 < tot; q0 += NC_U * WAVE) {
+    uint64_t v[NC_U], d1[NC_U], d2[NC_U];
+#pragma unroll
+    for (int j = 0; j < NC_U; ++j) {
+      const uint64_t q = q0 + (uint64_t)j * WAVE < tot ? q0 + (uint64_t)j * WAVE : tot - 1;
+      const int i = lds_last_le(t.q, n, q);
+      const uint64_t w = q - t.q[i];
+      v[j] = src[t.src[i] + w];
+      d1[j] = t.dst1[i] + w;
+      d2[j] = t.dst2[i] + w;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < NC_U; ++j)
+      if (q0 + (uint64_t)j * WAVE < tot) {
+        dst1[d1[j]] = v[j];
+        if (dst2) dst2[d2[j]] = v[j];
+      }
+  }
+}
+
+// New C records: their sizes into the encoding's table, their C' offsets,
+// and their words into the encoding and into C'.  A wave takes 64
+// consecutive new records from the list the scan of new records wrote (so
+// that runs of new records spread over many waves), tabulates them in LDS
+// and copies their words lane-parallel (consecutive lanes, consecutive
+// words).
+__global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t* cscan, const uint32_t* nlist,
                                                        const uint32_t* cwords, const uint8_t* cur, uint8_t* enc,
                                                        uint8_t* newref) {
   __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
-  const int64_t Cn = cm.meta[0];
+  const int64_t Nn = (int64_t)(cscan[cm.meta[0]] >> PK);
   const int l = lane_id(), wv = wave_id();
   NewTab& t = s_t[wv];
-  const uint64_t* src = reinterpret_cast<const uint64_t*>(cur);
-  uint64_t* e64 = reinterpret_cast<uint64_t*>(enc);
-  uint64_t* o64 = reinterpret_cast<uint64_t*>(newref);
   const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t gb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; gb < Cn; gb += stride) {
-    const int64_t gc = gb + l;
-    const bool isnew = gc < Cn && !cflag[gc];
-    const uint64_t mask = __ballot(isnew);
-    if (!mask) continue;
-    const int64_t ge = gb + WAVE - 1 < Cn ? gb + WAVE - 1 : Cn - 1;
-    const int64_t s = wave_seg(cm.cpre, cm.nseg, (uint64_t)(gc < Cn ? gc : Cn - 1), (uint64_t)gb, (uint64_t)ge);
-    const int slot = __popcll(mask & lanemask_lt(l)), n = __popcll(mask);
-    uint64_t words = 0;
-    if (isnew) {
-      const Seg& g = cm.seg[s];
-      const uint32_t o = ld32(cur + g.cmsg + 32 + 4 * (uint64_t)(gc - (int64_t)cm.cpre[s]));
-      words = cwords[gc];
-      const uint64_t qs = (cscan[gc] & WMASK) - g.npbase;  // word within the segment's new records
+  for (int64_t rb = ((int64_t)blockIdx.x * WAVES + wv) * WAVE; rb < Nn; rb += stride) {
+    const int64_t k = rb + l;
+    const int n = (int)(Nn - rb < WAVE ? Nn - rb : WAVE);
+    const int64_t gc = nlist[k < Nn ? k : Nn - 1];
+    const int64_t sg = wave_seg(cm.cpre, cm.nseg, (uint64_t)gc, readlane64((uint64_t)gc, 0),
+                                readlane64((uint64_t)gc, n - 1));
+    const Seg& g = cm.seg[sg];
+    const uint64_t cs = cscan[gc];
+    const uint64_t words = k < Nn ? cwords[gc] : 0;
+    const uint32_t o = ld32(cur + g.cmsg + 32 + 4 * (uint64_t)(gc - (int64_t)cm.cpre[sg]));
+    if (k < Nn) {
+      const uint64_t r = (cs >> PK) - g.nbase;      // index among the segment's new records
+      const uint64_t qs = (cs & WMASK) - g.npbase;  // word within the segment's new records
       const uint64_t nn = g.n_match + g.n_new;
-      t.src[slot] = (g.cbody + 8 * (uint64_t)o) / 8;
-      t.dst1[slot] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
-      t.dst2[slot] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
+      uint8_t* ns = enc + g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G);
+      *reinterpret_cast<uint32_t*>(ns + 4 * r) = (uint32_t)words;
+      if (r == g.n_new - 1 && (g.n_new & 1)) *reinterpret_cast<uint32_t*>(ns + 4 * (r + 1)) = 0;
+      *reinterpret_cast<uint32_t*>(newref + g.oref + 32 + 4 * (g.n_match + r)) = (uint32_t)(g.W + qs);
+      t.src[l] = (g.cbody + 8 * (uint64_t)o) / 8;
+      t.dst1[l] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
+      t.dst2[l] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
     }
-    const uint64_t incl = wave_incl_scan(words);
-    if (isnew) t.q[slot] = incl - words;
-    if (l == WAVE - 1) t.q[n] = incl;
+    const uint64_t winc = wave_incl_scan(words);
+    if (k < Nn) t.q[l] = winc - words;
+    if (l == WAVE - 1) t.q[n] = winc;
     wave_sync();
-    const uint64_t tot = t.q[n];
-    for (uint64_t q = l; q < tot; q += WAVE) {
-      const int i = lds_last_le(t.q, n, q);
-      const uint64_t w = q - t.q[i];
-      const uint64_t v = src[t.src[i] + w];
-      e64[t.dst1[i] + w] = v;
-      o64[t.dst2[i] + w] = v;
-    }
+    copy_tab(t, n, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<uint64_t*>(enc),
+             reinterpret_cast<uint64_t*>(newref));
     wave_sync();
   }
 }
@@ -2066,12 +2076,24 @@ __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t
     wave_sync();
     const uint64_t tot = t.q[n];
     bool bad = false;
-    for (uint64_t q = l; q < tot; q += WAVE) {
-      const int i = lds_last_le(t.q, n, q);
-      const uint64_t w = q - t.q[i];
-      const uint64_t v = e64[t.src[i] + w];
-      if ((w == 0 && v == 0) || (w == 1 && (v >> 32) != t.dst2[i])) bad = true;
-      o64[t.dst1[i] + w] = v;
+    for (uint64_t q0 = l; q0 < tot; q0 += NC_U * WAVE) {  // NC_U words per lane in flight
+      uint64_t v[NC_U], d[NC_U], w[NC_U], sz[NC_U];
+#pragma unroll
+      for (int j = 0; j < NC_U; ++j) {
+        const uint64_t q = q0 + (uint64_t)j * WAVE < tot ? q0 + (uint64_t)j * WAVE : tot - 1;
+        const int i = lds_last_le(t.q, n, q);
+        w[j] = q - t.q[i];
+        v[j] = e64[t.src[i] + w[j]];
+        d[j] = t.dst1[i] + w[j];
+        sz[j] = t.dst2[i];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < NC_U; ++j)
+        if (q0 + (uint64_t)j * WAVE < tot) {
+          if ((w[j] == 0 && v[j] == 0) || (w[j] == 1 && (v[j] >> 32) != sz[j])) bad = true;
+          o64[d[j]] = v[j];
+        }
     }
     if (__ballot(bad) && l == 0) fail(cm.status, ERR_CORRUPT);
     wave_sync();
@@ -2322,6 +2344,7 @@ struct Mem {
   uint8_t* cflag;   // encoder: matched C records; decoder: matched R slots
   uint64_t* rscan;
   uint64_t* cscan;  // encoder: new C records; decoder: new record words
+  uint32_t* nlist;  // encoder: indices of the new C records, in order
   MDir* mdir;
   uint64_t* crw;
   uint64_t* bm;
@@ -2369,6 +2392,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.cm.status = nullptr;
   m.tab = ar.take<Entry>(b.H);
   m.cwords = ar.take<uint32_t>(b.C);
+  m.nlist = ar.take<uint32_t>(b.C);
   m.rwords = ar.take<uint32_t>(b.R);
   m.m = ar.take<int32_t>(b.R);
   m.cflag = ar.take<uint8_t>(std::max(b.C, b.R));
@@ -2507,7 +2531,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   }
   k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
                                                                      lookback(c, 1));
-  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords}, m.cm.meta + 0, b.C, m.cscan,
+  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords, m.nlist}, m.cm.meta + 0, b.C, m.cscan,
                                                                    lookback(c, 2));
   {
     const ColScan cs = col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4}, {b.G, -1, -1, -1});
@@ -2560,9 +2584,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     }
     k_enc_place<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg, m.gex);
   }
-  k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.cflag, m.cwords, m.cscan, m.bm, m.gsz, m.gex, enc, enc_cap, enc_off,
-                                  modes, newref);
-  k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.cflag, m.cwords, cur, enc, newref);
+  k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.bm, m.gsz, m.gex, enc, enc_cap, enc_off, modes);
+  k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.nlist, m.cwords, cur, enc, newref);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
                 hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};

@@ -237,9 +237,16 @@ constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ROUNDS;
 // (every item's first loads, then every item's second loads, ...), so that
 // a wave waits once per stage rather than once per stage and item.  Lanes
 // past n may call operator() with index n - 1 (side effects of a functor
-// must be idempotent), so that no load sits behind a branch.
+// must be idempotent), so that no load sits behind a branch.  A functor may
+// also define emit(i, excl, v), called for every item i < n after out[i] is
+// stored, with the item's exclusive prefix and value (e.g. to list the items
+// of a kind by their rank).
 template <class T, class = void>
 struct has_wave_begin : std::false_type {};
+template <class T, class = void>
+struct has_emit : std::false_type {};
+template <class T>
+struct has_emit<T, std::void_t<decltype(&T::emit)>> : std::true_type {};
 template <class T>
 struct has_wave_begin<T, std::void_t<decltype(&T::wave_begin)>> : std::true_type {};
 template <class T, class = void>
@@ -317,7 +324,10 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan(In in, const int64_t* n_dev
 #pragma unroll
     for (int r = 0; r < SCAN_ROUNDS; ++r) {
       const int64_t i = wbase + r * WAVE + l;
-      if (i < n) out[i] = base + ex[r];
+      if (i < n) {
+        out[i] = base + ex[r];
+        if constexpr (has_emit<In>::value) fn.emit(i, base + ex[r], v[r]);
+      }
     }
     if ((int64_t)t == ntiles - 1 && threadIdx.x == 0) out[n] = s_prefix + tot;
     __syncthreads();
