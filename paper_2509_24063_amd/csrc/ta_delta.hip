@@ -1302,6 +1302,8 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
 }
 
 
+constexpr int FX_PW = 8;  // presence words per wave in k_enc_fixed
+
 // The encodings' offsets and headers (per segment), then their fixed
 // sections: presence bitmaps (one wave per 64 reference slots), word bitmaps
 // and block size tables (per group).  The new record sizes and the C'
@@ -1337,31 +1339,48 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
   }
   if (!fits) return;
   auto encm = [&](int64_t s) { return cm.seg[s].fixed_excl + gex[cm.gpre[s]]; };
-  // presence items first, padded to whole blocks so that every wave of the
-  // range works on one presence word; then groups
-  const int64_t A = (64 * cm.meta[4] + BLOCK - 1) / BLOCK * BLOCK, B = cm.meta[3];
-  const int64_t total = A + (B + 63) / 64 * 64;
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
+  // presence words first, FX_PW to a wave (the slot loads of all FX_PW words
+  // in flight at once), then groups, 64 to a wave
+  const int64_t P = cm.meta[4], B = cm.meta[3];
+  const int64_t TP = (P + FX_PW - 1) / FX_PW, TG = (B + 63) / 64;
   const int l = lane_id();
-  for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < total; base += stride) {
-    const int64_t wbase = base + 64 * wave_id();  // the wave's first item
+  for (int64_t task = (int64_t)blockIdx.x * WAVES + wave_id(); task < TP + TG; task += (int64_t)gridDim.x * WAVES) {
+    const int64_t wbase = 64 * (task - TP);  // groups: the wave's first group
     const int64_t it = wbase + l;
-    if (wbase < A) {  // presence words (A is a multiple of 64, BLOCK too)
-      const int64_t pw = wbase / 64;
-      bool bit = false;
-      int64_t s = 0;
-      if (pw < cm.meta[4]) {
-        s = seg_of(cm.ppre, cm.nseg, (uint64_t)pw);
-        const uint64_t j = 64 * (pw - cm.ppre[s]) + (uint64_t)l;
-        bit = j < cm.seg[s].nr && m[cm.rpre[s] + j] >= 0;
+    if (task < TP) {
+      const int64_t pw0 = task * FX_PW, pl = pw0 + FX_PW - 1 < P ? pw0 + FX_PW - 1 : P - 1;
+      const int64_t lo = seg_of(cm.ppre, cm.nseg, (uint64_t)pw0);
+      const int64_t hi = last_le<uint64_t>(cm.ppre, lo, cm.nseg, (uint64_t)pl);
+      int64_t sj[FX_PW];
+      uint64_t idx[FX_PW], dst[FX_PW];
+      bool ok[FX_PW];
+#pragma unroll
+      for (int j = 0; j < FX_PW; ++j) {
+        const int64_t pw = pw0 + j < pl ? pw0 + j : pl;
+        sj[j] = last_le<uint64_t>(cm.ppre, lo, hi + 1, (uint64_t)pw);
+        const uint64_t jj = 64 * (pw - cm.ppre[sj[j]]) + (uint64_t)l;
+        ok[j] = pw0 + j <= pl && jj < cm.seg[sj[j]].nr;
+        idx[j] = ok[j] ? cm.rpre[sj[j]] + jj : 0;
+        dst[j] = encm(sj[j]) + 64 + 8 * (pw - cm.ppre[sj[j]]);
       }
-      const uint64_t word = __ballot(bit);
-      if (pw < cm.meta[4] && l == 0) *reinterpret_cast<uint64_t*>(enc + encm(s) + 64 + 8 * (pw - cm.ppre[s])) = word;
+      int32_t mv[FX_PW];
+#pragma unroll
+      for (int j = 0; j < FX_PW; ++j) mv[j] = m[idx[j]];
+      __builtin_amdgcn_sched_barrier(0);
+      uint64_t word = 0, at = 0;
+#pragma unroll
+      for (int j = 0; j < FX_PW; ++j) {
+        const uint64_t w = __ballot(ok[j] && mv[j] >= 0);
+        if (l == j) {
+          word = w;
+          at = dst[j];
+        }
+      }
+      if (l < FX_PW && pw0 + l <= pl) *reinterpret_cast<uint64_t*>(enc + at) = word;
     } else {  // groups
-      const int64_t g0 = wbase - A;
-      if (g0 >= B) continue;
+      const int64_t g0 = wbase;
       const int64_t gl = g0 + 63 < B ? g0 + 63 : B - 1;
-      const int64_t gg = it - A;
+      const int64_t gg = it;
       const int64_t s = wave_seg(cm.gpre, cm.nseg, (uint64_t)(gg < B ? gg : B - 1), (uint64_t)g0, (uint64_t)gl);
       if (gg >= B) continue;
       const Seg& g = cm.seg[s];
