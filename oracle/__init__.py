@@ -48,6 +48,12 @@ class Agents(C.Structure):
                 ("beh_off", C.c_void_p), ("beh", C.c_void_p)]
 
 
+class OStore(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("uid", C.c_void_p), ("cls", C.c_void_p), ("nb", C.c_void_p),
+                ("f64", C.c_void_p), ("f64_stride", C.c_int64), ("i32", C.c_void_p), ("i32_stride", C.c_int64),
+                ("beh_off", C.c_void_p), ("beh", C.c_void_p), ("beh_cap", C.c_int64)]
+
+
 class MLP(C.Structure):
     _fields_ = [("w1", C.c_int8 * 768), ("w2", C.c_int8 * 4096), ("w3", C.c_int8 * 256),
                 ("b1", C.c_int32 * 64), ("b2", C.c_int32 * 64), ("b3", C.c_int32 * 4),
@@ -61,6 +67,9 @@ class Hist(C.Structure):
 def _declare(L):
     vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
     L.orc_select_aura.argtypes = [i64, vp, vp, i64, vp, C.c_double, i32, vp, i64, vp]
+    L.orc_select_migrants.argtypes = [i64, vp, vp, i64, vp, vp, i64, vp]
+    L.orc_migrate_apply.argtypes = [C.POINTER(Agents), i64, vp, vp, i32, vp, vp, i32, i32, vp, i64, vp, i64, vp,
+                                    C.POINTER(OStore), vp, vp]
     L.orc_serialize.argtypes = [C.POINTER(Agents), i32, vp, vp, vp, vp, i64, vp, i64, vp]
     L.orc_view.argtypes = [vp, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.orc_mlp_parse.argtypes = [vp, i64, C.POINTER(MLP)]
@@ -93,6 +102,71 @@ def select_aura(store, w: float, ndirs: int):
     if st:
         raise RuntimeError(f"orc_select_aura status {st}")
     return idx[: int(seg_off[-1])].copy(), seg_off
+
+
+def select_migrants(store):
+    """(idx int32[S], seg_off int64[P*26+1]): agents outside their partition box,
+    by the direction they left it in."""
+    L = lib()
+    f64 = np.ascontiguousarray(store.f64)
+    part_off = np.ascontiguousarray(store.part_off, dtype=np.int64)
+    boxes = np.ascontiguousarray(store.boxes, dtype=np.float64)
+    P = part_off.shape[0] - 1
+    seg_off = np.zeros(P * 26 + 1, dtype=np.int64)
+    cap = max(1, store.n)
+    idx = np.zeros(cap, dtype=np.int32)
+    st = L.orc_select_migrants(P, _p(part_off), _p(f64), f64.shape[1], _p(boxes), _p(idx), cap, _p(seg_off))
+    if st:
+        raise RuntimeError(f"orc_select_migrants status {st}")
+    return idx[: int(seg_off[-1])].copy(), seg_off
+
+
+def migrate_apply(store, schema, msgs: np.ndarray, msg_off: np.ndarray, dest: np.ndarray, nf_cols: int,
+                  ni_cols: int, cap: int | None = None, beh_cap: int | None = None):
+    """The store after a migration exchange: (status, out) with out a dict of
+    uid, cls, nb, f64 [nf_cols, n], i32 [ni_cols, n], beh_off, beh, part_off and
+    sizes (agents, behaviour bytes).  cap / beh_cap default to the sizes needed."""
+    L = lib()
+    a, keep = _agents(store)
+    part_off = np.ascontiguousarray(store.part_off, np.int64)
+    boxes = np.ascontiguousarray(store.boxes, np.float64)
+    P = part_off.shape[0] - 1
+    nf = np.asarray(schema.n_f64, np.uint16)
+    ni = np.asarray(schema.n_i32, np.uint16)
+    msgs = np.ascontiguousarray(msgs, np.uint8)
+    if msgs.size == 0:
+        msgs = np.zeros(8, np.uint8)
+        msgs_len = 0
+    else:
+        msgs_len = msgs.shape[0]
+    msg_off = np.ascontiguousarray(msg_off, np.int64)
+    nseg = msg_off.shape[0] - 1
+    dest = np.ascontiguousarray(dest, np.int32) if nseg else np.zeros(1, np.int32)
+    sizes = np.zeros(2, np.int64)
+    part_out = np.zeros(P + 1, np.int64)
+
+    def run(c, bc):
+        o = dict(uid=np.zeros(max(c, 1), np.uint64), cls=np.zeros(max(c, 1), np.uint16),
+                 nb=np.zeros(max(c, 1), np.uint16), f64=np.zeros((max(nf_cols, 1), max(c, 1))),
+                 i32=np.zeros((max(ni_cols, 1), max(c, 1)), np.int32), beh_off=np.zeros(c + 1, np.int64),
+                 beh=np.zeros(max(bc, 8), np.uint8))
+        st_ = OStore(c, _p(o["uid"]), _p(o["cls"]), _p(o["nb"]), _p(o["f64"]), o["f64"].shape[1], _p(o["i32"]),
+                     o["i32"].shape[1], _p(o["beh_off"]), _p(o["beh"]), bc)
+        r = L.orc_migrate_apply(C.byref(a), P, _p(part_off), _p(boxes), nf.shape[0], _p(nf), _p(ni), nf_cols,
+                                ni_cols, _p(msgs), msgs_len, _p(msg_off), nseg, _p(dest), C.byref(st_),
+                                _p(part_out), _p(sizes))
+        return r, o
+
+    st, o = run(0 if cap is None else cap, 0 if beh_cap is None else beh_cap)
+    if st == CAPACITY and cap is None and beh_cap is None:
+        st, o = run(int(sizes[0]), int(sizes[1]))
+    del keep
+    n = int(sizes[0])
+    out = dict(part_off=part_out.copy(), sizes=sizes.copy())
+    if st == OK:
+        out.update(uid=o["uid"][:n], cls=o["cls"][:n], nb=o["nb"][:n], f64=o["f64"][:nf_cols, :n],
+                   i32=o["i32"][:ni_cols, :n], beh_off=o["beh_off"][: n + 1], beh=o["beh"][: int(sizes[1])])
+    return st, out
 
 
 def _agents(store):

@@ -99,6 +99,47 @@ int orc_select_aura(int64_t P, const int64_t *part_off, const double *f64, int64
 }
 
 /* ======================================================================== */
+/* Migrant selection (Sec. 2.1, "Agent Migration")                           */
+/* ======================================================================== */
+/*
+ * An agent of partition p whose position lies outside box p belongs to the
+ * rank that owns the neighbouring box it moved into.  Per axis its offset is
+ * -1 when x < lo, +1 when x >= hi and 0 otherwise; the triple of offsets is
+ * one of the 26 directions (in the 26-direction order of the aura
+ * selection), or (0,0,0) for an agent that stays.
+ */
+static int axis_offset(double x, double lo, double hi) {
+  if (x < lo) return -1;
+  if (x >= hi) return +1;
+  return 0;
+}
+
+int orc_select_migrants(int64_t P, const int64_t *part_off, const double *f64, int64_t f64_stride,
+                        const double *boxes, int32_t *idx, int64_t idx_cap, int64_t *seg_off) {
+  int codes[26];
+  direction_codes(26, codes);
+  int64_t count = 0;
+  for (int64_t p = 0; p < P; ++p) {
+    const double *lo = boxes + 6 * p, *hi = boxes + 6 * p + 3;
+    for (int k = 0; k < 26; ++k) {
+      int d[3] = {codes[k] % 3 - 1, (codes[k] / 3) % 3 - 1, codes[k] / 9 - 1};
+      seg_off[p * 26 + k] = count;
+      for (int64_t i = part_off[p]; i < part_off[p + 1]; ++i) {
+        int same = 1;
+        for (int a = 0; a < 3; ++a)
+          if (axis_offset(f64[a * f64_stride + i], lo[a], hi[a]) != d[a]) same = 0;
+        if (same) {
+          if (count < idx_cap) idx[count] = (int32_t)i;
+          ++count;
+        }
+      }
+    }
+  }
+  seg_off[P * 26] = count;
+  return count > idx_cap ? ORC_CAPACITY : ORC_OK;
+}
+
+/* ======================================================================== */
 /* Serialization into TAM1 messages                                          */
 /* ======================================================================== */
 /*
@@ -777,4 +818,139 @@ int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, in
   free(nbr);
   free(D);
   return st;
+}
+
+/* ======================================================================== */
+/* Store after a migration exchange (Sec. 2.1 "Agent Migration", records as  */
+/* serialized in Sec. 2.2.1)                                                 */
+/* ======================================================================== */
+/*
+ * Partition q of the result: the agents of input partition q that lie inside
+ * box q (offset 0 on every axis, i.e. not selected as migrants), in store
+ * order; then the records of every message s with dest[s] == q, messages in
+ * ascending s, records in message order.  A kept agent keeps all nf_cols fp64
+ * and ni_cols int32 columns and its behaviour bytes.  An unpacked record gives
+ * uid (word 0), class and behaviour count (word 1), the class's fp64 fields
+ * (the next n_f64 words), its int32 attributes (the next ceil(n_i32/2) words,
+ * two per word, low half first), zeros in the remaining columns, and the rest
+ * of the record as behaviour bytes.
+ */
+static int msg_span(const uint8_t *msgs, int64_t msgs_len, const int64_t *msg_off, int64_t s, msg_t *m) {
+  int64_t a = msg_off[s], b = msg_off[s + 1];
+  if (a < 0 || b < a || b > msgs_len || a % 8 != 0) return ORC_INVALID;
+  return open_msg(msgs + a, b - a, m);
+}
+
+int orc_migrate_apply(const orc_agents *in, int64_t P, const int64_t *part_off, const double *boxes,
+                      int n_classes, const uint16_t *n_f64, const uint16_t *n_i32, int nf_cols, int ni_cols,
+                      const uint8_t *msgs, int64_t msgs_len, const int64_t *msg_off, int64_t nseg,
+                      const int32_t *dest, orc_store *out, int64_t *part_off_out, int64_t *sizes) {
+  if (part_off[0] != 0 || part_off[P] > in->n) return ORC_INVALID;
+  for (int64_t p = 0; p < P; ++p)
+    if (part_off[p + 1] < part_off[p]) return ORC_INVALID;
+  /* every message and record is checked, also those of skipped messages */
+  for (int64_t s = 0; s < nseg; ++s) {
+    msg_t m;
+    if (msg_span(msgs, msgs_len, msg_off, s, &m) || dest[s] >= P) return ORC_INVALID;
+    for (int64_t r = 0; r < m.n; ++r) {
+      const uint8_t *rec = record(&m, r);
+      uint64_t h = get64(rec + 8);
+      int c = (int)(h & 0xFFFF);
+      if (get64(rec) == 0 || c >= n_classes) return ORC_INVALID;
+      if (rec_words_of(rec) < 2 + n_f64[c] + (n_i32[c] + 1) / 2) return ORC_INVALID;
+    }
+  }
+  unsigned char *keep = malloc((size_t)in->n + 1);
+  int64_t n_out = 0, beh_out = 0;
+  for (int64_t q = 0; q < P; ++q) {
+    const double *lo = boxes + 6 * q, *hi = boxes + 6 * q + 3;
+    for (int64_t i = part_off[q]; i < part_off[q + 1]; ++i) {
+      int inside = 1;
+      for (int a = 0; a < 3; ++a)
+        if (axis_offset(in->f64[a * in->f64_stride + i], lo[a], hi[a]) != 0) inside = 0;
+      keep[i] = (unsigned char)inside;
+      if (!inside) continue;
+      int64_t bytes = in->beh_off[i + 1] - in->beh_off[i];
+      if (in->beh_off[i] % 8 != 0 || bytes < 0 || bytes % 8 != 0) { free(keep); return ORC_INVALID; }
+      ++n_out;
+      beh_out += bytes;
+    }
+  }
+  for (int64_t s = 0; s < nseg; ++s) {
+    if (dest[s] < 0) continue;
+    msg_t m;
+    msg_span(msgs, msgs_len, msg_off, s, &m);
+    for (int64_t r = 0; r < m.n; ++r) {
+      const uint8_t *rec = record(&m, r);
+      int c = (int)(get64(rec + 8) & 0xFFFF);
+      ++n_out;
+      beh_out += 8 * (rec_words_of(rec) - 2 - n_f64[c] - (n_i32[c] + 1) / 2);
+    }
+  }
+  sizes[0] = n_out;
+  sizes[1] = beh_out;
+  /* partition starts of the result */
+  int64_t pos = 0;
+  for (int64_t q = 0; q < P; ++q) {
+    part_off_out[q] = pos;
+    for (int64_t i = part_off[q]; i < part_off[q + 1]; ++i) pos += keep[i];
+    for (int64_t s = 0; s < nseg; ++s)
+      if (dest[s] == q) {
+        msg_t m;
+        msg_span(msgs, msgs_len, msg_off, s, &m);
+        pos += m.n;
+      }
+  }
+  part_off_out[P] = pos;
+  if (n_out > out->cap || beh_out > out->beh_cap) { free(keep); return ORC_CAPACITY; }
+  int64_t j = 0, boff = 0;
+  for (int64_t q = 0; q < P; ++q) {
+    for (int64_t i = part_off[q]; i < part_off[q + 1]; ++i) {
+      if (!keep[i]) continue;
+      out->uid[j] = in->uid[i];
+      out->cls[j] = in->cls[i];
+      out->nb[j] = in->nb[i];
+      for (int k = 0; k < nf_cols; ++k) out->f64[k * out->f64_stride + j] = in->f64[k * in->f64_stride + i];
+      for (int k = 0; k < ni_cols; ++k) out->i32[k * out->i32_stride + j] = in->i32[k * in->i32_stride + i];
+      int64_t bytes = in->beh_off[i + 1] - in->beh_off[i];
+      out->beh_off[j] = boff;
+      memcpy(out->beh + boff, in->beh + in->beh_off[i], (size_t)bytes);
+      boff += bytes;
+      ++j;
+    }
+    for (int64_t s = 0; s < nseg; ++s) {
+      if (dest[s] != q) continue;
+      msg_t m;
+      msg_span(msgs, msgs_len, msg_off, s, &m);
+      for (int64_t r = 0; r < m.n; ++r) {
+        const uint8_t *rec = record(&m, r);
+        uint64_t h = get64(rec + 8);
+        int c = (int)(h & 0xFFFF);
+        out->uid[j] = get64(rec);
+        out->cls[j] = (uint16_t)c;
+        out->nb[j] = (uint16_t)((h >> 16) & 0xFFFF);
+        const uint8_t *f = rec + 16;
+        for (int k = 0; k < nf_cols; ++k) {
+          double v = 0.0;
+          if (k < n_f64[c]) memcpy(&v, f + 8 * k, 8);
+          out->f64[k * out->f64_stride + j] = v;
+        }
+        const uint8_t *at = f + 8 * n_f64[c];
+        for (int k = 0; k < ni_cols; ++k) {
+          int32_t v = 0;
+          if (k < n_i32[c]) memcpy(&v, at + 4 * k, 4);
+          out->i32[k * out->i32_stride + j] = v;
+        }
+        int64_t fixed = 2 + n_f64[c] + (n_i32[c] + 1) / 2;
+        int64_t bytes = 8 * (rec_words_of(rec) - fixed);
+        out->beh_off[j] = boff;
+        memcpy(out->beh + boff, rec + 8 * fixed, (size_t)bytes);
+        boff += bytes;
+        ++j;
+      }
+    }
+  }
+  out->beh_off[j] = boff;
+  free(keep);
+  return ORC_OK;
 }

@@ -62,6 +62,13 @@ int orc_select_aura(int64_t P, const int64_t *part_off, const double *f64, int64
                     const double *boxes, double w, int ndirs, int32_t *idx, int64_t idx_cap,
                     int64_t *seg_off);
 
+/* Migrant selection (Sec. 2.1, "Agent Migration"): per partition and each of
+ * the 26 directions (aura order), the agents whose position lies outside
+ * their box on exactly that direction's side of each axis (x < lo: -1,
+ * x >= hi: +1, else 0).  Same output layout as orc_select_aura. */
+int orc_select_migrants(int64_t P, const int64_t *part_off, const double *f64, int64_t f64_stride,
+                        const double *boxes, int32_t *idx, int64_t idx_cap, int64_t *seg_off);
+
 /* TA IO serialization of every segment into one buffer (Sec. 2.2.1).
  * msg_off[nseg+1] receives the byte offset of each message. */
 int orc_serialize(const orc_agents *a, int n_classes, const uint16_t *n_f64, const uint16_t *n_i32,
@@ -92,6 +99,31 @@ int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, in
  * in[12*j..], and whether slot j is predicted at all (pred[j]). */
 int orc_predictor_inputs(const uint8_t *ref, int64_t ref_len, const orc_hist *h, double cell,
                          int32_t *in, uint8_t *pred);
+
+/* Mutable agent store with room for cap agents and beh_cap behaviour bytes. */
+typedef struct {
+  int64_t cap;
+  uint64_t *uid;
+  uint16_t *cls;
+  uint16_t *nb;
+  double *f64;
+  int64_t f64_stride;
+  int32_t *i32;
+  int64_t i32_stride;
+  int64_t *beh_off;
+  uint8_t *beh;
+  int64_t beh_cap;
+} orc_store;
+
+/* The store after one migration exchange (Sec. 2.1): per partition q, its
+ * agents that stay inside box q, then the records of the messages s with
+ * dest[s] == q (dest < 0: skipped) unpacked into the columns.  sizes[0..1] =
+ * agents and behaviour bytes of the result, part_off_out[P+1] its partition
+ * starts (both also on ORC_CAPACITY). */
+int orc_migrate_apply(const orc_agents *in, int64_t P, const int64_t *part_off, const double *boxes,
+                      int n_classes, const uint16_t *n_f64, const uint16_t *n_i32, int nf_cols, int ni_cols,
+                      const uint8_t *msgs, int64_t msgs_len, const int64_t *msg_off, int64_t nseg,
+                      const int32_t *dest, orc_store *out, int64_t *part_off_out, int64_t *sizes);
 
 #ifdef __cplusplus
 }

@@ -90,6 +90,8 @@ class Config:
     payload_words: tuple = (1, 1)   # payload size range in 8-byte words (inclusive)
     persistent: bool = False        # AR(1) velocity and growing diameter
     sort_cells: bool = True
+    walls: str = "box"              # "box": reflect at every partition box; "domain": only at the
+                                    # union of the boxes, so agents can leave their partition's box
 
     @property
     def schema(self) -> Schema:
@@ -119,6 +121,25 @@ def config(index: int, **over) -> Config:
     else:
         raise ValueError(index)
     return dataclasses.replace(c, **over)
+
+
+def neighbour_table(grid: tuple) -> np.ndarray:
+    """int32[P*26]: for partition p of a gx x gy x gz grid of boxes (p = ix + gx
+    (iy + gy iz)) and the k-th of the 26 directions (dx, dy, dz) in ascending
+    order of (dx+1) + 3(dy+1) + 9(dz+1), the partition of the neighbouring box,
+    or -1 past the edge of the grid.  This is the rank lookup a caller does to
+    route migration messages; it is geometry, not part of the exchange."""
+    gx, gy, gz = grid
+    P = gx * gy * gz
+    dirs = [(c % 3 - 1, (c // 3) % 3 - 1, c // 9 - 1) for c in range(27) if c != 13]
+    out = np.full(P * 26, -1, dtype=np.int32)
+    for p in range(P):
+        ix, iy, iz = p % gx, (p // gx) % gy, p // (gx * gy)
+        for k, (dx, dy, dz) in enumerate(dirs):
+            jx, jy, jz = ix + dx, iy + dy, iz + dz
+            if 0 <= jx < gx and 0 <= jy < gy and 0 <= jz < gz:
+                out[p * 26 + k] = jx + gx * (jy + gy * jz)
+    return out
 
 
 def _behaviours(rng, nb: np.ndarray, pw: tuple):
@@ -250,8 +271,13 @@ class World:
         cfg, rng, s = self.cfg, self.rng, self.store
         n = s.n
         part_of = np.repeat(np.arange(s.P), np.diff(s.part_off))
-        lo = s.boxes[part_of, :3].T
-        hi = s.boxes[part_of, 3:].T
+        if cfg.walls == "domain":
+            dlo, dhi = s.boxes[:, :3].min(axis=0), s.boxes[:, 3:].max(axis=0)
+            lo = np.repeat(dlo[:, None], n, axis=1)
+            hi = np.repeat(dhi[:, None], n, axis=1)
+        else:
+            lo = s.boxes[part_of, :3].T
+            hi = s.boxes[part_of, 3:].T
         if cfg.persistent:
             self.vel = 0.9 * self.vel + rng.normal(0.0, cfg.step_sigma, (3, n))
             s.f64[:3] += self.vel
@@ -270,7 +296,10 @@ class World:
         parents = np.sort(rng.choice(surv, size=k_div, replace=False)) if k_div else np.zeros(0, np.int64)
         dpart = part_of[parents]
         dpos = s.f64[:3, parents] + rng.normal(0.0, cfg.step_sigma, (3, k_div))
-        self._reflect(dpos, s.boxes[dpart, :3].T, s.boxes[dpart, 3:].T)
+        if cfg.walls == "domain":
+            self._reflect(dpos, lo[:, :k_div], hi[:, :k_div])
+        else:
+            self._reflect(dpos, s.boxes[dpart, :3].T, s.boxes[dpart, 3:].T)
         # new order: per partition, survivors then that partition's daughters
         keys = np.concatenate([part_of[surv] * 2, dpart * 2 + 1])
         src = np.concatenate([surv, parents])
