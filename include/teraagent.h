@@ -10,8 +10,11 @@
  *   3. delta-encodes every message against the previous iteration's message
  *      of the same neighbour pair                  (ta_delta_encode),
  *   4. decodes and applies the encoding on the receive side
- *                                                  (ta_delta_decode).
- * Paper: Sec. 2.1 (aura update), Sec. 2.2 / 2.2.1 (TA IO serialization and
+ *                                                  (ta_delta_decode),
+ * and moves the agents that left their partition's box to the partition that
+ * owns their new position (ta_select_migrants, ta_serialize,
+ * ta_migrate_apply).
+ * Paper: Sec. 2.1 (aura update, agent migration), Sec. 2.2 / 2.2.1 (TA IO serialization and
  * single-pass deserialization), Sec. 2.3 (delta encoding against a reference
  * shared by sender and receiver).
  *
@@ -157,6 +160,20 @@ ta_status ta_select_aura(ta_ctx *ctx, const ta_agents *agents, int32_t P, const 
                          const double *boxes, double w, int32_t ndirs, int32_t *idx_out, int64_t idx_cap,
                          int64_t *seg_off_out, void *stream);
 
+/* Migrant selection (Sec. 2.1, "Agent Migration"): the agents that left
+ * their partition's box, by the neighbour box they moved into.  Per axis an
+ * agent's offset is -1 when its coordinate is < lo, +1 when >= hi, 0
+ * otherwise; an agent with a nonzero offset belongs to exactly that one of the
+ * 26 directions (not to the directions of its faces or edges, unlike the
+ * aura), agents inside their box to none.  A NaN coordinate counts as inside.
+ * Arguments, segment order (s = p*26 + k) and outputs as for ta_select_aura
+ * with ndirs = 26; the segments are serialized by ta_serialize and taken in
+ * by ta_migrate_apply.  More than idx_cap migrants -> TA_ERR_CAPACITY
+ * (seg_off_out still holds the needed sizes). */
+ta_status ta_select_migrants(ta_ctx *ctx, const ta_agents *agents, int32_t P, const int64_t *part_off,
+                             const double *boxes, int32_t *idx_out, int64_t idx_cap, int64_t *seg_off_out,
+                             void *stream);
+
 /* TA IO serialization (Sec. 2.2.1, "Serialization"): one TAM1 message per
  * segment.  idx / seg_off (device) as produced by ta_select_aura, nseg
  * segments, at most idx_cap records in total.  Messages are packed densely
@@ -185,6 +202,52 @@ ta_status ta_view(uint8_t *msg, int64_t len, ta_view_t *out);
  * status word. */
 ta_status ta_view_validate(ta_ctx *ctx, const uint8_t *msgs, const int64_t *msg_off, int64_t nseg,
                            int64_t msgs_len, void *stream);
+
+/* An agent store the library writes: device arrays with room for cap agents
+ * (the column layout of ta_agents) and beh_cap behaviour bytes; beh_off has
+ * cap+1 entries.  Base pointers 8-byte aligned. */
+typedef struct {
+  int64_t cap;
+  uint64_t *uid;
+  uint16_t *cls;
+  uint16_t *nb;
+  double *f64;             /* field k of agent j at f64[k * f64_stride + j], f64_stride >= cap */
+  int64_t f64_stride;
+  int32_t *i32;            /* attribute k of agent j at i32[k * i32_stride + j], i32_stride >= cap */
+  int64_t i32_stride;
+  int64_t *beh_off;        /* [cap+1] */
+  uint8_t *beh;
+  int64_t beh_cap;
+} ta_store;
+
+/* The store after one exchange of migrants (Sec. 2.1, "Agent Migration";
+ * records as serialized in Sec. 2.2.1), built in one pass into `out` (which
+ * must not overlap `in`).  Partition q of the result holds:
+ *   1. the agents of input partition q (part_off, device int64[P+1]) whose
+ *      position lies inside box q (boxes as for ta_select_aura; the agents
+ *      ta_select_migrants does not select), in store order, with all of the
+ *      schema's fp64 and int32 columns (the largest class's counts) and
+ *      their behaviour bytes;
+ *   2. then the records of every message s whose msg_part[s] == q (device
+ *      int32[nseg]; < 0: the message is checked but not taken in), messages
+ *      in ascending s, records in message order, unpacked: uid, class,
+ *      behaviour count, the class's fp64 fields and int32 attributes (zero in
+ *      the other columns), the rest of the record as behaviour bytes.
+ * Both stores hold as many fp64 and int32 columns as the schema's largest
+ * class (the columns of every kept agent are copied).
+ * Messages: nseg TAM1 messages at msg_off[s] .. msg_off[s+1] of msgs (device,
+ * msgs_len bytes, 8-byte aligned starts).  part_off_out (device int64[P+1])
+ * receives the result's partition starts and sizes_out (device int64[2]) its
+ * agent count and behaviour bytes, also when they exceed out->cap or
+ * out->beh_cap (-> TA_ERR_CAPACITY, nothing else written).  A bad partition
+ * table, message, record (zero uid, class >= n_classes, fewer words than the
+ * class's fixed part), msg_part[s] >= P or a behaviour range of a kept agent
+ * that is not whole 8-byte words -> TA_ERR_INVALID (outputs unspecified).
+ * The result's beh_off[agents] is its behaviour byte count. */
+ta_status ta_migrate_apply(ta_ctx *ctx, const ta_agents *in, int32_t P, const int64_t *part_off,
+                           const double *boxes, const uint8_t *msgs, int64_t msgs_len, const int64_t *msg_off,
+                           int64_t nseg, const int32_t *msg_part, const ta_store *out, int64_t *part_off_out,
+                           int64_t *sizes_out, void *stream);
 
 /* Predictor for learned delta encoding: an integer MLP 12 -> 64 -> 64 -> 4
  * (int8 weights, int32 accumulation) estimating the next position and

@@ -52,8 +52,6 @@ constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int PK = 34;  // packed scan value: count << 34 | words
 constexpr uint64_t WMASK = (1ull << PK) - 1;
 constexpr int BLK_MAX = 544;          // 32 nibble bytes + 512 significant bytes
-constexpr uint32_t ANY_ERR = (1u << ERR_INVALID) | (1u << ERR_CAPACITY) | (1u << ERR_CORRUPT) | (1u << ERR_REF) |
-                             (1u << ERR_INTERNAL);
 
 constexpr int FOLD_SLOTS = 16;
 

@@ -18,6 +18,8 @@ constexpr uint32_t TAD1_MAGIC = 0x31444154u;  // "TAD1"
 
 // bits of the device status word
 enum : uint32_t { ERR_INVALID = 1, ERR_CAPACITY = 2, ERR_CORRUPT = 3, ERR_REF = 4, ERR_INTERNAL = 5 };
+constexpr uint32_t ANY_ERR = (1u << ERR_INVALID) | (1u << ERR_CAPACITY) | (1u << ERR_CORRUPT) | (1u << ERR_REF) |
+                             (1u << ERR_INTERNAL);
 
 __device__ inline void fail(uint32_t* status, uint32_t code) { atomicOr(status, 1u << code); }
 __device__ inline uint32_t status_of(const uint32_t* status) {

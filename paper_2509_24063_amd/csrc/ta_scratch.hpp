@@ -13,4 +13,5 @@ size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t re
 size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t out_cap, int64_t rec_cap,
                       bool learned, int64_t* tiles);
 size_t validate_scratch(int64_t nseg, int64_t len, int64_t* tiles);
+size_t migrate_scratch(int64_t n_agents, int64_t P, int64_t nseg, int64_t msgs_len, int64_t* tiles);
 }  // namespace ta

@@ -33,6 +33,16 @@ struct DirTable {
   uint8_t req[26];  // code bits direction k requires
 };
 
+// Membership of a 6-bit code in a direction: the aura takes every direction
+// whose bits the code has (an agent near a corner goes to three faces, three
+// edges and the corner); a migrant (EXACT) goes to the one direction whose
+// bits are exactly its code.
+template <bool EXACT>
+__device__ inline bool member(uint32_t code, uint32_t req) {
+  if constexpr (EXACT) return code == req;
+  else return (code & req) == req;
+}
+
 struct SelScratch {
   uint8_t* code;       // [n_agents]
   int64_t* tile_off;   // [P+1]
@@ -106,7 +116,7 @@ __device__ inline TileInfo tile_info(const SelScratch& sc, const int64_t* part_o
   return ti;
 }
 
-template <int NDIRS>
+template <int NDIRS, bool EXACT>
 __global__ __launch_bounds__(BLOCK) void k_sel_count(const double* f64, int64_t stride, const int64_t* part_off,
                                                      const double* boxes, double w, int32_t P, DirTable dt,
                                                      SelScratch sc) {
@@ -142,7 +152,7 @@ __global__ __launch_bounds__(BLOCK) void k_sel_count(const double* f64, int64_t 
       }
       if (__ballot(code != 0) == 0) continue;
 #pragma unroll
-      for (int d = 0; d < NDIRS; ++d) cnt[d] += (uint32_t)__popcll(__ballot((code & dt.req[d]) == dt.req[d]));
+      for (int d = 0; d < NDIRS; ++d) cnt[d] += (uint32_t)__popcll(__ballot(member<EXACT>(code, dt.req[d])));
     }
     if (lane_id() == 0) {
 #pragma unroll
@@ -172,7 +182,7 @@ struct CntIn {
 // packed increments of the directions the code belongs to, and those
 // directions as a bit mask; a wave then scatters only into the directions
 // some of its agents belong to.
-template <int NDIRS>
+template <int NDIRS, bool EXACT>
 __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, int32_t P, DirTable dt, SelScratch sc,
                                                        int32_t* idx_out, int64_t idx_cap, int64_t* seg_off,
                                                        uint32_t* status) {
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
     uint32_t dm = 0;
 #pragma unroll
     for (int d = 0; d < NDIRS; ++d) {
-      if (c && (c & dt.req[d]) == dt.req[d]) {
+      if (c && member<EXACT>(c, dt.req[d])) {
         inc[d / 5] += 1ull << (12 * (d % 5));
         dm |= 1u << d;
       }
@@ -275,7 +285,7 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
         int64_t pos = (int64_t)sc.cnt_pre[cbase + d * ti.nt] + (int64_t)((pre[j] >> sh) & 0xFFF);
 #pragma unroll
         for (int k = 0; k < SEL_IPT; ++k) {
-          if (code[k] && (code[k] & req) == req) {
+          if (code[k] && member<EXACT>(code[k], req)) {
             if (pos < idx_cap) idx_out[pos] = (int32_t)(i0 + k);
             ++pos;
           }
@@ -336,13 +346,11 @@ size_t select_scratch(int64_t n, int64_t P, int ndirs, int64_t* tiles) {
 }
 }  // namespace ta
 
-extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off,
-                                    const double* boxes, double w, int32_t ndirs, int32_t* idx_out, int64_t idx_cap,
-                                    int64_t* seg_off_out, void* stream) {
-  if (!c || !ag || P < 1 || (ndirs != 6 && ndirs != 26) || !part_off || !boxes || !seg_off_out || idx_cap < 0 ||
-      (idx_cap > 0 && !idx_out) || ag->n < 0 || ag->n > INT32_MAX || (ag->n > 0 && !ag->f64) ||
-      ag->f64_stride < ag->n || !(w == w))
-    return TA_ERR_INVALID;
+namespace {
+template <bool EXACT>
+ta_status select_impl(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off, const double* boxes,
+                      double w, int32_t ndirs, int32_t* idx_out, int64_t idx_cap, int64_t* seg_off_out,
+                      void* stream) {
   use_family(c, FAM_SELECT);
   int64_t tiles;
   ta_status st = ensure_scratch(c, select_scratch(ag->n, P, ndirs, &tiles), tiles);
@@ -358,9 +366,9 @@ extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, c
   {
     Timed tm(c, "select_count", s);
     if (ndirs == 26)
-      k_sel_count<26><<<g, BLOCK, 0, s>>>(ag->f64, ag->f64_stride, part_off, boxes, w, P, dt, sc);
+      k_sel_count<26, EXACT><<<g, BLOCK, 0, s>>>(ag->f64, ag->f64_stride, part_off, boxes, w, P, dt, sc);
     else
-      k_sel_count<6><<<g, BLOCK, 0, s>>>(ag->f64, ag->f64_stride, part_off, boxes, w, P, dt, sc);
+      k_sel_count<6, EXACT><<<g, BLOCK, 0, s>>>(ag->f64, ag->f64_stride, part_off, boxes, w, P, dt, sc);
   }
   k_scan<CntIn><<<grid_for(c, cnt_cap + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CntIn{sc.cnt}, sc.meta + 1, cnt_cap, sc.cnt_pre,
                                                                       lookback(c, 0));
@@ -368,10 +376,33 @@ extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, c
     Timed tm(c, "select_scatter", s);
     const int gs = grid_for(c, std::max<int64_t>(sel_sizes(ag->n, P, ndirs).ntiles, ceil_div(P * ndirs + 1, BLOCK)), 1);
     if (ndirs == 26)
-      k_sel_scatter<26><<<gs, BLOCK, 0, s>>>(part_off, P, dt, sc, idx_out, idx_cap, seg_off_out, c->d_status);
+      k_sel_scatter<26, EXACT><<<gs, BLOCK, 0, s>>>(part_off, P, dt, sc, idx_out, idx_cap, seg_off_out, c->d_status);
     else
-      k_sel_scatter<6><<<gs, BLOCK, 0, s>>>(part_off, P, dt, sc, idx_out, idx_cap, seg_off_out, c->d_status);
+      k_sel_scatter<6, EXACT><<<gs, BLOCK, 0, s>>>(part_off, P, dt, sc, idx_out, idx_cap, seg_off_out, c->d_status);
   }
   TA_LAUNCH_CHECK();
   return TA_OK;
+}
+}  // namespace
+
+extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off,
+                                    const double* boxes, double w, int32_t ndirs, int32_t* idx_out, int64_t idx_cap,
+                                    int64_t* seg_off_out, void* stream) {
+  if (!c || !ag || P < 1 || (ndirs != 6 && ndirs != 26) || !part_off || !boxes || !seg_off_out || idx_cap < 0 ||
+      (idx_cap > 0 && !idx_out) || ag->n < 0 || ag->n > INT32_MAX || (ag->n > 0 && !ag->f64) ||
+      ag->f64_stride < ag->n || !(w == w))
+    return TA_ERR_INVALID;
+  return select_impl<false>(c, ag, P, part_off, boxes, w, ndirs, idx_out, idx_cap, seg_off_out, stream);
+}
+
+// Migrants: the aura kernels with thresholds at the box faces (w = 0; lo + 0
+// and hi - 0 are lo and hi exactly) and an exact direction match, so that
+// each agent outside its box lands in one of the 26 segments.
+extern "C" ta_status ta_select_migrants(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off,
+                                        const double* boxes, int32_t* idx_out, int64_t idx_cap, int64_t* seg_off_out,
+                                        void* stream) {
+  if (!c || !ag || P < 1 || !part_off || !boxes || !seg_off_out || idx_cap < 0 || (idx_cap > 0 && !idx_out) ||
+      ag->n < 0 || ag->n > INT32_MAX || (ag->n > 0 && !ag->f64) || ag->f64_stride < ag->n)
+    return TA_ERR_INVALID;
+  return select_impl<true>(c, ag, P, part_off, boxes, 0.0, 26, idx_out, idx_cap, seg_off_out, stream);
 }

@@ -34,6 +34,12 @@ class Agents(C.Structure):
                 ("beh_off", C.c_void_p), ("beh", C.c_void_p)]
 
 
+class StoreT(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("uid", C.c_void_p), ("cls", C.c_void_p), ("nb", C.c_void_p),
+                ("f64", C.c_void_p), ("f64_stride", C.c_int64), ("i32", C.c_void_p), ("i32_stride", C.c_int64),
+                ("beh_off", C.c_void_p), ("beh", C.c_void_p), ("beh_cap", C.c_int64)]
+
+
 class ViewT(C.Structure):
     _fields_ = [("n", C.c_int64), ("rec_words", C.c_int64), ("off", C.c_void_p), ("records", C.c_void_p)]
 
@@ -71,6 +77,9 @@ def lib():
         L.ta_reserve.argtypes = [vp, i64, i64, i64, i64]
         L.ta_status_poll.argtypes = [vp, vp]
         L.ta_select_aura.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, C.c_double, i32, vp, i64, vp, vp]
+        L.ta_select_migrants.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, vp, i64, vp, vp]
+        L.ta_migrate_apply.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, vp, i64, vp, i64, vp, C.POINTER(StoreT),
+                                       vp, vp, vp]
         L.ta_serialize.argtypes = [vp, C.POINTER(Agents), vp, vp, i64, i64, vp, i64, vp, vp]
         L.ta_serialize_bound.argtypes = [i64, i64, i64]
         L.ta_serialize_bound.restype = i64
@@ -188,6 +197,49 @@ class DeviceStore:
     def agents(self):
         return self._s
 
+    @classmethod
+    def alloc(cls, F: int, I: int, boxes, cap: int, beh_cap: int, device="cuda"):
+        """An empty store (no live agents) with room for cap agents and beh_cap
+        behaviour bytes, for ta_migrate_apply to write into."""
+        boxes = np.ascontiguousarray(boxes, np.float64).reshape(-1, 6)
+        P = boxes.shape[0]
+        ds = cls.__new__(cls)
+        ds.fixed = True
+        ds.n, ds.P = cap, P
+        ds.uid = torch.zeros(max(cap, 1), dtype=torch.int64, device=device)
+        ds.cls = torch.zeros(max(cap, 1), dtype=torch.int16, device=device)
+        ds.nb = torch.zeros(max(cap, 1), dtype=torch.int16, device=device)
+        ds.f64 = torch.zeros((F, max(cap, 1)), dtype=torch.float64, device=device)
+        ds.i32 = torch.zeros((I, max(cap, 1)), dtype=torch.int32, device=device)
+        ds.beh_off = torch.zeros(cap + 1, dtype=torch.int64, device=device)
+        ds.beh = torch.zeros(max(beh_cap, 8), dtype=torch.uint8, device=device)
+        ds.beh_cap = beh_cap
+        ds.part_off = torch.zeros(P + 1, dtype=torch.int64, device=device)
+        ds.boxes = torch.from_numpy(boxes.reshape(-1).copy()).to(device)
+        ds.max_beh_words = 0
+        ds.live = 0
+        ds._s = Agents(ds.n, _p(ds.uid), _p(ds.cls), _p(ds.nb), _p(ds.f64), ds.f64.shape[1], _p(ds.i32),
+                       ds.i32.shape[1], _p(ds.beh_off), _p(ds.beh))
+        return ds
+
+    def store_struct(self):
+        """The buffers as a ta_store (for calls that write a store)."""
+        return StoreT(self.n, _p(self.uid), _p(self.cls), _p(self.nb), _p(self.f64), self.f64.shape[1],
+                      _p(self.i32), self.i32.shape[1], _p(self.beh_off), _p(self.beh),
+                      getattr(self, "beh_cap", self.beh.numel()))
+
+    def numpy(self):
+        """The live agents (part_off[P] of them) back on the host, as a synth.Store."""
+        from . import synth
+        po = self.part_off.cpu().numpy()
+        n = int(po[-1])
+        bo = self.beh_off[:n + 1].cpu().numpy()
+        return synth.Store(uid=self.uid[:n].cpu().numpy().view(np.uint64), cls=self.cls[:n].cpu().numpy().view(np.uint16),
+                           nb=self.nb[:n].cpu().numpy().view(np.uint16), f64=self.f64[:, :n].cpu().numpy(),
+                           i32=self.i32[:, :n].cpu().numpy(), beh_off=bo,
+                           beh=self.beh[:int(bo[-1]) if n else 0].cpu().numpy(), part_off=po,
+                           boxes=self.boxes.cpu().numpy().reshape(-1, 6))
+
 
 class History:
     """Predictor history on the device: h1, h2 int64[n,4] (fp64 bits), hlen uint8[n]."""
@@ -270,6 +322,28 @@ class Context:
         _check(lib().ta_select_aura(self.h, C.byref(ds.agents()), ds.P, _p(ds.part_off), _p(ds.boxes), float(w),
                                     ndirs, _p(idx), idx_cap, _p(seg_off), _stream()), "ta_select_aura")
         return idx, seg_off
+
+    def select_migrants(self, ds: DeviceStore, idx_cap: int | None = None, out=None):
+        if idx_cap is None:
+            idx_cap = max(64, ds.n)
+        idx = out[0] if out is not None else torch.empty(max(idx_cap, 1), dtype=torch.int32, device=ds.uid.device)
+        seg_off = out[1] if out is not None else torch.empty(ds.P * 26 + 1, dtype=torch.int64, device=ds.uid.device)
+        _check(lib().ta_select_migrants(self.h, C.byref(ds.agents()), ds.P, _p(ds.part_off), _p(ds.boxes), _p(idx),
+                                        idx_cap, _p(seg_off), _stream()), "ta_select_migrants")
+        return idx, seg_off
+
+    def migrate_apply(self, ds: DeviceStore, msgs, msg_off, msg_part, out: DeviceStore, sizes=None):
+        """Build out (a DeviceStore from DeviceStore.alloc) from ds and the
+        migration messages; out.part_off receives the result's partitions.
+        Returns the device int64[2] sizes (agents, behaviour bytes)."""
+        nseg = msg_off.numel() - 1
+        if sizes is None:
+            sizes = torch.empty(2, dtype=torch.int64, device=ds.uid.device)
+        so = out.store_struct()
+        _check(lib().ta_migrate_apply(self.h, C.byref(ds.agents()), ds.P, _p(ds.part_off), _p(ds.boxes), _p(msgs),
+                                      msgs.numel() if msgs is not None else 0, _p(msg_off), nseg, _p(msg_part),
+                                      C.byref(so), _p(out.part_off), _p(sizes), _stream()), "ta_migrate_apply")
+        return sizes
 
     def serialize_bound(self, ds: DeviceStore, nseg: int, idx_cap: int) -> int:
         words = 2 + self.max_f + (self.max_i + 1) // 2 + ds.max_beh_words
