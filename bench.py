@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-migration", action="store_true", help="skip the agent-migration measurement")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--per-partition", action="store_true", help="batched: also time per-partition calls")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -449,6 +450,13 @@ def main():
         out["bytes_per_agent"]["learned_segments"] = lsegs
         out["bytes_per_agent"]["learned_training"] = f"{trained['random_walk'][1]} windows of the 1e5-agent world"
         out["bytes_per_agent"]["persistent_variant"] = persistent_variant(native, synth, trained["persistent"][0])
+    if not args.no_migration and not batched:
+        del dev_states
+        torch.cuda.empty_cache()
+        out["migration"] = migration_pass(native, synth, args.warmup, args.steps)
+        log(f"migration: {out['migration']['ms_per_step']:.3f} ms/step, "
+            f"{out['migration']['migrants_per_step']} migrants, migrate_keep "
+            f"{out['migration']['roofline']['achieved']:.0f} GB/s")
     if not args.no_cpu and not batched:
         out["cpu_baseline"] = cpu_baseline(host_states, cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -472,6 +480,83 @@ def measured_traffic(kernel, workload):
     if digest != rec["sha256"] or rec["workload"] != workload:
         return None
     return rec["bytes_per_launch"]
+
+
+def migration_pass(native, synth, warmup, steps, agents=1e7):
+    """Agent migration on one GPU's share of space: `agents` sphere agents in a
+    2x2x2 grid of 500 um boxes (the 1000^3 um domain of the single-box
+    workload), walls only at the domain boundary, one Gaussian walk step of
+    sigma 0.1 um so that agents cross the inner faces.  A step selects the
+    migrants, serializes them and builds the new store from the old one and
+    the messages (each routed to the neighbouring box).  Every step takes the
+    same input, so its outputs are identical from step to step."""
+    import numpy as np
+    import torch
+    cfg = synth.config(2, grid=(2, 2, 2), side=500.0, median=agents / 8, walls="domain")
+    world = synth.World(cfg)
+    world.step()
+    st = world.store
+    ctx = native.Context(cfg.schema)
+    ds = native.DeviceStore(st)
+    F, I = st.f64.shape[0], st.i32.shape[0]
+    nseg = st.P * 26
+    dev = torch.device("cuda")
+    dest = torch.from_numpy(synth.neighbour_table(cfg.grid)).to(dev)
+    idx_cap = max(4096, st.n // 100)
+    idx = torch.empty(idx_cap, dtype=torch.int32, device=dev)
+    seg = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
+    ser_cap = ctx.serialize_bound(ds, nseg, idx_cap)
+    buf = torch.empty(ser_cap, dtype=torch.uint8, device=dev)
+    moff = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
+    out = native.DeviceStore.alloc(F, I, st.boxes, st.n + 4096, st.beh.size + (1 << 20))
+    sizes = torch.empty(2, dtype=torch.int64, device=dev)
+
+    def step():
+        ctx.select_migrants(ds, idx_cap=idx_cap, out=(idx, seg))
+        ctx.serialize(ds, idx, seg, idx_cap=idx_cap, out=(buf, moff))
+        ctx.migrate_apply(ds, buf, moff, dest, out, sizes=sizes)
+
+    for _ in range(warmup):
+        step()
+    ctx.check("migration warm-up")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(steps):
+        step()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    ctx.check("migration steps")
+    ctx.time_kernel("migrate_keep")
+    for _ in range(steps):
+        step()
+    launches, kernel_ms = ctx.kernel_time()
+    ctx.time_kernel(None)
+    ctx.check("migration instrumented steps")
+    migrants = int(seg[-1].item())
+    mi = idx[:migrants].cpu().numpy().astype(np.int64)
+    beh_m = int((st.beh_off[mi + 1] - st.beh_off[mi]).sum())
+    kept = st.n - migrants
+    sz = sizes.cpu().numpy()
+    assert int(sz[0]) == st.n and int(sz[1]) == st.beh.size, "migration lost or created agents"
+    # k_mig_keep moves every column of each agent that stays (read + write) and
+    # its behaviour bytes, reads two behaviour offsets and writes one
+    col_bytes = 12 + 8 * F + 4 * I
+    kb = 2 * (kept * col_bytes + (st.beh.size - beh_m)) + 24 * kept
+    avg_ms = kernel_ms / max(launches, 1)
+    achieved = kb / (avg_ms / 1000.0) / 1e9
+    ctx.close()
+    return {
+        "workload": (f"{st.n} sphere agents in 8 boxes of 500^3 um (2x2x2, walls at the 1000^3 um domain only), "
+                     "one walk step of sigma 0.1 um; select migrants + serialize + rebuild the store"),
+        "ms_per_step": ms,
+        "agents_per_s": st.n / (ms / 1000.0),
+        "migrants_per_step": migrants,
+        "roofline": {"kernel": "migrate_keep", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "launches": launches,
+                     "avg_ms": avg_ms, "algorithmic_bytes_per_launch": kb},
+    }
 
 
 def cpu_baseline(states, cfg, budget_s):

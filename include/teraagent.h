@@ -320,7 +320,8 @@ ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t
  * "encode_join", "encode_groups" (plain encodings: residual, block sizes,
  * offsets and blocks in one kernel), "predict", "encode_resid" and
  * "encode_pack" (learned encodings), "decode_unpack" (which also applies the
- * residual to the reference). */
+ * residual to the reference), "migrate_keep" (ta_migrate_apply: the agents
+ * that stay, copied into the new store). */
 ta_status ta_time_kernel(ta_ctx *ctx, const char *name);
 ta_status ta_kernel_time(ta_ctx *ctx, int64_t *launches, double *total_ms);
 

@@ -382,7 +382,10 @@ extern "C" ta_status ta_migrate_apply(ta_ctx* c, const ta_agents* in, int32_t P,
   const StoreOut so{out->uid, out->cls, out->nb, reinterpret_cast<uint64_t*>(out->f64), out->f64_stride, out->i32,
                     out->i32_stride, out->beh_off, out->beh};
   const uint64_t* opre = reinterpret_cast<const uint64_t*>(part_off_out);
-  k_mig_keep<<<grid_for(c, n, BLOCK), BLOCK, 0, s>>>(*in, po, P, c->max_f, c->max_i, sc, opre, so, c->d_status);
+  {
+    Timed tm(c, "migrate_keep", s);
+    k_mig_keep<<<grid_for(c, n, BLOCK), BLOCK, 0, s>>>(*in, po, P, c->max_f, c->max_i, sc, opre, so, c->d_status);
+  }
   k_mig_unpack<<<grid_for(c, rb, BLOCK), BLOCK, 0, s>>>(msgs, msg_off, msg_part, nseg, P, c->d_nf, c->d_ni, c->max_f,
                                                        c->max_i, sc, opre, so, c->d_status);
   TA_LAUNCH_CHECK();
