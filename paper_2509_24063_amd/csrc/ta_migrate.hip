@@ -134,6 +134,37 @@ struct KeepIn {
     }
     return in ? 1u : 0u;
   }
+  // All rounds' coordinates are loaded before any test; a wave inside one
+  // partition (the common case) reads its box once.
+  template <int R>
+  __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
+    const int l = lane_id();
+    int64_t ic[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = wbase + r * WAVE + l;
+      ic[r] = i < n ? i : n - 1;
+    }
+    if (lo == hi) {  // uniform
+      const double* b = boxes + 6 * lo;
+      double x[R][3];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[r][a] = __builtin_bit_cast(double, f64[a * stride + ic[r]]);
+      const double b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3], b4 = b[4], b5 = b[5];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool in = !(x[r][0] < b0) && !(x[r][0] >= b3) && !(x[r][1] < b1) && !(x[r][1] >= b4) &&
+                        !(x[r][2] < b2) && !(x[r][2] >= b5);
+        v[r] = (wbase + r * WAVE + l < n && in) ? 1u : 0u;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = wbase + r * WAVE + l < n ? (*this)(ic[r]) : 0u;
+    }
+  }
   __device__ void emit(int64_t i, uint64_t, uint64_t v) const { kflag[i] = (uint8_t)v; }
 };
 
@@ -141,14 +172,28 @@ struct KeepBehIn {
   const uint8_t* kflag;
   const int64_t* beh_off;
   uint32_t* status;
-  __device__ uint64_t operator()(int64_t i) const {
-    const int64_t a = beh_off[i], b = beh_off[i + 1];
-    if (!kflag[i]) return 0;
-    if ((a & 7) || b < a || ((b - a) & 7)) {
-      fail(status, ERR_INVALID);
-      return 0;
+  template <int R>
+  __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
+    const int l = lane_id();
+    uint8_t f[R];
+    int64_t a[R], b[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = wbase + r * WAVE + l, ic = i < n ? i : n - 1;
+      f[r] = kflag[ic];
+      a[r] = beh_off[ic];
+      b[r] = beh_off[ic + 1];
     }
-    return (uint64_t)(b - a);
+    __builtin_amdgcn_sched_barrier(0);
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool keep = wbase + r * WAVE + l < n && f[r];
+      const bool ok = !(a[r] & 7) && b[r] >= a[r] && !((b[r] - a[r]) & 7);
+      bad = bad || (keep && !ok);
+      v[r] = keep && ok ? (uint64_t)(b[r] - a[r]) : 0;
+    }
+    if (bad) fail(status, ERR_INVALID);
   }
 };
 
@@ -185,6 +230,58 @@ struct RecIn {
       return 0;
     }
     return dest[s] >= 0 ? 8 * (words - fixed) : 0;
+  }
+  // The same checks in stages for all rounds: message, then its
+  // descriptors, then the offsets, then the record words, then the class.
+  template <int R>
+  __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
+    const int l = lane_id();
+    int64_t s[R], rc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = wbase + r * WAVE + l;
+      rc[r] = i < n ? i : n - 1;
+      s[r] = last_le<uint64_t>(mpre, lo, hi + 1, (uint64_t)rc[r]);
+    }
+    const uint8_t* m[R];
+    uint32_t nn[R];
+    uint64_t rw[R], p0[R];
+    int32_t d[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      m[r] = msgs + msg_off[s[r]];
+      nn[r] = (uint32_t)mrec[s[r]];
+      rw[r] = mrw[s[r]];
+      p0[r] = mpre[s[r]];
+      d[r] = dest[s[r]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    Tam1Loc loc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) loc[r] = tam1_locate(m[r], nn[r], rw[r], (uint32_t)(rc[r] - (int64_t)p0[r]));
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t uid[R], hdr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tam1_words(m[r], nn[r], loc[r], &uid[r], &hdr[r]);
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t c[R];
+    uint64_t fx[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      c[r] = (uint32_t)(hdr[r] & 0xFFFF);
+      const uint32_t cc = c[r] < ncls ? c[r] : 0;
+      fx[r] = 2 + (uint64_t)nf[cc] + ((uint64_t)ni[cc] + 1) / 2;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t words = hdr[r] >> 32;
+      const bool ok = tam1_valid(loc[r], hdr[r]) && uid[r] != 0 && c[r] < ncls && words >= fx[r];
+      const bool live = wbase + r * WAVE + l < n;
+      bad = bad || (live && !ok);
+      v[r] = live && ok && d[r] >= 0 ? 8 * (words - fx[r]) : 0;
+    }
+    if (bad) fail(status, ERR_INVALID);
   }
 };
 
@@ -236,9 +333,12 @@ __global__ __launch_bounds__(1024) void k_mig_part(const int64_t* part_off, int3
   }
 }
 
-// Agents that stay: 64 consecutive agents per wave (their partition found
-// once per wave), every column copied as raw words, behaviour bytes word by
-// word.
+// Agents that stay: MK_U rounds of 64 consecutive agents per wave (their
+// partitions found once per wave).  Every agent's flag, prefixes and
+// behaviour range are loaded first, then each column is moved MK_U agents at
+// a time (loads of all rounds before their stores, indices clamped so no
+// load sits behind a branch), fp64 columns as raw words; behaviour bytes last.
+constexpr int MK_U = 4;
 __global__ __launch_bounds__(BLOCK) void k_mig_keep(ta_agents in, const uint64_t* part_off, int32_t P, int nfc,
                                                     int nic, MigScratch sc, const uint64_t* opre, StoreOut out,
                                                     uint32_t* status) {
@@ -246,22 +346,69 @@ __global__ __launch_bounds__(BLOCK) void k_mig_keep(ta_agents in, const uint64_t
   const int64_t n = sc.meta[1];
   const uint64_t* f64 = reinterpret_cast<const uint64_t*>(in.f64);
   const int l = lane_id();
-  for (int64_t b0 = ((int64_t)blockIdx.x * WAVES + wave_id()) * WAVE; b0 < n; b0 += (int64_t)gridDim.x * BLOCK) {
-    const int64_t i = b0 + l, last = b0 + WAVE - 1 < n ? b0 + WAVE - 1 : n - 1;
-    const int64_t q = wave_seg(part_off, P, (uint64_t)(i < n ? i : n - 1), (uint64_t)b0, (uint64_t)last);
-    if (i >= n || !sc.kflag[i]) continue;
-    const uint64_t j = opre[q] + sc.kscan[i] - sc.kscan[part_off[q]];
-    const uint64_t bb = sc.obpre[q] + sc.kbscan[i] - sc.kbscan[part_off[q]];
-    out.uid[j] = in.uid[i];
-    out.cls[j] = in.cls[i];
-    out.nb[j] = in.nb[i];
-    for (int k = 0; k < nfc; ++k) out.f64[k * out.fs + j] = f64[k * in.f64_stride + i];
-    for (int k = 0; k < nic; ++k) out.i32[k * out.is + j] = in.i32[k * in.i32_stride + i];
-    out.beh_off[j] = (int64_t)bb;
-    const int64_t a = in.beh_off[i], nw = (in.beh_off[i + 1] - a) / 8;
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(in.beh + a);
-    uint64_t* dst = reinterpret_cast<uint64_t*>(out.beh + bb);
-    for (int64_t w = 0; w < nw; ++w) dst[w] = src[w];
+  constexpr int64_t SPAN = (int64_t)WAVE * MK_U;
+  for (int64_t b0 = ((int64_t)blockIdx.x * WAVES + wave_id()) * SPAN; b0 < n; b0 += (int64_t)gridDim.x * WAVES * SPAN) {
+    const int64_t last = b0 + SPAN - 1 < n ? b0 + SPAN - 1 : n - 1;
+    const int64_t lo = wave_last_le<uint64_t>(part_off, 0, P, (uint64_t)b0);
+    const int64_t hi = wave_last_le<uint64_t>(part_off, lo, P, (uint64_t)last);
+    int64_t ic[MK_U];
+    uint64_t j[MK_U], bb[MK_U];
+    int64_t ba[MK_U], be[MK_U];
+    bool keep[MK_U];
+#pragma unroll
+    for (int u = 0; u < MK_U; ++u) {
+      const int64_t i = b0 + (int64_t)u * WAVE + l;
+      ic[u] = i < n ? i : n - 1;
+      const int64_t q = last_le<uint64_t>(part_off, lo, hi + 1, (uint64_t)ic[u]);
+      keep[u] = i < n && sc.kflag[ic[u]];
+      j[u] = opre[q] + sc.kscan[ic[u]] - sc.kscan[part_off[q]];
+      bb[u] = sc.obpre[q] + sc.kbscan[ic[u]] - sc.kbscan[part_off[q]];
+      ba[u] = in.beh_off[ic[u]];
+      be[u] = in.beh_off[ic[u] + 1];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      uint64_t uid[MK_U];
+      uint16_t cl[MK_U], nb[MK_U];
+#pragma unroll
+      for (int u = 0; u < MK_U; ++u) {
+        uid[u] = in.uid[ic[u]];
+        cl[u] = in.cls[ic[u]];
+        nb[u] = in.nb[ic[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < MK_U; ++u)
+        if (keep[u]) {
+          out.uid[j[u]] = uid[u];
+          out.cls[j[u]] = cl[u];
+          out.nb[j[u]] = nb[u];
+          out.beh_off[j[u]] = (int64_t)bb[u];
+        }
+    }
+    for (int k = 0; k < nfc; ++k) {
+      uint64_t v[MK_U];
+#pragma unroll
+      for (int u = 0; u < MK_U; ++u) v[u] = f64[k * in.f64_stride + ic[u]];
+#pragma unroll
+      for (int u = 0; u < MK_U; ++u)
+        if (keep[u]) out.f64[k * out.fs + j[u]] = v[u];
+    }
+    for (int k = 0; k < nic; ++k) {
+      int32_t v[MK_U];
+#pragma unroll
+      for (int u = 0; u < MK_U; ++u) v[u] = in.i32[k * in.i32_stride + ic[u]];
+#pragma unroll
+      for (int u = 0; u < MK_U; ++u)
+        if (keep[u]) out.i32[k * out.is + j[u]] = v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < MK_U; ++u) {
+      if (!keep[u]) continue;
+      const int64_t nw = (be[u] - ba[u]) / 8;
+      const uint64_t* src = reinterpret_cast<const uint64_t*>(in.beh + ba[u]);
+      uint64_t* dst = reinterpret_cast<uint64_t*>(out.beh + bb[u]);
+      for (int64_t w = 0; w < nw; ++w) dst[w] = src[w];
+    }
   }
 }
 
@@ -384,7 +531,8 @@ extern "C" ta_status ta_migrate_apply(ta_ctx* c, const ta_agents* in, int32_t P,
   const uint64_t* opre = reinterpret_cast<const uint64_t*>(part_off_out);
   {
     Timed tm(c, "migrate_keep", s);
-    k_mig_keep<<<grid_for(c, n, BLOCK), BLOCK, 0, s>>>(*in, po, P, c->max_f, c->max_i, sc, opre, so, c->d_status);
+    k_mig_keep<<<grid_for(c, n, BLOCK * MK_U), BLOCK, 0, s>>>(*in, po, P, c->max_f, c->max_i, sc, opre, so,
+                                                             c->d_status);
   }
   k_mig_unpack<<<grid_for(c, rb, BLOCK), BLOCK, 0, s>>>(msgs, msg_off, msg_part, nseg, P, c->d_nf, c->d_ni, c->max_f,
                                                        c->max_i, sc, opre, so, c->d_status);
