@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-migration", action="store_true", help="skip the agent-migration measurement")
+    ap.add_argument("--migration-only", action="store_true",
+                    help="only the agent-migration measurement (for profiling); prints its JSON object")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--per-partition", action="store_true", help="batched: also time per-partition calls")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -300,6 +302,9 @@ def main():
     from paper_2509_24063_amd import native, synth
 
     torch.cuda.set_device(0)
+    if args.migration_only:
+        print(json.dumps({"migration": migration_pass(native, synth, args.warmup, args.steps)}), flush=True)
+        return
     batched = args.workload == "batched"
     if batched:
         cfg = synth.config(3, **({"median": args.agents} if args.agents else {}))
