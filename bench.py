@@ -455,6 +455,11 @@ def main():
         out["bytes_per_agent"]["learned_segments"] = lsegs
         out["bytes_per_agent"]["learned_training"] = f"{trained['random_walk'][1]} windows of the 1e5-agent world"
         out["bytes_per_agent"]["persistent_variant"] = persistent_variant(native, synth, trained["persistent"][0])
+    if not batched:
+        rb = refresh_bytes(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap)
+        out["bytes_per_agent"]["plain_delta_by_refresh_interval"] = {str(k): v / records for k, v in rb.items()}
+        log("plain delta bytes/record by refresh interval: " +
+            ", ".join(f"k={k}: {v / records:.2f}" for k, v in rb.items()))
     if not args.no_migration and not batched:
         del dev_states
         torch.cuda.empty_cache()
@@ -485,6 +490,25 @@ def measured_traffic(kernel, workload):
     if digest != rec["sha256"] or rec["workload"] != workload:
         return None
     return rec["bytes_per_launch"]
+
+
+def refresh_bytes(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, intervals=(1, 2, 4, 8)):
+    """Encoded bytes over the timed states when sender and receiver refresh
+    their reference only every k-th iteration (Sec. 2.3), per k."""
+    from paper_2509_24063_amd.exchange import Pipeline
+    out = {}
+    for k in intervals:
+        pl = Pipeline(ctx, dev_states[0], cfg.w, cfg.ndirs, idx_cap, ser_cap, refresh=k)
+        total = 0
+        for t, ds in enumerate(dev_states):
+            pl.step(ds)
+            if t >= warmup:
+                total += int(pl.outputs()[1][-1].item())
+        ctx.check(f"refresh {k}")
+        pl.close()
+        del pl
+        out[k] = total
+    return out
 
 
 def migration_pass(native, synth, warmup, steps, agents=1e7):

@@ -2,10 +2,15 @@
 
 A Pipeline owns everything an iteration writes -- selection, messages,
 encodings -- and two copies of each side's reference state (messages and
-predictor history), used alternately: iteration t reads copy t % 2 and
-writes copy (t + 1) % 2.  It runs each iteration eagerly
-(Context.run_iteration), or replays one of two captured HIP graphs (one per
-parity) when the agent store lives in fixed buffers (DeviceStore with cap).
+predictor history): an iteration reads the reference copy and writes its C'
+into the other copy.  Sender and receiver update their reference at regular
+intervals (Sec. 2.3): after every `refresh`-th iteration (t = 0, refresh,
+2 refresh, ...) the copy just written becomes the reference; in between, the
+same reference serves several iterations and each iteration's C' is only an
+output.  refresh = 1 makes every C' the next reference.  It runs each
+iteration eagerly (Context.run_iteration), or replays one of two captured HIP
+graphs (one per reference copy) when the agent store lives in fixed buffers
+(DeviceStore with cap).
 """
 from __future__ import annotations
 
@@ -17,8 +22,12 @@ from . import native
 
 class Pipeline:
     def __init__(self, ctx: native.Context, ds: native.DeviceStore, w: float, ndirs: int, idx_cap: int,
-                 msgs_cap: int, pred: native.Predictor | None = None, decode: bool = True, device="cuda"):
+                 msgs_cap: int, pred: native.Predictor | None = None, decode: bool = True, device="cuda",
+                 refresh: int = 1):
+        if refresh < 1:
+            raise ValueError("refresh interval must be >= 1")
         self.ctx, self.ds, self.w, self.ndirs, self.pred = ctx, ds, w, ndirs, pred
+        self.refresh = refresh
         self.nseg = nseg = ds.P * ndirs
         self.idx_cap, self.msgs_cap = idx_cap, msgs_cap
         self.enc_cap = int(native.lib().ta_delta_bound(nseg, msgs_cap, msgs_cap))
@@ -54,6 +63,8 @@ class Pipeline:
                 for h in hs:
                     h.hlen.zero_()
         self.t = 0
+        self.r = 0  # the reference copy
+        self.last = 1  # the copy the last iteration wrote
 
     def iteration(self, parity: int, ds: native.DeviceStore | None = None) -> native.Iteration:
         p, q = parity, 1 - parity
@@ -75,7 +86,7 @@ class Pipeline:
 
     def step(self, ds: native.DeviceStore | None = None, graph: bool = False):
         """Run one iteration on `ds` (default: the pipeline's store)."""
-        p = self.t % 2
+        p = self.r
         if graph:
             if ds is not None and ds is not self.ds:
                 raise ValueError("graphs are bound to the pipeline's store")
@@ -83,12 +94,16 @@ class Pipeline:
             self.graphs[p].launch()
         else:
             self.ctx.run_iteration(self.iteration(p, ds))
+        self.last = 1 - p
+        if self.t % self.refresh == 0:
+            self.r = 1 - p
         self.t += 1
 
     # -- results of the last iteration -------------------------------------------
     def outputs(self):
-        """(enc, enc_off, newref, newref_off, rx_out, rx_out_off) of the last iteration."""
-        q = self.t % 2
+        """(enc, enc_off, newref, newref_off, rx_out, rx_out_off) of the last iteration
+        (newref: its C', the next reference only after a refresh iteration)."""
+        q = self.last
         rx = (self.rx[q], self.rx_off[q]) if self.decode else (None, None)
         return (self.enc, self.enc_off, self.ref[q], self.ref_off[q]) + rx
 
