@@ -70,6 +70,8 @@ def _declare(L):
     L.orc_select_migrants.argtypes = [i64, vp, vp, i64, vp, vp, i64, vp]
     L.orc_migrate_apply.argtypes = [C.POINTER(Agents), i64, vp, vp, i32, vp, vp, i32, i32, vp, i64, vp, i64, vp,
                                     C.POINTER(OStore), vp, vp]
+    L.orc_view_grow.argtypes = [vp, i64, vp, i64, vp, vp, vp, i64, C.POINTER(C.c_int64)]
+    L.orc_view_compact.argtypes = [vp, i64, vp, i64, vp, i64, vp]
     L.orc_serialize.argtypes = [C.POINTER(Agents), i32, vp, vp, vp, vp, i64, vp, i64, vp]
     L.orc_view.argtypes = [vp, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.orc_mlp_parse.argtypes = [vp, i64, C.POINTER(MLP)]
@@ -167,6 +169,39 @@ def migrate_apply(store, schema, msgs: np.ndarray, msg_off: np.ndarray, dest: np
         out.update(uid=o["uid"][:n], cls=o["cls"][:n], nb=o["nb"][:n], f64=o["f64"][:nf_cols, :n],
                    i32=o["i32"][:ni_cols, :n], beh_off=o["beh_off"][: n + 1], beh=o["beh"][: int(sizes[1])])
     return st, out
+
+
+def view_grow(buf: np.ndarray, msg_off: np.ndarray, seg, rec, words, arena_used: int = 0):
+    """Grow records in place (buf is modified): (status, arena_used)."""
+    L = lib()
+    assert buf.dtype == np.uint8 and buf.flags.c_contiguous
+    msg_off = np.ascontiguousarray(msg_off, np.int64)
+    seg = np.ascontiguousarray(seg, np.int32)
+    rec = np.ascontiguousarray(rec, np.uint32)
+    words = np.ascontiguousarray(words, np.uint32)
+    n = seg.shape[0]
+    pad = lambda a: a if a.size else np.zeros(1, a.dtype)  # noqa: E731
+    used = C.c_int64(arena_used)
+    st = L.orc_view_grow(_p(buf), buf.shape[0], _p(msg_off), msg_off.shape[0] - 1, _p(pad(seg)), _p(pad(rec)),
+                         _p(pad(words)), n, C.byref(used))
+    return st, int(used.value)
+
+
+def view_compact(buf: np.ndarray, msg_off: np.ndarray, out_cap: int | None = None):
+    """Canonical copies: (status, out bytes, out_off)."""
+    L = lib()
+    msg_off = np.ascontiguousarray(msg_off, np.int64)
+    nseg = msg_off.shape[0] - 1
+    out_off = np.zeros(nseg + 1, np.int64)
+    b = np.ascontiguousarray(buf, np.uint8)
+    if out_cap is None:
+        st = L.orc_view_compact(_p(b), b.shape[0], _p(msg_off), nseg, None, 0, _p(out_off))
+        if st not in (OK, CAPACITY):
+            return st, None, out_off
+        out_cap = int(out_off[-1])
+    out = np.zeros(max(out_cap, 8), np.uint8)
+    st = L.orc_view_compact(_p(b), b.shape[0], _p(msg_off), nseg, _p(out), out_cap, _p(out_off))
+    return st, out[: int(out_off[-1])] if st == OK else None, out_off
 
 
 def _agents(store):

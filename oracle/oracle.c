@@ -954,3 +954,123 @@ int orc_migrate_apply(const orc_agents *in, int64_t P, const int64_t *part_off, 
   free(keep);
   return ORC_OK;
 }
+
+/* ======================================================================== */
+/* Growth of viewed records (Sec. 2.2.1 "Mutability")                       */
+/* ======================================================================== */
+/*
+ * A record used in place may need more room than it has in its message (a
+ * behaviour is added).  The paper's answer is a new block outside the buffer
+ * and the old block given up.  Here the new block comes from an arena that
+ * follows the last message in the same buffer: bytes [msg_off[nseg], cap),
+ * of which *arena_used are taken; a record's block in use must lie below
+ * the arena's free part.  A grown record keeps its words, gets zero
+ * words up to its new size and that size in its header, and its offset is
+ * redirected to the new block (offsets count 8-byte words from the message's
+ * record area, so they may now point past it).  Compaction writes messages
+ * whose offsets are redirected back in canonical form.
+ */
+/* Header of a message whose offsets may be redirected: the checks of the
+ * view without the ones on offsets and records. */
+static int tam1_head(const uint8_t *msg, int64_t len, int64_t *n_out, int64_t *rw_out) {
+  if (len < 32) return ORC_INVALID;
+  if (get32(msg) != TAM1_MAGIC || get16(msg + 4) != 1 || get16(msg + 6) != 0) return ORC_INVALID;
+  if (get32(msg + 12) != 0 || get64(msg + 24) != 0) return ORC_INVALID;
+  int64_t n = get32(msg + 8);
+  uint64_t rw = get64(msg + 16);
+  if (n > len / 4 || rw > (uint64_t)len / 8) return ORC_INVALID;
+  if (rw < 2 * (uint64_t)n || (n == 0 && rw != 0)) return ORC_INVALID;
+  if (32 + 8 * ((n + 1) / 2) + 8 * (int64_t)rw != len) return ORC_INVALID;
+  if (n % 2 && get32(msg + 32 + 4 * n) != 0) return ORC_INVALID;
+  *n_out = n;
+  *rw_out = (int64_t)rw;
+  return ORC_OK;
+}
+
+/* Byte position of record r of the message at a (header already checked)
+ * and its size in words; the record must lie below byte `limit`. */
+static int locate_any(const uint8_t *msgs, int64_t limit, int64_t a, int64_t n, int64_t r, int64_t *pos,
+                      int64_t *words) {
+  int64_t recs = a + 32 + 8 * ((n + 1) / 2);
+  int64_t p = recs + 8 * (int64_t)get32(msgs + a + 32 + 4 * r);
+  if (p + 16 > limit) return ORC_INVALID;
+  int64_t w = (int64_t)(get64(msgs + p + 8) >> 32);
+  if (w < 2 || p + 8 * w > limit) return ORC_INVALID;
+  *pos = p;
+  *words = w;
+  return ORC_OK;
+}
+
+int orc_view_grow(uint8_t *msgs, int64_t cap, const int64_t *msg_off, int64_t nseg, const int32_t *seg,
+                  const uint32_t *rec, const uint32_t *words, int64_t n, int64_t *arena_used) {
+  if (nseg < 0 || n < 0 || cap > ((int64_t)1 << 35)) return ORC_INVALID;
+  int64_t a0 = msg_off[nseg];
+  if (a0 < 0 || a0 > cap || a0 % 8 != 0 || *arena_used < 0 || *arena_used % 8 != 0) return ORC_INVALID;
+  int64_t need = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t s = seg[k];
+    if (s < 0 || s >= nseg) return ORC_INVALID;
+    if (k > 0 && (seg[k] < seg[k - 1] || (seg[k] == seg[k - 1] && rec[k] <= rec[k - 1]))) return ORC_INVALID;
+    int64_t a = msg_off[s], nn, rw, pos, w;
+    if (a < 0 || msg_off[s + 1] < a || msg_off[s + 1] > a0 || a % 8 != 0) return ORC_INVALID;
+    if (tam1_head(msgs + a, msg_off[s + 1] - a, &nn, &rw) || rec[k] >= nn) return ORC_INVALID;
+    /* the block in use lies below the arena's free part (the part this call fills) */
+    if (locate_any(msgs, a0 + *arena_used, a, nn, rec[k], &pos, &w) || (int64_t)words[k] < w) return ORC_INVALID;
+    need += 8 * (int64_t)words[k];
+  }
+  if (a0 + *arena_used + need > cap) return ORC_CAPACITY;
+  int64_t at = a0 + *arena_used;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t s = seg[k], a = msg_off[s], nn, rw, pos, w;
+    tam1_head(msgs + a, msg_off[s + 1] - a, &nn, &rw);
+    locate_any(msgs, cap, a, nn, rec[k], &pos, &w);
+    memcpy(msgs + at, msgs + pos, (size_t)(8 * w));
+    memset(msgs + at + 8 * w, 0, (size_t)(8 * ((int64_t)words[k] - w)));
+    uint64_t h = get64(msgs + at + 8);
+    put64(msgs + at + 8, (h & 0xFFFFFFFFull) | ((uint64_t)words[k] << 32));
+    int64_t recs = a + 32 + 8 * ((nn + 1) / 2);
+    put32(msgs + a + 32 + 4 * (int64_t)rec[k], (uint32_t)((at - recs) / 8));
+    at += 8 * (int64_t)words[k];
+  }
+  *arena_used += need;
+  return ORC_OK;
+}
+
+int orc_view_compact(const uint8_t *msgs, int64_t cap, const int64_t *msg_off, int64_t nseg, uint8_t *out,
+                     int64_t out_cap, int64_t *out_off) {
+  if (nseg < 0) return ORC_INVALID;
+  int64_t total = 0;
+  for (int64_t s = 0; s < nseg; ++s) {
+    int64_t a = msg_off[s], nn, rw, pos, w, sum = 0;
+    if (a < 0 || msg_off[s + 1] < a || msg_off[s + 1] > cap || a % 8 != 0) return ORC_INVALID;
+    if (tam1_head(msgs + a, msg_off[s + 1] - a, &nn, &rw)) return ORC_INVALID;
+    for (int64_t r = 0; r < nn; ++r) {
+      if (locate_any(msgs, cap, a, nn, r, &pos, &w)) return ORC_INVALID;
+      sum += w;
+    }
+    out_off[s] = total;
+    total += 32 + 8 * ((nn + 1) / 2) + 8 * sum;
+  }
+  out_off[nseg] = total;
+  if (total > out_cap) return ORC_CAPACITY;
+  for (int64_t s = 0; s < nseg; ++s) {
+    int64_t a = msg_off[s], nn, rw, pos, w, sum = 0;
+    tam1_head(msgs + a, msg_off[s + 1] - a, &nn, &rw);
+    uint8_t *m = out + out_off[s];
+    uint8_t *recs = m + 32 + 8 * ((nn + 1) / 2);
+    for (int64_t r = 0; r < nn; ++r) {
+      locate_any(msgs, cap, a, nn, r, &pos, &w);
+      put32(m + 32 + 4 * r, (uint32_t)sum);
+      memcpy(recs + 8 * sum, msgs + pos, (size_t)(8 * w));
+      sum += w;
+    }
+    if (nn % 2) put32(m + 32 + 4 * nn, 0);
+    put32(m, TAM1_MAGIC);
+    put32(m + 4, 1);  /* version 1, flags 0 */
+    put32(m + 8, (uint32_t)nn);
+    put32(m + 12, 0);
+    put64(m + 16, (uint64_t)sum);
+    put64(m + 24, 0);
+  }
+  return ORC_OK;
+}

@@ -125,6 +125,19 @@ int orc_migrate_apply(const orc_agents *in, int64_t P, const int64_t *part_off, 
                       const uint8_t *msgs, int64_t msgs_len, const int64_t *msg_off, int64_t nseg,
                       const int32_t *dest, orc_store *out, int64_t *part_off_out, int64_t *sizes);
 
+/* Growth of viewed records (Sec. 2.2.1 "Mutability"): record rec[k] of
+ * message seg[k] ((seg, rec) strictly ascending) moves to the arena after the
+ * last message (bytes [msg_off[nseg], cap), *arena_used of them taken) with
+ * room for words[k] words (>= its size): words copied, the rest zero, header
+ * size updated, offset redirected.  cap <= 2^35. */
+int orc_view_grow(uint8_t *msgs, int64_t cap, const int64_t *msg_off, int64_t nseg, const int32_t *seg,
+                  const uint32_t *rec, const uint32_t *words, int64_t n, int64_t *arena_used);
+
+/* Canonical copies of messages whose offsets may be redirected (records in
+ * order, offsets the running sum of sizes). */
+int orc_view_compact(const uint8_t *msgs, int64_t cap, const int64_t *msg_off, int64_t nseg, uint8_t *out,
+                     int64_t out_cap, int64_t *out_off);
+
 #ifdef __cplusplus
 }
 #endif
