@@ -197,6 +197,36 @@ int64_t ta_serialize_bound(int64_t nseg, int64_t nrec, int64_t max_words);
  * updated in place.  Bad header or size -> TA_ERR_INVALID. */
 ta_status ta_view(uint8_t *msg, int64_t len, ta_view_t *out);
 
+/* Growth of records used in place (Sec. 2.2.1, "Mutability": a record that
+ * needs more room than its message gives it moves to a new block outside its
+ * message, and the old block is given up).  The new blocks come from an
+ * arena that follows the last message in the same device buffer: bytes
+ * [msg_off[nseg], cap) of msgs, of which *arena_used (device int64, a
+ * multiple of 8) are taken.  For k < n, record rec[k] of message seg[k]
+ * (device arrays; (seg, rec) strictly ascending) moves to the next free
+ * words[k] words of the arena (words[k] >= its size): its words are copied,
+ * the rest zeroed, its header's word count set to words[k], and its offset
+ * entry redirected there (offsets count 8-byte words from the message's
+ * record area, so they may point past it; views see the grown record).
+ * *arena_used grows by 8 * sum(words).  A listed record whose block in use
+ * is not below msg_off[nseg] + *arena_used, a bad message or list, or cap >
+ * 2^35 -> TA_ERR_INVALID; an arena too small -> TA_ERR_CAPACITY; in both
+ * cases nothing is written.  A message with redirected offsets is read by
+ * ta_view and by the caller, not by the delta encoder: ta_view_compact first. */
+ta_status ta_view_grow(ta_ctx *ctx, uint8_t *msgs, int64_t cap, const int64_t *msg_off, int64_t nseg,
+                       const int32_t *seg, const uint32_t *rec, const uint32_t *words, int64_t n,
+                       int64_t *arena_used, void *stream);
+
+/* Canonical copies of messages whose offsets may be redirected (Sec. 2.2.1):
+ * message s of out holds the records of message s of msgs (cap bytes) in
+ * order, offsets the running sum of their sizes.  out_off (device
+ * int64[nseg+1]) receives the output offsets, also when they exceed out_cap
+ * (-> TA_ERR_CAPACITY, nothing else written).  A bad header, or a record
+ * whose block is not inside msgs -> TA_ERR_INVALID (out and out_off
+ * unspecified).  Compacting a canonical message copies it unchanged. */
+ta_status ta_view_compact(ta_ctx *ctx, const uint8_t *msgs, int64_t cap, const int64_t *msg_off, int64_t nseg,
+                          uint8_t *out, int64_t out_cap, int64_t *out_off, void *stream);
+
 /* Full O(n) check of the offsets and record headers of nseg device messages
  * (msgs at msg_off[s] .. msg_off[s+1]); problems -> TA_ERR_INVALID in the
  * status word. */

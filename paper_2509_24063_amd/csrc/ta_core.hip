@@ -165,6 +165,10 @@ extern "C" ta_status ta_reserve(ta_ctx* c, int64_t max_agents, int64_t max_segme
   tiles = std::max(tiles, t);
   need = std::max(need, migrate_scratch(max_agents, max_segments, max_segments, max_msg_bytes, &t));
   tiles = std::max(tiles, t);
+  need = std::max(need, grow_scratch(max_records, &t));
+  tiles = std::max(tiles, t);
+  need = std::max(need, compact_scratch(max_segments, max_msg_bytes, &t));
+  tiles = std::max(tiles, t);
   return ensure_scratch(c, need, tiles);
 }
 

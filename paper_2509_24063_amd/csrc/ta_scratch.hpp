@@ -14,4 +14,6 @@ size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t ou
                       bool learned, int64_t* tiles);
 size_t validate_scratch(int64_t nseg, int64_t len, int64_t* tiles);
 size_t migrate_scratch(int64_t n_agents, int64_t P, int64_t nseg, int64_t msgs_len, int64_t* tiles);
+size_t grow_scratch(int64_t n, int64_t* tiles);
+size_t compact_scratch(int64_t nseg, int64_t cap, int64_t* tiles);
 }  // namespace ta

@@ -80,6 +80,8 @@ def lib():
         L.ta_select_migrants.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, vp, i64, vp, vp]
         L.ta_migrate_apply.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, vp, i64, vp, i64, vp, C.POINTER(StoreT),
                                        vp, vp, vp]
+        L.ta_view_grow.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, i64, vp, vp]
+        L.ta_view_compact.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
         L.ta_serialize.argtypes = [vp, C.POINTER(Agents), vp, vp, i64, i64, vp, i64, vp, vp]
         L.ta_serialize_bound.argtypes = [i64, i64, i64]
         L.ta_serialize_bound.restype = i64
@@ -344,6 +346,16 @@ class Context:
                                       msgs.numel() if msgs is not None else 0, _p(msg_off), nseg, _p(msg_part),
                                       C.byref(so), _p(out.part_off), _p(sizes), _stream()), "ta_migrate_apply")
         return sizes
+
+    def view_grow(self, buf, msg_off, seg, rec, words, arena_used):
+        """Grow records in place (see ta_view_grow); arena_used: device int64[1]."""
+        n = seg.numel()
+        _check(lib().ta_view_grow(self.h, _p(buf), buf.numel(), _p(msg_off), msg_off.numel() - 1, _p(seg), _p(rec),
+                                  _p(words), n, _p(arena_used), _stream()), "ta_view_grow")
+
+    def view_compact(self, buf, msg_off, out, out_off):
+        _check(lib().ta_view_compact(self.h, _p(buf), buf.numel(), _p(msg_off), msg_off.numel() - 1, _p(out),
+                                     out.numel(), _p(out_off), _stream()), "ta_view_compact")
 
     def serialize_bound(self, ds: DeviceStore, nseg: int, idx_cap: int) -> int:
         words = 2 + self.max_f + (self.max_i + 1) // 2 + ds.max_beh_words
