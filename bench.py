@@ -456,6 +456,9 @@ def main():
         out["bytes_per_agent"]["learned_training"] = f"{trained['random_walk'][1]} windows of the 1e5-agent world"
         out["bytes_per_agent"]["persistent_variant"] = persistent_variant(native, synth, trained["persistent"][0])
     if not batched:
+        out["growth"] = growth_pass(ctx, native, cfg, dev_states[0], idx_cap, ser_cap, args.warmup, K)
+        log(f"growth of every 100th record by 2 words: grow {out['growth']['grow_ms']:.3f} ms, compact "
+            f"{out['growth']['compact_ms']:.3f} ms ({out['growth']['compact_GBps']:.0f} GB/s)")
         rb = refresh_bytes(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap)
         out["bytes_per_agent"]["plain_delta_by_refresh_interval"] = {str(k): v / records for k, v in rb.items()}
         log("plain delta bytes/record by refresh interval: " +
@@ -509,6 +512,62 @@ def refresh_bytes(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, interv
         del pl
         out[k] = total
     return out
+
+
+def growth_pass(ctx, native, cfg, ds, idx_cap, ser_cap, warmup, steps, every=100, extra=2):
+    """Growth of records used in place and compaction (Sec. 2.2.1
+    "Mutability") on the messages of one state of the workload: every
+    `every`-th record grows by `extra` words (a 16-byte behaviour), then the
+    whole message set is compacted.  The messages are restored before each
+    step, outside the timed region."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda")
+    idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=idx_cap)
+    buf, moff = ctx.serialize(ds, idx, seg, idx_cap=idx_cap)
+    ctx.check("growth setup")
+    so, mo = seg.cpu().numpy(), moff.cpu().numpy()
+    M, nrec = int(mo[-1]), int(so[-1])
+    hb = buf[:M].cpu().numpy()
+    g = np.arange(0, nrec, every, dtype=np.int64)
+    s_of = np.searchsorted(so, g, side="right") - 1
+    r_of = g - so[s_of]
+    a = mo[s_of]
+    n = hb[(a[:, None] + 8 + np.arange(4)).astype(np.int64)].view(np.uint32).ravel().astype(np.int64)
+    off = hb[(a[:, None] + 32 + 4 * r_of[:, None] + np.arange(4)).astype(np.int64)].view(np.uint32).ravel()
+    p = a + 32 + 8 * ((n + 1) // 2) + 8 * off.astype(np.int64)
+    w = hb[(p[:, None] + 12 + np.arange(4)).astype(np.int64)].view(np.uint32).ravel().astype(np.int64)
+    words = (w + extra).astype(np.uint32)
+    arena = 8 * int(words.sum()) + 64
+    work = torch.empty(M + arena, dtype=torch.uint8, device=dev)
+    seg_t = torch.from_numpy(s_of.astype(np.int32)).to(dev)
+    rec_t = torch.from_numpy(r_of.astype(np.uint32)).to(dev)
+    words_t = torch.from_numpy(words).to(dev)
+    used = torch.zeros(1, dtype=torch.int64, device=dev)
+    out_cap = M + 8 * extra * len(g)
+    out = torch.empty(out_cap, dtype=torch.uint8, device=dev)
+    out_off = torch.empty(moff.numel(), dtype=torch.int64, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_grow = t_cmp = 0.0
+    for k in range(warmup + steps):
+        work[:M].copy_(buf[:M])
+        used.zero_()
+        ev[0].record()
+        ctx.view_grow(work, moff, seg_t, rec_t, words_t, used)
+        ev[1].record()
+        ctx.view_compact(work, moff, out, out_off)
+        ev[2].record()
+        torch.cuda.synchronize()
+        if k >= warmup:
+            t_grow += ev[0].elapsed_time(ev[1])
+            t_cmp += ev[1].elapsed_time(ev[2])
+    ctx.check("growth steps")
+    assert int(out_off[-1].item()) == out_cap, "compacted size"
+    cmp_ms = t_cmp / steps
+    cmp_bytes = M + out_cap  # read every message once, write its canonical copy
+    return {"records": nrec, "grown": int(len(g)), "grow_ms": t_grow / steps, "compact_ms": cmp_ms,
+            "compact_GBps": cmp_bytes / (cmp_ms / 1000.0) / 1e9,
+            "compact_frac_hbm_peak": cmp_bytes / (cmp_ms / 1000.0) / 1e9 / HBM_PEAK_GBPS}
 
 
 def migration_pass(native, synth, warmup, steps, agents=1e7):

@@ -12,7 +12,8 @@
 //                  copied, zero words added, header size and offset updated)
 // ta_view_compact: k_cmp_setup (headers), k_scan_cols (record prefix),
 //                  k_scan<CRecIn> (record sizes, every block checked),
-//                  k_cmp_sizes, k_scan_cols (message offsets), k_cmp_write
+//                  k_cmp_sizes, k_scan_cols (message offsets), k_cmp_heads,
+//                  k_cmp_write (offset entries and record words)
 #include "ta_internal.hpp"
 #include "ta_msg.hpp"
 #include "ta_scratch.hpp"
@@ -165,6 +166,44 @@ struct CRecIn {
     }
     return w;
   }
+  // The same in stages for all rounds: message, its descriptors, the offset,
+  // the header word (read from the buffer's start when out of range).
+  template <int R>
+  __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
+    const int l = lane_id();
+    int64_t s[R];
+    uint64_t i[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t it = wbase + r * WAVE + l, rc = it < n ? it : n - 1;
+      s[r] = last_le<uint64_t>(rpre, lo, hi + 1, (uint64_t)rc);
+      i[r] = (uint64_t)rc;
+    }
+    uint64_t a[R], nn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      a[r] = (uint64_t)msg_off[s[r]];
+      nn[r] = mrec[s[r]];
+      i[r] -= rpre[s[r]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t p[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) p[r] = a[r] + 32 + 8 * ((nn[r] + 1) / 2) + 8 * (uint64_t)ld32(msgs + a[r] + 32 + 4 * i[r]);
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) w[r] = ld64(msgs + (p[r] + 16 <= (uint64_t)cap ? p[r] : 0) + 8) >> 32;
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool live = wbase + r * WAVE + l < n;
+      const bool ok = p[r] + 16 <= (uint64_t)cap && w[r] >= 2 && p[r] + 8 * w[r] <= (uint64_t)cap;
+      bad = bad || (live && !ok);
+      v[r] = live && ok ? w[r] : 0;
+    }
+    if (bad) fail(status, ERR_INVALID);
+  }
 };
 
 __global__ __launch_bounds__(BLOCK) void k_cmp_sizes(int64_t nseg, CmpScratch c, uint32_t* status) {
@@ -175,38 +214,83 @@ __global__ __launch_bounds__(BLOCK) void k_cmp_sizes(int64_t nseg, CmpScratch c,
   }
 }
 
-// Items [0, nseg): message headers and the zero pad of an odd offset table;
-// items [nseg, nseg + records): offset entries and record words.
+// Message headers and the zero pad of an odd offset table (one thread per
+// message).
+__global__ __launch_bounds__(BLOCK) void k_cmp_heads(int64_t nseg, CmpScratch c, uint8_t* out, const int64_t* out_off,
+                                                     uint32_t* status) {
+  if (status_of(status) & ANY_ERR) return;
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * BLOCK) {
+    const uint64_t nn = c.mrec[s];
+    uint8_t* m = out + out_off[s];
+    uint64_t* h = reinterpret_cast<uint64_t*>(m);
+    h[0] = (uint64_t)TAM1_MAGIC | (1ull << 32);  // version 1, flags 0
+    h[1] = nn;
+    h[2] = c.wscan[c.rpre[s + 1]] - c.wscan[c.rpre[s]];
+    h[3] = 0;
+    if (nn & 1) *reinterpret_cast<uint32_t*>(m + 32 + 4 * nn) = 0;
+  }
+}
+
+// Records: a wave takes 64 consecutive records (their messages found once
+// per wave), writes their offset entries, tabulates source and destination
+// words in LDS and copies the words lane-parallel (consecutive lanes,
+// consecutive words; CW_U words per lane in flight).
+constexpr int CW_U = 4;
+struct CopyTab {
+  uint64_t q[WAVE + 1];
+  uint64_t src[WAVE];
+  uint64_t dst[WAVE];
+};
 __global__ __launch_bounds__(BLOCK) void k_cmp_write(const uint8_t* msgs, const int64_t* msg_off, int64_t nseg,
                                                      CmpScratch c, uint8_t* out, const int64_t* out_off,
                                                      uint32_t* status) {
+  __shared__ CopyTab s_t[WAVES];
   if (status_of(status) & ANY_ERR) return;
   const int64_t Rt = c.meta[0];
-  const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x, stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t it = tid; it < nseg + Rt; it += stride) {
-    if (it < nseg) {
-      const int64_t s = it;
-      const uint64_t nn = c.mrec[s];
-      uint8_t* m = out + out_off[s];
-      uint64_t* h = reinterpret_cast<uint64_t*>(m);
-      h[0] = (uint64_t)TAM1_MAGIC | (1ull << 32);  // version 1, flags 0
-      h[1] = nn;
-      h[2] = c.wscan[c.rpre[s + 1]] - c.wscan[c.rpre[s]];
-      h[3] = 0;
-      if (nn & 1) *reinterpret_cast<uint32_t*>(m + 32 + 4 * nn) = 0;
-      continue;
-    }
-    const int64_t r = it - nseg;
-    const int64_t s = last_le<uint64_t>(c.rpre, 0, nseg, (uint64_t)r);
-    const uint64_t a = (uint64_t)msg_off[s], nn = c.mrec[s], i = (uint64_t)r - c.rpre[s];
+  const int l = lane_id(), wv = wave_id();
+  CopyTab& t = s_t[wv];
+  const uint64_t* src64 = reinterpret_cast<const uint64_t*>(msgs);
+  uint64_t* dst64 = reinterpret_cast<uint64_t*>(out);
+  for (int64_t r0 = ((int64_t)blockIdx.x * WAVES + wv) * WAVE; r0 < Rt; r0 += (int64_t)gridDim.x * BLOCK) {
+    const int64_t r = r0 + l, last = r0 + WAVE - 1 < Rt ? r0 + WAVE - 1 : Rt - 1;
+    const int n = (int)(last - r0 + 1);
+    const int64_t rc = r < Rt ? r : Rt - 1;
+    const int64_t s = wave_seg(c.rpre, nseg, (uint64_t)rc, (uint64_t)r0, (uint64_t)last);
+    const uint64_t a = (uint64_t)msg_off[s], nn = c.mrec[s], i = (uint64_t)rc - c.rpre[s];
     const uint64_t p = a + 32 + 8 * ((nn + 1) / 2) + 8 * (uint64_t)ld32(msgs + a + 32 + 4 * i);
-    const uint64_t q = c.wscan[r] - c.wscan[c.rpre[s]];  // the record's canonical offset
-    uint8_t* m = out + out_off[s];
-    *reinterpret_cast<uint32_t*>(m + 32 + 4 * i) = (uint32_t)q;
-    const uint64_t w = c.wscan[r + 1] - c.wscan[r];
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(msgs + p);
-    uint64_t* dst = reinterpret_cast<uint64_t*>(m + 32 + 8 * ((nn + 1) / 2)) + q;
-    for (uint64_t k = 0; k < w; ++k) dst[k] = src[k];
+    const uint64_t q = c.wscan[rc] - c.wscan[c.rpre[s]];  // the record's canonical offset
+    const uint64_t o = (uint64_t)out_off[s];
+    const uint64_t wr = c.wscan[rc] - c.wscan[r0];        // words before it in the wave
+    if (r < Rt) {
+      *reinterpret_cast<uint32_t*>(out + o + 32 + 4 * i) = (uint32_t)q;
+      t.q[l] = wr;
+      t.src[l] = p / 8;
+      t.dst[l] = (o + 32 + 8 * ((nn + 1) / 2)) / 8 + q;
+    }
+    if (l == 0) t.q[n] = c.wscan[last + 1] - c.wscan[r0];
+    wave_sync();
+    const uint64_t tot = t.q[n];
+    for (uint64_t q0 = l; q0 < tot; q0 += CW_U * WAVE) {
+      uint64_t v[CW_U], d[CW_U];
+#pragma unroll
+      for (int j = 0; j < CW_U; ++j) {
+        const uint64_t qq = q0 + (uint64_t)j * WAVE < tot ? q0 + (uint64_t)j * WAVE : tot - 1;
+        int lo = 0, hi = n;  // the last record whose first word is <= qq
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (t.q[mid] <= qq) lo = mid;
+          else hi = mid;
+        }
+        const uint64_t w = qq - t.q[lo];
+        v[j] = src64[t.src[lo] + w];
+        d[j] = t.dst[lo] + w;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < CW_U; ++j)
+        if (q0 + (uint64_t)j * WAVE < tot) dst64[d[j]] = v[j];
+    }
+    wave_sync();
   }
 }
 
@@ -310,7 +394,8 @@ extern "C" ta_status ta_view_compact(ta_ctx* c, const uint8_t* msgs, int64_t cap
     cs.n = nseg;
     k_scan_cols<<<1, 1024, 0, s>>>(cs);
   }
-  k_cmp_write<<<grid_for(c, rb + nseg, BLOCK), BLOCK, 0, s>>>(msgs, msg_off, nseg, m, out, out_off, c->d_status);
+  k_cmp_heads<<<grid_for(c, nseg, BLOCK), BLOCK, 0, s>>>(nseg, m, out, out_off, c->d_status);
+  k_cmp_write<<<grid_for(c, rb, BLOCK), BLOCK, 0, s>>>(msgs, msg_off, nseg, m, out, out_off, c->d_status);
   TA_LAUNCH_CHECK();
   return TA_OK;
 }
