@@ -218,3 +218,18 @@ def test_invalid_inputs_match_oracle_status(native, case):
                                    beh_cap=store.beh.size + 4096)
     assert st == oracle.INVALID and gst == native.INVALID
     ctx.close()
+
+
+def test_full_size_migration(native):
+    """The bench's migration workload (1e7 agents in a 2x2x2 grid of 500 um
+    boxes, walls at the domain only, one walk step): selection, messages and
+    every column of the rebuilt store against the oracle."""
+    cfg = synth.config(2, grid=(2, 2, 2), side=500.0, median=1e7 / 8, walls="domain")
+    w = synth.World(cfg)
+    w.step()
+    ctx = native.Context(cfg.schema)
+    st, want, gst, got = _exchange(native, ctx, cfg, w.store, synth.neighbour_table(cfg.grid), "full size")
+    assert st == oracle.OK and gst == native.OK
+    assert int(want["sizes"][0]) == w.store.n
+    _compare_store("full size", got, want, *_cols(cfg))
+    ctx.close()
