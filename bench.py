@@ -198,6 +198,29 @@ def eager_timed_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap):
     return elapsed, pl
 
 
+def overlap_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap):
+    """The exchange as a three-stage pipeline on three streams, a context each
+    (OverlapPipeline): selection and serialization of iteration t + 1,
+    encoding of t and decoding of t - 1 at the same time.  Same work per step
+    as the other modes."""
+    import torch
+    from paper_2509_24063_amd.exchange import OverlapPipeline
+    pl = OverlapPipeline(cfg.schema, dev_states[0], cfg.w, cfg.ndirs, idx_cap, ser_cap)
+    pl.reserve(max(s.n for s in dev_states))
+    for k in range(warmup):
+        pl.step(dev_states[k])
+    pl.check("overlap warm-up")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(warmup, len(dev_states)):
+        pl.step(dev_states[k])
+    pl.join()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    pl.check("overlap steps")
+    return elapsed, pl
+
+
 def learned_bytes(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, pred):
     """TAD1 bytes of the timed steps in learned mode (and the modes chosen)."""
     import numpy as np
@@ -352,7 +375,7 @@ def main():
         log(f"instrumented pass: {acc['step_ms'] / args.steps:.3f} ms/step (events); {kname}: "
             f"{kernel_ms / max(launches, 1) * 1000:.1f} us per launch")
     timings = {}
-    for mode, fn in (("eager", eager_timed_pass), ("graph", graph_pass)):
+    for mode, fn in (("eager", eager_timed_pass), ("graph", graph_pass), ("overlap", overlap_pass)):
         el, pl = fn(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap)
         # every mode produces the instrumented pass's final C'
         _, _, nref, noff, _, _ = pl.outputs()
@@ -426,6 +449,7 @@ def main():
         "timed_mode": mode,
         "eager_ms_per_step": 1000.0 * timings["eager"] / K,
         "graph_ms_per_step": 1000.0 * timings["graph"] / K,
+        "overlap_ms_per_step": 1000.0 * timings["overlap"] / K,
         "launch_grids": tuned,
         "serialize_delta": {
             "ms_per_step": acc["sd_ms"] / K,

@@ -131,3 +131,101 @@ def split_host(t, off):
     """Host bytes of dense messages/encodings: (buffer up to off[-1], offsets)."""
     o = off.cpu().numpy()
     return t[: int(o[-1])].cpu().numpy(), o
+
+
+class OverlapPipeline:
+    """One GPU's exchange as a three-stage pipeline on three streams, each
+    stage with its own context (its own scratch memory): selection and
+    serialization of iteration t + 1, encoding of t and decoding of t - 1
+    run at the same time.  In a deployment the receiver works on other
+    neighbours' messages and never waits for the sender; here it decodes the
+    sender's own encodings, which only adds the wait for them.
+
+    Messages and encodings are double-buffered (iteration t uses copy t % 2).
+    Each hand-off records an event on the producing stream that the consumer
+    waits for, and a producer waits for the consumer's event of t - 2 before
+    it writes the same copy again.  References ping-pong on each side as in
+    Pipeline (refresh interval 1).  Every stream has the default priority."""
+
+    def __init__(self, schema, ds: native.DeviceStore, w: float, ndirs: int, idx_cap: int, msgs_cap: int,
+                 device="cuda"):
+        self.ser, self.tx, self.rxc = native.Context(schema), native.Context(schema), native.Context(schema)
+        self.s_ser, self.s_enc, self.s_dec = (torch.cuda.Stream(device=device) for _ in range(3))
+        self.w, self.ndirs, self.ds = w, ndirs, ds
+        self.nseg = nseg = ds.P * ndirs
+        self.idx_cap, self.msgs_cap = idx_cap, msgs_cap
+        self.enc_cap = int(native.lib().ta_delta_bound(nseg, msgs_cap, msgs_cap))
+        z8 = lambda n: torch.zeros(max(n, 8), dtype=torch.uint8, device=device)  # noqa: E731
+        zo = lambda: torch.zeros(nseg + 1, dtype=torch.int64, device=device)  # noqa: E731
+        self.idx = [torch.zeros(max(idx_cap, 1), dtype=torch.int32, device=device) for _ in range(2)]
+        self.seg_off = [zo(), zo()]
+        self.msgs, self.msg_off = [z8(msgs_cap), z8(msgs_cap)], [zo(), zo()]
+        self.modes = torch.zeros(max(nseg, 1), dtype=torch.uint8, device=device)
+        self.enc, self.enc_off = [z8(self.enc_cap), z8(self.enc_cap)], [zo(), zo()]
+        self.ref, self.ref_off = [z8(msgs_cap), z8(msgs_cap)], [zo(), zo()]
+        self.rx, self.rx_off = [z8(msgs_cap), z8(msgs_cap)], [zo(), zo()]
+        self.ev_ser = [torch.cuda.Event(), torch.cuda.Event()]  # messages t % 2 written
+        self.ev_enc = [torch.cuda.Event(), torch.cuda.Event()]  # messages read, encoding t % 2 written
+        self.ev_dec = [torch.cuda.Event(), torch.cuda.Event()]  # encoding t % 2 read
+        empty, off = native.empty_messages(nseg, device)
+        for bufs, offs in ((self.ref, self.ref_off), (self.rx, self.rx_off)):
+            bufs[0][:empty.numel()].copy_(empty)
+            offs[0].copy_(off)
+        torch.cuda.synchronize()
+        self.t = 0
+
+    @property
+    def streams(self):
+        return (self.s_ser, self.s_enc, self.s_dec)
+
+    def reserve(self, max_agents: int):
+        for c in (self.ser, self.tx, self.rxc):
+            c.reserve(max_agents, self.nseg, self.idx_cap, self.msgs_cap)
+
+    def step(self, ds: native.DeviceStore | None = None):
+        ds = self.ds if ds is None else ds
+        t = self.t
+        m = t % 2  # messages and encoding copy
+        p, q = t % 2, 1 - t % 2  # reference copies read and written
+        with torch.cuda.stream(self.s_ser):
+            if t >= 2:
+                self.s_ser.wait_event(self.ev_enc[m])
+            self.ser.select_aura(ds, self.w, self.ndirs, idx_cap=self.idx_cap, out=(self.idx[m], self.seg_off[m]))
+            self.ser.serialize(ds, self.idx[m], self.seg_off[m], idx_cap=self.idx_cap,
+                               out=(self.msgs[m], self.msg_off[m]))
+            self.ev_ser[m].record(self.s_ser)
+        with torch.cuda.stream(self.s_enc):
+            self.s_enc.wait_event(self.ev_ser[m])
+            if t >= 2:
+                self.s_enc.wait_event(self.ev_dec[m])
+            self.tx.delta_encode(self.msgs[m], self.msg_off[m], self.ref[p], self.ref_off[p],
+                                 out=(self.enc[m], self.enc_off[m], self.ref[q], self.ref_off[q], self.modes))
+            self.ev_enc[m].record(self.s_enc)
+        with torch.cuda.stream(self.s_dec):
+            self.s_dec.wait_event(self.ev_enc[m])
+            self.rxc.delta_decode(self.enc[m], self.enc_off[m], self.rx[p], self.rx_off[p],
+                                  out=(self.rx[q], self.rx_off[q]))
+            self.ev_dec[m].record(self.s_dec)
+        self.t += 1
+
+    def join(self):
+        """Make the current stream wait for every stage."""
+        cur = torch.cuda.current_stream()
+        for st in self.streams:
+            cur.wait_stream(st)
+
+    def check(self, what="pipelined exchange"):
+        self.join()
+        for c, side in ((self.ser, "select/serialize"), (self.tx, "encode"), (self.rxc, "decode")):
+            c.check(f"{what} ({side})")
+
+    def outputs(self):
+        """(enc, enc_off, newref, newref_off, rx_out, rx_out_off) of the last iteration."""
+        e, q = (self.t - 1) % 2, self.t % 2
+        return self.enc[e], self.enc_off[e], self.ref[q], self.ref_off[q], self.rx[q], self.rx_off[q]
+
+    def close(self):
+        self.join()
+        torch.cuda.synchronize()
+        for c in (self.ser, self.tx, self.rxc):
+            c.close()
