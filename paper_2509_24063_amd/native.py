@@ -508,8 +508,10 @@ class Trainer:
         """(loss, gradient float32 [5252]) at the current parameters."""
         n = inputs.shape[0]
         out = torch.empty(self.N_PARAMS + 1, dtype=torch.float32, device=inputs.device)
-        _check(lib().ta_trainer_grad(self.ctx.h, self.h, _p(inputs.contiguous()), _p(targets.contiguous()), n,
-                                     _p(out), _stream()), "ta_trainer_grad")
+        # contiguous copies stay referenced until the call has been enqueued (a
+        # tensor freed earlier could be handed to another allocation first)
+        x, y = inputs.contiguous(), targets.contiguous()
+        _check(lib().ta_trainer_grad(self.ctx.h, self.h, _p(x), _p(y), n, _p(out), _stream()), "ta_trainer_grad")
         g = out.cpu().numpy()
         return float(g[-1]), g[:-1]
 
