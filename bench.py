@@ -171,7 +171,7 @@ def graph_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, pred=None
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     ctx.check("graph steps")
-    pl.t = len(dev_states)
+    pl.ran(len(dev_states))
     for g in graphs:
         g.close()
     return elapsed, pl
@@ -194,7 +194,7 @@ def eager_timed_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     ctx.check("eager timed steps")
-    pl.t = len(dev_states)
+    pl.ran(len(dev_states))
     return elapsed, pl
 
 

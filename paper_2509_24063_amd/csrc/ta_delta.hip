@@ -155,12 +155,25 @@ struct Common {
 // buckets (mean <= JB_TARGET items), and one block joins each bucket in LDS.
 constexpr int JT = 2048;          // minimum items per counting tile
 constexpr int JT_MAX_TILES = 64;  // counting tiles per segment side at most
-constexpr int JB_TARGET = 1024;
+#ifndef TA_JB_TARGET
+#define TA_JB_TARGET 1024
+#endif
+constexpr int JB_TARGET = TA_JB_TARGET;
 constexpr int JC_U = 4;           // join count: items per thread and pass
 constexpr int RS_U = 4;           // decoder reference slots: slots per lane and pass
 constexpr int JB_MAX = 8192;      // buckets per segment (LDS histogram)
-constexpr int JCAP = 3072;        // items of one bucket held in LDS
-constexpr int JTAB = 4096;        // LDS hash slots
+// A bucket holds JB_TARGET / 2 .. JB_TARGET items on average; JCAP at 1.5x
+// the target keeps the bucket block at 32 KB of LDS (five blocks per CU),
+// larger buckets take the global-table path.
+#ifndef TA_JCAP
+#define TA_JCAP 1536
+#endif
+#ifndef TA_JTAB
+#define TA_JTAB 2048
+#endif
+constexpr int JCAP = TA_JCAP;     // items of one bucket held in LDS
+constexpr int JTAB = TA_JTAB;     // LDS hash slots (a power of two above JCAP)
+static_assert(JTAB > JCAP && (JTAB & (JTAB - 1)) == 0, "the LDS table must never fill");
 __device__ inline uint32_t join_bucket(uint64_t uid, uint64_t B) { return (uint32_t)(mix64(uid) & (B - 1)); }
 
 // ---------------------------------------------------------------------------
@@ -2451,8 +2464,8 @@ Bounds enc_bounds(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t rec_ca
   b.R = rec_bound(ref_len, rec_cap);
   b.H = 4 * (b.C + b.R) + 2 * nseg + 1;
   b.G = ref_len / 512 + nseg + 1;
-  // join: per segment at most 130 counting tiles and 2 n/1024 + 1 buckets
-  b.E = (b.C + b.R) / 4 + 130 * nseg + 1;
+  // join: per segment at most 130 counting tiles and 2 n/JB_TARGET + 1 buckets
+  b.E = 260 * (b.C + b.R) / JB_TARGET + 130 * nseg + 1;
   b.T = (b.C + b.R) / JT + 2 * nseg + 1;
   b.B = 2 * (b.C + b.R) / JB_TARGET + nseg + 1;
   b.W = ref_len / 8 + 1;

@@ -99,6 +99,15 @@ class Pipeline:
             self.r = 1 - p
         self.t += 1
 
+    def ran(self, n: int):
+        """Bookkeeping after n iterations run outside step() (each one the
+        iteration of its parity, t = 0 .. n-1, refresh interval 1)."""
+        if self.refresh != 1:
+            raise ValueError("iterations run outside step() assume refresh interval 1")
+        self.t = n
+        self.r = n % 2
+        self.last = 1 - (n - 1) % 2
+
     # -- results of the last iteration -------------------------------------------
     def outputs(self):
         """(enc, enc_off, newref, newref_off, rx_out, rx_out_off) of the last iteration
