@@ -217,22 +217,8 @@ struct RecIn {
     lo = wave_last_le<uint64_t>(mpre, 0, nseg, (uint64_t)first);
     hi = wave_last_le<uint64_t>(mpre, lo, nseg, (uint64_t)last);
   }
-  __device__ uint64_t operator()(int64_t r) const {
-    const int64_t s = last_le<uint64_t>(mpre, lo, hi + 1, (uint64_t)r);
-    const uint8_t* m = msgs + msg_off[s];
-    uint32_t o;
-    uint64_t uid, hdr;
-    const bool ok = tam1_record(m, (uint32_t)mrec[s], mrw[s], (uint32_t)(r - (int64_t)mpre[s]), &o, &uid, &hdr);
-    const uint32_t c = (uint32_t)(hdr & 0xFFFF), cc = c < ncls ? c : 0;
-    const uint64_t fixed = 2 + (uint64_t)nf[cc] + ((uint64_t)ni[cc] + 1) / 2, words = hdr >> 32;
-    if (!ok || uid == 0 || c >= ncls || words < fixed) {
-      fail(status, ERR_INVALID);
-      return 0;
-    }
-    return dest[s] >= 0 ? 8 * (words - fixed) : 0;
-  }
-  // The same checks in stages for all rounds: message, then its
-  // descriptors, then the offsets, then the record words, then the class.
+  // All rounds in stages: message, then its descriptors, then the offsets,
+  // then the record words, then the class.
   template <int R>
   __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
     const int l = lane_id();

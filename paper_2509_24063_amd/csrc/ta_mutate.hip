@@ -151,23 +151,8 @@ struct CRecIn {
     lo = wave_last_le<uint64_t>(rpre, 0, nseg, (uint64_t)first);
     hi = wave_last_le<uint64_t>(rpre, lo, nseg, (uint64_t)last);
   }
-  __device__ uint64_t operator()(int64_t r) const {
-    const int64_t s = last_le<uint64_t>(rpre, lo, hi + 1, (uint64_t)r);
-    const uint64_t a = (uint64_t)msg_off[s], nn = mrec[s], i = (uint64_t)r - rpre[s];
-    const uint64_t p = a + 32 + 8 * ((nn + 1) / 2) + 8 * (uint64_t)ld32(msgs + a + 32 + 4 * i);
-    if (p + 16 > (uint64_t)cap) {
-      fail(status, ERR_INVALID);
-      return 0;
-    }
-    const uint64_t w = ld64(msgs + p + 8) >> 32;
-    if (w < 2 || p + 8 * w > (uint64_t)cap) {
-      fail(status, ERR_INVALID);
-      return 0;
-    }
-    return w;
-  }
-  // The same in stages for all rounds: message, its descriptors, the offset,
-  // the header word (read from the buffer's start when out of range).
+  // All rounds in stages: message, its descriptors, the offset, the header
+  // word (read from the buffer's start when out of range).
   template <int R>
   __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
     const int l = lane_id();
