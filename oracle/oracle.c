@@ -468,7 +468,8 @@ static int64_t packed_var_bytes(const uint64_t *D, int64_t W) {
 /*
  * TAD1 encoding of C against R:
  *   64-byte header {u32 magic "TAD1", u16 version 1, u8 mode (0 plain,
- *   1 learned), u8 packer 1, u32 n_ref, u32 n_match, u32 n_new, u32 0,
+ *   1 learned, 2 mixed: per group, bit 7 of its size byte set = learned),
+ *   u8 packer 1, u32 n_ref, u32 n_match, u32 n_new, u32 0,
  *   u64 ref_words, u64 XOR of all reference uids, u64 W, u64 new_words,
  *   u64 var_bytes};
  *   presence bitmap: ceil(n_ref/64) u64, bit j = reference slot j matched;
@@ -583,12 +584,32 @@ int orc_delta_encode(const uint8_t *cur, int64_t cur_len, const uint8_t *ref, in
   int mode = 0;
   const uint64_t *D = Dp;
   int64_t var_bytes = var_plain;
+  int64_t G = (W + 63) / 64;
+  /* learned calls: per group the smaller of the two residuals (the learned
+   * one only when strictly smaller); the segment is plain when that is no
+   * smaller than the plain residual, learned when no smaller than the learned
+   * one, and mixed (mode 2, a flag per group) otherwise */
+  uint64_t *Dm = NULL;
+  uint8_t *gl = NULL;
   if (mlp) {
-    int64_t var_learned = packed_var_bytes(Dl, W);
-    if (var_learned < var_plain) { mode = 1; D = Dl; var_bytes = var_learned; }
+    int64_t var_learned = packed_var_bytes(Dl, W), var_mixed = 0;
+    Dm = malloc(sizeof(uint64_t) * (size_t)(W + 1));
+    gl = calloc((size_t)G + 1, 1);
+    for (int64_t g = 0; g < G; ++g) {
+      int64_t bp = group_block_bytes(Dp, W, g), bl = group_block_bytes(Dl, W, g);
+      gl[g] = bl < bp;
+      var_mixed += gl[g] ? bl : bp;
+      for (int64_t w = 64 * g; w < W && w < 64 * g + 64; ++w) Dm[w] = gl[g] ? Dl[w] : Dp[w];
+    }
+    if (var_mixed == var_plain) {
+      mode = 0;
+    } else if (var_mixed == var_learned) {
+      mode = 1; D = Dl; var_bytes = var_learned;
+    } else {
+      mode = 2; D = Dm; var_bytes = var_mixed;
+    }
   }
 
-  int64_t G = (W + 63) / 64;
   int64_t sz_pres = 8 * ((R.n + 63) / 64), sz_bits = 8 * G, sz_gs = round8(G), sz_ns = round8(4 * n_new);
   int64_t total = 64 + sz_pres + sz_bits + sz_gs + sz_ns + 8 * new_words + var_bytes;
   int64_t n_out = n_match + n_new;
@@ -622,7 +643,7 @@ int orc_delta_encode(const uint8_t *cur, int64_t cur_len, const uint8_t *ref, in
     int64_t at = 0;
     for (int64_t g = 0; g < G; ++g) {
       int64_t blk = group_block_bytes(D, W, g);
-      gs[g] = (uint8_t)(blk / 8);
+      gs[g] = (uint8_t)(blk / 8 | (mode == 2 && gl[g] ? 0x80 : 0));
       int64_t popc = 0;
       for (int64_t w = 64 * g; w < W && w < 64 * g + 64; ++w) popc += D[w] != 0;
       uint8_t *nib = var + at, *sig = var + at + (popc + 1) / 2;
@@ -681,6 +702,8 @@ int orc_delta_encode(const uint8_t *cur, int64_t cur_len, const uint8_t *ref, in
   free(used);
   free(Dp);
   free(Dl);
+  free(Dm);
+  free(gl);
   return st;
 }
 
@@ -691,10 +714,10 @@ int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, in
                      const orc_hist *hin, orc_hist *hout, uint8_t *out, int64_t cap, int64_t *out_len) {
   msg_t R;
   if (enc_len < 64) return ORC_CORRUPT;
-  if (get32(enc) != TAD1_MAGIC || get16(enc + 4) != 1 || enc[7] != 1 || enc[6] > 1 || get32(enc + 20) != 0)
+  if (get32(enc) != TAD1_MAGIC || get16(enc + 4) != 1 || enc[7] != 1 || enc[6] > 2 || get32(enc + 20) != 0)
     return ORC_CORRUPT;
   int mode = enc[6];
-  if (mode == 1 && (!mlp || !hin)) return ORC_INVALID;
+  if (mode >= 1 && (!mlp || !hin)) return ORC_INVALID;
   if (open_msg(ref, ref_len, &R)) return ORC_INVALID;
   int64_t n_ref = get32(enc + 8), n_match = get32(enc + 12), n_new = get32(enc + 16);
   uint64_t ref_words = get64(enc + 24), fold = get64(enc + 32);
@@ -725,8 +748,11 @@ int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, in
   if (cnt != n_match || wsum != W) return ORC_CORRUPT;
   for (int64_t w = (int64_t)W; w < 8 * sz_bits; ++w)
     if ((bits[w / 8] >> (w % 8)) & 1) return ORC_CORRUPT;
+  /* mode 2: bit 7 of a group's size byte says its residual is against the
+   * prediction; the size is the other 7 bits */
+  const uint8_t size_mask = mode == 2 ? 0x7F : 0xFF;
   uint64_t gsum = 0;
-  for (int64_t g = 0; g < G; ++g) gsum += 8u * gs[g];
+  for (int64_t g = 0; g < G; ++g) gsum += 8u * (gs[g] & size_mask);
   for (int64_t g = G; g < sz_gs; ++g)
     if (gs[g]) return ORC_CORRUPT;
   if (gsum != var_bytes) return ORC_CORRUPT;
@@ -744,7 +770,7 @@ int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, in
   uint64_t *D = calloc((size_t)W + 1, sizeof(uint64_t));
   int64_t at = 0;
   for (int64_t g = 0; g < G; ++g) {
-    int64_t blk = 8 * (int64_t)gs[g];
+    int64_t blk = 8 * (int64_t)(gs[g] & size_mask);
     int64_t popc = 0;
     for (int64_t w = 64 * g; w < (int64_t)W && w < 64 * g + 64; ++w) popc += (bits[w / 8] >> (w % 8)) & 1;
     int64_t need = (popc + 1) / 2;
@@ -775,7 +801,7 @@ int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, in
   *out_len = size;
   if (size > cap) { free(D); return ORC_CAPACITY; }
   int32_t *nbr = NULL;
-  if (mode == 1) {
+  if (mode >= 1) {
     nbr = malloc(sizeof(int32_t) * (size_t)(R.n + 1));
     neighbour_counts(&R, mlp->cell, nbr);
   }
@@ -793,10 +819,14 @@ int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, in
     if (!((pres[j / 8] >> (j % 8)) & 1)) continue;
     const uint8_t *rj = record(&R, j);
     int64_t words = rec_words_of(rj);
-    if (mode == 1) predicted_record(&R, j, mlp, hin, nbr, X);
+    if (mode >= 1) predicted_record(&R, j, mlp, hin, nbr, X);
     else for (int64_t t = 0; t < words; ++t) X[t] = get64(rj + 8 * t);
     put32(offs + 4 * k, (uint32_t)wat);
-    for (int64_t t = 0; t < words; ++t) put64(recs + 8 * (wat + t), D[q + t] ^ X[t]);
+    for (int64_t t = 0; t < words; ++t) {
+      /* mode 2: the prediction only in groups flagged learned */
+      int use_x = mode != 2 || (gs[(q + t) / 64] & 0x80);
+      put64(recs + 8 * (wat + t), D[q + t] ^ (use_x ? X[t] : get64(rj + 8 * t)));
+    }
     /* identity and shape of a matched record are those of the reference */
     if (get64(recs + 8 * wat) != get64(rj) || get64(recs + 8 * wat + 8) != get64(rj + 8)) st = ORC_CORRUPT;
     slot_of[k++] = j;
