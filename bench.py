@@ -231,7 +231,7 @@ def learned_bytes(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, pred):
         pl.step(ds)
         if k >= warmup:
             total += int(pl.enc_off[-1].item())
-            learned_segments += int(pl.modes[: pl.nseg].sum().item())
+            learned_segments += int((pl.modes[: pl.nseg] != 0).sum().item())
     ctx.check("learned pass")
     return total, learned_segments
 

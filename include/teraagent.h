@@ -55,12 +55,13 @@
  *
  *  TAD1 encoding of a current message C against a reference R (Sec. 2.3):
  *    64-byte header: u32 magic "TAD1" | u16 version 1 | u8 mode (0 plain,
- *    1 learned) | u8 packer (1) | u32 n_ref | u32 n_match | u32 n_new |
+ *    1 learned, 2 mixed) | u8 packer (1) | u32 n_ref | u32 n_match | u32 n_new |
  *    u32 0 | u64 ref_words | u64 XOR of all reference uids | u64 W |
  *    u64 new_words | u64 var_bytes;
  *    presence bitmap (ceil(n_ref/64) u64; bit j: reference slot j matched);
  *    word bitmap (ceil(W/64) u64; bit q: residual word q non-zero);
- *    group block sizes (ceil(W/64) u8, bytes/8), padded to 8;
+ *    group block sizes (ceil(W/64) u8, bytes/8; in mode 2 bit 7 set marks a
+ *    group whose residual is against the learned X), padded to 8;
  *    new record sizes (n_new u32 words), padded to 8;
  *    new records verbatim (new_words words);
  *    group blocks (var_bytes): for each group of 64 residual words, one
@@ -71,7 +72,7 @@
  *  the same header word.  The residual is the XOR of the matched current
  *  records, taken in reference order, with X: the reference record (plain)
  *  or the reference record with words 2..5 replaced by the predictor's
- *  estimate (learned).  C' = matched records in reference order followed by
+ *  estimate (learned; in mixed mode per 64-word group, as flagged).  C' = matched records in reference order followed by
  *  the new records in C order; it is returned to the sender and rebuilt by
  *  the receiver, and it is the next reference of both.
  */
@@ -311,14 +312,15 @@ typedef struct {
 /* Delta encoding (Sec. 2.3) of nseg current messages against nseg
  * reference messages (same segment order).  cur/ref: device buffers of
  * cur_len/ref_len bytes holding the messages at cur_off/ref_off (device
- * int64[nseg+1]).  pred == NULL: plain mode.  Otherwise learned mode: each
- * segment is encoded both ways and the smaller encoding is kept (plain on
- * ties); hist_in (slots flattened in segment order, device) must then be
- * given.  hist_out (nullable) receives the history of C'.
+ * int64[nseg+1]).  pred == NULL: plain mode.  Otherwise each 64-word group
+ * of the residual takes the learned X when that makes its block strictly
+ * smaller; a segment where no group does is plain (mode 0), one where every
+ * group with a different size does is learned (mode 1), else mixed (mode 2);
+ * hist_in (slots flattened in segment order, device) must then be given.  hist_out (nullable) receives the history of C'.
  * Outputs: enc (device, enc_cap bytes) with the TAD1 encodings packed densely
  * at enc_off (device int64[nseg+1]); newref (device, newref_cap bytes) with
  * the C' messages at newref_off (device int64[nseg+1]); modes (nullable,
- * device uint8[nseg]) the mode chosen per segment.  Invalid or duplicate
+ * device uint8[nseg]) the mode chosen per segment (0, 1 or 2).  Invalid or duplicate
  * input -> TA_ERR_INVALID; too small outputs -> TA_ERR_CAPACITY. */
 ta_status ta_delta_encode(ta_ctx *ctx, int64_t nseg, const uint8_t *cur, int64_t cur_len, const int64_t *cur_off,
                           const uint8_t *ref, int64_t ref_len, const int64_t *ref_off, const ta_predictor *pred,
@@ -332,9 +334,10 @@ int64_t ta_delta_bound(int64_t nseg, int64_t cur_len, int64_t ref_len);
 
 /* Delta decoding (Sec. 2.3): rebuild C' of every segment from its TAD1
  * encoding (enc at enc_off, device) and the stored reference (ref at
- * ref_off, device).  Learned encodings need pred and hist_in.  Output: C'
- * messages packed densely in out (device, out_cap bytes) at out_off (device
- * int64[nseg+1]); hist_out (nullable) as for encoding.  Damaged encodings ->
+ * ref_off, device).  Learned and mixed encodings (modes 1 and 2) need pred
+ * and hist_in, else TA_ERR_INVALID.  Output: C' messages packed densely in
+ * out (device, out_cap bytes) at out_off (device int64[nseg+1]); hist_out
+ * (nullable) as for encoding.  Damaged encodings (mode above 2 included) ->
  * TA_ERR_CORRUPT; encodings made against another reference ->
  * TA_ERR_REF_MISMATCH; too small output -> TA_ERR_CAPACITY. */
 ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t enc_len, const int64_t *enc_off,

@@ -1025,24 +1025,43 @@ struct GszIn {
   const uint8_t* gsz;
   __device__ uint64_t operator()(int64_t g) const { return 8 * (uint64_t)gsz[g]; }
 };
-struct GChosenIn {  // block bytes of the variant chosen for the group's segment
+// Learned calls choose per segment among plain (mode 0), learned (1) and
+// mixed (2): in a mixed segment each group takes the learned residual when
+// its block is strictly smaller, and bit 7 of its size byte says so.
+__device__ inline bool group_learned(uint32_t mode, uint8_t plain, uint8_t learned) {
+  return mode == 1 || (mode == 2 && learned < plain);
+}
+struct GMinIn {  // block bytes of the smaller variant of each group
+  const uint8_t* gsz;
+  const uint8_t* gsz2;
+  __device__ uint64_t operator()(int64_t g) const {
+    const uint8_t a = gsz[g], b = gsz2[g];
+    return 8 * (uint64_t)(b < a ? b : a);
+  }
+};
+struct GChosenIn {  // block bytes of the variant chosen for the group
   const uint8_t* gsz;
   const uint8_t* gsz2;
   const uint32_t* gseg;
   const Seg* seg;
   __device__ uint64_t operator()(int64_t g) const {
-    return 8 * (uint64_t)(seg[gseg[g]].mode == 1 ? gsz2[g] : gsz[g]);
+    const uint8_t a = gsz[g], b = gsz2[g];
+    return 8 * (uint64_t)(group_learned(seg[gseg[g]].mode, a, b) ? b : a);
   }
 };
 
 // Learned mode: per segment, keep the predictor's encoding only when it is
 // strictly smaller (the fixed sections are the same for both).
-__global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm, const uint64_t* gex, const uint64_t* gex2) {
+// Plain when mixing gains nothing over plain, learned when it gains
+// nothing over learned, else mixed (the mixed total is never larger).
+__global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm, const uint64_t* gex, const uint64_t* gex2,
+                                                       const uint64_t* gex3) {
   if (status_of(cm.status) & ANY_ERR) return;
   for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
     const uint64_t plain = gex[cm.gpre[s + 1]] - gex[cm.gpre[s]];
     const uint64_t learned = gex2[cm.gpre[s + 1]] - gex2[cm.gpre[s]];
-    cm.seg[s].mode = learned < plain ? 1 : 0;
+    const uint64_t mixed = gex3[cm.gpre[s + 1]] - gex3[cm.gpre[s]];
+    cm.seg[s].mode = mixed == plain ? 0 : (mixed == learned ? 1 : 2);
   }
 }
 
@@ -1059,16 +1078,21 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a, const Seg* __re
   const int64_t nw = (int64_t)gridDim.x * WAVES;
   for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
     uint64_t Dv[PG_WAVE], at[PG_WAVE];
+    uint32_t flag[PG_WAVE];
 #pragma unroll
     for (int x = 0; x < PG_WAVE; ++x) {
       const int64_t gg = g0 + x;
       Dv[x] = 0;
       at[x] = 0;
+      flag[x] = 0;
       if (gg < Gt) {
         const int64_t s = (int64_t)uniform32(gseg[gg]);
         const Seg& sg = segs[s];
         const uint64_t q = 64 * ((uint64_t)gg - gpre[s]) + (uint64_t)l;
-        const uint64_t* src = (a.D2 && sg.mode == 1) ? a.D2 : a.D;
+        const uint32_t md = uniform32((uint32_t)sg.mode);
+        const bool lrn = a.D2 && group_learned(md, a.gsz[gg], a.gsz2[gg]);
+        flag[x] = md == 2 && lrn ? 0x80u : 0u;
+        const uint64_t* src = lrn ? a.D2 : a.D;
         if (q < sg.W) Dv[x] = src[sg.dbase + q];
         at[x] = uniform64(sg.fixed_excl + sg.fixed + gex[gg]);
       }
@@ -1079,9 +1103,10 @@ __global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a, const Seg* __re
       if (gg >= Gt) break;
       uint64_t bm;
       const uint32_t size = build_block(Dv[x], s_blk[wv], &bm);
-      if (a.D2 && l == 0) {  // the tables of the chosen variant
+      wave_sync();  // every lane has read this group's sizes before lane 0 rewrites them
+      if (a.D2 && l == 0) {  // the tables of the chosen variant (mixed: bit 7 = learned)
         a.bm[gg] = bm;
-        a.gsz[gg] = (uint8_t)(size / 8);
+        a.gsz[gg] = (uint8_t)(size / 8 | flag[x]);
       }
       if (size) {
         if (at[x] + size > (uint64_t)a.enc_cap) {
@@ -1508,8 +1533,8 @@ __device__ void dec_setup(Common cm, const uint8_t* enc, int64_t enc_len,
         for (int k = 0; k < 8; ++k) h[k] = ld64(e + 8 * k);
         const uint32_t magic = (uint32_t)h[0], ver = (uint32_t)(h[0] >> 32) & 0xFFFF;
         const uint32_t mode = (uint32_t)(h[0] >> 48) & 0xFF, packer = (uint32_t)(h[0] >> 56);
-        if (magic != TAD1_MAGIC || ver != 1 || packer != 1 || mode > 1 || (h[2] >> 32) != 0) code = ERR_CORRUPT;
-        else if (mode == 1 && !have_pred) code = ERR_INVALID;
+        if (magic != TAD1_MAGIC || ver != 1 || packer != 1 || mode > 2 || (h[2] >> 32) != 0) code = ERR_CORRUPT;
+        else if (mode >= 1 && !have_pred) code = ERR_INVALID;
         g.mode = mode;
       }
       if (!code && !tam1_header(ref + ra, rb - ra, &n, &rw)) code = ERR_INVALID;
@@ -1756,6 +1781,7 @@ struct DGroupIn {
   __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
     const int l = lane_id();
     uint64_t at[R];
+    uint8_t mk[R];  // mixed segments: bit 7 of a size byte is the group's flag
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t i = wbase + r * WAVE + l;
@@ -1763,6 +1789,7 @@ struct DGroupIn {
       const int64_t s = lo == hi ? lo : last_le<uint64_t>(cm.gpre, lo, hi + 1, x);
       const Seg& g = cm.seg[s];
       at[r] = g.encm + 64 + 8 * g.PG + 8 * g.G + (x - cm.gpre[s]);
+      mk[r] = g.mode == 2 ? 0x7F : 0xFF;
     }
     __builtin_amdgcn_sched_barrier(0);
     uint8_t b[R];
@@ -1770,7 +1797,7 @@ struct DGroupIn {
     for (int r = 0; r < R; ++r) b[r] = enc[at[r]];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = wbase + r * WAVE + l >= n ? 0 : 8 * (uint64_t)b[r];
+    for (int r = 0; r < R; ++r) v[r] = wbase + r * WAVE + l >= n ? 0 : 8 * (uint64_t)(b[r] & mk[r]);
   }
 };
 
@@ -1932,6 +1959,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
     // wave-uniform per group (scalar registers) ...
     uint64_t bmv[UNPACK_PG];
     uint32_t sizev[UNPACK_PG];
+    bool usep[UNPACK_PG];
     // ... and per lane: record start (relative to the group's first word)
     // and reference word offset of record k0 + lane, block words lane and 64 + lane
     int relv[UNPACK_PG];
@@ -1942,6 +1970,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
       const int64_t gg = g0 + x;
       bmv[x] = 0;
       sizev[x] = 0;
+      usep[x] = false;
       relv[x] = 64;
       rwv[x] = 0;
       b0v[x] = b1v[x] = 0;
@@ -1954,8 +1983,12 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
         bmv[x] = uniform64(ld64(e + 64 + 8 * sg.PG + 8 * lg));
         // the size byte, from its aligned dword (the size table is 8-byte aligned)
         const uint32_t sw = *reinterpret_cast<const uint32_t*>(e + 64 + 8 * sg.PG + 8 * sg.G + (lg & ~3ull));
-        const uint32_t size = uniform32(8u * ((sw >> (8 * (lg & 3))) & 0xFFu));
+        const uint32_t byte = (sw >> (8 * (lg & 3))) & 0xFFu;
+        const uint32_t md = uniform32((uint32_t)sg.mode);
+        // mixed segments: bit 7 says the group's residual is against the prediction
+        const uint32_t size = uniform32(8u * (md == 2 ? byte & 0x7Fu : byte));
         sizev[x] = size;
+        usep[x] = md == 1 || (md == 2 && (byte >> 7));
         // (loads from clamped indices, not behind divergent branches: a group
         // implies a matched record, so M >= 1)
         const bool has = l <= 32 && k0 + l < (uint64_t)M;
@@ -2002,7 +2035,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
       // (a word that is not live reads word 0 of lane 0's record, the one
       // holding the group's first word: in the segment, always valid)
       const uint32_t ri = live ? rw + off : (uint32_t)__builtin_amdgcn_readlane((int)rwv[x], 0);
-      if (uniform32((uint32_t)sg.mode) == 1) {
+      if (usep[x]) {  // uniform
         const uint64_t k = uniform32(gfirst[gg]) + (live ? (uint64_t)idx : 0);
         const bool pred = live && off >= 2 && off < 6 && a.pred_on[k];
         const uint64_t px = a.pred_x[4 * k + (pred ? off - 2 : 0)];
@@ -2390,6 +2423,7 @@ struct Mem {
   uint64_t* D2;
   uint8_t* gsz2;
   uint64_t* gex2;
+  uint64_t* gex3;
   uint64_t* juid;
   uint64_t* jhdr;
   uint32_t* jcnt;
@@ -2443,6 +2477,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.D2 = learned ? ar.take<uint64_t>(b.W) : nullptr;
   m.gsz2 = learned ? ar.take<uint8_t>(b.G) : nullptr;
   m.gex2 = learned ? ar.take<uint64_t>(b.G + 1) : nullptr;
+  m.gex3 = learned ? ar.take<uint64_t>(b.G + 1) : nullptr;
   m.juid = ar.take<uint64_t>(b.C + b.R);
   m.jhdr = ar.take<uint64_t>(b.C + b.R);
   m.jcnt = ar.take<uint32_t>(b.E);
@@ -2608,9 +2643,10 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     k_scan<GszIn><<<gs, SCAN_BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, b.G, m.gex, lookback(c, 3));
     if (pw) {
       k_scan<GszIn><<<gs, SCAN_BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, b.G, m.gex2, lookback(c, 4));
-      k_choose_mode<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, m.gex2);
+      k_scan<GMinIn><<<gs, SCAN_BLOCK, 0, s>>>(GMinIn{m.gsz, m.gsz2}, m.cm.meta + 3, b.G, m.gex3, lookback(c, 5));
+      k_choose_mode<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, m.gex2, m.gex3);
       k_scan<GChosenIn><<<gs, SCAN_BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, b.G, m.gex,
-                                             lookback(c, 5));
+                                             lookback(c, 6));
     }
     k_enc_place<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg, m.gex);
   }

@@ -82,7 +82,7 @@ def test_learned_handmade_exact_prediction(native):
     ctx.close()
 
 
-@pytest.mark.parametrize("persistent,which", [(True, "copy"), (False, "random"), (True, "zero")])
+@pytest.mark.parametrize("persistent,which", [(True, "copy"), (False, "copy"), (False, "random"), (True, "zero")])
 def test_learned_iterations_match_oracle(native, persistent, which):
     """Sender and receiver on the GPU, oracle beside them, over several
     exchanges with the history carried along."""
@@ -106,7 +106,7 @@ def test_learned_iterations_match_oracle(native, persistent, which):
     href, hrx = native.History(0), native.History(0)
     oref, ooff = oracle.empty_messages(nseg)
     ohist = oracle.History(0)
-    learned_segments = 0
+    learned_segments = mixed_segments = 0
     for it in range(6):
         s = world.store
         print(f"[learned {which}] iteration {it}", flush=True)
@@ -128,13 +128,16 @@ def test_learned_iterations_match_oracle(native, persistent, which):
         for hh in (hout, hrxo):
             a1, a2, al = hh.numpy()
             assert np.array_equal(a1, onh.h1) and np.array_equal(a2, onh.h2) and np.array_equal(al, onh.hlen)
-        learned_segments += int(omodes.sum())
+        learned_segments += int(np.count_nonzero(omodes))
+        mixed_segments += int(np.count_nonzero(omodes == 2))
         ref, roff, rx, rxoff = nref[: int(host(noff)[-1])].clone(), noff.clone(), dec[: int(host(doff)[-1])].clone(), doff.clone()
         href, hrx = hout, hrxo
         oref, ooff, ohist = onref, onoff, onh
         world.step()
-    if which == "copy":
+    if which == "copy" and persistent:
         assert learned_segments > 0   # the copy-last-move network wins on persistent motion
+    if which == "copy" and not persistent:
+        assert mixed_segments > 0     # on a random walk it helps some groups and hurts others
     if which == "zero":
         assert learned_segments == 0  # zero weights never beat plain (ties go to plain)
     ctx.close()
