@@ -78,9 +78,9 @@ def _declare(L):
     L.orc_mlp_forward.argtypes = [C.POINTER(MLP), vp, vp]
     L.orc_mlp_forward.restype = None
     L.orc_delta_encode.argtypes = [vp, i64, vp, i64, C.POINTER(MLP), C.POINTER(Hist), C.POINTER(Hist), vp, i64,
-                                   C.POINTER(C.c_int64), vp, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int)]
+                                   C.POINTER(C.c_int64), vp, i64, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.c_int]
     L.orc_delta_decode.argtypes = [vp, i64, vp, i64, C.POINTER(MLP), C.POINTER(Hist), C.POINTER(Hist), vp, i64,
-                                   C.POINTER(C.c_int64)]
+                                   C.POINTER(C.c_int64), C.c_int]
     L.orc_predictor_inputs.argtypes = [vp, i64, C.POINTER(Hist), C.c_double, vp, vp]
 
 
@@ -304,8 +304,9 @@ def _buf(x):
 
 
 def delta_encode(cur: np.ndarray, ref: np.ndarray, mlp: MLP | None = None, hist: History | None = None,
-                 want_hist: bool = False):
-    """Encode one message.  Returns (status, enc, newref, mode, hist_out)."""
+                 want_hist: bool = False, op: int = 0):
+    """Encode one message with difference operator op (0 XOR, 1 byte-wise
+    subtraction mod 256).  Returns (status, enc, newref, mode, hist_out)."""
     L = lib()
     c, cl = _buf(cur)
     r, rl = _buf(ref)
@@ -320,15 +321,16 @@ def delta_encode(cur: np.ndarray, ref: np.ndarray, mlp: MLP | None = None, hist:
     hout = hout_obj.struct() if hout_obj is not None else None
     st = L.orc_delta_encode(_p(c), cl, _p(r), rl, C.byref(mlp) if mlp is not None else None,
                             C.byref(hin) if hin is not None else None, C.byref(hout) if hout is not None else None,
-                            _p(out), cap, C.byref(ol), _p(nref), ncap, C.byref(nl), C.byref(mode))
+                            _p(out), cap, C.byref(ol), _p(nref), ncap, C.byref(nl), C.byref(mode), op)
     if st:
         return st, None, None, None, None
     return st, out[: ol.value].copy(), nref[: nl.value].copy(), mode.value, hout_obj
 
 
 def delta_decode(enc: np.ndarray, ref: np.ndarray, mlp: MLP | None = None, hist: History | None = None,
-                 want_hist: bool = False, cap: int | None = None):
-    """Decode one message.  Returns (status, out, hist_out)."""
+                 want_hist: bool = False, cap: int | None = None, op: int = 0):
+    """Decode one message with the receiver's operator op.  Returns
+    (status, out, hist_out)."""
     L = lib()
     e, el = _buf(enc)
     r, rl = _buf(ref)
@@ -345,7 +347,7 @@ def delta_decode(enc: np.ndarray, ref: np.ndarray, mlp: MLP | None = None, hist:
     hout = hout_obj.struct() if hout_obj is not None else None
     st = L.orc_delta_decode(_p(e), el, _p(r), rl, C.byref(mlp) if mlp is not None else None,
                             C.byref(hin) if hin is not None else None, C.byref(hout) if hout is not None else None,
-                            _p(out), cap, C.byref(ol))
+                            _p(out), cap, C.byref(ol), op)
     if st:
         return st, None, None
     return st, out[: ol.value].copy(), hout_obj
@@ -385,7 +387,7 @@ def empty_messages(nseg: int):
     return join([one.copy() for _ in range(nseg)])
 
 
-def encode_all(cur, cur_off, ref, ref_off, mlp=None, hist=None, want_hist=False):
+def encode_all(cur, cur_off, ref, ref_off, mlp=None, hist=None, want_hist=False, op=0):
     """Encode every segment.  Returns (enc, enc_off, newref, newref_off, modes, hist_out)."""
     cs, rs = split(cur, cur_off), split(ref, ref_off)
     encs, nrefs, modes, hists = [], [], [], []
@@ -394,7 +396,7 @@ def encode_all(cur, cur_off, ref, ref_off, mlp=None, hist=None, want_hist=False)
         _, nr, _ = view(rs[s])
         hs = hist.slice(base, base + nr) if hist is not None else None
         base += nr
-        st, e, n, m, h = delta_encode(cs[s], rs[s], mlp, hs, want_hist)
+        st, e, n, m, h = delta_encode(cs[s], rs[s], mlp, hs, want_hist, op=op)
         if st:
             raise RuntimeError(f"orc_delta_encode segment {s}: status {st}")
         encs.append(e)
@@ -407,7 +409,7 @@ def encode_all(cur, cur_off, ref, ref_off, mlp=None, hist=None, want_hist=False)
     return enc, enc_off, nref, nref_off, np.array(modes, np.uint8), hout
 
 
-def decode_all(enc, enc_off, ref, ref_off, mlp=None, hist=None, want_hist=False):
+def decode_all(enc, enc_off, ref, ref_off, mlp=None, hist=None, want_hist=False, op=0):
     es, rs = split(enc, enc_off), split(ref, ref_off)
     outs, hists = [], []
     base = 0
@@ -415,7 +417,7 @@ def decode_all(enc, enc_off, ref, ref_off, mlp=None, hist=None, want_hist=False)
         _, nr, _ = view(rs[s])
         hs = hist.slice(base, base + nr) if hist is not None else None
         base += nr
-        st, o, h = delta_decode(es[s], rs[s], mlp, hs, want_hist)
+        st, o, h = delta_decode(es[s], rs[s], mlp, hs, want_hist, op=op)
         if st:
             raise RuntimeError(f"orc_delta_decode segment {s}: status {st}")
         outs.append(o)

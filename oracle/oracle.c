@@ -523,10 +523,35 @@ static void write_history(const msg_t *R, int64_t n_out, const int64_t *slot_of,
   }
 }
 
+/* The difference operator of Sec. 2.3, which the paper leaves open.
+ * op 0: XOR of the two 8-byte words.  op 1: each of the eight bytes
+ * subtracted on its own, modulo 256 (no borrow between bytes); inverting it
+ * adds the bytes back modulo 256. */
+static uint64_t diff_word(uint64_t c, uint64_t x, int op) {
+  if (op == 0) return c ^ x;
+  uint64_t d = 0;
+  for (int b = 0; b < 8; ++b) {
+    uint8_t cb = (uint8_t)(c >> (8 * b)), xb = (uint8_t)(x >> (8 * b));
+    d |= (uint64_t)(uint8_t)(cb - xb) << (8 * b);
+  }
+  return d;
+}
+
+static uint64_t undiff_word(uint64_t d, uint64_t x, int op) {
+  if (op == 0) return d ^ x;
+  uint64_t c = 0;
+  for (int b = 0; b < 8; ++b) {
+    uint8_t db = (uint8_t)(d >> (8 * b)), xb = (uint8_t)(x >> (8 * b));
+    c |= (uint64_t)(uint8_t)(db + xb) << (8 * b);
+  }
+  return c;
+}
+
 int orc_delta_encode(const uint8_t *cur, int64_t cur_len, const uint8_t *ref, int64_t ref_len, const orc_mlp *mlp,
                      const orc_hist *hin, orc_hist *hout, uint8_t *out, int64_t cap, int64_t *out_len,
-                     uint8_t *newref, int64_t newref_cap, int64_t *newref_len, int *mode_used) {
+                     uint8_t *newref, int64_t newref_cap, int64_t *newref_len, int *mode_used, int op) {
   msg_t C, R;
+  if (op < 0 || op > 1) return ORC_INVALID;
   if (open_msg(cur, cur_len, &C) || open_msg(ref, ref_len, &R)) return ORC_INVALID;
   if (mlp && !hin) return ORC_INVALID;
   uidpos_t *cu = NULL, *ru = NULL;
@@ -573,8 +598,8 @@ int orc_delta_encode(const uint8_t *cur, int64_t cur_len, const uint8_t *ref, in
     int64_t words = rec_words_of(rj);
     if (mlp) predicted_record(&R, j, mlp, hin, nbr, X);
     for (int64_t k = 0; k < words; ++k) {
-      Dp[q + k] = get64(ci + 8 * k) ^ get64(rj + 8 * k);
-      if (mlp) Dl[q + k] = get64(ci + 8 * k) ^ X[k];
+      Dp[q + k] = diff_word(get64(ci + 8 * k), get64(rj + 8 * k), op);
+      if (mlp) Dl[q + k] = diff_word(get64(ci + 8 * k), X[k], op);
     }
     q += words;
   }
@@ -629,6 +654,7 @@ int orc_delta_encode(const uint8_t *cur, int64_t cur_len, const uint8_t *ref, in
     put32(out + 8, (uint32_t)R.n);
     put32(out + 12, (uint32_t)n_match);
     put32(out + 16, (uint32_t)n_new);
+    put32(out + 20, (uint32_t)op);
     put64(out + 24, (uint64_t)R.rec_words);
     put64(out + 32, fold);
     put64(out + 40, (uint64_t)W);
@@ -711,13 +737,14 @@ int orc_delta_encode(const uint8_t *cur, int64_t cur_len, const uint8_t *ref, in
 /* Delta decoding                                                            */
 /* ======================================================================== */
 int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, int64_t ref_len, const orc_mlp *mlp,
-                     const orc_hist *hin, orc_hist *hout, uint8_t *out, int64_t cap, int64_t *out_len) {
+                     const orc_hist *hin, orc_hist *hout, uint8_t *out, int64_t cap, int64_t *out_len, int op) {
   msg_t R;
   if (enc_len < 64) return ORC_CORRUPT;
-  if (get32(enc) != TAD1_MAGIC || get16(enc + 4) != 1 || enc[7] != 1 || enc[6] > 2 || get32(enc + 20) != 0)
+  if (get32(enc) != TAD1_MAGIC || get16(enc + 4) != 1 || enc[7] != 1 || enc[6] > 2 || get32(enc + 20) > 1)
     return ORC_CORRUPT;
   int mode = enc[6];
-  if (mode >= 1 && (!mlp || !hin)) return ORC_INVALID;
+  /* both ends of a pair agree on the operator, as on the predictor */
+  if ((mode >= 1 && (!mlp || !hin)) || (int)get32(enc + 20) != op) return ORC_INVALID;
   if (open_msg(ref, ref_len, &R)) return ORC_INVALID;
   int64_t n_ref = get32(enc + 8), n_match = get32(enc + 12), n_new = get32(enc + 16);
   uint64_t ref_words = get64(enc + 24), fold = get64(enc + 32);
@@ -825,7 +852,7 @@ int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, in
     for (int64_t t = 0; t < words; ++t) {
       /* mode 2: the prediction only in groups flagged learned */
       int use_x = mode != 2 || (gs[(q + t) / 64] & 0x80);
-      put64(recs + 8 * (wat + t), D[q + t] ^ (use_x ? X[t] : get64(rj + 8 * t)));
+      put64(recs + 8 * (wat + t), undiff_word(D[q + t], use_x ? X[t] : get64(rj + 8 * t), op));
     }
     /* identity and shape of a matched record are those of the reference */
     if (get64(recs + 8 * wat) != get64(rj) || get64(recs + 8 * wat + 8) != get64(rj + 8)) st = ORC_CORRUPT;

@@ -84,16 +84,19 @@ int orc_mlp_parse(const uint8_t *blob, int64_t len, orc_mlp *out);
 void orc_mlp_forward(const orc_mlp *m, const int32_t in[12], int32_t q[4]);
 
 /* Delta encoding of cur against ref (Sec. 2.3).  mlp == NULL: plain mode.
- * hin/hout may be NULL when mlp is NULL.  *mode_used is 0 (plain) or 1. */
+ * hin/hout may be NULL when mlp is NULL.  *mode_used is 0 (plain), 1
+ * (learned) or 2 (mixed).  op: the difference operator, 0 XOR, 1 byte-wise
+ * subtraction modulo 256. */
 int orc_delta_encode(const uint8_t *cur, int64_t cur_len, const uint8_t *ref, int64_t ref_len,
                      const orc_mlp *mlp, const orc_hist *hin, orc_hist *hout, uint8_t *out,
                      int64_t cap, int64_t *out_len, uint8_t *newref, int64_t newref_cap,
-                     int64_t *newref_len, int *mode_used);
+                     int64_t *newref_len, int *mode_used, int op);
 
-/* Decoding against the same reference (Sec. 2.3). */
+/* Decoding against the same reference (Sec. 2.3) with the receiver's
+ * operator op; an encoding made with another operator is ORC_INVALID. */
 int orc_delta_decode(const uint8_t *enc, int64_t enc_len, const uint8_t *ref, int64_t ref_len,
                      const orc_mlp *mlp, const orc_hist *hin, orc_hist *hout, uint8_t *out,
-                     int64_t cap, int64_t *out_len);
+                     int64_t cap, int64_t *out_len, int op);
 
 /* The 12 predictor inputs of every slot of ref (for training data and tests):
  * in[12*j..], and whether slot j is predicted at all (pred[j]). */

@@ -22,11 +22,21 @@ def parse_tam1(buf: bytes):
     return recs
 
 
+def _undiff(r: int, d: int, op: int) -> int:
+    """Invert the difference operator: XOR (op 0), or add each byte of d to
+    the byte of r modulo 256 (op 1)."""
+    if op == 0:
+        return r ^ d
+    rb, db = r.to_bytes(8, "little"), d.to_bytes(8, "little")
+    return int.from_bytes(bytes((x + y) & 0xFF for x, y in zip(rb, db)), "little")
+
+
 def decode_tad1(enc: bytes, ref_records):
     """Decode a plain-mode TAD1 against the reference records -> records of C'."""
-    (magic, ver, mode, packer, n_ref, n_match, n_new, zero, ref_words, fold, W, new_words,
+    (magic, ver, mode, packer, n_ref, n_match, n_new, op, ref_words, fold, W, new_words,
      var_bytes) = struct.unpack_from("<IHBBIIIIQQQQQ", enc, 0)
     assert magic == int.from_bytes(b"TAD1", "little") and ver == 1 and packer == 1 and mode == 0
+    assert op in (0, 1)
     assert n_ref == len(ref_records)
     at = 64
     pres = int.from_bytes(enc[at:at + 8 * ((n_ref + 63) // 64)], "little")
@@ -55,7 +65,7 @@ def decode_tad1(enc: bytes, ref_records):
     out, q = [], 0
     for j, rec in enumerate(ref_records):
         if (pres >> j) & 1:
-            out.append([a ^ b for a, b in zip(rec, D[q:q + len(rec)])])
+            out.append([_undiff(a, b, op) for a, b in zip(rec, D[q:q + len(rec)])])
             q += len(rec)
     p = new_area
     for s in sizes:

@@ -199,7 +199,8 @@ def test_damaged_or_mismatched_encodings_are_rejected():
         bad = enc.copy()
         bad[rng.integers(0, enc.size)] ^= np.uint8(1 << rng.integers(0, 8))
         st, out, _ = oracle.delta_decode(bad, ref)
-        assert st in (0, oracle.CORRUPT, oracle.REF_MISMATCH)
+        # INVALID: the operator field now names subtraction, which this receiver is not set to
+        assert st in (0, oracle.CORRUPT, oracle.REF_MISMATCH, oracle.INVALID)
 
 
 def test_multi_iteration_world_roundtrip_and_compression():
