@@ -20,8 +20,9 @@ per second over the whole step.  Also reported: an eager pass over the same
 steps that times serialize + delta-encode on their own (algorithmic bytes,
 fraction of the 8 TB/s HBM peak) and the dominant kernel's launches (HIP
 events on the library's stream), encoded bytes per record in plain and
-learned mode (predictor trained on the GPU), and the CPU oracle's throughput
-on a bounded sample of the same workload.
+learned mode (predictor trained on the GPU), the eager steps again with
+the byte-wise subtraction operator (`subtraction_eager_ms_per_step`), and
+the CPU oracle's throughput on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -388,6 +389,17 @@ def main():
         del pl, nref, noff
         timings[mode] = el
         log(f"{mode} pass: {1000 * el / args.steps:.3f} ms/step")
+    # the same eager steps with the byte-wise subtraction operator (not a candidate for `value`)
+    ctx.set_difference_op(1)
+    el, pl = eager_timed_pass(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap)
+    _, _, nref, noff, _, _ = pl.outputs()
+    assert torch.equal(noff, final[1]) and torch.equal(nref[: int(final[1][-1])], final[0]), \
+        "subtraction pass differs from the instrumented pass"
+    pl.close()
+    del pl, nref, noff
+    ctx.set_difference_op(0)
+    subtraction_s = el
+    log(f"eager pass, subtraction operator: {1000 * el / args.steps:.3f} ms/step")
     mode = min(timings, key=timings.get)
     best_s = timings[mode]
 
@@ -451,6 +463,7 @@ def main():
         },
         "timed_mode": mode,
         "eager_ms_per_step": 1000.0 * timings["eager"] / K,
+        "subtraction_eager_ms_per_step": 1000.0 * subtraction_s / K,
         "graph_ms_per_step": 1000.0 * timings["graph"] / K,
         "overlap_ms_per_step": 1000.0 * timings["overlap"] / K if "overlap" in timings else None,
         "launch_grids": tuned,

@@ -56,7 +56,8 @@
  *  TAD1 encoding of a current message C against a reference R (Sec. 2.3):
  *    64-byte header: u32 magic "TAD1" | u16 version 1 | u8 mode (0 plain,
  *    1 learned, 2 mixed) | u8 packer (1) | u32 n_ref | u32 n_match | u32 n_new |
- *    u32 0 | u64 ref_words | u64 XOR of all reference uids | u64 W |
+ *    u32 operator (0 XOR, 1 byte-wise subtraction) | u64 ref_words |
+ *    u64 XOR of all reference uids | u64 W |
  *    u64 new_words | u64 var_bytes;
  *    presence bitmap (ceil(n_ref/64) u64; bit j: reference slot j matched);
  *    word bitmap (ceil(W/64) u64; bit q: residual word q non-zero);
@@ -69,9 +70,10 @@
  *    two per byte, low nibble first), then those low-order bytes of each
  *    non-zero word, padded to a multiple of 8 bytes.
  *  A reference slot is matched when C holds a record with the same uid and
- *  the same header word.  The residual is the XOR of the matched current
- *  records, taken in reference order, with X: the reference record (plain)
- *  or the reference record with words 2..5 replaced by the predictor's
+ *  the same header word.  The residual combines the matched current
+ *  records, taken in reference order, with X by XOR (operator 0) or by
+ *  byte-wise subtraction modulo 256 (operator 1).  X is the reference record
+ *  (plain) or the reference record with words 2..5 replaced by the predictor's
  *  estimate (learned; in mixed mode per 64-word group, as flagged).  C' = matched records in reference order followed by
  *  the new records in C order; it is returned to the sender and rebuilt by
  *  the receiver, and it is the next reference of both.
@@ -327,6 +329,16 @@ ta_status ta_delta_encode(ta_ctx *ctx, int64_t nseg, const uint8_t *cur, int64_t
                           const ta_history *hist_in, ta_history *hist_out, uint8_t *enc, int64_t enc_cap,
                           int64_t *enc_off, uint8_t *newref, int64_t newref_cap, int64_t *newref_off,
                           uint8_t *modes, void *stream);
+
+/* The difference operator (Sec. 2.3 leaves it open) of this context's
+ * later ta_delta_encode and ta_delta_decode calls: 0 XOR (the default), 1
+ * each byte subtracted modulo 256 (decoding adds it back).  The zero bytes,
+ * and so every size, are those of XOR.  The operator is written into each
+ * encoding (header bytes 20..23); a decoder set to another operator rejects
+ * it with TA_ERR_INVALID, as both ends of a pair share it like the
+ * predictor.  Other values -> TA_ERR_INVALID.  Not to be changed while calls
+ * of the context are being captured into a graph. */
+ta_status ta_set_difference_op(ta_ctx *ctx, int32_t op);
 
 /* Upper bound of the encoding size for current messages of cur_len bytes
  * and a reference of ref_len bytes, nseg segments. */

@@ -190,6 +190,12 @@ extern "C" int64_t ta_serialize_bound(int64_t nseg, int64_t nrec, int64_t max_wo
   return 32 * nseg + 8 * ((nrec + 1) / 2 + nseg) + 8 * nrec * max_words;
 }
 
+extern "C" ta_status ta_set_difference_op(ta_ctx* c, int32_t op) {
+  if (!c || op < 0 || op > 1) return TA_ERR_INVALID;
+  c->diff_op = (uint32_t)op;
+  return TA_OK;
+}
+
 extern "C" int64_t ta_delta_bound(int64_t nseg, int64_t cur_len, int64_t ref_len) {
   // headers and paddings per segment; presence bitmap (reference records are
   // >= 20 bytes each); word bitmaps and size tables of the residual (its words

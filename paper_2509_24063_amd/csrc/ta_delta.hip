@@ -149,7 +149,26 @@ struct Common {
                    // [6] new records [7] new words [8] unused [9] fixed bytes [10] join tiles
                    // [11] join count entries [12] join buckets [13] join bucket overflow
   uint32_t* status;
+  uint32_t op;     // difference operator of the call: 0 XOR, 1 byte-wise subtraction mod 256
 };
+
+// The difference of Sec. 2.3, which the paper leaves open.  OP 0: XOR.
+// OP 1: each byte subtracted on its own modulo 256, all eight at once: the
+// top bit of every byte of c is set and cleared in x so no borrow leaves a
+// byte, and the top bits are then corrected (c7 ^ x7 ^ borrow).  Its
+// inverse adds the low seven bits of each byte (no carry can leave it) and
+// corrects the top bits the same way.  Zero bytes are those of the XOR.
+constexpr uint64_t BYTE_TOP = 0x8080808080808080ull;
+template <int OP>
+__device__ inline uint64_t diff_word(uint64_t c, uint64_t x) {
+  if constexpr (OP == 0) return c ^ x;
+  else return ((c | BYTE_TOP) - (x & ~BYTE_TOP)) ^ ((c ^ ~x) & BYTE_TOP);
+}
+template <int OP>
+__device__ inline uint64_t undiff_word(uint64_t d, uint64_t x) {
+  if constexpr (OP == 0) return d ^ x;
+  else return ((d & ~BYTE_TOP) + (x & ~BYTE_TOP)) ^ ((d ^ x) & BYTE_TOP);
+}
 
 // Partitioned join: every segment's C and R uids are split into B hash
 // buckets (mean <= JB_TARGET items), and one block joins each bucket in LDS.
@@ -908,6 +927,7 @@ struct ResidArgs {
 
 // Matched records in C' order: their C words go to C' and C xor X to the
 // dense residual (D against R; D2 against the predictions in learned mode).
+template <int OP>
 __global__ __launch_bounds__(BLOCK) void k_enc_resid(ResidArgs a) {
   __shared__ RecTab s_t[WAVES];
   const Common& cm = a.cm;
@@ -937,10 +957,10 @@ __global__ __launch_bounds__(BLOCK) void k_enc_resid(ResidArgs a) {
       const uint64_t c = a.cur[t.c[i] + off];
       const uint64_t x = a.ref[t.r[i] + off];
       a.newref[t.o[i] + off] = c;
-      a.D[d] = c ^ x;
+      a.D[d] = diff_word<OP>(c, x);
       if (a.D2) {
         const uint64_t xl = (t.p[i] && off >= 2 && off < 6) ? a.pred_x[4 * (kb + i) + (off - 2)] : x;
-        a.D2[d] = c ^ xl;
+        a.D2[d] = diff_word<OP>(c, xl);
       }
     }
     wave_sync();
@@ -1157,6 +1177,7 @@ struct GroupArgs {
 
 // (segs, gpre, gseg, gfirst: read-only here; as restrict parameters their
 // uniform reads become scalar loads)
+template <int OP>
 __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg* __restrict__ segs,
                                                          const uint64_t* __restrict__ gpre,
                                                          const uint32_t* __restrict__ gseg,
@@ -1267,7 +1288,7 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
       uint64_t wsum = 0;
 #pragma unroll
       for (int x = 0; x < EG_R; ++x) {
-        D[x] = live[x] ? cv[x] ^ xv[x] : 0;
+        D[x] = live[x] ? diff_word<OP>(cv[x], xv[x]) : 0;
         const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
         const Seg& sg = segs[sx];
         if (live[x]) a.newref[sg.cpw + sg.dbase + 64 * ((uint64_t)gc[x] - gpre[sx]) + (uint64_t)l] = cv[x];
@@ -1366,7 +1387,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
     uint64_t* h = reinterpret_cast<uint64_t*>(enc + off);
     h[0] = (uint64_t)TAD1_MAGIC | (1ull << 32) | ((uint64_t)g.mode << 48) | (1ull << 56);
     h[1] = g.nr | (g.n_match << 32);
-    h[2] = g.n_new;
+    h[2] = g.n_new | ((uint64_t)cm.op << 32);
     h[3] = g.rwr;
     h[4] = g.fold;
     h[5] = g.W;
@@ -1533,8 +1554,9 @@ __device__ void dec_setup(Common cm, const uint8_t* enc, int64_t enc_len,
         for (int k = 0; k < 8; ++k) h[k] = ld64(e + 8 * k);
         const uint32_t magic = (uint32_t)h[0], ver = (uint32_t)(h[0] >> 32) & 0xFFFF;
         const uint32_t mode = (uint32_t)(h[0] >> 48) & 0xFF, packer = (uint32_t)(h[0] >> 56);
-        if (magic != TAD1_MAGIC || ver != 1 || packer != 1 || mode > 2 || (h[2] >> 32) != 0) code = ERR_CORRUPT;
-        else if (mode >= 1 && !have_pred) code = ERR_INVALID;
+        if (magic != TAD1_MAGIC || ver != 1 || packer != 1 || mode > 2 || (h[2] >> 32) > 1) code = ERR_CORRUPT;
+        // both ends of a pair agree on the predictor and on the operator
+        else if ((mode >= 1 && !have_pred) || (h[2] >> 32) != cm.op) code = ERR_INVALID;
         g.mode = mode;
       }
       if (!code && !tam1_header(ref + ra, rb - ra, &n, &rw)) code = ERR_INVALID;
@@ -1936,6 +1958,7 @@ __device__ inline uint32_t funnel32(uint32_t hi, uint32_t lo, uint32_t s) {
 // uid and header words of a matched record must have a zero residual.
 // (segs, gpre, gex, gseg, gfirst: read-only here; as restrict parameters
 // their uniform reads become scalar loads)
+template <int OP>
 __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* __restrict__ segs,
                                                       const uint64_t* __restrict__ gpre,
                                                       const uint64_t* __restrict__ gex,
@@ -2096,7 +2119,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
       if (64 * lg + (uint64_t)l < sg.W) {
         if (offv[x] < 2 && D != 0) bad = true;
         uint64_t* ob = a.out + uniform64(sg.cpw + sg.dbase + 64 * lg);
-        ob[l] = D ^ xwv[x];
+        ob[l] = undiff_word<OP>(D, xwv[x]);
       }
       anybad = anybad || bad || gchk;
     }
@@ -2454,6 +2477,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.cm.fold = ar.take<uint64_t>(FOLD_SLOTS * (nseg + 1));
   m.cm.meta = ar.take<int64_t>(16);
   m.cm.status = nullptr;
+  m.cm.op = 0;
   m.tab = ar.take<Entry>(b.H);
   m.cwords = ar.take<uint32_t>(b.C);
   m.nlist = ar.take<uint32_t>(b.C);
@@ -2570,6 +2594,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   const Bounds b = enc_bounds(nseg, cur_len, ref_len, c->rec_cap);
   Mem m = carve(ar, nseg, b, pred != nullptr);
   m.cm.status = c->d_status;
+  m.cm.op = c->diff_op;
   const int g = c->grid;
   const int gseg = grid_for(c, nseg, BLOCK);
   const bool few = nseg <= FUSE_NSEG;
@@ -2626,14 +2651,20 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     Timed tm(c, "encode_groups", s);
     GroupArgs ga{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.crw,
                  m.mstart, reinterpret_cast<uint64_t*>(newref), enc, enc_cap, m.bm, m.gsz, m.gex};
-    k_enc_groups<<<grid_for(c, b.G, EG_TILE), EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst,
-                                                                 lookback(c, 3));
+    const int gg = grid_for(c, b.G, EG_TILE);
+    if (c->diff_op)
+      k_enc_groups<1><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lookback(c, 3));
+    else
+      k_enc_groups<0><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lookback(c, 3));
   } else {
     {
       Timed tm(c, "encode_resid", s);
       ResidArgs ra{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir,
                    m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(newref), m.D, m.D2};
-      k_enc_resid<<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
+      if (c->diff_op)
+        k_enc_resid<1><<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
+      else
+        k_enc_resid<0><<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
     }
     Timed tm(c, "encode_pack", s);
     PackArgs pa{m.cm, m.D, enc, enc_cap, m.bm, m.gsz, m.gex, m.gseg, m.D2, m.gsz2};
@@ -2681,6 +2712,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   const Bounds b = dec_bounds(nseg, enc_len, ref_len, c->rec_cap);
   Mem m = carve(ar, nseg, b, pred != nullptr);
   m.cm.status = c->d_status;
+  m.cm.op = c->diff_op;
   const int g = c->grid;
   const int gseg = grid_for(c, nseg, BLOCK);
   {
@@ -2724,7 +2756,11 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
     Timed tm(c, "decode_unpack", s);
     UnpackArgs ua{m.cm,  enc,      m.gex,    m.gseg,    m.gfirst, reinterpret_cast<const uint64_t*>(ref),
                   m.mrw, m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(out)};
-    k_dec_unpack<<<grid_for(c, b.G, WAVES * UNPACK_PG), BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst, ua.enc);
+    const int gu = grid_for(c, b.G, WAVES * UNPACK_PG);
+    if (c->diff_op)
+      k_dec_unpack<1><<<gu, BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst, ua.enc);
+    else
+      k_dec_unpack<0><<<gu, BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst, ua.enc);
   }
   k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
   if (hist_out) {

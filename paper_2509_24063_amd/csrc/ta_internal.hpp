@@ -45,6 +45,7 @@ struct ta_ctx {
   int fam_grid[N_FAMILIES] = {2048, 2048, 2048, 2048};
   bool capturing = false;           // a graph capture is in progress: no allocation
   int64_t rec_cap = 0;              // records per message side the delta scratch holds (0: from the sizes)
+  uint32_t diff_op = 0;             // difference operator of encode and decode: 0 XOR, 1 byte-wise subtraction
   uint32_t n_classes = 0;
   uint16_t* d_nf = nullptr;  // device copies of the schema
   uint16_t* d_ni = nullptr;

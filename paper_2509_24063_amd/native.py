@@ -114,9 +114,10 @@ def lib():
         L.ta_graph_free.restype = None
         L.ta_get_grids.argtypes = [vp, vp]
         L.ta_set_grids.argtypes = [vp, vp]
+        L.ta_set_difference_op.argtypes = [vp, C.c_int32]
         L.ta_tune.argtypes = [vp, C.POINTER(IterationT), C.c_char_p, i32, vp, C.POINTER(C.c_int32)]
         for f in ("ta_iteration_run", "ta_graph_capture", "ta_graph_launch", "ta_get_grids", "ta_set_grids",
-                  "ta_tune"):
+                  "ta_tune", "ta_set_difference_op"):
             getattr(L, f).restype = st
         for f in ("ta_create", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_serialize", "ta_view",
                   "ta_view_validate", "ta_predictor_load", "ta_predictor_eval", "ta_delta_encode", "ta_delta_decode",
@@ -455,6 +456,10 @@ class Context:
         g = (C.c_int32 * 4)()
         _check(lib().ta_get_grids(self.h, g), "ta_get_grids")
         return list(g)
+
+    def set_difference_op(self, op: int):
+        """0: XOR residuals (default); 1: byte-wise subtraction mod 256."""
+        _check(lib().ta_set_difference_op(self.h, op), "ta_set_difference_op")
 
     def set_grids(self, grids=None):
         g = (C.c_int32 * 4)(*grids) if grids is not None else None
