@@ -36,14 +36,15 @@ class GpuSide:
 
 
 class OracleSide:
-    def __init__(self, nseg):
+    def __init__(self, nseg, op=0):
         self.ref, self.ref_off = oracle.empty_messages(nseg)
+        self.op = op
 
     def step(self, store, cfg):
         idx, seg = oracle.select_aura(store, cfg.w, cfg.ndirs)
         buf, moff = oracle.serialize(store, cfg.schema, idx, seg)
-        enc, eoff, nref, noff, modes, _ = oracle.encode_all(buf, moff, self.ref, self.ref_off)
-        dec, doff, _ = oracle.decode_all(enc, eoff, self.ref, self.ref_off)
+        enc, eoff, nref, noff, modes, _ = oracle.encode_all(buf, moff, self.ref, self.ref_off, op=self.op)
+        dec, doff, _ = oracle.decode_all(enc, eoff, self.ref, self.ref_off, op=self.op)
         assert np.array_equal(dec, nref)
         out = dict(idx=idx, seg=seg, buf=buf, moff=moff, enc=enc, eoff=eoff, nref=nref, noff=noff)
         self.ref, self.ref_off = nref, noff

@@ -23,11 +23,12 @@ def native():
     return n
 
 
-def _run(native, cfg, iterations, tag, idx_cap=None, max_agents=None):
+def _run(native, cfg, iterations, tag, idx_cap=None, max_agents=None, op=0):
     world = synth.World(cfg, max_agents=max_agents)
     ctx = native.Context(cfg.schema)
+    ctx.set_difference_op(op)
     nseg = world.store.P * cfg.ndirs
-    gs, os_ = GpuSide(ctx, nseg), OracleSide(nseg)
+    gs, os_ = GpuSide(ctx, nseg), OracleSide(nseg, op)
     for it in range(iterations):
         print(f"[{tag}] iteration {it}: {world.store.n} agents, {nseg} segments", flush=True)
         ds = native.DeviceStore(world.store)
@@ -88,10 +89,12 @@ def test_face_and_corner_edge_cases(native):
     _run(native, cfg, 3, "tiny")
 
 
-def test_full_size_config2(native):
-    """1e7 agents, 26 directions: the benchmark's launch configuration, full parity."""
+@pytest.mark.parametrize("op", [0, 1])
+def test_full_size_config2(native, op):
+    """1e7 agents, 26 directions: the benchmark's launch configuration, full
+    parity, with XOR and with the byte-wise subtraction operator."""
     cfg = synth.config(2)
-    _run(native, cfg, 2, "cfg2", idx_cap=int(0.3 * 1e7) + 4096)
+    _run(native, cfg, 2, f"cfg2 op {op}", idx_cap=int(0.3 * 1e7) + 4096, op=op)
 
 
 def _upload(native, msgs):

@@ -42,17 +42,19 @@ def _same(a, b, tag):
         assert np.array_equal(a[k], b[k]), f"{tag}: {k}"
 
 
-def test_iteration_entry_matches_oracle(native):
+@pytest.mark.parametrize("op", [0, 1])
+def test_iteration_entry_matches_oracle(native, op):
     from paper_2509_24063_amd.exchange import Pipeline, capacities
     cfg = synth.config(3, median=300.0)
     world = synth.World(cfg)
     ctx = native.Context(cfg.schema)
+    ctx.set_difference_op(op)
     idx_cap, msgs_cap = capacities(ctx, world.store, cfg.ndirs, cfg.w, slack=1.5)
     ds0 = native.DeviceStore(world.store)
     pl = Pipeline(ctx, ds0, cfg.w, cfg.ndirs, idx_cap, msgs_cap)
-    orc = OracleSide(pl.nseg)
+    orc = OracleSide(pl.nseg, op)
     for it in range(3):
-        print(f"[iteration] cfg3-small {it}", flush=True)
+        print(f"[iteration] cfg3-small op {op} {it}", flush=True)
         ds = native.DeviceStore(world.store)
         pl.step(ds)
         ctx.check(f"iteration {it}")
@@ -66,12 +68,13 @@ def test_iteration_entry_matches_oracle(native):
     ctx.close()
 
 
-@pytest.mark.parametrize("learned", [False, True])
-def test_graph_replays_match_eager(native, learned):
+@pytest.mark.parametrize("learned,op", [(False, 0), (True, 0), (True, 1)])
+def test_graph_replays_match_eager(native, learned, op):
     from paper_2509_24063_amd.exchange import Pipeline, capacities
     cfg = synth.config(3, median=500.0, persistent=learned)
     world = synth.World(cfg)
     ctx = native.Context(cfg.schema)
+    ctx.set_difference_op(op)  # graphs captured under an operator replay it
     pred = native.Predictor(ctx, copy_last_move_blob()) if learned else None
     idx_cap, msgs_cap = capacities(ctx, world.store, cfg.ndirs, cfg.w, slack=1.5)
     cap = int(world.store.n * 1.3)
