@@ -126,8 +126,11 @@ typedef struct {
  * 256, n_f64[c] <= 64, n_i32[c] <= 64).  Uses the current HIP device. */
 ta_status ta_create(ta_ctx **out, uint32_t n_classes, const uint16_t *n_f64, const uint16_t *n_i32);
 
-/* Release the context and its device scratch memory.  Null is accepted. */
-void ta_destroy(ta_ctx *ctx);
+/* Release the context and its device scratch memory (after waiting for the
+ * device).  Null is accepted (TA_OK).  The context is gone afterwards even
+ * when a HIP call failed on the way; that failure is returned as
+ * TA_ERR_HIP. */
+ta_status ta_destroy(ta_ctx *ctx);
 
 /* Pre-size the device scratch memory for calls with at most max_agents
  * agents in the store, max_segments segments, idx_cap <= max_records and
@@ -193,12 +196,21 @@ ta_status ta_serialize(ta_ctx *ctx, const ta_agents *agents, const int32_t *idx,
 int64_t ta_serialize_bound(int64_t nseg, int64_t nrec, int64_t max_words);
 
 /* View of one TAM1 message (Sec. 2.2.1, "Deserialization"/"Mutability"):
- * O(1).  The message may be in host or device memory; for device memory the
- * 32-byte header is copied to the host (a synchronous copy).  Checks the
- * header and the size identity len == 32 + 8*ceil(n/2) + 8*rec_words and
- * fills *out with pointers into the message itself, so records are read and
- * updated in place.  Bad header or size -> TA_ERR_INVALID. */
-ta_status ta_view(uint8_t *msg, int64_t len, ta_view_t *out);
+ * O(1).  Checks the header (magic, version, zero flags and reserved fields,
+ * n <= len/4, rec_words >= 2n) and the size identity
+ * len == 32 + 8*ceil(n/2) + 8*rec_words, and fills *out with pointers into
+ * the message itself, so records are read and updated in place.  The
+ * message may be in host or device memory.  header (nullable, host): the
+ * message's first 32 bytes as the caller already holds them; msg is then
+ * not read, nothing is copied and nothing waits, so the call may sit
+ * between captured or queued work.  header == NULL with a device message:
+ * the 32 header bytes are copied on `stream` and the host waits for that
+ * stream, so work enqueued on it before the call (e.g. the ta_serialize that
+ * wrote the message) is complete first; work on other streams must be
+ * ordered with `stream` by the caller.  The offsets and records are not
+ * checked here (ta_view_validate does that).  Bad header or size ->
+ * TA_ERR_INVALID. */
+ta_status ta_view(uint8_t *msg, int64_t len, const void *header, ta_view_t *out, void *stream);
 
 /* Growth of records used in place (Sec. 2.2.1, "Mutability": a record that
  * needs more room than its message gives it moves to a new block outside its
@@ -230,8 +242,12 @@ ta_status ta_view_grow(ta_ctx *ctx, uint8_t *msgs, int64_t cap, const int64_t *m
 ta_status ta_view_compact(ta_ctx *ctx, const uint8_t *msgs, int64_t cap, const int64_t *msg_off, int64_t nseg,
                           uint8_t *out, int64_t out_cap, int64_t *out_off, void *stream);
 
-/* Full O(n) check of the offsets and record headers of nseg device messages
- * (msgs at msg_off[s] .. msg_off[s+1]); problems -> TA_ERR_INVALID in the
+/* Full O(n) check of nseg device messages (msgs at msg_off[s] ..
+ * msg_off[s+1], 8-byte aligned, inside msgs_len bytes): every check of
+ * ta_view, a zero pad entry after an odd offset table, offsets that are the
+ * running sum of the record sizes from 0 to rec_words, record sizes of at
+ * least 2 words, and a non-zero uid in every record (uids name one agent
+ * each, Sec. 2.5; zero is reserved).  Problems -> TA_ERR_INVALID in the
  * status word. */
 ta_status ta_view_validate(ta_ctx *ctx, const uint8_t *msgs, const int64_t *msg_off, int64_t nseg,
                            int64_t msgs_len, void *stream);

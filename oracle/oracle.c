@@ -221,6 +221,9 @@ int orc_serialize(const orc_agents *a, int n_classes, const uint16_t *n_f64, con
 /* ======================================================================== */
 /* View: full validation of a TAM1 message                                   */
 /* ======================================================================== */
+/* Header and size identity, the offsets as the running sum of record sizes
+ * (at least two words each), and a non-zero uid in every record: uids name
+ * one agent each (Sec. 2.5) and the record format reserves zero. */
 int orc_view(const uint8_t *msg, int64_t len, int64_t *n_out, int64_t *rw_out) {
   if (len < 32) return ORC_INVALID;
   if (get32(msg) != TAM1_MAGIC || get16(msg + 4) != 1 || get16(msg + 6) != 0) return ORC_INVALID;
@@ -239,6 +242,7 @@ int orc_view(const uint8_t *msg, int64_t len, int64_t *n_out, int64_t *rw_out) {
     if (expect + 2 > rw) return ORC_INVALID;
     uint64_t words = get64(recs + 8 * expect + 8) >> 32;
     if (words < 2 || words > rw - expect) return ORC_INVALID;
+    if (get64(recs + 8 * expect) == 0) return ORC_INVALID;
     expect += words;
   }
   if (expect != rw) return ORC_INVALID;

@@ -75,7 +75,8 @@ int orc_serialize(const orc_agents *a, int n_classes, const uint16_t *n_f64, con
                   const int32_t *idx, const int64_t *seg_off, int64_t nseg, uint8_t *out, int64_t cap,
                   int64_t *msg_off);
 
-/* Full validation of one TAM1 message; returns n and rec_words. */
+/* Full validation of one TAM1 message (header, size identity, canonical
+ * offsets, record sizes >= 2 words, non-zero uids); returns n and rec_words. */
 int orc_view(const uint8_t *msg, int64_t len, int64_t *n, int64_t *rec_words);
 
 /* Parse a predictor weight blob. */

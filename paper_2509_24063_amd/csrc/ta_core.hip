@@ -130,21 +130,19 @@ extern "C" ta_status ta_create(ta_ctx** out, uint32_t n_classes, const uint16_t*
   return TA_OK;
 }
 
-extern "C" void ta_destroy(ta_ctx* c) {
-  if (!c) return;
-  (void)hipDeviceSynchronize();
-  (void)hipFree(c->d_nf);
-  (void)hipFree(c->d_ni);
-  (void)hipFree(c->d_status);
-  (void)hipFree(c->d_tickets);
-  (void)hipFree(c->d_lb[0]);
-  (void)hipFree(c->d_lb[1]);
-  (void)hipFree(c->scratch);
+extern "C" ta_status ta_destroy(ta_ctx* c) {
+  if (!c) return TA_OK;
+  // every step is attempted; the first failure is reported
+  bool ok = hipDeviceSynchronize() == hipSuccess;
+  for (void* p : {(void*)c->d_nf, (void*)c->d_ni, (void*)c->d_status, (void*)c->d_tickets, (void*)c->d_lb[0],
+                  (void*)c->d_lb[1], (void*)c->scratch})
+    ok = hipFree(p) == hipSuccess && ok;
   for (auto& e : c->events) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    ok = hipEventDestroy(e.first) == hipSuccess && ok;
+    ok = hipEventDestroy(e.second) == hipSuccess && ok;
   }
   delete c;
+  return ok ? TA_OK : TA_ERR_HIP;
 }
 
 extern "C" ta_status ta_reserve(ta_ctx* c, int64_t max_agents, int64_t max_segments, int64_t max_records,
@@ -206,17 +204,24 @@ extern "C" int64_t ta_delta_bound(int64_t nseg, int64_t cur_len, int64_t ref_len
 }
 
 // ---------------------------------------------------------------------------
-extern "C" ta_status ta_view(uint8_t* msg, int64_t len, ta_view_t* out) {
+extern "C" ta_status ta_view(uint8_t* msg, int64_t len, const void* header, ta_view_t* out, void* stream) {
   if (!msg || !out || len < 32) return TA_ERR_INVALID;
   uint8_t hdr[40] = {0};
-  hipPointerAttribute_t attr;
-  bool on_device = false;
-  if (hipPointerGetAttributes(&attr, msg) == hipSuccess && attr.type == hipMemoryTypeDevice) on_device = true;
-  (void)hipGetLastError();
-  if (on_device) {
-    TA_HIP(hipMemcpy(hdr, msg, 32, hipMemcpyDeviceToHost));
+  if (header) {
+    memcpy(hdr, header, 32);  // the caller's copy: msg itself is not read
   } else {
-    memcpy(hdr, msg, 32);
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, msg) == hipSuccess && attr.type == hipMemoryTypeDevice) on_device = true;
+    (void)hipGetLastError();
+    if (on_device) {
+      // ordered after the work already enqueued on `stream`
+      hipStream_t s = (hipStream_t)stream;
+      TA_HIP(hipMemcpyAsync(hdr, msg, 32, hipMemcpyDeviceToHost, s));
+      TA_HIP(hipStreamSynchronize(s));
+    } else {
+      memcpy(hdr, msg, 32);
+    }
   }
   uint32_t magic, n, pad;
   uint16_t ver, flags;
@@ -229,7 +234,7 @@ extern "C" ta_status ta_view(uint8_t* msg, int64_t len, ta_view_t* out) {
   memcpy(&rw, hdr + 16, 8);
   memcpy(&reserved, hdr + 24, 8);
   if (magic != TAM1_MAGIC || ver != 1 || flags != 0 || pad != 0 || reserved != 0) return TA_ERR_INVALID;
-  if ((uint64_t)n > (uint64_t)len / 4 || rw > (uint64_t)len / 8) return TA_ERR_INVALID;
+  if ((uint64_t)n > (uint64_t)len / 4 || rw > (uint64_t)len / 8 || rw < 2 * (uint64_t)n) return TA_ERR_INVALID;
   if (32 + 8 * (((uint64_t)n + 1) / 2) + 8 * rw != (uint64_t)len) return TA_ERR_INVALID;
   out->n = n;
   out->rec_words = (int64_t)rw;

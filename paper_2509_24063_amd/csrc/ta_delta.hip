@@ -91,6 +91,11 @@ __device__ inline int64_t mdir_seg(const MDir& e) { return (int64_t)(e.gs >> 34)
 [[maybe_unused]] __device__ inline uint64_t mdir_slot(const MDir& e) { return e.gs & ((1ull << 34) - 1); }
 
 
+// 64-bit bit mixer for hash buckets and table slots: D. Stafford's "Mix01"
+// variant of the MurmurHash3 64-bit finalizer ("Better Bit Mixing -
+// Improving on MurmurHash3's 64-bit Finalizer", 2011): xor-shift 31,
+// multiply, xor-shift 27, multiply, xor-shift 33 with his published
+// multipliers.
 __device__ inline uint64_t mix64(uint64_t x) {
   x ^= x >> 31;
   x *= 0x7fb5d329728ea185ull;

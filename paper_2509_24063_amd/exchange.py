@@ -154,7 +154,14 @@ class OverlapPipeline:
     Each hand-off records an event on the producing stream that the consumer
     waits for, and a producer waits for the consumer's event of t - 2 before
     it writes the same copy again.  References ping-pong on each side as in
-    Pipeline (refresh interval 1).  Every stream has the default priority."""
+    Pipeline (refresh interval 1).  Every stream has the default priority.
+
+    The agent store is the caller's: step() orders the serialization after
+    the work already enqueued on the caller's current stream (e.g. a
+    DeviceStore.load() of this state), and returns with that stream ordered
+    after the serialization, so the caller may load the next state into the
+    same buffers right away.  The store's memory is marked as used by the
+    serialization stream, so freeing the store early is safe too."""
 
     def __init__(self, schema, ds: native.DeviceStore, w: float, ndirs: int, idx_cap: int, msgs_cap: int,
                  device="cuda"):
@@ -196,13 +203,18 @@ class OverlapPipeline:
         t = self.t
         m = t % 2  # messages and encoding copy
         p, q = t % 2, 1 - t % 2  # reference copies read and written
+        caller = torch.cuda.current_stream()
         with torch.cuda.stream(self.s_ser):
+            self.s_ser.wait_stream(caller)  # the store as the caller wrote it
             if t >= 2:
                 self.s_ser.wait_event(self.ev_enc[m])
             self.ser.select_aura(ds, self.w, self.ndirs, idx_cap=self.idx_cap, out=(self.idx[m], self.seg_off[m]))
             self.ser.serialize(ds, self.idx[m], self.seg_off[m], idx_cap=self.idx_cap,
                                out=(self.msgs[m], self.msg_off[m]))
             self.ev_ser[m].record(self.s_ser)
+            for x in ds.tensors():
+                x.record_stream(self.s_ser)
+        caller.wait_event(self.ev_ser[m])  # the store is free again after this point
         with torch.cuda.stream(self.s_enc):
             self.s_enc.wait_event(self.ev_ser[m])
             if t >= 2:

@@ -73,7 +73,6 @@ def lib():
         vp, i64, i32, st = C.c_void_p, C.c_int64, C.c_int32, C.c_int
         L.ta_create.argtypes = [C.POINTER(vp), C.c_uint32, vp, vp]
         L.ta_destroy.argtypes = [vp]
-        L.ta_destroy.restype = None
         L.ta_reserve.argtypes = [vp, i64, i64, i64, i64]
         L.ta_status_poll.argtypes = [vp, vp]
         L.ta_select_aura.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, C.c_double, i32, vp, i64, vp, vp]
@@ -85,7 +84,7 @@ def lib():
         L.ta_serialize.argtypes = [vp, C.POINTER(Agents), vp, vp, i64, i64, vp, i64, vp, vp]
         L.ta_serialize_bound.argtypes = [i64, i64, i64]
         L.ta_serialize_bound.restype = i64
-        L.ta_view.argtypes = [vp, i64, C.POINTER(ViewT)]
+        L.ta_view.argtypes = [vp, i64, vp, C.POINTER(ViewT), vp]
         L.ta_view_validate.argtypes = [vp, vp, vp, i64, i64, vp]
         L.ta_predictor_load.argtypes = [vp, vp, C.c_size_t, C.POINTER(vp)]
         L.ta_predictor_free.argtypes = [vp]
@@ -119,7 +118,7 @@ def lib():
         for f in ("ta_iteration_run", "ta_graph_capture", "ta_graph_launch", "ta_get_grids", "ta_set_grids",
                   "ta_tune", "ta_set_difference_op"):
             getattr(L, f).restype = st
-        for f in ("ta_create", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_serialize", "ta_view",
+        for f in ("ta_create", "ta_destroy", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_serialize", "ta_view",
                   "ta_view_validate", "ta_predictor_load", "ta_predictor_eval", "ta_delta_encode", "ta_delta_decode",
                   "ta_time_kernel", "ta_kernel_time", "ta_set_window_tap", "ta_trainer_create", "ta_trainer_grad",
                   "ta_trainer_step", "ta_trainer_params", "ta_trainer_export"):
@@ -199,6 +198,10 @@ class DeviceStore:
 
     def agents(self):
         return self._s
+
+    def tensors(self):
+        """Every device tensor of the store (for stream bookkeeping)."""
+        return (self.uid, self.cls, self.nb, self.f64, self.i32, self.beh_off, self.beh, self.part_off, self.boxes)
 
     @classmethod
     def alloc(cls, F: int, I: int, boxes, cap: int, beh_cap: int, device="cuda"):
@@ -297,8 +300,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().ta_destroy(self.h)
-            self.h = None
+            h, self.h = self.h, None
+            _check(lib().ta_destroy(h), "ta_destroy")
 
     def __del__(self):
         try:
@@ -429,10 +432,13 @@ class Context:
         _check(lib().ta_predictor_eval(self.h, pred.h, _p(inputs), _p(q), n, _stream()), "ta_predictor_eval")
         return q[:n]
 
-    def view(self, buf, start: int, length: int):
+    def view(self, buf, start: int, length: int, header: bytes | None = None):
+        """ta_view of the message at buf[start:start+length]; header: its first
+        32 bytes as the caller holds them (then the device is not read)."""
         v = ViewT()
         ptr = C.c_void_p(buf.data_ptr() + start)
-        _check(lib().ta_view(ptr, length, C.byref(v)), "ta_view")
+        hb = (C.c_uint8 * 32).from_buffer_copy(header[:32]) if header is not None else None
+        _check(lib().ta_view(ptr, length, hb, C.byref(v), _stream()), "ta_view")
         return v
 
     def validate(self, buf, off):

@@ -72,3 +72,72 @@ def decode_tad1(enc: bytes, ref_records):
         out.append(list(struct.unpack_from(f"<{s}Q", enc, p)))
         p += 8 * s
     return out
+
+
+def _diff(c: int, r: int, op: int) -> int:
+    """The difference operator: XOR (op 0), or each byte of c minus the byte
+    of r modulo 256 (op 1)."""
+    if op == 0:
+        return c ^ r
+    cb, rb = c.to_bytes(8, "little"), r.to_bytes(8, "little")
+    return int.from_bytes(bytes((x - y) & 0xFF for x, y in zip(cb, rb)), "little")
+
+
+def _bits_of(values, width):
+    """Little-endian packing of a list of `width`-bit fields into bytes."""
+    acc = 0
+    for k, v in enumerate(values):
+        acc |= v << (width * k)
+    return acc.to_bytes((width * len(values) + 7) // 8, "little")
+
+
+def _pad8(b: bytes) -> bytes:
+    return b + b"\0" * (-len(b) % 8)
+
+
+def encode_tad1(cur_records, ref_records, op: int = 0) -> bytes:
+    """A plain-mode TAD1 encoding of current records against reference records
+    (both lists of word lists), built bit by bit from the format's definition:
+    a reference slot is matched by the current record with the same uid and
+    header word; the residual runs over the matched records in reference
+    order; per 64-word group the packer keeps one 4-bit length per non-zero
+    word (the number of bytes up to and including its highest non-zero byte,
+    found here from the bit length) and those low bytes."""
+    by_key = {}
+    for i, c in enumerate(cur_records):
+        by_key[(c[0], c[1])] = i
+    partner = [by_key.get((r[0], r[1]), -1) for r in ref_records]
+    used = {i for i in partner if i >= 0}
+    new = [i for i in range(len(cur_records)) if i not in used]
+    D = []
+    for j, r in enumerate(ref_records):
+        if partner[j] >= 0:
+            D += [_diff(c, x, op) for c, x in zip(cur_records[partner[j]], r)]
+    W = len(D)
+    G = (W + 63) // 64
+    presence = _bits_of([1 if p >= 0 else 0 for p in partner], 1)
+    presence += b"\0" * (8 * ((len(ref_records) + 63) // 64) - len(presence))
+    word_bits = b""
+    sizes = []
+    blocks = b""
+    for g in range(G):
+        words = D[64 * g: 64 * g + 64]
+        word_bits += _bits_of([1 if w else 0 for w in words] + [0] * (64 - len(words)), 1)
+        nz = [w for w in words if w]
+        lens = [(w.bit_length() + 7) // 8 for w in nz]
+        nibbles = _bits_of(lens, 4)
+        sig = b"".join(w.to_bytes(8, "little")[:n] for w, n in zip(nz, lens))
+        blk = _pad8(nibbles + sig)
+        sizes.append(len(blk) // 8)
+        blocks += blk
+    new_sizes = [len(cur_records[i]) for i in new]
+    new_words = sum(new_sizes)
+    fold = 0
+    for r in ref_records:
+        fold ^= r[0]
+    hdr = struct.pack("<IHBBIIIIQQQQQ", int.from_bytes(b"TAD1", "little"), 1, 0, 1, len(ref_records),
+                      len(ref_records) - partner.count(-1), len(new), op, sum(len(r) for r in ref_records), fold,
+                      W, new_words, len(blocks))
+    body = presence + word_bits + _pad8(bytes(sizes)) + _pad8(struct.pack(f"<{len(new)}I", *new_sizes))
+    body += b"".join(struct.pack(f"<{len(cur_records[i])}Q", *cur_records[i]) for i in new)
+    return hdr + body + blocks

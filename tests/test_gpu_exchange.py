@@ -345,6 +345,8 @@ def test_view_reads_and_mutates_in_place(native):
 
 
 def _mix64(x):
+    """The library's bucket hash: D. Stafford's "Mix01" finalizer (shifts
+    31/27/33 and his two published multipliers)."""
     x = np.asarray(x, np.uint64)
     with np.errstate(over="ignore"):
         x = x ^ (x >> np.uint64(31))

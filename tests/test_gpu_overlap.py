@@ -73,3 +73,34 @@ def test_overlapped_exchange_matches_oracle(native, sync_each):
     pl.check("end")
     _same(pl.outputs(), want[-1], "last")
     pl.close()
+
+
+def test_overlapped_exchange_reusing_one_store(native):
+    """One fixed-capacity store whose buffers receive every state by load()
+    on the caller's stream right before each step, with no host
+    synchronisation in between: each serialization must see its own state
+    complete, and the next load must not overwrite a state still being
+    serialized."""
+    from paper_2509_24063_amd.exchange import OverlapPipeline, capacities
+    cfg = synth.config(3, median=300.0, grid=(2, 2, 2))
+    states = _states(cfg, 6)
+    want = _oracle(states, cfg)
+    ctx = native.Context(cfg.schema)
+    idx_cap, msgs_cap = capacities(ctx, states[0], cfg.ndirs, cfg.w, slack=1.5)
+    ctx.close()
+    cap = max(s.n for s in states)
+    ds = native.DeviceStore(states[0], cap=cap, beh_cap=max(s.beh.size for s in states))
+    pl = OverlapPipeline(cfg.schema, ds, cfg.w, cfg.ndirs, idx_cap, msgs_cap)
+    pl.reserve(cap)
+    outs = []
+    for t, st in enumerate(states):
+        print(f"[overlap one store] iteration {t}", flush=True)
+        ds.load(st)
+        pl.step(ds)
+        if t >= len(states) - 2:
+            pl.check(f"iteration {t}")
+            outs.append(tuple(x.clone() for x in pl.outputs()))
+    pl.check("end")
+    _same(outs[0], want[-2], "second to last")
+    _same(outs[1], want[-1], "last")
+    pl.close()

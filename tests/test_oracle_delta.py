@@ -222,3 +222,45 @@ def test_multi_iteration_world_roundtrip_and_compression():
             assert enc.size < 0.4 * buf.size       # positions move ~0.1 um: most bytes vanish
         ref, ref_off = nref, noff
         w.step()
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_packer_against_bitwise_encoder(op):
+    """The whole plain encoding, byte for byte, against an encoder built bit
+    by bit from the format (tests/specparse.encode_tad1): residual words of
+    every significant-byte length 1..8 (and zero) at random word positions,
+    several 64-word groups with a ragged last one, vanished and new records.
+    A non-minimal length, a swapped nibble order or a misplaced byte in the
+    oracle's packer changes the bytes."""
+    from tests.specparse import _undiff, encode_tad1
+
+    rng = np.random.default_rng(101 + op)
+    seen = set()
+    for trial in range(12):
+        nref = int(rng.integers(1, 48))
+        uids = rng.choice(np.arange(1, 5000), size=nref + 8, replace=False)
+        ref_recs = [rec(int(u), x=float(rng.normal()), words=int(rng.integers(2, 24)),
+                        fill=int(rng.integers(0, 1 << 63))) for u in uids[:nref]]
+        cur_recs = []
+        for r in ref_recs:
+            if rng.random() < 0.15:  # vanished
+                continue
+            c = list(r)
+            for q in range(2, len(c)):
+                L = int(rng.integers(0, 9))
+                if L == 0:
+                    continue
+                d = int(rng.integers(1 << (8 * (L - 1)), 1 << min(63, 8 * L))) if L < 8 else \
+                    int(rng.integers(1 << 56, 1 << 63)) | (int(rng.integers(0, 2)) << 63)
+                assert (d.bit_length() + 7) // 8 == L
+                seen.add(L)
+                c[q] = _undiff(r[q], d, op)
+            cur_recs.append(c)
+        for u in uids[nref:nref + int(rng.integers(0, 8))]:  # new
+            cur_recs.append(rec(int(u), words=int(rng.integers(2, 12)), fill=7))
+        order = rng.permutation(len(cur_recs))
+        cur_recs = [cur_recs[i] for i in order]
+        st, enc, nref_msg, mode, _ = oracle.delta_encode(tam1(cur_recs), tam1(ref_recs), op=op)
+        assert st == 0 and mode == 0
+        assert enc.tobytes() == encode_tad1(cur_recs, ref_recs, op)
+    assert seen == set(range(1, 9))
