@@ -67,3 +67,27 @@ def assert_same(g, o, tag=""):
     doff = host(g["doff"])
     assert np.array_equal(doff, o["noff"]), f"{tag}: C' offsets (receiver)"
     assert np.array_equal(host(g["dec"], doff), o["nref"]), f"{tag}: C' (receiver)"
+
+
+class OracleLearnedSide:
+    """The oracle's sender and receiver in learned mode: the reference (C' of
+    the previous exchange) and its predictor history, the same on both sides;
+    each step checks that the receiver's C' and history equal the sender's."""
+
+    def __init__(self, nseg, mlp, op=0):
+        self.ref, self.ref_off = oracle.empty_messages(nseg)
+        self.hist = oracle.History(0)
+        self.mlp, self.op = mlp, op
+
+    def step(self, store, cfg):
+        idx, seg = oracle.select_aura(store, cfg.w, cfg.ndirs)
+        buf, moff = oracle.serialize(store, cfg.schema, idx, seg)
+        enc, eoff, nref, noff, modes, h = oracle.encode_all(buf, moff, self.ref, self.ref_off, self.mlp, self.hist,
+                                                            op=self.op)
+        dec, doff, hd = oracle.decode_all(enc, eoff, self.ref, self.ref_off, self.mlp, self.hist, op=self.op)
+        assert np.array_equal(dec, nref) and np.array_equal(doff, noff)
+        assert np.array_equal(hd.h1, h.h1) and np.array_equal(hd.h2, h.h2) and np.array_equal(hd.hlen, h.hlen)
+        out = dict(idx=idx, seg=seg, buf=buf, moff=moff, enc=enc, eoff=eoff, nref=nref, noff=noff, modes=modes,
+                   hist=h)
+        self.ref, self.ref_off, self.hist = nref, noff, h
+        return out

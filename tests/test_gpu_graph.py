@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2509_24063_amd import synth
-from tests.exchange_util import OracleSide, host
+from tests.exchange_util import OracleLearnedSide, OracleSide, host
 from tests.test_oracle_predictor import copy_last_move_blob
 
 pytestmark = pytest.mark.gpu
@@ -68,8 +68,27 @@ def test_iteration_entry_matches_oracle(native, op):
     ctx.close()
 
 
+def _same_as_oracle(g, o, tag, pl=None):
+    """Graph or eager pipeline outputs against the oracle's learned exchange:
+    messages, encodings, modes, both sides' C' and the sender's history."""
+    assert np.array_equal(g["moff"], o["moff"]) and np.array_equal(g["msgs"], o["buf"]), f"{tag}: messages"
+    assert np.array_equal(g["eoff"], o["eoff"]) and np.array_equal(g["enc"], o["enc"]), f"{tag}: encodings"
+    assert np.array_equal(g["noff"], o["noff"]) and np.array_equal(g["nref"], o["nref"]), f"{tag}: sender C'"
+    assert np.array_equal(g["rxoff"], o["noff"]) and np.array_equal(g["rx"], o["nref"]), f"{tag}: receiver C'"
+    if pl is not None:
+        assert np.array_equal(host(pl.modes)[: pl.nseg], o["modes"]), f"{tag}: modes"
+        h = o["hist"]
+        for side in (pl.hist, pl.rx_hist):
+            a1, a2, al = side[pl.last].numpy(h.hlen.shape[0])
+            assert np.array_equal(a1, h.h1) and np.array_equal(a2, h.h2) and np.array_equal(al, h.hlen), \
+                f"{tag}: history"
+
+
 @pytest.mark.parametrize("learned,op", [(False, 0), (True, 0), (True, 1)])
 def test_graph_replays_match_eager(native, learned, op):
+    """Graph replays against eager iterations; learned replays (13,312
+    segments: 512 partitions x 26) also against the oracle's learned
+    exchange, with the predictor history carried along on both sides."""
     from paper_2509_24063_amd.exchange import Pipeline, capacities
     cfg = synth.config(3, median=500.0, persistent=learned)
     world = synth.World(cfg)
@@ -83,20 +102,54 @@ def test_graph_replays_match_eager(native, learned, op):
     gpl = Pipeline(ctx, fixed, cfg.w, cfg.ndirs, idx_cap, msgs_cap, pred=pred)
     epl = Pipeline(ctx, native.DeviceStore(world.store), cfg.w, cfg.ndirs, idx_cap, msgs_cap, pred=pred)
     gpl.capture()
+    orc = OracleLearnedSide(gpl.nseg, oracle.mlp_struct(copy_last_move_blob()), op) if learned else None
     learned_segments = 0
     for it in range(6):
-        print(f"[graph] learned={learned} iteration {it}", flush=True)
+        print(f"[graph] learned={learned} op {op} iteration {it} ({gpl.nseg} segments)", flush=True)
         fixed.load(world.store)           # eager work between replays
         gpl.step(graph=True)
         epl.step(native.DeviceStore(world.store))
         ctx.check(f"iteration {it}")
-        _same(_outputs(gpl), _outputs(epl), f"iteration {it}")
+        g = _outputs(gpl)
+        _same(g, _outputs(epl), f"iteration {it}")
         if learned:
-            learned_segments += int(host(gpl.modes)[: gpl.nseg].sum())
+            learned_segments += int(np.count_nonzero(host(gpl.modes)[: gpl.nseg]))
+            _same_as_oracle(g, orc.step(world.store, cfg), f"learned op {op} iteration {it}", gpl)
         world.step()
     if learned:
         assert learned_segments > 0
     gpl.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_heterogeneous_learned_matches_oracle(native, op):
+    """The heterogeneous workload at reduced size (80/20 spheres and
+    cylinders with 14 fp64 fields each, 0-4 behaviours of 1-7 payload words,
+    2 % division, 1 % death; 2x2x2 partitions, 208 segments) in learned mode
+    through the iteration entry: every buffer, the chosen modes and both
+    sides' histories equal the oracle's."""
+    from paper_2509_24063_amd.exchange import Pipeline, capacities
+    cfg = synth.config(5, median=400.0, grid=(2, 2, 2), persistent=True)
+    world = synth.World(cfg)
+    ctx = native.Context(cfg.schema)
+    ctx.set_difference_op(op)
+    blob = copy_last_move_blob()
+    pred = native.Predictor(ctx, blob)
+    idx_cap, msgs_cap = capacities(ctx, world.store, cfg.ndirs, cfg.w, slack=1.5)
+    pl = Pipeline(ctx, native.DeviceStore(world.store), cfg.w, cfg.ndirs, idx_cap, msgs_cap, pred=pred)
+    orc = OracleLearnedSide(pl.nseg, oracle.mlp_struct(blob), op)
+    modes = []
+    for it in range(5):
+        print(f"[cfg5 learned] op {op} iteration {it}", flush=True)
+        pl.step(native.DeviceStore(world.store))
+        ctx.check(f"iteration {it}")
+        o = orc.step(world.store, cfg)
+        _same_as_oracle(_outputs(pl), o, f"cfg5 op {op} iteration {it}", pl)
+        modes.append(o["modes"])
+        world.step()
+    assert np.count_nonzero(np.concatenate(modes)) > 0  # the predictor wins some segments
+    assert len(set(np.unique(world.store.cls))) == 2 and int(world.store.nb.max()) == 4
     ctx.close()
 
 
