@@ -166,6 +166,23 @@ ta_status ta_select_aura(ta_ctx *ctx, const ta_agents *agents, int32_t P, const 
                          const double *boxes, double w, int32_t ndirs, int32_t *idx_out, int64_t idx_cap,
                          int64_t *seg_off_out, void *stream);
 
+/* Aura selection that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Arguments, results and errors are those
+ * of ta_select_aura, whose kernels it runs; its scratch memory (agent
+ * codes, per-tile counts and their prefix, look-back flags) is a static
+ * device array of 22 MiB that the library holds on every device it runs on
+ * until the process ends, instead of the context's scratch, which it never
+ * grows.  Every store of at most 2^24 agents in at most 4096 partitions fits;
+ * a larger one is rejected with TA_ERR_CAPACITY before anything is
+ * enqueued.  All calls on one device share the array and find the previous
+ * call's contents in it (each call clears what it needs): calls that
+ * overlap on one device, on any streams or contexts, race and give
+ * unspecified results.  The status word is the context's. */
+ta_status ta_select_aura_static(ta_ctx *ctx, const ta_agents *agents, int32_t P, const int64_t *part_off,
+                                const double *boxes, double w, int32_t ndirs, int32_t *idx_out, int64_t idx_cap,
+                                int64_t *seg_off_out, void *stream);
+
 /* Migrant selection (Sec. 2.1, "Agent Migration"): the agents that left
  * their partition's box, by the neighbour box they moved into.  Per axis an
  * agent's offset is -1 when its coordinate is < lo, +1 when >= hi, 0

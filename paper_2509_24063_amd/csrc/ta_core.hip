@@ -122,6 +122,7 @@ extern "C" ta_status ta_create(ta_ctx** out, uint32_t n_classes, const uint16_t*
          hipMemset(c->d_status, 0, 64) == hipSuccess && hipMemset(c->d_tickets, 0, 64) == hipSuccess;
   }
   if (ok) ok = ensure_scratch(c, 1 << 20, 1024) == TA_OK;
+  if (ok) ok = static_scratch_init(c->device) == TA_OK;
   if (!ok) {
     ta_destroy(c);
     return TA_ERR_HIP;

@@ -108,6 +108,10 @@ struct Timed {
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline void use_family(ta_ctx* c, int f) { c->grid = c->fam_grid[f]; }
 
+// Looks up, once per device, the device address of the static scratch of
+// ta_select_aura_static (with `device` current).
+ta_status static_scratch_init(int device);
+
 // Zero n int64 values on the stream with a kernel (graph-capture safe).
 ta_status zero_i64(int64_t* p, int64_t n, hipStream_t s);
 inline int grid_for(ta_ctx* c, int64_t items, int per_block) {

@@ -15,6 +15,8 @@
 //                 output position in segment order
 //   k_sel_scatter per tile: stable compaction of store indices into the
 //                 segments, and the segment offsets
+#include <mutex>
+
 #include "ta_internal.hpp"
 #include "ta_scratch.hpp"
 
@@ -347,22 +349,17 @@ size_t select_scratch(int64_t n, int64_t P, int ndirs, int64_t* tiles) {
 }  // namespace ta
 
 namespace {
+// The selection's kernels on scratch carved from `ar`; cf and lb0 clear and
+// use the look-back flags of its one scan.
 template <bool EXACT>
-ta_status select_impl(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off, const double* boxes,
-                      double w, int32_t ndirs, int32_t* idx_out, int64_t idx_cap, int64_t* seg_off_out,
-                      void* stream) {
-  use_family(c, FAM_SELECT);
-  int64_t tiles;
-  ta_status st = ensure_scratch(c, select_scratch(ag->n, P, ndirs, &tiles), tiles);
-  if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
-  Arena ar{c->scratch, c->scratch_cap, 0};
+ta_status select_launch(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off, const double* boxes,
+                        double w, int32_t ndirs, int32_t* idx_out, int64_t idx_cap, int64_t* seg_off_out,
+                        hipStream_t s, Arena ar, const ClearFirst& cf, const LookBack& lb0) {
   SelScratch sc = carve(ar, ag->n, P, ndirs);
   const DirTable dt = make_dirs(ndirs);
   const int64_t cnt_cap = sel_sizes(ag->n, P, ndirs).cnt_cap;
   const int g = grid_for(c, sel_sizes(ag->n, P, ndirs).ntiles, 1);
-  k_sel_prep<<<1, 1024, 0, s>>>(part_off, P, ndirs, ag->n, sc, clear_first(c, ceil_div(cnt_cap + 1, SCAN_TILE)),
-                                c->d_status);
+  k_sel_prep<<<1, 1024, 0, s>>>(part_off, P, ndirs, ag->n, sc, cf, c->d_status);
   {
     Timed tm(c, "select_count", s);
     if (ndirs == 26)
@@ -371,7 +368,7 @@ ta_status select_impl(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* 
       k_sel_count<6, EXACT><<<g, BLOCK, 0, s>>>(ag->f64, ag->f64_stride, part_off, boxes, w, P, dt, sc);
   }
   k_scan<CntIn><<<grid_for(c, cnt_cap + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CntIn{sc.cnt}, sc.meta + 1, cnt_cap, sc.cnt_pre,
-                                                                      lookback(c, 0));
+                                                                      lb0);
   {
     Timed tm(c, "select_scatter", s);
     const int gs = grid_for(c, std::max<int64_t>(sel_sizes(ag->n, P, ndirs).ntiles, ceil_div(P * ndirs + 1, BLOCK)), 1);
@@ -383,7 +380,104 @@ ta_status select_impl(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* 
   TA_LAUNCH_CHECK();
   return TA_OK;
 }
+
+template <bool EXACT>
+ta_status select_impl(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off, const double* boxes,
+                      double w, int32_t ndirs, int32_t* idx_out, int64_t idx_cap, int64_t* seg_off_out,
+                      void* stream) {
+  use_family(c, FAM_SELECT);
+  int64_t tiles;
+  ta_status st = ensure_scratch(c, select_scratch(ag->n, P, ndirs, &tiles), tiles);
+  if (st) return st;
+  const int64_t cnt_cap = sel_sizes(ag->n, P, ndirs).cnt_cap;
+  return select_launch<EXACT>(c, ag, P, part_off, boxes, w, ndirs, idx_out, idx_cap, seg_off_out,
+                              (hipStream_t)stream, Arena{c->scratch, c->scratch_cap, 0},
+                              clear_first(c, ceil_div(cnt_cap + 1, SCAN_TILE)), lookback(c, 0));
+}
+
+// ---- selection without allocation ---------------------------------------------
+// Scratch of ta_select_aura_static, one copy per device for the whole
+// process: the per-agent codes, per-tile counts and their prefix, two
+// look-back flag arrays and their tickets.  Sized for STATIC_AGENTS agents
+// in STATIC_PARTS partitions with 26 directions (about 20.6 MB needed).
+constexpr int64_t STATIC_AGENTS = int64_t(1) << 24;
+constexpr int64_t STATIC_PARTS = 4096;
+constexpr size_t STATIC_BYTES = size_t(22) << 20;
+static __device__ __align__(256) uint8_t scratch[STATIC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[MAX_DEVICES];  // device address of `scratch` on each device (null: not looked up)
+
+// The carve of the static scratch: selection arrays, then the flags and
+// tickets; returns the bytes used.
+struct StaticLayout {
+  uint64_t* flags[2];
+  uint32_t* tickets;
+  int64_t nflags;
+  size_t used;
+};
+StaticLayout static_layout(uint8_t* base, int64_t n, int64_t P, int ndirs) {
+  Arena ar{base, STATIC_BYTES, 0};
+  carve(ar, n, P, ndirs);
+  StaticLayout L;
+  L.nflags = ceil_div(sel_sizes(n, P, ndirs).cnt_cap + 1, SCAN_TILE) + 1;
+  L.flags[0] = ar.take<uint64_t>(L.nflags);
+  L.flags[1] = ar.take<uint64_t>(L.nflags);
+  L.tickets = ar.take<uint32_t>(2);
+  L.used = ar.used;
+  return L;
+}
 }  // namespace
+
+namespace ta {
+// Once per device, with that device current (called by ta_create): the
+// device address of the static scratch.
+ta_status static_scratch_init(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return TA_ERR_HIP;
+  // the documented guarantee: every store of up to STATIC_AGENTS agents in
+  // up to STATIC_PARTS partitions fits
+  if (static_layout(nullptr, STATIC_AGENTS, STATIC_PARTS, 26).used > STATIC_BYTES) return TA_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (g_static_ptr[device]) return TA_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TA_ERR_HIP;
+  g_static_ptr[device] = ptr;
+  return TA_OK;
+}
+}  // namespace ta
+
+extern "C" ta_status ta_select_aura_static(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off,
+                                           const double* boxes, double w, int32_t ndirs, int32_t* idx_out,
+                                           int64_t idx_cap, int64_t* seg_off_out, void* stream) {
+  if (!c || !ag || P < 1 || (ndirs != 6 && ndirs != 26) || !part_off || !boxes || !seg_off_out || idx_cap < 0 ||
+      (idx_cap > 0 && !idx_out) || ag->n < 0 || ag->n > INT32_MAX || (ag->n > 0 && !ag->f64) ||
+      ag->f64_stride < ag->n || !(w == w))
+    return TA_ERR_INVALID;
+  void* base;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    base = c->device >= 0 && c->device < MAX_DEVICES ? g_static_ptr[c->device] : nullptr;
+  }
+  if (!base) return TA_ERR_HIP;
+  // sizes beyond the array: rejected before anything is enqueued
+  if (static_layout(nullptr, ag->n, P, ndirs).used > STATIC_BYTES) return TA_ERR_CAPACITY;
+  use_family(c, FAM_SELECT);
+  const StaticLayout L = static_layout(static_cast<uint8_t*>(base), ag->n, P, ndirs);
+  const int64_t cnt_cap = sel_sizes(ag->n, P, ndirs).cnt_cap;
+  // the first kernel zeroes the flags and ticket the scan uses (the array
+  // keeps the previous call's contents); the scan zeroes the other pair
+  const ClearFirst cf{L.flags[0], L.tickets, ceil_div(cnt_cap + 1, SCAN_TILE) + 1};
+  LookBack lb;
+  lb.flags = L.flags[0];
+  lb.ticket = L.tickets;
+  lb.clear_flags = L.flags[1];
+  lb.clear_ticket = L.tickets + 1;
+  lb.clear_n = L.nflags;
+  lb.status = c->d_status;
+  return select_launch<false>(c, ag, P, part_off, boxes, w, ndirs, idx_out, idx_cap, seg_off_out,
+                              (hipStream_t)stream, Arena{static_cast<uint8_t*>(base), STATIC_BYTES, 0}, cf, lb);
+}
 
 extern "C" ta_status ta_select_aura(ta_ctx* c, const ta_agents* ag, int32_t P, const int64_t* part_off,
                                     const double* boxes, double w, int32_t ndirs, int32_t* idx_out, int64_t idx_cap,

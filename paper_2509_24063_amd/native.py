@@ -76,6 +76,7 @@ def lib():
         L.ta_reserve.argtypes = [vp, i64, i64, i64, i64]
         L.ta_status_poll.argtypes = [vp, vp]
         L.ta_select_aura.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, C.c_double, i32, vp, i64, vp, vp]
+        L.ta_select_aura_static.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, C.c_double, i32, vp, i64, vp, vp]
         L.ta_select_migrants.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, vp, i64, vp, vp]
         L.ta_migrate_apply.argtypes = [vp, C.POINTER(Agents), i32, vp, vp, vp, i64, vp, i64, vp, C.POINTER(StoreT),
                                        vp, vp, vp]
@@ -118,7 +119,8 @@ def lib():
         for f in ("ta_iteration_run", "ta_graph_capture", "ta_graph_launch", "ta_get_grids", "ta_set_grids",
                   "ta_tune", "ta_set_difference_op"):
             getattr(L, f).restype = st
-        for f in ("ta_create", "ta_destroy", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_serialize", "ta_view",
+        for f in ("ta_create", "ta_destroy", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_select_aura_static",
+                  "ta_serialize", "ta_view",
                   "ta_view_validate", "ta_predictor_load", "ta_predictor_eval", "ta_delta_encode", "ta_delta_decode",
                   "ta_time_kernel", "ta_kernel_time", "ta_set_window_tap", "ta_trainer_create", "ta_trainer_grad",
                   "ta_trainer_step", "ta_trainer_params", "ta_trainer_export"):
@@ -327,6 +329,14 @@ class Context:
                                                              device=ds.uid.device)
         _check(lib().ta_select_aura(self.h, C.byref(ds.agents()), ds.P, _p(ds.part_off), _p(ds.boxes), float(w),
                                     ndirs, _p(idx), idx_cap, _p(seg_off), _stream()), "ta_select_aura")
+        return idx, seg_off
+
+    def select_aura_static(self, ds: DeviceStore, w: float, ndirs: int, idx, seg_off):
+        """ta_select_aura_static into caller-given idx (device int32) and
+        seg_off (device int64[P*ndirs+1]): the selection without allocation."""
+        _check(lib().ta_select_aura_static(self.h, C.byref(ds.agents()), ds.P, _p(ds.part_off), _p(ds.boxes),
+                                           float(w), ndirs, _p(idx), idx.numel(), _p(seg_off), _stream()),
+               "ta_select_aura_static")
         return idx, seg_off
 
     def select_migrants(self, ds: DeviceStore, idx_cap: int | None = None, out=None):
