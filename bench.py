@@ -15,14 +15,26 @@ the faster mode (named in `timed_mode`).
 periodic grid, 26 segments each; the same iteration timed as batched calls,
 as graph replays, and (--per-partition) as one set of calls per partition.
 
-Prints one JSON line.  `value` is aura records (agent x direction) exchanged
-per second over the whole step.  Also reported: an eager pass over the same
-steps that times serialize + delta-encode on their own (algorithmic bytes,
-fraction of the 8 TB/s HBM peak) and the dominant kernel's launches (HIP
-events on the library's stream), encoded bytes per record in plain and
-learned mode (predictor trained on the GPU), the eager steps again with
-the byte-wise subtraction operator (`subtraction_eager_ms_per_step`), and
-the CPU oracle's throughput on a bounded sample of the same workload.
+Prints one JSON line.  `value` is aura records (one agent sent to one
+neighbour direction) exchanged per second over the whole step.  Also
+reported:
+- `steps_ms_GBps`: ms per step and algorithmic GB/s of select, serialize,
+  match, xor_pack and decode, from one pass with events at the step
+  boundaries and around the encoder's match kernels only;
+- `serialize_delta`: serialize + delta-encode on their own (algorithmic
+  bytes, fraction of the 8 TB/s HBM peak and of `copy_peak_GBps`, the rate
+  of a plain device copy timed in the same run);
+- `roofline` / `rooflines`: the measured kernel families' launches (HIP
+  events on the library's stream around every launch), their algorithmic
+  bytes and fractions of both peaks;
+- `learned`: the same steps in learned mode (predictor trained on the GPU):
+  ms per step, stage times, serialize + delta GB/s, the learned kernels;
+- encoded bytes per record in plain and learned mode, the eager steps again
+  with the byte-wise subtraction operator, growth and compaction, agent
+  migration;
+- `cpu_baseline`: the CPU oracle on a bounded sample of the same workload,
+  on one host thread and with its one-message calls spread over the host
+  threads, with the CPU model.
 """
 import argparse
 import json
@@ -44,8 +56,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["single", "batched"], default="single")
     ap.add_argument("--agents", type=float, default=None, help="agents (single) or median per partition (batched)")
-    ap.add_argument("--roofline-kernels", default="decode_unpack,encode_groups",
+    ap.add_argument("--roofline-kernels", default="encode_groups,decode_unpack,serialize_pack,select_count,encode_join",
                     help="kernel families timed with HIP events; the one with the largest time is `roofline`")
+    ap.add_argument("--copy-peak-mib", type=float, default=1024.0, help="size of the copies timed for copy_peak_GBps")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
@@ -75,10 +88,13 @@ def generate(world, nstates, native):
     return host_states, dev_states
 
 
-def eager_pass(ctx, native, cfg, dev_states, host_states, warmup, idx_cap, ser_cap, enc_cap, kernel):
-    """Every step through the single calls, with events before select, before
-    serialize, after encode and after decode; the byte accounting of a step
-    is read back after it (outside the events)."""
+def eager_pass(ctx, native, cfg, dev_states, host_states, warmup, idx_cap, ser_cap, enc_cap, kernels, pred=None):
+    """Every step through the single calls, with events at the stage
+    boundaries only (before select, serialize and encode, after encode and
+    after decode) and the library's events around the kernel families named
+    in `kernels` (comma-separated); the byte accounting of a step is read
+    back after it, outside the events.  With `pred`, learned mode on both
+    sides (the predictor history carried along)."""
     import numpy as np
     import torch
     nstates = len(dev_states)
@@ -94,35 +110,43 @@ def eager_pass(ctx, native, cfg, dev_states, host_states, warmup, idx_cap, ser_c
     roffs = [torch.empty(nseg + 1, **i64) for _ in range(2)]
     rx = [torch.empty(ser_cap, **u8) for _ in range(2)]
     rxoffs = [torch.empty(nseg + 1, **i64) for _ in range(2)]
+    hc = idx_cap if pred is not None else 0
+    hist = [native.History(hc) for _ in range(2)]
+    rxhist = [native.History(hc) for _ in range(2)]
     modes = torch.empty(nseg, **u8)
     e0, e1 = native.empty_messages(nseg)
     refs[1][: e0.numel()].copy_(e0)
     roffs[1].copy_(e1)
     rx[1][: e0.numel()].copy_(e0)
     rxoffs[1].copy_(e1)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    acc = dict(records=0, ser=0, enc=0, dec=0, sel=0, W=0, var=0, match=0, groups=0, tad=0, msg=0, sd_ms=0.0,
-               step_ms=0.0)
-    prev_msg = 32 * nseg
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    acc = dict(records=0, ser=0, enc=0, match=0, dec=0, sel=0, W=0, var=0, matched=0, groups=0, tad=0, msg=0,
+               sd_ms=0.0, step_ms=0.0, select_ms=0.0, serialize_ms=0.0, encode_ms=0.0, decode_ms=0.0,
+               learned_segments=0)
+    prev_msg, prev_S = 32 * nseg, 0
     for k in range(nstates):
         if k == warmup:
             ctx.check("eager warmup")
-            ctx.time_kernel(kernel)
+            ctx.time_kernel(kernels)
         ds = dev_states[k]
         cur_ref, nxt = (k + 1) % 2, k % 2
+        lp = dict(pred=pred, hist=hist[cur_ref], hist_out=hist[nxt]) if pred is not None else {}
+        lr = dict(pred=pred, hist=rxhist[cur_ref], hist_out=rxhist[nxt]) if pred is not None else {}
         ev[0].record()
         ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=idx_cap, out=(idx, seg))
         ev[1].record()
         ctx.serialize(ds, idx, seg, idx_cap=idx_cap, out=(buf, moff))
-        ctx.delta_encode(buf, moff, refs[cur_ref], roffs[cur_ref], out=(enc, eoff, refs[nxt], roffs[nxt], modes))
         ev[2].record()
-        ctx.delta_decode(enc, eoff, rx[cur_ref], rxoffs[cur_ref], out=(rx[nxt], rxoffs[nxt]))
+        ctx.delta_encode(buf, moff, refs[cur_ref], roffs[cur_ref], out=(enc, eoff, refs[nxt], roffs[nxt], modes),
+                         **lp)
         ev[3].record()
+        ctx.delta_decode(enc, eoff, rx[cur_ref], rxoffs[cur_ref], out=(rx[nxt], rxoffs[nxt]), **lr)
+        ev[4].record()
         torch.cuda.synchronize()
         mo = moff.cpu().numpy()
         M = int(mo[-1])
+        S = int(seg[-1].item())
         if k >= warmup:
-            S = int(seg[-1].item())
             eo = eoff.cpu().numpy()
             T = int(eo[-1])
             hdr = enc[:T].cpu().numpy()
@@ -130,29 +154,39 @@ def eager_pass(ctx, native, cfg, dev_states, host_states, warmup, idx_cap, ser_c
             acc["records"] += S
             acc["W"] += int(heads[:, 5].sum())
             acc["var"] += int(heads[:, 7].sum())
-            acc["match"] += int((heads[:, 1] >> np.uint64(32)).sum())
+            acc["matched"] += int((heads[:, 1] >> np.uint64(32)).sum())
             acc["groups"] += int(((heads[:, 5] + np.uint64(63)) // np.uint64(64)).sum())
+            acc["learned_segments"] += int(np.count_nonzero(modes[:nseg].cpu().numpy()))
             acc["tad"] += T
             acc["msg"] += M
             R = prev_msg  # the reference is the previous step's C', the size of that step's messages
             acc["sel"] += 24 * host_states[k].n + 4 * S
             # serialize: indices, behaviour offsets, gathered source fields (about the record bytes), records + offsets
             acc["ser"] += 4 * S + 16 * S + M + M
-            # encode: read C and R, write the encoding and C'
+            # match: a 16-byte (uid, item) entry built per reference record and probed per current record
+            acc["match"] += 16 * (S + prev_S)
+            # residual and packing: read C and R, write the encoding and C'
             acc["enc"] += M + R + T + M
             # decode: read the encoding and R, write C'
             acc["dec"] += T + R + M
-            acc["sd_ms"] += ev[1].elapsed_time(ev[2])
-            acc["step_ms"] += ev[0].elapsed_time(ev[3])
-        prev_msg = M
-    launches, kernel_ms = ctx.kernel_time()
+            acc["select_ms"] += ev[0].elapsed_time(ev[1])
+            acc["serialize_ms"] += ev[1].elapsed_time(ev[2])
+            acc["encode_ms"] += ev[2].elapsed_time(ev[3])
+            acc["decode_ms"] += ev[3].elapsed_time(ev[4])
+            acc["sd_ms"] += ev[1].elapsed_time(ev[3])
+            acc["step_ms"] += ev[0].elapsed_time(ev[4])
+        prev_msg, prev_S = M, S
+    fam = {}
+    for name in [x for x in kernels.split(",") if x]:
+        fam[name] = ctx.kernel_time(name)
     ctx.time_kernel(None)
     ctx.check("eager steps")
     last = (nstates - 1) % 2
     n_last = int(roffs[last][-1])
-    assert torch.equal(rx[last][:n_last], refs[last][:n_last]), "receiver C' differs from sender C'"
-    final = (refs[last][:n_last].clone(), roffs[last].clone())
-    return acc, acc["step_ms"] / 1000.0, launches, kernel_ms, final
+    assert torch.equal(rxoffs[last], roffs[last]) and torch.equal(rx[last][:n_last], refs[last][:n_last]), \
+        "receiver C' differs from sender C'"
+    final = dict(nref=refs[last][:n_last].clone(), noff=roffs[last].clone(), eoff=eoff.clone())
+    return acc, fam, final
 
 
 def graph_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, pred=None, hist_cap=None):
@@ -178,12 +212,12 @@ def graph_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, pred=None
     return elapsed, pl
 
 
-def eager_timed_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap):
+def eager_timed_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, pred=None):
     """Every step as one batched iteration call (no host synchronisation
     between steps); wall clock over the timed steps."""
     import torch
     from paper_2509_24063_amd.exchange import Pipeline
-    pl = Pipeline(ctx, dev_states[0], cfg.w, cfg.ndirs, idx_cap, ser_cap)
+    pl = Pipeline(ctx, dev_states[0], cfg.w, cfg.ndirs, idx_cap, ser_cap, pred=pred)
     its = [pl.iteration(k % 2, ds) for k, ds in enumerate(dev_states)]
     for k in range(warmup):
         ctx.run_iteration(its[k])
@@ -222,19 +256,112 @@ def overlap_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap):
     return elapsed, pl
 
 
-def learned_bytes(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap, pred):
-    """TAD1 bytes of the timed steps in learned mode (and the modes chosen)."""
-    import numpy as np
-    from paper_2509_24063_amd.exchange import Pipeline
-    pl = Pipeline(ctx, dev_states[0], cfg.w, cfg.ndirs, idx_cap, ser_cap, pred=pred, decode=False)
-    total, learned_segments = 0, 0
-    for k, ds in enumerate(dev_states):
-        pl.step(ds)
-        if k >= warmup:
-            total += int(pl.enc_off[-1].item())
-            learned_segments += int((pl.modes[: pl.nseg] != 0).sum().item())
-    ctx.check("learned pass")
-    return total, learned_segments
+def copy_peak(mib):
+    """Device-to-device copy rate (read + write bytes per second) of a plain
+    torch copy of `mib` MiB, the best of five."""
+    import torch
+    nb = int(mib * (1 << 20))
+    src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = float("inf")
+    for _ in range(5):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    del src, dst
+    return 2 * nb / (best / 1000.0) / 1e9
+
+
+def stage_times(acc, fam, K):
+    """ms per step and algorithmic GB/s of the five steps of an exchange."""
+    m_launch, m_ms = fam.get("encode_match", (0, 0.0))
+    match_ms = m_ms
+    parts = {
+        "select": (acc["select_ms"], acc["sel"]),
+        "serialize": (acc["serialize_ms"], acc["ser"]),
+        "match": (match_ms, acc["match"]),
+        "xor_pack": (acc["encode_ms"] - match_ms, acc["enc"]),
+        "decode": (acc["decode_ms"], acc["dec"]),
+    }
+    return {k: {"ms_per_step": ms / K, "GBps_algorithmic": b / (ms / 1000.0) / 1e9 if ms > 0 else None,
+                "frac_hbm_peak": b / (ms / 1000.0) / 1e9 / HBM_PEAK_GBPS if ms > 0 else None}
+            for k, (ms, b) in parts.items()}
+
+
+def kernel_bytes(kname, acc):
+    """Algorithmic bytes of one kernel family over the timed steps."""
+    return {
+        # plain mode: read C and R words of matched records and their starts and C/R words, write C' words,
+        # the group blocks, bitmaps, sizes and offsets; read the group-to-segment and first-record maps
+        "encode_groups": 24 * acc["W"] + 24 * acc["matched"] + acc["var"] + 25 * acc["groups"],
+        # learned mode: read C and R words of matched records and their directory entries, write C' words and
+        # the residual
+        "encode_resid": 32 * acc["W"] + 40 * acc["matched"],
+        # read the residual, write the group blocks, bitmaps, sizes, offsets
+        "encode_pack": 8 * acc["W"] + acc["var"] + 17 * acc["groups"],
+        # read the group blocks and their tables, R words and directory entries, write C' words
+        "decode_unpack": 16 * acc["W"] + acc["var"] + 17 * acc["groups"] + 40 * acc["matched"],
+        # gather the agents' fields (about the record bytes), indices, offsets; write records + offsets
+        "serialize_pack": 2 * acc["msg"] + 32 * acc["records"],
+        # read x, y, z of every agent, write one code byte per agent
+        "select_count": acc["sel"] - 4 * acc["records"] + (acc["sel"] - 4 * acc["records"]) // 24,
+        # the join's 16-byte entries, built and probed
+        "encode_join": acc["match"],
+    }.get(kname, float("nan"))
+
+
+def roofline_entry(kname, launches, kernel_ms, total_bytes, copy_gbps, traffic):
+    avg_ms = kernel_ms / max(launches, 1)
+    kb = total_bytes / max(launches, 1)
+    achieved = kb / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
+    return {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS, "frac_copy_peak": achieved / copy_gbps, "traffic": traffic,
+            "launches": launches, "avg_ms": avg_ms, "algorithmic_bytes_per_launch": kb}
+
+
+def same_as_final(pl, final, mode):
+    """A timed mode's last iteration: its encoding offsets, the sender's C'
+    and the receiver's C' equal the stage pass's."""
+    import torch
+    _, eoff, nref, noff, rx, rxoff = pl.outputs()
+    n = int(final["noff"][-1])
+    assert torch.equal(eoff, final["eoff"]), f"{mode} pass: encoding sizes differ from the stage pass"
+    assert torch.equal(noff, final["noff"]) and torch.equal(nref[:n], final["nref"]), \
+        f"{mode} pass: sender C' differs from the stage pass"
+    if rx is not None:
+        assert torch.equal(rxoff, final["noff"]) and torch.equal(rx[:n], final["nref"]), \
+            f"{mode} pass: receiver C' differs from the stage pass"
+
+
+def learned_mode(ctx, native, cfg, dev_states, host_states, args, idx_cap, ser_cap, enc_cap, pred, copy_gbps):
+    """The same steps in learned mode: wall clock of the batched iteration
+    calls, stage times and serialize + delta GB/s (same byte formula as plain
+    mode), the learned kernels' times, and encoded bytes per record."""
+    K = args.steps
+    kern = "encode_match,predict,encode_resid,encode_pack,decode_unpack"
+    acc, fam, final = eager_pass(ctx, native, cfg, dev_states, host_states, args.warmup, idx_cap, ser_cap, enc_cap,
+                                 kern, pred=pred)
+    el, pl = eager_timed_pass(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap, pred=pred)
+    same_as_final(pl, final, "learned")
+    pl.close()
+    del pl
+    sd_bytes = acc["ser"] + acc["match"] + acc["enc"]
+    sd_gbps = sd_bytes / (acc["sd_ms"] / 1000.0) / 1e9
+    return {
+        "ms_per_step": 1000.0 * el / K,
+        "steps_ms_GBps": stage_times(acc, fam, K),
+        "serialize_delta": {"ms_per_step": acc["sd_ms"] / K, "GBps_algorithmic": sd_gbps,
+                            "frac_hbm_peak": sd_gbps / HBM_PEAK_GBPS, "frac_copy_peak": sd_gbps / copy_gbps},
+        "kernels_us_per_step": {k: 1000.0 * ms / K for k, (n, ms) in fam.items()},
+        "rooflines": [roofline_entry(k, n, ms, kernel_bytes(k, acc), copy_gbps, None)
+                      for k, (n, ms) in fam.items() if k in ("encode_resid", "encode_pack", "decode_unpack")],
+        "bytes_per_agent": acc["tad"] / acc["records"],
+        "learned_segments": acc["learned_segments"],
+    }
 
 
 def train_predictor(native, synth, log_fn):
@@ -367,72 +494,55 @@ def main():
         pl.close()
         del pl
 
-    # one instrumented pass per timed kernel family (the byte accounting is the same in every pass)
-    ktimes = {}
-    for kname in [k for k in args.roofline_kernels.split(",") if k]:
-        acc, _, launches, kernel_ms, final = eager_pass(ctx, native, cfg, dev_states, host_states, args.warmup,
-                                                        idx_cap, ser_cap, enc_cap, kname)
-        ktimes[kname] = (launches, kernel_ms)
-        log(f"instrumented pass: {acc['step_ms'] / args.steps:.3f} ms/step (events); {kname}: "
-            f"{kernel_ms / max(launches, 1) * 1000:.1f} us per launch")
+    copy_gbps = copy_peak(args.copy_peak_mib)
+    log(f"device copy peak: {copy_gbps:.0f} GB/s ({args.copy_peak_mib} MiB copies)")
+
+    # stage pass: events at the step boundaries and around the encoder's match part only
+    acc, fam, final = eager_pass(ctx, native, cfg, dev_states, host_states, args.warmup, idx_cap, ser_cap, enc_cap,
+                                 "encode_match")
+    K = args.steps
+    stages = stage_times(acc, fam, K)
+    log("stage pass: " + ", ".join(f"{k} {v['ms_per_step']:.3f} ms" for k, v in stages.items()))
+    # kernel pass: the library's events around every launch of the measured kernel families
+    kernels = [k for k in args.roofline_kernels.split(",") if k]
+    acc_k, ktimes, final_k = eager_pass(ctx, native, cfg, dev_states, host_states, args.warmup, idx_cap, ser_cap,
+                                        enc_cap, ",".join(kernels))
+    assert torch.equal(final_k["noff"], final["noff"]) and torch.equal(final_k["nref"], final["nref"])
+    for kname, (launches, kernel_ms) in ktimes.items():
+        log(f"kernel pass: {kname}: {kernel_ms / max(launches, 1) * 1000:.1f} us per launch")
     timings = {}
     modes = [("eager", eager_timed_pass), ("graph", graph_pass)]
     if not batched:  # three more contexts' scratch would not fit beside the batched states
         modes.append(("overlap", overlap_pass))
     for mode, fn in modes:
         el, pl = fn(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap)
-        # every mode produces the instrumented pass's final C'
-        _, _, nref, noff, _, _ = pl.outputs()
-        assert torch.equal(noff, final[1]) and torch.equal(nref[: int(final[1][-1])], final[0]), \
-            f"{mode} pass differs from the instrumented pass"
+        same_as_final(pl, final, mode)
         pl.close()
-        del pl, nref, noff
+        del pl
         timings[mode] = el
         log(f"{mode} pass: {1000 * el / args.steps:.3f} ms/step")
     # the same eager steps with the byte-wise subtraction operator (not a candidate for `value`)
     ctx.set_difference_op(1)
     el, pl = eager_timed_pass(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap)
-    _, _, nref, noff, _, _ = pl.outputs()
-    assert torch.equal(noff, final[1]) and torch.equal(nref[: int(final[1][-1])], final[0]), \
-        "subtraction pass differs from the instrumented pass"
+    same_as_final(pl, final, "subtraction")
     pl.close()
-    del pl, nref, noff
+    del pl
     ctx.set_difference_op(0)
     subtraction_s = el
     log(f"eager pass, subtraction operator: {1000 * el / args.steps:.3f} ms/step")
     mode = min(timings, key=timings.get)
     best_s = timings[mode]
 
-    K = args.steps
     records = acc["records"]
     value = records / best_s
-    sd_gbps = (acc["ser"] + acc["enc"]) / (acc["sd_ms"] / 1000.0) / 1e9
-    # algorithmic bytes of the measured kernels over the timed steps
-    per_kernel = {
-        # plain mode: read C and R words of matched records and their starts and C/R words, write C' words,
-        # the group blocks, bitmaps, sizes and offsets; read the group-to-segment and first-record maps
-        "encode_groups": 24 * acc["W"] + 24 * acc["match"] + acc["var"] + 25 * acc["groups"],
-        # learned mode: read C and R words of matched records and their directory entries, write C' words and
-        # the residual
-        "encode_resid": 32 * acc["W"] + 40 * acc["match"],
-        # read the residual, write the group blocks, bitmaps, sizes, offsets
-        "encode_pack": 8 * acc["W"] + acc["var"] + 17 * acc["groups"],
-        # read the group blocks and their tables, R words and directory entries, write C' words
-        "decode_unpack": 16 * acc["W"] + acc["var"] + 17 * acc["groups"] + 40 * acc["match"],
-        # gather the agents' fields (about the record bytes), indices, offsets; write records + offsets
-        "serialize_pack": 2 * acc["msg"] + 32 * records,
-    }
+    sd_bytes = acc["ser"] + acc["match"] + acc["enc"]
+    sd_gbps = sd_bytes / (acc["sd_ms"] / 1000.0) / 1e9
     rooflines = []
     for kname, (launches, kernel_ms) in ktimes.items():
-        avg_ms = kernel_ms / max(launches, 1)
-        kb = per_kernel.get(kname, float("nan")) / max(launches, 1)
-        achieved = kb / (avg_ms / 1000.0) / 1e9 if avg_ms > 0 else 0.0
-        rooflines.append({"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                          "traffic": measured_traffic(kname, f"{args.workload}:{n_agents}"),
-                          "launches": launches, "avg_ms": avg_ms, "algorithmic_bytes_per_launch": kb})
+        rooflines.append(roofline_entry(kname, launches, kernel_ms, kernel_bytes(kname, acc_k), copy_gbps,
+                                        measured_traffic(kname, f"{args.workload}:{n_agents}")))
     # the dominant kernel: the largest time per step
-    rooflines.sort(key=lambda r: -r["avg_ms"])
+    rooflines.sort(key=lambda r: -r["avg_ms"] * r["launches"])
     if batched:
         workload = (f"{P} partitions (8x8x8 periodic, lognormal sizes, median {int(cfg.median)}), "
                     f"{n_agents} sphere agents, 26 auras each ({nseg} segments); select + serialize + "
@@ -444,7 +554,7 @@ def main():
     out = {
         "metric": METRIC,
         "value": value,
-        "unit": "agents/s",
+        "unit": "aura records/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
@@ -459,6 +569,8 @@ def main():
             "agents": int(n_agents),
             "partitions": P,
             "records_per_step": records // K,
+            "record": "one agent sent to one neighbour direction (an agent near an edge or corner is sent "
+                      "to several)",
             "segments": nseg,
         },
         "timed_mode": mode,
@@ -467,17 +579,20 @@ def main():
         "graph_ms_per_step": 1000.0 * timings["graph"] / K,
         "overlap_ms_per_step": 1000.0 * timings["overlap"] / K if "overlap" in timings else None,
         "launch_grids": tuned,
+        "copy_peak_GBps": copy_gbps,
+        "steps_ms_GBps": stages,
         "serialize_delta": {
             "ms_per_step": acc["sd_ms"] / K,
             "GBps_algorithmic": sd_gbps,
             "frac_hbm_peak": sd_gbps / HBM_PEAK_GBPS,
+            "frac_copy_peak": sd_gbps / copy_gbps,
         },
         "bytes_per_agent": {
             "raw_record": acc["msg"] / records,
             "plain_delta": acc["tad"] / records,
             "learned_delta": None,
         },
-        "step_algorithmic_GBps": (acc["sel"] + acc["ser"] + acc["enc"] + acc["dec"]) / best_s / 1e9,
+        "step_algorithmic_GBps": (acc["sel"] + acc["ser"] + acc["match"] + acc["enc"] + acc["dec"]) / best_s / 1e9,
         "roofline": rooflines[0] if rooflines else None,
         "rooflines": rooflines,
     }
@@ -490,9 +605,13 @@ def main():
         trained = train_predictor(native, synth, log)
         blob = trained["random_walk"][0]
         pred = native.Predictor(ctx, blob)
-        lb, lsegs = learned_bytes(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap, pred)
-        out["bytes_per_agent"]["learned_delta"] = lb / records
-        out["bytes_per_agent"]["learned_segments"] = lsegs
+        out["learned"] = learned_mode(ctx, native, cfg, dev_states, host_states, args, idx_cap, ser_cap, enc_cap,
+                                      pred, copy_gbps)
+        lm = out["learned"]
+        log(f"learned mode: {lm['ms_per_step']:.3f} ms/step, serialize+delta "
+            f"{lm['serialize_delta']['GBps_algorithmic']:.0f} GB/s, {lm['bytes_per_agent']:.3f} B/record")
+        out["bytes_per_agent"]["learned_delta"] = lm["bytes_per_agent"]
+        out["bytes_per_agent"]["learned_segments"] = lm["learned_segments"]
         out["bytes_per_agent"]["learned_training"] = f"{trained['random_walk'][1]} windows of the 1e5-agent world"
         out["bytes_per_agent"]["persistent_variant"] = persistent_variant(native, synth, trained["persistent"][0])
     if not batched:
@@ -511,7 +630,13 @@ def main():
             f"{out['migration']['migrants_per_step']} migrants, migrate_keep "
             f"{out['migration']['roofline']['achieved']:.0f} GB/s")
     if not args.no_cpu and not batched:
-        out["cpu_baseline"] = cpu_baseline(host_states, cfg, args.cpu_seconds)
+        per_rec = {"select": acc["sel"], "serialize": acc["ser"], "encode": acc["match"] + acc["enc"],
+                   "decode": acc["dec"]}
+        out["cpu_baseline"] = cpu_baseline(host_states, cfg, args.cpu_seconds,
+                                           {k: v / acc["records"] for k, v in per_rec.items()})
+        cb = out["cpu_baseline"]
+        log(f"cpu baseline: {cb['value']:.3g} records/s on {cb['cores']} threads "
+            f"({cb['single_core']['value']:.3g} on one core), {cb['cpu_model']}")
     print(json.dumps(out), flush=True)
 
 
@@ -687,32 +812,129 @@ def migration_pass(native, synth, warmup, steps, agents=1e7):
     }
 
 
-def cpu_baseline(states, cfg, budget_s):
-    """The oracle, as it stands, on the first states of the same workload until
-    the time budget is used: records exchanged per second on one host core."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_exchange(oracle, store, cfg, ref, ref_off, pool, nthreads):
+    """One exchange through the oracle (select, serialize, encode, decode).
+    With a thread pool the oracle's one-message functions run concurrently
+    over the segments (and the selection over agent ranges of the box, whose
+    per-direction lists are concatenated in range order): the oracle's own
+    code, called from several threads (ctypes releases the interpreter lock
+    inside each call).  Returns (times per step, records, C', offsets)."""
+    import ctypes as C
+    import numpy as np
+    L = oracle.lib()
+    t = {}
+    t0 = time.perf_counter()
+    if pool is None or store.P != 1:
+        idx, seg = oracle.select_aura(store, cfg.w, cfg.ndirs)
+    else:
+        f64 = np.ascontiguousarray(store.f64)
+        n, stride = store.n, f64.shape[1]
+        bounds = np.linspace(0, n, nthreads + 1).astype(np.int64)
+        boxes = np.ascontiguousarray(store.boxes, np.float64)
+
+        def sel(c):
+            a, b = int(bounds[c]), int(bounds[c + 1])
+            po = np.array([0, b - a], np.int64)
+            so = np.zeros(cfg.ndirs + 1, np.int64)
+            ix = np.zeros(max(1, 26 * (b - a)), np.int32)
+            st = L.orc_select_aura(1, po.ctypes.data_as(C.c_void_p), C.c_void_p(f64.ctypes.data + 8 * a), stride,
+                                   boxes.ctypes.data_as(C.c_void_p), float(cfg.w), cfg.ndirs,
+                                   ix.ctypes.data_as(C.c_void_p), ix.size, so.ctypes.data_as(C.c_void_p))
+            assert st == 0
+            return [ix[so[d]:so[d + 1]] + a for d in range(cfg.ndirs)]
+        parts = list(pool.map(sel, range(nthreads)))
+        lists = [np.concatenate([parts[c][d] for c in range(nthreads)]) for d in range(cfg.ndirs)]
+        seg = np.zeros(cfg.ndirs + 1, np.int64)
+        np.cumsum([x.size for x in lists], out=seg[1:])
+        idx = np.concatenate(lists).astype(np.int32)
+    t1 = time.perf_counter()
+    nseg = seg.shape[0] - 1
+    if pool is None:
+        buf, moff = oracle.serialize(store, cfg.schema, idx, seg)
+        t2 = time.perf_counter()
+        enc, eoff, nref, noff, _, _ = oracle.encode_all(buf, moff, ref, ref_off)
+        t3 = time.perf_counter()
+        dec, doff, _ = oracle.decode_all(enc, eoff, ref, ref_off)
+    else:
+        def ser(s):
+            a, b = int(seg[s]), int(seg[s + 1])
+            return oracle.serialize(store, cfg.schema, idx[a:b], np.array([0, b - a], np.int64))[0]
+        msgs = list(pool.map(ser, range(nseg)))
+        t2 = time.perf_counter()
+        refs = oracle.split(ref, ref_off)
+
+        def encode(s):
+            st, e, nr, _, _ = oracle.delta_encode(msgs[s], refs[s])
+            assert st == 0
+            return e, nr
+        er = list(pool.map(encode, range(nseg)))
+        t3 = time.perf_counter()
+
+        def decode(s):
+            st, d, _ = oracle.delta_decode(er[s][0], refs[s])
+            assert st == 0
+            return d
+        decs = list(pool.map(decode, range(nseg)))
+        nref, noff = oracle.join([x[1] for x in er])
+        dec, doff = oracle.join(decs)
+    t4 = time.perf_counter()
+    assert np.array_equal(dec, nref)
+    t.update(select=t1 - t0, serialize=t2 - t1, encode=t3 - t2, decode=t4 - t3)
+    return t, int(seg[-1]), nref, noff
+
+
+def cpu_baseline(states, cfg, budget_s, bytes_per_record):
+    """The oracle, as it stands, on the same workload's states: first on one
+    host thread, then with its one-message calls spread over the host's
+    threads (up to 16), each leg until its share of the time budget is used.
+    Records per second over whole exchanges (select, serialize, encode,
+    decode), and per step."""
+    import concurrent.futures as cf
+
     import oracle
 
-    ref, ref_off = oracle.empty_messages(cfg.ndirs)
-    # the first exchange against an empty reference is not representative: do it untimed
-    idx, seg = oracle.select_aura(states[0], cfg.w, cfg.ndirs)
-    buf, moff = oracle.serialize(states[0], cfg.schema, idx, seg)
-    _, _, ref, ref_off, _, _ = oracle.encode_all(buf, moff, ref, ref_off)
-    records, spent, steps = 0, 0.0, 0
-    for s in states[1:]:
-        t = time.perf_counter()
-        idx, seg = oracle.select_aura(s, cfg.w, cfg.ndirs)
-        buf, moff = oracle.serialize(s, cfg.schema, idx, seg)
-        enc, eoff, nref, noff, _, _ = oracle.encode_all(buf, moff, ref, ref_off)
-        oracle.decode_all(enc, eoff, ref, ref_off)
-        spent += time.perf_counter() - t
-        records += int(seg[-1])
-        steps += 1
-        ref, ref_off = nref, noff
-        if spent > budget_s:
-            break
-    return {"value": records / spent, "unit": "agents/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} whole exchanges (select, serialize, encode, decode) of the same "
-                      f"{states[0].n:.0e}-agent workload, {records} records, {spent:.1f} s on one core"}
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    legs = {}
+    for name, nthreads, share in (("single_core", 1, 0.6), ("threads", threads, 0.4)):
+        pool = cf.ThreadPoolExecutor(nthreads) if nthreads > 1 else None
+        ref, ref_off = oracle.empty_messages(states[0].P * cfg.ndirs)
+        # the first exchange against an empty reference is not representative: done untimed
+        _, _, ref, ref_off = cpu_exchange(oracle, states[0], cfg, ref, ref_off, pool, nthreads)
+        tot = dict(select=0.0, serialize=0.0, encode=0.0, decode=0.0)
+        records, steps = 0, 0
+        for st in states[1:]:
+            t, S, ref, ref_off = cpu_exchange(oracle, st, cfg, ref, ref_off, pool, nthreads)
+            for k in tot:
+                tot[k] += t[k]
+            records += S
+            steps += 1
+            if sum(tot.values()) > share * budget_s:
+                break
+        if pool is not None:
+            pool.shutdown()
+        spent = sum(tot.values())
+        legs[name] = {"value": records / spent, "threads": nthreads, "exchanges": steps, "records": records,
+                      "seconds": spent, "ms_per_step": {k: 1000.0 * v / steps for k, v in tot.items()},
+                      "GBps_algorithmic": {k: bytes_per_record[k] * records / v / 1e9 for k, v in tot.items()}}
+    best = legs["threads"] if legs["threads"]["value"] > legs["single_core"]["value"] else legs["single_core"]
+    return {"value": best["value"], "unit": "aura records/s", "cores": best["threads"], "kind": "oracle",
+            "sample": (f"{best['exchanges']} whole exchanges (select, serialize, encode, decode) of the same "
+                       f"{states[0].n:.0e}-agent workload, {best['records']} records, {best['seconds']:.1f} s on "
+                       f"{best['threads']} host thread(s); the oracle's one-message calls spread over the threads "
+                       "by segment (the selection by agent range)"),
+            "cpu_model": cpu_model(), "host_threads_available": len(os.sched_getaffinity(0)),
+            "single_core": legs["single_core"], "threaded": legs["threads"]}
 
 
 if __name__ == "__main__":

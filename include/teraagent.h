@@ -390,18 +390,23 @@ ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t
                           const ta_history *hist_in, ta_history *hist_out, uint8_t *out, int64_t out_cap,
                           int64_t *out_off, void *stream);
 
-/* Timing of one kernel family for measurement: when enabled, every launch
- * of the named kernel is bracketed by HIP events on its stream, and
- * ta_kernel_time returns (after syncing) the number of launches and their
- * summed duration in milliseconds since the last call.  name = NULL
- * disables.  Names: "select_count", "select_scatter", "serialize_pack",
- * "encode_join", "encode_groups" (plain encodings: residual, block sizes,
- * offsets and blocks in one kernel), "predict", "encode_resid" and
- * "encode_pack" (learned encodings), "decode_unpack" (which also applies the
- * residual to the reference), "migrate_keep" (ta_migrate_apply: the agents
- * that stay, copied into the new store). */
+/* Timing of kernel families for measurement: name is a comma-separated list
+ * of family names (NULL or "" disables timing); while it is set, every
+ * launch of a listed family is bracketed by HIP events on its stream.
+ * ta_kernel_time returns (after waiting for the events) the number of timed
+ * launches and their summed duration in milliseconds since the last call,
+ * over every family; ta_kernel_time_of the same for one family (its events
+ * only).  Names: "select_count", "select_scatter", "serialize_pack",
+ * "encode_match" (every encoder kernel before the residual: headers,
+ * UID join, layout, directory), "encode_join" (the UID join alone),
+ * "encode_groups" (plain encodings: residual, block sizes, offsets and
+ * blocks in one kernel), "predict", "encode_resid" and "encode_pack"
+ * (learned encodings), "decode_unpack" (which also applies the residual to
+ * the reference), "migrate_keep" (ta_migrate_apply: the agents that stay,
+ * copied into the new store). */
 ta_status ta_time_kernel(ta_ctx *ctx, const char *name);
 ta_status ta_kernel_time(ta_ctx *ctx, int64_t *launches, double *total_ms);
+ta_status ta_kernel_time_of(ta_ctx *ctx, const char *name, int64_t *launches, double *total_ms);
 
 /* ---- One exchange iteration as a unit: batched over every partition and
  * segment, run eagerly, captured in a HIP graph, or tuned. ---- */

@@ -73,8 +73,20 @@ ta_status zero_i64(int64_t* p, int64_t n, hipStream_t s) {
   return TA_OK;
 }
 
-Timed::Timed(ta_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stream) {
-  on = !c->timed.empty() && c->timed == name;
+// Is `name` one of the comma-separated names of `list`?
+static bool listed(const std::string& list, const char* name) {
+  const size_t n = strlen(name);
+  for (size_t at = 0; at <= list.size();) {
+    size_t end = list.find(',', at);
+    if (end == std::string::npos) end = list.size();
+    if (end - at == n && list.compare(at, n, name) == 0) return true;
+    at = end + 1;
+  }
+  return false;
+}
+
+Timed::Timed(ta_ctx* ctx, const char* nm, hipStream_t stream) : c(ctx), s(stream), name(nm) {
+  on = !c->timed.empty() && listed(c->timed, nm);
   if (on) {
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
@@ -84,7 +96,7 @@ Timed::Timed(ta_ctx* ctx, const char* name, hipStream_t stream) : c(ctx), s(stre
 Timed::~Timed() {
   if (on) {
     (void)hipEventRecord(b, s);
-    c->events.push_back({a, b});
+    c->events.push_back({name, a, b});
   }
 }
 
@@ -139,8 +151,8 @@ extern "C" ta_status ta_destroy(ta_ctx* c) {
                   (void*)c->d_lb[1], (void*)c->scratch})
     ok = hipFree(p) == hipSuccess && ok;
   for (auto& e : c->events) {
-    ok = hipEventDestroy(e.first) == hipSuccess && ok;
-    ok = hipEventDestroy(e.second) == hipSuccess && ok;
+    ok = hipEventDestroy(e.a) == hipSuccess && ok;
+    ok = hipEventDestroy(e.b) == hipSuccess && ok;
   }
   delete c;
   return ok ? TA_OK : TA_ERR_HIP;
@@ -331,28 +343,44 @@ extern "C" ta_status ta_time_kernel(ta_ctx* c, const char* name) {
   if (!c) return TA_ERR_INVALID;
   c->timed = name ? name : "";
   for (auto& e : c->events) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
   }
   c->events.clear();
-  c->timed_launches = 0;
-  c->timed_ms = 0;
+  return TA_OK;
+}
+
+// Launches and summed milliseconds of the recorded events whose family is
+// `name` (every family when name is null); those events are released.
+static ta_status collect(ta_ctx* c, const char* name, int64_t* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return TA_ERR_INVALID;
+  double ms = 0;
+  int64_t k = 0;
+  std::vector<ta_ctx::TimedLaunch> keep;
+  for (auto& e : c->events) {
+    if (name && e.name != name) {
+      keep.push_back(e);
+      continue;
+    }
+    TA_HIP(hipEventSynchronize(e.b));
+    float t = 0;
+    TA_HIP(hipEventElapsedTime(&t, e.a, e.b));
+    ms += t;
+    ++k;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  c->events.swap(keep);
+  *launches = k;
+  *total_ms = ms;
   return TA_OK;
 }
 
 extern "C" ta_status ta_kernel_time(ta_ctx* c, int64_t* launches, double* total_ms) {
-  if (!c || !launches || !total_ms) return TA_ERR_INVALID;
-  double ms = 0;
-  for (auto& e : c->events) {
-    TA_HIP(hipEventSynchronize(e.second));
-    float t = 0;
-    TA_HIP(hipEventElapsedTime(&t, e.first, e.second));
-    ms += t;
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
-  *launches = (int64_t)c->events.size();
-  *total_ms = ms;
-  c->events.clear();
-  return TA_OK;
+  return collect(c, nullptr, launches, total_ms);
+}
+
+extern "C" ta_status ta_kernel_time_of(ta_ctx* c, const char* name, int64_t* launches, double* total_ms) {
+  if (!name) return TA_ERR_INVALID;
+  return collect(c, name, launches, total_ms);
 }

@@ -2604,44 +2604,47 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   const int gseg = grid_for(c, nseg, BLOCK);
   const bool few = nseg <= FUSE_NSEG;
   {
-    const ClearFirst cf = clear_first(c, ceil_div(b.E + 1, SCAN_TILE));
-    const ColScan cs = col_scan(m.cm, {m.cm.cpre, m.cm.rpre, m.cm.hpre, m.cm.tpre, m.cm.jepre, m.cm.bpre},
-                                {0, 1, 2, 10, 11, 12}, {b.C, b.R, b.H, b.T, b.E, b.B});
-    if (few) {
-      k_enc_setup1<<<1, 1024, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off, cf, cs, 6);
-    } else {
-      k_enc_setup<<<gseg, BLOCK, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off, cf);
-      k_scan_cols<<<6, 1024, 0, s>>>(cs);
+    Timed t_match(c, "encode_match", s);  // headers, UID join, layout and directory
+    {
+      const ClearFirst cf = clear_first(c, ceil_div(b.E + 1, SCAN_TILE));
+      const ColScan cs = col_scan(m.cm, {m.cm.cpre, m.cm.rpre, m.cm.hpre, m.cm.tpre, m.cm.jepre, m.cm.bpre},
+                                  {0, 1, 2, 10, 11, 12}, {b.C, b.R, b.H, b.T, b.E, b.B});
+      if (few) {
+        k_enc_setup1<<<1, 1024, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off, cf, cs, 6);
+      } else {
+        k_enc_setup<<<gseg, BLOCK, 0, s>>>(m.cm, cur, cur_len, cur_off, ref, ref_len, ref_off, cf);
+        k_scan_cols<<<6, 1024, 0, s>>>(cs);
+      }
     }
-  }
-  {
-    Timed tm(c, "encode_join", s);
-    JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag, m.tab};
-    k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre);
-    k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
-                                                                     lookback(c, 0));
-    k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre,
-                                                         m.jcnt_pre);
-    k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.bpre, m.cm.cpre, m.cm.jepre, m.jcnt_pre);
-  }
-  k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
-                                                                     lookback(c, 1));
-  k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords, m.nlist}, m.cm.meta + 0, b.C, m.cscan,
-                                                                   lookback(c, 2));
-  {
-    const ColScan cs = col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4}, {b.G, -1, -1, -1});
-    if (few) {
-      k_enc_layout1<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart, cs, 4, newref, newref_cap, newref_off, m.gex);
-    } else {
-      k_enc_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart);
-      k_scan_cols<<<4, 1024, 0, s>>>(cs);
-      k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
+    {
+      Timed tm(c, "encode_join", s);
+      JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag, m.tab};
+      k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre);
+      k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
+                                                                       lookback(c, 0));
+      k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre,
+                                                           m.jcnt_pre);
+      k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.bpre, m.cm.cpre, m.cm.jepre, m.jcnt_pre);
     }
+    k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
+                                                                       lookback(c, 1));
+    k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords, m.nlist}, m.cm.meta + 0, b.C, m.cscan,
+                                                                     lookback(c, 2));
+    {
+      const ColScan cs = col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4}, {b.G, -1, -1, -1});
+      if (few) {
+        k_enc_layout1<<<1, 1024, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart, cs, 4, newref, newref_cap, newref_off, m.gex);
+      } else {
+        k_enc_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.mstart);
+        k_scan_cols<<<4, 1024, 0, s>>>(cs);
+        k_enc_seg3<<<gseg, BLOCK, 0, s>>>(m.cm, newref, newref_cap, newref_off, m.gex);
+      }
+    }
+    k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords,
+                                                                pred || hist_out ? m.mdir : nullptr, pred ? nullptr : m.crw,
+                                                                m.mstart, newref, m.gseg,
+                                   m.gfirst);
   }
-  k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords,
-                                                              pred || hist_out ? m.mdir : nullptr, pred ? nullptr : m.crw,
-                                                              m.mstart, newref, m.gseg,
-                                 m.gfirst);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
     Timed tm(c, "predict", s);

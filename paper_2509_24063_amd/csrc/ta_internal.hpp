@@ -61,11 +61,14 @@ struct ta_ctx {
   float* tap_tgt = nullptr;
   int64_t tap_cap = 0;
   unsigned long long* tap_count = nullptr;
-  // timing of one kernel family
+  // timing of kernel families: `timed` is a comma-separated list of names;
+  // every launch of a listed family leaves (family, start, end) events
   std::string timed;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-  int64_t timed_launches = 0;
-  double timed_ms = 0;
+  struct TimedLaunch {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<TimedLaunch> events;
 };
 
 namespace ta {
@@ -100,6 +103,7 @@ struct Timed {
   ta_ctx* c;
   hipStream_t s;
   bool on;
+  const char* name;
   hipEvent_t a{}, b{};
   Timed(ta_ctx* ctx, const char* name, hipStream_t stream);
   ~Timed();

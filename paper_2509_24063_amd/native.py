@@ -99,6 +99,7 @@ def lib():
         L.ta_predictor_eval.argtypes = [vp, vp, vp, vp, i64, vp]
         L.ta_time_kernel.argtypes = [vp, C.c_char_p]
         L.ta_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.ta_kernel_time_of.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.ta_set_window_tap.argtypes = [vp, vp, vp, i64, vp]
         L.ta_trainer_create.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_double, C.POINTER(vp)]
         L.ta_trainer_free.argtypes = [vp]
@@ -122,7 +123,7 @@ def lib():
         for f in ("ta_create", "ta_destroy", "ta_reserve", "ta_status_poll", "ta_select_aura", "ta_select_aura_static",
                   "ta_serialize", "ta_view",
                   "ta_view_validate", "ta_predictor_load", "ta_predictor_eval", "ta_delta_encode", "ta_delta_decode",
-                  "ta_time_kernel", "ta_kernel_time", "ta_set_window_tap", "ta_trainer_create", "ta_trainer_grad",
+                  "ta_time_kernel", "ta_kernel_time", "ta_kernel_time_of", "ta_set_window_tap", "ta_trainer_create", "ta_trainer_grad",
                   "ta_trainer_step", "ta_trainer_params", "ta_trainer_export"):
             getattr(L, f).restype = st
         _lib = L
@@ -458,9 +459,14 @@ class Context:
     def time_kernel(self, name: str | None):
         _check(lib().ta_time_kernel(self.h, name.encode() if name else None), "ta_time_kernel")
 
-    def kernel_time(self):
+    def kernel_time(self, name: str | None = None):
+        """(launches, total ms) of the timed launches of family `name`, or of
+        every timed family."""
         n, ms = C.c_int64(0), C.c_double(0)
-        _check(lib().ta_kernel_time(self.h, C.byref(n), C.byref(ms)), "ta_kernel_time")
+        if name is None:
+            _check(lib().ta_kernel_time(self.h, C.byref(n), C.byref(ms)), "ta_kernel_time")
+        else:
+            _check(lib().ta_kernel_time_of(self.h, name.encode(), C.byref(n), C.byref(ms)), "ta_kernel_time_of")
         return n.value, ms.value
 
 
