@@ -2240,20 +2240,35 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_build(Common cm, const uint8_t* r
     const int64_t g = base + lane_id();
     const uint64_t last = (uint64_t)(base + WAVE - 1 < Rt ? base + WAVE - 1 : Rt - 1);
     const int64_t s = wave_seg(cm.rpre, cm.nseg, (uint64_t)(g < Rt ? g : Rt - 1), (uint64_t)base, last);
-    if (g >= Rt) continue;
-    const uint64_t* rec = ref64 + ref_record_word(cm, ref, s, g - cm.rpre[s]);
-    uint64_t key;
-    if ((rec[1] >> 32) < 5 || !cell_key(rec, cell, &key)) continue;
-    const Seg& sg = cm.seg[s];
-    const uint64_t H = sg.hsize;
-    uint64_t h = mix64(key) & (H - 1);
-    for (uint64_t probe = 0; probe < H; ++probe) {
-      const unsigned long long prev = atomicCAS(&tab[cm.hpre[s] + h].key, 0ull, (unsigned long long)key);
-      if (prev == 0ull || prev == (unsigned long long)key) {
-        atomicAdd(&tab[cm.hpre[s] + h].ci, 1u);
-        break;
+    uint64_t key = 0;
+    bool v = false;
+    if (g < Rt) {
+      const uint64_t* rec = ref64 + ref_record_word(cm, ref, s, g - cm.rpre[s]);
+      v = (rec[1] >> 32) >= 5 && cell_key(rec, cell, &key);
+    }
+    // Lanes with the same segment and cell add their count with one atomic:
+    // neighbouring records mostly share a cell, so a wave has few distinct
+    // ones.  Each round takes the first pending lane's (segment, cell).
+    uint64_t pending = __ballot(v);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const uint64_t lk = readlane64(key, leader);
+      const int64_t ls = (int64_t)readlane64((uint64_t)s, leader);
+      const uint64_t same = __ballot(v && key == lk && s == ls);
+      if (lane_id() == leader) {
+        const Seg& sg = cm.seg[ls];
+        const uint64_t H = sg.hsize;
+        uint64_t h = mix64(lk) & (H - 1);
+        for (uint64_t probe = 0; probe < H; ++probe) {
+          const unsigned long long prev = atomicCAS(&tab[cm.hpre[ls] + h].key, 0ull, (unsigned long long)lk);
+          if (prev == 0ull || prev == (unsigned long long)lk) {
+            atomicAdd(&tab[cm.hpre[ls] + h].ci, (uint32_t)__popcll(same));
+            break;
+          }
+          h = (h + 1) & (H - 1);
+        }
       }
-      h = (h + 1) & (H - 1);
+      pending &= ~same;
     }
   }
 }
@@ -2292,30 +2307,32 @@ struct PredictArgs {
   unsigned long long* tcount;
 };
 
-// One wave per 16 matched records: inputs, integer MLP, predicted words.
+// One wave per 64 matched records at a time: every lane forms one record's
+// inputs, the integer MLP runs on four groups of 16 rows, and every lane
+// writes its record's predicted words.
 __global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
   __shared__ PredW s_w;
-  __shared__ int32_t s_in[WAVES][16][12];
-  __shared__ int32_t s_q[WAVES][16][4];
+  __shared__ int32_t s_in[WAVES][WAVE][12];
+  __shared__ int32_t s_q[WAVES][WAVE][4];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   load_weights(&s_w, a.pw);
   const int64_t M = cm.meta[5];
   const int l = lane_id(), wv = wave_id();
-  const int64_t chunks = (M + 15) / 16;
+  const int64_t chunks = (M + WAVE - 1) / WAVE;
   for (int64_t ch = (int64_t)blockIdx.x * WAVES + wv; ch < chunks; ch += (int64_t)gridDim.x * WAVES) {
-    const int64_t k = ch * 16 + l;
+    const int64_t k = ch * WAVE + l;
     bool on = false;
     const uint64_t* rec = nullptr;
-    if (l < 16 && k < M) {
+    int32_t* in = s_in[wv][l];
+    for (int c = 0; c < 12; ++c) in[c] = 0;
+    if (k < M) {
       const MDir e = a.mdir[k];
       const uint64_t g = mdir_slot(e);
       rec = a.ref + e.rword;
       const uint64_t hdr = rec[1];
       const int hl = a.hlen[g];
       on = hl >= 1 && (hdr >> 32) >= 6;
-      int32_t* in = s_in[wv][l];
-      for (int c = 0; c < 12; ++c) in[c] = 0;
       if (on) {
         for (int c = 0; c < 4; ++c) {
           const double r = __longlong_as_double((long long)rec[2 + c]);
@@ -2351,15 +2368,19 @@ __global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
         base = __shfl(base, lead, WAVE);
         const int64_t at = (int64_t)base + __popcll(mask & lanemask_lt(l));
         if (w && at < a.tcap) {
-          for (int c = 0; c < 12; ++c) a.tin[12 * at + c] = s_in[wv][l][c];
+          for (int c = 0; c < 12; ++c) a.tin[12 * at + c] = in[c];
           for (int c = 0; c < 4; ++c) a.ttgt[4 * at + c] = tg[c];
         }
       }
     }
     wave_sync();
-    mlp16(s_w, s_in[wv], s_q[wv]);
+    // rows of records that need no prediction are skipped four groups at a time
+    const uint64_t need = __ballot(on);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if ((need >> (16 * r)) & 0xFFFFull) mlp16(s_w, s_in[wv] + 16 * r, s_q[wv] + 16 * r);
     wave_sync();
-    if (l < 16 && k < M) {
+    if (k < M) {
       a.pred_on[k] = on ? 1 : 0;
       if (on) {
         for (int c = 0; c < 4; ++c) {
@@ -2391,6 +2412,9 @@ struct HistArgs {
   int64_t ocap;
 };
 
+// Four lanes per C' record (one per history word), 16 records per wave at a
+// time: every load and store instruction of a wave covers 16 consecutive
+// records' words.
 __global__ __launch_bounds__(BLOCK) void k_hist_out(HistArgs a) {
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
@@ -2399,8 +2423,12 @@ __global__ __launch_bounds__(BLOCK) void k_hist_out(HistArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) fail(cm.status, ERR_CAPACITY);
     return;
   }
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t it = (int64_t)blockIdx.x * BLOCK + threadIdx.x; it < M + Nn; it += stride) {
+  const int l = lane_id(), c = l & 3;
+  const int64_t total = M + Nn;
+  const int64_t stride = (int64_t)gridDim.x * WAVES * 16;
+  for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave_id()) * 16; base < total; base += stride) {
+    const int64_t it = base + (l >> 2);
+    if (it >= total) continue;
     if (it < M) {
       const MDir e = a.mdir[it];
       const int64_t s = mdir_seg(e);
@@ -2408,19 +2436,19 @@ __global__ __launch_bounds__(BLOCK) void k_hist_out(HistArgs a) {
       const uint64_t* rec = a.ref + e.rword;
       const bool has = (rec[1] >> 32) >= 6;
       const int64_t o = it + (int64_t)cm.npre[s];
-      const int hl = a.hlen ? a.hlen[g] : 0;
-      for (int c = 0; c < 4; ++c) {
-        a.o2[4 * o + c] = a.h1 ? a.h1[4 * g + c] : 0;
-        a.o1[4 * o + c] = has ? rec[2 + c] : 0;
+      a.o2[4 * o + c] = a.h1 ? a.h1[4 * g + c] : 0;
+      a.o1[4 * o + c] = has ? rec[2 + c] : 0;
+      if (c == 0) {
+        const int hl = a.hlen ? a.hlen[g] : 0;
+        a.olen[o] = (uint8_t)(hl + 1 > 2 ? 2 : hl + 1);
       }
-      a.olen[o] = (uint8_t)(hl + 1 > 2 ? 2 : hl + 1);
     } else {
       const int64_t r = it - M;
       const int64_t s = last_le<uint64_t>(cm.npre, 0, cm.nseg, (uint64_t)r);
       const Seg& g = cm.seg[s];
       const int64_t o = (int64_t)(g.mbase + g.n_match) + r;
-      for (int c = 0; c < 4; ++c) a.o1[4 * o + c] = a.o2[4 * o + c] = 0;
-      a.olen[o] = 0;
+      a.o1[4 * o + c] = a.o2[4 * o + c] = 0;
+      if (c == 0) a.olen[o] = 0;
     }
   }
 }
@@ -2653,7 +2681,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     PredictArgs pa{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, pw, m.tab, hist_in->h1, hist_in->h2,
                    hist_in->hlen, m.pred_x, m.pred_on, reinterpret_cast<const uint64_t*>(cur), c->tap_in,
                    c->tap_tgt, c->tap_cap, c->tap_count};
-    k_predict<<<grid_for(c, b.R, 16 * WAVES), BLOCK, 0, s>>>(pa);
+    k_predict<<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
   }
   if (!pw) {
     Timed tm(c, "encode_groups", s);
@@ -2758,7 +2786,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                    nullptr,    nullptr,
                    nullptr,    0,
                    nullptr};
-    k_predict<<<grid_for(c, b.R, 16 * WAVES), BLOCK, 0, s>>>(pa);
+    k_predict<<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
   }
   {
     Timed tm(c, "decode_unpack", s);
