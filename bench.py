@@ -298,11 +298,9 @@ def kernel_bytes(kname, acc):
         # plain mode: read C and R words of matched records and their starts and C/R words, write C' words,
         # the group blocks, bitmaps, sizes and offsets; read the group-to-segment and first-record maps
         "encode_groups": 24 * acc["W"] + 24 * acc["matched"] + acc["var"] + 25 * acc["groups"],
-        # learned mode: read C and R words of matched records and their directory entries, write C' words and
-        # the residual
-        "encode_resid": 32 * acc["W"] + 40 * acc["matched"],
-        # read the residual, write the group blocks, bitmaps, sizes, offsets
-        "encode_pack": 8 * acc["W"] + acc["var"] + 17 * acc["groups"],
+        # learned mode: the same, plus per matched record its four predicted words and flag, per group its
+        # choice byte
+        "encode_groups_learned": 24 * acc["W"] + 57 * acc["matched"] + acc["var"] + 26 * acc["groups"],
         # read the group blocks and their tables, R words and directory entries, write C' words
         "decode_unpack": 16 * acc["W"] + acc["var"] + 17 * acc["groups"] + 40 * acc["matched"],
         # gather the agents' fields (about the record bytes), indices, offsets; write records + offsets
@@ -342,7 +340,7 @@ def learned_mode(ctx, native, cfg, dev_states, host_states, args, idx_cap, ser_c
     calls, stage times and serialize + delta GB/s (same byte formula as plain
     mode), the learned kernels' times, and encoded bytes per record."""
     K = args.steps
-    kern = "encode_match,predict,encode_resid,encode_pack,decode_unpack"
+    kern = "encode_match,predict,encode_groups,decode_unpack"
     acc, fam, final = eager_pass(ctx, native, cfg, dev_states, host_states, args.warmup, idx_cap, ser_cap, enc_cap,
                                  kern, pred=pred)
     el, pl = eager_timed_pass(ctx, native, cfg, dev_states, args.warmup, idx_cap, ser_cap, pred=pred)
@@ -357,8 +355,9 @@ def learned_mode(ctx, native, cfg, dev_states, host_states, args, idx_cap, ser_c
         "serialize_delta": {"ms_per_step": acc["sd_ms"] / K, "GBps_algorithmic": sd_gbps,
                             "frac_hbm_peak": sd_gbps / HBM_PEAK_GBPS, "frac_copy_peak": sd_gbps / copy_gbps},
         "kernels_us_per_step": {k: 1000.0 * ms / K for k, (n, ms) in fam.items()},
-        "rooflines": [roofline_entry(k, n, ms, kernel_bytes(k, acc), copy_gbps, None)
-                      for k, (n, ms) in fam.items() if k in ("encode_resid", "encode_pack", "decode_unpack")],
+        "rooflines": [roofline_entry(k, n, ms, kernel_bytes(k + "_learned" if k == "encode_groups" else k, acc),
+                                     copy_gbps, None)
+                      for k, (n, ms) in fam.items() if k in ("encode_groups", "decode_unpack")],
         "bytes_per_agent": acc["tad"] / acc["records"],
         "learned_segments": acc["learned_segments"],
     }

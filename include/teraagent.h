@@ -399,9 +399,10 @@ ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t
  * only).  Names: "select_count", "select_scatter", "serialize_pack",
  * "encode_match" (every encoder kernel before the residual: headers,
  * UID join, layout, directory), "encode_join" (the UID join alone),
- * "encode_groups" (plain encodings: residual, block sizes, offsets and
- * blocks in one kernel), "predict", "encode_resid" and "encode_pack"
- * (learned encodings), "decode_unpack" (which also applies the residual to
+ * "encode_groups" (residual, block sizes, offsets and blocks in one kernel;
+ * in learned encodings both residuals and the smaller block), "predict"
+ * (learned encodings and decodings: neighbour counts and the network),
+ * "decode_unpack" (which also applies the residual to
  * the reference), "migrate_keep" (ta_migrate_apply: the agents that stay,
  * copied into the new store). */
 ta_status ta_time_kernel(ta_ctx *ctx, const char *name);

@@ -25,9 +25,11 @@
 //   k_enc_groups   plain mode: per 64-word group, C' words, the residual
 //                  C xor R (in registers), its block; a look-back over tiles
 //                  of groups places the blocks
-//   learned mode instead: k_enc_resid (C' words and both dense residuals),
-//                  k_enc_gsize (bitmaps, block sizes), scans, k_choose_mode,
-//                  k_enc_place (blocks of the chosen variant)
+//                  learned mode: the same kernel also forms the residual
+//                  against the predictions, keeps the smaller block of each
+//                  group and flags the segment's choices; k_choose_mode
+//                  picks each segment's mode, k_enc_fixup rewrites the rare
+//                  tied groups of learned segments
 //   k_enc_fixed    encoding offsets and headers; presence bitmaps, word
 //                  bitmaps, block size tables
 //   k_enc_newcopy  new record sizes, C' offsets of new records, new records
@@ -150,6 +152,8 @@ struct Common {
   uint64_t* opre;  // [nseg+1] C' message offsets
   uint64_t* cols;  // [COL_MAX][nseg+1] per segment values to scan
   uint64_t* fold;  // [nseg][FOLD_SLOTS] partial XORs of reference uids (spread to avoid atomic contention)
+  uint32_t* sflag; // [nseg] learned encodings: bit 0 some group's learned block is smaller, bit 1 some
+                   // group's plain block is smaller
   int64_t* meta;   // [0] C records [1] R records [2] hash slots [3] groups [4] presence words [5] matched
                    // [6] new records [7] new words [8] unused [9] fixed bytes [10] join tiles
                    // [11] join count entries [12] join buckets [13] join bucket overflow
@@ -287,6 +291,7 @@ __device__ void enc_setup(Common cm, const uint8_t* cur, int64_t cur_len,
     g.hsize = hs;
     g.fold = 0;
     for (int k = 0; k < FOLD_SLOTS; ++k) cm.fold[s * FOLD_SLOTS + k] = 0;
+    cm.sflag[s] = 0;
     g.mode = 0;
     // join layout: B buckets, counting tiles of TJ items (C tiles, then R tiles)
     uint64_t B = pow2ceil((nc + nr + JB_TARGET - 1) / JB_TARGET);
@@ -827,7 +832,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
         e.gs = (uint64_t)g | ((uint64_t)sx << 34);
         mdir[k] = e;
       }
-      if (crw) crw[k] = (uint64_t)coff[u] | ((uint64_t)roff[u] << 32);  // plain mode
+      if (crw) crw[k] = (uint64_t)coff[u] | ((uint64_t)roff[u] << 32);
       mstart[k] = d;
       *reinterpret_cast<uint32_t*>(newref + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
       map_groups(cm, sx, d - sg.dbase, rwv[u], gseg, gfirst, k);
@@ -884,18 +889,6 @@ __device__ inline uint32_t build_block(uint64_t D, uint64_t* b64, uint64_t* bitm
   return size;
 }
 
-// The 64 consecutive matched records a wave works on, as a table in LDS:
-// residual start (d[n] = end of the last record), source words in C and R,
-// and the record's first word in C'.  The wave then walks the residual
-// words lane-parallel: each lane finds its record with a binary search in
-// the table, and consecutive lanes read and write consecutive words.
-struct RecTab {
-  uint64_t d[WAVE + 1];
-  uint64_t c[WAVE];
-  uint64_t r[WAVE];
-  uint64_t o[WAVE];
-  uint8_t p[WAVE];  // learned: the record's words 2..5 are predicted
-};
 // Largest i < n with a[i] <= x (a non-decreasing, a[0] <= x): a search in LDS.
 __device__ inline int lds_last_le(const uint64_t* a, int n, uint64_t x) {
   int lo = 0, hi = n;
@@ -906,7 +899,6 @@ __device__ inline int lds_last_le(const uint64_t* a, int n, uint64_t x) {
   }
   return lo;
 }
-__device__ inline int rec_of(const RecTab& t, int n, uint64_t d) { return lds_last_le(t.d, n, d); }
 
 // New records a wave copies (up to 64): word prefix within the wave (q[n]
 // = total), first source word, first destination words (uint64 indices).
@@ -917,240 +909,17 @@ struct NewTab {
   uint64_t dst2[WAVE];
 };
 
-struct ResidArgs {
-  Common cm;
-  const uint64_t* cur;
-  const uint64_t* ref;
-  const MDir* mdir;
-  const uint64_t* mstart;  // [matched+1] residual start of every matched record
-  const uint64_t* pred_x;  // learned: predicted words 2..5 per matched record [k][4]
-  const uint8_t* pred_on;  // learned: record k predicted
-  uint64_t* newref;        // C' (words)
-  uint64_t* D;             // dense residual of all segments (against R)
-  uint64_t* D2;            // learned mode: residual against the predictions (nullptr: plain)
-};
-
-// Matched records in C' order: their C words go to C' and C xor X to the
-// dense residual (D against R; D2 against the predictions in learned mode).
-template <int OP>
-__global__ __launch_bounds__(BLOCK) void k_enc_resid(ResidArgs a) {
-  __shared__ RecTab s_t[WAVES];
-  const Common& cm = a.cm;
-  if (status_of(cm.status) & ANY_ERR) return;
-  const int64_t M = cm.meta[5];
-  const int l = lane_id(), wv = wave_id();
-  RecTab& t = s_t[wv];
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t kb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; kb < M; kb += stride) {
-    const int64_t k = kb + l;
-    const int64_t ke = kb + WAVE < M ? kb + WAVE : M;
-    const int n = (int)(ke - kb);
-    if (k < M) {
-      const MDir e = a.mdir[k];
-      t.d[l] = e.dstart;
-      t.c[l] = e.cword;
-      t.r[l] = e.rword;
-      t.o[l] = cm.seg[mdir_seg(e)].cpw + e.dstart;
-      t.p[l] = a.D2 ? a.pred_on[k] : 0;
-    }
-    if (l == 0) t.d[n] = a.mstart[ke];
-    wave_sync();
-    const uint64_t d1 = t.d[n];
-    for (uint64_t d = t.d[0] + l; d < d1; d += WAVE) {
-      const int i = rec_of(t, n, d);
-      const uint64_t off = d - t.d[i];
-      const uint64_t c = a.cur[t.c[i] + off];
-      const uint64_t x = a.ref[t.r[i] + off];
-      a.newref[t.o[i] + off] = c;
-      a.D[d] = diff_word<OP>(c, x);
-      if (a.D2) {
-        const uint64_t xl = (t.p[i] && off >= 2 && off < 6) ? a.pred_x[4 * (kb + i) + (off - 2)] : x;
-        a.D2[d] = diff_word<OP>(c, xl);
-      }
-    }
-    wave_sync();
-  }
-}
-
-struct PackArgs {
-  Common cm;
-  const uint64_t* D;
-  uint8_t* enc;
-  int64_t enc_cap;
-  uint64_t* bm;          // [groups] word bitmaps (of the chosen variant after pass 3)
-  uint8_t* gsz;          // [groups] block sizes / 8 (of the chosen variant after pass 3)
-  const uint64_t* gex;   // [groups+1] exclusive prefix of block bytes (pass 3)
-  const uint32_t* gseg;  // [groups] segment of the group
-  const uint64_t* D2;    // learned variant (nullptr: plain only)
-  uint8_t* gsz2;         // learned variant block sizes / 8
-};
-
-#ifndef TA_PG_WAVE
-#define TA_PG_WAVE 4
-#endif
-constexpr int PG_WAVE = TA_PG_WAVE;  // groups one wave handles at a time (loads issued together)
 #ifndef TA_UNPACK_PG
 #define TA_UNPACK_PG 1
 #endif
 constexpr int UNPACK_PG = TA_UNPACK_PG;  // the decoder's groups per wave at a time
 
-// Pass 1 of the zero-block packer: per 64-word group, its bitmap word and
-// its block size (nibbles + significant bytes, rounded to 8).
-// (segs, gpre, gseg: read-only here; as restrict parameters their uniform
-// reads become scalar loads)
-__global__ __launch_bounds__(BLOCK) void k_enc_gsize(PackArgs a, const Seg* __restrict__ segs,
-                                                     const uint64_t* __restrict__ gpre,
-                                                     const uint32_t* __restrict__ gseg) {
-  const Common& cm = a.cm;
-  if (status_of(cm.status) & ANY_ERR) return;
-  const int64_t Gt = cm.meta[3];
-  const int l = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * WAVES;
-  for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wave_id()) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
-    uint64_t Dv[PG_WAVE], D2v[PG_WAVE];
-#pragma unroll
-    for (int x = 0; x < PG_WAVE; ++x) {
-      const int64_t gg = g0 + x;
-      Dv[x] = 0;
-      D2v[x] = 0;
-      if (gg < Gt) {
-        const int64_t s = (int64_t)uniform32(gseg[gg]);
-        const Seg& sg = segs[s];
-        const uint64_t q = 64 * ((uint64_t)gg - gpre[s]) + (uint64_t)l;
-        if (q < sg.W) {
-          Dv[x] = a.D[sg.dbase + q];
-          if (a.D2) D2v[x] = a.D2[sg.dbase + q];
-        }
-      }
-    }
-#pragma unroll
-    for (int x = 0; x < PG_WAVE; ++x) {
-      const int64_t gg = g0 + x;
-      if (gg >= Gt) break;
-      const uint64_t D = Dv[x];
-      const uint64_t bm = __ballot(D != 0);
-      const uint32_t len = D ? (uint32_t)(8 - (__clzll((long long)D) >> 3)) : 0u;
-      const uint32_t sig = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan32(len), 63);
-      if (l == 0) {
-        a.bm[gg] = bm;
-        a.gsz[gg] = (uint8_t)((((uint32_t)__popcll(bm) + 1) / 2 + sig + 7) / 8);
-      }
-      if (a.D2) {
-        const uint64_t D2 = D2v[x];
-        const uint64_t bm2 = __ballot(D2 != 0);
-        const uint32_t len2 = D2 ? (uint32_t)(8 - (__clzll((long long)D2) >> 3)) : 0u;
-        const uint32_t sig2 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan32(len2), 63);
-        if (l == 0) a.gsz2[gg] = (uint8_t)((((uint32_t)__popcll(bm2) + 1) / 2 + sig2 + 7) / 8);
-      }
-    }
-  }
-}
-
-struct GszIn {
-  const uint8_t* gsz;
-  __device__ uint64_t operator()(int64_t g) const { return 8 * (uint64_t)gsz[g]; }
-};
-// Learned calls choose per segment among plain (mode 0), learned (1) and
-// mixed (2): in a mixed segment each group takes the learned residual when
-// its block is strictly smaller, and bit 7 of its size byte says so.
-__device__ inline bool group_learned(uint32_t mode, uint8_t plain, uint8_t learned) {
-  return mode == 1 || (mode == 2 && learned < plain);
-}
-struct GMinIn {  // block bytes of the smaller variant of each group
-  const uint8_t* gsz;
-  const uint8_t* gsz2;
-  __device__ uint64_t operator()(int64_t g) const {
-    const uint8_t a = gsz[g], b = gsz2[g];
-    return 8 * (uint64_t)(b < a ? b : a);
-  }
-};
-struct GChosenIn {  // block bytes of the variant chosen for the group
-  const uint8_t* gsz;
-  const uint8_t* gsz2;
-  const uint32_t* gseg;
-  const Seg* seg;
-  __device__ uint64_t operator()(int64_t g) const {
-    const uint8_t a = gsz[g], b = gsz2[g];
-    return 8 * (uint64_t)(group_learned(seg[gseg[g]].mode, a, b) ? b : a);
-  }
-};
-
-// Learned mode: per segment, keep the predictor's encoding only when it is
-// strictly smaller (the fixed sections are the same for both).
-// Plain when mixing gains nothing over plain, learned when it gains
-// nothing over learned, else mixed (the mixed total is never larger).
-__global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm, const uint64_t* gex, const uint64_t* gex2,
-                                                       const uint64_t* gex3) {
-  if (status_of(cm.status) & ANY_ERR) return;
-  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
-    const uint64_t plain = gex[cm.gpre[s + 1]] - gex[cm.gpre[s]];
-    const uint64_t learned = gex2[cm.gpre[s + 1]] - gex2[cm.gpre[s]];
-    const uint64_t mixed = gex3[cm.gpre[s + 1]] - gex3[cm.gpre[s]];
-    cm.seg[s].mode = mixed == plain ? 0 : (mixed == learned ? 1 : 2);
-  }
-}
-
-// Pass 3: every group rebuilds its block in LDS and writes it at its offset.
-__global__ __launch_bounds__(BLOCK) void k_enc_place(PackArgs a, const Seg* __restrict__ segs,
-                                                     const uint64_t* __restrict__ gpre,
-                                                     const uint32_t* __restrict__ gseg,
-                                                     const uint64_t* __restrict__ gex) {
-  __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8 + 1];
-  const Common& cm = a.cm;
-  if (status_of(cm.status) & ANY_ERR) return;
-  const int64_t Gt = cm.meta[3];
-  const int l = lane_id(), wv = wave_id();
-  const int64_t nw = (int64_t)gridDim.x * WAVES;
-  for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * PG_WAVE; g0 < Gt; g0 += nw * PG_WAVE) {
-    uint64_t Dv[PG_WAVE], at[PG_WAVE];
-    uint32_t flag[PG_WAVE];
-#pragma unroll
-    for (int x = 0; x < PG_WAVE; ++x) {
-      const int64_t gg = g0 + x;
-      Dv[x] = 0;
-      at[x] = 0;
-      flag[x] = 0;
-      if (gg < Gt) {
-        const int64_t s = (int64_t)uniform32(gseg[gg]);
-        const Seg& sg = segs[s];
-        const uint64_t q = 64 * ((uint64_t)gg - gpre[s]) + (uint64_t)l;
-        const uint32_t md = uniform32((uint32_t)sg.mode);
-        const bool lrn = a.D2 && group_learned(md, a.gsz[gg], a.gsz2[gg]);
-        flag[x] = md == 2 && lrn ? 0x80u : 0u;
-        const uint64_t* src = lrn ? a.D2 : a.D;
-        if (q < sg.W) Dv[x] = src[sg.dbase + q];
-        at[x] = uniform64(sg.fixed_excl + sg.fixed + gex[gg]);
-      }
-    }
-#pragma unroll
-    for (int x = 0; x < PG_WAVE; ++x) {
-      const int64_t gg = g0 + x;
-      if (gg >= Gt) break;
-      uint64_t bm;
-      const uint32_t size = build_block(Dv[x], s_blk[wv], &bm);
-      wave_sync();  // every lane has read this group's sizes before lane 0 rewrites them
-      if (a.D2 && l == 0) {  // the tables of the chosen variant (mixed: bit 7 = learned)
-        a.bm[gg] = bm;
-        a.gsz[gg] = (uint8_t)(size / 8 | flag[x]);
-      }
-      if (size) {
-        if (at[x] + size > (uint64_t)a.enc_cap) {
-          if (l == 0) fail(cm.status, ERR_CAPACITY);
-        } else {
-          uint64_t* dst = reinterpret_cast<uint64_t*>(a.enc + at[x]);
-          for (uint32_t w = l; w < size / 8; w += WAVE) dst[w] = s_blk[wv][w];
-        }
-      }
-      wave_sync();
-    }
-  }
-}
-
-// Plain mode, residual and packing in one pass.  A wave takes EG_R
-// consecutive 64-word groups; for each, the matched records overlapping it
-// (at most 33, one per lane, lane 0 holding the one with the group's first
-// word) give every word's C and R words: C goes to C', D = C xor R stays in
-// registers with its block size.  Tiles of EG_TILE groups (one block) are
+// Residual and packing in one pass.  A wave takes EG_R consecutive 64-word
+// groups; for each, the matched records overlapping it (at most 33, one per
+// lane, lane 0 holding the one with the group's first word) give every
+// word's C and R words: C goes to C', D = C xor R stays in registers with
+// its block size.  Learned calls also form D2 = C xor X (X: the prediction
+// for predicted words, else R) and keep the smaller block.  Tiles of EG_TILE groups (one block) are
 // handed out in order and join a decoupled look-back over their block
 // bytes, which gives every group's block offset; then each group's block is
 // built in LDS and written in place.  The dense residual never goes to
@@ -1175,14 +944,31 @@ struct GroupArgs {
   uint64_t* newref;        // C' (words)
   uint8_t* enc;
   int64_t enc_cap;
-  uint64_t* bm;   // [groups] word bitmaps
-  uint8_t* gsz;   // [groups] block sizes / 8
+  uint64_t* bm;   // [groups] word bitmaps (learned: of the variant written)
+  uint8_t* gsz;   // [groups] block sizes / 8 (learned: the smaller variant's)
   uint64_t* gex;  // [groups+1] exclusive prefix of block bytes (gex[groups] = total)
+  // learned calls only
+  const uint64_t* pred_x;  // [matched][4] predicted words 2..5
+  const uint8_t* pred_on;  // [matched] the record's words 2..5 are predicted
+  uint8_t* gch;            // [groups] 0 plain block written, 1 learned block (strictly smaller),
+                           // 2 plain block written for a tie whose learned block differs
 };
+
+// Learned calls: the group's variant and the segment flags.  The block of a
+// group is the smaller one (learned on a strict win); a tie keeps the plain
+// bytes unless its segment turns out to be learned (mode 1), which
+// k_enc_fixup handles.  The size and so every block offset is min(plain,
+// learned) whatever the segment's mode.
+__device__ inline void note_choice(const Common& cm, int64_t s, uint32_t plain, uint32_t learned) {
+  const uint32_t bits = (learned < plain ? 1u : 0u) | (plain < learned ? 2u : 0u);
+  if (bits && lane_id() == 0 &&
+      (__hip_atomic_load(cm.sflag + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bits) != bits)
+    atomicOr(cm.sflag + s, bits);
+}
 
 // (segs, gpre, gseg, gfirst: read-only here; as restrict parameters their
 // uniform reads become scalar loads)
-template <int OP>
+template <int OP, bool LRN>
 __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg* __restrict__ segs,
                                                          const uint64_t* __restrict__ gpre,
                                                          const uint32_t* __restrict__ gseg,
@@ -1235,7 +1021,8 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
       // nothing.
       int64_t gc[EG_R];
       bool gv[EG_R], has[EG_R];
-      uint64_t mst[EG_R], cwd[EG_R], rwd[EG_R];
+      uint64_t mst[EG_R], cwd[EG_R], rwd[EG_R], k0v[EG_R];
+      uint32_t pon[EG_R];
 #pragma unroll
       for (int x = 0; x < EG_R; ++x) {
         gv[x] = g0 + x < Gt;
@@ -1243,12 +1030,14 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
         // lane i <= 32: start, C word and R word of record k0 + i (a group
         // implies a matched record, so M >= 1 and the clamped index is valid)
         const uint64_t k0 = uniform32(gfirst[gc[x]]);
+        k0v[x] = k0;
         has[x] = l <= 32 && k0 + l < (uint64_t)M;
         const uint64_t kk = has[x] ? k0 + l : (uint64_t)M - 1;
         mst[x] = a.mstart[kk];
         const uint64_t crw = a.crw[kk];
         cwd[x] = (uint32_t)crw;
         rwd[x] = crw >> 32;
+        pon[x] = LRN ? (uint32_t)a.pred_on[kk] : 0u;
       }
       __builtin_amdgcn_sched_barrier(0);
       // start relative to the group (clamped to [-2^30, 64]), words relative to
@@ -1267,8 +1056,8 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
         if (l >= 1 && relv[x] >= 1 && relv[x] < WAVE) s_mark[wv][x][relv[x]] = (uint32_t)gc[x] + 1;
       }
       wave_sync();
-      uint64_t cv[EG_R], xv[EG_R];
-      bool live[EG_R];
+      uint64_t cv[EG_R], xv[EG_R], pv[EG_R];
+      bool live[EG_R], prd[EG_R];
 #pragma unroll
       for (int x = 0; x < EG_R; ++x) {
         const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
@@ -1287,6 +1076,15 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
         const uint32_t rw0 = (uint32_t)__builtin_amdgcn_readlane((int)rw, 0);
         cv[x] = a.cur[uniform64(sg.cbody / 8) + (live[x] ? cwi + off : cw0)];
         xv[x] = a.ref[uniform64(sg.rbody / 8) + (live[x] ? rwi + off : rw0)];
+        if constexpr (LRN) {
+          // a predicted word (2..5 of a predicted record) is taken against the
+          // prediction; others read prediction 0 (valid: M >= 1), unused
+          prd[x] = live[x] && __shfl((int)pon[x], idx, WAVE) != 0 && off >= 2 && off < 6;
+          pv[x] = a.pred_x[prd[x] ? 4 * (k0v[x] + (uint64_t)idx) + (off - 2) : 0];
+        } else {
+          prd[x] = false;
+          pv[x] = 0;
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
       // C' words, residual words and block sizes
@@ -1297,14 +1095,34 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
         const int64_t sx = (int64_t)uniform32(gseg[gc[x]]);
         const Seg& sg = segs[sx];
         if (live[x]) a.newref[sg.cpw + sg.dbase + 64 * ((uint64_t)gc[x] - gpre[sx]) + (uint64_t)l] = cv[x];
-        const uint64_t bmw = __ballot(D[x] != 0);
+        uint64_t bmw = __ballot(D[x] != 0);
         const uint32_t len = D[x] ? (uint32_t)(8 - (__clzll((long long)D[x]) >> 3)) : 0u;
         inclv[x] = wave_incl_scan32(len);
         const uint32_t sig = (uint32_t)__builtin_amdgcn_readlane((int)inclv[x], 63);
         size[x] = gv[x] ? ((((uint32_t)__popcll(bmw) + 1) / 2 + sig + 7) & ~7u) : 0u;
+        uint8_t choice = 0;
+        if constexpr (LRN) {
+          const uint64_t D2 = live[x] ? diff_word<OP>(cv[x], prd[x] ? pv[x] : xv[x]) : 0;
+          const uint64_t bm2 = __ballot(D2 != 0);
+          const uint32_t len2 = D2 ? (uint32_t)(8 - (__clzll((long long)D2) >> 3)) : 0u;
+          const uint32_t incl2 = wave_incl_scan32(len2);
+          const uint32_t sig2 = (uint32_t)__builtin_amdgcn_readlane((int)incl2, 63);
+          const uint32_t size2 = gv[x] ? ((((uint32_t)__popcll(bm2) + 1) / 2 + sig2 + 7) & ~7u) : 0u;
+          if (gv[x]) note_choice(cm, sx, size[x], size2);
+          if (size2 < size[x]) {  // uniform
+            D[x] = D2;
+            bmw = bm2;
+            inclv[x] = incl2;
+            size[x] = size2;
+            choice = 1;
+          } else if (size2 == size[x] && __ballot(D2 != D[x])) {
+            choice = 2;
+          }
+        }
         if (gv[x] && l == 0) {
           a.bm[gc[x]] = bmw;
           a.gsz[gc[x]] = (uint8_t)(size[x] / 8);
+          if constexpr (LRN) a.gch[gc[x]] = choice;
         }
         wsum += size[x];
       }
@@ -1363,6 +1181,81 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
   }
 }
 
+// Learned calls: each segment's mode from its flags -- plain (0) when no
+// group's learned block is smaller, learned (1) when no group's plain block
+// is smaller, else mixed (2) (a mixed encoding is never larger than either).
+__global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm) {
+  if (status_of(cm.status) & ANY_ERR) return;
+  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
+    const uint32_t f = cm.sflag[s];
+    cm.seg[s].mode = !(f & 1u) ? 0 : (!(f & 2u) ? 1 : 2);
+  }
+}
+
+// Learned calls, after k_choose_mode: in a learned (mode 1) segment a group
+// whose two blocks tie in size but differ was written with the plain bytes;
+// its learned block replaces them (same size and offset) with its bitmap.
+// One wave per such group; every other group is only looked at.
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_enc_fixup(GroupArgs a, const Seg* __restrict__ segs,
+                                                     const uint64_t* __restrict__ gpre,
+                                                     const uint32_t* __restrict__ gseg,
+                                                     const uint32_t* __restrict__ gfirst) {
+  __shared__ uint64_t s_blk[WAVES][BLK_MAX / 8 + 1];
+  __shared__ uint32_t s_mark[WAVES][WAVE];
+  const Common& cm = a.cm;
+  if (status_of(cm.status) & ANY_ERR) return;
+  const int64_t Gt = cm.meta[3], M = cm.meta[5];
+  const int l = lane_id(), wv = wave_id();
+  for (int64_t b0 = ((int64_t)blockIdx.x * WAVES + wv) * WAVE; b0 < Gt; b0 += (int64_t)gridDim.x * WAVES * WAVE) {
+    const int64_t mine = b0 + l;
+    bool todo = false;
+    if (mine < Gt && a.gch[mine] == 2) todo = segs[gseg[mine]].mode == 1;
+    uint64_t pending = __ballot(todo);
+    while (pending) {
+      const int lead = __ffsll((unsigned long long)pending) - 1;
+      pending &= pending - 1;
+      const int64_t gg = b0 + lead;
+      const int64_t sx = (int64_t)uniform32(gseg[gg]);
+      const Seg& sg = segs[sx];
+      const uint64_t lg = (uint64_t)gg - gpre[sx];
+      const uint64_t k0 = uniform32(gfirst[gg]);
+      const bool has = l <= 32 && k0 + l < (uint64_t)M;
+      const uint64_t kk = has ? k0 + l : (uint64_t)M - 1;
+      const int64_t r = (int64_t)a.mstart[kk] - (int64_t)(sg.dbase + 64 * lg);
+      const int rel = !has ? 64 : (r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r));
+      const uint64_t crw = a.crw[kk];
+      const uint32_t cw = (uint32_t)crw, rw = (uint32_t)(crw >> 32);
+      const uint32_t pon = a.pred_on[kk];
+      s_mark[wv][l] = 0;
+      wave_sync();
+      if (l >= 1 && rel >= 1 && rel < WAVE) s_mark[wv][rel] = 1;
+      wave_sync();
+      const uint64_t starts = __ballot(s_mark[wv][l] != 0);
+      const int idx = __popcll(starts & lanemask_le(l));
+      const uint32_t off = (uint32_t)(l - __shfl(rel, idx, WAVE));
+      const bool live = 64 * lg + (uint64_t)l < sg.W;
+      const uint32_t cwi = (uint32_t)__shfl((int)cw, idx, WAVE), rwi = (uint32_t)__shfl((int)rw, idx, WAVE);
+      const uint32_t cw0 = (uint32_t)__builtin_amdgcn_readlane((int)cw, 0);
+      const uint32_t rw0 = (uint32_t)__builtin_amdgcn_readlane((int)rw, 0);
+      const uint64_t c = a.cur[sg.cbody / 8 + (live ? cwi + off : cw0)];
+      const uint64_t x = a.ref[sg.rbody / 8 + (live ? rwi + off : rw0)];
+      const bool prd = live && __shfl((int)pon, idx, WAVE) != 0 && off >= 2 && off < 6;
+      const uint64_t pv = a.pred_x[prd ? 4 * (k0 + (uint64_t)idx) + (off - 2) : 0];
+      const uint64_t D2 = live ? diff_word<OP>(c, prd ? pv : x) : 0;
+      uint64_t bm2;
+      const uint32_t size = build_block(D2, s_blk[wv], &bm2);
+      if (l == 0) a.bm[gg] = bm2;
+      const uint64_t at = sg.fixed_excl + sg.fixed + a.gex[gg];
+      if (size && at + size <= (uint64_t)a.enc_cap) {
+        uint64_t* dst = reinterpret_cast<uint64_t*>(a.enc + at);
+        for (uint32_t w = l; w < size / 8; w += WAVE) dst[w] = s_blk[wv][w];
+      }
+      wave_sync();
+    }
+  }
+}
+
 
 constexpr int FX_PW = 8;  // presence words per wave in k_enc_fixed
 
@@ -1373,8 +1266,9 @@ constexpr int FX_PW = 8;  // presence words per wave in k_enc_fixed
 // block bytes before its first group.  The offsets are written even when the
 // encodings do not fit (they give the size needed).
 __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m, const uint64_t* bm,
-                                                     const uint8_t* gsz, const uint64_t* gex, uint8_t* enc,
-                                                     int64_t enc_cap, int64_t* enc_off, uint8_t* modes) {
+                                                     const uint8_t* gsz, const uint8_t* gch, const uint64_t* gex,
+                                                     uint8_t* enc, int64_t enc_cap, int64_t* enc_off,
+                                                     uint8_t* modes) {
   if (status_of(cm.status) & ANY_ERR) return;
   const uint64_t total_bytes = (uint64_t)cm.meta[9] + gex[cm.meta[3]];
   const bool fits = total_bytes <= (uint64_t)enc_cap;
@@ -1450,7 +1344,8 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
       uint8_t* sec = enc + encm(s) + 64 + 8 * g.PG;
       *reinterpret_cast<uint64_t*>(sec + 8 * lg) = bm[gg];
       sec += 8 * g.G;
-      sec[lg] = gsz[gg];
+      // mixed segments: bit 7 marks a group whose block is the learned one
+      sec[lg] = (uint8_t)(gsz[gg] | (gch && g.mode == 2 && gch[gg] == 1 ? 0x80u : 0u));
       if (lg == g.G - 1)
         for (uint64_t b = g.G; b < round8(g.G); ++b) sec[b] = 0;
     }
@@ -2475,11 +2370,7 @@ struct Mem {
   uint32_t* gfirst;
   uint32_t* mrw;
   uint64_t* mstart;
-  uint64_t* D;
-  uint64_t* D2;
-  uint8_t* gsz2;
-  uint64_t* gex2;
-  uint64_t* gex3;
+  uint8_t* gch;
   uint64_t* juid;
   uint64_t* jhdr;
   uint32_t* jcnt;
@@ -2508,6 +2399,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.cm.opre = ar.take<uint64_t>(nseg + 1);
   m.cm.cols = ar.take<uint64_t>(COL_MAX * (nseg + 1));
   m.cm.fold = ar.take<uint64_t>(FOLD_SLOTS * (nseg + 1));
+  m.cm.sflag = ar.take<uint32_t>(nseg + 1);
   m.cm.meta = ar.take<int64_t>(16);
   m.cm.status = nullptr;
   m.cm.op = 0;
@@ -2530,11 +2422,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.gfirst = ar.take<uint32_t>(b.G);
   m.mrw = ar.take<uint32_t>(b.R);
   m.mstart = ar.take<uint64_t>(b.R + 1);
-  m.D = learned ? ar.take<uint64_t>(b.W) : nullptr;
-  m.D2 = learned ? ar.take<uint64_t>(b.W) : nullptr;
-  m.gsz2 = learned ? ar.take<uint8_t>(b.G) : nullptr;
-  m.gex2 = learned ? ar.take<uint64_t>(b.G + 1) : nullptr;
-  m.gex3 = learned ? ar.take<uint64_t>(b.G + 1) : nullptr;
+  m.gch = learned ? ar.take<uint8_t>(b.G) : nullptr;
   m.juid = ar.take<uint64_t>(b.C + b.R);
   m.jhdr = ar.take<uint64_t>(b.C + b.R);
   m.jcnt = ar.take<uint32_t>(b.E);
@@ -2669,7 +2557,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
       }
     }
     k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords,
-                                                                pred || hist_out ? m.mdir : nullptr, pred ? nullptr : m.crw,
+                                                                pred || hist_out ? m.mdir : nullptr, m.crw,
                                                                 m.mstart, newref, m.gseg,
                                    m.gfirst);
   }
@@ -2683,41 +2571,32 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                    c->tap_tgt, c->tap_cap, c->tap_count};
     k_predict<<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
   }
-  if (!pw) {
+  {
     Timed tm(c, "encode_groups", s);
     GroupArgs ga{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.crw,
-                 m.mstart, reinterpret_cast<uint64_t*>(newref), enc, enc_cap, m.bm, m.gsz, m.gex};
+                 m.mstart, reinterpret_cast<uint64_t*>(newref), enc, enc_cap, m.bm, m.gsz, m.gex,
+                 m.pred_x, m.pred_on, m.gch};
     const int gg = grid_for(c, b.G, EG_TILE);
-    if (c->diff_op)
-      k_enc_groups<1><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lookback(c, 3));
-    else
-      k_enc_groups<0><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lookback(c, 3));
-  } else {
-    {
-      Timed tm(c, "encode_resid", s);
-      ResidArgs ra{m.cm, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<const uint64_t*>(ref), m.mdir,
-                   m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(newref), m.D, m.D2};
-      if (c->diff_op)
-        k_enc_resid<1><<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
-      else
-        k_enc_resid<0><<<grid_for(c, b.R, BLOCK), BLOCK, 0, s>>>(ra);
-    }
-    Timed tm(c, "encode_pack", s);
-    PackArgs pa{m.cm, m.D, enc, enc_cap, m.bm, m.gsz, m.gex, m.gseg, m.D2, m.gsz2};
-    const int gp = grid_for(c, b.G, WAVES * PG_WAVE);
-    const int gs = grid_for(c, b.G + 1, SCAN_TILE);
-    k_enc_gsize<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg);
-    k_scan<GszIn><<<gs, SCAN_BLOCK, 0, s>>>(GszIn{m.gsz}, m.cm.meta + 3, b.G, m.gex, lookback(c, 3));
+    const LookBack lb = lookback(c, 3);
     if (pw) {
-      k_scan<GszIn><<<gs, SCAN_BLOCK, 0, s>>>(GszIn{m.gsz2}, m.cm.meta + 3, b.G, m.gex2, lookback(c, 4));
-      k_scan<GMinIn><<<gs, SCAN_BLOCK, 0, s>>>(GMinIn{m.gsz, m.gsz2}, m.cm.meta + 3, b.G, m.gex3, lookback(c, 5));
-      k_choose_mode<<<gseg, BLOCK, 0, s>>>(m.cm, m.gex, m.gex2, m.gex3);
-      k_scan<GChosenIn><<<gs, SCAN_BLOCK, 0, s>>>(GChosenIn{m.gsz, m.gsz2, m.gseg, m.cm.seg}, m.cm.meta + 3, b.G, m.gex,
-                                             lookback(c, 6));
+      if (c->diff_op)
+        k_enc_groups<1, true><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lb);
+      else
+        k_enc_groups<0, true><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lb);
+      k_choose_mode<<<gseg, BLOCK, 0, s>>>(m.cm);
+      const int gf = grid_for(c, b.G, WAVES * WAVE);
+      if (c->diff_op)
+        k_enc_fixup<1><<<gf, BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst);
+      else
+        k_enc_fixup<0><<<gf, BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst);
+    } else {
+      if (c->diff_op)
+        k_enc_groups<1, false><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lb);
+      else
+        k_enc_groups<0, false><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lb);
     }
-    k_enc_place<<<gp, BLOCK, 0, s>>>(pa, m.cm.seg, m.cm.gpre, m.gseg, m.gex);
   }
-  k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.bm, m.gsz, m.gex, enc, enc_cap, enc_off, modes);
+  k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.bm, m.gsz, m.gch, m.gex, enc, enc_cap, enc_off, modes);
   k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.nlist, m.cwords, cur, enc, newref);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,

@@ -91,3 +91,20 @@ class OracleLearnedSide:
                    hist=h)
         self.ref, self.ref_off, self.hist = nref, noff, h
         return out
+
+
+def tied_learned_groups(enc, eoff, plain, plain_off):
+    """Groups of learned (mode 1) segments whose learned and plain blocks
+    have the same size but differ (the encoder must write the learned one):
+    counted from the oracle's learned encodings and its plain encodings of
+    the same messages."""
+    from tests.specparse import group_blocks
+    n = 0
+    for s in range(len(eoff) - 1):
+        mode, gl = group_blocks(enc[eoff[s]:eoff[s + 1]].tobytes())
+        if mode != 1:
+            continue
+        _, gp = group_blocks(plain[plain_off[s]:plain_off[s + 1]].tobytes())
+        for (sl, bl, xl), (sp, bp, xp) in zip(gl, gp):
+            n += int((sl & 0x7F) == (sp & 0x7F) and (bl != bp or xl != xp))
+    return n

@@ -141,3 +141,23 @@ def encode_tad1(cur_records, ref_records, op: int = 0) -> bytes:
     body = presence + word_bits + _pad8(bytes(sizes)) + _pad8(struct.pack(f"<{len(new)}I", *new_sizes))
     body += b"".join(struct.pack(f"<{len(cur_records[i])}Q", *cur_records[i]) for i in new)
     return hdr + body + blocks
+
+
+def group_blocks(enc: bytes):
+    """The residual groups of one TAD1 encoding: (mode, [(size byte, bitmap
+    word, block bytes), ...]) in group order."""
+    (magic, ver, mode, packer, n_ref, n_match, n_new, op, ref_words, fold, W, new_words,
+     var_bytes) = struct.unpack_from("<IHBBIIIIQQQQQ", enc, 0)
+    at = 64 + 8 * ((n_ref + 63) // 64)
+    G = (W + 63) // 64
+    bits = [struct.unpack_from("<Q", enc, at + 8 * g)[0] for g in range(G)]
+    at += 8 * G
+    gsz = list(enc[at:at + G])
+    at += (G + 7) // 8 * 8
+    at += (4 * n_new + 7) // 8 * 8 + 8 * new_words
+    out = []
+    for g in range(G):
+        n = 8 * (gsz[g] & 0x7F)
+        out.append((gsz[g], bits[g], bytes(enc[at:at + n])))
+        at += n
+    return mode, out

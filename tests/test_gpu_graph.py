@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_2509_24063_amd import synth
-from tests.exchange_util import OracleLearnedSide, OracleSide, host
+from tests.exchange_util import OracleLearnedSide, OracleSide, host, tied_learned_groups
 from tests.test_oracle_predictor import copy_last_move_blob
 
 pytestmark = pytest.mark.gpu
@@ -139,16 +139,20 @@ def test_heterogeneous_learned_matches_oracle(native, op):
     idx_cap, msgs_cap = capacities(ctx, world.store, cfg.ndirs, cfg.w, slack=1.5)
     pl = Pipeline(ctx, native.DeviceStore(world.store), cfg.w, cfg.ndirs, idx_cap, msgs_cap, pred=pred)
     orc = OracleLearnedSide(pl.nseg, oracle.mlp_struct(blob), op)
-    modes = []
+    modes, ties = [], 0
     for it in range(5):
         print(f"[cfg5 learned] op {op} iteration {it}", flush=True)
         pl.step(native.DeviceStore(world.store))
         ctx.check(f"iteration {it}")
+        ref, ref_off = orc.ref, orc.ref_off
         o = orc.step(world.store, cfg)
         _same_as_oracle(_outputs(pl), o, f"cfg5 op {op} iteration {it}", pl)
         modes.append(o["modes"])
+        pe, peo, _, _, _, _ = oracle.encode_all(o["buf"], o["moff"], ref, ref_off, op=op)
+        ties += tied_learned_groups(o["enc"], o["eoff"], pe, peo)
         world.step()
     assert np.count_nonzero(np.concatenate(modes)) > 0  # the predictor wins some segments
+    assert ties > 0  # learned segments with tied groups whose learned block differs were checked
     assert len(set(np.unique(world.store.cls))) == 2 and int(world.store.nb.max()) == 4
     ctx.close()
 
