@@ -54,7 +54,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "batched-full", "hetero"], default="single",
+                    help="single: 1e7 agents, one box; batched: 512 uneven partitions from host-generated states "
+                         "(--agents scales them down); batched-full and hetero: 512 partitions of 1.7e8 agents and "
+                         "256 partitions of 2e8 heterogeneous agents (learned), states advanced on the GPU, one "
+                         "graph per iteration")
     ap.add_argument("--agents", type=float, default=None, help="agents (single) or median per partition (batched)")
     ap.add_argument("--roofline-kernels", default="encode_groups,decode_unpack,serialize_pack,select_count,encode_join",
                     help="kernel families timed with HIP events; the one with the largest time is `roofline`")
@@ -363,13 +367,13 @@ def learned_mode(ctx, native, cfg, dev_states, host_states, args, idx_cap, ser_c
     }
 
 
-def train_predictor(native, synth, log_fn):
+def train_predictor(native, synth, log_fn, which=("random_walk", "persistent")):
     """Predictor trained on the GPU on windows of the 1e5-agent, 13-iteration
     world (200^3 um box, 6 faces), like the exchange's own history."""
     from paper_2509_24063_amd import train
     tctx = native.Context(synth.Schema((4,), (1,)))
     out = {}
-    for name, persistent in (("random_walk", False), ("persistent", True)):
+    for name, persistent in [x for x in (("random_walk", False), ("persistent", True)) if x[0] in which]:
         world = synth.World(synth.config(4, persistent=persistent))
         x, t = train.harvest(tctx, world, iterations=13, cap=2_000_000)
         losses = []
@@ -452,6 +456,9 @@ def main():
     from paper_2509_24063_amd import native, synth
 
     torch.cuda.set_device(0)
+    if args.workload in ("batched-full", "hetero"):
+        print(json.dumps(scale_pass(args, native, synth)), flush=True)
+        return
     if args.migration_only:
         print(json.dumps({"migration": migration_pass(native, synth, args.warmup, args.steps)}), flush=True)
         return
@@ -809,6 +816,162 @@ def migration_pass(native, synth, warmup, steps, agents=1e7):
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "launches": launches,
                      "avg_ms": avg_ms, "algorithmic_bytes_per_launch": kb},
     }
+
+
+def scale_pass(args, native, synth):
+    """A large batched workload with its states advanced on the GPU
+    (synth_device.DeviceWorld): every iteration (select, serialize, encode,
+    decode over all partitions) is one graph replay, timed with events; the
+    population moves on between iterations, outside the timed region.
+    hetero: 80/20 spheres and cylinders with 14 fp64 fields, 0-4 behaviours
+    of 1-7 words, the learned predictor (trained on the GPU on the 1e5-agent
+    world); after each timed iteration the same messages are also encoded in
+    plain mode for the bytes per record.  The receiver decodes against the
+    sender's reference copy (byte-identical) and writes its C' over the
+    consumed messages, so that 2e8 agents fit one GPU; tests/test_gpu_scale.py
+    checks one sampled partition of the same runs against the oracle every
+    iteration."""
+    import numpy as np
+    import torch
+
+    from paper_2509_24063_amd.exchange import sized_pipeline
+    from paper_2509_24063_amd.synth_device import DeviceWorld, partition_sizes
+
+    hetero = args.workload == "hetero"
+    over = {"median": args.agents} if args.agents else {}
+    cfg = synth.config(5 if hetero else 3, **over)
+    iterations = args.warmup + args.steps
+    copy_gbps = copy_peak(args.copy_peak_mib)
+    torch.cuda.empty_cache()
+    t0 = time.time()
+    cap, beh_cap = DeviceWorld.capacity(cfg, iterations + 1)
+    counts, boxes = partition_sizes(cfg)
+    ds = native.DeviceStore.alloc(max(cfg.n_f64), max(cfg.n_i32), boxes, cap, beh_cap)
+    world = DeviceWorld(cfg, ds, log=log)
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    n0, P = world.n, world.P
+    nseg = P * cfg.ndirs
+    log(f"{cfg.name}: {n0} agents in {P} partitions (store for {cap}), {time.time() - t0:.0f}s")
+    pred = None
+    if hetero:
+        blob = train_predictor(native, synth, log, which=("random_walk",))["random_walk"][0]
+    ctx = native.Context(cfg.schema)
+    if hetero:
+        pred = native.Predictor(ctx, blob)
+    pl = sized_pipeline(ctx, ds, cfg.ndirs, cfg.w, cap / n0, pred)
+    pl.capture()
+    torch.cuda.synchronize()
+    log(f"buffers {pl.sizing}; {torch.cuda.memory_allocated() / 1e9:.1f} GB allocated by torch")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    acc = dict(records=0, msg=0, tad=0, plain=0, ms=0.0, agents=0, learned=0, mixed=0, sel=0, ser=0, match=0,
+               enc=0, dec=0)
+    prev_M, prev_S = 32 * nseg, 0
+    for t in range(iterations):
+        n_now = world.n
+        ev[0].record()
+        pl.step(graph=True)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ctx.check(f"iteration {t}")
+        S = int(pl.seg_off[-1].item())
+        M = int(pl.msg_off[-1].item())
+        T = int(pl.enc_off[-1].item())
+        if t >= args.warmup:
+            acc["ms"] += ev[0].elapsed_time(ev[1])
+            acc["records"] += S
+            acc["agents"] += n_now
+            acc["msg"] += M
+            acc["tad"] += T
+            modes = pl.modes[:nseg].cpu().numpy()
+            acc["learned"] += int(np.count_nonzero(modes == 1))
+            acc["mixed"] += int(np.count_nonzero(modes == 2))
+            acc["sel"] += 24 * n_now + 4 * S
+            acc["ser"] += 4 * S + 16 * S + 2 * M
+            acc["match"] += 16 * (S + prev_S)
+            acc["enc"] += M + prev_M + T + M
+            acc["dec"] += T + prev_M + M
+            if hetero:  # the same messages in plain mode (C' is the same either way)
+                p = 1 - pl.r
+                ctx.delta_encode(pl.msgs, pl.msg_off, pl.ref[p], pl.ref_off[p],
+                                 out=(pl.enc, pl.enc_off, pl.ref[pl.last], pl.ref_off[pl.last], pl.modes))
+                ctx.check(f"plain encoding {t}")
+                acc["plain"] += int(pl.enc_off[-1].item())
+        log(f"iteration {t}: {ev[0].elapsed_time(ev[1]):.2f} ms, {n_now} agents, {S} records, {T} encoded bytes")
+        prev_M, prev_S = M, S
+        world.step()
+    K = args.steps
+    # the dominant kernels in one more (eager) iteration, timed with events
+    fams = "encode_groups,decode_unpack,serialize_pack,select_count,encode_join,predict"
+    ctx.time_kernel(fams)
+    pl.step()
+    ktimes = {f: ctx.kernel_time(f) for f in fams.split(",")}
+    ctx.time_kernel(None)
+    ctx.check("instrumented iteration")
+    at = pl.enc_off[:nseg, None] + torch.arange(64, device=pl.enc.device)
+    heads = pl.enc[at.reshape(-1)].cpu().numpy().view(np.uint64).reshape(nseg, 8)
+    one = dict(records=int(pl.seg_off[-1].item()), msg=int(pl.msg_off[-1].item()),
+               W=int(heads[:, 5].sum()), var=int(heads[:, 7].sum()),
+               matched=int((heads[:, 1] >> np.uint64(32)).sum()),
+               groups=int(((heads[:, 5] + np.uint64(63)) // np.uint64(64)).sum()))
+    one["sel"] = 24 * world.n + 4 * one["records"]
+    one["match"] = 16 * (one["records"] + prev_S)
+    rooflines = []
+    for f, (launches, ms) in ktimes.items():
+        key = f + "_learned" if (hetero and f == "encode_groups") else f
+        b = kernel_bytes(key, one)
+        if launches and b == b:
+            rooflines.append(roofline_entry(f, launches, ms, b, copy_gbps, None))
+    rooflines.sort(key=lambda r: -r["avg_ms"])
+    single = [r for r in rooflines if r["kernel"] not in ("encode_join", "predict")]
+    sd = acc["ser"] + acc["match"] + acc["enc"]
+    step_bytes = acc["sel"] + sd + acc["dec"]
+    out = {
+        "metric": METRIC,
+        "value": acc["records"] / (acc["ms"] / 1000.0),
+        "unit": "aura records/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": acc["ms"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded, generated and advanced on the GPU; the paper's BioDynaMo models are not "
+                "available)",
+        "config": {
+            "workload": (f"{P} partitions ({'x'.join(map(str, cfg.grid))} periodic, lognormal sizes, median "
+                         f"{cfg.median:.3g}), {n0:.3g} agents at the start"
+                         + (", 80/20 spheres/cylinders with 14 fp64 fields, 0-4 behaviours of 1-7 words, 2% "
+                            "division, 1% death, learned predictor" if hetero else
+                            ", spheres, 1% division, 0.5% death, plain delta")
+                         + "; one graph replay per iteration (select + serialize + encode + decode)"),
+            "agents_start": n0,
+            "agents_mean_timed": acc["agents"] / K,
+            "partitions": P,
+            "segments": nseg,
+            "records_per_step": acc["records"] / K,
+        },
+        "timed_mode": "graph",
+        "copy_peak_GBps": copy_gbps,
+        "step_algorithmic_GBps": step_bytes / (acc["ms"] / 1000.0) / 1e9,
+        "bytes_per_agent": {"raw_record": acc["msg"] / acc["records"], "delta": acc["tad"] / acc["records"]},
+        "roofline": single[0] if single else None,
+        "rooflines": rooflines,
+        "kernels_us_instrumented_step": {f: 1000.0 * ms for f, (n, ms) in ktimes.items() if n},
+        "buffers": pl.sizing,
+        "device_memory_GB": {"allocated_peak": torch.cuda.max_memory_allocated() / 1e9,
+                             "reserved_peak": torch.cuda.max_memory_reserved() / 1e9},
+    }
+    if hetero:
+        out["bytes_per_agent"]["plain_delta"] = acc["plain"] / acc["records"]
+        out["bytes_per_agent"]["learned_delta"] = acc["tad"] / acc["records"]
+        out["learned_segments"] = acc["learned"] / K
+        out["mixed_segments"] = acc["mixed"] / K
+    pl.close()
+    ctx.close()
+    return out
 
 
 def cpu_model():

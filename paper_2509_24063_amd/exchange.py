@@ -23,14 +23,24 @@ from . import native
 class Pipeline:
     def __init__(self, ctx: native.Context, ds: native.DeviceStore, w: float, ndirs: int, idx_cap: int,
                  msgs_cap: int, pred: native.Predictor | None = None, decode: bool = True, device="cuda",
-                 refresh: int = 1):
+                 refresh: int = 1, shared_rx: bool = False, enc_cap: int | None = None):
+        """shared_rx: the receiver, on the same GPU, decodes against the
+        sender's reference and predictor history (byte-identical to its own
+        copies) and writes its C' over the sender's message buffer, which the
+        encoder has consumed by then: two message buffers and two histories
+        less, for populations that would not fit otherwise (refresh 1 only).
+        enc_cap: capacity of the encoding buffer (default: the worst-case
+        bound)."""
         if refresh < 1:
             raise ValueError("refresh interval must be >= 1")
+        if shared_rx and (refresh != 1 or not decode):
+            raise ValueError("a shared receiver needs refresh 1 and decoding")
         self.ctx, self.ds, self.w, self.ndirs, self.pred = ctx, ds, w, ndirs, pred
         self.refresh = refresh
+        self.shared_rx = shared_rx
         self.nseg = nseg = ds.P * ndirs
         self.idx_cap, self.msgs_cap = idx_cap, msgs_cap
-        self.enc_cap = int(native.lib().ta_delta_bound(nseg, msgs_cap, msgs_cap))
+        self.enc_cap = int(native.lib().ta_delta_bound(nseg, msgs_cap, msgs_cap)) if enc_cap is None else enc_cap
         z8 = lambda n: torch.zeros(max(n, 8), dtype=torch.uint8, device=device)  # noqa: E731
         zo = lambda: torch.zeros(nseg + 1, dtype=torch.int64, device=device)  # noqa: E731
         self.idx = torch.zeros(max(idx_cap, 1), dtype=torch.int32, device=device)
@@ -40,12 +50,17 @@ class Pipeline:
         self.modes = torch.zeros(max(nseg, 1), dtype=torch.uint8, device=device)
         self.ref = [z8(msgs_cap), z8(msgs_cap)]
         self.ref_off = [zo(), zo()]
-        self.rx = [z8(msgs_cap), z8(msgs_cap)] if decode else None
-        self.rx_off = [zo(), zo()] if decode else None
         # predictor history (learned mode only), per reference slot of each side
         hc = idx_cap if pred is not None else 0
         self.hist = [native.History(hc, device), native.History(hc, device)]
-        self.rx_hist = [native.History(hc, device), native.History(hc, device)] if decode else None
+        if shared_rx:
+            self.rx = [self.msgs, self.msgs]
+            self.rx_off = [zo()] * 2
+            self.rx_hist = [native.History(hc, device)] * 2
+        else:
+            self.rx = [z8(msgs_cap), z8(msgs_cap)] if decode else None
+            self.rx_off = [zo(), zo()] if decode else None
+            self.rx_hist = [native.History(hc, device), native.History(hc, device)] if decode else None
         self.decode = decode
         self.reset()
         self.graphs = [None, None]
@@ -53,7 +68,7 @@ class Pipeline:
     def reset(self):
         """Back to the first iteration: empty references, no history."""
         empty, off = native.empty_messages(self.nseg, self.ref[0].device)
-        for bufs, offs in ((self.ref, self.ref_off), (self.rx, self.rx_off)):
+        for bufs, offs in ((self.ref, self.ref_off), (None if self.shared_rx else self.rx, self.rx_off)):
             if bufs is None:
                 continue
             bufs[0][:empty.numel()].copy_(empty)
@@ -70,9 +85,13 @@ class Pipeline:
         p, q = parity, 1 - parity
         ds = self.ds if ds is None else ds
         pred = self.pred
-        rx = dict(rx_ref=self.rx[p], rx_ref_off=self.rx_off[p], rx_out=self.rx[q], rx_out_off=self.rx_off[q],
-                  rx_hist=self.rx_hist[p] if pred else None,
-                  rx_hist_out=self.rx_hist[q] if pred else None) if self.decode else {}
+        if self.shared_rx:
+            rx = dict(rx_ref=self.ref[p], rx_ref_off=self.ref_off[p], rx_out=self.rx[q], rx_out_off=self.rx_off[q],
+                      rx_hist=self.hist[p] if pred else None, rx_hist_out=self.rx_hist[q] if pred else None)
+        else:
+            rx = dict(rx_ref=self.rx[p], rx_ref_off=self.rx_off[p], rx_out=self.rx[q], rx_out_off=self.rx_off[q],
+                      rx_hist=self.rx_hist[p] if pred else None,
+                      rx_hist_out=self.rx_hist[q] if pred else None) if self.decode else {}
         return native.Iteration(ds, self.w, self.ndirs, self.idx, self.seg_off, self.msgs, self.msg_off,
                                 self.ref[p], self.ref_off[p], self.enc, self.enc_off, self.ref[q], self.ref_off[q],
                                 self.modes, pred=pred, hist=self.hist[p] if pred else None,
@@ -134,6 +153,44 @@ def capacities(ctx: native.Context, store, ndirs: int, w: float, slack: float = 
     msgs_cap = ctx.serialize_bound(ds, store.P * ndirs, idx_cap)
     del ds, idx, seg
     return idx_cap, int(msgs_cap)
+
+
+def sized_pipeline(ctx: native.Context, ds: native.DeviceStore, ndirs: int, w: float, growth: float,
+                   pred: native.Predictor | None = None, slack: float = 1.03):
+    """A shared-receiver Pipeline for a large population in a fixed-capacity
+    store, its buffers sized from the present state's selection and message
+    bytes (measured on the device: the serialization is sized without being
+    written) times `growth`, the population's growth until the last
+    iteration."""
+    nseg = ds.P * ndirs
+    dev = ds.uid.device
+    idx = torch.empty(int(0.8 * ds.live) + 4096, dtype=torch.int32, device=dev)
+    seg = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
+    ctx.select_aura(ds, w, ndirs, idx_cap=idx.numel(), out=(idx, seg))
+    ctx.check("selection for sizing")
+    records = int(seg[-1].item())
+    tiny = torch.empty(8, dtype=torch.uint8, device=dev)
+    moff = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
+    st = native.lib().ta_serialize(ctx.h, native.C.byref(ds.agents()), native._p(idx), native._p(seg), nseg,
+                                   idx.numel(), native._p(tiny), 0, native._p(moff), native._stream())
+    if st or ctx.poll() not in (native.OK, native.CAPACITY):
+        raise native.TAError(st or native.INVALID, "serialization for sizing")
+    msg_bytes = int(moff[-1].item())
+    del idx, seg, tiny, moff
+    idx_cap = int(records * growth * slack) + 4096
+    msgs_cap = (int(msg_bytes * growth * slack) + 64 * nseg) // 8 * 8
+    enc_cap = (int(msgs_cap * 1.08) + 64 * nseg) // 8 * 8
+    ctx.reserve(ds.n, nseg, idx_cap, msgs_cap)
+    pl = Pipeline(ctx, ds, w, ndirs, idx_cap, msgs_cap, pred=pred, shared_rx=True, enc_cap=enc_cap)
+    pl.sizing = dict(records=records, msg_bytes=msg_bytes, idx_cap=idx_cap, msgs_cap=msgs_cap, enc_cap=enc_cap)
+    return pl
+
+
+def segment_bytes(buf, off, s0: int, s1: int):
+    """Host bytes of segments [s0, s1) of dense messages or encodings, and
+    their offsets from the first one's start."""
+    o = off[s0:s1 + 1].cpu().numpy()
+    return buf[int(o[0]):int(o[-1])].cpu().numpy(), o - o[0]
 
 
 def split_host(t, off):

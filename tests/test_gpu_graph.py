@@ -213,3 +213,39 @@ def test_tune_and_cache(native, tmp_path):
     ctx.check("after tuning")
     _same(_outputs(pl), want, "tuned")
     ctx.close()
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_shared_receiver_matches_own_copies(native, learned):
+    """A receiver that decodes against the sender's reference and history and
+    writes its C' over the consumed message buffer gives the same C' and
+    history as one with copies of its own, eagerly and from graphs."""
+    from paper_2509_24063_amd.exchange import Pipeline, capacities
+    cfg = synth.config(5, median=400.0, grid=(2, 2, 2), persistent=True)
+    world = synth.World(cfg)
+    ctx = native.Context(cfg.schema)
+    pred = native.Predictor(ctx, copy_last_move_blob()) if learned else None
+    idx_cap, msgs_cap = capacities(ctx, world.store, cfg.ndirs, cfg.w, slack=1.5)
+    cap = int(world.store.n * 1.3)
+    fixed = native.DeviceStore(world.store, cap=cap, beh_cap=int(world.store.beh.size * 1.3) + 64)
+    own = Pipeline(ctx, native.DeviceStore(world.store), cfg.w, cfg.ndirs, idx_cap, msgs_cap, pred=pred)
+    shared = Pipeline(ctx, fixed, cfg.w, cfg.ndirs, idx_cap, msgs_cap, pred=pred, shared_rx=True,
+                      enc_cap=int(msgs_cap * 1.1) + 64 * 208)
+    shared.capture()
+    for it in range(5):
+        print(f"[shared rx] learned={learned} iteration {it}", flush=True)
+        fixed.load(world.store)
+        shared.step(graph=it % 2 == 1)
+        own.step(native.DeviceStore(world.store))
+        ctx.check(f"iteration {it}")
+        a, b = _outputs(shared), _outputs(own)
+        for k in ("eoff", "enc", "noff", "nref", "rxoff", "rx"):
+            assert np.array_equal(a[k], b[k]), f"iteration {it}: {k}"
+        if learned:  # the C' histories (records of C' of every segment)
+            nrec = int(sum(np.frombuffer(b["nref"][o:o + 12].tobytes(), np.uint32)[2] for o in b["noff"][:-1]))
+            x1, x2, xl = shared.rx_hist[0].numpy(nrec)
+            y1, y2, yl = own.rx_hist[own.last].numpy(nrec)
+            assert np.array_equal(x1, y1) and np.array_equal(x2, y2) and np.array_equal(xl, yl), f"history {it}"
+        world.step()
+    shared.close()
+    ctx.close()
