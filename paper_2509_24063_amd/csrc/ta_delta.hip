@@ -287,7 +287,7 @@ __device__ void enc_setup(Common cm, const uint8_t* cur, int64_t cur_len,
     g.rbody = ra + 32 + 8 * ((nr + 1) / 2);
     g.nc = nc;
     g.nr = nr;
-    hs = pow2ceil(2 * (nc + nr));
+    hs = pow2ceil(2 * nr);  // neighbour-count table (learned calls): at most nr cells
     g.hsize = hs;
     g.fold = 0;
     for (int k = 0; k < FOLD_SLOTS; ++k) cm.fold[s * FOLD_SLOTS + k] = 0;
@@ -2143,27 +2143,32 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_build(Common cm, const uint8_t* r
     }
     // Lanes with the same segment and cell add their count with one atomic:
     // neighbouring records mostly share a cell, so a wave has few distinct
-    // ones.  Each round takes the first pending lane's (segment, cell).
+    // ones.  Each round of the loop only finds the lanes of the first pending
+    // lane's (segment, cell); then every such first lane inserts its cell and
+    // adds its count, all at once.
     uint64_t pending = __ballot(v);
+    uint32_t count = 0;
     while (pending) {
       const int leader = __ffsll((unsigned long long)pending) - 1;
       const uint64_t lk = readlane64(key, leader);
       const int64_t ls = (int64_t)readlane64((uint64_t)s, leader);
       const uint64_t same = __ballot(v && key == lk && s == ls);
-      if (lane_id() == leader) {
-        const Seg& sg = cm.seg[ls];
-        const uint64_t H = sg.hsize;
-        uint64_t h = mix64(lk) & (H - 1);
-        for (uint64_t probe = 0; probe < H; ++probe) {
-          const unsigned long long prev = atomicCAS(&tab[cm.hpre[ls] + h].key, 0ull, (unsigned long long)lk);
-          if (prev == 0ull || prev == (unsigned long long)lk) {
-            atomicAdd(&tab[cm.hpre[ls] + h].ci, (uint32_t)__popcll(same));
-            break;
-          }
-          h = (h + 1) & (H - 1);
-        }
-      }
+      if (lane_id() == leader) count = (uint32_t)__popcll(same);
       pending &= ~same;
+    }
+    if (count) {
+      const Seg& sg = cm.seg[s];
+      const uint64_t H = sg.hsize;
+      Entry* t = tab + cm.hpre[s];
+      uint64_t h = mix64(key) & (H - 1);
+      for (uint64_t probe = 0; probe < H; ++probe) {
+        const unsigned long long prev = atomicCAS(&t[h].key, 0ull, (unsigned long long)key);
+        if (prev == 0ull || prev == (unsigned long long)key) {
+          atomicAdd(&t[h].ci, count);
+          break;
+        }
+        h = (h + 1) & (H - 1);
+      }
     }
   }
 }
@@ -2209,9 +2214,11 @@ __global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
   __shared__ PredW s_w;
   __shared__ int32_t s_in[WAVES][WAVE][12];
   __shared__ int32_t s_q[WAVES][WAVE][4];
+  __shared__ uint8_t s_h[WAVES][16][64];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   load_weights(&s_w, a.pw);
+  const MlpOps ops = mlp_ops(s_w);
   const int64_t M = cm.meta[5];
   const int l = lane_id(), wv = wave_id();
   const int64_t chunks = (M + WAVE - 1) / WAVE;
@@ -2273,7 +2280,7 @@ __global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
     const uint64_t need = __ballot(on);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if ((need >> (16 * r)) & 0xFFFFull) mlp16(s_w, s_in[wv] + 16 * r, s_q[wv] + 16 * r);
+      if ((need >> (16 * r)) & 0xFFFFull) mlp16(s_w, ops, s_in[wv] + 16 * r, s_h[wv], s_q[wv] + 16 * r);
     wave_sync();
     if (k < M) {
       a.pred_on[k] = on ? 1 : 0;

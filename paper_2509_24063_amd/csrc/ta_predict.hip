@@ -18,7 +18,9 @@ __global__ __launch_bounds__(BLOCK) void k_pred_eval(const PredW* w, const int32
   __shared__ PredW s_w;
   __shared__ int32_t s_in[WAVES][16][12];
   __shared__ int32_t s_q[WAVES][16][4];
+  __shared__ uint8_t s_h[WAVES][16][64];
   load_weights(&s_w, w);
+  const MlpOps ops = mlp_ops(s_w);
   const int l = lane_id(), wv = wave_id();
   const int64_t chunks = (n + 15) / 16;
   for (int64_t ch = (int64_t)blockIdx.x * WAVES + wv; ch < chunks; ch += (int64_t)gridDim.x * WAVES) {
@@ -28,7 +30,7 @@ __global__ __launch_bounds__(BLOCK) void k_pred_eval(const PredW* w, const int32
       s_in[wv][e / 12][e % 12] = row < n ? in[row * 12 + e % 12] : 0;
     }
     wave_sync();
-    mlp16(s_w, s_in[wv], s_q[wv]);
+    mlp16(s_w, ops, s_in[wv], s_h[wv], s_q[wv]);
     wave_sync();
     const int64_t row = r0 + l / 4;
     if (l < 64 && row < n) q[row * 4 + (l & 3)] = s_q[wv][l / 4][l & 3];

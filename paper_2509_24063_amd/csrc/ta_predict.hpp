@@ -37,70 +37,111 @@ __device__ inline int32_t quantise(double v) {
   return (int32_t)rint(t);
 }
 
-// One wave: rows 0..15 of s_in (12 inputs each) -> s_q (4 outputs each).
-// MFMA operand layout (16x16x32, int8): lane l holds row l%16 of A and
-// column l%16 of B for k = 8*(l/16) .. +7; the result holds rows
-// 4*(l/16) .. +3 of column l%16.
-__device__ inline void mlp16(const PredW& W, const int32_t (*s_in)[12], int32_t (*s_q)[4]) {
+// The matrix-core layout of v_mfma_i32_16x16x32_i8 (A 16x32, B 32x16, D
+// 16x16, int8 operands, int32 accumulation): lane l holds row l%16 of A and
+// column l%16 of B for k = 8*(l/16) .. +7 (eight bytes, lowest k in the low
+// byte); D holds rows 4*(l/16) .. +3 of column l%16.
+__device__ inline v4i mfma_i8(int64_t a, int64_t b, v4i c) {
+  return __builtin_amdgcn_mfma_i32_16x16x32_i8(a, b, c, 0, 0, 0);
+}
+
+// The B operands of the three layers for this lane, read once from the
+// weights: layer 1 (W1 transposed, k = input, padded from 12 to 32 with
+// zeros), four blocks of 16 hidden units; layer 2 (W2 transposed), four
+// blocks of 16 outputs times two halves of k; layer 3 (W3 transposed, four
+// output columns of 16, the others zero), two halves of k.
+struct MlpOps {
+  int64_t b1[4];
+  int64_t b2[4][2];
+  int64_t b3[2];
+};
+__device__ inline MlpOps mlp_ops(const PredW& W) {
   const int l = lane_id();
   const int rc = l & 15, qd = l >> 4;
-  // layer 1 for row rc: hidden units 8qd..8qd+7 and 32+8qd..32+8qd+7
-  int64_t a[2];
+  MlpOps o;
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    uint64_t packed = 0;
+  for (int ob = 0; ob < 4; ++ob) {
+    uint64_t v = 0;
+    const int j = 16 * ob + rc;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int j = 32 * half + 8 * qd + t;
-      int32_t acc = W.b1[j];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc += (int32_t)W.w1[j * 12 + c] * s_in[rc][c];
-      const int32_t h = clampi(requant(acc, W.r1), 0, 127);
-      packed |= (uint64_t)(uint8_t)h << (8 * t);
+      const int k = 8 * qd + t;
+      if (k < 12) v |= (uint64_t)(uint8_t)W.w1[j * 12 + k] << (8 * t);
     }
-    a[half] = (int64_t)packed;
+    o.b1[ob] = (int64_t)v;
+#pragma unroll
+    for (int half = 0; half < 2; ++half)
+      o.b2[ob][half] = *reinterpret_cast<const int64_t*>(&W.w2[j * 64 + 32 * half + 8 * qd]);
   }
-  // layer 2 on the matrix cores: 4 blocks of 16 outputs, K = 64 in two steps
-  v4i acc[4];
+#pragma unroll
+  for (int half = 0; half < 2; ++half)
+    o.b3[half] = rc < 4 ? *reinterpret_cast<const int64_t*>(&W.w3[rc * 64 + 32 * half + 8 * qd]) : 0;
+  return o;
+}
+
+// One wave: rows 0..15 of s_in (12 inputs each) -> s_q (4 outputs each), all
+// three layers on the matrix cores.  Layer 1's inputs are int16 (moves,
+// counts) or u16 (behaviour count, class) values v in [-32768, 65535]; each
+// is split exactly into three int8 planes, v = a*2^14 + b*2^7 + c with c, b
+// in [0,127] and a in [-2,3], and W1 v = 2^14 W1 a + 2^7 W1 b + W1 c, one
+// MFMA per plane, every sum exact in int32.  Between layers the activations
+// go through s_h (16 rows x 64 bytes of LDS, this wave's) from the output
+// layout into the input layout.
+__device__ inline void mlp16(const PredW& W, const MlpOps& ops, const int32_t (*s_in)[12], uint8_t (*s_h)[64],
+                             int32_t (*s_q)[4]) {
+  const int l = lane_id();
+  const int rc = l & 15, qd = l >> 4;
+  // layer 1 A operands: row rc, inputs 8qd .. 8qd+7 (k >= 12: zero)
+  uint64_t pa = 0, pb = 0, pc = 0;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int k = 8 * qd + t;
+    const int32_t v = k < 12 ? s_in[rc][k < 12 ? k : 0] : 0;
+    pc |= (uint64_t)(uint32_t)(v & 127) << (8 * t);
+    pb |= (uint64_t)(uint32_t)((v >> 7) & 127) << (8 * t);
+    pa |= (uint64_t)(uint8_t)(int8_t)(v >> 14) << (8 * t);
+  }
+  // layer 1: 64 hidden units in four blocks; rows 4qd .. 4qd+3, unit 16ob + rc
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
-    const int n = 16 * ob + rc;  // output neuron of this lane's column
-    const int32_t b = W.b2[n];
-    acc[ob] = v4i{b, b, b, b};
-    const int64_t b0 = *reinterpret_cast<const int64_t*>(&W.w2[n * 64 + 8 * qd]);
-    const int64_t b1 = *reinterpret_cast<const int64_t*>(&W.w2[n * 64 + 32 + 8 * qd]);
-    acc[ob] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a[0], b0, acc[ob], 0, 0, 0);
-    acc[ob] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a[1], b1, acc[ob], 0, 0, 0);
-  }
-  // layer 3: partial sums over this lane's 4 columns for its 4 rows
-  int32_t part[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int o = 0; o < 4; ++o) part[r][o] = 0;
-#pragma unroll
-  for (int ob = 0; ob < 4; ++ob) {
+    const v4i z = v4i{0, 0, 0, 0};
+    const v4i da = mfma_i8((int64_t)pa, ops.b1[ob], z);
+    const v4i db = mfma_i8((int64_t)pb, ops.b1[ob], z);
+    const v4i dc = mfma_i8((int64_t)pc, ops.b1[ob], z);
     const int j = 16 * ob + rc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int32_t h2 = clampi(requant(acc[ob][r], W.r2), 0, 127);
-#pragma unroll
-      for (int o = 0; o < 4; ++o) part[r][o] += (int32_t)W.w3[o * 64 + j] * h2;
+      const int32_t acc = W.b1[j] + da[r] * 16384 + db[r] * 128 + dc[r];
+      s_h[4 * qd + r][j] = (uint8_t)clampi(requant(acc, W.r1), 0, 127);
     }
   }
-  // sum over the 16 lanes holding the same rows
+  wave_sync();
+  int64_t a[2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int half = 0; half < 2; ++half) a[half] = *reinterpret_cast<const int64_t*>(&s_h[rc][32 * half + 8 * qd]);
+  wave_sync();  // every lane has its layer 1 operands before s_h is rewritten
+  // layer 2: 4 blocks of 16 outputs, K = 64 in two steps
 #pragma unroll
-    for (int o = 0; o < 4; ++o)
+  for (int ob = 0; ob < 4; ++ob) {
+    const int n = 16 * ob + rc;
+    const int32_t b = W.b2[n];
+    v4i acc = v4i{b, b, b, b};
+    acc = mfma_i8(a[0], ops.b2[ob][0], acc);
+    acc = mfma_i8(a[1], ops.b2[ob][1], acc);
 #pragma unroll
-      for (int d = 1; d < 16; d <<= 1) part[r][o] += __shfl_xor(part[r][o], d, WAVE);
-  if (rc == 0) {
+    for (int r = 0; r < 4; ++r) s_h[4 * qd + r][n] = (uint8_t)clampi(requant(acc[r], W.r2), 0, 127);
+  }
+  wave_sync();
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+  for (int half = 0; half < 2; ++half) a[half] = *reinterpret_cast<const int64_t*>(&s_h[rc][32 * half + 8 * qd]);
+  wave_sync();
+  // layer 3: output o = column rc < 4
+  v4i o = v4i{0, 0, 0, 0};
+  o = mfma_i8(a[0], ops.b3[0], o);
+  o = mfma_i8(a[1], ops.b3[1], o);
+  if (rc < 4) {
 #pragma unroll
-      for (int o = 0; o < 4; ++o)
-        s_q[4 * qd + r][o] = clampi(requant(part[r][o] + W.b3[o], W.r3), -(1 << 24), 1 << 24);
+    for (int r = 0; r < 4; ++r) s_q[4 * qd + r][rc] = clampi(requant(o[r] + W.b3[rc], W.r3), -(1 << 24), 1 << 24);
   }
 }
 

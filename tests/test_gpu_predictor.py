@@ -41,6 +41,10 @@ def test_mlp_matches_oracle(native):
         b = _random_blob(rng, r)
         x = rng.integers(-32768, 32768, (1000, 12)).astype(np.int32)
         x[:, 8:] = rng.integers(0, 128, (1000, 4))
+        # the full input ranges: moves at the int16 limits, behaviour count and
+        # class up to the u16 limit
+        x[:100, :8] = rng.choice([-32768, -32767, -16385, -16384, -1, 0, 16383, 16384, 32767], (100, 8))
+        x[:200, 9:11] = rng.choice([0, 127, 128, 16383, 16384, 32767, 32768, 65535], (200, 2))
         print(f"[mlp] shifts {r}", flush=True)
         pred = native.Predictor(ctx, b)
         q = host(ctx.predictor_eval(pred, torch.from_numpy(x).cuda()))
