@@ -12,8 +12,9 @@
 //   k_scan       exclusive scan of record sizes (words) over all records
 //   k_ser_sizes  message sizes; k_scan_cols turns them into offsets
 //   k_ser_heads  message headers
-//   k_ser_pack   one thread per record: fields gathered from the store,
-//                record and offset-table entry written
+//   k_ser_pack   one thread per record: fields gathered from the store into
+//                LDS (runs of records that fit together), offset-table
+//                entry written; the records leave LDS in coalesced stores
 #include "ta_internal.hpp"
 #include "ta_msg.hpp"
 #include "ta_scratch.hpp"
@@ -170,9 +171,10 @@ constexpr int PACK_CAP = 1024;  // record words one wave stages in LDS
 constexpr int PACK_CHUNK = 8;   // payload words a lane gathers at a time
 
 // One lane per record: it gathers the agent's fields and writes its offset
-// table entry.  When the wave's 64 records belong to one message and fit in
-// LDS, the records are assembled there and written with coalesced stores;
-// otherwise each lane writes its own record.
+// table entry.  The wave's records are assembled in LDS in batches -- runs
+// of consecutive records of one message that fit PACK_CAP words together --
+// and each batch is written with coalesced stores; a single record larger
+// than PACK_CAP words is written by its lane directly.
 __global__ __launch_bounds__(BLOCK) void k_ser_pack(PackArgs a, SerScratch sc) {
   __shared__ uint64_t s_buf[WAVES][PACK_CAP];
   const int64_t R = sc.meta[0];
@@ -186,37 +188,38 @@ __global__ __launch_bounds__(BLOCK) void k_ser_pack(PackArgs a, SerScratch sc) {
     const int64_t re = base + WAVE < R ? base + WAVE : R;
     const uint64_t last = (uint64_t)(re - 1);
     const int64_t s = wave_seg(seg_off, a.nseg, (uint64_t)(r < R ? r : R - 1), (uint64_t)base, last);
-    const int64_t s_first = __shfl(s, 0, WAVE), s_last = __shfl(s, (int)(re - 1 - base), WAVE);
-    const uint64_t w0 = sc.wpre[base], w1 = sc.wpre[re];
-    const bool staged = s_first == s_last && w1 - w0 <= PACK_CAP;
-    uint64_t* dst = nullptr;
-    uint64_t rel = 0, words = 0;
+    uint64_t wr = 0, words = 0, uid = 0, nb = 0;
+    uint64_t* rec = nullptr;  // the record's place in its message
     int32_t ag = 0;
     uint32_t c = 0, F = 0, I = 0, IW = 0;
+    int64_t boff = 0;
     if (r < R) {
       // everything read per agent and per message, before the first store
       ag = a.idx[r];
       c = a.cls[ag];
-      const uint64_t uid = a.uid[ag], nb = a.nb[ag];
-      const int64_t boff = a.beh_off[ag];
+      uid = a.uid[ag];
+      nb = a.nb[ag];
+      boff = a.beh_off[ag];
       const int64_t first = a.seg_off[s];
       const uint64_t n = (uint64_t)(a.seg_off[s + 1] - first);
-      const uint64_t wr = sc.wpre[r], ws = sc.wpre[first];
+      wr = sc.wpre[r];
+      const uint64_t ws = sc.wpre[first];
       words = sc.wpre[r + 1] - wr;
       uint8_t* m = a.out + a.msg_off[s];
       F = a.nf[c];
       I = a.ni[c];
       IW = (I + 1) / 2;
       *reinterpret_cast<uint32_t*>(m + 32 + 4 * (r - first)) = (uint32_t)(wr - ws);
-      rel = wr - w0;
-      dst = staged ? buf + rel : reinterpret_cast<uint64_t*>(m + 32 + 8 * ((n + 1) / 2) + 8 * (wr - ws));
+      rec = reinterpret_cast<uint64_t*>(m + 32 + 8 * ((n + 1) / 2) + 8 * (wr - ws));
+    }
+    // The record's words into dst: header, F fields, IW attribute pairs,
+    // behaviour words.  The 64-bit words (fields and behaviour words) are
+    // gathered PACK_CHUNK at a time, then the attribute pairs; every load of
+    // a chunk is issued before its stores and takes its address by
+    // selection, not behind a branch (an unused one reads the agent's uid).
+    auto gather = [&](uint64_t* dst) {
       dst[0] = uid;
       dst[1] = (uint64_t)c | (nb << 16) | (words << 32);
-      // payload: F fields, IW attribute pairs, then behaviour words.  The
-      // 64-bit words (fields and behaviour words) are gathered PACK_CHUNK at a
-      // time, then the attribute pairs; every load of a chunk is issued
-      // before its stores and takes its address by selection, not behind a
-      // branch (an unused one reads the agent's uid instead).
       const uint64_t* bsrc = reinterpret_cast<const uint64_t*>(a.beh + boff);
       const uint64_t* dummy = a.uid + ag;
       const uint32_t Q = (uint32_t)(words - 2 - IW);  // fields + behaviour words
@@ -250,16 +253,30 @@ __global__ __launch_bounds__(BLOCK) void k_ser_pack(PackArgs a, SerScratch sc) {
           if (j0 + j < IW) dst[2 + F + j0 + j] = (uint64_t)lo[j] | ((uint64_t)(q + 1 < I ? hi[j] : 0u) << 32);
         }
       }
-    }
-    if (staged) {
+    };
+    // batches: from the first pending lane, the run of lanes in its message
+    // whose records end within PACK_CAP words of its record's start (the
+    // records of a message are consecutive in the words' order)
+    uint64_t pending = __ballot(r < R);
+    while (pending) {
+      const int lead = __ffsll((unsigned long long)pending) - 1;
+      const uint64_t bs = readlane64(wr, lead);
+      const int64_t bseg = (int64_t)readlane64((uint64_t)s, lead);
+      const bool mine = ((pending >> l) & 1) && s == bseg && wr + words - bs <= PACK_CAP;
+      const uint64_t batch = __ballot(mine);
+      if (!batch) {  // the lead record alone is larger than the LDS buffer
+        if (l == lead) gather(rec);
+        pending &= pending - 1;
+        continue;
+      }
+      if (mine) gather(buf + (wr - bs));
       wave_sync();
-      // the wave's records are one contiguous stretch of its message
-      const int64_t first = a.seg_off[s_first];
-      const uint64_t n = (uint64_t)(a.seg_off[s_first + 1] - first);
-      uint64_t* out = reinterpret_cast<uint64_t*>(a.out + a.msg_off[s_first] + 32 + 8 * ((n + 1) / 2)) +
-                      (w0 - sc.wpre[first]);
-      for (uint64_t p = l; p < w1 - w0; p += WAVE) out[p] = buf[p];
-      wave_sync();
+      const int hi_lane = 63 - __clzll((long long)batch);
+      const uint64_t be = readlane64(wr + words, hi_lane);
+      uint64_t* out = reinterpret_cast<uint64_t*>(readlane64(reinterpret_cast<uint64_t>(rec), lead));
+      for (uint64_t p = l; p < be - bs; p += WAVE) out[p] = buf[p];
+      wave_sync();  // the buffer is refilled by the next batch
+      pending &= ~batch;
     }
   }
 }
