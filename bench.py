@@ -116,6 +116,9 @@ def eager_pass(ctx, native, cfg, dev_states, host_states, warmup, idx_cap, ser_c
     rxoffs = [torch.empty(nseg + 1, **i64) for _ in range(2)]
     hc = idx_cap if pred is not None else 0
     hist = [native.History(hc) for _ in range(2)]
+    # record keys beside every message set (as the pipelines keep them)
+    zk = lambda: torch.zeros(2 * idx_cap, dtype=torch.int64, device=dev)  # noqa: E731
+    mkeys, rkeys, xkeys = zk(), [zk(), zk()], [zk(), zk()]
     rxhist = [native.History(hc) for _ in range(2)]
     modes = torch.empty(nseg, **u8)
     e0, e1 = native.empty_messages(nseg)
@@ -139,12 +142,13 @@ def eager_pass(ctx, native, cfg, dev_states, host_states, warmup, idx_cap, ser_c
         ev[0].record()
         ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=idx_cap, out=(idx, seg))
         ev[1].record()
-        ctx.serialize(ds, idx, seg, idx_cap=idx_cap, out=(buf, moff))
+        ctx.serialize(ds, idx, seg, idx_cap=idx_cap, out=(buf, moff), keys=mkeys)
         ev[2].record()
         ctx.delta_encode(buf, moff, refs[cur_ref], roffs[cur_ref], out=(enc, eoff, refs[nxt], roffs[nxt], modes),
-                         **lp)
+                         keys=(mkeys, rkeys[cur_ref], rkeys[nxt]), **lp)
         ev[3].record()
-        ctx.delta_decode(enc, eoff, rx[cur_ref], rxoffs[cur_ref], out=(rx[nxt], rxoffs[nxt]), **lr)
+        ctx.delta_decode(enc, eoff, rx[cur_ref], rxoffs[cur_ref], out=(rx[nxt], rxoffs[nxt]),
+                         keys=(xkeys[cur_ref], xkeys[nxt]), **lr)
         ev[4].record()
         torch.cuda.synchronize()
         mo = moff.cpu().numpy()

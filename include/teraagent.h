@@ -197,16 +197,37 @@ ta_status ta_select_migrants(ta_ctx *ctx, const ta_agents *agents, int32_t P, co
                              const double *boxes, int32_t *idx_out, int64_t idx_cap, int64_t *seg_off_out,
                              void *stream);
 
+/* Record keys: the uid and header word of every record of a message set,
+ * in record order (message 0's records, then message 1's, ...): key[2i] =
+ * uid, key[2i+1] = header word of record i.  Device memory, 16-byte aligned,
+ * 16 bytes per record.  They are optional companions of a message set: the
+ * library writes them beside the messages it writes (ta_serialize, the C'
+ * of ta_delta_encode and ta_delta_decode), and the delta calls that are
+ * given the keys of their inputs read each record's uid and header from
+ * them instead of from the record (16 bytes instead of the record's cache
+ * lines); offsets and sizes are still checked against the messages.
+ * Whoever passes keys in vouches that they describe the messages: after a
+ * message has been changed where a uid or header word lives, its keys must
+ * be rewritten or left out. */
+typedef struct {
+  const uint64_t *cur;     /* keys of the current messages (ta_delta_encode), nullable */
+  const uint64_t *ref;     /* keys of the reference messages, nullable */
+  uint64_t *out;           /* nullable: receives the keys of C' (newref / out) */
+  int64_t out_cap;         /* records `out` holds; more C' records -> TA_ERR_CAPACITY */
+} ta_keys;
+
 /* TA IO serialization (Sec. 2.2.1, "Serialization"): one TAM1 message per
  * segment.  idx / seg_off (device) as produced by ta_select_aura, nseg
  * segments, at most idx_cap records in total.  Messages are packed densely
  * into out (device, out_cap bytes); msg_off_out (device int64[nseg+1])
  * receives their byte offsets.  A class id >= n_classes or a behaviour range
  * that is not a multiple of 8 bytes -> TA_ERR_INVALID; messages larger than
- * out_cap -> TA_ERR_CAPACITY (msg_off_out still holds the needed sizes). */
+ * out_cap -> TA_ERR_CAPACITY (msg_off_out still holds the needed sizes).
+ * keys_out (nullable; keys_cap >= idx_cap records) receives the records'
+ * keys (see ta_keys). */
 ta_status ta_serialize(ta_ctx *ctx, const ta_agents *agents, const int32_t *idx, const int64_t *seg_off,
                        int64_t nseg, int64_t idx_cap, uint8_t *out, int64_t out_cap, int64_t *msg_off_out,
-                       void *stream);
+                       uint64_t *keys_out, int64_t keys_cap, void *stream);
 
 /* Upper bound of the serialized size of nrec records of at most max_words
  * words each, in nseg messages. */
@@ -355,13 +376,15 @@ typedef struct {
  * Outputs: enc (device, enc_cap bytes) with the TAD1 encodings packed densely
  * at enc_off (device int64[nseg+1]); newref (device, newref_cap bytes) with
  * the C' messages at newref_off (device int64[nseg+1]); modes (nullable,
- * device uint8[nseg]) the mode chosen per segment (0, 1 or 2).  Invalid or duplicate
- * input -> TA_ERR_INVALID; too small outputs -> TA_ERR_CAPACITY. */
+ * device uint8[nseg]) the mode chosen per segment (0, 1 or 2).  keys
+ * (nullable): keys of cur and ref to read, and a buffer for the keys of C'.
+ * Invalid or duplicate input -> TA_ERR_INVALID; too small outputs ->
+ * TA_ERR_CAPACITY. */
 ta_status ta_delta_encode(ta_ctx *ctx, int64_t nseg, const uint8_t *cur, int64_t cur_len, const int64_t *cur_off,
                           const uint8_t *ref, int64_t ref_len, const int64_t *ref_off, const ta_predictor *pred,
                           const ta_history *hist_in, ta_history *hist_out, uint8_t *enc, int64_t enc_cap,
                           int64_t *enc_off, uint8_t *newref, int64_t newref_cap, int64_t *newref_off,
-                          uint8_t *modes, void *stream);
+                          uint8_t *modes, const ta_keys *keys, void *stream);
 
 /* The difference operator (Sec. 2.3 leaves it open) of this context's
  * later ta_delta_encode and ta_delta_decode calls: 0 XOR (the default), 1
@@ -384,11 +407,13 @@ int64_t ta_delta_bound(int64_t nseg, int64_t cur_len, int64_t ref_len);
  * out (device, out_cap bytes) at out_off (device int64[nseg+1]); hist_out
  * (nullable) as for encoding.  Damaged encodings (mode above 2 included) ->
  * TA_ERR_CORRUPT; encodings made against another reference ->
- * TA_ERR_REF_MISMATCH; too small output -> TA_ERR_CAPACITY. */
+ * TA_ERR_REF_MISMATCH; too small output -> TA_ERR_CAPACITY.  keys
+ * (nullable; cur unused): keys of ref to read, and a buffer for the keys of
+ * C'. */
 ta_status ta_delta_decode(ta_ctx *ctx, int64_t nseg, const uint8_t *enc, int64_t enc_len, const int64_t *enc_off,
                           const uint8_t *ref, int64_t ref_len, const int64_t *ref_off, const ta_predictor *pred,
                           const ta_history *hist_in, ta_history *hist_out, uint8_t *out, int64_t out_cap,
-                          int64_t *out_off, void *stream);
+                          int64_t *out_off, const ta_keys *keys, void *stream);
 
 /* Timing of kernel families for measurement: name is a comma-separated list
  * of family names (NULL or "" disables timing); while it is set, every
@@ -455,6 +480,15 @@ typedef struct {
   uint8_t *rx_out;
   int64_t rx_out_cap;
   int64_t *rx_out_off;
+  /* record keys (nullable each, see ta_keys): of msgs (written by
+   * ta_serialize, read by ta_delta_encode), of ref, of newref (written), of
+   * rx_ref, of rx_out (written); every written one holds keys_cap records */
+  uint64_t *msg_keys;
+  const uint64_t *ref_keys;
+  uint64_t *newref_keys;
+  const uint64_t *rx_ref_keys;
+  uint64_t *rx_out_keys;
+  int64_t keys_cap;
 } ta_iteration;
 
 /* Enqueue the iteration's calls in order; the first host-side error is

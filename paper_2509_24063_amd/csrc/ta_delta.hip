@@ -336,6 +336,8 @@ struct JoinArgs {
   int32_t* m;
   uint8_t* cflag;
   Entry* tab;        // open-addressing tables of buckets too large for LDS
+  const uint64_t* ckeys;  // nullable: uid and header word of every current record (2 words each)
+  const uint64_t* rkeys;  // nullable: the same for the reference
 };
 
 // A bucketed join item: uid and item index, moved as one 16-byte access
@@ -386,6 +388,8 @@ __global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a, const Seg* __r
     const uint32_t n = (uint32_t)(jt.isC ? g.nc : g.nr);
     const uint64_t rw = jt.isC ? g.rwc : g.rwr;
     const uint64_t gbase = jt.isC ? cpre[jt.s] : Ct + rpre[jt.s];
+    const uint64_t* keys = jt.isC ? a.ckeys : a.rkeys;
+    const uint64_t kbase = jt.isC ? cpre[jt.s] : rpre[jt.s];
     uint64_t fold = 0;
     bool bad = false;
     // JC_U items per thread and pass: their records' loads are issued
@@ -399,8 +403,18 @@ __global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a, const Seg* __r
         const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
         loc[u] = tam1_locate(msg, n, rw, (uint32_t)(i < jt.i1 ? i : jt.i0));
       }
+      if (keys) {  // (uniform) the record words from the compact key array
 #pragma unroll
-      for (int u = 0; u < JC_U; ++u) tam1_words(msg, n, loc[u], &uid[u], &hdr[u]);
+        for (int u = 0; u < JC_U; ++u) {
+          const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
+          const ulonglong2 kv = *reinterpret_cast<const ulonglong2*>(keys + 2 * (kbase + (i < jt.i1 ? i : jt.i0)));
+          uid[u] = kv.x;
+          hdr[u] = kv.y;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < JC_U; ++u) tam1_words(msg, n, loc[u], &uid[u], &hdr[u]);
+      }
       __builtin_amdgcn_sched_barrier(0);  // keep the checks below every record load
 #pragma unroll
       for (int u = 0; u < JC_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
@@ -782,7 +796,8 @@ __device__ inline void map_groups(const Common& cm, int64_t s, uint64_t q0, uint
 __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
                                                     const int32_t* m, const uint64_t* rscan, const uint32_t* rwords,
                                                     MDir* mdir, uint64_t* crw, uint64_t* mstart, uint8_t* newref,
-                                                    uint32_t* gseg, uint32_t* gfirst) {
+                                                    uint32_t* gseg, uint32_t* gfirst, const uint64_t* juid,
+                                                    const uint64_t* jhdr, uint64_t* okeys, uint64_t okeys_cap) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
@@ -833,6 +848,13 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
         mdir[k] = e;
       }
       if (crw) crw[k] = (uint64_t)coff[u] | ((uint64_t)roff[u] << 32);
+      if (okeys) {  // C' record k + (new records of earlier segments): the slot's uid and header
+        const uint64_t Ct = (uint64_t)cm.meta[0], o = k + cm.npre[sx];
+        if (o < okeys_cap)
+          *reinterpret_cast<ulonglong2*>(okeys + 2 * o) = ulonglong2{juid[Ct + (uint64_t)g], jhdr[Ct + (uint64_t)g]};
+        else
+          fail(cm.status, ERR_CAPACITY);
+      }
       mstart[k] = d;
       *reinterpret_cast<uint32_t*>(newref + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
       map_groups(cm, sx, d - sg.dbase, rwv[u], gseg, gfirst, k);
@@ -907,6 +929,7 @@ struct NewTab {
   uint64_t src[WAVE];
   uint64_t dst1[WAVE];
   uint64_t dst2[WAVE];
+  uint64_t kidx[WAVE];  // decoder: the record's index among all C' records (for its key)
 };
 
 #ifndef TA_UNPACK_PG
@@ -1387,7 +1410,8 @@ __device__ inline void copy_tab(const NewTab& t, int n, const uint64_t* src, uin
 // words).
 __global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t* cscan, const uint32_t* nlist,
                                                        const uint32_t* cwords, const uint8_t* cur, uint8_t* enc,
-                                                       uint8_t* newref) {
+                                                       uint8_t* newref, const uint64_t* juid, const uint64_t* jhdr,
+                                                       uint64_t* okeys, uint64_t okeys_cap) {
   __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Nn = (int64_t)(cscan[cm.meta[0]] >> PK);
@@ -1412,6 +1436,11 @@ __global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t
       *reinterpret_cast<uint32_t*>(ns + 4 * r) = (uint32_t)words;
       if (r == g.n_new - 1 && (g.n_new & 1)) *reinterpret_cast<uint32_t*>(ns + 4 * (r + 1)) = 0;
       *reinterpret_cast<uint32_t*>(newref + g.oref + 32 + 4 * (g.n_match + r)) = (uint32_t)(g.W + qs);
+      if (okeys) {  // C' record: after the segment's matched ones
+        const uint64_t o = g.mbase + g.nbase + g.n_match + r;
+        if (o < okeys_cap) *reinterpret_cast<ulonglong2*>(okeys + 2 * o) = ulonglong2{juid[gc], jhdr[gc]};
+        else fail(cm.status, ERR_CAPACITY);
+      }
       t.src[l] = (g.cbody + 8 * (uint64_t)o) / 8;
       t.dst1[l] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
       t.dst2[l] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
@@ -1568,7 +1597,7 @@ __global__ __launch_bounds__(1024) void k_dec_setup1(Common cm, const uint8_t* e
 __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* enc, const uint8_t* ref,
                                                       uint32_t* rwords, uint8_t* rmatch,
                                                       const Seg* __restrict__ segs,
-                                                      const uint64_t* __restrict__ rpre) {
+                                                      const uint64_t* __restrict__ rpre, const uint64_t* rkeys) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
@@ -1600,8 +1629,17 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
         jv[u] = j;
         sv[u] = su;
       }
+      if (rkeys) {
 #pragma unroll
-      for (int u = 0; u < RS_U; ++u) tam1_words(m, (uint32_t)sg.nr, loc[u], &uid[u], &hdr[u]);
+        for (int u = 0; u < RS_U; ++u) {
+          const ulonglong2 kv = *reinterpret_cast<const ulonglong2*>(rkeys + 2 * (r0 + jv[u]));
+          uid[u] = kv.x;
+          hdr[u] = kv.y;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < RS_U; ++u) tam1_words(m, (uint32_t)sg.nr, loc[u], &uid[u], &hdr[u]);
+      }
       __builtin_amdgcn_sched_barrier(0);  // keep the checks below every record load
 #pragma unroll
       for (int u = 0; u < RS_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
@@ -1620,7 +1658,13 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
 #pragma unroll
       for (int u = 0; u < RS_U; ++u) {
         const Seg& sg = segs[sv[u]];
-        tam1_words(ref + sg.rmsg, (uint32_t)sg.nr, loc[u], &uid[u], &hdr[u]);
+        if (rkeys) {
+          const ulonglong2 kv = *reinterpret_cast<const ulonglong2*>(rkeys + 2 * (rpre[sv[u]] + jv[u]));
+          uid[u] = kv.x;
+          hdr[u] = kv.y;
+        } else {
+          tam1_words(ref + sg.rmsg, (uint32_t)sg.nr, loc[u], &uid[u], &hdr[u]);
+        }
       }
 #pragma unroll
       for (int u = 0; u < RS_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
@@ -1772,7 +1816,8 @@ __global__ __launch_bounds__(BLOCK) void k_dec_seg2(Common cm, const uint64_t* r
 __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* ref, const uint8_t* rmatch,
                                                     const uint64_t* rscan, const uint32_t* rwords, MDir* mdir,
                                                     uint64_t* mstart, uint8_t* out, uint32_t* gseg,
-                                                    uint32_t* gfirst, uint32_t* mrw) {
+                                                    uint32_t* gfirst, uint32_t* mrw, const uint64_t* rkeys,
+                                                    uint64_t* okeys, uint64_t okeys_cap) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
@@ -1816,6 +1861,13 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
       }
       mstart[k] = d;
       mrw[k] = roff[u];  // word offset in the reference's record area
+      if (okeys) {  // C' record k + (new records of earlier segments): the slot's uid and header
+        const uint64_t* src = rkeys ? rkeys + 2 * g
+                                    : reinterpret_cast<const uint64_t*>(ref + sg.rbody + 8 * (uint64_t)roff[u]);
+        const uint64_t o = k + cm.npre[sx];
+        if (o < okeys_cap) *reinterpret_cast<ulonglong2*>(okeys + 2 * o) = ulonglong2{src[0], src[1]};
+        else fail(cm.status, ERR_CAPACITY);
+      }
       *reinterpret_cast<uint32_t*>(out + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
       map_groups(cm, sx, d - sg.dbase, rwv[u], gseg, gfirst, k);
     }
@@ -2033,7 +2085,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
 // lane-parallel.  A new record's uid must be non-zero and its header must
 // give the size the table announced.
 __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t* nscan, const uint8_t* enc,
-                                                       uint8_t* out) {
+                                                       uint8_t* out, uint64_t* okeys, uint64_t okeys_cap) {
   __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Nn = cm.meta[6];
@@ -2055,15 +2107,16 @@ __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t
       t.src[l] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
       t.dst1[l] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
       t.dst2[l] = nscan[r + 1] - nscan[r];  // size
+      t.kidx[l] = g.mbase + g.n_match + (uint64_t)r;  // the record's index among all C' records
       *reinterpret_cast<uint32_t*>(out + g.oref + 32 + 4 * (g.n_match + (uint64_t)r - cm.npre[s])) =
           (uint32_t)(g.W + qs);
     }
     if (l == 0) t.q[n] = nscan[rb + n] - nscan[rb];
     wave_sync();
     const uint64_t tot = t.q[n];
-    bool bad = false;
+    bool bad = false, cap = false;
     for (uint64_t q0 = l; q0 < tot; q0 += NC_U * WAVE) {  // NC_U words per lane in flight
-      uint64_t v[NC_U], d[NC_U], w[NC_U], sz[NC_U];
+      uint64_t v[NC_U], d[NC_U], w[NC_U], sz[NC_U], ki[NC_U];
 #pragma unroll
       for (int j = 0; j < NC_U; ++j) {
         const uint64_t q = q0 + (uint64_t)j * WAVE < tot ? q0 + (uint64_t)j * WAVE : tot - 1;
@@ -2072,6 +2125,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t
         v[j] = e64[t.src[i] + w[j]];
         d[j] = t.dst1[i] + w[j];
         sz[j] = t.dst2[i];
+        ki[j] = t.kidx[i];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -2079,9 +2133,14 @@ __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t
         if (q0 + (uint64_t)j * WAVE < tot) {
           if ((w[j] == 0 && v[j] == 0) || (w[j] == 1 && (v[j] >> 32) != sz[j])) bad = true;
           o64[d[j]] = v[j];
+          if (okeys && w[j] < 2) {  // the record's uid and header word
+            if (ki[j] < okeys_cap) okeys[2 * ki[j] + w[j]] = v[j];
+            else cap = true;
+          }
         }
     }
     if (__ballot(bad) && l == 0) fail(cm.status, ERR_CORRUPT);
+    if (__ballot(cap) && l == 0) fail(cm.status, ERR_CAPACITY);
     wave_sync();
   }
 }
@@ -2438,6 +2497,12 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   return m;
 }
 
+// Key arrays are 16-byte aligned (one uid and header word pair per record).
+inline bool keys_ok(const ta_keys* k) {
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  return al(k->cur) && al(k->ref) && al(k->out) && k->out_cap >= 0 && (k->out || k->out_cap == 0);
+}
+
 // Records are >= 20 bytes (two words and an offset), so the byte sizes
 // bound the record counts; a record capacity (rec_cap > 0) tightens them and
 // the column scans flag larger inputs as capacity errors.
@@ -2499,11 +2564,15 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                                      const int64_t* ref_off, const ta_predictor* pred, const ta_history* hist_in,
                                      ta_history* hist_out, uint8_t* enc, int64_t enc_cap, int64_t* enc_off,
                                      uint8_t* newref, int64_t newref_cap, int64_t* newref_off, uint8_t* modes,
-                                     void* stream) {
+                                     const ta_keys* keys, void* stream) {
   if (!c || nseg < 0 || !cur_off || !ref_off || !enc_off || !newref_off || cur_len < 0 || ref_len < 0 ||
       enc_cap < 0 || newref_cap < 0 || (cur_len && !cur) || (ref_len && !ref) || (enc_cap && !enc) ||
-      (newref_cap && !newref) || (pred && !hist_in))
+      (newref_cap && !newref) || (pred && !hist_in) || (keys && !keys_ok(keys)))
     return TA_ERR_INVALID;
+  const uint64_t* ckeys = keys ? keys->cur : nullptr;
+  const uint64_t* rkeys = keys ? keys->ref : nullptr;
+  uint64_t* okeys = keys ? keys->out : nullptr;
+  const uint64_t okeys_cap = keys && keys->out ? (uint64_t)keys->out_cap : 0;
   hipStream_t s = (hipStream_t)stream;
   if (nseg == 0) {
     ta_status z = zero_i64(enc_off, 1, s);
@@ -2541,7 +2610,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     }
     {
       Timed tm(c, "encode_join", s);
-      JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag, m.tab};
+      JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag, m.tab,
+                ckeys, rkeys};
       k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre);
       k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
                                                                        lookback(c, 0));
@@ -2565,8 +2635,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     }
     k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords,
                                                                 pred || hist_out ? m.mdir : nullptr, m.crw,
-                                                                m.mstart, newref, m.gseg,
-                                   m.gfirst);
+                                                                m.mstart, newref, m.gseg, m.gfirst, m.juid, m.jhdr,
+                                                                okeys, okeys_cap);
   }
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
@@ -2604,7 +2674,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     }
   }
   k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.bm, m.gsz, m.gch, m.gex, enc, enc_cap, enc_off, modes);
-  k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.nlist, m.cwords, cur, enc, newref);
+  k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.nlist, m.cwords, cur, enc, newref, m.juid,
+                                                          m.jhdr, okeys, okeys_cap);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
                 hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};
@@ -2618,10 +2689,13 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                                      const int64_t* enc_off, const uint8_t* ref, int64_t ref_len,
                                      const int64_t* ref_off, const ta_predictor* pred, const ta_history* hist_in,
                                      ta_history* hist_out, uint8_t* out, int64_t out_cap, int64_t* out_off,
-                                     void* stream) {
+                                     const ta_keys* keys, void* stream) {
   if (!c || nseg < 0 || !enc_off || !ref_off || !out_off || enc_len < 0 || ref_len < 0 || out_cap < 0 ||
-      (enc_len && !enc) || (ref_len && !ref) || (out_cap && !out) || (pred && !hist_in))
+      (enc_len && !enc) || (ref_len && !ref) || (out_cap && !out) || (pred && !hist_in) || (keys && !keys_ok(keys)))
     return TA_ERR_INVALID;
+  const uint64_t* rkeys = keys ? keys->ref : nullptr;
+  uint64_t* okeys = keys ? keys->out : nullptr;
+  const uint64_t okeys_cap = keys && keys->out ? (uint64_t)keys->out_cap : 0;
   hipStream_t s = (hipStream_t)stream;
   if (nseg == 0) return zero_i64(out_off, 1, s);
   use_family(c, FAM_DECODE);
@@ -2648,7 +2722,8 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
       k_scan_cols<<<6, 1024, 0, s>>>(cs);
     }
   }
-  k_dec_rslots<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre);
+  k_dec_rslots<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre,
+                                                                rkeys);
   k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
                                                                      m.rscan, lookback(c, 0));
   k_scan<DNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, b.C, m.cscan,
@@ -2658,7 +2733,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
   k_dec_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords,
                                                               pred || hist_out ? m.mdir : nullptr, m.mstart, out, m.gseg, m.gfirst,
-                                 m.mrw);
+                                 m.mrw, rkeys, okeys, okeys_cap);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
     Timed tm(c, "predict", s);
@@ -2684,7 +2759,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
     else
       k_dec_unpack<0><<<gu, BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst, ua.enc);
   }
-  k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out);
+  k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out, okeys, okeys_cap);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
                 hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};

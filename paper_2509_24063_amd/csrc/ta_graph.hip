@@ -37,16 +37,20 @@ ta_status run(ta_ctx* c, const ta_iteration* it, void* stream) {
   if (st) return st;
   const int64_t nseg = (int64_t)it->P * it->ndirs;
   st = ta_serialize(c, it->agents, it->idx, it->seg_off, nseg, it->idx_cap, it->msgs, it->msgs_cap, it->msg_off,
-                    stream);
+                    it->msg_keys, it->msg_keys ? it->keys_cap : 0, stream);
   if (st) return st;
+  const ta_keys tk{it->msg_keys, it->ref_keys, it->newref_keys, it->newref_keys ? it->keys_cap : 0};
+  const bool tx_keys = it->msg_keys || it->ref_keys || it->newref_keys;
   st = ta_delta_encode(c, nseg, it->msgs, it->msgs_cap, it->msg_off, it->ref, it->ref_len, it->ref_off, it->pred,
                        it->hist_in, it->hist_out, it->enc, it->enc_cap, it->enc_off, it->newref, it->newref_cap,
-                       it->newref_off, it->modes, stream);
+                       it->newref_off, it->modes, tx_keys ? &tk : nullptr, stream);
   if (st) return st;
   if (!it->rx_out) return TA_OK;
+  const ta_keys rk{nullptr, it->rx_ref_keys, it->rx_out_keys, it->rx_out_keys ? it->keys_cap : 0};
+  const bool rx_keys = it->rx_ref_keys || it->rx_out_keys;
   return ta_delta_decode(c, nseg, it->enc, it->enc_cap, it->enc_off, it->rx_ref, it->rx_ref_len, it->rx_ref_off,
                          it->pred, it->rx_hist_in, it->rx_hist_out, it->rx_out, it->rx_out_cap, it->rx_out_off,
-                         stream);
+                         rx_keys ? &rk : nullptr, stream);
 }
 
 // Size the scratch memory for every call of the iteration (so that a

@@ -165,6 +165,7 @@ struct PackArgs {
   int64_t nseg;
   const int64_t* msg_off;
   uint8_t* out;
+  uint64_t* keys;  // nullable: uid and header word of every record (record order)
 };
 
 constexpr int PACK_CAP = 1024;  // record words one wave stages in LDS
@@ -211,6 +212,8 @@ __global__ __launch_bounds__(BLOCK) void k_ser_pack(PackArgs a, SerScratch sc) {
       IW = (I + 1) / 2;
       *reinterpret_cast<uint32_t*>(m + 32 + 4 * (r - first)) = (uint32_t)(wr - ws);
       rec = reinterpret_cast<uint64_t*>(m + 32 + 8 * ((n + 1) / 2) + 8 * (wr - ws));
+      if (a.keys)
+        *reinterpret_cast<ulonglong2*>(a.keys + 2 * r) = ulonglong2{uid, (uint64_t)c | (nb << 16) | (words << 32)};
     }
     // The record's words into dst: header, F fields, IW attribute pairs,
     // behaviour words.  The 64-bit words (fields and behaviour words) are
@@ -302,9 +305,10 @@ size_t serialize_scratch(int64_t nseg, int64_t idx_cap, int64_t* tiles) {
 
 extern "C" ta_status ta_serialize(ta_ctx* c, const ta_agents* ag, const int32_t* idx, const int64_t* seg_off,
                                   int64_t nseg, int64_t idx_cap, uint8_t* out, int64_t out_cap, int64_t* msg_off,
-                                  void* stream) {
+                                  uint64_t* keys_out, int64_t keys_cap, void* stream) {
   if (!c || !ag || nseg < 0 || !seg_off || !msg_off || idx_cap < 0 || (idx_cap > 0 && !idx) || out_cap < 0 ||
-      (out_cap > 0 && !out) || ag->n < 0 || ag->f64_stride < ag->n || ag->i32_stride < ag->n)
+      (out_cap > 0 && !out) || ag->n < 0 || ag->f64_stride < ag->n || ag->i32_stride < ag->n ||
+      (keys_out && (keys_cap < idx_cap || ((uintptr_t)keys_out & 15))))
     return TA_ERR_INVALID;
   if (nseg == 0) return zero_i64(msg_off, 1, (hipStream_t)stream);
   use_family(c, FAM_SERIALIZE);
@@ -338,7 +342,7 @@ extern "C" ta_status ta_serialize(ta_ctx* c, const ta_agents* ag, const int32_t*
   {
     Timed tm(c, "serialize_pack", s);
     PackArgs pa{ag->uid, ag->cls, ag->nb, ag->f64, ag->f64_stride, ag->i32, ag->i32_stride, ag->beh_off,
-                ag->beh, c->d_nf, c->d_ni, idx, seg_off, nseg, msg_off, out};
+                ag->beh, c->d_nf, c->d_ni, idx, seg_off, nseg, msg_off, out, keys_out};
     // words: at most idx_cap records of at most 2 + 64 + 32 + behaviour words; the
     // grid only needs to be large enough to fill the chip
     k_ser_pack<<<c->grid, BLOCK, 0, s>>>(pa, sc);

@@ -23,14 +23,16 @@ from . import native
 class Pipeline:
     def __init__(self, ctx: native.Context, ds: native.DeviceStore, w: float, ndirs: int, idx_cap: int,
                  msgs_cap: int, pred: native.Predictor | None = None, decode: bool = True, device="cuda",
-                 refresh: int = 1, shared_rx: bool = False, enc_cap: int | None = None):
+                 refresh: int = 1, shared_rx: bool = False, enc_cap: int | None = None, keys: bool = True):
         """shared_rx: the receiver, on the same GPU, decodes against the
         sender's reference and predictor history (byte-identical to its own
         copies) and writes its C' over the sender's message buffer, which the
         encoder has consumed by then: two message buffers and two histories
         less, for populations that would not fit otherwise (refresh 1 only).
         enc_cap: capacity of the encoding buffer (default: the worst-case
-        bound)."""
+        bound).  keys: keep the record keys (uid and header word per record)
+        of every message set beside it, so that the delta calls read them
+        instead of the records."""
         if refresh < 1:
             raise ValueError("refresh interval must be >= 1")
         if shared_rx and (refresh != 1 or not decode):
@@ -53,14 +55,19 @@ class Pipeline:
         # predictor history (learned mode only), per reference slot of each side
         hc = idx_cap if pred is not None else 0
         self.hist = [native.History(hc, device), native.History(hc, device)]
+        zk = lambda: torch.zeros(2 * max(idx_cap, 1), dtype=torch.int64, device=device) if keys else None  # noqa
+        self.msg_keys = zk()
+        self.ref_keys = [zk(), zk()]
         if shared_rx:
             self.rx = [self.msgs, self.msgs]
             self.rx_off = [zo()] * 2
             self.rx_hist = [native.History(hc, device)] * 2
+            self.rx_keys = [self.msg_keys] * 2
         else:
             self.rx = [z8(msgs_cap), z8(msgs_cap)] if decode else None
             self.rx_off = [zo(), zo()] if decode else None
             self.rx_hist = [native.History(hc, device), native.History(hc, device)] if decode else None
+            self.rx_keys = [zk(), zk()] if decode else [None, None]
         self.decode = decode
         self.reset()
         self.graphs = [None, None]
@@ -85,6 +92,11 @@ class Pipeline:
         p, q = parity, 1 - parity
         ds = self.ds if ds is None else ds
         pred = self.pred
+        keys = None
+        if self.msg_keys is not None:
+            keys = dict(msg=self.msg_keys, ref=self.ref_keys[p], newref=self.ref_keys[q])
+            if self.decode:
+                keys.update(rx_ref=self.ref_keys[p] if self.shared_rx else self.rx_keys[p], rx_out=self.rx_keys[q])
         if self.shared_rx:
             rx = dict(rx_ref=self.ref[p], rx_ref_off=self.ref_off[p], rx_out=self.rx[q], rx_out_off=self.rx_off[q],
                       rx_hist=self.hist[p] if pred else None, rx_hist_out=self.rx_hist[q] if pred else None)
@@ -95,7 +107,7 @@ class Pipeline:
         return native.Iteration(ds, self.w, self.ndirs, self.idx, self.seg_off, self.msgs, self.msg_off,
                                 self.ref[p], self.ref_off[p], self.enc, self.enc_off, self.ref[q], self.ref_off[q],
                                 self.modes, pred=pred, hist=self.hist[p] if pred else None,
-                                hist_out=self.hist[q] if pred else None, **rx)
+                                hist_out=self.hist[q] if pred else None, keys=keys, **rx)
 
     def capture(self, stream=None):
         """Capture the two parities' iterations as graphs (store: self.ds)."""
@@ -172,7 +184,7 @@ def sized_pipeline(ctx: native.Context, ds: native.DeviceStore, ndirs: int, w: f
     tiny = torch.empty(8, dtype=torch.uint8, device=dev)
     moff = torch.empty(nseg + 1, dtype=torch.int64, device=dev)
     st = native.lib().ta_serialize(ctx.h, native.C.byref(ds.agents()), native._p(idx), native._p(seg), nseg,
-                                   idx.numel(), native._p(tiny), 0, native._p(moff), native._stream())
+                                   idx.numel(), native._p(tiny), 0, native._p(moff), None, 0, native._stream())
     if st or ctx.poll() not in (native.OK, native.CAPACITY):
         raise native.TAError(st or native.INVALID, "serialization for sizing")
     msg_bytes = int(moff[-1].item())
@@ -221,7 +233,7 @@ class OverlapPipeline:
     serialization stream, so freeing the store early is safe too."""
 
     def __init__(self, schema, ds: native.DeviceStore, w: float, ndirs: int, idx_cap: int, msgs_cap: int,
-                 device="cuda"):
+                 device="cuda", keys: bool = True):
         self.ser, self.tx, self.rxc = native.Context(schema), native.Context(schema), native.Context(schema)
         self.s_ser, self.s_enc, self.s_dec = (torch.cuda.Stream(device=device) for _ in range(3))
         self.w, self.ndirs, self.ds = w, ndirs, ds
@@ -237,6 +249,8 @@ class OverlapPipeline:
         self.enc, self.enc_off = [z8(self.enc_cap), z8(self.enc_cap)], [zo(), zo()]
         self.ref, self.ref_off = [z8(msgs_cap), z8(msgs_cap)], [zo(), zo()]
         self.rx, self.rx_off = [z8(msgs_cap), z8(msgs_cap)], [zo(), zo()]
+        zk = lambda: torch.zeros(2 * max(idx_cap, 1), dtype=torch.int64, device=device) if keys else None  # noqa
+        self.msg_keys, self.ref_keys, self.rx_keys = [zk(), zk()], [zk(), zk()], [zk(), zk()]
         self.ev_ser = [torch.cuda.Event(), torch.cuda.Event()]  # messages t % 2 written
         self.ev_enc = [torch.cuda.Event(), torch.cuda.Event()]  # messages read, encoding t % 2 written
         self.ev_dec = [torch.cuda.Event(), torch.cuda.Event()]  # encoding t % 2 read
@@ -267,7 +281,7 @@ class OverlapPipeline:
                 self.s_ser.wait_event(self.ev_enc[m])
             self.ser.select_aura(ds, self.w, self.ndirs, idx_cap=self.idx_cap, out=(self.idx[m], self.seg_off[m]))
             self.ser.serialize(ds, self.idx[m], self.seg_off[m], idx_cap=self.idx_cap,
-                               out=(self.msgs[m], self.msg_off[m]))
+                               out=(self.msgs[m], self.msg_off[m]), keys=self.msg_keys[m])
             self.ev_ser[m].record(self.s_ser)
             for x in ds.tensors():
                 x.record_stream(self.s_ser)
@@ -277,12 +291,15 @@ class OverlapPipeline:
             if t >= 2:
                 self.s_enc.wait_event(self.ev_dec[m])
             self.tx.delta_encode(self.msgs[m], self.msg_off[m], self.ref[p], self.ref_off[p],
-                                 out=(self.enc[m], self.enc_off[m], self.ref[q], self.ref_off[q], self.modes))
+                                 out=(self.enc[m], self.enc_off[m], self.ref[q], self.ref_off[q], self.modes),
+                                 keys=(self.msg_keys[m], self.ref_keys[p], self.ref_keys[q])
+                                 if self.msg_keys[m] is not None else None)
             self.ev_enc[m].record(self.s_enc)
         with torch.cuda.stream(self.s_dec):
             self.s_dec.wait_event(self.ev_enc[m])
             self.rxc.delta_decode(self.enc[m], self.enc_off[m], self.rx[p], self.rx_off[p],
-                                  out=(self.rx[q], self.rx_off[q]))
+                                  out=(self.rx[q], self.rx_off[q]),
+                                  keys=(self.rx_keys[p], self.rx_keys[q]) if self.rx_keys[p] is not None else None)
             self.ev_dec[m].record(self.s_dec)
         self.t += 1
 

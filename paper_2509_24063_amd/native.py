@@ -44,6 +44,10 @@ class ViewT(C.Structure):
     _fields_ = [("n", C.c_int64), ("rec_words", C.c_int64), ("off", C.c_void_p), ("records", C.c_void_p)]
 
 
+class KeysT(C.Structure):
+    _fields_ = [("cur", C.c_void_p), ("ref", C.c_void_p), ("out", C.c_void_p), ("out_cap", C.c_int64)]
+
+
 class HistT(C.Structure):
     _fields_ = [("h1", C.c_void_p), ("h2", C.c_void_p), ("hlen", C.c_void_p), ("cap", C.c_int64)]
 
@@ -58,7 +62,9 @@ class IterationT(C.Structure):
                 ("newref_off", C.c_void_p), ("modes", C.c_void_p), ("rx_ref", C.c_void_p),
                 ("rx_ref_len", C.c_int64), ("rx_ref_off", C.c_void_p), ("rx_hist_in", C.c_void_p),
                 ("rx_hist_out", C.c_void_p), ("rx_out", C.c_void_p), ("rx_out_cap", C.c_int64),
-                ("rx_out_off", C.c_void_p)]
+                ("rx_out_off", C.c_void_p), ("msg_keys", C.c_void_p), ("ref_keys", C.c_void_p),
+                ("newref_keys", C.c_void_p), ("rx_ref_keys", C.c_void_p), ("rx_out_keys", C.c_void_p),
+                ("keys_cap", C.c_int64)]
 
 
 _lib = None
@@ -82,7 +88,7 @@ def lib():
                                        vp, vp, vp]
         L.ta_view_grow.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, i64, vp, vp]
         L.ta_view_compact.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
-        L.ta_serialize.argtypes = [vp, C.POINTER(Agents), vp, vp, i64, i64, vp, i64, vp, vp]
+        L.ta_serialize.argtypes = [vp, C.POINTER(Agents), vp, vp, i64, i64, vp, i64, vp, vp, i64, vp]
         L.ta_serialize_bound.argtypes = [i64, i64, i64]
         L.ta_serialize_bound.restype = i64
         L.ta_view.argtypes = [vp, i64, vp, C.POINTER(ViewT), vp]
@@ -91,11 +97,11 @@ def lib():
         L.ta_predictor_free.argtypes = [vp]
         L.ta_predictor_free.restype = None
         L.ta_delta_encode.argtypes = [vp, i64, vp, i64, vp, vp, i64, vp, vp, C.POINTER(HistT), C.POINTER(HistT),
-                                      vp, i64, vp, vp, i64, vp, vp, vp]
+                                      vp, i64, vp, vp, i64, vp, vp, C.POINTER(KeysT), vp]
         L.ta_delta_bound.argtypes = [i64, i64, i64]
         L.ta_delta_bound.restype = i64
         L.ta_delta_decode.argtypes = [vp, i64, vp, i64, vp, vp, i64, vp, vp, C.POINTER(HistT), C.POINTER(HistT),
-                                      vp, i64, vp, vp]
+                                      vp, i64, vp, C.POINTER(KeysT), vp]
         L.ta_predictor_eval.argtypes = [vp, vp, vp, vp, i64, vp]
         L.ta_time_kernel.argtypes = [vp, C.c_char_p]
         L.ta_kernel_time.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -134,6 +140,10 @@ def _p(t):
     if t is None:
         return None
     return C.c_void_p(t.data_ptr()) if t.numel() else None
+
+
+def _keys(cur, ref, out):
+    return KeysT(_p(cur), _p(ref), _p(out), out.numel() // 2 if out is not None else 0)
 
 
 def _stream():
@@ -377,7 +387,8 @@ class Context:
         return int(lib().ta_serialize_bound(nseg, idx_cap, words))
 
     def serialize(self, ds: DeviceStore, idx, seg_off, idx_cap: int | None = None, out_cap: int | None = None,
-                  out=None):
+                  out=None, keys=None):
+        """keys (optional): device int64 [>= 2 idx_cap] receiving the records' keys."""
         nseg = seg_off.numel() - 1
         if idx_cap is None:
             idx_cap = idx.numel()
@@ -390,11 +401,14 @@ class Context:
             buf, msg_off = out
             out_cap = buf.numel()
         _check(lib().ta_serialize(self.h, C.byref(ds.agents()), _p(idx), _p(seg_off), nseg, idx_cap, _p(buf),
-                                  out_cap, _p(msg_off), _stream()), "ta_serialize")
+                                  out_cap, _p(msg_off), _p(keys), keys.numel() // 2 if keys is not None else 0,
+                                  _stream()), "ta_serialize")
         return buf, msg_off
 
     def delta_encode(self, cur, cur_off, ref, ref_off, pred: Predictor | None = None, hist: History | None = None,
-                     hist_out: History | None = None, out=None, enc_cap=None):
+                     hist_out: History | None = None, out=None, enc_cap=None, keys=None):
+        """keys (optional): (cur keys, ref keys, C' keys out), each a device
+        int64 tensor or None."""
         nseg = cur_off.numel() - 1
         dev = cur.device
         if out is None:
@@ -409,15 +423,18 @@ class Context:
             enc, enc_off, newref, newref_off, modes = out
         hs = hist.struct() if hist is not None else None
         ho = hist_out.struct() if hist_out is not None else None
+        ks = _keys(*keys) if keys is not None else None
         _check(lib().ta_delta_encode(self.h, nseg, _p(cur), cur.numel(), _p(cur_off), _p(ref), ref.numel(),
                                      _p(ref_off), pred.h if pred is not None else None,
                                      C.byref(hs) if hs is not None else None, C.byref(ho) if ho is not None else None,
                                      _p(enc), enc.numel(), _p(enc_off), _p(newref), newref.numel(), _p(newref_off),
-                                     _p(modes), _stream()), "ta_delta_encode")
+                                     _p(modes), C.byref(ks) if ks is not None else None, _stream()),
+               "ta_delta_encode")
         return enc, enc_off, newref, newref_off, modes
 
     def delta_decode(self, enc, enc_off, ref, ref_off, pred: Predictor | None = None, hist: History | None = None,
-                     hist_out: History | None = None, out=None, out_cap=None):
+                     hist_out: History | None = None, out=None, out_cap=None, keys=None):
+        """keys (optional): (ref keys, C' keys out), each a device int64 tensor or None."""
         nseg = enc_off.numel() - 1
         dev = enc.device
         if out is None:
@@ -429,10 +446,12 @@ class Context:
             buf, off = out
         hs = hist.struct() if hist is not None else None
         ho = hist_out.struct() if hist_out is not None else None
+        ks = _keys(None, *keys) if keys is not None else None
         _check(lib().ta_delta_decode(self.h, nseg, _p(enc), enc.numel(), _p(enc_off), _p(ref), ref.numel(),
                                      _p(ref_off), pred.h if pred is not None else None,
                                      C.byref(hs) if hs is not None else None, C.byref(ho) if ho is not None else None,
-                                     _p(buf), buf.numel(), _p(off), _stream()), "ta_delta_decode")
+                                     _p(buf), buf.numel(), _p(off), C.byref(ks) if ks is not None else None,
+                                     _stream()), "ta_delta_decode")
         return buf, off
 
     def predictor_eval(self, pred: Predictor, inputs):
@@ -564,9 +583,14 @@ class Iteration:
     def __init__(self, ds: DeviceStore, w: float, ndirs: int, idx, seg_off, msgs, msg_off, ref, ref_off, enc,
                  enc_off, newref, newref_off, modes, pred: Predictor | None = None, hist: History | None = None,
                  hist_out: History | None = None, rx_ref=None, rx_ref_off=None, rx_hist: History | None = None,
-                 rx_hist_out: History | None = None, rx_out=None, rx_out_off=None):
+                 rx_hist_out: History | None = None, rx_out=None, rx_out_off=None, keys=None):
+        """keys (optional): dict of record-key tensors msg, ref, newref, rx_ref,
+        rx_out (any may be None), each holding `cap` records."""
         self._keep = [ds, idx, seg_off, msgs, msg_off, ref, ref_off, enc, enc_off, newref, newref_off, modes, pred,
-                      hist, hist_out, rx_ref, rx_ref_off, rx_hist, rx_hist_out, rx_out, rx_out_off]
+                      hist, hist_out, rx_ref, rx_ref_off, rx_hist, rx_hist_out, rx_out, rx_out_off, keys]
+        k = keys or {}
+        kcap = min([t.numel() // 2 for n, t in k.items() if t is not None and n in ("msg", "newref", "rx_out")],
+                   default=0)
         self._agents = ds.agents()
         hs = [h.struct() if h is not None else None for h in (hist, hist_out, rx_hist, rx_hist_out)]
         self._hs = hs
@@ -577,7 +601,8 @@ class Iteration:
             ref.numel(), _p(ref_off), ptr(hs[0]), ptr(hs[1]), _p(enc), enc.numel(), _p(enc_off), _p(newref),
             newref.numel(), _p(newref_off), _p(modes), _p(rx_ref), rx_ref.numel() if rx_ref is not None else 0,
             _p(rx_ref_off), ptr(hs[2]), ptr(hs[3]), _p(rx_out), rx_out.numel() if rx_out is not None else 0,
-            _p(rx_out_off))
+            _p(rx_out_off), _p(k.get("msg")), _p(k.get("ref")), _p(k.get("newref")), _p(k.get("rx_ref")),
+            _p(k.get("rx_out")), kcap)
 
 
 class Graph:

@@ -385,3 +385,62 @@ def test_join_bucket_overflow_falls_back(native, shuffled):
     assert np.array_equal(host(enc, host(eoff)), oenc)
     assert np.array_equal(host(nref, host(noff)), onref)
     ctx.close()
+
+
+def _keys_of(buf, off):
+    """(uid, header word) of every record of dense messages, in record order."""
+    from tests.specparse import parse_tam1
+    out = []
+    for s in range(len(off) - 1):
+        for r in parse_tam1(buf[off[s]:off[s + 1]].tobytes()):
+            out += [r[0], r[1]]
+    return np.array(out, np.uint64)
+
+
+def test_record_keys(native):
+    """Serialization writes every record's uid and header word beside the
+    messages; encoding and decoding that read the keys of their inputs (and
+    write those of C') give the oracle's encodings and C', and every key
+    array written equals the records' own words."""
+    import torch
+    cfg = synth.config(3, median=300.0, grid=(2, 2, 2))
+    world = synth.World(cfg)
+    ctx = native.Context(cfg.schema)
+    nseg = world.store.P * cfg.ndirs
+    orc = OracleSide(nseg)
+    ref, roff = native.empty_messages(nseg)
+    rx, rxoff = ref, roff
+    cap = 26 * int(world.store.n * 1.2)
+    z = lambda: torch.zeros(2 * cap, dtype=torch.int64, device="cuda")  # noqa: E731
+    ref_keys, rx_keys = z(), z()
+    for it in range(4):
+        print(f"[keys] iteration {it}", flush=True)
+        ds = native.DeviceStore(world.store)
+        idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=cap)
+        mk, nk, dk = z(), z(), z()
+        buf, moff = ctx.serialize(ds, idx, seg, keys=mk)
+        enc, eoff, nref, noff, _ = ctx.delta_encode(buf, moff, ref, roff, keys=(mk, ref_keys, nk))
+        dec, doff = ctx.delta_decode(enc, eoff, rx, rxoff, keys=(rx_keys, dk))
+        ctx.check(f"iteration {it}")
+        o = orc.step(world.store, cfg)
+        assert np.array_equal(host(enc, host(eoff)), o["enc"]), it
+        assert np.array_equal(host(nref, host(noff)), o["nref"]), it
+        assert np.array_equal(host(dec, host(doff)), o["nref"]), it
+        S = int(host(seg)[-1])
+        assert np.array_equal(host(mk)[: 2 * S].view(np.uint64), _keys_of(o["buf"], o["moff"])), it
+        want = _keys_of(o["nref"], o["noff"])
+        assert np.array_equal(host(nk)[: want.size].view(np.uint64), want), it
+        assert np.array_equal(host(dk)[: want.size].view(np.uint64), want), it
+        ref, roff, ref_keys = nref[: int(host(noff)[-1])].clone(), noff.clone(), nk
+        rx, rxoff, rx_keys = dec[: int(host(doff)[-1])].clone(), doff.clone(), dk
+        world.step()
+    # a key buffer too small for C' is a capacity error, nothing written past it
+    ds = native.DeviceStore(world.store)
+    idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=cap)
+    mk = z()
+    buf, moff = ctx.serialize(ds, idx, seg, keys=mk)
+    small = torch.zeros(2 * 10 + 2, dtype=torch.int64, device="cuda")
+    ctx.delta_encode(buf, moff, ref, roff, keys=(mk, ref_keys, small[:20]))
+    assert ctx.poll() == native.CAPACITY
+    assert int(small[20].item()) == 0 and int(small[21].item()) == 0
+    ctx.close()
