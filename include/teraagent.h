@@ -372,7 +372,8 @@ typedef struct {
  * of the residual takes the learned X when that makes its block strictly
  * smaller; a segment where no group does is plain (mode 0), one where every
  * group with a different size does is learned (mode 1), else mixed (mode 2);
- * hist_in (slots flattened in segment order, device) must then be given.  hist_out (nullable) receives the history of C'.
+ * hist_in (slots flattened in segment order, device) must then be given.  hist_out (nullable) receives the history of C';
+ * its arrays must not overlap those of hist_in (else TA_ERR_INVALID).
  * Outputs: enc (device, enc_cap bytes) with the TAD1 encodings packed densely
  * at enc_off (device int64[nseg+1]); newref (device, newref_cap bytes) with
  * the C' messages at newref_off (device int64[nseg+1]); modes (nullable,

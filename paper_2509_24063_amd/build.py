@@ -18,8 +18,12 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libteraagent.so")
 ARCH = os.environ.get("TA_OFFLOAD_ARCH", "gfx950")
 
+# -amdgpu-mfma-vgpr-form: matrix-core results in ordinary vector registers
+# (gfx950 has one register file), so no accumulator-register moves follow
+# each MFMA of the predictor
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
-         "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _compile(src: str) -> str:

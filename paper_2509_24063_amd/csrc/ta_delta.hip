@@ -2150,13 +2150,14 @@ __global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t
 // Learned predictor inside the exchange (both sides evaluate it identically
 // from the reference and the per-slot history).
 
-// Cell of a reference record from its words 2..4 (x, y, z): floor(v / cell)
-// per axis, packed in 21 bits each; false when not finite or out of range.
-__device__ inline bool cell_key(const uint64_t* rec, double cell, uint64_t* key) {
+// Cell of a reference record from its words 2..4 (x, y, z at x[0..2]):
+// floor(v / cell) per axis, packed in 21 bits each; false when not finite or
+// out of range.
+__device__ inline bool cell_key_of(const uint64_t* x, double cell, uint64_t* key) {
   uint64_t k = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double f = floor(__longlong_as_double((long long)rec[2 + a]) / cell);
+    const double f = floor(__longlong_as_double((long long)x[a]) / cell);
     if (!(f > -1048576.0 && f < 1048576.0)) return false;
     k = (k << 21) | (uint64_t)((int64_t)f + 1048576);
   }
@@ -2165,18 +2166,19 @@ __device__ inline bool cell_key(const uint64_t* rec, double cell, uint64_t* key)
 }
 
 // Neighbour counts: per segment, an open-addressing table of the cells of
-// its reference records (key, count).
+// its reference records (key, count).  Entries are cleared whole, as
+// 16-byte stores (the table is 256-byte aligned).
 __global__ __launch_bounds__(BLOCK) void k_nbr_clear(Common cm, Entry* tab, int64_t hist_cap) {
   if (status_of(cm.status) & ANY_ERR) return;
   if (hist_cap < cm.meta[1]) {  // the history must cover every reference slot
     if (blockIdx.x == 0 && threadIdx.x == 0) fail(cm.status, ERR_INVALID);
     return;
   }
+  static_assert(sizeof(Entry) == 16, "one 16-byte store per entry");
   const int64_t H = cm.meta[2];
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < H; i += (int64_t)gridDim.x * BLOCK) {
-    tab[i].key = 0;
-    tab[i].ci = 0;
-  }
+  ulonglong2* t = reinterpret_cast<ulonglong2*>(tab);
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < H; i += (int64_t)gridDim.x * BLOCK)
+    t[i] = ulonglong2{0, 0};
 }
 
 __device__ inline uint64_t ref_record_word(const Common& cm, const uint8_t* ref, int64_t s, uint64_t j) {
@@ -2198,7 +2200,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_build(Common cm, const uint8_t* r
     bool v = false;
     if (g < Rt) {
       const uint64_t* rec = ref64 + ref_record_word(cm, ref, s, g - cm.rpre[s]);
-      v = (rec[1] >> 32) >= 5 && cell_key(rec, cell, &key);
+      v = (rec[1] >> 32) >= 5 && cell_key_of(rec + 2, cell, &key);
     }
     // Lanes with the same segment and cell add their count with one atomic:
     // neighbouring records mostly share a cell, so a wave has few distinct
@@ -2232,24 +2234,10 @@ __global__ __launch_bounds__(BLOCK) void k_nbr_build(Common cm, const uint8_t* r
   }
 }
 
-__device__ inline uint32_t nbr_count(const Common& cm, const Entry* tab, int64_t s, const uint64_t* rec, double cell) {
-  uint64_t key;
-  if ((rec[1] >> 32) < 5 || !cell_key(rec, cell, &key)) return 0;
-  const Seg& sg = cm.seg[s];
-  const uint64_t H = sg.hsize;
-  uint64_t h = mix64(key) & (H - 1);
-  for (uint64_t probe = 0; probe < H; ++probe) {
-    const Entry e = tab[cm.hpre[s] + h];
-    if (e.key == key) return e.ci > 127 ? 127 : e.ci;
-    if (e.key == 0) return 0;
-    h = (h + 1) & (H - 1);
-  }
-  return 0;
-}
-
 struct PredictArgs {
   Common cm;
   const uint64_t* ref;
+  uint64_t ref_words;  // words of the reference buffer
   const MDir* mdir;
   const PredW* pw;
   const Entry* tab;
@@ -2258,6 +2246,11 @@ struct PredictArgs {
   const uint8_t* hlen;
   uint64_t* pred_x;    // [matched][4] predicted words 2..5
   uint8_t* pred_on;    // [matched]
+  // history of C' for the matched records (o1 null: none asked for)
+  uint64_t* o1;
+  uint64_t* o2;
+  uint8_t* olen;
+  int64_t ocap;
   // training-window tap (encoder only; tcount null: off)
   const uint64_t* cur;
   int32_t* tin;        // [tcap][12]
@@ -2266,46 +2259,82 @@ struct PredictArgs {
   unsigned long long* tcount;
 };
 
-// One wave per 64 matched records at a time: every lane forms one record's
-// inputs, the integer MLP runs on four groups of 16 rows, and every lane
-// writes its record's predicted words.
-__global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
+// Prediction of the matched records, 64 per wave at a time (one per lane).
+// A lane's loads go out together: its directory entry, then its record's
+// header and words 2..5, its slot's history and its segment's table place;
+// its inputs go to LDS as int8 planes; the MLP runs on four groups of 16
+// rows; the lane writes its record's predicted words and, with a history
+// to write, the record's C' history (h2 <- h1, h1 <- the reference words).
+template <bool HIST>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_predict(PredictArgs a) {
   __shared__ PredW s_w;
-  __shared__ int32_t s_in[WAVES][WAVE][12];
+  __shared__ MlpIn s_in[WAVES];
   __shared__ int32_t s_q[WAVES][WAVE][4];
   __shared__ uint8_t s_h[WAVES][16][64];
   const Common& cm = a.cm;
   if (status_of(cm.status) & ANY_ERR) return;
   load_weights(&s_w, a.pw);
   const MlpOps ops = mlp_ops(s_w);
+  const double cell = s_w.cell;
   const int64_t M = cm.meta[5];
+  // (over capacity k_hist_out reports the error; nothing is written here)
+  const bool hist = HIST && M + cm.meta[6] <= a.ocap;
   const int l = lane_id(), wv = wave_id();
   const int64_t chunks = (M + WAVE - 1) / WAVE;
   for (int64_t ch = (int64_t)blockIdx.x * WAVES + wv; ch < chunks; ch += (int64_t)gridDim.x * WAVES) {
     const int64_t k = ch * WAVE + l;
-    bool on = false;
-    const uint64_t* rec = nullptr;
-    int32_t* in = s_in[wv][l];
+    const bool live = k < M;
+    const MDir e = a.mdir[live ? k : M - 1];
+    const uint64_t g = mdir_slot(e);
+    const int64_t s = mdir_seg(e);
+    // words 2..5 are read before the record's size is known, from an address
+    // kept inside the buffer (a matched record's message has a 32-byte
+    // header, so the buffer holds at least 4 words); they are used only when
+    // the record has them
+    const uint64_t w0 = e.rword + 6 <= a.ref_words ? e.rword + 2 : a.ref_words - 4;
+    const uint64_t hdr = a.ref[e.rword + 1];
+    const int hl = a.hlen[g];
+    uint64_t x[4], v1[4], v2[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      x[c] = a.ref[w0 + c];
+      v1[c] = a.h1[4 * g + c];
+      v2[c] = a.h2[4 * g + c];
+    }
+    const uint64_t H = cm.seg[s].hsize, hp = cm.hpre[s];
+    const uint64_t np = HIST ? cm.npre[s] : 0;
+    __builtin_amdgcn_sched_barrier(0);  // every load above is in flight before any use
+    const bool words6 = (hdr >> 32) >= 6;
+    const bool on = live && hl >= 1 && words6;
+    int32_t in[12];
+#pragma unroll
     for (int c = 0; c < 12; ++c) in[c] = 0;
-    if (k < M) {
-      const MDir e = a.mdir[k];
-      const uint64_t g = mdir_slot(e);
-      rec = a.ref + e.rword;
-      const uint64_t hdr = rec[1];
-      const int hl = a.hlen[g];
-      on = hl >= 1 && (hdr >> 32) >= 6;
-      if (on) {
-        for (int c = 0; c < 4; ++c) {
-          const double r = __longlong_as_double((long long)rec[2 + c]);
-          const double v1 = __longlong_as_double((long long)a.h1[4 * g + c]);
-          const double v2 = __longlong_as_double((long long)a.h2[4 * g + c]);
-          in[c] = quantise(r - v1);
-          in[4 + c] = hl >= 2 ? quantise(v1 - v2) : 0;
+    uint64_t key = 0;
+    bool look = false;
+    if (on) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double r = __longlong_as_double((long long)x[c]);
+        const double d1 = __longlong_as_double((long long)v1[c]);
+        const double d2 = __longlong_as_double((long long)v2[c]);
+        in[c] = quantise(r - d1);
+        in[4 + c] = hl >= 2 ? quantise(d1 - d2) : 0;
+      }
+      in[9] = (int32_t)((hdr >> 16) & 0xFFFF);
+      in[10] = (int32_t)(hdr & 0xFFFF);
+      in[11] = hl;
+      look = cell_key_of(x, cell, &key);
+    }
+    if (look) {  // neighbour count of the record's cell, clamped to 127
+      uint64_t h = mix64(key) & (H - 1);
+      for (uint64_t probe = 0; probe < H; ++probe) {
+        const Entry t = a.tab[hp + h];
+        if (t.key == key) {
+          in[8] = (int32_t)(t.ci > 127 ? 127 : t.ci);
+          break;
         }
-        in[8] = (int32_t)nbr_count(cm, a.tab, mdir_seg(e), rec, s_w.cell);
-        in[9] = (int32_t)((hdr >> 16) & 0xFFFF);
-        in[10] = (int32_t)(hdr & 0xFFFF);
-        in[11] = hl;
+        if (t.key == 0) break;
+        h = (h + 1) & (H - 1);
       }
     }
     if (a.tcount) {
@@ -2313,10 +2342,11 @@ __global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
       float tg[4] = {0.f, 0.f, 0.f, 0.f};
       bool w = on;
       if (w) {
-        const uint64_t* crec = a.cur + a.mdir[k].cword;
+        const uint64_t* crec = a.cur + e.cword;
+#pragma unroll
         for (int c = 0; c < 4; ++c) {
           const double d = (__longlong_as_double((long long)crec[2 + c]) -
-                            __longlong_as_double((long long)rec[2 + c])) * 4096.0;
+                            __longlong_as_double((long long)x[c])) * 4096.0;
           tg[c] = (float)d;
           w = w && isfinite(tg[c]);
         }
@@ -2329,28 +2359,44 @@ __global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
         base = __shfl(base, lead, WAVE);
         const int64_t at = (int64_t)base + __popcll(mask & lanemask_lt(l));
         if (w && at < a.tcap) {
+#pragma unroll
           for (int c = 0; c < 12; ++c) a.tin[12 * at + c] = in[c];
+#pragma unroll
           for (int c = 0; c < 4; ++c) a.ttgt[4 * at + c] = tg[c];
         }
       }
     }
+    mlp_in_store(s_in[wv], l, in);
     wave_sync();
-    // rows of records that need no prediction are skipped four groups at a time
+    // rows of records that need no prediction are skipped 16 at a time
     const uint64_t need = __ballot(on);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if ((need >> (16 * r)) & 0xFFFFull) mlp16(s_w, ops, s_in[wv] + 16 * r, s_h[wv], s_q[wv] + 16 * r);
+      if ((need >> (16 * r)) & 0xFFFFull) mlp16(s_w, ops, s_in[wv], 16 * r, s_h[wv], s_q[wv] + 16 * r);
     wave_sync();
-    if (k < M) {
+    if (live) {
       a.pred_on[k] = on ? 1 : 0;
       if (on) {
+        const int4 q4 = *reinterpret_cast<const int4*>(s_q[wv][l]);
+        const int32_t q[4] = {q4.x, q4.y, q4.z, q4.w};
+        uint64_t p[4];
+#pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const uint64_t rb = rec[2 + c];
-          const double r = __longlong_as_double((long long)rb);
-          const int32_t q = s_q[wv][l][c];
-          a.pred_x[4 * k + c] =
-              (q != 0 && isfinite(r)) ? (uint64_t)__double_as_longlong(r + (double)q * 0x1p-12) : rb;
+          const double r = __longlong_as_double((long long)x[c]);
+          p[c] = (q[c] != 0 && isfinite(r)) ? (uint64_t)__double_as_longlong(r + (double)q[c] * 0x1p-12) : x[c];
         }
+        // (the arena array is 256-byte aligned: 32 bytes per record)
+        *reinterpret_cast<ulonglong2*>(a.pred_x + 4 * k) = ulonglong2{p[0], p[1]};
+        *reinterpret_cast<ulonglong2*>(a.pred_x + 4 * k + 2) = ulonglong2{p[2], p[3]};
+      }
+      if (hist) {
+        const int64_t o = k + (int64_t)np;  // C' index of matched record k
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          a.o2[4 * o + c] = v1[c];
+          a.o1[4 * o + c] = words6 ? x[c] : 0;
+        }
+        a.olen[o] = (uint8_t)(hl + 1 > 2 ? 2 : hl + 1);
       }
     }
     wave_sync();
@@ -2371,6 +2417,7 @@ struct HistArgs {
   uint64_t* o2;
   uint8_t* olen;
   int64_t ocap;
+  bool new_only;       // the matched records' history was written by k_predict
 };
 
 // Four lanes per C' record (one per history word), 16 records per wave at a
@@ -2385,9 +2432,9 @@ __global__ __launch_bounds__(BLOCK) void k_hist_out(HistArgs a) {
     return;
   }
   const int l = lane_id(), c = l & 3;
-  const int64_t total = M + Nn;
+  const int64_t first = a.new_only ? M : 0, total = M + Nn;
   const int64_t stride = (int64_t)gridDim.x * WAVES * 16;
-  for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave_id()) * 16; base < total; base += stride) {
+  for (int64_t base = first + ((int64_t)blockIdx.x * WAVES + wave_id()) * 16; base < total; base += stride) {
     const int64_t it = base + (l >> 2);
     if (it >= total) continue;
     if (it < M) {
@@ -2498,6 +2545,22 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
 }
 
 // Key arrays are 16-byte aligned (one uid and header word pair per record).
+// True when an array of the history to write overlaps one of the history
+// read: the prediction kernel reads the one while it writes the other.
+inline bool hist_overlap(const ta_history* in, const ta_history* out) {
+  if (!in || !out) return false;
+  auto lo = [](const void* p) { return (uintptr_t)p; };
+  auto hi = [](const void* p, int64_t n) { return (uintptr_t)p + (uintptr_t)(n > 0 ? n : 0); };
+  const uintptr_t ia[3] = {lo(in->h1), lo(in->h2), lo(in->hlen)};
+  const uintptr_t ib[3] = {hi(in->h1, 32 * in->cap), hi(in->h2, 32 * in->cap), hi(in->hlen, in->cap)};
+  const uintptr_t oa[3] = {lo(out->h1), lo(out->h2), lo(out->hlen)};
+  const uintptr_t ob[3] = {hi(out->h1, 32 * out->cap), hi(out->h2, 32 * out->cap), hi(out->hlen, out->cap)};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (ia[i] < ob[j] && oa[j] < ib[i]) return true;
+  return false;
+}
+
 inline bool keys_ok(const ta_keys* k) {
   auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   return al(k->cur) && al(k->ref) && al(k->out) && k->out_cap >= 0 && (k->out || k->out_cap == 0);
@@ -2567,7 +2630,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                                      const ta_keys* keys, void* stream) {
   if (!c || nseg < 0 || !cur_off || !ref_off || !enc_off || !newref_off || cur_len < 0 || ref_len < 0 ||
       enc_cap < 0 || newref_cap < 0 || (cur_len && !cur) || (ref_len && !ref) || (enc_cap && !enc) ||
-      (newref_cap && !newref) || (pred && !hist_in) || (keys && !keys_ok(keys)))
+      (newref_cap && !newref) || (pred && !hist_in) || (keys && !keys_ok(keys)) ||
+      hist_overlap(hist_in, hist_out))
     return TA_ERR_INVALID;
   const uint64_t* ckeys = keys ? keys->cur : nullptr;
   const uint64_t* rkeys = keys ? keys->ref : nullptr;
@@ -2643,10 +2707,30 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     Timed tm(c, "predict", s);
     k_nbr_clear<<<g, BLOCK, 0, s>>>(m.cm, m.tab, hist_in->cap);
     k_nbr_build<<<g, BLOCK, 0, s>>>(m.cm, ref, pw, m.tab);
-    PredictArgs pa{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, pw, m.tab, hist_in->h1, hist_in->h2,
-                   hist_in->hlen, m.pred_x, m.pred_on, reinterpret_cast<const uint64_t*>(cur), c->tap_in,
-                   c->tap_tgt, c->tap_cap, c->tap_count};
-    k_predict<<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
+    PredictArgs pa{m.cm,
+                   reinterpret_cast<const uint64_t*>(ref),
+                   (uint64_t)ref_len / 8,
+                   m.mdir,
+                   pw,
+                   m.tab,
+                   hist_in->h1,
+                   hist_in->h2,
+                   hist_in->hlen,
+                   m.pred_x,
+                   m.pred_on,
+                   hist_out ? hist_out->h1 : nullptr,
+                   hist_out ? hist_out->h2 : nullptr,
+                   hist_out ? hist_out->hlen : nullptr,
+                   hist_out ? hist_out->cap : 0,
+                   reinterpret_cast<const uint64_t*>(cur),
+                   c->tap_in,
+                   c->tap_tgt,
+                   c->tap_cap,
+                   c->tap_count};
+    if (hist_out)
+      k_predict<true><<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
+    else
+      k_predict<false><<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
   }
   {
     Timed tm(c, "encode_groups", s);
@@ -2678,7 +2762,8 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                                                           m.jhdr, okeys, okeys_cap);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
-                hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};
+                hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap,
+                pw != nullptr};
     k_hist_out<<<g, BLOCK, 0, s>>>(ha);
   }
   TA_LAUNCH_CHECK();
@@ -2691,7 +2776,8 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                                      ta_history* hist_out, uint8_t* out, int64_t out_cap, int64_t* out_off,
                                      const ta_keys* keys, void* stream) {
   if (!c || nseg < 0 || !enc_off || !ref_off || !out_off || enc_len < 0 || ref_len < 0 || out_cap < 0 ||
-      (enc_len && !enc) || (ref_len && !ref) || (out_cap && !out) || (pred && !hist_in) || (keys && !keys_ok(keys)))
+      (enc_len && !enc) || (ref_len && !ref) || (out_cap && !out) || (pred && !hist_in) || (keys && !keys_ok(keys)) ||
+      hist_overlap(hist_in, hist_out))
     return TA_ERR_INVALID;
   const uint64_t* rkeys = keys ? keys->ref : nullptr;
   uint64_t* okeys = keys ? keys->out : nullptr;
@@ -2739,15 +2825,30 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
     Timed tm(c, "predict", s);
     k_nbr_clear<<<g, BLOCK, 0, s>>>(m.cm, m.tab, hist_in->cap);
     k_nbr_build<<<g, BLOCK, 0, s>>>(m.cm, ref, pw, m.tab);
-    PredictArgs pa{m.cm,       reinterpret_cast<const uint64_t*>(ref),
-                   m.mdir,     pw,
-                   m.tab,      hist_in->h1,
-                   hist_in->h2, hist_in->hlen,
-                   m.pred_x,   m.pred_on,
-                   nullptr,    nullptr,
-                   nullptr,    0,
+    PredictArgs pa{m.cm,
+                   reinterpret_cast<const uint64_t*>(ref),
+                   (uint64_t)ref_len / 8,
+                   m.mdir,
+                   pw,
+                   m.tab,
+                   hist_in->h1,
+                   hist_in->h2,
+                   hist_in->hlen,
+                   m.pred_x,
+                   m.pred_on,
+                   hist_out ? hist_out->h1 : nullptr,
+                   hist_out ? hist_out->h2 : nullptr,
+                   hist_out ? hist_out->hlen : nullptr,
+                   hist_out ? hist_out->cap : 0,
+                   nullptr,
+                   nullptr,
+                   nullptr,
+                   0,
                    nullptr};
-    k_predict<<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
+    if (hist_out)
+      k_predict<true><<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
+    else
+      k_predict<false><<<grid_for(c, b.R, WAVE * WAVES), BLOCK, 0, s>>>(pa);
   }
   {
     Timed tm(c, "decode_unpack", s);
@@ -2762,7 +2863,8 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out, okeys, okeys_cap);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
-                hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap};
+                hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap,
+                pw != nullptr};
     k_hist_out<<<g, BLOCK, 0, s>>>(ha);
   }
   TA_LAUNCH_CHECK();

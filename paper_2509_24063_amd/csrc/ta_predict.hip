@@ -13,27 +13,33 @@ namespace {
 constexpr uint32_t TAP1_MAGIC = 0x31504154u;  // "TAP1"
 constexpr size_t BLOB_LEN = 5672;
 
-// Rows are handled 16 per wave; weights live in LDS.
+// Rows are handled 64 per wave (one per lane, four groups of 16 through
+// the network); weights live in LDS.
 __global__ __launch_bounds__(BLOCK) void k_pred_eval(const PredW* w, const int32_t* in, int32_t* q, int64_t n) {
   __shared__ PredW s_w;
-  __shared__ int32_t s_in[WAVES][16][12];
-  __shared__ int32_t s_q[WAVES][16][4];
+  __shared__ MlpIn s_in[WAVES];
+  __shared__ int32_t s_q[WAVES][WAVE][4];
   __shared__ uint8_t s_h[WAVES][16][64];
   load_weights(&s_w, w);
   const MlpOps ops = mlp_ops(s_w);
   const int l = lane_id(), wv = wave_id();
-  const int64_t chunks = (n + 15) / 16;
+  const int64_t chunks = (n + WAVE - 1) / WAVE;
   for (int64_t ch = (int64_t)blockIdx.x * WAVES + wv; ch < chunks; ch += (int64_t)gridDim.x * WAVES) {
-    const int64_t r0 = ch * 16;
-    for (int e = l; e < 16 * 12; e += WAVE) {
-      const int64_t row = r0 + e / 12;
-      s_in[wv][e / 12][e % 12] = row < n ? in[row * 12 + e % 12] : 0;
+    const int64_t row = ch * WAVE + l;
+    int32_t v[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) v[i] = row < n ? in[row * 12 + i] : 0;
+    mlp_in_store(s_in[wv], l, v);
+    wave_sync();
+    const int64_t left = n - ch * WAVE;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (16 * r < left) mlp16(s_w, ops, s_in[wv], 16 * r, s_h[wv], s_q[wv] + 16 * r);
+    wave_sync();
+    if (row < n) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[row * 4 + c] = s_q[wv][l][c];
     }
-    wave_sync();
-    mlp16(s_w, ops, s_in[wv], s_h[wv], s_q[wv]);
-    wave_sync();
-    const int64_t row = r0 + l / 4;
-    if (l < 64 && row < n) q[row * 4 + (l & 3)] = s_q[wv][l / 4][l & 3];
     wave_sync();
   }
 }
@@ -97,7 +103,7 @@ extern "C" ta_status ta_predictor_eval(ta_ctx* c, const ta_predictor* p, const i
   if (!c || !p || n < 0 || (n > 0 && (!in || !q))) return TA_ERR_INVALID;
   if (n == 0) return TA_OK;
   c->grid = c->grid_default;
-  const int g = grid_for(c, ceil_div(n, 16), WAVES);
+  const int g = grid_for(c, ceil_div(n, WAVE), WAVES);
   k_pred_eval<<<g, BLOCK, 0, (hipStream_t)stream>>>(static_cast<const PredW*>(p->dev), in, q, n);
   TA_LAUNCH_CHECK();
   return TA_OK;
