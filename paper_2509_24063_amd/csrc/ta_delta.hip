@@ -90,6 +90,22 @@ struct MDir {
   uint64_t gs;      // global reference slot | segment << 34
 };
 __device__ inline int64_t mdir_seg(const MDir& e) { return (int64_t)(e.gs >> 34); }
+// Decoder: what unpacking one residual group needs, written by the
+// directory pass so that the unpack reads it with one 64-byte scalar load.
+struct alignas(64) GDesc {
+  uint64_t blk;    // byte offset of the group's block in the encodings
+  uint64_t bm;     // word bitmap of the group's residual
+  uint64_t out;    // word index in C' of the group's first residual word
+  uint64_t g0w;    // the group's first residual position
+  uint64_t rbw;    // word index of the segment's reference record area
+  uint32_t k0;     // matched record holding the group's first word
+  uint32_t size;   // block bytes (the size byte times 8, the mixed-mode flag taken off)
+  uint32_t nlive;  // residual words of the group (1..64)
+  uint32_t usep;   // 1: the residual is against the prediction
+  uint32_t pad[2];
+};
+static_assert(sizeof(GDesc) == 64, "one scalar load per group");
+
 [[maybe_unused]] __device__ inline uint64_t mdir_slot(const MDir& e) { return e.gs & ((1ull << 34) - 1); }
 
 
@@ -785,6 +801,36 @@ __device__ inline void map_groups(const Common& cm, int64_t s, uint64_t q0, uint
   for (uint64_t lg = (q0 + 63) / 64; 64 * lg < q0 + w; ++lg) {
     gseg[cm.gpre[s] + lg] = (uint32_t)s;
     if (gfirst) gfirst[cm.gpre[s] + lg] = (uint32_t)k;  // the matched record holding the group's first word
+  }
+}
+
+// Decoder: descriptors of the groups whose first residual word lies in
+// matched record k (local residual words [q0, q0 + w) of segment s).  The
+// group's bitmap and size byte are read from the encoding's tables (inside
+// it: the header checks passed); its block offset is the segment's block
+// area plus the prefix of the group sizes within the segment.
+__device__ inline void map_groups_dec(const Common& cm, const Seg& sg, int64_t s, uint64_t q0, uint64_t w,
+                                      uint64_t k, const uint8_t* enc, const uint64_t* gex, GDesc* gd) {
+  for (uint64_t lg = (q0 + 63) / 64; 64 * lg < q0 + w; ++lg) {
+    const uint64_t gg = cm.gpre[s] + lg;
+    const uint8_t* e = enc + sg.encm;
+    const uint32_t byte = e[64 + 8 * sg.PG + 8 * sg.G + lg];
+    const uint32_t md = (uint32_t)sg.mode;
+    GDesc d;
+    d.blk = sg.encm + sg.fixed + (gex[gg] - gex[cm.gpre[s]]);
+    d.bm = ld64(e + 64 + 8 * sg.PG + 8 * lg);
+    d.out = sg.cpw + sg.dbase + 64 * lg;
+    d.g0w = sg.dbase + 64 * lg;
+    d.rbw = sg.rbody / 8;
+    d.k0 = (uint32_t)k;
+    d.size = 8u * (md == 2 ? byte & 0x7Fu : byte);
+    d.nlive = (uint32_t)(sg.W - 64 * lg < 64 ? sg.W - 64 * lg : 64);
+    d.usep = md == 1 || (md == 2 && (byte >> 7)) ? 1u : 0u;
+    d.pad[0] = d.pad[1] = 0;
+    ulonglong2* dst = reinterpret_cast<ulonglong2*>(gd + gg);
+    const ulonglong2* src = reinterpret_cast<const ulonglong2*>(&d);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dst[i] = src[i];
   }
 }
 
@@ -1812,12 +1858,13 @@ __global__ __launch_bounds__(BLOCK) void k_dec_seg2(Common cm, const uint64_t* r
 
 // Directory of the matched records (decoder): R word, residual start,
 // slot; word offsets of the records in the reference's record area; C'
-// offsets; groups' segment and first record.  Staged like the encoder's.
+// offsets; the descriptors of the residual groups.  Staged like the
+// encoder's.
 __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* ref, const uint8_t* rmatch,
                                                     const uint64_t* rscan, const uint32_t* rwords, MDir* mdir,
-                                                    uint64_t* mstart, uint8_t* out, uint32_t* gseg,
-                                                    uint32_t* gfirst, uint32_t* mrw, const uint64_t* rkeys,
-                                                    uint64_t* okeys, uint64_t okeys_cap) {
+                                                    uint64_t* mstart, uint8_t* out, const uint8_t* enc,
+                                                    const uint64_t* gex, GDesc* gdesc, uint32_t* mrw,
+                                                    const uint64_t* rkeys, uint64_t* okeys, uint64_t okeys_cap) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
@@ -1869,7 +1916,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
         else fail(cm.status, ERR_CAPACITY);
       }
       *reinterpret_cast<uint32_t*>(out + sg.oref + 32 + 4 * (k - sg.mbase)) = (uint32_t)(d - sg.dbase);
-      map_groups(cm, sx, d - sg.dbase, rwv[u], gseg, gfirst, k);
+      map_groups_dec(cm, sg, sx, d - sg.dbase, rwv[u], k, enc, gex, gdesc);
     }
   }
 }
@@ -1877,9 +1924,6 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
 struct UnpackArgs {
   Common cm;
   const uint8_t* enc;
-  const uint64_t* gex;
-  const uint32_t* gseg;
-  const uint32_t* gfirst;  // matched record holding each group's first word
   const uint64_t* ref;     // (words)
   const uint32_t* mrw;     // [matched] word offset of every matched record in its reference's record area
   const uint64_t* mstart;  // [matched+1]
@@ -1908,14 +1952,10 @@ __device__ inline uint32_t funnel32(uint32_t hi, uint32_t lo, uint32_t s) {
 //
 // Every length, size, padding byte and unused nibble is checked, and the
 // uid and header words of a matched record must have a zero residual.
-// (segs, gpre, gex, gseg, gfirst: read-only here; as restrict parameters
-// their uniform reads become scalar loads)
+// (gdesc: read-only here; as a restrict parameter its uniform reads become
+// scalar loads)
 template <int OP>
-__global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* __restrict__ segs,
-                                                      const uint64_t* __restrict__ gpre,
-                                                      const uint64_t* __restrict__ gex,
-                                                      const uint32_t* __restrict__ gseg,
-                                                      const uint32_t* __restrict__ gfirst,
+__global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const GDesc* __restrict__ gdesc,
                                                       const uint8_t* __restrict__ enc) {
   constexpr int BW = BLK_MAX / 8 + 1;  // block words, one spare for the two-word read
   __shared__ uint64_t s_blk[WAVES][UNPACK_PG][BW];
@@ -1931,10 +1971,8 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
   bool anybad = false;
   const int64_t nw = (int64_t)gridDim.x * WAVES;
   for (int64_t g0 = ((int64_t)blockIdx.x * WAVES + wv) * UNPACK_PG; g0 < Gt; g0 += nw * UNPACK_PG) {
-    // wave-uniform per group (scalar registers) ...
-    uint64_t bmv[UNPACK_PG];
-    uint32_t sizev[UNPACK_PG];
-    bool usep[UNPACK_PG];
+    // the groups' descriptors (scalar registers) ...
+    GDesc dv[UNPACK_PG];
     // ... and per lane: record start (relative to the group's first word)
     // and reference word offset of record k0 + lane, block words lane and 64 + lane
     int relv[UNPACK_PG];
@@ -1942,44 +1980,26 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
     uint64_t b0v[UNPACK_PG], b1v[UNPACK_PG];
 #pragma unroll
     for (int x = 0; x < UNPACK_PG; ++x) {
-      const int64_t gg = g0 + x;
-      bmv[x] = 0;
-      sizev[x] = 0;
-      usep[x] = false;
-      relv[x] = 64;
-      rwv[x] = 0;
+      const int64_t gg = g0 + x < Gt ? g0 + x : Gt - 1;
+      dv[x] = gdesc[gg];
+      const GDesc& d = dv[x];
+      // (loads from clamped indices, not behind divergent branches: a group
+      // implies a matched record, so M >= 1)
+      const uint64_t k0 = d.k0;
+      const bool has = l <= 32 && k0 + l < (uint64_t)M;
+      const uint64_t kk = has ? k0 + l : (uint64_t)M - 1;
+      const int64_t r = (int64_t)a.mstart[kk] - (int64_t)d.g0w;
+      const uint32_t rwk = a.mrw[kk];
+      // clamped to [-2^30, 64]: lane 0's record may start long before the group
+      relv[x] = !has ? 64 : (r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r));
+      rwv[x] = has ? rwk : 0u;
       b0v[x] = b1v[x] = 0;
-      if (gg < Gt) {
-        const uint64_t k0 = uniform32(gfirst[gg]);
-        const int64_t sx = (int64_t)uniform32(gseg[gg]);
-        const Seg& sg = segs[sx];
-        const uint64_t lg = (uint64_t)gg - gpre[sx];
-        const uint8_t* e = enc + sg.encm;
-        bmv[x] = uniform64(ld64(e + 64 + 8 * sg.PG + 8 * lg));
-        // the size byte, from its aligned dword (the size table is 8-byte aligned)
-        const uint32_t sw = *reinterpret_cast<const uint32_t*>(e + 64 + 8 * sg.PG + 8 * sg.G + (lg & ~3ull));
-        const uint32_t byte = (sw >> (8 * (lg & 3))) & 0xFFu;
-        const uint32_t md = uniform32((uint32_t)sg.mode);
-        // mixed segments: bit 7 says the group's residual is against the prediction
-        const uint32_t size = uniform32(8u * (md == 2 ? byte & 0x7Fu : byte));
-        sizev[x] = size;
-        usep[x] = md == 1 || (md == 2 && (byte >> 7));
-        // (loads from clamped indices, not behind divergent branches: a group
-        // implies a matched record, so M >= 1)
-        const bool has = l <= 32 && k0 + l < (uint64_t)M;
-        const uint64_t kk = has ? k0 + l : (uint64_t)M - 1;
-        const int64_t r = (int64_t)a.mstart[kk] - (int64_t)(sg.dbase + 64 * lg);
-        const uint32_t rwk = a.mrw[kk];
-        // clamped to [-2^30, 64]: lane 0's record may start long before the group
-        relv[x] = !has ? 64 : (r > 64 ? 64 : (r < -(1 << 30) ? -(1 << 30) : (int)r));
-        rwv[x] = has ? rwk : 0u;
-        if (size > 0 && size <= BLK_MAX) {  // uniform; lanes past the block read its last word
-          const uint64_t* src =
-              reinterpret_cast<const uint64_t*>(enc + uniform64(sg.encm + sg.fixed + (gex[gg] - gex[gpre[sx]])));
-          const uint32_t nwd = size / 8;
-          b0v[x] = src[(uint32_t)l < nwd ? (uint32_t)l : nwd - 1];
-          if (size > 8 * WAVE) b1v[x] = src[(uint32_t)(WAVE + l) < nwd ? (uint32_t)(WAVE + l) : nwd - 1];
-        }
+      const uint32_t size = d.size;
+      if (size > 0 && size <= BLK_MAX) {  // uniform; lanes past the block read its last word
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(enc + d.blk);
+        const uint32_t nwd = size / 8;
+        b0v[x] = src[(uint32_t)l < nwd ? (uint32_t)l : nwd - 1];
+        if (size > 8 * WAVE) b1v[x] = src[(uint32_t)(WAVE + l) < nwd ? (uint32_t)(WAVE + l) : nwd - 1];
       }
     }
     // record starts inside each group
@@ -1997,21 +2017,19 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
       xwv[x] = 0;
       offv[x] = 0;
       if (gg >= Gt) break;
+      const GDesc& d = dv[x];
       const uint64_t starts = __ballot(s_mark[wv][x][l] == (uint32_t)gg + 1);
       const int idx = __popcll(starts & le_mask);  // <= 32
       const uint32_t off = (uint32_t)(l - __shfl(relv[x], idx, WAVE));
       const uint32_t rw = (uint32_t)__shfl((int)rwv[x], idx, WAVE);
       offv[x] = off;
-      const int64_t sx = (int64_t)uniform32(gseg[gg]);
-      const Seg& sg = segs[sx];
-      const uint64_t lg = uniform64((uint64_t)gg - gpre[sx]);
-      const bool live = 64 * lg + (uint64_t)l < sg.W;
-      const uint64_t* rbody = a.ref + uniform64(sg.rbody / 8);  // the segment's reference records
+      const bool live = (uint32_t)l < d.nlive;
+      const uint64_t* rbody = a.ref + d.rbw;  // the segment's reference records
       // (a word that is not live reads word 0 of lane 0's record, the one
       // holding the group's first word: in the segment, always valid)
       const uint32_t ri = live ? rw + off : (uint32_t)__builtin_amdgcn_readlane((int)rwv[x], 0);
-      if (usep[x]) {  // uniform
-        const uint64_t k = uniform32(gfirst[gg]) + (live ? (uint64_t)idx : 0);
+      if (d.usep) {  // uniform
+        const uint64_t k = (uint64_t)d.k0 + (live ? (uint64_t)idx : 0);
         const bool pred = live && off >= 2 && off < 6 && a.pred_on[k];
         const uint64_t px = a.pred_x[4 * k + (pred ? off - 2 : 0)];
         const uint64_t rx = rbody[ri];
@@ -2025,12 +2043,13 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
     for (int x = 0; x < UNPACK_PG; ++x) {
       const int64_t gg = g0 + x;
       if (gg >= Gt) break;
+      const GDesc& d = dv[x];
       uint64_t* blk = s_blk[wv][x];
       blk[l] = b0v[x];
       if (l < BW - WAVE) blk[WAVE + l] = b1v[x];
       wave_sync();
-      const uint64_t bitmap = uniform64(bmv[x]);
-      const uint32_t size = uniform32(sizev[x]);
+      const uint64_t bitmap = d.bm;
+      const uint32_t size = d.size;
       const uint32_t popc = (uint32_t)__popcll(bitmap);
       const uint32_t nib = (popc + 1) / 2;
       const bool bit = (bitmap >> l) & 1;
@@ -2065,13 +2084,9 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const Seg* _
         if ((end & 7) && (blk[size / 8 - 1] >> (8 * (end & 7))) != 0) gchk = true;
         if ((popc & 1) && (b8[popc >> 1] >> 4) != 0) gchk = true;
       }
-      const int64_t sx = (int64_t)uniform32(gseg[gg]);
-      const Seg& sg = segs[sx];
-      const uint64_t lg = uniform64((uint64_t)gg - gpre[sx]);
-      if (64 * lg + (uint64_t)l < sg.W) {
+      if ((uint32_t)l < d.nlive) {
         if (offv[x] < 2 && D != 0) bad = true;
-        uint64_t* ob = a.out + uniform64(sg.cpw + sg.dbase + 64 * lg);
-        ob[l] = undiff_word<OP>(D, xwv[x]);
+        a.out[d.out + (uint64_t)l] = undiff_word<OP>(D, xwv[x]);
       }
       anybad = anybad || bad || gchk;
     }
@@ -2481,6 +2496,7 @@ struct Mem {
   uint8_t* pred_on;
   uint32_t* gseg;
   uint32_t* gfirst;
+  GDesc* gdesc;     // decoder
   uint32_t* mrw;
   uint64_t* mstart;
   uint8_t* gch;
@@ -2533,6 +2549,7 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.pred_on = learned ? ar.take<uint8_t>(b.R) : nullptr;
   m.gseg = ar.take<uint32_t>(b.G);
   m.gfirst = ar.take<uint32_t>(b.G);
+  m.gdesc = ar.take<GDesc>(b.G);
   m.mrw = ar.take<uint32_t>(b.R);
   m.mstart = ar.take<uint64_t>(b.R + 1);
   m.gch = learned ? ar.take<uint8_t>(b.G) : nullptr;
@@ -2544,7 +2561,6 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   return m;
 }
 
-// Key arrays are 16-byte aligned (one uid and header word pair per record).
 // True when an array of the history to write overlaps one of the history
 // read: the prediction kernel reads the one while it writes the other.
 inline bool hist_overlap(const ta_history* in, const ta_history* out) {
@@ -2561,6 +2577,7 @@ inline bool hist_overlap(const ta_history* in, const ta_history* out) {
   return false;
 }
 
+// Key arrays are 16-byte aligned (one uid and header word pair per record).
 inline bool keys_ok(const ta_keys* k) {
   auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   return al(k->cur) && al(k->ref) && al(k->out) && k->out_cap >= 0 && (k->out || k->out_cap == 0);
@@ -2818,8 +2835,8 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                                                                      lookback(c, 2));
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
   k_dec_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords,
-                                                              pred || hist_out ? m.mdir : nullptr, m.mstart, out, m.gseg, m.gfirst,
-                                 m.mrw, rkeys, okeys, okeys_cap);
+                                                              pred || hist_out ? m.mdir : nullptr, m.mstart, out, enc,
+                                                              m.gex, m.gdesc, m.mrw, rkeys, okeys, okeys_cap);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
     Timed tm(c, "predict", s);
@@ -2852,13 +2869,13 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   }
   {
     Timed tm(c, "decode_unpack", s);
-    UnpackArgs ua{m.cm,  enc,      m.gex,    m.gseg,    m.gfirst, reinterpret_cast<const uint64_t*>(ref),
-                  m.mrw, m.mstart, m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(out)};
+    UnpackArgs ua{m.cm,     enc,       reinterpret_cast<const uint64_t*>(ref), m.mrw, m.mstart,
+                  m.pred_x, m.pred_on, reinterpret_cast<uint64_t*>(out)};
     const int gu = grid_for(c, b.G, WAVES * UNPACK_PG);
     if (c->diff_op)
-      k_dec_unpack<1><<<gu, BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst, ua.enc);
+      k_dec_unpack<1><<<gu, BLOCK, 0, s>>>(ua, m.gdesc, enc);
     else
-      k_dec_unpack<0><<<gu, BLOCK, 0, s>>>(ua, m.cm.seg, m.cm.gpre, m.gex, m.gseg, m.gfirst, ua.enc);
+      k_dec_unpack<0><<<gu, BLOCK, 0, s>>>(ua, m.gdesc, enc);
   }
   k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out, okeys, okeys_cap);
   if (hist_out) {
