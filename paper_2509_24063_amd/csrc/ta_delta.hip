@@ -203,8 +203,10 @@ constexpr int JT_MAX_TILES = 64;  // counting tiles per segment side at most
 #define TA_JB_TARGET 1024
 #endif
 constexpr int JB_TARGET = TA_JB_TARGET;
-constexpr int JC_U = 4;           // join count: items per thread and pass
-constexpr int RS_U = 4;           // decoder reference slots: slots per lane and pass
+constexpr int JC_U = 4;           // join count and bucket: items per thread and pass
+constexpr int JS_U = 16;          // join scatter: items per thread and pass (a tile's items in few passes)
+constexpr int RS_U = 4;           // record directories: reference slots per lane and pass
+constexpr int RL_U = 8;           // decoder reference slots: slots per lane and pass
 constexpr int JB_MAX = 8192;      // buckets per segment (LDS histogram)
 // A bucket holds JB_TARGET / 2 .. JB_TARGET items on average; JCAP at 1.5x
 // the target keeps the bucket block at 32 KB of LDS (five blocks per CU),
@@ -493,17 +495,17 @@ __global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a, const Seg* _
     for (uint64_t b = threadIdx.x; b < B; b += BLOCK) s_off[b] = (uint32_t)(src[b * g.jT] - seg0);
     __syncthreads();
     const uint64_t gbase = jt.isC ? cpre[jt.s] : Ct + rpre[jt.s];
-    // JC_U items per thread and pass, their uids loaded together; each pair
+    // JS_U items per thread and pass, their uids loaded together; each pair
     // goes out as one 16-byte store
-    for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += (uint64_t)BLOCK * JC_U) {
-      uint64_t uid[JC_U];
+    for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += (uint64_t)BLOCK * JS_U) {
+      uint64_t uid[JS_U];
 #pragma unroll
-      for (int u = 0; u < JC_U; ++u) {
+      for (int u = 0; u < JS_U; ++u) {
         const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
         uid[u] = a.juid[gbase + (i < jt.i1 ? i : jt.i1 - 1)];
       }
 #pragma unroll
-      for (int u = 0; u < JC_U; ++u) {
+      for (int u = 0; u < JS_U; ++u) {
         const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
         if (i < jt.i1) {
           const uint32_t pos = atomicAdd(&s_off[join_bucket(uid[u], B)], 1u);
@@ -1636,7 +1638,7 @@ __global__ __launch_bounds__(1024) void k_dec_setup1(Common cm, const uint8_t* e
 
 // Every reference slot: its size in words, whether the encoding keeps it
 // (presence bit), and the XOR of the reference uids (compared with the
-// encoding's later).  A wave takes RS_U * 64 consecutive slots per pass, RS_U
+// encoding's later).  A wave takes RL_U * 64 consecutive slots per pass, RL_U
 // per lane, and issues all their loads before it stores anything.
 // (segs, rpre: read-only here; as restrict parameters, reads with a
 // wave-uniform segment become scalar loads)
@@ -1647,17 +1649,17 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
-  constexpr int64_t SPAN = (int64_t)WAVE * RS_U;
+  constexpr int64_t SPAN = (int64_t)WAVE * RL_U;
   const int64_t nwv = (int64_t)gridDim.x * WAVES;
   bool bad = false;
   for (int64_t base = ((int64_t)blockIdx.x * WAVES + wave_id()) * SPAN; base < Rt; base += nwv * SPAN) {
     const int64_t last = base + SPAN - 1 < Rt ? base + SPAN - 1 : Rt - 1;
     const int64_t lo = wave_last_le<uint64_t>(rpre, 0, cm.nseg, (uint64_t)base);
     const int64_t hi = wave_last_le<uint64_t>(rpre, lo, cm.nseg, (uint64_t)last);
-    uint64_t uid[RS_U], hdr[RS_U], pw[RS_U], jv[RS_U];
-    int64_t sv[RS_U];
-    bool ok[RS_U];
-    Tam1Loc loc[RS_U];
+    uint64_t uid[RL_U], hdr[RL_U], pw[RL_U], jv[RL_U];
+    int64_t sv[RL_U];
+    bool ok[RL_U];
+    Tam1Loc loc[RL_U];
     // slots past the end read the last one (unused); all offsets and
     // presence words are loaded before any record word
     const bool one = lo == hi;  // uniform: the whole pass in one segment
@@ -1667,7 +1669,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
       const uint64_t r0 = rpre[su];
       const uint8_t* m = ref + sg.rmsg;
 #pragma unroll
-      for (int u = 0; u < RS_U; ++u) {
+      for (int u = 0; u < RL_U; ++u) {
         const int64_t g = base + (int64_t)u * WAVE + l;
         const uint64_t j = (uint64_t)(g <= last ? g : last) - r0;
         loc[u] = tam1_locate(m, (uint32_t)sg.nr, sg.rwr, (uint32_t)j);
@@ -1677,21 +1679,21 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
       }
       if (rkeys) {
 #pragma unroll
-        for (int u = 0; u < RS_U; ++u) {
+        for (int u = 0; u < RL_U; ++u) {
           const ulonglong2 kv = *reinterpret_cast<const ulonglong2*>(rkeys + 2 * (r0 + jv[u]));
           uid[u] = kv.x;
           hdr[u] = kv.y;
         }
       } else {
 #pragma unroll
-        for (int u = 0; u < RS_U; ++u) tam1_words(m, (uint32_t)sg.nr, loc[u], &uid[u], &hdr[u]);
+        for (int u = 0; u < RL_U; ++u) tam1_words(m, (uint32_t)sg.nr, loc[u], &uid[u], &hdr[u]);
       }
       __builtin_amdgcn_sched_barrier(0);  // keep the checks below every record load
 #pragma unroll
-      for (int u = 0; u < RS_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
+      for (int u = 0; u < RL_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
     } else {
 #pragma unroll
-      for (int u = 0; u < RS_U; ++u) {
+      for (int u = 0; u < RL_U; ++u) {
         const int64_t g = base + (int64_t)u * WAVE + l;
         const int64_t s = last_le<uint64_t>(rpre, lo, hi + 1, (uint64_t)(g <= last ? g : last));
         const Seg& sg = segs[s];
@@ -1702,7 +1704,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
         sv[u] = s;
       }
 #pragma unroll
-      for (int u = 0; u < RS_U; ++u) {
+      for (int u = 0; u < RL_U; ++u) {
         const Seg& sg = segs[sv[u]];
         if (rkeys) {
           const ulonglong2 kv = *reinterpret_cast<const ulonglong2*>(rkeys + 2 * (rpre[sv[u]] + jv[u]));
@@ -1713,11 +1715,11 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
         }
       }
 #pragma unroll
-      for (int u = 0; u < RS_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
+      for (int u = 0; u < RL_U; ++u) ok[u] = tam1_valid(loc[u], hdr[u]) && uid[u] != 0;
     }
     uint64_t f = 0;
 #pragma unroll
-    for (int u = 0; u < RS_U; ++u) {
+    for (int u = 0; u < RL_U; ++u) {
       const int64_t g = base + (int64_t)u * WAVE + l;
       const bool active = g <= last;
       if (active) {
@@ -2825,7 +2827,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
       k_scan_cols<<<6, 1024, 0, s>>>(cs);
     }
   }
-  k_dec_rslots<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre,
+  k_dec_rslots<<<grid_for(c, b.R, BLOCK * RL_U), BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre,
                                                                 rkeys);
   k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
                                                                      m.rscan, lookback(c, 0));
