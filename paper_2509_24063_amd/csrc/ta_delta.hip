@@ -645,6 +645,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_bucket(JoinArgs a, const Seg* __
 // Loaded in stages for the scan's rounds together: partners and segments,
 // then segment bounds, sizes and reference headers, then partner headers.
 struct RMatchIn {
+  static constexpr int ROUNDS = 16;  // a tile of 8192 slots: fewer tiles to look back over
   Common cm;
   int32_t* m;
   const uint32_t* rwords;
@@ -700,6 +701,7 @@ struct RMatchIn {
   }
 };
 struct CNewIn {  // count << 34 | words of new current records; nlist[rank] = index of each new record
+  static constexpr int ROUNDS = 16;  // a tile of 8192 records
   const uint8_t* cflag;
   const uint32_t* cwords;
   uint32_t* nlist;
@@ -1739,6 +1741,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_rslots(Common cm, const uint8_t* 
 }
 
 struct DMatchIn {
+  static constexpr int ROUNDS = 16;  // a tile of 8192 slots
   const uint8_t* rmatch;
   const uint32_t* rwords;
   __device__ uint64_t operator()(int64_t g) const {
@@ -1750,6 +1753,7 @@ struct DMatchIn {
 // bytes, from their group size tables: segment and its table's offset for
 // the scan's rounds, then the table entries.
 struct DNewIn {
+  static constexpr int ROUNDS = 4;  // short scans: more tiles in flight
   Common cm;
   const uint8_t* enc;
   int64_t lo = 0, hi = 0;  // segments of the wave's items
@@ -1784,6 +1788,7 @@ struct DNewIn {
   }
 };
 struct DGroupIn {
+  static constexpr int ROUNDS = 4;  // short scans: more tiles in flight
   Common cm;
   const uint8_t* enc;
   int64_t lo = 0, hi = 0;  // segments of the wave's items
@@ -2626,7 +2631,7 @@ size_t encode_scratch(int64_t nseg, int64_t cur_len, int64_t ref_len, int64_t re
   Arena ar{nullptr, 0, 0};
   const Bounds b = enc_bounds(nseg, cur_len, ref_len, rec_cap);
   carve(ar, nseg, b, learned);
-  *tiles = std::max(ceil_div(std::max(std::max(std::max(b.C, b.R), b.E), b.G) + 1, SCAN_TILE),
+  *tiles = std::max(ceil_div(std::max(std::max(std::max(b.C, b.R), b.E), b.G) + 1, SCAN_TILE_MIN),
                     ceil_div(b.G, EG_TILE)) + 2;
   return ar.used + 256;
 }
@@ -2636,7 +2641,7 @@ size_t decode_scratch(int64_t nseg, int64_t enc_len, int64_t ref_len, int64_t ou
   Arena ar{nullptr, 0, 0};
   const Bounds b = dec_bounds(nseg, enc_len, ref_len, rec_cap);
   carve(ar, nseg, b, learned);
-  *tiles = ceil_div(std::max(std::max(b.C, b.R), b.G) + 1, SCAN_TILE) + 2;
+  *tiles = ceil_div(std::max(std::max(b.C, b.R), b.G) + 1, SCAN_TILE_MIN) + 2;
   return ar.used + 256;
 }
 }  // namespace ta
@@ -2696,15 +2701,15 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
       JoinArgs ja{m.cm, cur, ref, m.juid, m.jhdr, m.cwords, m.rwords, m.jcnt, m.jcnt_pre, m.part, m.m, m.cflag, m.tab,
                 ckeys, rkeys};
       k_join_count<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre);
-      k_scan<JCntIn><<<grid_for(c, b.E + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
+      k_scan<JCntIn><<<grid_for(c, b.E + 1, scan_tile<JCntIn>()), SCAN_BLOCK, 0, s>>>(JCntIn{m.jcnt}, m.cm.meta + 11, b.E, m.jcnt_pre,
                                                                        lookback(c, 0));
       k_join_scatter<<<grid_for(c, b.T, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.tpre, m.cm.cpre, m.cm.rpre, m.cm.jepre,
                                                            m.jcnt_pre);
       k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.bpre, m.cm.cpre, m.cm.jepre, m.jcnt_pre);
     }
-    k_scan<RMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
+    k_scan<RMatchIn><<<grid_for(c, b.R + 1, scan_tile<RMatchIn>()), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
                                                                        lookback(c, 1));
-    k_scan<CNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords, m.nlist}, m.cm.meta + 0, b.C, m.cscan,
+    k_scan<CNewIn><<<grid_for(c, b.C + 1, scan_tile<CNewIn>()), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords, m.nlist}, m.cm.meta + 0, b.C, m.cscan,
                                                                      lookback(c, 2));
     {
       const ColScan cs = col_scan(m.cm, {m.cm.gpre, m.cm.fxpre, m.cm.opre, m.cm.ppre}, {3, 9, -1, 4}, {b.G, -1, -1, -1});
@@ -2829,11 +2834,11 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   }
   k_dec_rslots<<<grid_for(c, b.R, BLOCK * RL_U), BLOCK, 0, s>>>(m.cm, enc, ref, m.rwords, m.cflag, m.cm.seg, m.cm.rpre,
                                                                 rkeys);
-  k_scan<DMatchIn><<<grid_for(c, b.R + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
+  k_scan<DMatchIn><<<grid_for(c, b.R + 1, scan_tile<DMatchIn>()), SCAN_BLOCK, 0, s>>>(DMatchIn{m.cflag, m.rwords}, m.cm.meta + 1, b.R,
                                                                      m.rscan, lookback(c, 0));
-  k_scan<DNewIn><<<grid_for(c, b.C + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, b.C, m.cscan,
+  k_scan<DNewIn><<<grid_for(c, b.C + 1, scan_tile<DNewIn>()), SCAN_BLOCK, 0, s>>>(DNewIn{m.cm, enc}, m.cm.meta + 6, b.C, m.cscan,
                                                                    lookback(c, 1));
-  k_scan<DGroupIn><<<grid_for(c, b.G + 1, SCAN_TILE), SCAN_BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, b.G, m.gex,
+  k_scan<DGroupIn><<<grid_for(c, b.G + 1, scan_tile<DGroupIn>()), SCAN_BLOCK, 0, s>>>(DGroupIn{m.cm, enc}, m.cm.meta + 3, b.G, m.gex,
                                                                      lookback(c, 2));
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
   k_dec_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords,

@@ -226,9 +226,25 @@ __device__ inline uint64_t lb_exclusive(const LookBack& lb, uint32_t t, uint64_t
 #define TA_SCAN_BLOCK 512
 #endif
 constexpr int SCAN_ROUNDS = TA_SCAN_ROUNDS;
-constexpr int SCAN_BLOCK = TA_SCAN_BLOCK;  // threads of a scan block (a tile is SCAN_BLOCK x SCAN_ROUNDS items)
+constexpr int SCAN_BLOCK = TA_SCAN_BLOCK;  // threads of a scan block (a tile is SCAN_BLOCK x rounds items)
 constexpr int SCAN_WAVES = SCAN_BLOCK / WAVE;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ROUNDS;
+// Rounds per thread of a functor's scan: SCAN_ROUNDS, or the functor's
+// static ROUNDS (4, 8 or 16) where measurement favours another tile: larger
+// tiles for dense scans over many items (fewer tiles to look back over),
+// smaller ones for short scans (more tiles in flight).  Look-back flag
+// arrays are sized for the smallest tile.
+constexpr int SCAN_ROUNDS_MIN = 4;
+constexpr int SCAN_TILE_MIN = SCAN_BLOCK * SCAN_ROUNDS_MIN;
+template <class In, class = void>
+struct scan_rounds : std::integral_constant<int, SCAN_ROUNDS> {};
+template <class In>
+struct scan_rounds<In, std::void_t<decltype(In::ROUNDS)>> : std::integral_constant<int, In::ROUNDS> {};
+template <class In>
+constexpr int scan_tile() {
+  static_assert(scan_rounds<In>::value >= SCAN_ROUNDS_MIN, "flag arrays are sized for SCAN_TILE_MIN");
+  return SCAN_BLOCK * scan_rounds<In>::value;
+}
 
 // A functor gives the value of item i with operator()(i).  It may define
 // wave_begin(first, last), called by all 64 lanes of a wave before it reads
@@ -262,6 +278,8 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan(In in, const int64_t* n_dev
   __shared__ uint64_t s_wave[SCAN_WAVES];
   __shared__ uint32_t s_ticket;
   __shared__ uint64_t s_prefix;
+  constexpr int R = scan_rounds<In>::value;
+  constexpr int64_t TILE = (int64_t)SCAN_BLOCK * R;
   lb_clear_next(lb);
   int64_t n = *n_dev;
   if (n > n_cap) {  // more items than the arrays hold: nothing is scanned
@@ -272,7 +290,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan(In in, const int64_t* n_dev
     if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
     return;
   }
-  const int64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  const int64_t ntiles = (n + TILE - 1) / TILE;
   // blocks beyond the tile count leave before taking a ticket: each ticket is
   // an atomic on one address, and they serialize
   if ((int64_t)blockIdx.x >= ntiles) return;
@@ -280,31 +298,31 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan(In in, const int64_t* n_dev
   for (;;) {
     const uint32_t t = lb_take_ticket(lb, &s_ticket);
     if ((int64_t)t >= ntiles) break;
-    const int64_t wbase = (int64_t)t * SCAN_TILE + (int64_t)wv * (WAVE * SCAN_ROUNDS);
+    const int64_t wbase = (int64_t)t * TILE + (int64_t)wv * (WAVE * R);
     In fn = in;
     if constexpr (has_wave_begin<In>::value) {
-      const int64_t last = wbase + WAVE * SCAN_ROUNDS - 1 < n ? wbase + WAVE * SCAN_ROUNDS - 1 : n - 1;
+      const int64_t last = wbase + WAVE * R - 1 < n ? wbase + WAVE * R - 1 : n - 1;
       fn.wave_begin(wbase < n ? wbase : n - 1, last);
     }
-    uint64_t v[SCAN_ROUNDS];
+    uint64_t v[R];
     if constexpr (has_values<In>::value) {
-      fn.template values<SCAN_ROUNDS>(wbase, n, v);
-    } else if (wbase + WAVE * SCAN_ROUNDS <= n) {  // uniform: every item of the wave exists
+      fn.template values<R>(wbase, n, v);
+    } else if (wbase + WAVE * R <= n) {  // uniform: every item of the wave exists
 #pragma unroll
-      for (int r = 0; r < SCAN_ROUNDS; ++r) v[r] = fn(wbase + r * WAVE + l);
+      for (int r = 0; r < R; ++r) v[r] = fn(wbase + r * WAVE + l);
     } else {
 #pragma unroll
-      for (int r = 0; r < SCAN_ROUNDS; ++r) {
+      for (int r = 0; r < R; ++r) {
         const int64_t i = wbase + r * WAVE + l;
         const uint64_t x = fn(i < n ? i : n - 1);
         v[r] = i < n ? x : 0;
       }
     }
     __builtin_amdgcn_sched_barrier(0);  // every item's loads before the first scan
-    uint64_t ex[SCAN_ROUNDS];
+    uint64_t ex[R];
     uint64_t carry = 0;
 #pragma unroll
-    for (int r = 0; r < SCAN_ROUNDS; ++r) {
+    for (int r = 0; r < R; ++r) {
       const uint64_t incl = wave_incl_scan64(v[r]);
       ex[r] = carry + incl - v[r];
       carry += readlane64(incl, WAVE - 1);
@@ -324,7 +342,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan(In in, const int64_t* n_dev
     __syncthreads();
     const uint64_t base = s_prefix + woff;
 #pragma unroll
-    for (int r = 0; r < SCAN_ROUNDS; ++r) {
+    for (int r = 0; r < R; ++r) {
       const int64_t i = wbase + r * WAVE + l;
       if (i < n) {
         out[i] = base + ex[r];
