@@ -168,8 +168,6 @@ struct Common {
   uint64_t* opre;  // [nseg+1] C' message offsets
   uint64_t* cols;  // [COL_MAX][nseg+1] per segment values to scan
   uint64_t* fold;  // [nseg][FOLD_SLOTS] partial XORs of reference uids (spread to avoid atomic contention)
-  uint32_t* sflag; // [nseg] learned encodings: bit 0 some group's learned block is smaller, bit 1 some
-                   // group's plain block is smaller
   int64_t* meta;   // [0] C records [1] R records [2] hash slots [3] groups [4] presence words [5] matched
                    // [6] new records [7] new words [8] unused [9] fixed bytes [10] join tiles
                    // [11] join count entries [12] join buckets [13] join bucket overflow
@@ -309,7 +307,6 @@ __device__ void enc_setup(Common cm, const uint8_t* cur, int64_t cur_len,
     g.hsize = hs;
     g.fold = 0;
     for (int k = 0; k < FOLD_SLOTS; ++k) cm.fold[s * FOLD_SLOTS + k] = 0;
-    cm.sflag[s] = 0;
     g.mode = 0;
     // join layout: B buckets, counting tiles of TJ items (C tiles, then R tiles)
     uint64_t B = pow2ceil((nc + nr + JB_TARGET - 1) / JB_TARGET);
@@ -1023,21 +1020,19 @@ struct GroupArgs {
   // learned calls only
   const uint64_t* pred_x;  // [matched][4] predicted words 2..5
   const uint8_t* pred_on;  // [matched] the record's words 2..5 are predicted
-  uint8_t* gch;            // [groups] 0 plain block written, 1 learned block (strictly smaller),
-                           // 2 plain block written for a tie whose learned block differs
+  uint8_t* gch;            // [groups] bits 0-1: 0 plain block written, 1 learned block (strictly
+                           // smaller), 2 plain block written for a tie whose learned block differs;
+                           // bit 2: the learned block is smaller, bit 3: the plain block is smaller
 };
 
-// Learned calls: the group's variant and the segment flags.  The block of a
-// group is the smaller one (learned on a strict win); a tie keeps the plain
-// bytes unless its segment turns out to be learned (mode 1), which
-// k_enc_fixup handles.  The size and so every block offset is min(plain,
-// learned) whatever the segment's mode.
-__device__ inline void note_choice(const Common& cm, int64_t s, uint32_t plain, uint32_t learned) {
-  const uint32_t bits = (learned < plain ? 1u : 0u) | (plain < learned ? 2u : 0u);
-  if (bits && lane_id() == 0 &&
-      (__hip_atomic_load(cm.sflag + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bits) != bits)
-    atomicOr(cm.sflag + s, bits);
-}
+// Learned calls: the group's variant.  The block of a group is the smaller
+// one (learned on a strict win); a tie keeps the plain bytes unless its
+// segment turns out to be learned (mode 1), which k_enc_fixup handles.  The
+// size and so every block offset is min(plain, learned) whatever the
+// segment's mode.  The group's choice byte also says which block was
+// smaller; k_choose_mode reduces those bits per segment (no atomics on the
+// segments' words while the groups are formed).
+constexpr uint8_t GCH_VARIANT = 3, GCH_LEARNED_SMALLER = 4, GCH_PLAIN_SMALLER = 8;
 
 // (segs, gpre, gseg, gfirst: read-only here; as restrict parameters their
 // uniform reads become scalar loads)
@@ -1181,7 +1176,7 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
           const uint32_t incl2 = wave_incl_scan32(len2);
           const uint32_t sig2 = (uint32_t)__builtin_amdgcn_readlane((int)incl2, 63);
           const uint32_t size2 = gv[x] ? ((((uint32_t)__popcll(bm2) + 1) / 2 + sig2 + 7) & ~7u) : 0u;
-          if (gv[x]) note_choice(cm, sx, size[x], size2);
+          const uint8_t smaller = (size2 < size[x] ? GCH_LEARNED_SMALLER : 0) | (size[x] < size2 ? GCH_PLAIN_SMALLER : 0);
           if (size2 < size[x]) {  // uniform
             D[x] = D2;
             bmw = bm2;
@@ -1191,6 +1186,7 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
           } else if (size2 == size[x] && __ballot(D2 != D[x])) {
             choice = 2;
           }
+          choice |= smaller;
         }
         if (gv[x] && l == 0) {
           a.bm[gc[x]] = bmw;
@@ -1254,14 +1250,41 @@ __global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg*
   }
 }
 
-// Learned calls: each segment's mode from its flags -- plain (0) when no
-// group's learned block is smaller, learned (1) when no group's plain block
-// is smaller, else mixed (2) (a mixed encoding is never larger than either).
-__global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm) {
+// Learned calls: each segment's mode from its groups' choice bytes -- plain
+// (0) when no group's learned block is smaller, learned (1) when no group's
+// plain block is smaller, else mixed (2) (a mixed encoding is never larger
+// than either).  One block per segment ORs the bits of its groups, 16 bytes
+// per thread and load where they are aligned.
+__global__ __launch_bounds__(BLOCK) void k_choose_mode(Common cm, const uint8_t* gch) {
+  __shared__ uint32_t s_or[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
-  for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < cm.nseg; s += (int64_t)gridDim.x * BLOCK) {
-    const uint32_t f = cm.sflag[s];
-    cm.seg[s].mode = !(f & 1u) ? 0 : (!(f & 2u) ? 1 : 2);
+  const int l = lane_id(), wv = wave_id();
+  for (int64_t s = blockIdx.x; s < cm.nseg; s += gridDim.x) {
+    const uint64_t g0 = cm.gpre[s], g1 = cm.gpre[s + 1];
+    uint32_t f = 0;
+    // the unaligned head and tail byte by byte, the aligned middle by 16 bytes
+    const uint64_t a0 = (g0 + 15) & ~15ull, a1 = g1 & ~15ull;
+    if (a0 >= a1) {
+      for (uint64_t g = g0 + threadIdx.x; g < g1; g += BLOCK) f |= gch[g];
+    } else {
+      for (uint64_t g = g0 + threadIdx.x; g < a0; g += BLOCK) f |= gch[g];
+      for (uint64_t g = a1 + threadIdx.x; g < g1; g += BLOCK) f |= gch[g];
+      const uint4* v = reinterpret_cast<const uint4*>(gch + a0);
+      for (uint64_t q = threadIdx.x; q < (a1 - a0) / 16; q += BLOCK) {
+        const uint4 w = v[q];
+        f |= w.x | w.y | w.z | w.w;
+      }
+    }
+    f = (f | (f >> 8) | (f >> 16) | (f >> 24)) & (GCH_LEARNED_SMALLER | GCH_PLAIN_SMALLER);
+    f = wave_or(f);
+    if (l == 0) s_or[wv] = f;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int i = 0; i < WAVES; ++i) t |= s_or[i];
+      cm.seg[s].mode = !(t & GCH_LEARNED_SMALLER) ? 0 : (!(t & GCH_PLAIN_SMALLER) ? 1 : 2);
+    }
+    __syncthreads();
   }
 }
 
@@ -1283,7 +1306,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixup(GroupArgs a, const Seg* __r
   for (int64_t b0 = ((int64_t)blockIdx.x * WAVES + wv) * WAVE; b0 < Gt; b0 += (int64_t)gridDim.x * WAVES * WAVE) {
     const int64_t mine = b0 + l;
     bool todo = false;
-    if (mine < Gt && a.gch[mine] == 2) todo = segs[gseg[mine]].mode == 1;
+    if (mine < Gt && (a.gch[mine] & GCH_VARIANT) == 2) todo = segs[gseg[mine]].mode == 1;
     uint64_t pending = __ballot(todo);
     while (pending) {
       const int lead = __ffsll((unsigned long long)pending) - 1;
@@ -1418,7 +1441,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
       *reinterpret_cast<uint64_t*>(sec + 8 * lg) = bm[gg];
       sec += 8 * g.G;
       // mixed segments: bit 7 marks a group whose block is the learned one
-      sec[lg] = (uint8_t)(gsz[gg] | (gch && g.mode == 2 && gch[gg] == 1 ? 0x80u : 0u));
+      sec[lg] = (uint8_t)(gsz[gg] | (gch && g.mode == 2 && (gch[gg] & GCH_VARIANT) == 1 ? 0x80u : 0u));
       if (lg == g.G - 1)
         for (uint64_t b = g.G; b < round8(g.G); ++b) sec[b] = 0;
     }
@@ -2535,7 +2558,6 @@ Mem carve(Arena& ar, int64_t nseg, const Bounds& b, bool learned) {
   m.cm.opre = ar.take<uint64_t>(nseg + 1);
   m.cm.cols = ar.take<uint64_t>(COL_MAX * (nseg + 1));
   m.cm.fold = ar.take<uint64_t>(FOLD_SLOTS * (nseg + 1));
-  m.cm.sflag = ar.take<uint32_t>(nseg + 1);
   m.cm.meta = ar.take<int64_t>(16);
   m.cm.status = nullptr;
   m.cm.op = 0;
@@ -2768,7 +2790,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
         k_enc_groups<1, true><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lb);
       else
         k_enc_groups<0, true><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lb);
-      k_choose_mode<<<gseg, BLOCK, 0, s>>>(m.cm);
+      k_choose_mode<<<grid_for(c, nseg, 1), BLOCK, 0, s>>>(m.cm, m.gch);
       const int gf = grid_for(c, b.G, WAVES * WAVE);
       if (c->diff_op)
         k_enc_fixup<1><<<gf, BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst);
