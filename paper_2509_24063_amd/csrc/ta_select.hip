@@ -8,13 +8,13 @@
 //
 // Kernels (all partitions in one launch each):
 //   k_sel_prep    one block: tiles per partition and their prefix
-//   k_sel_count   per 2048-agent tile: the 6-bit codes (1 byte/agent) and the
-//                 number of members per direction
+//   k_sel_count   per 2048-agent tile: the 6-bit codes (1 byte/agent), the
+//                 number of members per direction and whether it has any
 //   k_scan        look-back exclusive scan of the counts, laid out
 //                 [partition][direction][tile], which yields every tile's
 //                 output position in segment order
-//   k_sel_scatter per tile: stable compaction of store indices into the
-//                 segments, and the segment offsets
+//   k_sel_scatter per tile with members: stable compaction of store indices
+//                 into the segments, and the segment offsets
 #include <mutex>
 
 #include "ta_internal.hpp"
@@ -50,6 +50,7 @@ struct SelScratch {
   int64_t* tile_off;   // [P+1]
   uint32_t* cnt;       // [cnt_cap]
   uint64_t* cnt_pre;   // [cnt_cap+1]
+  uint8_t* tany;       // [tiles] 1 when some agent of the tile goes to some direction
   int64_t* meta;       // [0] tiles, [1] count entries
 };
 
@@ -161,12 +162,14 @@ __global__ __launch_bounds__(BLOCK) void k_sel_count(const double* f64, int64_t 
       for (int d = 0; d < NDIRS; ++d) s_cnt[wave_id()][d] = cnt[d];
     }
     __syncthreads();
-    if (threadIdx.x < NDIRS) {
+    if (threadIdx.x < NDIRS) {  // (the first wave's lanes)
       const int d = threadIdx.x;
       uint32_t sum = 0;
 #pragma unroll
       for (int wv = 0; wv < WAVES; ++wv) sum += s_cnt[wv][d];
       sc.cnt[sc.tile_off[ti.p] * NDIRS + d * ti.nt + ti.lt] = sum;
+      const uint64_t nz = __ballot(sum != 0);
+      if (d == 0) sc.tany[t] = nz != 0 ? 1 : 0;
     }
     __syncthreads();
   }
@@ -229,6 +232,9 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
   const int l = lane_id(), wv = wave_id();
   const int64_t ntiles = sc.meta[0];
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // (the same in the whole block) a tile none of whose agents is selected
+    // writes nothing: it skips its loads, scan and barriers
+    if (!uniform32(sc.tany[t])) continue;
     const TileInfo ti = tile_info(sc, part_off, P, t);
     const int64_t i0 = ti.a0 + (int64_t)threadIdx.x * SEL_IPT;
     uint32_t code[SEL_IPT];
@@ -333,6 +339,7 @@ SelScratch carve(Arena& ar, int64_t n, int64_t P, int ndirs) {
   sc.tile_off = ar.take<int64_t>(P + 1);
   sc.cnt = ar.take<uint32_t>(z.cnt_cap);
   sc.cnt_pre = ar.take<uint64_t>(z.cnt_cap + 1);
+  sc.tany = ar.take<uint8_t>(z.ntiles);
   sc.meta = ar.take<int64_t>(4);
   return sc;
 }
