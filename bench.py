@@ -257,6 +257,8 @@ def overlap_pass(ctx, native, cfg, dev_states, warmup, idx_cap, ser_cap):
     from paper_2509_24063_amd.exchange import OverlapPipeline
     pl = OverlapPipeline(cfg.schema, dev_states[0], cfg.w, cfg.ndirs, idx_cap, ser_cap)
     pl.reserve(max(s.n for s in dev_states))
+    # the stages' streams chosen by timing a few short trials (untimed here)
+    pl.tune_streams(dev_states[:8])
     for k in range(warmup):
         pl.step(dev_states[k])
     pl.check("overlap warm-up")

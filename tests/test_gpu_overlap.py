@@ -104,3 +104,27 @@ def test_overlapped_exchange_reusing_one_store(native):
     _same(outs[0], want[-2], "second to last")
     _same(outs[1], want[-1], "last")
     pl.close()
+
+
+def test_stream_tuning_keeps_results(native):
+    """Choosing the stages' streams by timing runs trial iterations and then
+    starts over: the exchange that follows still equals the oracle's."""
+    from paper_2509_24063_amd.exchange import OverlapPipeline, capacities
+    cfg = synth.config(3, median=300.0, grid=(2, 2, 2))
+    states = _states(cfg, 5)
+    want = _oracle(states, cfg)
+    ctx = native.Context(cfg.schema)
+    idx_cap, msgs_cap = capacities(ctx, states[0], cfg.ndirs, cfg.w, slack=1.5)
+    ctx.close()
+    dss = [native.DeviceStore(s) for s in states]
+    pl = OverlapPipeline(cfg.schema, dss[0], cfg.w, cfg.ndirs, idx_cap, msgs_cap)
+    pl.reserve(max(s.n for s in states))
+    print("[overlap] stream tuning", flush=True)
+    sec = pl.tune_streams(dss[::-1], trials=3, steps=2)
+    assert sec > 0 and pl.t == 0
+    for t, ds in enumerate(dss):
+        print(f"[overlap tuned] iteration {t}", flush=True)
+        pl.step(ds)
+    pl.check("end")
+    _same(pl.outputs(), want[-1], "last")
+    pl.close()
