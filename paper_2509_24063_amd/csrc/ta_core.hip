@@ -88,8 +88,10 @@ static bool listed(const std::string& list, const char* name) {
 Timed::Timed(ta_ctx* ctx, const char* nm, hipStream_t stream) : c(ctx), s(stream), name(nm) {
   on = !c->timed.empty() && listed(c->timed, nm);
   if (on) {
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
+    // (no system-scope fence when an event completes: the timestamps are all
+    // that is wanted, and the fence lengthens the gap around the kernels)
+    (void)hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
+    (void)hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
     (void)hipEventRecord(a, s);
   }
 }
