@@ -480,8 +480,7 @@ def per_partition_pass(native, cfg, host_states, warmup):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no multi-GPU path",
-              file=sys.stderr)
+        print(f"bench.py measures the exchange on one GPU only (asked for {args.gpus})", file=sys.stderr)
         sys.exit(2)
     import torch
 
