@@ -83,13 +83,14 @@ struct Seg {
   uint64_t cpw;               // word index of C' for residual position 0 (C' word of position d = cpw + d)
 };
 
-struct MDir {
-  uint64_t cword;   // encoder: C record word index in cur; decoder: unused
+// Directory entry of a matched record (learned calls, or a history to
+// write): where its reference record is, and its slot and segment.
+struct alignas(16) MDir {
   uint64_t rword;   // R record word index in ref
-  uint64_t dstart;  // global residual word position of the record
   uint64_t gs;      // global reference slot | segment << 34
 };
 __device__ inline int64_t mdir_seg(const MDir& e) { return (int64_t)(e.gs >> 34); }
+__device__ inline uint64_t mdir_slot(const MDir& e) { return e.gs & ((1ull << 34) - 1); }
 // Decoder: what unpacking one residual group needs, written by the
 // directory pass so that the unpack reads it with one 64-byte scalar load.
 struct alignas(64) GDesc {
@@ -106,7 +107,6 @@ struct alignas(64) GDesc {
 };
 static_assert(sizeof(GDesc) == 64, "one scalar load per group");
 
-[[maybe_unused]] __device__ inline uint64_t mdir_slot(const MDir& e) { return e.gs & ((1ull << 34) - 1); }
 
 
 // 64-bit bit mixer for hash buckets and table slots: D. Stafford's "Mix01"
@@ -887,12 +887,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
       const uint64_t k = rsv[u] >> PK;
       const uint64_t d = rsv[u] & WMASK;
       if (mdir) {  // learned mode or a history to write: the full entry
-        MDir e;
-        e.cword = sg.cbody / 8 + coff[u];
-        e.rword = sg.rbody / 8 + roff[u];
-        e.dstart = d;
-        e.gs = (uint64_t)g | ((uint64_t)sx << 34);
-        mdir[k] = e;
+        mdir[k] = MDir{sg.rbody / 8 + roff[u], (uint64_t)g | ((uint64_t)sx << 34)};
       }
       if (crw) crw[k] = (uint64_t)coff[u] | ((uint64_t)roff[u] << 32);
       if (okeys) {  // C' record k + (new records of earlier segments): the slot's uid and header
@@ -1929,12 +1924,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
       const uint64_t k = rsv[u] >> PK;
       const uint64_t d = rsv[u] & WMASK;
       if (mdir) {  // learned mode or a history to write: the full entry
-        MDir e;
-        e.cword = 0;
-        e.rword = sg.rbody / 8 + roff[u];
-        e.dstart = d;
-        e.gs = (uint64_t)g | ((uint64_t)sx << 34);
-        mdir[k] = e;
+        mdir[k] = MDir{sg.rbody / 8 + roff[u], (uint64_t)g | ((uint64_t)sx << 34)};
       }
       mstart[k] = d;
       mrw[k] = roff[u];  // word offset in the reference's record area
@@ -2298,6 +2288,7 @@ struct PredictArgs {
   int64_t ocap;
   // training-window tap (encoder only; tcount null: off)
   const uint64_t* cur;
+  const uint64_t* crw; // [matched] C (low) and R word offsets in the segments' record areas
   int32_t* tin;        // [tcap][12]
   float* ttgt;         // [tcap][4]
   int64_t tcap;
@@ -2387,7 +2378,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       float tg[4] = {0.f, 0.f, 0.f, 0.f};
       bool w = on;
       if (w) {
-        const uint64_t* crec = a.cur + e.cword;
+        const uint64_t* crec = a.cur + cm.seg[s].cbody / 8 + (uint32_t)a.crw[k];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const double d = (__longlong_as_double((long long)crec[2 + c]) -
@@ -2769,6 +2760,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                    hist_out ? hist_out->hlen : nullptr,
                    hist_out ? hist_out->cap : 0,
                    reinterpret_cast<const uint64_t*>(cur),
+                   m.crw,
                    c->tap_in,
                    c->tap_tgt,
                    c->tap_cap,
@@ -2886,6 +2878,7 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
                    hist_out ? hist_out->h2 : nullptr,
                    hist_out ? hist_out->hlen : nullptr,
                    hist_out ? hist_out->cap : 0,
+                   nullptr,
                    nullptr,
                    nullptr,
                    nullptr,
