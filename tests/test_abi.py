@@ -38,3 +38,15 @@ def test_host_side_bounds_without_gpu():
     L = native.lib()
     assert L.ta_serialize_bound(2, 3, 11) >= 2 * 32 + 16 + 3 * 88
     assert L.ta_delta_bound(1, 1000, 1000) >= 1000 + 64
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench measures one GPU; asked for more, it says so and exits
+    before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
