@@ -341,8 +341,8 @@ struct JoinArgs {
   Common cm;
   const uint8_t* cur;
   const uint8_t* ref;
-  uint64_t* juid;    // [C+R] uid of every item
-  uint64_t* jhdr;    // [C+R] header word of every item
+  uint64_t* juid;    // [C+R] uid of every item (items of a side without keys)
+  uint64_t* jhdr;    // [C+R] header word of every item (the same)
   uint32_t* cwords;
   uint32_t* rwords;
   uint32_t* cnt;     // [count entries] items per (segment, bucket, tile)
@@ -441,9 +441,10 @@ __global__ __launch_bounds__(BLOCK) void k_join_count(JoinArgs a, const Seg* __r
           bad = true;
           continue;
         }
-        const uint64_t item = gbase + i;
-        a.juid[item] = uid[u];
-        a.jhdr[item] = hdr[u];
+        if (!keys) {  // (uniform) a side with keys is read from them by the later passes
+          a.juid[gbase + i] = uid[u];
+          a.jhdr[gbase + i] = hdr[u];
+        }
         if (jt.isC) a.cwords[cpre[jt.s] + i] = (uint32_t)(hdr[u] >> 32);
         else a.rwords[rpre[jt.s] + i] = (uint32_t)(hdr[u] >> 32);
         atomicAdd(&s_hist[join_bucket(uid[u], B)], 1u);
@@ -492,6 +493,11 @@ __global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a, const Seg* _
     for (uint64_t b = threadIdx.x; b < B; b += BLOCK) s_off[b] = (uint32_t)(src[b * g.jT] - seg0);
     __syncthreads();
     const uint64_t gbase = jt.isC ? cpre[jt.s] : Ct + rpre[jt.s];
+    // the tile's uids: from its side's keys (every second word) or from the
+    // count pass's copies
+    const uint64_t* keys = jt.isC ? a.ckeys : a.rkeys;
+    const uint64_t* usrc = keys ? keys + 2 * (jt.isC ? cpre[jt.s] : rpre[jt.s]) : a.juid + gbase;
+    const uint64_t ust = keys ? 2 : 1;
     // JS_U items per thread and pass, their uids loaded together; each pair
     // goes out as one 16-byte store
     for (uint64_t i0 = jt.i0; i0 < jt.i1; i0 += (uint64_t)BLOCK * JS_U) {
@@ -499,7 +505,7 @@ __global__ __launch_bounds__(BLOCK) void k_join_scatter(JoinArgs a, const Seg* _
 #pragma unroll
       for (int u = 0; u < JS_U; ++u) {
         const uint64_t i = i0 + threadIdx.x + (uint64_t)u * BLOCK;
-        uid[u] = a.juid[gbase + (i < jt.i1 ? i : jt.i1 - 1)];
+        uid[u] = usrc[ust * (i < jt.i1 ? i : jt.i1 - 1)];
       }
 #pragma unroll
       for (int u = 0; u < JS_U; ++u) {
@@ -648,6 +654,8 @@ struct RMatchIn {
   const uint32_t* rwords;
   const uint64_t* jhdr;  // [C+R] header words: current records, then reference slots
   uint8_t* cflag;
+  const uint64_t* ckeys;  // nullable: the current records' header words are read from these
+  const uint64_t* rkeys;  // nullable: the same for the reference slots
   int64_t lo = 0, hi = 0;  // segments of the wave's slots
   __device__ void wave_begin(int64_t first, int64_t last) {
     lo = wave_last_le<uint64_t>(cm.rpre, 0, cm.nseg, (uint64_t)first);
@@ -657,6 +665,9 @@ struct RMatchIn {
   __device__ void values(int64_t wbase, int64_t n, uint64_t* v) const {
     const int l = lane_id();
     const uint64_t Ct = (uint64_t)cm.meta[0];
+    const uint64_t* hdr_r = rkeys ? rkeys + 1 : jhdr + Ct;
+    const uint64_t* hdr_c = ckeys ? ckeys + 1 : jhdr;
+    const uint64_t rst = rkeys ? 2 : 1, cst = ckeys ? 2 : 1;
     int64_t g[R], s[R];
     int32_t mi[R];
 #pragma unroll
@@ -674,7 +685,7 @@ struct RMatchIn {
       nc[r] = cm.seg[s[r]].nc;
       cp[r] = cm.cpre[s[r]];
       rw[r] = rwords[g[r]];
-      hr[r] = jhdr[Ct + (uint64_t)g[r]];
+      hr[r] = hdr_r[rst * (uint64_t)g[r]];
     }
     __builtin_amdgcn_sched_barrier(0);
     // (after an earlier error the join may not have run: stay inside the segment)
@@ -683,7 +694,7 @@ struct RMatchIn {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       ok[r] = mi[r] >= 0 && (uint64_t)mi[r] < nc[r];
-      hc[r] = ok[r] ? jhdr[cp[r] + (uint64_t)mi[r]] : 0;
+      hc[r] = ok[r] ? hdr_c[cst * (cp[r] + (uint64_t)mi[r])] : 0;
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -844,7 +855,8 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
                                                     const int32_t* m, const uint64_t* rscan, const uint32_t* rwords,
                                                     MDir* mdir, uint64_t* crw, uint64_t* mstart, uint8_t* newref,
                                                     uint32_t* gseg, uint32_t* gfirst, const uint64_t* juid,
-                                                    const uint64_t* jhdr, uint64_t* okeys, uint64_t okeys_cap) {
+                                                    const uint64_t* jhdr, const uint64_t* rkeys, uint64_t* okeys,
+                                                    uint64_t okeys_cap) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
@@ -893,7 +905,9 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
       if (okeys) {  // C' record k + (new records of earlier segments): the slot's uid and header
         const uint64_t Ct = (uint64_t)cm.meta[0], o = k + cm.npre[sx];
         if (o < okeys_cap)
-          *reinterpret_cast<ulonglong2*>(okeys + 2 * o) = ulonglong2{juid[Ct + (uint64_t)g], jhdr[Ct + (uint64_t)g]};
+          *reinterpret_cast<ulonglong2*>(okeys + 2 * o) =
+              rkeys ? *reinterpret_cast<const ulonglong2*>(rkeys + 2 * (uint64_t)g)
+                    : ulonglong2{juid[Ct + (uint64_t)g], jhdr[Ct + (uint64_t)g]};
         else
           fail(cm.status, ERR_CAPACITY);
       }
@@ -1479,7 +1493,7 @@ __device__ inline void copy_tab(const NewTab& t, int n, const uint64_t* src, uin
 __global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t* cscan, const uint32_t* nlist,
                                                        const uint32_t* cwords, const uint8_t* cur, uint8_t* enc,
                                                        uint8_t* newref, const uint64_t* juid, const uint64_t* jhdr,
-                                                       uint64_t* okeys, uint64_t okeys_cap) {
+                                                       const uint64_t* ckeys, uint64_t* okeys, uint64_t okeys_cap) {
   __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Nn = (int64_t)(cscan[cm.meta[0]] >> PK);
@@ -1506,7 +1520,9 @@ __global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t
       *reinterpret_cast<uint32_t*>(newref + g.oref + 32 + 4 * (g.n_match + r)) = (uint32_t)(g.W + qs);
       if (okeys) {  // C' record: after the segment's matched ones
         const uint64_t o = g.mbase + g.nbase + g.n_match + r;
-        if (o < okeys_cap) *reinterpret_cast<ulonglong2*>(okeys + 2 * o) = ulonglong2{juid[gc], jhdr[gc]};
+        if (o < okeys_cap)
+          *reinterpret_cast<ulonglong2*>(okeys + 2 * o) =
+              ckeys ? *reinterpret_cast<const ulonglong2*>(ckeys + 2 * (uint64_t)gc) : ulonglong2{juid[gc], jhdr[gc]};
         else fail(cm.status, ERR_CAPACITY);
       }
       t.src[l] = (g.cbody + 8 * (uint64_t)o) / 8;
@@ -2720,7 +2736,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
                                                            m.jcnt_pre);
       k_join_bucket<<<grid_for(c, b.B, 1), BLOCK, 0, s>>>(ja, m.cm.seg, m.cm.bpre, m.cm.cpre, m.cm.jepre, m.jcnt_pre);
     }
-    k_scan<RMatchIn><<<grid_for(c, b.R + 1, scan_tile<RMatchIn>()), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag}, m.cm.meta + 1, b.R, m.rscan,
+    k_scan<RMatchIn><<<grid_for(c, b.R + 1, scan_tile<RMatchIn>()), SCAN_BLOCK, 0, s>>>(RMatchIn{m.cm, m.m, m.rwords, m.jhdr, m.cflag, ckeys, rkeys}, m.cm.meta + 1, b.R, m.rscan,
                                                                        lookback(c, 1));
     k_scan<CNewIn><<<grid_for(c, b.C + 1, scan_tile<CNewIn>()), SCAN_BLOCK, 0, s>>>(CNewIn{m.cflag, m.cwords, m.nlist}, m.cm.meta + 0, b.C, m.cscan,
                                                                      lookback(c, 2));
@@ -2737,7 +2753,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords,
                                                                 pred || hist_out ? m.mdir : nullptr, m.crw,
                                                                 m.mstart, newref, m.gseg, m.gfirst, m.juid, m.jhdr,
-                                                                okeys, okeys_cap);
+                                                                rkeys, okeys, okeys_cap);
   }
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
@@ -2797,7 +2813,7 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
   }
   k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.bm, m.gsz, m.gch, m.gex, enc, enc_cap, enc_off, modes);
   k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.nlist, m.cwords, cur, enc, newref, m.juid,
-                                                          m.jhdr, okeys, okeys_cap);
+                                                          m.jhdr, ckeys, okeys, okeys_cap);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
                 hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap,

@@ -197,6 +197,7 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
   __shared__ uint32_t s_dm[64];       // per code: its directions, one bit each
   __shared__ uint32_t s_wm[WAVES];    // per wave: directions some of its agents belong to
   __shared__ uint32_t s_req[NDIRS];   // code bits each direction requires
+  __shared__ int64_t s_base[NDIRS];   // per direction: the tile's first output position
   const int64_t nseg = (int64_t)P * NDIRS;
   const int64_t gstride = (int64_t)gridDim.x * BLOCK;
   for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s <= nseg; s += gstride) {
@@ -236,6 +237,10 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
     // writes nothing: it skips its loads, scan and barriers
     if (!uniform32(sc.tany[t])) continue;
     const TileInfo ti = tile_info(sc, part_off, P, t);
+    const int64_t cbase = sc.tile_off[ti.p] * NDIRS + ti.lt;
+    // every direction's output position loaded at once, ahead of the scan,
+    // so that the direction loop below waits on no global load
+    if (threadIdx.x < NDIRS) s_base[threadIdx.x] = (int64_t)sc.cnt_pre[cbase + (int64_t)threadIdx.x * ti.nt];
     const int64_t i0 = ti.a0 + (int64_t)threadIdx.x * SEL_IPT;
     uint32_t code[SEL_IPT];
     uint64_t packed[NW];
@@ -280,7 +285,6 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
     if (lmask) atomicOr(&s_wm[wv], lmask);
     __syncthreads();
     const uint32_t wm = uniform32(s_wm[wv]);
-    const int64_t cbase = sc.tile_off[ti.p] * NDIRS + ti.lt;
     // the wave's directions, one at a time: the packed word of five
     // directions by a static index, its directions present by a uniform loop
 #pragma unroll
@@ -290,7 +294,7 @@ __global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, 
         const uint64_t mine = (packed[j] >> sh) & 0xFFF;
         if (!mine) continue;
         const uint32_t req = s_req[d];
-        int64_t pos = (int64_t)sc.cnt_pre[cbase + d * ti.nt] + (int64_t)((pre[j] >> sh) & 0xFFF);
+        int64_t pos = s_base[d] + (int64_t)((pre[j] >> sh) & 0xFFF);
 #pragma unroll
         for (int k = 0; k < SEL_IPT; ++k) {
           if (code[k] && member<EXACT>(code[k], req)) {
