@@ -31,14 +31,13 @@
 //                  picks each segment's mode, k_enc_fixup rewrites the rare
 //                  tied groups of learned segments
 //   k_enc_fixed    encoding offsets and headers; presence bitmaps, word
-//                  bitmaps, block size tables
-//   k_enc_newcopy  new record sizes, C' offsets of new records, new records
-//                  into the encoding and into C'
+//                  bitmaps, block size tables; then the new records: their
+//                  sizes, C' offsets and words, into the encoding and into C'
 // Decoder: k_dec_setup (header checks), k_dec_rslots (reference slots,
 // presence bits), scans of matched slots, new records and group blocks,
-// k_dec_seg2 (checks against the header, C' headers), k_dec_mdir, then
-// k_dec_unpack (group blocks -> residual -> C' = D xor X in one pass) and
-// k_dec_newcopy.
+// k_dec_seg2 (checks against the header, C' headers), k_dec_mdir (then the
+// new records into C'), then k_dec_unpack (group blocks -> residual -> C' =
+// D xor X in one pass).
 #include <initializer_list>
 
 #include "ta_internal.hpp"
@@ -1362,18 +1361,109 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixup(GroupArgs a, const Seg* __r
 }
 
 
+// Copies of the words a wave tabulated in t (t.q[n] words in all), NC_U per
+// lane in flight: all searches and loads first, then the stores.  dst2 may
+// be null.
+constexpr int NC_U = 4;
+__device__ inline void copy_tab(const NewTab& t, int n, const uint64_t* src, uint64_t* dst1, uint64_t* dst2) {
+  const uint64_t tot = t.q[n];
+  for (uint64_t q0 = lane_id(); q0 < tot; q0 += NC_U * WAVE) {
+    uint64_t v[NC_U], d1[NC_U], d2[NC_U];
+#pragma unroll
+    for (int j = 0; j < NC_U; ++j) {
+      const uint64_t q = q0 + (uint64_t)j * WAVE < tot ? q0 + (uint64_t)j * WAVE : tot - 1;
+      const int i = lds_last_le(t.q, n, q);
+      const uint64_t w = q - t.q[i];
+      v[j] = src[t.src[i] + w];
+      d1[j] = t.dst1[i] + w;
+      d2[j] = t.dst2[i] + w;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < NC_U; ++j)
+      if (q0 + (uint64_t)j * WAVE < tot) {
+        dst1[d1[j]] = v[j];
+        if (dst2) dst2[d2[j]] = v[j];
+      }
+  }
+}
+
+// New C records, 64 consecutive ones of the list the scan of new records
+// wrote (so that runs of new records spread over many waves), from the
+// wave's first rb: their sizes into the encoding's table, their C' offsets,
+// and their words into the encoding and into C', copied lane-parallel
+// (consecutive lanes, consecutive words) from a table in LDS.  The
+// segment's encoding offset is taken from the group block prefix (encm).
+__device__ inline void enc_new_wave(const Common& cm, int64_t rb, int64_t Nn, const uint64_t* cscan,
+                                    const uint32_t* nlist, const uint32_t* cwords, const uint8_t* cur,
+                                    uint8_t* enc, uint8_t* newref, const uint64_t* gex, const uint64_t* juid,
+                                    const uint64_t* jhdr, const uint64_t* ckeys, uint64_t* okeys,
+                                    uint64_t okeys_cap, NewTab& t) {
+  const int l = lane_id();
+  const int64_t k = rb + l;
+  const int n = (int)(Nn - rb < WAVE ? Nn - rb : WAVE);
+  const int64_t gc = nlist[k < Nn ? k : Nn - 1];
+  const int64_t sg = wave_seg(cm.cpre, cm.nseg, (uint64_t)gc, readlane64((uint64_t)gc, 0),
+                              readlane64((uint64_t)gc, n - 1));
+  const Seg& g = cm.seg[sg];
+  const uint64_t cs = cscan[gc];
+  const uint64_t words = k < Nn ? cwords[gc] : 0;
+  const uint32_t o = ld32(cur + g.cmsg + 32 + 4 * (uint64_t)(gc - (int64_t)cm.cpre[sg]));
+  if (k < Nn) {
+    const uint64_t encm = g.fixed_excl + gex[cm.gpre[sg]];
+    const uint64_t r = (cs >> PK) - g.nbase;      // index among the segment's new records
+    const uint64_t qs = (cs & WMASK) - g.npbase;  // word within the segment's new records
+    const uint64_t nn = g.n_match + g.n_new;
+    uint8_t* ns = enc + encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G);
+    *reinterpret_cast<uint32_t*>(ns + 4 * r) = (uint32_t)words;
+    if (r == g.n_new - 1 && (g.n_new & 1)) *reinterpret_cast<uint32_t*>(ns + 4 * (r + 1)) = 0;
+    *reinterpret_cast<uint32_t*>(newref + g.oref + 32 + 4 * (g.n_match + r)) = (uint32_t)(g.W + qs);
+    if (okeys) {  // C' record: after the segment's matched ones
+      const uint64_t ko = g.mbase + g.nbase + g.n_match + r;
+      if (ko < okeys_cap)
+        *reinterpret_cast<ulonglong2*>(okeys + 2 * ko) =
+            ckeys ? *reinterpret_cast<const ulonglong2*>(ckeys + 2 * (uint64_t)gc) : ulonglong2{juid[gc], jhdr[gc]};
+      else fail(cm.status, ERR_CAPACITY);
+    }
+    t.src[l] = (g.cbody + 8 * (uint64_t)o) / 8;
+    t.dst1[l] = (encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
+    t.dst2[l] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
+  }
+  const uint64_t winc = wave_incl_scan(words);
+  if (k < Nn) t.q[l] = winc - words;
+  if (l == WAVE - 1) t.q[n] = winc;
+  wave_sync();
+  copy_tab(t, n, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<uint64_t*>(enc),
+           reinterpret_cast<uint64_t*>(newref));
+  wave_sync();
+}
+
 constexpr int FX_PW = 8;  // presence words per wave in k_enc_fixed
 
 // The encodings' offsets and headers (per segment), then their fixed
 // sections: presence bitmaps (one wave per 64 reference slots), word bitmaps
-// and block size tables (per group).  The new record sizes and the C'
-// offsets of new records are written by k_enc_newcopy.  A segment's encoding starts at its fixed bytes' prefix plus the
-// block bytes before its first group.  The offsets are written even when the
-// encodings do not fit (they give the size needed).
+// and block size tables (per group), then the new records (enc_new_wave, 64
+// to a wave).  A segment's encoding starts at its fixed bytes' prefix plus
+// the block bytes before its first group.  The offsets are written even
+// when the encodings do not fit (they give the size needed); nothing else is
+// written then.
+struct NewArgs {
+  const uint64_t* cscan;
+  const uint32_t* nlist;
+  const uint32_t* cwords;
+  const uint8_t* cur;
+  uint8_t* newref;
+  const uint64_t* juid;
+  const uint64_t* jhdr;
+  const uint64_t* ckeys;
+  uint64_t* okeys;
+  uint64_t okeys_cap;
+};
 __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m, const uint64_t* bm,
                                                      const uint8_t* gsz, const uint8_t* gch, const uint64_t* gex,
                                                      uint8_t* enc, int64_t enc_cap, int64_t* enc_off,
-                                                     uint8_t* modes) {
+                                                     uint8_t* modes, NewArgs na) {
+  __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
   const uint64_t total_bytes = (uint64_t)cm.meta[9] + gex[cm.meta[3]];
   const bool fits = total_bytes <= (uint64_t)enc_cap;
@@ -1400,15 +1490,21 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
   }
   if (!fits) return;
   auto encm = [&](int64_t s) { return cm.seg[s].fixed_excl + gex[cm.gpre[s]]; };
-  // presence words first, FX_PW to a wave (the slot loads of all FX_PW words
-  // in flight at once), then groups, 64 to a wave
+  // wave tasks: presence words first, FX_PW to a wave (the slot loads of all
+  // FX_PW words in flight at once), then groups, 64 to a wave, then new
+  // records, 64 to a wave
   const int64_t P = cm.meta[4], B = cm.meta[3];
-  const int64_t TP = (P + FX_PW - 1) / FX_PW, TG = (B + 63) / 64;
+  const int64_t Nn = (int64_t)(na.cscan[cm.meta[0]] >> PK);
+  const int64_t TP = (P + FX_PW - 1) / FX_PW, TG = (B + 63) / 64, TN = (Nn + WAVE - 1) / WAVE;
   const int l = lane_id();
-  for (int64_t task = (int64_t)blockIdx.x * WAVES + wave_id(); task < TP + TG; task += (int64_t)gridDim.x * WAVES) {
+  for (int64_t task = (int64_t)blockIdx.x * WAVES + wave_id(); task < TP + TG + TN;
+       task += (int64_t)gridDim.x * WAVES) {
     const int64_t wbase = 64 * (task - TP);  // groups: the wave's first group
     const int64_t it = wbase + l;
-    if (task < TP) {
+    if (task >= TP + TG) {
+      enc_new_wave(cm, WAVE * (task - TP - TG), Nn, na.cscan, na.nlist, na.cwords, na.cur, enc, na.newref, gex,
+                   na.juid, na.jhdr, na.ckeys, na.okeys, na.okeys_cap, s_t[wave_id()]);
+    } else if (task < TP) {
       const int64_t pw0 = task * FX_PW, pl = pw0 + FX_PW - 1 < P ? pw0 + FX_PW - 1 : P - 1;
       const int64_t lo = seg_of(cm.ppre, cm.nseg, (uint64_t)pw0);
       const int64_t hi = last_le<uint64_t>(cm.ppre, lo, cm.nseg, (uint64_t)pl);
@@ -1454,88 +1550,6 @@ __global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m
       if (lg == g.G - 1)
         for (uint64_t b = g.G; b < round8(g.G); ++b) sec[b] = 0;
     }
-  }
-}
-
-// Copies of the words a wave tabulated in t (t.q[n] words in all), NC_U per
-// lane in flight: all searches and loads first, then the stores.  dst2 may
-// be null.
-constexpr int NC_U = 4;
-__device__ inline void copy_tab(const NewTab& t, int n, const uint64_t* src, uint64_t* dst1, uint64_t* dst2) {
-  const uint64_t tot = t.q[n];
-  for (uint64_t q0 = lane_id(); q0 < tot; q0 += NC_U * WAVE) {
-    uint64_t v[NC_U], d1[NC_U], d2[NC_U];
-#pragma unroll
-    for (int j = 0; j < NC_U; ++j) {
-      const uint64_t q = q0 + (uint64_t)j * WAVE < tot ? q0 + (uint64_t)j * WAVE : tot - 1;
-      const int i = lds_last_le(t.q, n, q);
-      const uint64_t w = q - t.q[i];
-      v[j] = src[t.src[i] + w];
-      d1[j] = t.dst1[i] + w;
-      d2[j] = t.dst2[i] + w;
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < NC_U; ++j)
-      if (q0 + (uint64_t)j * WAVE < tot) {
-        dst1[d1[j]] = v[j];
-        if (dst2) dst2[d2[j]] = v[j];
-      }
-  }
-}
-
-// New C records: their sizes into the encoding's table, their C' offsets,
-// and their words into the encoding and into C'.  A wave takes 64
-// consecutive new records from the list the scan of new records wrote (so
-// that runs of new records spread over many waves), tabulates them in LDS
-// and copies their words lane-parallel (consecutive lanes, consecutive
-// words).
-__global__ __launch_bounds__(BLOCK) void k_enc_newcopy(Common cm, const uint64_t* cscan, const uint32_t* nlist,
-                                                       const uint32_t* cwords, const uint8_t* cur, uint8_t* enc,
-                                                       uint8_t* newref, const uint64_t* juid, const uint64_t* jhdr,
-                                                       const uint64_t* ckeys, uint64_t* okeys, uint64_t okeys_cap) {
-  __shared__ NewTab s_t[WAVES];
-  if (status_of(cm.status) & ANY_ERR) return;
-  const int64_t Nn = (int64_t)(cscan[cm.meta[0]] >> PK);
-  const int l = lane_id(), wv = wave_id();
-  NewTab& t = s_t[wv];
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t rb = ((int64_t)blockIdx.x * WAVES + wv) * WAVE; rb < Nn; rb += stride) {
-    const int64_t k = rb + l;
-    const int n = (int)(Nn - rb < WAVE ? Nn - rb : WAVE);
-    const int64_t gc = nlist[k < Nn ? k : Nn - 1];
-    const int64_t sg = wave_seg(cm.cpre, cm.nseg, (uint64_t)gc, readlane64((uint64_t)gc, 0),
-                                readlane64((uint64_t)gc, n - 1));
-    const Seg& g = cm.seg[sg];
-    const uint64_t cs = cscan[gc];
-    const uint64_t words = k < Nn ? cwords[gc] : 0;
-    const uint32_t o = ld32(cur + g.cmsg + 32 + 4 * (uint64_t)(gc - (int64_t)cm.cpre[sg]));
-    if (k < Nn) {
-      const uint64_t r = (cs >> PK) - g.nbase;      // index among the segment's new records
-      const uint64_t qs = (cs & WMASK) - g.npbase;  // word within the segment's new records
-      const uint64_t nn = g.n_match + g.n_new;
-      uint8_t* ns = enc + g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G);
-      *reinterpret_cast<uint32_t*>(ns + 4 * r) = (uint32_t)words;
-      if (r == g.n_new - 1 && (g.n_new & 1)) *reinterpret_cast<uint32_t*>(ns + 4 * (r + 1)) = 0;
-      *reinterpret_cast<uint32_t*>(newref + g.oref + 32 + 4 * (g.n_match + r)) = (uint32_t)(g.W + qs);
-      if (okeys) {  // C' record: after the segment's matched ones
-        const uint64_t o = g.mbase + g.nbase + g.n_match + r;
-        if (o < okeys_cap)
-          *reinterpret_cast<ulonglong2*>(okeys + 2 * o) =
-              ckeys ? *reinterpret_cast<const ulonglong2*>(ckeys + 2 * (uint64_t)gc) : ulonglong2{juid[gc], jhdr[gc]};
-        else fail(cm.status, ERR_CAPACITY);
-      }
-      t.src[l] = (g.cbody + 8 * (uint64_t)o) / 8;
-      t.dst1[l] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
-      t.dst2[l] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
-    }
-    const uint64_t winc = wave_incl_scan(words);
-    if (k < Nn) t.q[l] = winc - words;
-    if (l == WAVE - 1) t.q[n] = winc;
-    wave_sync();
-    copy_tab(t, n, reinterpret_cast<const uint64_t*>(cur), reinterpret_cast<uint64_t*>(enc),
-             reinterpret_cast<uint64_t*>(newref));
-    wave_sync();
   }
 }
 
@@ -1897,16 +1911,84 @@ __global__ __launch_bounds__(BLOCK) void k_dec_seg2(Common cm, const uint64_t* r
   }
 }
 
+// New records from the encoding into C', and their offsets, for the 64 new
+// records from the wave's first rb: tabulated in LDS, their words copied
+// lane-parallel.  A new record's uid must be non-zero and its header must
+// give the size the table announced.
+__device__ inline void dec_new_wave(const Common& cm, int64_t rb, int64_t Nn, const uint64_t* nscan,
+                                    const uint8_t* enc, uint8_t* out, uint64_t* okeys, uint64_t okeys_cap,
+                                    NewTab& t) {
+  const int l = lane_id();
+  const uint64_t* e64 = reinterpret_cast<const uint64_t*>(enc);
+  uint64_t* o64 = reinterpret_cast<uint64_t*>(out);
+  const int64_t r = rb + l;
+  const int64_t re = rb + WAVE - 1 < Nn ? rb + WAVE - 1 : Nn - 1;
+  const int n = (int)(re - rb + 1);
+  const int64_t s = wave_seg(cm.npre, cm.nseg, (uint64_t)(r < Nn ? r : Nn - 1), (uint64_t)rb, (uint64_t)re);
+  if (r < Nn) {
+    const Seg& g = cm.seg[s];
+    const uint64_t qs = nscan[r] - g.npbase;
+    const uint64_t nn = g.n_match + g.n_new;
+    t.q[l] = nscan[r] - nscan[rb];
+    t.src[l] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
+    t.dst1[l] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
+    t.dst2[l] = nscan[r + 1] - nscan[r];  // size
+    t.kidx[l] = g.mbase + g.n_match + (uint64_t)r;  // the record's index among all C' records
+    *reinterpret_cast<uint32_t*>(out + g.oref + 32 + 4 * (g.n_match + (uint64_t)r - cm.npre[s])) =
+        (uint32_t)(g.W + qs);
+  }
+  if (l == 0) t.q[n] = nscan[rb + n] - nscan[rb];
+  wave_sync();
+  const uint64_t tot = t.q[n];
+  bool bad = false, cap = false;
+  for (uint64_t q0 = l; q0 < tot; q0 += NC_U * WAVE) {  // NC_U words per lane in flight
+    uint64_t v[NC_U], d[NC_U], w[NC_U], sz[NC_U], ki[NC_U];
+#pragma unroll
+    for (int j = 0; j < NC_U; ++j) {
+      const uint64_t q = q0 + (uint64_t)j * WAVE < tot ? q0 + (uint64_t)j * WAVE : tot - 1;
+      const int i = lds_last_le(t.q, n, q);
+      w[j] = q - t.q[i];
+      v[j] = e64[t.src[i] + w[j]];
+      d[j] = t.dst1[i] + w[j];
+      sz[j] = t.dst2[i];
+      ki[j] = t.kidx[i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < NC_U; ++j)
+      if (q0 + (uint64_t)j * WAVE < tot) {
+        if ((w[j] == 0 && v[j] == 0) || (w[j] == 1 && (v[j] >> 32) != sz[j])) bad = true;
+        o64[d[j]] = v[j];
+        if (okeys && w[j] < 2) {  // the record's uid and header word
+          if (ki[j] < okeys_cap) okeys[2 * ki[j] + w[j]] = v[j];
+          else cap = true;
+        }
+      }
+  }
+  if (__ballot(bad) && l == 0) fail(cm.status, ERR_CORRUPT);
+  if (__ballot(cap) && l == 0) fail(cm.status, ERR_CAPACITY);
+  wave_sync();
+}
+
 // Directory of the matched records (decoder): R word, residual start,
 // slot; word offsets of the records in the reference's record area; C'
 // offsets; the descriptors of the residual groups.  Staged like the
-// encoder's.
+// encoder's.  Then the new records into C' (dec_new_wave): only the
+// unpacking follows, and it writes other words of C'.  hist_cap >= 0
+// (learned calls): the history's capacity, checked here, before any new
+// record is copied, as the neighbour table's pass checks it.
 __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* ref, const uint8_t* rmatch,
                                                     const uint64_t* rscan, const uint32_t* rwords, MDir* mdir,
                                                     uint64_t* mstart, uint8_t* out, const uint8_t* enc,
                                                     const uint64_t* gex, GDesc* gdesc, uint32_t* mrw,
-                                                    const uint64_t* rkeys, uint64_t* okeys, uint64_t okeys_cap) {
+                                                    const uint64_t* rkeys, uint64_t* okeys, uint64_t okeys_cap,
+                                                    const uint64_t* nscan, int64_t hist_cap) {
+  __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
+  if (hist_cap >= 0 && hist_cap < cm.meta[1]) {  // the prediction's history must cover every reference slot
+    if (blockIdx.x == 0 && threadIdx.x == 0) fail(cm.status, ERR_INVALID);
+    return;
+  }
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
   constexpr int64_t SPAN = (int64_t)WAVE * RS_U;
@@ -1955,6 +2037,10 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
       map_groups_dec(cm, sg, sx, d - sg.dbase, rwv[u], k, enc, gex, gdesc);
     }
   }
+  // then the new records, 64 to a wave
+  const int64_t Nn = cm.meta[6];
+  for (int64_t rb = ((int64_t)blockIdx.x * WAVES + wave_id()) * WAVE; rb < Nn; rb += nwv * WAVE)
+    dec_new_wave(cm, rb, Nn, nscan, enc, out, okeys, okeys_cap, s_t[wave_id()]);
 }
 
 struct UnpackArgs {
@@ -2131,70 +2217,6 @@ __global__ __launch_bounds__(BLOCK) void k_dec_unpack(UnpackArgs a, const GDesc*
   if (__ballot(anybad) && l == 0) fail(cm.status, ERR_CORRUPT);
 }
 
-// New records from the encoding into C', and their offsets: a wave takes
-// 64 new records, tabulates them in LDS and copies their words
-// lane-parallel.  A new record's uid must be non-zero and its header must
-// give the size the table announced.
-__global__ __launch_bounds__(BLOCK) void k_dec_newcopy(Common cm, const uint64_t* nscan, const uint8_t* enc,
-                                                       uint8_t* out, uint64_t* okeys, uint64_t okeys_cap) {
-  __shared__ NewTab s_t[WAVES];
-  if (status_of(cm.status) & ANY_ERR) return;
-  const int64_t Nn = cm.meta[6];
-  const int l = lane_id(), wv = wave_id();
-  NewTab& t = s_t[wv];
-  const uint64_t* e64 = reinterpret_cast<const uint64_t*>(enc);
-  uint64_t* o64 = reinterpret_cast<uint64_t*>(out);
-  const int64_t stride = (int64_t)gridDim.x * BLOCK;
-  for (int64_t rb = (int64_t)blockIdx.x * BLOCK + wv * WAVE; rb < Nn; rb += stride) {
-    const int64_t r = rb + l;
-    const int64_t re = rb + WAVE - 1 < Nn ? rb + WAVE - 1 : Nn - 1;
-    const int n = (int)(re - rb + 1);
-    const int64_t s = wave_seg(cm.npre, cm.nseg, (uint64_t)(r < Nn ? r : Nn - 1), (uint64_t)rb, (uint64_t)re);
-    if (r < Nn) {
-      const Seg& g = cm.seg[s];
-      const uint64_t qs = nscan[r] - g.npbase;
-      const uint64_t nn = g.n_match + g.n_new;
-      t.q[l] = nscan[r] - nscan[rb];
-      t.src[l] = (g.encm + 64 + 8 * g.PG + 8 * g.G + round8(g.G) + round8(4 * g.n_new)) / 8 + qs;
-      t.dst1[l] = (g.oref + 32 + 8 * ((nn + 1) / 2)) / 8 + g.W + qs;
-      t.dst2[l] = nscan[r + 1] - nscan[r];  // size
-      t.kidx[l] = g.mbase + g.n_match + (uint64_t)r;  // the record's index among all C' records
-      *reinterpret_cast<uint32_t*>(out + g.oref + 32 + 4 * (g.n_match + (uint64_t)r - cm.npre[s])) =
-          (uint32_t)(g.W + qs);
-    }
-    if (l == 0) t.q[n] = nscan[rb + n] - nscan[rb];
-    wave_sync();
-    const uint64_t tot = t.q[n];
-    bool bad = false, cap = false;
-    for (uint64_t q0 = l; q0 < tot; q0 += NC_U * WAVE) {  // NC_U words per lane in flight
-      uint64_t v[NC_U], d[NC_U], w[NC_U], sz[NC_U], ki[NC_U];
-#pragma unroll
-      for (int j = 0; j < NC_U; ++j) {
-        const uint64_t q = q0 + (uint64_t)j * WAVE < tot ? q0 + (uint64_t)j * WAVE : tot - 1;
-        const int i = lds_last_le(t.q, n, q);
-        w[j] = q - t.q[i];
-        v[j] = e64[t.src[i] + w[j]];
-        d[j] = t.dst1[i] + w[j];
-        sz[j] = t.dst2[i];
-        ki[j] = t.kidx[i];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int j = 0; j < NC_U; ++j)
-        if (q0 + (uint64_t)j * WAVE < tot) {
-          if ((w[j] == 0 && v[j] == 0) || (w[j] == 1 && (v[j] >> 32) != sz[j])) bad = true;
-          o64[d[j]] = v[j];
-          if (okeys && w[j] < 2) {  // the record's uid and header word
-            if (ki[j] < okeys_cap) okeys[2 * ki[j] + w[j]] = v[j];
-            else cap = true;
-          }
-        }
-    }
-    if (__ballot(bad) && l == 0) fail(cm.status, ERR_CORRUPT);
-    if (__ballot(cap) && l == 0) fail(cm.status, ERR_CAPACITY);
-    wave_sync();
-  }
-}
 
 
 // ---------------------------------------------------------------------------
@@ -2811,9 +2833,9 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
         k_enc_groups<0, false><<<gg, EG_BLOCK, 0, s>>>(ga, m.cm.seg, m.cm.gpre, m.gseg, m.gfirst, lb);
     }
   }
-  k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.bm, m.gsz, m.gch, m.gex, enc, enc_cap, enc_off, modes);
-  k_enc_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, m.nlist, m.cwords, cur, enc, newref, m.juid,
-                                                          m.jhdr, ckeys, okeys, okeys_cap);
+  k_enc_fixed<<<g, BLOCK, 0, s>>>(m.cm, m.m, m.bm, m.gsz, m.gch, m.gex, enc, enc_cap, enc_off, modes,
+                                  NewArgs{m.cscan, m.nlist, m.cwords, cur, newref, m.juid, m.jhdr, ckeys, okeys,
+                                          (uint64_t)okeys_cap});
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
                 hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap,
@@ -2873,7 +2895,8 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_dec_seg2<<<gseg, BLOCK, 0, s>>>(m.cm, m.rscan, m.cscan, m.gex, out, out_cap, out_off, m.mstart);
   k_dec_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords,
                                                               pred || hist_out ? m.mdir : nullptr, m.mstart, out, enc,
-                                                              m.gex, m.gdesc, m.mrw, rkeys, okeys, okeys_cap);
+                                                              m.gex, m.gdesc, m.mrw, rkeys, okeys, okeys_cap, m.cscan,
+                                                              pred && hist_in ? hist_in->cap : -1);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
     Timed tm(c, "predict", s);
@@ -2915,7 +2938,6 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
     else
       k_dec_unpack<0><<<gu, BLOCK, 0, s>>>(ua, m.gdesc, enc);
   }
-  k_dec_newcopy<<<grid_for(c, b.C, BLOCK), BLOCK, 0, s>>>(m.cm, m.cscan, enc, out, okeys, okeys_cap);
   if (hist_out) {
     HistArgs ha{m.cm, reinterpret_cast<const uint64_t*>(ref), m.mdir, hist_in ? hist_in->h1 : nullptr,
                 hist_in ? hist_in->hlen : nullptr, hist_out->h1, hist_out->h2, hist_out->hlen, hist_out->cap,
