@@ -845,17 +845,32 @@ __device__ inline void map_groups_dec(const Common& cm, const Seg& sg, int64_t s
   }
 }
 
+// Learned calls: the neighbour table's entries cleared whole, as 16-byte
+// stores (the table is 256-byte aligned), by the grid of the pass that runs
+// before the table is built; hist_cap must cover every reference slot.
+__device__ inline void nbr_clear(const Common& cm, Entry* tab, int64_t hist_cap) {
+  if (hist_cap < cm.meta[1]) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) fail(cm.status, ERR_INVALID);
+    return;
+  }
+  static_assert(sizeof(Entry) == 16, "one 16-byte store per entry");
+  const int64_t H = cm.meta[2];
+  ulonglong2* t = reinterpret_cast<ulonglong2*>(tab);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < H; i += (int64_t)gridDim.x * blockDim.x)
+    t[i] = ulonglong2{0, 0};
+}
+
 // Directory of the matched records, in C' order: C and R word, residual
 // start, slot (learned mode), or the C and R word offsets in the segment's
 // record areas (plain mode); C' offsets; groups' segment and first record.  A wave takes
 // RS_U * 64 consecutive reference slots per pass and issues their loads in
 // two stages before it stores anything.
-__global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
                                                     const int32_t* m, const uint64_t* rscan, const uint32_t* rwords,
                                                     MDir* mdir, uint64_t* crw, uint64_t* mstart, uint8_t* newref,
                                                     uint32_t* gseg, uint32_t* gfirst, const uint64_t* juid,
                                                     const uint64_t* jhdr, const uint64_t* rkeys, uint64_t* okeys,
-                                                    uint64_t okeys_cap) {
+                                                    uint64_t okeys_cap, Entry* ntab, int64_t hist_cap) {
   if (status_of(cm.status) & ANY_ERR) return;
   const int64_t Rt = cm.meta[1];
   const int l = lane_id();
@@ -915,6 +930,7 @@ __global__ __launch_bounds__(BLOCK) void k_enc_mdir(Common cm, const uint8_t* cu
       map_groups(cm, sx, d - sg.dbase, rwv[u], gseg, gfirst, k);
     }
   }
+  if (ntab) nbr_clear(cm, ntab, hist_cap);
 }
 
 // Assemble the block of one group in LDS (b64: BLK_MAX/8 + 1 words).
@@ -1459,7 +1475,7 @@ struct NewArgs {
   uint64_t* okeys;
   uint64_t okeys_cap;
 };
-__global__ __launch_bounds__(BLOCK) void k_enc_fixed(Common cm, const int32_t* m, const uint64_t* bm,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_enc_fixed(Common cm, const int32_t* m, const uint64_t* bm,
                                                      const uint8_t* gsz, const uint8_t* gch, const uint64_t* gex,
                                                      uint8_t* enc, int64_t enc_cap, int64_t* enc_off,
                                                      uint8_t* modes, NewArgs na) {
@@ -1982,7 +1998,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
                                                     uint64_t* mstart, uint8_t* out, const uint8_t* enc,
                                                     const uint64_t* gex, GDesc* gdesc, uint32_t* mrw,
                                                     const uint64_t* rkeys, uint64_t* okeys, uint64_t okeys_cap,
-                                                    const uint64_t* nscan, int64_t hist_cap) {
+                                                    const uint64_t* nscan, int64_t hist_cap, Entry* ntab) {
   __shared__ NewTab s_t[WAVES];
   if (status_of(cm.status) & ANY_ERR) return;
   if (hist_cap >= 0 && hist_cap < cm.meta[1]) {  // the prediction's history must cover every reference slot
@@ -2041,6 +2057,7 @@ __global__ __launch_bounds__(BLOCK) void k_dec_mdir(Common cm, const uint8_t* re
   const int64_t Nn = cm.meta[6];
   for (int64_t rb = ((int64_t)blockIdx.x * WAVES + wave_id()) * WAVE; rb < Nn; rb += nwv * WAVE)
     dec_new_wave(cm, rb, Nn, nscan, enc, out, okeys, okeys_cap, s_t[wave_id()]);
+  if (ntab) nbr_clear(cm, ntab, hist_cap);
 }
 
 struct UnpackArgs {
@@ -2239,21 +2256,7 @@ __device__ inline bool cell_key_of(const uint64_t* x, double cell, uint64_t* key
 }
 
 // Neighbour counts: per segment, an open-addressing table of the cells of
-// its reference records (key, count).  Entries are cleared whole, as
-// 16-byte stores (the table is 256-byte aligned).
-__global__ __launch_bounds__(BLOCK) void k_nbr_clear(Common cm, Entry* tab, int64_t hist_cap) {
-  if (status_of(cm.status) & ANY_ERR) return;
-  if (hist_cap < cm.meta[1]) {  // the history must cover every reference slot
-    if (blockIdx.x == 0 && threadIdx.x == 0) fail(cm.status, ERR_INVALID);
-    return;
-  }
-  static_assert(sizeof(Entry) == 16, "one 16-byte store per entry");
-  const int64_t H = cm.meta[2];
-  ulonglong2* t = reinterpret_cast<ulonglong2*>(tab);
-  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < H; i += (int64_t)gridDim.x * BLOCK)
-    t[i] = ulonglong2{0, 0};
-}
-
+// its reference records (key, count), cleared by the directory pass before.
 __device__ inline uint64_t ref_record_word(const Common& cm, const uint8_t* ref, int64_t s, uint64_t j) {
   const Seg& g = cm.seg[s];
   return g.rbody / 8 + ld32(ref + g.rmsg + 32 + 4 * j);
@@ -2775,12 +2778,12 @@ extern "C" ta_status ta_delta_encode(ta_ctx* c, int64_t nseg, const uint8_t* cur
     k_enc_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, cur, ref, m.m, m.rscan, m.rwords,
                                                                 pred || hist_out ? m.mdir : nullptr, m.crw,
                                                                 m.mstart, newref, m.gseg, m.gfirst, m.juid, m.jhdr,
-                                                                rkeys, okeys, okeys_cap);
+                                                                rkeys, okeys, okeys_cap, pred ? m.tab : nullptr,
+                                                                pred && hist_in ? hist_in->cap : 0);
   }
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
     Timed tm(c, "predict", s);
-    k_nbr_clear<<<g, BLOCK, 0, s>>>(m.cm, m.tab, hist_in->cap);
     k_nbr_build<<<g, BLOCK, 0, s>>>(m.cm, ref, pw, m.tab);
     PredictArgs pa{m.cm,
                    reinterpret_cast<const uint64_t*>(ref),
@@ -2896,11 +2899,11 @@ extern "C" ta_status ta_delta_decode(ta_ctx* c, int64_t nseg, const uint8_t* enc
   k_dec_mdir<<<grid_for(c, b.R, BLOCK * RS_U), BLOCK, 0, s>>>(m.cm, ref, m.cflag, m.rscan, m.rwords,
                                                               pred || hist_out ? m.mdir : nullptr, m.mstart, out, enc,
                                                               m.gex, m.gdesc, m.mrw, rkeys, okeys, okeys_cap, m.cscan,
-                                                              pred && hist_in ? hist_in->cap : -1);
+                                                              pred && hist_in ? hist_in->cap : -1,
+                                                              pred ? m.tab : nullptr);
   const PredW* pw = pred ? static_cast<const PredW*>(pred->dev) : nullptr;
   if (pw) {
     Timed tm(c, "predict", s);
-    k_nbr_clear<<<g, BLOCK, 0, s>>>(m.cm, m.tab, hist_in->cap);
     k_nbr_build<<<g, BLOCK, 0, s>>>(m.cm, ref, pw, m.tab);
     PredictArgs pa{m.cm,
                    reinterpret_cast<const uint64_t*>(ref),

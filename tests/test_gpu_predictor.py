@@ -86,6 +86,34 @@ def test_learned_handmade_exact_prediction(native):
     ctx.close()
 
 
+def test_history_smaller_than_reference_is_invalid(native):
+    """A learned call whose history holds fewer slots than the reference has
+    records is rejected with TA_ERR_INVALID, on either side; the same
+    context then runs the full call correctly."""
+    ref, cur, h = _moving_pair()
+    b = copy_last_move_blob()
+    ctx = native.Context(synth.Schema((4,), (1,)))
+    pred = native.Predictor(ctx, b)
+    R, roff = _upload([ref])
+    Cb, coff = _upload([cur])
+    n = len(h.hlen)
+    full = native.History.from_numpy(h.h1, h.h2, h.hlen)
+    short = native.History.from_numpy(h.h1[:n - 1], h.h2[:n - 1], h.hlen[:n - 1])
+    print("[learned] short history", flush=True)
+    ctx.delta_encode(Cb, coff, R, roff, pred=pred, hist=short, hist_out=native.History(n))
+    assert ctx.poll() == native.INVALID
+    enc, eoff, nref, noff, _ = ctx.delta_encode(Cb, coff, R, roff, pred=pred, hist=full, hist_out=native.History(n))
+    ctx.check("encode")
+    ctx.delta_decode(enc, eoff, R, roff, pred=pred, hist=short, hist_out=native.History(n))
+    assert ctx.poll() == native.INVALID
+    dec, doff = ctx.delta_decode(enc, eoff, R, roff, pred=pred, hist=full, hist_out=native.History(n))
+    ctx.check("decode")
+    st, _, onref, _, _ = oracle.delta_encode(cur, ref, oracle.mlp_struct(b), h)
+    assert st == 0
+    assert np.array_equal(host(nref, host(noff)), onref) and np.array_equal(host(dec, host(doff)), onref)
+    ctx.close()
+
+
 @pytest.mark.parametrize("persistent,which", [(True, "copy"), (False, "copy"), (False, "random"), (True, "zero")])
 def test_learned_iterations_match_oracle(native, persistent, which):
     """Sender and receiver on the GPU, oracle beside them, over several
