@@ -1061,7 +1061,7 @@ constexpr uint8_t GCH_VARIANT = 3, GCH_LEARNED_SMALLER = 4, GCH_PLAIN_SMALLER = 
 // (segs, gpre, gseg, gfirst: read-only here; as restrict parameters their
 // uniform reads become scalar loads)
 template <int OP, bool LRN>
-__global__ __launch_bounds__(EG_BLOCK) void k_enc_groups(GroupArgs a, const Seg* __restrict__ segs,
+__global__ __launch_bounds__(EG_BLOCK) __attribute__((amdgpu_waves_per_eu(LRN ? 6 : 1))) void k_enc_groups(GroupArgs a, const Seg* __restrict__ segs,
                                                          const uint64_t* __restrict__ gpre,
                                                          const uint32_t* __restrict__ gseg,
                                                          const uint32_t* __restrict__ gfirst, LookBack lb) {

@@ -188,7 +188,7 @@ struct CntIn {
 // directions as a bit mask; a wave then scatters only into the directions
 // some of its agents belong to.
 template <int NDIRS, bool EXACT>
-__global__ __launch_bounds__(BLOCK) void k_sel_scatter(const int64_t* part_off, int32_t P, DirTable dt, SelScratch sc,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_sel_scatter(const int64_t* part_off, int32_t P, DirTable dt, SelScratch sc,
                                                        int32_t* idx_out, int64_t idx_cap, int64_t* seg_off,
                                                        uint32_t* status) {
   constexpr int NW = (NDIRS + 4) / 5;
