@@ -203,7 +203,7 @@ constexpr int JB_TARGET = TA_JB_TARGET;
 constexpr int JC_U = 4;           // join count and bucket: items per thread and pass
 constexpr int JS_U = 16;          // join scatter: items per thread and pass (a tile's items in few passes)
 constexpr int RS_U = 4;           // record directories: reference slots per lane and pass
-constexpr int RL_U = 8;           // decoder reference slots: slots per lane and pass
+constexpr int RL_U = 6;           // decoder reference slots: slots per lane and pass
 constexpr int JB_MAX = 8192;      // buckets per segment (LDS histogram)
 // A bucket holds JB_TARGET / 2 .. JB_TARGET items on average; JCAP at 1.5x
 // the target keeps the bucket block at 32 KB of LDS (five blocks per CU),
@@ -862,9 +862,12 @@ __device__ inline void nbr_clear(const Common& cm, Entry* tab, int64_t hist_cap)
 
 // Directory of the matched records, in C' order: C and R word, residual
 // start, slot (learned mode), or the C and R word offsets in the segment's
-// record areas (plain mode); C' offsets; groups' segment and first record.  A wave takes
-// RS_U * 64 consecutive reference slots per pass and issues their loads in
-// two stages before it stores anything.
+// record areas (plain mode); C' offsets; groups' segment and first record.
+// A wave takes RS_U * 64 consecutive reference slots per pass and issues
+// their loads in two stages before it stores anything.  Learned calls (ntab
+// set) then clear the neighbour table.  Six waves per SIMD: the pass is
+// bound by its loads in flight, and at 81 registers it ran at five (23 ->
+// 29 us on 1.5e6 slots).
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_enc_mdir(Common cm, const uint8_t* cur, const uint8_t* ref,
                                                     const int32_t* m, const uint64_t* rscan, const uint32_t* rwords,
                                                     MDir* mdir, uint64_t* crw, uint64_t* mstart, uint8_t* newref,
@@ -1059,7 +1062,8 @@ struct GroupArgs {
 constexpr uint8_t GCH_VARIANT = 3, GCH_LEARNED_SMALLER = 4, GCH_PLAIN_SMALLER = 8;
 
 // (segs, gpre, gseg, gfirst: read-only here; as restrict parameters their
-// uniform reads become scalar loads)
+// uniform reads become scalar loads.  The learned kernel is held to six
+// waves per SIMD, as the plain one has by itself: 75 registers, no spill.)
 template <int OP, bool LRN>
 __global__ __launch_bounds__(EG_BLOCK) __attribute__((amdgpu_waves_per_eu(LRN ? 6 : 1))) void k_enc_groups(GroupArgs a, const Seg* __restrict__ segs,
                                                          const uint64_t* __restrict__ gpre,
@@ -1475,6 +1479,7 @@ struct NewArgs {
   uint64_t* okeys;
   uint64_t okeys_cap;
 };
+// (five waves per SIMD: 96 registers, no spill)
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_enc_fixed(Common cm, const int32_t* m, const uint64_t* bm,
                                                      const uint8_t* gsz, const uint8_t* gch, const uint64_t* gex,
                                                      uint8_t* enc, int64_t enc_cap, int64_t* enc_off,
