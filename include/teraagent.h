@@ -362,7 +362,10 @@ typedef struct {
   uint64_t *h1;
   uint64_t *h2;
   uint8_t *hlen;
-  int64_t cap;             /* slots the arrays hold */
+  int64_t cap;             /* slots the arrays hold; a learned call whose hist_in
+                              holds fewer slots than its reference has records
+                              fails with TA_ERR_INVALID (found on the device,
+                              reported by ta_status_poll) */
 } ta_history;
 
 /* Delta encoding (Sec. 2.3) of nseg current messages against nseg
