@@ -387,13 +387,45 @@ __global__ __launch_bounds__(BLOCK) void k_mig_keep(ta_agents in, const uint64_t
       for (int u = 0; u < MK_U; ++u)
         if (keep[u]) out.i32[k * out.is + j[u]] = v[u];
     }
+    // Behaviour bytes.  When every agent of the wave's span stays and the span
+    // lies in one partition, its bytes are one range on both sides: the wave
+    // copies it lane-parallel, MK_U words per lane in flight.  Otherwise each
+    // lane copies its own agents' words.
+    bool span_kept = true;
 #pragma unroll
-    for (int u = 0; u < MK_U; ++u) {
-      if (!keep[u]) continue;
-      const int64_t nw = (be[u] - ba[u]) / 8;
-      const uint64_t* src = reinterpret_cast<const uint64_t*>(in.beh + ba[u]);
-      uint64_t* dst = reinterpret_cast<uint64_t*>(out.beh + bb[u]);
-      for (int64_t w = 0; w < nw; ++w) dst[w] = src[w];
+    for (int u = 0; u < MK_U; ++u) span_kept = span_kept && (b0 + (int64_t)u * WAVE + l > last || keep[u]);
+    if (lo == hi && __ballot(!span_kept) == 0) {
+      const int64_t lu = (last - b0) / WAVE, ll = (last - b0) % WAVE;  // round and lane of the span's last agent
+      const uint64_t s0 = readlane64((uint64_t)ba[0], 0), d0 = readlane64(bb[0], 0);
+      uint64_t s1 = s0;
+#pragma unroll
+      for (int u = 0; u < MK_U; ++u)
+        if (u == lu) s1 = readlane64((uint64_t)be[u], (int)ll);
+      const int64_t nw = (int64_t)(s1 - s0) / 8;
+      const uint64_t* src = reinterpret_cast<const uint64_t*>(in.beh + s0);
+      uint64_t* dst = reinterpret_cast<uint64_t*>(out.beh + d0);
+      for (int64_t w0 = l; w0 < nw; w0 += (int64_t)MK_U * WAVE) {
+        uint64_t v[MK_U];
+#pragma unroll
+        for (int u = 0; u < MK_U; ++u) {
+          const int64_t w = w0 + (int64_t)u * WAVE;
+          v[u] = src[w < nw ? w : nw - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < MK_U; ++u) {
+          const int64_t w = w0 + (int64_t)u * WAVE;
+          if (w < nw) dst[w] = v[u];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < MK_U; ++u) {
+        if (!keep[u]) continue;
+        const int64_t nw = (be[u] - ba[u]) / 8;
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(in.beh + ba[u]);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(out.beh + bb[u]);
+        for (int64_t w = 0; w < nw; ++w) dst[w] = src[w];
+      }
     }
   }
 }
