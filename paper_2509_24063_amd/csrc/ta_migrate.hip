@@ -169,6 +169,7 @@ struct KeepIn {
 };
 
 struct KeepBehIn {
+  static constexpr int ROUNDS = 16;  // tiles of 8192 agents: half the tickets and look-backs (76 -> 63 us over 1e7)
   const uint8_t* kflag;
   const int64_t* beh_off;
   uint32_t* status;
