@@ -255,6 +255,27 @@ def test_selection_and_serialize_capacity(native):
     ctx.close()
 
 
+def test_serialize_with_large_capacity(native):
+    """A small world selected into a large index buffer (2^22 + 7 records):
+    the scan of record sizes runs over the whole capacity's tile bound, and
+    the messages and offsets still equal the oracle's."""
+    cfg = synth.config(1, median=2000.0)
+    w = synth.World(cfg)
+    ds = native.DeviceStore(w.store)
+    ctx = native.Context(cfg.schema)
+    print("[large capacity] select + serialize", flush=True)
+    idx, seg = ctx.select_aura(ds, cfg.w, cfg.ndirs, idx_cap=(1 << 22) + 7)
+    ctx.check("select")
+    buf, moff = ctx.serialize(ds, idx, seg)
+    ctx.check("serialize")
+    oidx, oseg = oracle.select_aura(w.store, cfg.w, cfg.ndirs)
+    obuf, omoff = oracle.serialize(w.store, cfg.schema, oidx, oseg)
+    assert np.array_equal(host(seg), oseg)
+    assert np.array_equal(host(moff), omoff)
+    assert np.array_equal(host(buf, host(moff)), obuf)
+    ctx.close()
+
+
 def test_record_capacity(native):
     """A record capacity set by reserve bounds the delta scratch: inputs with
     more records per side fail with a capacity error (and write nothing out of
