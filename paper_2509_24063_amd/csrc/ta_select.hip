@@ -251,7 +251,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     uint32_t any = 0;
 #pragma unroll
     for (int k = 0; k < SEL_IPT; ++k) {
-      code[k] = (i0 + k < ti.a1) ? sc.code[i0 + k] : 0u;
+      // (6-bit codes, as the counting pass wrote them: the mask keeps the
+      // table lookups below inside their 64 rows whatever the byte holds)
+      code[k] = (i0 + k < ti.a1) ? (sc.code[i0 + k] & 63u) : 0u;
       any |= code[k];
     }
     // most waves (agents away from the box faces) select nothing: they skip
