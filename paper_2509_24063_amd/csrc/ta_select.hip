@@ -195,8 +195,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
                                                        uint32_t* status) {
   constexpr int NW = (NDIRS + 4) / 5;
   __shared__ uint64_t s_w[WAVES][NW];
-  __shared__ uint64_t s_inc[64][NW];  // per code: +1 in the field of every direction it belongs to
-  __shared__ uint32_t s_dm[64];       // per code: its directions, one bit each
+  // (256 rows: any byte value indexes inside the tables; codes are 6-bit, rows
+  // 64 and up stay empty)
+  __shared__ uint64_t s_inc[256][NW];  // per code: +1 in the field of every direction it belongs to
+  __shared__ uint32_t s_dm[256];      // per code: its directions, one bit each
   __shared__ uint32_t s_wm[WAVES];    // per wave: directions some of its agents belong to
   __shared__ uint32_t s_req[NDIRS];   // code bits each direction requires
   __shared__ int64_t s_base[NDIRS];   // per direction: the tile's first output position
@@ -214,14 +216,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     }
     seg_off[s] = pos;
   }
-  for (int c = threadIdx.x; c < 64; c += BLOCK) {
+  for (int c = threadIdx.x; c < 256; c += BLOCK) {
     uint64_t inc[NW];
 #pragma unroll
     for (int j = 0; j < NW; ++j) inc[j] = 0;
     uint32_t dm = 0;
 #pragma unroll
     for (int d = 0; d < NDIRS; ++d) {
-      if (c && member<EXACT>(c, dt.req[d])) {
+      if (c && c < 64 && member<EXACT>(c, dt.req[d])) {
         inc[d / 5] += 1ull << (12 * (d % 5));
         dm |= 1u << d;
       }
@@ -251,9 +253,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) void
     uint32_t any = 0;
 #pragma unroll
     for (int k = 0; k < SEL_IPT; ++k) {
-      // (6-bit codes, as the counting pass wrote them: the mask keeps the
-      // table lookups below inside their 64 rows whatever the byte holds)
-      code[k] = (i0 + k < ti.a1) ? (sc.code[i0 + k] & 63u) : 0u;
+      code[k] = (i0 + k < ti.a1) ? sc.code[i0 + k] : 0u;
       any |= code[k];
     }
     // most waves (agents away from the box faces) select nothing: they skip
